@@ -1,0 +1,258 @@
+"""ctypes front end of the plain FP64 CPU oracle (``qtb_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg use it to check and time the GPU library.  The product path
+never imports it, and this module imports nothing from the product package.
+
+Paper: Dammak, Hayoun, Brieuc, Geneste, arXiv:1905.02521 (eq. numbers are
+cited on each function in ``qtb_oracle.c``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qtb_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# -ffp-contract=off: the Gaussian transform is specified operation by operation.
+CFLAGS = ["-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+          "-fno-fast-math", "-mavx2", "-mfma", "-std=c11"]
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (always, when force=True)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Units(ctypes.Structure):
+    _fields_ = [("hbar", ctypes.c_double), ("kB", ctypes.c_double),
+                ("coulomb_k", ctypes.c_double), ("mass_unit", ctypes.c_double)]
+
+
+MAX_SPECIES = 4
+
+
+class Pot(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("n_species", ctypes.c_int),
+                ("mass", ctypes.c_double * MAX_SPECIES),
+                ("charge", ctypes.c_double * MAX_SPECIES),
+                ("buck_A", ctypes.c_double * (MAX_SPECIES * MAX_SPECIES)),
+                ("buck_rho", ctypes.c_double * (MAX_SPECIES * MAX_SPECIES)),
+                ("buck_C", ctypes.c_double * (MAX_SPECIES * MAX_SPECIES)),
+                ("dsf_alpha", ctypes.c_double), ("r_cut", ctypes.c_double),
+                ("skin", ctypes.c_double)]
+
+
+_lib = None
+_D = ctypes.c_double
+_PD = ctypes.POINTER(ctypes.c_double)
+_PU = ctypes.POINTER(Units)
+_PP = ctypes.POINTER(Pot)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        L = _lib
+        L.orc_theta.restype = _D
+        L.orc_theta.argtypes = [_D, _D, _PU]
+        L.orc_kappa.restype = _D
+        L.orc_kappa.argtypes = [_D, _D, ctypes.c_int, _PU, _D]
+        L.orc_taps.restype = ctypes.c_int
+        L.orc_taps.argtypes = [ctypes.c_int, _D, ctypes.c_int, _D, ctypes.c_int, _PU, _PD]
+        L.orc_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+        L.orc_gauss.restype = _D
+        L.orc_gauss.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32,
+                                ctypes.c_uint32, ctypes.c_uint32]
+        L.orc_gauss_fill.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_uint32, _PD]
+        L.orc_log_spec.restype = _D
+        L.orc_log_spec.argtypes = [_D]
+        L.orc_cos2pi_spec.restype = _D
+        L.orc_cos2pi_spec.argtypes = [ctypes.c_uint64]
+        L.orc_zeta.restype = _D
+        L.orc_zeta.argtypes = [_PD, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+                               ctypes.c_int64, ctypes.c_uint32]
+        L.orc_pair_bruteforce.restype = _D
+        L.orc_pair_bruteforce.argtypes = [_PP, _PU, ctypes.c_int, _PD,
+                                          ctypes.POINTER(ctypes.c_int32), _PD, _PD, _PD]
+        L.orc_sim_new.restype = ctypes.c_void_p
+        L.orc_sim_new.argtypes = [_PP, _PU, ctypes.c_int, ctypes.c_int, ctypes.c_int, _PD,
+                                  ctypes.POINTER(ctypes.c_int32), _PD, _D, _D, _D,
+                                  ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                                  _PD, _PD, ctypes.c_int64, ctypes.c_int]
+        L.orc_sim_run.restype = ctypes.c_int
+        L.orc_sim_run.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, _PD]
+        L.orc_sim_get.argtypes = [ctypes.c_void_p, _PD, _PD, _PD,
+                                  ctypes.POINTER(ctypes.c_int64)]
+        L.orc_sim_free.argtypes = [ctypes.c_void_p]
+        L.orc_sim_observe.argtypes = [ctypes.c_void_p, _PD]
+        L.orc_sim_hamiltonian.restype = _D
+        L.orc_sim_hamiltonian.argtypes = [ctypes.c_void_p]
+        L.orc_sim_taps.restype = _PD
+        L.orc_sim_taps.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
+        L.orc_nm_matrix.argtypes = [ctypes.c_int, _PD]
+    return _lib
+
+
+def _pd(a: np.ndarray):
+    return a.ctypes.data_as(_PD)
+
+
+def make_units(hbar, kB, coulomb_k=0.0, mass_unit=1.0) -> Units:
+    return Units(hbar, kB, coulomb_k, mass_unit)
+
+
+def make_pot(kind=0, mass=(1.0,), charge=(0.0,), buck_A=None, buck_rho=None, buck_C=None,
+             dsf_alpha=0.0, r_cut=1.0, skin=0.0) -> Pot:
+    ns = len(mass)
+    p = Pot()
+    p.kind = kind
+    p.n_species = ns
+    for a in range(ns):
+        p.mass[a] = mass[a]
+        p.charge[a] = charge[a] if a < len(charge) else 0.0
+    for ab in range(ns * ns):
+        p.buck_A[ab] = buck_A[ab] if buck_A is not None else 0.0
+        p.buck_rho[ab] = buck_rho[ab] if buck_rho is not None else 1.0
+        p.buck_C[ab] = buck_C[ab] if buck_C is not None else 0.0
+    p.dsf_alpha, p.r_cut, p.skin = dsf_alpha, r_cut, skin
+    return p
+
+
+# ---------------------------------------------------------------- functions
+def theta(omega, T, units: Units):
+    return lib().orc_theta(float(omega), float(T), ctypes.byref(units))
+
+
+def kappa(omega, T, P, units: Units, h_quad=0.0):
+    return lib().orc_kappa(float(omega), float(T), int(P), ctypes.byref(units), float(h_quad))
+
+
+def taps(kind, T, P, dt, two_nf, units: Units) -> np.ndarray:
+    h = np.zeros(two_nf)
+    rc = lib().orc_taps(int(kind), float(T), int(P), float(dt), int(two_nf),
+                        ctypes.byref(units), _pd(h))
+    if rc:
+        raise ValueError("bad filter length")
+    return h
+
+
+def philox(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def gauss(seed, n, d, stream=0, tag=0):
+    return lib().orc_gauss(seed, n, d, stream, tag)
+
+
+def gauss_fill(seed, n0, n_rows, d0, n_dof, stream=0, tag=0) -> np.ndarray:
+    out = np.empty((n_rows, n_dof))
+    lib().orc_gauss_fill(seed, n0, n_rows, d0, n_dof, stream, tag, _pd(out))
+    return out
+
+
+def log_spec(u):
+    return lib().orc_log_spec(float(u))
+
+
+def cos2pi_spec(odd53):
+    return lib().orc_cos2pi_spec(int(odd53))
+
+
+def zeta(h: np.ndarray, seed, stream, n, d):
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    return lib().orc_zeta(_pd(h), len(h), seed, stream, n, d)
+
+
+def nm_matrix(P) -> np.ndarray:
+    C = np.zeros((P, P))
+    lib().orc_nm_matrix(P, _pd(C))
+    return C
+
+
+def pair_bruteforce(pot: Pot, units: Units, box, species, pos):
+    """pos: [3][N] -> (energy, forces [3][N], virial 3x3)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    N = pos.shape[1]
+    sp = np.ascontiguousarray(species, dtype=np.int32)
+    f = np.zeros_like(pos)
+    vir = np.zeros(9)
+    boxa = np.ascontiguousarray(box, dtype=np.float64)
+    e = lib().orc_pair_bruteforce(ctypes.byref(pot), ctypes.byref(units), N, _pd(boxa),
+                                  sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  _pd(pos), _pd(f), _pd(vir))
+    return e, f, vir.reshape(3, 3)
+
+
+OBS_NAMES = ("kinetic", "potential", "spring", "e_primitive", "e_virial",
+             "t_kinetic", "x2_mean", "step")
+
+
+class Sim:
+    """One replica integrated by the oracle; state arrays are [P][dims][N]."""
+
+    def __init__(self, pot: Pot, units: Units, N, P, dims, box, species, T, gamma, dt,
+                 seed, stream, noise_kind, two_nf, pos0, vel0=None, harm_omega=None,
+                 step0=0, n_threads=1):
+        self.N, self.P, self.dims = N, P, dims
+        self._keep = []
+        sp = np.ascontiguousarray(species, dtype=np.int32)
+        boxa = np.ascontiguousarray(box if box is not None else [0, 0, 0], dtype=np.float64)
+        pos0 = np.ascontiguousarray(pos0, dtype=np.float64).reshape(P, dims, N)
+        v0 = None if vel0 is None else np.ascontiguousarray(vel0, dtype=np.float64).reshape(P, dims, N)
+        hom = None if harm_omega is None else np.ascontiguousarray(harm_omega, dtype=np.float64)
+        self._keep += [sp, boxa, pos0, v0, hom]
+        self.h = lib().orc_sim_new(ctypes.byref(pot), ctypes.byref(units), N, P, dims, _pd(boxa),
+                                   sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   None if hom is None else _pd(hom),
+                                   T, gamma, dt, seed, stream, noise_kind, two_nf,
+                                   _pd(pos0), None if v0 is None else _pd(v0), step0, n_threads)
+        if not self.h:
+            raise ValueError("oracle rejected the replica description")
+
+    def run(self, n_steps, obs_every=0):
+        nmax = (n_steps // obs_every) if obs_every > 0 else 0
+        obs = np.zeros((max(nmax, 1), 8))
+        n = lib().orc_sim_run(self.h, n_steps, obs_every, _pd(obs))
+        return obs[:n]
+
+    def state(self):
+        shape = (self.P, self.dims, self.N)
+        r, v, f = np.zeros(shape), np.zeros(shape), np.zeros(shape)
+        st = ctypes.c_int64()
+        lib().orc_sim_get(self.h, _pd(r), _pd(v), _pd(f), ctypes.byref(st))
+        return r, v, f, st.value
+
+    def observe(self):
+        o = np.zeros(8)
+        lib().orc_sim_observe(self.h, _pd(o))
+        return o
+
+    def hamiltonian(self):
+        return lib().orc_sim_hamiltonian(self.h)
+
+    def taps(self):
+        n = ctypes.c_int()
+        p = lib().orc_sim_taps(self.h, ctypes.byref(n))
+        return np.ctypeslib.as_array(p, shape=(n.value,)).copy()
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_sim_free(self.h)
+            self.h = None

@@ -1,0 +1,86 @@
+"""Closed forms that pin the oracle (written from the mathematics, not from it).
+
+* ``pimd_ho_energy``: exact <E_prim> of a P-bead harmonic ring polymer with the
+  paper's conventions (bead mass m, V/P, omega_P = sqrt(P)/(beta hbar), eq. 3-5),
+  from the product form of Z_P: sinh(a/2) = beta hbar omega / (2P),
+  <E>_P = (hbar omega/2) coth(P a/2) / cosh(a/2).
+* ``stationary_moments``: exact stationary covariance of the discrete linear
+  scheme z_{n+1} = M z_n + b zeta_n driven by the FIR noise zeta = h * w,
+  using the noise autocorrelation R(tau) = sum_k h_k h_{k+tau} and the
+  discrete Lyapunov solution X0 = M X0 M^T + b b^T:
+  Sigma = R(0) X0 + sum_{tau>0} R(tau) (X0 (M^tau)^T + M^tau X0).
+  This is the exact answer of the integrator for harmonic systems, so it
+  separates time-step / filter-resolution effects from implementation errors.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.linalg import solve_discrete_lyapunov
+
+
+def theta_coth(omega, kT, hbar):
+    """theta = (hbar w/2) coth(hbar w / 2kT): eq. (1) rewritten with coth."""
+    x = hbar * abs(omega) / (2 * kT)
+    if x == 0:
+        return kT
+    return hbar * abs(omega) / 2.0 / math.tanh(x)
+
+
+def pimd_ho_energy(omega, kT, hbar, P):
+    if P == 1:
+        return kT
+    a = 2.0 * math.asinh(hbar * omega / (kT * 2.0 * P))
+    return hbar * omega / 2.0 / math.tanh(P * a / 2.0) / math.cosh(a / 2.0)
+
+
+def baoab_mode_map(acc2, w_free, c1, sigma, dt):
+    """One B A O A B step of a single mode: B kicks with acceleration -acc2 q,
+    A rotates at w_free (drift if 0) for dt/2, O applies c1 and noise sigma."""
+    h = dt / 2.0
+    B = np.array([[1.0, 0.0], [-h * acc2, 1.0]])
+    if w_free == 0.0:
+        A = np.array([[1.0, h], [0.0, 1.0]])
+    else:
+        c, s = math.cos(w_free * h), math.sin(w_free * h)
+        A = np.array([[c, s / w_free], [-w_free * s, c]])
+    Om = np.array([[1.0, 0.0], [0.0, c1]])
+    M = B @ A @ Om @ A @ B
+    b = B @ A @ np.array([0.0, sigma])
+    return M, b
+
+
+def stationary_moments(M, b, taps):
+    taps = np.asarray(taps, dtype=np.float64)
+    L = len(taps)
+    R = np.array([np.dot(taps[: L - t], taps[t:]) for t in range(L)])
+    X0 = solve_discrete_lyapunov(M, np.outer(b, b))
+    S = R[0] * X0
+    Mt = np.eye(len(b))
+    for t in range(1, L):
+        Mt = Mt @ M
+        if R[t] != 0.0:
+            S += R[t] * (X0 @ Mt.T + Mt @ X0)
+    return S
+
+
+def ho_energy_discrete(omega, m, P, kT, hbar, gamma, dt, taps):
+    """Exact stationary <E_prim> (eq. 5) of the BAOAB / normal-mode scheme on a
+    1D harmonic oscillator with P beads, plus <q^2> summed over modes (bead
+    averaged <x^2> = sum_k <q_k^2> / P) and the kinetic part."""
+    c1 = math.exp(-gamma * dt)
+    sigma = math.sqrt((1 - c1 * c1) / m)
+    wP = math.sqrt(P) * kT / hbar
+    E = 0.0
+    x2 = 0.0
+    ke = 0.0
+    for k in range(P):
+        wf = 2 * wP * math.sin(math.pi * k / P)
+        M, b = baoab_mode_map(omega * omega / P, wf, c1, sigma, dt)
+        S = stationary_moments(M, b, taps)
+        q2, v2 = S[0, 0], S[1, 1]
+        E += 0.5 * m * v2 - 0.5 * m * wf * wf * q2 + 0.5 * m * omega * omega / P * q2
+        x2 += q2
+        ke += 0.5 * m * v2
+    return E, x2 / P, ke

@@ -1,0 +1,124 @@
+"""Pins of the oracle's pair potential (Buckingham + damped shifted force Coulomb).
+
+The paper gives no MgO potential; the workload's potential is pinned by
+physics that does not depend on the oracle's own formula: the rock-salt
+Madelung constant, symmetry (zero force on a perfect lattice), Newton's third
+law, continuity of energy and force at the cut-off, the alpha -> 0 limit
+(plain shifted-force Coulomb), and central finite differences of the energy.
+The neighbour-list force path is pinned to the all-image brute force.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1905_02521_amd import workloads as W
+
+MADELUNG_NACL = 1.747565
+
+
+@pytest.fixture(scope="module")
+def U(orc):
+    return orc.make_units(**W.METAL_UNITS)
+
+
+def mgo_pot(orc, alpha=0.2, rc=9.0, skin=1.0, coulomb=True, buck=True):
+    p = W.mgo_potential(r_cut=rc, skin=skin, dsf_alpha=alpha)
+    return orc.make_pot(0, p.mass, p.charge if coulomb else (0.0, 0.0),
+                        p.buck_A if buck else None, p.buck_rho, p.buck_C if buck else None,
+                        alpha, rc, skin)
+
+
+def test_madelung_converged_dsf(orc, U):
+    pos, sp, box = W.rocksalt(5)
+    e, f, _ = orc.pair_bruteforce(mgo_pot(orc, 0.3, 14.0, buck=False), U, box, sp, pos)
+    per_pair = e / (pos.shape[1] / 2)
+    ref = -MADELUNG_NACL * W.METAL_UNITS["coulomb_k"] * 4.0 / 2.105
+    assert abs(per_pair / ref - 1) < 1e-5
+    assert np.max(np.abs(f)) < 1e-11
+
+
+def test_madelung_workload_settings(orc, U):
+    # alpha = 0.2/A, r_c = 9 A: DSF is within ~1% of the Ewald (Madelung) value
+    pos, sp, box = W.rocksalt(3)
+    e, _, _ = orc.pair_bruteforce(mgo_pot(orc, buck=False), U, box, sp, pos)
+    ref = -MADELUNG_NACL * W.METAL_UNITS["coulomb_k"] * 4.0 / 2.105
+    assert abs(e / (pos.shape[1] / 2) / ref - 1) < 0.015
+    # r_c = 9 A exceeds half the 3x3x3 box (6.3 A): the sum must see several
+    # images; the 4x4x4 box must give the same energy per pair
+    pos4, sp4, box4 = W.rocksalt(4)
+    e4, _, _ = orc.pair_bruteforce(mgo_pot(orc, buck=False), U, box4, sp4, pos4)
+    assert abs(e4 / (pos4.shape[1] / 2) - e / (pos.shape[1] / 2)) < 1e-10
+
+
+def test_perfect_lattice_zero_force_and_newton3(orc, U):
+    pos, sp, box = W.rocksalt(3)
+    pot = mgo_pot(orc)
+    _, f, _ = orc.pair_bruteforce(pot, U, box, sp, pos)
+    assert np.max(np.abs(f)) < 1e-11
+    posd = W.displaced(pos, 0.0421, 1)
+    _, fd, _ = orc.pair_bruteforce(pot, U, box, sp, posd)
+    assert np.max(np.abs(fd)) > 0.1
+    assert np.max(np.abs(fd.sum(axis=1))) < 1e-10
+
+
+def test_finite_difference_forces(orc, U):
+    pos, sp, box = W.rocksalt(2)
+    pos = W.displaced(pos, 0.08, 2)
+    pot = mgo_pot(orc)
+    _, f, _ = orc.pair_bruteforce(pot, U, box, sp, pos)
+    h = 1e-5
+    rng = np.random.default_rng(0)
+    for _ in range(6):
+        i = int(rng.integers(pos.shape[1]))
+        d = int(rng.integers(3))
+        p1, p2 = pos.copy(), pos.copy()
+        p1[d, i] += h
+        p2[d, i] -= h
+        e1, _, _ = orc.pair_bruteforce(pot, U, box, sp, p1)
+        e2, _, _ = orc.pair_bruteforce(pot, U, box, sp, p2)
+        assert abs(-(e1 - e2) / (2 * h) - f[d, i]) < 2e-6
+
+
+def _two_ion_energy(orc, U, r, pot, species=(0, 1)):
+    L = 60.0
+    pos = np.array([[10.0, 10.0 + r], [10.0, 10.0], [10.0, 10.0]])
+    e, f, _ = orc.pair_bruteforce(pot, U, [L, L, L], np.array(species), pos)
+    e0, _, _ = orc.pair_bruteforce(pot, U, [L, L, L], np.array(species),
+                                   np.array([[10.0, 40.0], [10.0, 40.0], [10.0, 40.0]]))
+    return e - e0, f[0, 1]
+
+
+def test_energy_and_force_vanish_at_cutoff(orc, U):
+    for sp in ((0, 1), (1, 1), (0, 0)):
+        pot = mgo_pot(orc)
+        e_in, f_in = _two_ion_energy(orc, U, 9.0 - 1e-7, pot, sp)
+        e_out, f_out = _two_ion_energy(orc, U, 9.0 + 1e-7, pot, sp)
+        assert e_out == 0.0 and f_out == 0.0
+        assert abs(e_in) < 1e-10 and abs(f_in) < 1e-6
+
+
+def test_small_alpha_is_shifted_force_coulomb(orc, U):
+    # alpha -> 0: erfc -> 1, DSF -> k q q (1/r - 1/rc + (r - rc)/rc^2)
+    pot = mgo_pot(orc, alpha=1e-9, buck=False)
+    k = W.METAL_UNITS["coulomb_k"]
+    for r in (2.0, 4.5, 8.0):
+        e, f = _two_ion_energy(orc, U, r, pot)
+        ref = k * 2 * -2 * (1 / r - 1 / 9.0 + (r - 9.0) / 81.0)
+        fref = k * 2 * -2 * (1 / r**2 - 1 / 81.0)
+        assert abs(e - ref) < 1e-7
+        assert abs(f - fref) < 1e-7   # force on ion 1 along +x
+
+
+@pytest.mark.parametrize("P", [1, 3])
+def test_neighbour_list_forces_match_bruteforce(orc, U, P):
+    for n in (2, 3):
+        pos, sp, box = W.rocksalt(n)
+        N = pos.shape[1]
+        beads = np.stack([W.displaced(pos, 0.05, 10 + b) for b in range(P)])
+        pot = mgo_pot(orc)
+        s = orc.Sim(pot, U, N, P, 3, box, sp, 100.0, 0.0, 1.0, 1, 0, 0, 2, beads)
+        _, _, f, _ = s.state()
+        for b in range(P):
+            _, fb, _ = orc.pair_bruteforce(pot, U, box, sp, beads[b])
+            assert np.linalg.norm(f[b] - fb) / np.linalg.norm(fb) < 1e-12
