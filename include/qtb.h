@@ -1,0 +1,235 @@
+/*
+ * qtb.h -- C ABI of libqtb.so, the MI355X (gfx950) integrator step for
+ * quantum-thermal-bath (QTB) Langevin dynamics and its combination with
+ * path-integral MD (QTB-PIMD), after Dammak, Hayoun, Brieuc and Geneste,
+ * "Nuclear quantum effects in molecular dynamics simulations"
+ * (arXiv:1905.02521).
+ *
+ * One step advances every replica of a context by dt:
+ *   B(dt/2) -> normal modes -> A(dt/2) -> O(dt) -> A(dt/2) -> beads ->
+ *   forces -> B(dt/2)
+ * B applies the bead force -(1/P) grad V with bead mass m (eq. 4); A is the
+ * exact propagation of the ring-polymer springs of eq. (3) in normal modes;
+ * O is the Langevin friction of eq. (8) with a coloured random force of power
+ * spectral density 2 m gamma theta(omega, T) (eq. 6-7, theta from eq. 1) for
+ * QTB, or 2 m gamma kappa_P(omega, T) (eq. 10-12) for QTB-PIMD, acting on
+ * the ring-polymer normal modes (Sec. 2.3).  White noise (k_B T) gives
+ * classical Langevin dynamics (P = 1) or classical PIMD (P > 1).
+ *
+ * Conventions shared by every entry point:
+ *  - Units are the caller's, fixed by qtb_options: the library takes hbar,
+ *    k_B, the Coulomb constant and the mass unit as inputs (the tests use
+ *    eV, Angstrom, amu, fs, K, or reduced units).
+ *  - State arrays are FP64, layout [P][n_dims][N] (bead-major, then
+ *    Cartesian component, then atom: structure of arrays), caller-owned
+ *    device memory.  Positions are never wrapped into the box.
+ *  - The library never allocates device memory: every device buffer comes
+ *    from the caller (state arrays and one workspace sized by
+ *    qtb_workspace_bytes).  The library frees only its host-side context.
+ *  - Work is enqueued on the caller's HIP stream.  Only qtb_observables,
+ *    qtb_get_state, qtb_set_state, qtb_evaluate and qtb_get_noise
+ *    synchronise that stream.
+ *  - Errors: every call returns a qtb_status; nothing aborts or throws
+ *    across the ABI.  A failing call leaves a message for qtb_last_error.
+ *  - A context is not re-entrant; separate contexts on separate streams are
+ *    independent.
+ */
+#ifndef QTB_H
+#define QTB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qtb_ctx qtb_ctx; /* opaque */
+
+typedef enum {
+    QTB_OK = 0,
+    QTB_E_INVALID = 1,     /* bad argument or size */
+    QTB_E_NOMEM = 2,       /* workspace too small, neighbour list overflow */
+    QTB_E_DEVICE = 3,      /* HIP runtime error */
+    QTB_E_STATE = 4,       /* call out of order (e.g. step before its filter) */
+    QTB_E_NONFINITE = 5,   /* NaN / Inf found in the state */
+    QTB_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+} qtb_status;
+
+/* Noise kinds: the power spectral density of the random force, eq. (7)/(12). */
+typedef enum {
+    QTB_NOISE_CLASSICAL = 0, /* k_B T: white noise (Langevin / classical PIMD) */
+    QTB_NOISE_QTB = 1,       /* theta(omega, T), eq. (1) and (7)              */
+    QTB_NOISE_QTB_PIMD = 2   /* kappa_P(omega, T), eq. (10)-(12)              */
+} qtb_noise;
+
+/* Arithmetic of the force and noise kernels.  State, energies and the filter
+ * design are FP64 in every mode. */
+typedef enum { QTB_PREC_FP32 = 0, QTB_PREC_FP64 = 1 } qtb_prec;
+
+/* Arithmetic of the coloured-noise contraction (FIR blocked over K steps). */
+typedef enum {
+    QTB_FIR_FP32 = 0,   /* FP32 matrix cores, FP32 accumulation                    */
+    QTB_FIR_BF16X3 = 1, /* BF16 matrix cores, hi*hi + hi*lo + lo*hi split, FP32 acc */
+    QTB_FIR_BF16 = 2,   /* BF16 matrix cores, single product, FP32 acc             */
+    QTB_FIR_FP64 = 3    /* FP64 vector ALU                                          */
+} qtb_fir;
+
+typedef enum {
+    QTB_POT_PAIR = 0,     /* Buckingham + damped shifted force Coulomb, 3D, periodic */
+    QTB_POT_HARMONIC = 1  /* independent oscillators V = 1/2 m omega_i^2 x^2 per dof  */
+} qtb_pot_kind;
+
+#define QTB_MAX_SPECIES 4
+
+/*
+ * Potential, shared by every replica of a context.  The paper gives no pair
+ * potential; the pair kind is V = sum_pairs [Buckingham in shifted-force form
+ * at r_cut: A exp(-r/rho) - C/r^6] + damped shifted force Coulomb (alpha,
+ * r_cut) including its self term.  Pairs are summed over every periodic
+ * image within r_cut (boxes smaller than 2 r_cut are handled).
+ * Host pointers; copied at qtb_init.
+ */
+typedef struct {
+    int32_t kind;              /* qtb_pot_kind                                  */
+    int32_t n_species;         /* 1..QTB_MAX_SPECIES                            */
+    const double *mass;        /* [n_species] mass                              */
+    const double *charge;      /* [n_species] charge (pair kind)                */
+    const double *buck_A;      /* [n_species^2] energy; 0 = no Buckingham term  */
+    const double *buck_rho;    /* [n_species^2] length                          */
+    const double *buck_C;      /* [n_species^2] energy * length^6               */
+    double dsf_alpha;          /* damping parameter, 1/length                   */
+    double r_cut;              /* cut-off, > 0                                  */
+    double skin;               /* Verlet skin, >= 0                             */
+} qtb_potential;
+
+/*
+ * One replica: N atoms x P beads (P = 1: QTB / Langevin; P > 1: the ring
+ * polymer of eq. 3 with omega_P = sqrt(P) k_B T / hbar).  species and
+ * harm_omega are host pointers copied at qtb_init; d_pos / d_vel are device
+ * pointers that stay owned by the caller and must outlive the context.
+ */
+typedef struct {
+    int32_t n_atoms;           /* N >= 1                                        */
+    int32_t n_beads;           /* P >= 1                                        */
+    int32_t n_dims;            /* 3 (pair kind) or 1 / 3 (harmonic kind)        */
+    int32_t noise;             /* qtb_noise                                     */
+    double box[3];             /* orthorhombic box lengths (pair kind)          */
+    double T;                  /* temperature, > 0                              */
+    double gamma;              /* friction, 1/time, >= 0                        */
+    double dt;                 /* time step, > 0                                */
+    uint64_t seed;             /* Philox key                                    */
+    uint32_t stream;           /* Philox counter word: independent noise stream */
+    uint32_t reserved;
+    const int32_t *species;    /* host [N], values in [0, n_species)            */
+    const double *harm_omega;  /* host [N] angular frequencies (harmonic kind)  */
+    double *d_pos;             /* device [P][n_dims][N] FP64                    */
+    double *d_vel;             /* device [P][n_dims][N] FP64                    */
+} qtb_replica;
+
+typedef struct {
+    double hbar;               /* energy * time                                  */
+    double kB;                 /* energy / temperature                           */
+    double coulomb_k;          /* energy * length / charge^2                     */
+    double mass_unit;          /* energy per (mass * length^2 / time^2)          */
+    int32_t prec;              /* qtb_prec                                       */
+    int32_t fir;               /* qtb_fir                                        */
+    int32_t fir_block_K;       /* steps per noise block: multiple of 64, >= 64   */
+    int32_t obs_every;         /* sample observables every n steps (0 = never)   */
+    int32_t max_two_nf;        /* largest FIR length any replica will use        */
+    int32_t reserved[3];
+} qtb_options;
+
+/* Means over the samples taken since the previous qtb_observables call of
+ * this replica (eq. 5 primitive estimator with instantaneous momenta). */
+typedef struct {
+    int64_t step;              /* step counter at the call                        */
+    double kinetic;            /* sum_s sum_i p^2 / 2m                            */
+    double potential;          /* sum_s V(r^(s)) / P                              */
+    double spring;             /* sum_s sum_i m omega_P^2 (r_s - r_s+1)^2 / 2     */
+    double e_primitive;        /* kinetic - spring + potential (eq. 5)            */
+    double e_virial;           /* centroid virial estimator (dims N k_B T / 2 + ...) */
+    double t_kinetic;          /* 2 kinetic / (dims N P k_B)                      */
+    double x2_mean;            /* mean of (r - r(init))^2 over beads, dims, atoms */
+    int32_t n_samples;
+} qtb_obs;
+
+/* Workspace bytes needed for these replicas and options (0 on bad input). */
+size_t qtb_workspace_bytes(const qtb_potential *pot, const qtb_replica *reps, int32_t n_rep,
+                           const qtb_options *opt);
+
+/*
+ * Create a context over n_rep replicas that step together (one launch per
+ * kernel covers all of them).  d_workspace: device buffer of at least
+ * qtb_workspace_bytes, 256-byte aligned, owned by the caller.  hip_stream:
+ * a hipStream_t (NULL = default stream).  Builds neighbour lists and the
+ * initial forces; replicas with noise != CLASSICAL need qtb_build_filter
+ * before qtb_step.
+ */
+qtb_status qtb_init(qtb_ctx **out, const qtb_potential *pot, const qtb_replica *reps,
+                    int32_t n_rep, const qtb_options *opt, void *d_workspace,
+                    size_t ws_bytes, void *hip_stream);
+
+/*
+ * Design the FIR filter of a replica (replica = -1: all replicas) from the
+ * spectrum of eq. (7) (kind QTB: theta) or eq. (12) (kind QTB_PIMD: kappa_P
+ * solving eq. 10-11), sampled on omega_j = pi j / (Nf dt), j = 0..Nf: the
+ * taps are the 2Nf-point inverse DFT of sqrt(S_j), so the realised noise
+ * spectrum equals S on that grid.  FP64 on the host, then copied to the
+ * device in the precision of the FIR mode.  two_nf: even, 2..max_two_nf.
+ * taps_out (nullable, host, [two_nf]) receives h_k for k = -Nf..Nf-1.
+ * kind must equal the replica's noise.
+ */
+qtb_status qtb_build_filter(qtb_ctx *ctx, int32_t replica, int32_t kind, int32_t two_nf,
+                            double *taps_out);
+
+/* Enqueue n_steps integrator steps of every replica; returns without waiting. */
+qtb_status qtb_step(qtb_ctx *ctx, int64_t n_steps);
+
+/* Synchronise the stream and return the observables of one replica.
+ * Returns QTB_E_NONFINITE if a NaN/Inf was found in any state since the last
+ * check, QTB_E_NOMEM if a neighbour list overflowed. */
+qtb_status qtb_observables(qtb_ctx *ctx, int32_t replica, qtb_obs *out);
+
+/* Copy a replica's state to / from host arrays [P][n_dims][N]; set_state
+ * also sets the replica's step counter, rebuilds its neighbour list and
+ * recomputes its forces.  Either pointer may be NULL (that half unchanged). */
+qtb_status qtb_get_state(qtb_ctx *ctx, int32_t replica, double *h_pos, double *h_vel,
+                         int64_t *step);
+qtb_status qtb_set_state(qtb_ctx *ctx, int32_t replica, const double *h_pos,
+                         const double *h_vel, int64_t step);
+
+/* Recompute forces of the current state of every replica (no kick) and
+ * return replica's forces -grad V(r^(s)) per bead (host [P][n_dims][N]) and
+ * per-bead potential energies V(r^(s)) (host [P]).  Either may be NULL. */
+qtb_status qtb_evaluate(qtb_ctx *ctx, int32_t replica, double *h_force, double *h_epot);
+
+/* The coloured noise zeta_{n,d} = sum_k h_k w_{n-k,d} of the last completed
+ * noise block of a replica: host [K][n_dof] FP64 (n_dof = n_dims N P,
+ * dof d = (n_dims * atom + dim) * P + mode), first step in *n0. */
+qtb_status qtb_get_noise(qtb_ctx *ctx, int32_t replica, double *h_zeta, int64_t *n0);
+
+/*
+ * The library's white-noise generator, standalone: d_out[r * n_dof + j] =
+ * w(n0 + r, d0 + j) for the given key and stream, FP64, device buffer of
+ * n_rows * n_dof doubles.  w is a unit Gaussian from one Philox4x32-10 block
+ * (Salmon et al., SC'11) at counter (n + 2^40 as two words, d, 16 stream +
+ * tag), key (seed low, seed high): two 52-bit uniforms, then the cosine
+ * branch of Box-Muller with the library's own ln and cos(2 pi u).  The paper
+ * asks only for normally distributed numbers (eq. 9); the counter-based form
+ * makes every value reproducible from its indices.
+ */
+qtb_status qtb_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
+                        int64_t n_rows, uint32_t d0, uint32_t n_dof, double *d_out,
+                        void *hip_stream);
+
+const char *qtb_last_error(const qtb_ctx *ctx); /* never NULL */
+void qtb_destroy(qtb_ctx *ctx);                 /* NULL is a no-op */
+
+/* Version string of the library build. */
+const char *qtb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTB_H */

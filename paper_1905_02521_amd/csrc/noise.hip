@@ -1,0 +1,185 @@
+// noise.hip -- counter-based white noise for the QTB random force.
+//
+// The paper draws the a_j, b_j of eq. (9) from a normal distribution and
+// says no more; this library fixes a reproducible generator: one
+// Philox4x32-10 block (Salmon et al., SC'11) per (step, dof) turned into one
+// unit Gaussian.  Every operation of the transform is spelled out (no
+// library ln / cos, no contraction) so that any implementation of the same
+// specification produces the same bits:
+//   counter = (lo, hi of n + 2^40, dof, 16 stream + tag), key = seed words
+//   u1 = (2 m1 + 1) 2^-53, m1 = (x0 >> 6) 2^26 + (x1 >> 6)      (exact)
+//   N2 = 2 m2 + 1,         m2 = (x2 >> 6) 2^26 + (x3 >> 6)
+//   w  = sqrt(-2 ln u1) cos(2 pi N2 / 2^53)
+// ln: exponent split, f in (1/sqrt2, sqrt2], s = (f-1)/(f+1), Horner in s^2
+// of the atanh series to s^22/23, e ln2 with the fdlibm hi/lo split.
+// cos: quadrant q = round(4u) taken on the integer, r = 4u - q exact,
+// x = r pi/2 (hi/lo), Taylor series of cos and sin to x^18 / x^19.
+#include "qtb_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace qtb {
+namespace {
+
+__device__ __forceinline__ void philox_4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ __forceinline__ double spec_log(double u)
+{
+    const uint64_t bits = __double_as_longlong(u);
+    int e = (int)((bits >> 52) & 0x7ff) - 1023;
+    double f = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) |
+                                                0x3FF0000000000000ull));
+    if (f > 1.4142135623730951) {
+        f = f * 0.5;
+        e = e + 1;
+    }
+    const double s = (f - 1.0) / (f + 1.0);
+    const double z = s * s;
+    double q = 1.0 / 23.0;
+    q = __builtin_fma(q, z, 1.0 / 21.0);
+    q = __builtin_fma(q, z, 1.0 / 19.0);
+    q = __builtin_fma(q, z, 1.0 / 17.0);
+    q = __builtin_fma(q, z, 1.0 / 15.0);
+    q = __builtin_fma(q, z, 1.0 / 13.0);
+    q = __builtin_fma(q, z, 1.0 / 11.0);
+    q = __builtin_fma(q, z, 1.0 / 9.0);
+    q = __builtin_fma(q, z, 1.0 / 7.0);
+    q = __builtin_fma(q, z, 1.0 / 5.0);
+    q = __builtin_fma(q, z, 1.0 / 3.0);
+    q = __builtin_fma(q, z, 1.0);
+    const double t = s * q;
+    const double lnf = t + t;
+    const double de = (double)e;
+    const double hi = de * 6.93147180369123816490e-01;
+    const double lo = __builtin_fma(de, 1.90821492927058770002e-10, lnf);
+    return hi + lo;
+}
+
+__device__ __forceinline__ double spec_cos2pi(uint64_t N)
+{
+    const uint64_t q = (N + (1ull << 50)) >> 51;
+    const int64_t rem = (int64_t)N - (int64_t)(q << 51);
+    const double r = (double)rem * 4.4408920985006262e-16;  // 2^-51
+    const double xh = r * 1.5707963267948966;
+    const double x = __builtin_fma(r, 6.123233995736766e-17, xh);
+    const double z = x * x;
+    double c = -1.0 / 6402373705728000.0;
+    c = __builtin_fma(c, z, 1.0 / 20922789888000.0);
+    c = __builtin_fma(c, z, -1.0 / 87178291200.0);
+    c = __builtin_fma(c, z, 1.0 / 479001600.0);
+    c = __builtin_fma(c, z, -1.0 / 3628800.0);
+    c = __builtin_fma(c, z, 1.0 / 40320.0);
+    c = __builtin_fma(c, z, -1.0 / 720.0);
+    c = __builtin_fma(c, z, 1.0 / 24.0);
+    c = __builtin_fma(c, z, -1.0 / 2.0);
+    const double cosx = __builtin_fma(c, z, 1.0);
+    double p = -1.0 / 121645100408832000.0;
+    p = __builtin_fma(p, z, 1.0 / 355687428096000.0);
+    p = __builtin_fma(p, z, -1.0 / 1307674368000.0);
+    p = __builtin_fma(p, z, 1.0 / 6227020800.0);
+    p = __builtin_fma(p, z, -1.0 / 39916800.0);
+    p = __builtin_fma(p, z, 1.0 / 362880.0);
+    p = __builtin_fma(p, z, -1.0 / 5040.0);
+    p = __builtin_fma(p, z, 1.0 / 120.0);
+    p = __builtin_fma(p, z, -1.0 / 6.0);
+    const double xz = x * z;
+    const double sinx = __builtin_fma(xz, p, x);
+    const uint32_t quad = (uint32_t)q & 3u;
+    const double v = (quad & 1u) ? sinx : cosx;
+    return (quad == 1u || quad == 2u) ? -v : v;
+}
+
+}  // namespace
+
+__device__ __forceinline__ double white_gauss(uint64_t seed, int64_t n, uint32_t d,
+                                              uint32_t stream, uint32_t tag)
+{
+    const uint64_t cnt = (uint64_t)(n + ((int64_t)1 << 40));
+    uint32_t c[4] = {(uint32_t)cnt, (uint32_t)(cnt >> 32), d, stream * 16u + tag};
+    philox_4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t m1 = ((uint64_t)(c[0] >> 6) << 26) | (uint64_t)(c[1] >> 6);
+    const uint64_t m2 = ((uint64_t)(c[2] >> 6) << 26) | (uint64_t)(c[3] >> 6);
+    const double u1 = (double)(2 * m1 + 1) * 1.1102230246251565e-16;  // 2^-53
+    const double a = -2.0 * spec_log(u1);
+    return __builtin_sqrt(a) * spec_cos2pi(2 * m2 + 1);
+}
+
+namespace {
+
+__global__ void k_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
+                           int64_t n_rows, uint32_t d0, uint32_t n_dof, double* __restrict__ out)
+{
+    const int64_t total = n_rows * (int64_t)n_dof;
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = id / n_dof;
+        const uint32_t j = (uint32_t)(id - r * n_dof);
+        out[id] = white_gauss(seed, n0 + r, d0 + j, stream, tag);
+    }
+}
+
+// White-noise rows m0 .. m0+rows-1 (global step index) for every column of
+// the concatenated replica dof ranges, stored at ring row m mod R.
+template <typename T>
+__global__ void k_gen_white(const RepDev* __restrict__ reps, const FirTile* __restrict__ tiles,
+                            T* __restrict__ ring, int64_t m0, int R, int64_t n_cols)
+{
+    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t m = m0 + blockIdx.y;
+    if (col >= n_cols) return;
+    const int tile = (int)(col / kDofTile);
+    const int rep = __builtin_amdgcn_readfirstlane(tiles[tile].rep);
+    const RepDev& Rp = reps[rep];
+    const int64_t d = col - Rp.dof_off;
+    const int64_t D = (int64_t)Rp.dims * Rp.N * Rp.P;
+    T w = T(0);
+    if (d < D) w = (T)white_gauss(Rp.seed, m + Rp.step_off, (uint32_t)d, Rp.stream, 0);
+    int64_t slot = m % R;
+    if (slot < 0) slot += R;
+    ring[slot * n_cols + col] = w;
+}
+
+}  // namespace
+
+void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
+                     int64_t n_rows, uint32_t d0, uint32_t n_dof, double* out)
+{
+    const int64_t total = n_rows * (int64_t)n_dof;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) return;
+    hipLaunchKernelGGL(k_gaussian, dim3((unsigned)blocks), dim3(256), 0, st, seed, stream, tag,
+                       n0, n_rows, d0, n_dof, out);
+}
+
+void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, void* ring,
+                      bool fp64, int64_t m0, int rows, int R, int64_t n_cols, int32_t)
+{
+    if (rows <= 0) return;
+    dim3 grid((unsigned)((n_cols + 255) / 256), (unsigned)rows);
+    if (fp64)
+        hipLaunchKernelGGL(k_gen_white<double>, grid, dim3(256), 0, st, reps, tiles,
+                           (double*)ring, m0, R, n_cols);
+    else
+        hipLaunchKernelGGL(k_gen_white<float>, grid, dim3(256), 0, st, reps, tiles,
+                           (float*)ring, m0, R, n_cols);
+}
+
+}  // namespace qtb

@@ -1,0 +1,864 @@
+// qtb_api.cpp -- the C ABI of libqtb.so (include/qtb.h): argument checks,
+// workspace layout, per-replica tables, and the step schedule.  All device
+// memory comes from the caller's workspace; all work goes on the caller's
+// stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "qtb_internal.h"
+
+namespace qtb {
+double design_theta(double omega, double T, double hbar, double kB);
+void design_taps(int kind, double T, int P, double dt, int two_nf, double hbar, double kB,
+                 double* out);
+}  // namespace qtb
+
+using namespace qtb;
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Region {
+    size_t off = 0, bytes = 0;
+};
+
+// Everything the workspace holds, in the order it is carved.
+struct Layout {
+    size_t total = 0;
+    Region reps, status, rebuild, tiles, taps, ring, zeta, partials, acc, counts, pairtab;
+    Region blk_upd, blk_nl, blk_force;
+    struct Per {
+        Region force, u, rref, r0, eatom, species, homega, nb, nbc, nm, ring;
+    };
+    std::vector<Per> per;
+    // derived sizes
+    int64_t n_cols = 0;
+    int R = 0, K = 0, max_two_nf = 0, taps_stride = 0;
+    std::vector<int64_t> dof_off;
+    std::vector<int> maxnb;
+    std::vector<BlockEntry> upd, nl, force;
+    std::vector<std::pair<int, std::pair<int, int>>> upd_groups;    // P -> [b0, b1)
+    std::vector<std::pair<int, std::pair<int, int>>> force_groups;  // G -> [b0, b1)
+    std::vector<int> obs_b0, obs_nb;
+    std::vector<FirTile> tilev;
+};
+
+int bead_group(int P)
+{
+    int G = 1;
+    while (G * 2 <= 8 && P % (G * 2) == 0) G *= 2;
+    return G;
+}
+
+size_t add(size_t& cur, Region& r, size_t bytes)
+{
+    r.off = cur;
+    r.bytes = bytes;
+    cur += align_up(bytes);
+    return r.off;
+}
+
+const char* check_inputs(const qtb_potential* pot, const qtb_replica* reps, int n_rep,
+                         const qtb_options* opt)
+{
+    if (!pot || !reps || !opt) return "null argument";
+    if (n_rep < 1) return "n_rep must be >= 1";
+    if (pot->kind != QTB_POT_PAIR && pot->kind != QTB_POT_HARMONIC) return "unknown potential kind";
+    if (pot->n_species < 1 || pot->n_species > QTB_MAX_SPECIES) return "n_species out of range";
+    if (!pot->mass) return "mass table missing";
+    for (int a = 0; a < pot->n_species; ++a)
+        if (!(pot->mass[a] > 0.0)) return "masses must be > 0";
+    if (pot->kind == QTB_POT_PAIR) {
+        if (!pot->charge || !pot->buck_A || !pot->buck_rho || !pot->buck_C)
+            return "pair potential tables missing";
+        if (!(pot->r_cut > 0.0)) return "r_cut must be > 0";
+        if (!(pot->skin >= 0.0)) return "skin must be >= 0";
+        if (!(pot->dsf_alpha >= 0.0)) return "dsf_alpha must be >= 0";
+        const int ns = pot->n_species;
+        for (int ab = 0; ab < ns * ns; ++ab)
+            if (pot->buck_A[ab] != 0.0 && !(pot->buck_rho[ab] > 0.0)) return "buck_rho must be > 0";
+    }
+    if (!(opt->hbar > 0.0) || !(opt->kB > 0.0) || !(opt->mass_unit > 0.0)) return "bad units";
+    if (opt->prec != QTB_PREC_FP32 && opt->prec != QTB_PREC_FP64) return "bad precision";
+    if (opt->fir < 0 || opt->fir > 3) return "bad FIR mode";
+    if ((opt->prec == QTB_PREC_FP64) != (opt->fir == QTB_FIR_FP64))
+        return "FP64 precision pairs with the FP64 FIR, FP32 with the FP32/BF16 FIRs";
+    if (opt->fir_block_K != 64 && opt->fir_block_K != 128 && opt->fir_block_K != 256)
+        return "fir_block_K must be 64, 128 or 256";
+    if (opt->obs_every < 0) return "obs_every must be >= 0";
+    if (opt->max_two_nf < 2 || (opt->max_two_nf & 1) || opt->max_two_nf > 8192)
+        return "max_two_nf must be even, in [2, 8192]";
+    if (opt->fir != QTB_FIR_FP64 && opt->max_two_nf > 4096) return "BF16/FP32 FIR: max_two_nf <= 4096";
+    for (int r = 0; r < n_rep; ++r) {
+        const qtb_replica& R = reps[r];
+        if (R.n_atoms < 1 || R.n_beads < 1 || R.n_beads > 64) return "replica sizes out of range";
+        if (R.n_dims != 1 && R.n_dims != 3) return "n_dims must be 1 or 3";
+        if (pot->kind == QTB_POT_PAIR && R.n_dims != 3) return "pair potential needs n_dims = 3";
+        if (R.noise < 0 || R.noise > 2) return "bad noise kind";
+        if (!(R.T > 0.0) || !(R.gamma >= 0.0) || !(R.dt > 0.0)) return "T, gamma, dt out of range";
+        if (!R.species || !R.d_pos || !R.d_vel) return "replica pointers missing";
+        if (pot->kind == QTB_POT_HARMONIC && !R.harm_omega) return "harmonic frequencies missing";
+        for (int i = 0; i < R.n_atoms; ++i)
+            if (R.species[i] < 0 || R.species[i] >= pot->n_species) return "species out of range";
+        if (pot->kind == QTB_POT_PAIR) {
+            for (int a = 0; a < 3; ++a)
+                if (!(R.box[a] > 0.0)) return "box lengths must be > 0";
+            if ((int64_t)R.n_atoms >= (1 << 30)) return "too many atoms";
+        }
+        if ((int64_t)R.n_dims * R.n_atoms * R.n_beads > (int64_t)1 << 31) return "too many dofs";
+    }
+    return nullptr;
+}
+
+int estimate_maxnb(const qtb_potential* pot, const qtb_replica& R)
+{
+    const double Rl = pot->r_cut + pot->skin;
+    const double vol = R.box[0] * R.box[1] * R.box[2];
+    const double n_est = 4.0 / 3.0 * kPi * Rl * Rl * Rl * R.n_atoms / vol;
+    int m = (int)std::ceil(1.3 * n_est + 48.0);
+    m = (m + 63) / 64 * 64;
+    return std::max(m, 64);
+}
+
+void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qtb_options* opt,
+          Layout& L)
+{
+    const bool pair = pot->kind == QTB_POT_PAIR;
+    const size_t ts = opt->prec == QTB_PREC_FP64 ? 8 : 4;   // force / u element
+    const size_t zs = opt->fir == QTB_FIR_FP64 ? 8 : 4;     // ring / zeta element
+    L.K = opt->fir_block_K;
+    L.max_two_nf = opt->max_two_nf;
+    L.R = L.K + opt->max_two_nf;
+    L.taps_stride = opt->max_two_nf + 2 * fir_pad();
+    L.per.assign(n_rep, {});
+    L.dof_off.assign(n_rep, 0);
+    L.maxnb.assign(n_rep, 0);
+    int64_t cols = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        const qtb_replica& R = reps[r];
+        L.dof_off[r] = cols;
+        const int64_t D = (int64_t)R.n_dims * R.n_atoms * R.n_beads;
+        cols += (D + kDofTile - 1) / kDofTile * kDofTile;
+        if (pair) L.maxnb[r] = estimate_maxnb(pot, R);
+    }
+    L.n_cols = cols;
+    // block tables
+    L.upd.clear(); L.nl.clear(); L.force.clear();
+    L.upd_groups.clear(); L.force_groups.clear();
+    std::map<int, std::vector<int>> byP, byG;
+    for (int r = 0; r < n_rep; ++r) {
+        byP[reps[r].n_beads].push_back(r);
+        byG[bead_group(reps[r].n_beads)].push_back(r);
+    }
+    for (auto& kv : byP) {
+        const int P = kv.first;
+        const int per = P <= 8 ? 256 : 64;
+        const int b0 = (int)L.upd.size();
+        for (int r : kv.second)
+            for (int a = 0; a < reps[r].n_atoms; a += per) L.upd.push_back({r, a, 0, 0});
+        L.upd_groups.push_back({P, {b0, (int)L.upd.size()}});
+    }
+    for (int r = 0; r < n_rep; ++r)
+        for (int a = 0; a < reps[r].n_atoms; a += 256) L.nl.push_back({r, a, 0, 0});
+    L.obs_b0.assign(n_rep, 0);
+    L.obs_nb.assign(n_rep, 0);
+    for (auto& kv : byG) {
+        const int G = kv.first;
+        const int b0 = (int)L.force.size();
+        for (int r : kv.second) {
+            L.obs_b0[r] = (int)L.force.size();
+            if (pair) {
+                for (int g = 0; g < reps[r].n_beads / G; ++g)
+                    for (int a = 0; a < reps[r].n_atoms; a += kAtomsPerBlock)
+                        L.force.push_back({r, a, g, 0});
+            } else {
+                for (int a = 0; a < reps[r].n_atoms; a += 256) L.force.push_back({r, a, 0, 0});
+            }
+            L.obs_nb[r] = (int)L.force.size() - L.obs_b0[r];
+        }
+        L.force_groups.push_back({pair ? G : 0, {b0, (int)L.force.size()}});
+        if (!pair) break;  // harmonic: every replica went into the first group
+    }
+    if (!pair) {
+        // harmonic kernel ignores G; rebuild a single group over all replicas
+        L.force.clear();
+        L.force_groups.clear();
+        for (int r = 0; r < n_rep; ++r) {
+            L.obs_b0[r] = (int)L.force.size();
+            for (int a = 0; a < reps[r].n_atoms; a += 256) L.force.push_back({r, a, 0, 0});
+            L.obs_nb[r] = (int)L.force.size() - L.obs_b0[r];
+        }
+        L.force_groups.push_back({0, {0, (int)L.force.size()}});
+    }
+    L.tilev.assign(cols / kDofTile, FirTile{0, 2, 0, 0});
+    for (int r = 0; r < n_rep; ++r) {
+        const int64_t D = (int64_t)reps[r].n_dims * reps[r].n_atoms * reps[r].n_beads;
+        const int64_t nt = (D + kDofTile - 1) / kDofTile;
+        for (int64_t t = 0; t < nt; ++t)
+            L.tilev[L.dof_off[r] / kDofTile + t] = FirTile{r, 2, r * L.taps_stride, 0};
+    }
+
+    size_t cur = 0;
+    add(cur, L.reps, sizeof(RepDev) * n_rep);
+    add(cur, L.status, 64);
+    add(cur, L.rebuild, sizeof(int32_t) * n_rep);
+    add(cur, L.tiles, sizeof(FirTile) * L.tilev.size());
+    add(cur, L.taps, zs * (size_t)L.taps_stride * n_rep);
+    add(cur, L.ring, zs * (size_t)L.R * cols);
+    add(cur, L.zeta, zs * (size_t)L.K * cols);
+    add(cur, L.partials, sizeof(double) * kNobs * std::max<size_t>(1, L.force.size()));
+    add(cur, L.acc, sizeof(double) * kNobs * n_rep);
+    add(cur, L.counts, sizeof(int32_t) * n_rep);
+    add(cur, L.pairtab, sizeof(PairTable<double>));
+    add(cur, L.blk_upd, sizeof(BlockEntry) * std::max<size_t>(1, L.upd.size()));
+    add(cur, L.blk_nl, sizeof(BlockEntry) * std::max<size_t>(1, L.nl.size()));
+    add(cur, L.blk_force, sizeof(BlockEntry) * std::max<size_t>(1, L.force.size()));
+    for (int r = 0; r < n_rep; ++r) {
+        const qtb_replica& R = reps[r];
+        const size_t N = R.n_atoms, P = R.n_beads, dm = R.n_dims;
+        auto& p = L.per[r];
+        add(cur, p.force, ts * P * dm * N);
+        add(cur, p.r0, 8 * P * dm * N);
+        add(cur, p.eatom, 8 * P * N);
+        add(cur, p.species, 4 * N);
+        add(cur, p.nm, 8 * P * P);
+        add(cur, p.ring, 8 * 3 * P);
+        if (pair) {
+            add(cur, p.u, 4 * ts * P * N);
+            add(cur, p.rref, 8 * 3 * N);
+            add(cur, p.nb, 4 * ts * N * (size_t)L.maxnb[r]);
+            add(cur, p.nbc, 4 * N);
+        } else {
+            add(cur, p.homega, 8 * N);
+        }
+    }
+    L.total = cur;
+}
+
+std::string g_static_err;
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct qtb_ctx {
+    qtb_options opt{};
+    hipStream_t st = nullptr;
+    bool fp64 = false, pair = false;
+    int n_rep = 0;
+    std::vector<qtb_replica> reps;
+    std::vector<std::vector<int32_t>> species;
+    std::vector<std::vector<double>> homega;
+    std::vector<double> mass, charge, bA, brho, bC;
+    double alpha = 0, rc = 0, skin = 0;
+    Layout L;
+    char* ws = nullptr;
+    std::vector<RepDev> rd;
+    std::vector<int> two_nf;
+    std::vector<bool> filter_ready;
+    std::vector<std::vector<double>> taps;
+    std::vector<double> eself;
+    PairTable<float> tabf{};
+    PairTable<double> tabd{};
+    int64_t step = 0;          // global step counter
+    int64_t block_start = -1;  // global step of the current noise block
+    int block_row = 0;
+    bool ring_valid = false;
+    int64_t ring_hi = 0;       // last generated ring row (global step)
+    std::string err;
+
+    template <typename X>
+    X* at(const Region& r) const { return reinterpret_cast<X*>(ws + r.off); }
+};
+
+namespace {
+
+qtb_status fail(qtb_ctx* c, qtb_status s, const std::string& m)
+{
+    if (c) c->err = m;
+    else g_static_err = m;
+    return s;
+}
+
+qtb_status hip_check(qtb_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return QTB_OK;
+    return fail(c, QTB_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define QTB_HIP(c, call)                                               \
+    do {                                                               \
+        qtb_status s_ = hip_check((c), (call), #call);                 \
+        if (s_ != QTB_OK) return s_;                                   \
+    } while (0)
+
+void nm_matrix(int P, double* C)
+{
+    for (int s = 0; s < P; ++s)
+        for (int k = 0; k < P; ++k) {
+            double v;
+            if (k == 0) v = 1.0 / std::sqrt((double)P);
+            else if (2 * k < P) v = std::sqrt(2.0 / P) * std::cos(2.0 * kPi * s * k / P);
+            else if (2 * k == P) v = ((s % 2) ? -1.0 : 1.0) / std::sqrt((double)P);
+            else v = std::sqrt(2.0 / P) * std::sin(2.0 * kPi * s * k / P);
+            C[s * P + k] = v;
+        }
+}
+
+template <typename T>
+void fill_pair_table(qtb_ctx* c, PairTable<T>& tab)
+{
+    const int ns = (int)c->mass.size();
+    const double rc = c->rc, al = c->alpha, k = c->opt.coulomb_k;
+    const double g = 2.0 * al / std::sqrt(kPi);
+    const double erc = std::erfc(al * rc);
+    const double Sc = erc / (rc * rc) + g * std::exp(-al * al * rc * rc) / rc;
+    std::memset(&tab, 0, sizeof(tab));
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) {
+            const int ab = a * ns + b;
+            const double A = c->bA[ab], rho = c->brho[ab], C = c->bC[ab];
+            const double irho = A != 0.0 ? 1.0 / rho : 0.0;
+            const double VB = A * std::exp(-rc * irho) - C / std::pow(rc, 6);
+            const double dVB = -A * irho * std::exp(-rc * irho) + 6.0 * C / std::pow(rc, 7);
+            const double kqq = k * c->charge[a] * c->charge[b];
+            const double F0 = dVB - kqq * Sc;
+            const double E0 = -VB + rc * dVB - kqq * erc / rc - kqq * Sc * rc;
+            PairParam<T>& p = tab.p[a * kMaxSpecies + b];
+            p.Arho = (T)(A * irho);
+            p.irho = (T)irho;
+            p.C6 = (T)(6.0 * C);
+            p.kqq = (T)kqq;
+            p.F0 = (T)F0;
+            p.A = (T)A;
+            p.C = (T)C;
+            p.E0 = (T)E0;
+        }
+    tab.alpha = (T)al;
+    tab.g = (T)g;
+    tab.rc2 = (T)(rc * rc);
+    tab.n_species = ns;
+}
+
+void fill_repdev(qtb_ctx* c, int r)
+{
+    const qtb_replica& R = c->reps[r];
+    const Layout::Per& p = c->L.per[r];
+    RepDev& d = c->rd[r];
+    d.pos = R.d_pos;
+    d.vel = R.d_vel;
+    d.force = c->at<void>(p.force);
+    d.u = c->pair ? c->at<void>(p.u) : nullptr;
+    d.rref = c->pair ? c->at<double>(p.rref) : nullptr;
+    d.r0 = c->at<double>(p.r0);
+    d.eatom = c->at<double>(p.eatom);
+    d.species = c->at<int32_t>(p.species);
+    d.homega = c->pair ? nullptr : c->at<double>(p.homega);
+    d.nb_entries = c->pair ? c->at<void>(p.nb) : nullptr;
+    d.nb_count = c->pair ? c->at<int32_t>(p.nbc) : nullptr;
+    d.nm = c->at<double>(p.nm);
+    d.ring = c->at<double>(p.ring);
+    d.rebuild = c->at<int32_t>(c->L.rebuild) + r;
+    d.dof_off = c->L.dof_off[r];
+    d.N = R.n_atoms;
+    d.P = R.n_beads;
+    d.dims = R.n_dims;
+    d.maxnb = c->pair ? c->L.maxnb[r] : 0;
+    d.two_nf = c->two_nf[r];
+    d.noise = R.noise;
+    d.obs_block0 = c->L.obs_b0[r];
+    d.obs_nblocks = c->L.obs_nb[r];
+    for (int a = 0; a < 3; ++a) d.box[a] = R.box[a];
+    d.c1 = std::exp(-R.gamma * R.dt);
+    d.kT = c->opt.kB * R.T;
+    d.omega_P = std::sqrt((double)R.n_beads) * d.kT / c->opt.hbar;
+    d.u_lim = c->skin / (2.0 * std::sqrt(3.0));
+    d.r_skin2 = (c->rc + c->skin) * (c->rc + c->skin);
+    for (int a = 0; a < kMaxSpecies; ++a) {
+        const double m = a < (int)c->mass.size() ? c->mass[a] * c->opt.mass_unit : 1.0;
+        d.mmu[a] = m;
+        d.kick[a] = R.dt / (2.0 * R.n_beads * m);
+        d.sigma[a] = std::sqrt((1.0 - d.c1 * d.c1) / m);
+    }
+    d.seed = R.seed;
+    d.stream = R.stream;
+}
+
+qtb_status upload_tables(qtb_ctx* c)
+{
+    QTB_HIP(c, hipMemcpyAsync(c->at<void>(c->L.reps), c->rd.data(), sizeof(RepDev) * c->n_rep,
+                              hipMemcpyHostToDevice, c->st));
+    QTB_HIP(c, hipMemcpyAsync(c->at<void>(c->L.tiles), c->L.tilev.data(),
+                              sizeof(FirTile) * c->L.tilev.size(), hipMemcpyHostToDevice, c->st));
+    return QTB_OK;
+}
+
+template <typename Z>
+qtb_status upload_taps_T(qtb_ctx* c, int r)
+{
+    std::vector<Z> buf(c->L.taps_stride, Z(0));
+    const int pad = fir_pad();
+    for (int x = 0; x < c->two_nf[r]; ++x) buf[pad + x] = (Z)c->taps[r][x];
+    QTB_HIP(c, hipMemcpyAsync(c->at<Z>(c->L.taps) + (size_t)r * c->L.taps_stride, buf.data(),
+                              sizeof(Z) * buf.size(), hipMemcpyHostToDevice, c->st));
+    return hipStreamSynchronize(c->st) == hipSuccess ? QTB_OK
+                                                      : fail(c, QTB_E_DEVICE, "taps upload");
+}
+
+qtb_status upload_taps(qtb_ctx* c, int r)
+{
+    if (c->opt.fir == QTB_FIR_FP64) return upload_taps_T<double>(c, r);
+    return upload_taps_T<float>(c, r);
+}
+
+// Force evaluation of every replica (no kick), used at init and set_state.
+void launch_forces(qtb_ctx* c, int32_t flags)
+{
+    const Layout& L = c->L;
+    const RepDev* dreps = c->at<RepDev>(L.reps);
+    const BlockEntry* fb = c->at<BlockEntry>(L.blk_force);
+    double* part = c->at<double>(L.partials);
+    for (auto& g : L.force_groups) {
+        const int b0 = g.second.first, nb = g.second.second - g.second.first;
+        if (nb <= 0) continue;
+        if (c->pair) {
+            const void* tab = c->fp64 ? (const void*)&c->tabd : (const void*)&c->tabf;
+            launch_forces_pair(c->st, c->fp64, g.first, dreps, fb + b0, nb, tab, flags,
+                               part + (size_t)b0 * kNobs, c->at<int32_t>(L.rebuild), c->n_rep);
+        } else {
+            launch_forces_harmonic(c->st, c->fp64, dreps, fb + b0, nb, flags,
+                                   part + (size_t)b0 * kNobs);
+        }
+    }
+}
+
+void launch_rebuild(qtb_ctx* c)
+{
+    if (!c->pair) return;
+    const Layout& L = c->L;
+    launch_nlist(c->st, c->fp64, c->at<RepDev>(L.reps), c->at<BlockEntry>(L.blk_nl),
+                 (int)L.nl.size(), c->at<int32_t>(L.status));
+}
+
+qtb_status refresh_forces(qtb_ctx* c)
+{
+    if (c->pair) {
+        launch_fill(c->st, c->at<int32_t>(c->L.rebuild), c->n_rep, 1);
+        launch_rebuild(c);
+    }
+    launch_forces(c, 0);
+    QTB_HIP(c, hipGetLastError());
+    return QTB_OK;
+}
+
+qtb_status read_status(qtb_ctx* c)
+{
+    int32_t st[2] = {0, 0};
+    QTB_HIP(c, hipMemcpyAsync(st, c->at<int32_t>(c->L.status), sizeof(st), hipMemcpyDeviceToHost,
+                              c->st));
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    if (st[0] & kStatusNbOverflow)
+        return fail(c, QTB_E_NOMEM, "neighbour list overflow: density above the planned maximum");
+    if (st[0] & kStatusNonfinite) return fail(c, QTB_E_NONFINITE, "non-finite position or velocity");
+    return QTB_OK;
+}
+
+// Generate white-noise rows (global steps) lo..hi into the ring.
+void gen_rows(qtb_ctx* c, int64_t lo, int64_t hi)
+{
+    if (hi < lo) return;
+    const Layout& L = c->L;
+    const int64_t rows = hi - lo + 1;
+    for (int64_t m0 = lo; m0 <= hi; m0 += 1024) {
+        const int rr = (int)std::min<int64_t>(1024, hi - m0 + 1);
+        launch_gen_white(c->st, c->at<RepDev>(L.reps), c->at<FirTile>(L.tiles),
+                         c->at<void>(L.ring), c->opt.fir == QTB_FIR_FP64, m0, rr, L.R, L.n_cols,
+                         (int)L.tilev.size());
+    }
+    (void)rows;
+    c->ring_hi = hi;
+}
+
+void start_block(qtb_ctx* c)
+{
+    const Layout& L = c->L;
+    const int maxNf = L.max_two_nf / 2;
+    const int64_t nb = c->step;
+    if (!c->ring_valid) {
+        gen_rows(c, nb - maxNf + 1, nb + maxNf - 1);
+        c->ring_valid = true;
+    }
+    gen_rows(c, nb + maxNf, nb + L.K - 1 + maxNf);
+    launch_fir(c->st, c->opt.fir, L.K, c->at<FirTile>(L.tiles), (int)L.tilev.size(),
+               c->at<void>(L.taps), c->at<void>(L.ring), c->at<void>(L.zeta), L.n_cols, nb, L.R,
+               L.max_two_nf);
+    c->block_start = nb;
+    c->block_row = 0;
+}
+
+void one_step(qtb_ctx* c)
+{
+    const Layout& L = c->L;
+    if (c->block_start < 0 || c->block_row >= L.K) start_block(c);
+    const size_t zs = c->opt.fir == QTB_FIR_FP64 ? 8 : 4;
+    const char* zrow = c->at<char>(L.zeta) + (size_t)c->block_row * L.n_cols * zs;
+    const RepDev* dreps = c->at<RepDev>(L.reps);
+    const BlockEntry* ub = c->at<BlockEntry>(L.blk_upd);
+    for (auto& g : L.upd_groups) {
+        const int b0 = g.second.first, nb = g.second.second - g.second.first;
+        if (nb > 0)
+            launch_update(c->st, c->fp64, c->pair, g.first, dreps, ub + b0, nb, zrow,
+                          c->at<int32_t>(L.status));
+    }
+    launch_rebuild(c);
+    const bool sample = c->opt.obs_every > 0 && ((c->step + 1) % c->opt.obs_every) == 0;
+    launch_forces(c, kKick | (sample ? kSample : 0));
+    if (sample)
+        launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
+                          c->at<int32_t>(L.counts));
+    c->step += 1;
+    c->block_row += 1;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+size_t qtb_workspace_bytes(const qtb_potential* pot, const qtb_replica* reps, int32_t n_rep,
+                           const qtb_options* opt)
+{
+    if (check_inputs(pot, reps, n_rep, opt)) return 0;
+    Layout L;
+    plan(pot, reps, n_rep, opt, L);
+    return L.total;
+}
+
+qtb_status qtb_init(qtb_ctx** out, const qtb_potential* pot, const qtb_replica* reps,
+                    int32_t n_rep, const qtb_options* opt, void* d_workspace, size_t ws_bytes,
+                    void* hip_stream)
+{
+    if (!out) return fail(nullptr, QTB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (const char* e = check_inputs(pot, reps, n_rep, opt)) return fail(nullptr, QTB_E_INVALID, e);
+    if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0)
+        return fail(nullptr, QTB_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    qtb_ctx* c = new qtb_ctx();
+    c->opt = *opt;
+    c->st = (hipStream_t)hip_stream;
+    c->fp64 = opt->prec == QTB_PREC_FP64;
+    c->pair = pot->kind == QTB_POT_PAIR;
+    c->n_rep = n_rep;
+    c->reps.assign(reps, reps + n_rep);
+    const int ns = pot->n_species;
+    c->mass.assign(pot->mass, pot->mass + ns);
+    if (c->pair) {
+        c->charge.assign(pot->charge, pot->charge + ns);
+        c->bA.assign(pot->buck_A, pot->buck_A + ns * ns);
+        c->brho.assign(pot->buck_rho, pot->buck_rho + ns * ns);
+        c->bC.assign(pot->buck_C, pot->buck_C + ns * ns);
+        c->alpha = pot->dsf_alpha;
+        c->rc = pot->r_cut;
+        c->skin = pot->skin;
+    }
+    plan(pot, reps, n_rep, opt, c->L);
+    if (ws_bytes < c->L.total) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "workspace too small: %zu < %zu bytes", ws_bytes,
+                      c->L.total);
+        delete c;
+        return fail(nullptr, QTB_E_NOMEM, msg);
+    }
+    c->ws = (char*)d_workspace;
+    c->two_nf.assign(n_rep, 2);
+    c->filter_ready.assign(n_rep, false);
+    c->taps.assign(n_rep, {});
+    c->eself.assign(n_rep, 0.0);
+    c->rd.assign(n_rep, RepDev{});
+    c->species.resize(n_rep);
+    c->homega.resize(n_rep);
+    if (c->pair) {
+        fill_pair_table(c, c->tabf);
+        fill_pair_table(c, c->tabd);
+    }
+    qtb_status s = QTB_OK;
+    auto bail = [&](qtb_status st) {
+        std::string m = c->err;
+        delete c;
+        fail(nullptr, st, m);
+        return st;
+    };
+    // zero every region first (fill kernel; the caller may capture later work)
+    launch_fill(c->st, c->ws, (int64_t)(c->L.total / 4), 0);
+    for (int r = 0; r < n_rep; ++r) {
+        const qtb_replica& R = reps[r];
+        c->species[r].assign(R.species, R.species + R.n_atoms);
+        if (!c->pair) c->homega[r].assign(R.harm_omega, R.harm_omega + R.n_atoms);
+        fill_repdev(c, r);
+        const Layout::Per& p = c->L.per[r];
+        const int P = R.n_beads;
+        std::vector<double> C(P * P), ring(3 * P);
+        nm_matrix(P, C.data());
+        const double h = 0.5 * R.dt;
+        const double wP = c->rd[r].omega_P;
+        for (int k = 0; k < P; ++k) {
+            const double w = 2.0 * wP * std::sin(kPi * k / P);
+            if (k == 0) {
+                ring[k] = 1.0; ring[P + k] = h; ring[2 * P + k] = 0.0;
+            } else {
+                ring[k] = std::cos(w * h);
+                ring[P + k] = std::sin(w * h) / w;
+                ring[2 * P + k] = -w * std::sin(w * h);
+            }
+        }
+        if ((s = hip_check(c, hipMemcpyAsync(c->at<void>(p.nm), C.data(), 8 * C.size(),
+                                             hipMemcpyHostToDevice, c->st), "nm")) ||
+            (s = hip_check(c, hipMemcpyAsync(c->at<void>(p.ring), ring.data(), 8 * ring.size(),
+                                             hipMemcpyHostToDevice, c->st), "ring")) ||
+            (s = hip_check(c, hipMemcpyAsync(c->at<void>(p.species), c->species[r].data(),
+                                             4 * R.n_atoms, hipMemcpyHostToDevice, c->st), "species")) ||
+            (s = hip_check(c, hipMemcpyAsync(c->at<void>(p.r0), R.d_pos,
+                                             8 * (size_t)P * R.n_dims * R.n_atoms,
+                                             hipMemcpyDeviceToDevice, c->st), "r0")))
+            return bail(s);
+        if (!c->pair &&
+            (s = hip_check(c, hipMemcpyAsync(c->at<void>(p.homega), c->homega[r].data(),
+                                             8 * R.n_atoms, hipMemcpyHostToDevice, c->st), "homega")))
+            return bail(s);
+        // default filter: white noise, sqrt(kT) delta
+        c->taps[r].assign(2, 0.0);
+        c->taps[r][1] = std::sqrt(opt->kB * R.T);
+        c->filter_ready[r] = (R.noise == QTB_NOISE_CLASSICAL);
+        if (c->pair) {
+            double q2 = 0.0;
+            for (int i = 0; i < R.n_atoms; ++i) q2 += c->charge[R.species[i]] * c->charge[R.species[i]];
+            c->eself[r] = -(std::erfc(c->alpha * c->rc) / (2.0 * c->rc) + c->alpha / std::sqrt(kPi)) *
+                          opt->coulomb_k * q2;
+        }
+    }
+    if ((s = upload_tables(c))) return bail(s);
+    if ((s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.blk_upd), c->L.upd.data(),
+                                         sizeof(BlockEntry) * c->L.upd.size(), hipMemcpyHostToDevice, c->st), "blk")) ||
+        (s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.blk_nl), c->L.nl.data(),
+                                         sizeof(BlockEntry) * c->L.nl.size(), hipMemcpyHostToDevice, c->st), "blk")) ||
+        (s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.blk_force), c->L.force.data(),
+                                         sizeof(BlockEntry) * c->L.force.size(), hipMemcpyHostToDevice, c->st), "blk")))
+        return bail(s);
+    for (int r = 0; r < n_rep; ++r)
+        if ((s = upload_taps(c, r))) return bail(s);
+    if ((s = refresh_forces(c))) return bail(s);
+    if ((s = read_status(c))) return bail(s);
+    *out = c;
+    return QTB_OK;
+}
+
+qtb_status qtb_build_filter(qtb_ctx* c, int32_t replica, int32_t kind, int32_t two_nf,
+                            double* taps_out)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (replica < -1 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    if (kind < 0 || kind > 2) return fail(c, QTB_E_INVALID, "bad noise kind");
+    if (two_nf < 2 || (two_nf & 1) || two_nf > c->opt.max_two_nf)
+        return fail(c, QTB_E_INVALID, "two_nf must be even and in [2, max_two_nf]");
+    const int r0 = replica < 0 ? 0 : replica, r1 = replica < 0 ? c->n_rep : replica + 1;
+    for (int r = r0; r < r1; ++r)
+        if (c->reps[r].noise != kind)
+            return fail(c, QTB_E_STATE, "filter kind differs from the replica's noise kind");
+    for (int r = r0; r < r1; ++r) {
+        const qtb_replica& R = c->reps[r];
+        c->taps[r].assign(two_nf, 0.0);
+        design_taps(kind, R.T, R.n_beads, R.dt, two_nf, c->opt.hbar, c->opt.kB, c->taps[r].data());
+        c->two_nf[r] = two_nf;
+        c->rd[r].two_nf = two_nf;
+        for (auto& t : c->L.tilev)
+            if (t.rep == r) t.two_nf = two_nf;
+        qtb_status s = upload_taps(c, r);
+        if (s) return s;
+        c->filter_ready[r] = true;
+        if (taps_out && replica >= 0) std::memcpy(taps_out, c->taps[r].data(), 8 * (size_t)two_nf);
+    }
+    qtb_status s = upload_tables(c);
+    if (s) return s;
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    // the current noise block (if any) was filtered with the old taps: restart
+    c->block_start = -1;
+    return QTB_OK;
+}
+
+qtb_status qtb_step(qtb_ctx* c, int64_t n_steps)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (n_steps < 0) return fail(c, QTB_E_INVALID, "n_steps must be >= 0");
+    for (int r = 0; r < c->n_rep; ++r)
+        if (!c->filter_ready[r]) return fail(c, QTB_E_STATE, "qtb_build_filter not called");
+    for (int64_t it = 0; it < n_steps; ++it) one_step(c);
+    QTB_HIP(c, hipGetLastError());
+    return QTB_OK;
+}
+
+qtb_status qtb_observables(qtb_ctx* c, int32_t replica, qtb_obs* out)
+{
+    if (!c || !out) return fail(c, QTB_E_INVALID, "null argument");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    double acc[kNobs];
+    int32_t cnt = 0;
+    QTB_HIP(c, hipMemcpyAsync(acc, c->at<double>(c->L.acc) + (size_t)replica * kNobs,
+                              sizeof(acc), hipMemcpyDeviceToHost, c->st));
+    QTB_HIP(c, hipMemcpyAsync(&cnt, c->at<int32_t>(c->L.counts) + replica, 4,
+                              hipMemcpyDeviceToHost, c->st));
+    qtb_status s = read_status(c);
+    launch_fill(c->st, c->at<double>(c->L.acc) + (size_t)replica * kNobs, 2 * kNobs, 0);
+    launch_fill(c->st, c->at<int32_t>(c->L.counts) + replica, 1, 0);
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    const qtb_replica& R = c->reps[replica];
+    std::memset(out, 0, sizeof(*out));
+    out->step = c->step + (int64_t)0;
+    out->n_samples = cnt;
+    if (cnt > 0) {
+        const double inv = 1.0 / cnt;
+        const double kT = c->opt.kB * R.T;
+        const double ke = acc[0] * inv, U = acc[1] * inv + c->eself[replica],
+                     spr = acc[2] * inv, vir = acc[3] * inv, x2 = acc[4] * inv;
+        const double dof = (double)R.n_dims * R.n_atoms;
+        out->kinetic = ke;
+        out->potential = U;
+        out->spring = spr;
+        out->e_primitive = ke - spr + U;
+        out->e_virial = 0.5 * dof * kT - vir / (2.0 * R.n_beads) + U;
+        out->t_kinetic = 2.0 * ke / (dof * R.n_beads * c->opt.kB);
+        out->x2_mean = x2 / (dof * R.n_beads);
+    }
+    return s;
+}
+
+qtb_status qtb_get_state(qtb_ctx* c, int32_t replica, double* h_pos, double* h_vel,
+                         int64_t* step)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    const qtb_replica& R = c->reps[replica];
+    const size_t n = (size_t)R.n_beads * R.n_dims * R.n_atoms * 8;
+    if (h_pos) QTB_HIP(c, hipMemcpyAsync(h_pos, R.d_pos, n, hipMemcpyDeviceToHost, c->st));
+    if (h_vel) QTB_HIP(c, hipMemcpyAsync(h_vel, R.d_vel, n, hipMemcpyDeviceToHost, c->st));
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    if (step) *step = c->step + c->rd[replica].step_off;
+    return QTB_OK;
+}
+
+qtb_status qtb_set_state(qtb_ctx* c, int32_t replica, const double* h_pos, const double* h_vel,
+                         int64_t step)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    const qtb_replica& R = c->reps[replica];
+    const size_t n = (size_t)R.n_beads * R.n_dims * R.n_atoms * 8;
+    if (h_pos) {
+        QTB_HIP(c, hipMemcpyAsync(R.d_pos, h_pos, n, hipMemcpyHostToDevice, c->st));
+        QTB_HIP(c, hipMemcpyAsync(c->at<void>(c->L.per[replica].r0), h_pos, n,
+                                  hipMemcpyHostToDevice, c->st));
+    }
+    if (h_vel) QTB_HIP(c, hipMemcpyAsync(R.d_vel, h_vel, n, hipMemcpyHostToDevice, c->st));
+    const int64_t off = step - c->step;
+    if (off != c->rd[replica].step_off) {
+        c->rd[replica].step_off = off;
+        c->ring_valid = false;
+        c->block_start = -1;
+        qtb_status s = upload_tables(c);
+        if (s) return s;
+    }
+    launch_fill(c->st, c->at<int32_t>(c->L.status), 1, 0);
+    qtb_status s = refresh_forces(c);
+    if (s) return s;
+    return read_status(c);
+}
+
+qtb_status qtb_evaluate(qtb_ctx* c, int32_t replica, double* h_force, double* h_epot)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    if (c->pair) launch_rebuild(c);  // no-op unless a rebuild is pending
+    launch_forces(c, kEvaluate);
+    QTB_HIP(c, hipGetLastError());
+    const qtb_replica& R = c->reps[replica];
+    const Layout::Per& p = c->L.per[replica];
+    const size_t nf = (size_t)R.n_beads * R.n_dims * R.n_atoms;
+    if (h_force) {
+        if (c->fp64) {
+            QTB_HIP(c, hipMemcpyAsync(h_force, c->at<void>(p.force), 8 * nf, hipMemcpyDeviceToHost, c->st));
+            QTB_HIP(c, hipStreamSynchronize(c->st));
+        } else {
+            std::vector<float> tmp(nf);
+            QTB_HIP(c, hipMemcpyAsync(tmp.data(), c->at<void>(p.force), 4 * nf, hipMemcpyDeviceToHost, c->st));
+            QTB_HIP(c, hipStreamSynchronize(c->st));
+            for (size_t q = 0; q < nf; ++q) h_force[q] = tmp[q];
+        }
+    }
+    if (h_epot) {
+        std::vector<double> ea((size_t)R.n_beads * R.n_atoms);
+        QTB_HIP(c, hipMemcpyAsync(ea.data(), c->at<void>(p.eatom), 8 * ea.size(), hipMemcpyDeviceToHost, c->st));
+        QTB_HIP(c, hipStreamSynchronize(c->st));
+        for (int s = 0; s < R.n_beads; ++s) {
+            double e = 0.0;
+            for (int i = 0; i < R.n_atoms; ++i) e += ea[(size_t)s * R.n_atoms + i];
+            h_epot[s] = e + c->eself[replica];
+        }
+    }
+    return read_status(c);
+}
+
+qtb_status qtb_get_noise(qtb_ctx* c, int32_t replica, double* h_zeta, int64_t* n0)
+{
+    if (!c || !h_zeta) return fail(c, QTB_E_INVALID, "null argument");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    if (c->block_start < 0) return fail(c, QTB_E_STATE, "no noise block computed yet");
+    const qtb_replica& R = c->reps[replica];
+    const int64_t D = (int64_t)R.n_dims * R.n_atoms * R.n_beads;
+    const size_t zs = c->opt.fir == QTB_FIR_FP64 ? 8 : 4;
+    const int K = c->L.K;
+    std::vector<char> buf((size_t)K * D * zs);
+    QTB_HIP(c, hipMemcpy2DAsync(buf.data(), D * zs,
+                                c->at<char>(c->L.zeta) + c->L.dof_off[replica] * zs,
+                                c->L.n_cols * zs, D * zs, K, hipMemcpyDeviceToHost, c->st));
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    for (size_t q = 0; q < (size_t)K * D; ++q)
+        h_zeta[q] = zs == 8 ? ((double*)buf.data())[q] : (double)((float*)buf.data())[q];
+    if (n0) *n0 = c->block_start + c->rd[replica].step_off;
+    return QTB_OK;
+}
+
+qtb_status qtb_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0, int64_t n_rows,
+                        uint32_t d0, uint32_t n_dof, double* d_out, void* hip_stream)
+{
+    if (!d_out || n_rows < 0) return fail(nullptr, QTB_E_INVALID, "bad gaussian arguments");
+    launch_gaussian((hipStream_t)hip_stream, seed, stream, tag, n0, n_rows, d0, n_dof, d_out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, QTB_E_DEVICE, hipGetErrorString(e));
+    return QTB_OK;
+}
+
+const char* qtb_last_error(const qtb_ctx* c)
+{
+    if (c) return c->err.c_str();
+    return g_static_err.c_str();
+}
+
+void qtb_destroy(qtb_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->st);
+    delete c;
+}
+
+const char* qtb_version(void) { return "qtb-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// qtb_internal.h -- structures shared by the host side of libqtb.so and its
+// HIP kernels (gfx950).  Not part of the public ABI (include/qtb.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "qtb.h"
+
+namespace qtb {
+
+constexpr int kMaxSpecies = QTB_MAX_SPECIES;
+constexpr int kPairs = kMaxSpecies * kMaxSpecies;
+constexpr int kDofTile = 256;      // replica dof ranges are padded to this
+constexpr int kAtomsPerBlock = 4;  // force kernel: one wavefront per atom
+constexpr int kNobs = 6;           // ke, U, spring, virial, x2, (unused)
+
+// Pair potential in the form the force kernels evaluate:
+//   F(r) = -dV/dr = Arho e^{-r irho} - C6 r^-7
+//                   + kqq [erfc(a r)/r^2 + g e^{-a^2 r^2}/r] + F0
+//   V(r) = A e^{-r irho} - C r^-6 + kqq erfc(a r)/r - F0 r + E0
+// where the constants fold the shifted-force Buckingham and the damped
+// shifted force Coulomb terms (both vanish with their slope at r_cut).
+template <typename T>
+struct PairParam {
+    T Arho, irho, C6, kqq, F0, A, C, E0;
+};
+
+template <typename T>
+struct PairTable {
+    PairParam<T> p[kPairs];
+    T alpha, g, rc2;
+    int32_t n_species;
+};
+
+// Per-replica description the kernels read (device copy in the workspace).
+struct RepDev {
+    double* pos;         // [P][dims][N]
+    double* vel;         // [P][dims][N]
+    void* force;         // T [P][dims][N]
+    void* u;             // T4 [P][N]: position minus reference, species bits in .w
+    double* rref;        // [3][N] reference positions (bead centroids at the last build)
+    double* r0;          // [P][dims][N] positions given at init / set_state
+    double* eatom;       // [P][N] per-atom energies (evaluate mode)
+    const int32_t* species;  // [N]
+    const double* homega;    // [N]
+    void* nb_entries;        // T4 [N][maxnb]: reference displacement d_ij, j bits in .w
+    int32_t* nb_count;       // [N]
+    const double* nm;        // [P][P] orthonormal normal-mode matrix C[s][k]
+    const double* ring;      // [3][P]: cos(w h), sin(w h)/w, -w sin(w h), h = dt/2
+    int32_t* rebuild;        // neighbour-list rebuild flag
+    int64_t dof_off;         // first column in the global noise arrays
+    int64_t step_off;        // replica step = global step + step_off
+    int32_t N, P, dims, maxnb;
+    int32_t two_nf, noise, obs_block0, obs_nblocks;
+    double box[3];
+    double c1, kT, omega_P, u_lim, r_skin2;
+    double kick[kMaxSpecies];   // dt / (2 P m mu)
+    double sigma[kMaxSpecies];  // sqrt((1 - c1^2) / (m mu))
+    double mmu[kMaxSpecies];    // m mu
+    uint64_t seed;
+    uint32_t stream;
+    int32_t pad;
+};
+
+// Work tables: replica and first atom per block (uniform per block).
+struct BlockEntry {
+    int32_t rep;
+    int32_t atom0;
+    int32_t group;   // bead group (force kernel)
+    int32_t pad;
+};
+
+// FIR tile descriptor: one per kDofTile columns.
+struct FirTile {
+    int32_t rep;
+    int32_t two_nf;
+    int32_t taps_off;   // offset (elements) of this replica's taps
+    int32_t pad;
+};
+
+enum StatusBits : int32_t { kStatusNonfinite = 1, kStatusNbOverflow = 2 };
+
+// Kernel-side flags of the force kernels.
+enum ForceFlags : int32_t { kKick = 1, kSample = 2, kEvaluate = 4 };
+
+// ---------------------------------------------------------------- launchers
+// noise.hip
+void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, void* ring,
+                      bool fp64, int64_t m0, int rows, int R, int64_t n_cols, int32_t n_rep_tiles);
+void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
+                     int64_t n_rows, uint32_t d0, uint32_t n_dof, double* out);
+// fir.hip
+void launch_fir(hipStream_t st, int mode, int K, const FirTile* tiles, int n_tiles,
+                const void* taps, const void* ring, void* zeta, int64_t n_cols, int64_t nb, int R,
+                int max_two_nf);
+int fir_pad();
+size_t fir_lds_bytes(int mode, int max_two_nf);
+// update.hip
+void launch_update(hipStream_t st, bool fp64, bool pair, int P, const RepDev* reps,
+                   const BlockEntry* blocks, int n_blocks, const void* zeta_row,
+                   int32_t* status);
+// nlist.hip
+void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
+                  int n_blocks, int32_t* status);
+// forces.hip
+void launch_forces_pair(hipStream_t st, bool fp64, int G, const RepDev* reps,
+                        const BlockEntry* blocks, int n_blocks, const void* table,
+                        int32_t flags, double* partials, int32_t* rebuild_clear, int n_rep);
+void launch_forces_harmonic(hipStream_t st, bool fp64, const RepDev* reps,
+                            const BlockEntry* blocks, int n_blocks, int32_t flags,
+                            double* partials);
+void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
+                       double* acc, int32_t* counts);
+void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value);
+
+}  // namespace qtb

@@ -1,0 +1,306 @@
+"""ctypes binding of libqtb.so (include/qtb.h), same names as the C ABI.
+
+Argument marshalling only: every step of the integrator runs in the HIP
+kernels of libqtb.so.  PyTorch provides device memory (state arrays and the
+workspace) and the stream.  Importing this module loads nothing; the first
+call loads the library and raises if it is missing (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqtb.so")
+
+QTB_OK, QTB_E_INVALID, QTB_E_NOMEM, QTB_E_DEVICE, QTB_E_STATE, QTB_E_NONFINITE, \
+    QTB_E_UNSUPPORTED = range(7)
+NOISE_CLASSICAL, NOISE_QTB, NOISE_QTB_PIMD = 0, 1, 2
+PREC_FP32, PREC_FP64 = 0, 1
+FIR_FP32, FIR_BF16X3, FIR_BF16, FIR_FP64 = 0, 1, 2, 3
+POT_PAIR, POT_HARMONIC = 0, 1
+MAX_SPECIES = 4
+
+_STATUS = {1: "QTB_E_INVALID", 2: "QTB_E_NOMEM", 3: "QTB_E_DEVICE", 4: "QTB_E_STATE",
+           5: "QTB_E_NONFINITE", 6: "QTB_E_UNSUPPORTED"}
+
+
+class QtbError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_PD = ctypes.POINTER(ctypes.c_double)
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+
+
+class qtb_potential(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_species", ctypes.c_int32),
+                ("mass", _PD), ("charge", _PD), ("buck_A", _PD), ("buck_rho", _PD),
+                ("buck_C", _PD), ("dsf_alpha", ctypes.c_double), ("r_cut", ctypes.c_double),
+                ("skin", ctypes.c_double)]
+
+
+class qtb_replica(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("n_beads", ctypes.c_int32),
+                ("n_dims", ctypes.c_int32), ("noise", ctypes.c_int32),
+                ("box", ctypes.c_double * 3), ("T", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("dt", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("stream", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("species", _PI32), ("harm_omega", _PD),
+                ("d_pos", ctypes.c_void_p), ("d_vel", ctypes.c_void_p)]
+
+
+class qtb_options(ctypes.Structure):
+    _fields_ = [("hbar", ctypes.c_double), ("kB", ctypes.c_double),
+                ("coulomb_k", ctypes.c_double), ("mass_unit", ctypes.c_double),
+                ("prec", ctypes.c_int32), ("fir", ctypes.c_int32),
+                ("fir_block_K", ctypes.c_int32), ("obs_every", ctypes.c_int32),
+                ("max_two_nf", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class qtb_obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("kinetic", ctypes.c_double),
+                ("potential", ctypes.c_double), ("spring", ctypes.c_double),
+                ("e_primitive", ctypes.c_double), ("e_virial", ctypes.c_double),
+                ("t_kinetic", ctypes.c_double), ("x2_mean", ctypes.c_double),
+                ("n_samples", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
+           "qtb_observables", "qtb_get_state", "qtb_set_state", "qtb_evaluate",
+           "qtb_get_noise", "qtb_gaussian", "qtb_last_error", "qtb_destroy", "qtb_version")
+
+_lib = None
+
+
+def lib():
+    """Load libqtb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} not found: build it with "
+                      "`python -m paper_1905_02521_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.qtb_workspace_bytes.restype = ctypes.c_size_t
+    L.qtb_workspace_bytes.argtypes = [ctypes.POINTER(qtb_potential), ctypes.POINTER(qtb_replica),
+                                      ctypes.c_int32, ctypes.POINTER(qtb_options)]
+    L.qtb_init.restype = ctypes.c_int
+    L.qtb_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(qtb_potential),
+                           ctypes.POINTER(qtb_replica), ctypes.c_int32,
+                           ctypes.POINTER(qtb_options), vp, ctypes.c_size_t, vp]
+    L.qtb_build_filter.restype = ctypes.c_int
+    L.qtb_build_filter.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _PD]
+    L.qtb_step.restype = ctypes.c_int
+    L.qtb_step.argtypes = [vp, ctypes.c_int64]
+    L.qtb_observables.restype = ctypes.c_int
+    L.qtb_observables.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(qtb_obs)]
+    L.qtb_get_state.restype = ctypes.c_int
+    L.qtb_get_state.argtypes = [vp, ctypes.c_int32, _PD, _PD, ctypes.POINTER(ctypes.c_int64)]
+    L.qtb_set_state.restype = ctypes.c_int
+    L.qtb_set_state.argtypes = [vp, ctypes.c_int32, _PD, _PD, ctypes.c_int64]
+    L.qtb_evaluate.restype = ctypes.c_int
+    L.qtb_evaluate.argtypes = [vp, ctypes.c_int32, _PD, _PD]
+    L.qtb_get_noise.restype = ctypes.c_int
+    L.qtb_get_noise.argtypes = [vp, ctypes.c_int32, _PD, ctypes.POINTER(ctypes.c_int64)]
+    L.qtb_gaussian.restype = ctypes.c_int
+    L.qtb_gaussian.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
+                               ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, vp, vp]
+    L.qtb_last_error.restype = ctypes.c_char_p
+    L.qtb_last_error.argtypes = [vp]
+    L.qtb_destroy.restype = None
+    L.qtb_destroy.argtypes = [vp]
+    L.qtb_version.restype = ctypes.c_char_p
+    L.qtb_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status, ctx=None):
+    if status != QTB_OK:
+        msg = lib().qtb_last_error(ctx).decode()
+        raise QtbError(status, msg)
+
+
+def _pd(a):
+    return a.ctypes.data_as(_PD)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream_ptr():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------- gaussian
+def qtb_gaussian(seed, stream, tag, n0, n_rows, d0, n_dof, out=None):
+    """Device tensor [n_rows, n_dof] float64 of the library's white noise."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((n_rows, n_dof), dtype=torch.float64, device="cuda")
+    _check(lib().qtb_gaussian(seed, stream, tag, n0, n_rows, d0, n_dof,
+                              ctypes.c_void_p(out.data_ptr()), current_stream_ptr()))
+    return out
+
+
+# ---------------------------------------------------------------- context
+@dataclass
+class Replica:
+    """One replica; positions / velocities [P][dims][N] (numpy, copied to device)."""
+    pos: np.ndarray
+    species: np.ndarray
+    T: float
+    gamma: float
+    dt: float
+    noise: int = NOISE_QTB
+    vel: np.ndarray | None = None
+    box: tuple = (0.0, 0.0, 0.0)
+    seed: int = 0
+    stream: int = 0
+    harm_omega: np.ndarray | None = None
+
+
+class Context:
+    """Owns the device buffers (torch) of a qtb_ctx and forwards the C calls."""
+
+    def __init__(self, potential: dict, replicas: list[Replica], units: dict, *,
+                 prec=PREC_FP32, fir=FIR_BF16X3, fir_block_K=64, obs_every=0, max_two_nf=512):
+        torch = _torch()
+        L = lib()
+        self._keep = []
+        ns = len(potential["mass"])
+        arr = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+        mass = arr(potential["mass"])
+        self._keep.append(mass)
+        pot = qtb_potential()
+        pot.kind = potential.get("kind", POT_PAIR)
+        pot.n_species = ns
+        pot.mass = _pd(mass)
+        if pot.kind == POT_PAIR:
+            tabs = [arr(potential[k]) for k in ("charge", "buck_A", "buck_rho", "buck_C")]
+            self._keep += tabs
+            pot.charge, pot.buck_A, pot.buck_rho, pot.buck_C = (_pd(t) for t in tabs)
+            pot.dsf_alpha = potential["dsf_alpha"]
+            pot.r_cut = potential["r_cut"]
+            pot.skin = potential["skin"]
+        self.pot = pot
+        self.n_rep = len(replicas)
+        self.reps = (qtb_replica * self.n_rep)()
+        self.d_pos, self.d_vel, self.shapes = [], [], []
+        for r, rp in enumerate(replicas):
+            pos = arr(rp.pos)
+            P, dims, N = pos.shape
+            vel = np.zeros_like(pos) if rp.vel is None else arr(rp.vel).reshape(pos.shape)
+            dp = torch.from_numpy(pos).to("cuda")
+            dv = torch.from_numpy(vel).to("cuda")
+            self.d_pos.append(dp)
+            self.d_vel.append(dv)
+            self.shapes.append((P, dims, N))
+            sp = np.ascontiguousarray(rp.species, dtype=np.int32)
+            self._keep.append(sp)
+            R = self.reps[r]
+            R.n_atoms, R.n_beads, R.n_dims, R.noise = N, P, dims, rp.noise
+            for a in range(3):
+                R.box[a] = float(rp.box[a]) if rp.box is not None else 0.0
+            R.T, R.gamma, R.dt = rp.T, rp.gamma, rp.dt
+            R.seed, R.stream = rp.seed, rp.stream
+            R.species = sp.ctypes.data_as(_PI32)
+            if rp.harm_omega is not None:
+                hw = arr(rp.harm_omega)
+                self._keep.append(hw)
+                R.harm_omega = _pd(hw)
+            R.d_pos = dp.data_ptr()
+            R.d_vel = dv.data_ptr()
+        opt = qtb_options()
+        opt.hbar, opt.kB = units["hbar"], units["kB"]
+        opt.coulomb_k, opt.mass_unit = units.get("coulomb_k", 0.0), units["mass_unit"]
+        opt.prec, opt.fir, opt.fir_block_K = prec, fir, fir_block_K
+        opt.obs_every, opt.max_two_nf = obs_every, max_two_nf
+        self.opt = opt
+        nbytes = L.qtb_workspace_bytes(ctypes.byref(pot), self.reps, self.n_rep, ctypes.byref(opt))
+        if nbytes == 0:
+            raise QtbError(QTB_E_INVALID, "qtb_workspace_bytes rejected the description")
+        self.ws_bytes = nbytes
+        # torch's allocator returns 512-byte aligned blocks
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        self.stream = current_stream_ptr()
+        self.ctx = ctypes.c_void_p()
+        _check(L.qtb_init(ctypes.byref(self.ctx), ctypes.byref(pot), self.reps, self.n_rep,
+                          ctypes.byref(opt), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                          self.stream))
+
+    # -- the C calls ---------------------------------------------------------
+    def build_filter(self, replica, kind, two_nf):
+        n = two_nf
+        taps = np.zeros(n)
+        _check(lib().qtb_build_filter(self.ctx, replica, kind, two_nf,
+                                      _pd(taps) if replica >= 0 else None), self.ctx)
+        return taps
+
+    def step(self, n):
+        _check(lib().qtb_step(self.ctx, int(n)), self.ctx)
+
+    def observables(self, replica=0):
+        o = qtb_obs()
+        _check(lib().qtb_observables(self.ctx, replica, ctypes.byref(o)), self.ctx)
+        return o.as_dict()
+
+    def get_state(self, replica=0):
+        shape = self.shapes[replica]
+        r, v = np.zeros(shape), np.zeros(shape)
+        st = ctypes.c_int64()
+        _check(lib().qtb_get_state(self.ctx, replica, _pd(r), _pd(v), ctypes.byref(st)), self.ctx)
+        return r, v, st.value
+
+    def set_state(self, replica, pos, vel, step):
+        shape = self.shapes[replica]
+        p = None if pos is None else np.ascontiguousarray(pos, dtype=np.float64).reshape(shape)
+        v = None if vel is None else np.ascontiguousarray(vel, dtype=np.float64).reshape(shape)
+        _check(lib().qtb_set_state(self.ctx, replica, None if p is None else _pd(p),
+                                   None if v is None else _pd(v), int(step)), self.ctx)
+
+    def evaluate(self, replica=0):
+        shape = self.shapes[replica]
+        f = np.zeros(shape)
+        e = np.zeros(shape[0])
+        _check(lib().qtb_evaluate(self.ctx, replica, _pd(f), _pd(e)), self.ctx)
+        return f, e
+
+    def get_noise(self, replica=0):
+        P, dims, N = self.shapes[replica]
+        z = np.zeros((self.opt.fir_block_K, dims * N * P))
+        n0 = ctypes.c_int64()
+        _check(lib().qtb_get_noise(self.ctx, replica, _pd(z), ctypes.byref(n0)), self.ctx)
+        return z, n0.value
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            lib().qtb_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pair_potential_dict(p) -> dict:
+    """From workloads.PairPotential to the dict Context takes."""
+    return dict(kind=POT_PAIR, mass=p.mass, charge=p.charge, buck_A=p.buck_A,
+                buck_rho=p.buck_rho, buck_C=p.buck_C, dsf_alpha=p.dsf_alpha, r_cut=p.r_cut,
+                skin=p.skin)
