@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Throughput of the QTB-PIMD integrator step on one MI355X.
+
+Workload (default): MgO-like rock salt, 8x8x8 conventional cells (4096 atoms)
+x P = 8 beads, QTB-PIMD at 50 K with the bead-modified spectrum kappa_P,
+gamma = 1/ps, dt = 1 fs, 512-tap FIR blocked over K = 64 steps on BF16x3
+matrix cores, FP32 forces with FP64 state.  A step is one pass of the whole
+hot path: white noise + FIR (once per K steps), fused B/NM/A/O/A update,
+neighbour-list check, pair forces with the closing kick.
+
+Prints one JSON line: atom-bead-steps/s, the roofline of the dominant kernel
+(pair forces, ALU bound) and of the FIR (HBM bytes), and the oracle timed on
+the host cores on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work of one unique pair within r_cut (see the pair kernel):
+# displacement 6, r^2 5, rsqrt 1, r 1, Buckingham exp 2, damping x 1, Gaussian
+# exp 2, erfc 1, r^-2 / r^-6 3, force magnitude 11, F/r 1, force on i 6,
+# reaction on j 3 (Newton's third law) -> 43 flops.
+FLOPS_PER_PAIR = 43
+# Algorithmic HBM bytes of the FIR per dof-step: one white-noise value read and
+# one coloured-noise value written, FP32 each.
+FIR_BYTES_PER_DOF_STEP = 8
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def unique_pairs(beads, box, r_cut):
+    """Number of distinct pairs within r_cut over all beads (min image; the
+    benchmark box is larger than 2 r_cut)."""
+    from scipy.spatial import cKDTree
+    n = 0
+    for b in range(beads.shape[0]):
+        x = np.mod(beads[b].T, box)
+        t = cKDTree(x, boxsize=box)
+        n += len(t.query_pairs(r_cut, output_type="ndarray"))
+    return n
+
+
+def cpu_baseline(w, beads, sp, box, pot, budget_s=15.0):
+    """The oracle (plain FP64 C, OpenMP over atoms) on the same workload,
+    bounded to about budget_s seconds of stepping."""
+    from oracle import oracle as orc
+    from paper_1905_02521_amd import workloads as W
+    threads = min(os.cpu_count() or 1, 16)
+    U = orc.make_units(**W.METAL_UNITS)
+    opot = orc.make_pot(0, pot.mass, pot.charge, pot.buck_A, pot.buck_rho, pot.buck_C,
+                        pot.dsf_alpha, pot.r_cut, pot.skin)
+    N, P = beads.shape[2], beads.shape[0]
+    sim = orc.Sim(opot, U, N, P, 3, box, sp, w.T, w.gamma, w.dt, w.seed, w.stream, w.noise,
+                  w.two_nf, beads, n_threads=threads)
+    sim.run(1)  # first step outside the clock
+    n, t = 0, 0.0
+    while t < budget_s and n < 10000:
+        k = 1 if n == 0 else max(1, int(n * (budget_s - t) / max(t, 1e-9) / 2))
+        k = min(k, 200)
+        t0 = time.perf_counter()
+        sim.run(k)
+        t += time.perf_counter() - t0
+        n += k
+    return {"value": N * P * n / t, "unit": "atom-bead-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n} steps of the same workload ({N} atoms x {P} beads), "
+                      f"{t:.1f} s, FP64, {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="mgo-8x8x8-qtbpimd-P8-50K")
+    ap.add_argument("--fir", default="bf16x3", choices=["fp32", "bf16x3", "bf16", "fp64"])
+    ap.add_argument("--K", type=int, default=64)
+    ap.add_argument("--skin", type=float, default=1.0)
+    ap.add_argument("--profile-steps", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (HBM counter scale)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1905_02521_amd import qtb, workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.workload(a.workload)
+    beads, sp, box = W.crystal_inputs(w)
+    pot = W.mgo_potential(skin=a.skin)
+    fir = {"fp32": qtb.FIR_FP32, "bf16x3": qtb.FIR_BF16X3, "bf16": qtb.FIR_BF16,
+           "fp64": qtb.FIR_FP64}[a.fir]
+    prec = qtb.PREC_FP64 if fir == qtb.FIR_FP64 else qtb.PREC_FP32
+    rep = qtb.Replica(pos=beads, species=sp, T=w.T, gamma=w.gamma, dt=w.dt, noise=w.noise,
+                      box=tuple(box), seed=w.seed, stream=w.stream)
+    ctx = qtb.Context(qtb.pair_potential_dict(pot), [rep], W.METAL_UNITS, prec=prec, fir=fir,
+                      fir_block_K=a.K, obs_every=0, max_two_nf=max(w.two_nf, 2))
+    if w.noise:
+        ctx.build_filter(0, w.noise, w.two_nf)
+    P, _, N = beads.shape
+
+    if a.copy_calibration:
+        src = torch.empty(256 * 2**20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    ctx.step(a.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(a.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    value = N * P * a.steps / (t1 - t0)
+
+    # per-kernel durations from HIP events on the library's stream
+    ctx.profile(True)
+    ctx.step(a.profile_steps)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    f_ms, f_n = prof["forces"]
+    force_ms = f_ms / max(f_n, 1)
+    pairs = unique_pairs(beads, box, pot.r_cut)
+    flops = pairs * FLOPS_PER_PAIR
+    achieved = flops / (force_ms * 1e-3) / 1e12
+    fir_ms, fir_n = prof["fir"]
+    D = 3 * N * P
+    fir_bytes = a.K * D * FIR_BYTES_PER_DOF_STEP
+    fir_gbs = fir_bytes / (fir_ms / max(fir_n, 1) * 1e-3) / 1e9 if fir_n else None
+    phases = {k: {"ms_per_launch": v[0] / max(v[1], 1), "launches": v[1],
+                  "ms_per_step": v[0] / a.profile_steps} for k, v in prof.items()}
+
+    out = {
+        "metric": "atom-bead-steps/s per GPU (forces+QTB noise+update)",
+        "value": value,
+        "unit": "atom-bead-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == qtb.PREC_FP32 else "f64",
+        "data": "synthetic (seeded rock-salt crystal, numpy PCG64 displacements)",
+        "config": {"workload": a.workload, "atoms": N, "beads": P, "T_K": w.T,
+                   "noise": "QTB-PIMD kappa_P" if w.noise == 2 else "QTB theta",
+                   "two_nf": w.two_nf, "fir": a.fir, "fir_block_K": a.K,
+                   "forces": "fp32" if prec == qtb.PREC_FP32 else "fp64", "state": "fp64",
+                   "r_cut_A": pot.r_cut, "skin_A": pot.skin, "parallelism": "1 GPU"},
+        "roofline": {"kernel": "pair forces", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops, "unique_pairs": pairs,
+                     "flops_per_pair": FLOPS_PER_PAIR, "ms_per_launch": force_ms},
+        "fir": {"achieved_GBs": fir_gbs, "peak_GBs": PEAK_HBM_GBS,
+                "frac": (fir_gbs / PEAK_HBM_GBS) if fir_gbs else None,
+                "bytes_per_launch": fir_bytes,
+                "ms_per_launch": fir_ms / max(fir_n, 1)},
+        "phases": phases,
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, beads, sp, box, pot, a.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -137,8 +137,14 @@ typedef struct {
     int32_t fir_block_K;       /* steps per noise block: multiple of 64, >= 64   */
     int32_t obs_every;         /* sample observables every n steps (0 = never)   */
     int32_t max_two_nf;        /* largest FIR length any replica will use        */
-    int32_t reserved[3];
+    int32_t flags;             /* QTB_OPT_* bits                                 */
+    int32_t reserved[2];
 } qtb_options;
+
+/* qtb_options.flags: run every step eagerly instead of replaying whole noise
+ * blocks as captured HIP graphs (graphs are used on a non-default stream when
+ * obs_every is 0 or divides fir_block_K). */
+#define QTB_OPT_NO_GRAPH 1
 
 /* Means over the samples taken since the previous qtb_observables call of
  * this replica (eq. 5 primitive estimator with instantaneous momenta). */
@@ -222,6 +228,18 @@ qtb_status qtb_get_noise(qtb_ctx *ctx, int32_t replica, double *h_zeta, int64_t 
 qtb_status qtb_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
                         int64_t n_rows, uint32_t d0, uint32_t n_dof, double *d_out,
                         void *hip_stream);
+
+/*
+ * Diagnostics: while enabled, qtb_step records a HIP event pair around every
+ * kernel phase on the context's stream (steps then run without graph
+ * replay).  qtb_profile_read synchronises and returns, per phase, the total
+ * GPU milliseconds and the number of launches since the last enable.
+ * Phases: 0 white noise, 1 FIR, 2 update, 3 neighbour list, 4 forces,
+ * 5 observable reduction.
+ */
+#define QTB_N_PHASES 6
+qtb_status qtb_profile(qtb_ctx *ctx, int32_t enable);
+qtb_status qtb_profile_read(qtb_ctx *ctx, double *ms, int64_t *launches);
 
 const char *qtb_last_error(const qtb_ctx *ctx); /* never NULL */
 void qtb_destroy(qtb_ctx *ctx);                 /* NULL is a no-op */

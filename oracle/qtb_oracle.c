@@ -423,6 +423,7 @@ struct orc_sim {
     double *wring;          /* [two_nf][D], row m lives in slot m mod two_nf */
     /* neighbour list (pair potential): full list built from bead centroids */
     double *rref;           /* [3][N] */
+    double nb_dev;          /* largest bead-to-centroid distance at the build */
     int *nb_start, *nb_j, nb_cap;
     double *nb_shift;       /* [3 * entries] */
     int nthreads;
@@ -430,16 +431,33 @@ struct orc_sim {
 
 static int64_t pmod(int64_t a, int64_t m) { int64_t r = a % m; return r < 0 ? r + m : r; }
 
+/*
+ * Full list from the bead centroids.  A bead may sit up to dev from its
+ * centroid, so the list radius is r_cut + skin + 2 dev: any pair that is not
+ * listed then stays beyond r_cut while every bead remains within
+ * skin/2 + dev of its reference (the rebuild test below).
+ */
 static void nlist_build(orc_sim *s)
 {
     int N = s->N, P = s->P;
-    double R = s->pot.r_cut + s->pot.skin;
     for (int d = 0; d < 3; ++d)
         for (int i = 0; i < N; ++i) {
             double c = 0.0;
             for (int b = 0; b < P; ++b) c += s->r[(b * 3 + d) * N + i];
             s->rref[d * N + i] = c / P;
         }
+    double dev2 = 0.0;
+    for (int b = 0; b < P; ++b)
+        for (int i = 0; i < N; ++i) {
+            double x2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                double x = s->r[(b * 3 + d) * N + i] - s->rref[d * N + i];
+                x2 += x * x;
+            }
+            if (x2 > dev2) dev2 = x2;
+        }
+    s->nb_dev = sqrt(dev2);
+    double R = s->pot.r_cut + s->pot.skin + 2.0 * s->nb_dev;
     int m[3];
     for (int d = 0; d < 3; ++d) m[d] = (int)floor(R / s->box[d] + 0.5) + 1;
     int cnt = 0;
@@ -480,7 +498,7 @@ static void nlist_build(orc_sim *s)
 static int nlist_stale(const orc_sim *s)
 {
     int N = s->N;
-    double lim = 0.5 * s->pot.skin;
+    double lim = 0.5 * s->pot.skin + s->nb_dev;
     for (int b = 0; b < s->P; ++b)
         for (int i = 0; i < N; ++i) {
             double d2 = 0.0;

@@ -40,9 +40,10 @@ __global__ void __launch_bounds__(256) k_fir_fp64(const FirTile* __restrict__ ti
                                                   const double* __restrict__ taps,
                                                   const double* __restrict__ ring,
                                                   double* __restrict__ zeta, int64_t n_cols,
-                                                  int64_t nb, int R)
+                                                  const int64_t* __restrict__ clock, int R)
 {
     extern __shared__ __attribute__((aligned(16))) double sh64[];
+    const int64_t nb = *clock;
     const FirTile t = tiles[blockIdx.x];
     const int two_nf = t.two_nf, Nf = two_nf / 2;
     const int L = two_nf + 2 * kPad;
@@ -70,9 +71,10 @@ __global__ void __launch_bounds__(256) k_fir_f32(const FirTile* __restrict__ til
                                                  const float* __restrict__ taps,
                                                  const float* __restrict__ ring,
                                                  float* __restrict__ zeta, int64_t n_cols,
-                                                 int64_t nb, int R)
+                                                 const int64_t* __restrict__ clock, int R)
 {
     extern __shared__ __attribute__((aligned(16))) float sh32[];
+    const int64_t nb = *clock;
     constexpr int MT = K / 32;
     const int64_t col0 = (int64_t)blockIdx.x * 128;
     const FirTile t = tiles[col0 / kDofTile];
@@ -122,8 +124,9 @@ __global__ void __launch_bounds__(256) k_fir_bf16(const FirTile* __restrict__ ti
                                                   const float* __restrict__ taps,
                                                   const float* __restrict__ ring,
                                                   float* __restrict__ zeta, int64_t n_cols,
-                                                  int64_t nb, int R, int LR)
+                                                  const int64_t* __restrict__ clock, int R, int LR)
 {
+    const int64_t nb = *clock;
     // LDS: reversed taps as hi and lo bf16, in 8 copies shifted by 0..7
     // elements so that any 8 consecutive entries are one aligned 16-byte read.
     extern __shared__ __attribute__((aligned(16))) uint16_t shb[];
@@ -204,7 +207,8 @@ void allow_lds(F kernel, size_t bytes)
 
 template <int K>
 void launch_fir_K(hipStream_t st, int mode, const FirTile* tiles, int n_tiles, const void* taps,
-                  const void* ring, void* zeta, int64_t n_cols, int64_t nb, int R, int max_two_nf)
+                  const void* ring, void* zeta, int64_t n_cols, const int64_t* nb, int R,
+                  int max_two_nf)
 {
     const int L = max_two_nf + 2 * kPad;
     if (mode == QTB_FIR_FP64) {
@@ -244,8 +248,8 @@ size_t fir_lds_bytes(int mode, int max_two_nf)
 }
 
 void launch_fir(hipStream_t st, int mode, int K, const FirTile* tiles, int n_tiles,
-                const void* taps, const void* ring, void* zeta, int64_t n_cols, int64_t nb, int R,
-                int max_two_nf)
+                const void* taps, const void* ring, void* zeta, int64_t n_cols, const int64_t* nb,
+                int R, int max_two_nf)
 {
     switch (K) {
     case 64: launch_fir_K<64>(st, mode, tiles, n_tiles, taps, ring, zeta, n_cols, nb, R, max_two_nf); break;

@@ -6,14 +6,15 @@
 // Buckingham term in shifted-force form plus damped shifted force Coulomb
 // (constants folded into PairParam; see qtb_internal.h).
 //
-// Mapping on CDNA4: one 64-wide wavefront per atom i.  Lane l takes bead
-// s = group*G + l % G and neighbour chunk l / G; the G beads of an atom share
-// one neighbour list (built from bead centroids, entries hold the reference
-// displacement, so a pair distance is d_ij + u_i - u_j with small u in the
-// working precision).  Per-bead sums are reduced across chunks with
-// wavefront shuffles (FP64 accumulators), so no atomics and no write
-// conflicts; lanes of chunk 0 finish the atom: store the force, apply the
-// kick, and on sampling steps form the eq. (5) terms.
+// Mapping on CDNA4: W 64-wide wavefronts per atom i.  Lane l takes bead
+// s = group*G + l % G and neighbour chunk l / G (+ 64/G per extra wavefront);
+// the G beads of an atom share one neighbour list (built from bead
+// centroids, entries hold the reference displacement, so a pair distance is
+// d_ij + u_i - u_j with small u in the working precision).  Per-bead sums are
+// reduced across chunks with wavefront shuffles and across the W wavefronts
+// in LDS (FP64 accumulators): no atomics, no write conflicts.  The first
+// lanes of the atom finish it: store the force, apply the kick, and on
+// sampling steps form the eq. (5) terms.
 #include "qtb_internal.h"
 
 namespace qtb {
@@ -41,74 +42,159 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
-template <typename T, int G>
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+template <typename T> struct NV;
+template <> struct NV<float> { using v4 = f4v; };
+template <> struct NV<double> { using v4 = d4v; };
+// Workspace pointers live in RepDev (generic address space); casting them to
+// the global address space lets the compiler emit global (not flat) loads.
+template <typename X>
+using gptr = const __attribute__((address_space(1))) X*;
+
+__device__ __forceinline__ int32_t vbits(f4v x) { return __float_as_int(x.w); }
+__device__ __forceinline__ int32_t vbits(d4v x) { return (int32_t)__double_as_longlong(x.w); }
+
+// NS: species count rounded up to 2 or 4 (parameters of the centre atom's
+// row are kept in registers and picked per neighbour with selects).
+// FAST (FP32 only): hardware rsq / exp2 and the fitted erfcx polynomial.
+template <typename T, int G, int W, int NS, bool FAST, int DEG>
 __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ reps,
                                                     const BlockEntry* __restrict__ blocks,
                                                     const PairTable<T> tab, int32_t flags,
                                                     double* __restrict__ partials,
-                                                    int32_t* __restrict__ rebuild_clear, int n_rep)
+                                                    int32_t* __restrict__ rebuild_clear, int n_rep,
+                                                    int32_t* __restrict__ rebuild_any)
 {
-    using T4 = typename Vec4<T>::type;
-    constexpr int NCH = 64 / G;
+    using V4 = typename NV<T>::v4;
+    constexpr int NCH = 64 / G;   // neighbour chunks per wavefront
+    constexpr int APB = 4 / W;    // atoms per block (W wavefronts per atom)
+    __shared__ double part[APB][W][G][4];
     __shared__ double red[4][kNobs];
     const BlockEntry be = blocks[blockIdx.x];
     const int rep = __builtin_amdgcn_readfirstlane(be.rep);
     const RepDev& R = reps[rep];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int bl = lane % G, ch = lane / G;
-    const int i = be.atom0 + wave;
+    const int slot = wave / W, wsub = wave % W;
+    const int bl = lane % G, ch = lane / G + wsub * NCH;
+    const int i = be.atom0 + slot;
     const int N = R.N, P = R.P;
     const bool active = i < N;
     const int s = be.group * G + bl;
     const bool want_e = (flags & (kSample | kEvaluate)) != 0;
 
-    if (blockIdx.x == 0)
+    if (blockIdx.x == 0) {
         for (int r = threadIdx.x; r < n_rep; r += blockDim.x) rebuild_clear[r] = 0;
+        if (threadIdx.x == 0) rebuild_any[0] = 0;
+    }
 
     double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
     int spi = 0;
     if (active) {
-        const T4* __restrict__ u = (const T4*)R.u + (size_t)s * N;
-        const T4 ui = u[i];
-        spi = as_bits(ui.w);
+        // u is atom-major [N][P]: the G beads of a neighbour share cache lines
+        gptr<V4> u = (gptr<V4>)R.u + s;
+        const V4 ui = u[(size_t)i * P];
+        spi = vbits(ui);
         const int row = __builtin_amdgcn_readfirstlane(spi) * kMaxSpecies;
-        const T4* __restrict__ ent = (const T4*)R.nb_entries + (size_t)i * R.maxnb;
+        T pArho[NS], pirho[NS], pC6[NS], pkqq[NS], pF0[NS], pA[NS], pC[NS], pE0[NS];
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+            const PairParam<T>& q = tab.p[row + b];
+            pArho[b] = q.Arho;
+            pirho[b] = FAST ? q.irho2 : q.irho;
+            pC6[b] = q.C6;
+            pkqq[b] = q.kqq;
+            pF0[b] = q.F0;
+            pA[b] = q.A;
+            pC[b] = q.C;
+            pE0[b] = q.E0;
+        }
+        // keep the neighbour-species parameters in VGPRs for the whole loop
+        // (selects on gfx950 take at most one SGPR operand)
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+            asm volatile("" : "+v"(pArho[b]), "+v"(pirho[b]), "+v"(pC6[b]), "+v"(pkqq[b]),
+                         "+v"(pF0[b]));
+        }
+        T ex[DEG + 1];
+#pragma unroll
+        for (int k = 0; k <= DEG; ++k) ex[k] = tab.ex[k];
+        const T rc2 = tab.rc2, a2l = tab.a2l, s_mul = tab.s_mul, alpha = tab.alpha, g = tab.g;
+        gptr<V4> ent = (gptr<V4>)R.nb_entries + (size_t)i * R.maxnb;
         const int cnt = R.nb_count[i];
-        const T rc2 = tab.rc2, alpha = tab.alpha, g = tab.g;
-        const int ns = tab.n_species;
-        for (int q = ch; q < cnt; q += NCH) {
-            const T4 E = ent[q];
-            const int j = as_bits(E.w);
-            const T4 uj = u[j];
-            const T dx = (E.x + ui.x) - uj.x;
-            const T dy = (E.y + ui.y) - uj.y;
-            const T dz = (E.z + ui.z) - uj.z;
+        constexpr int ST = NCH * W;
+        // three-stage pipeline: entry q+2*ST and the neighbour of entry q+ST
+        // are loading while the pair of entry q is evaluated
+        int q = ch;
+        V4 E0 = ent[q < cnt ? q : 0];
+        V4 E1 = ent[q + ST < cnt ? q + ST : 0];
+        V4 U0 = u[(size_t)vbits(E0) * P];
+        while (q < cnt) {
+            const int q2 = q + 2 * ST;
+            const V4 E2 = ent[q2 < cnt ? q2 : 0];
+            const V4 U1 = u[(size_t)vbits(E1) * P];
+            const T dx = (E0.x + ui.x) - U0.x;
+            const T dy = (E0.y + ui.y) - U0.y;
+            const T dz = (E0.z + ui.z) - U0.z;
             const T r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < rc2) {
-                const int spj = as_bits(uj.w);
-                PairParam<T> pp = tab.p[row];
+                const int spj = vbits(U0);
+                T Arho = pArho[0], irho = pirho[0], C6 = pC6[0], kqq = pkqq[0], F0 = pF0[0];
 #pragma unroll
-                for (int b = 1; b < kMaxSpecies; ++b)
-                    if (b < ns && spj == b) pp = tab.p[row + b];
-                const T rinv = t_rsqrt(r2);
-                const T r = r2 * rinv;
-                const T e1 = t_exp(-r * pp.irho);
-                const T x = alpha * r;
-                const T e2 = t_exp(-x * x);
-                const T ec = t_erfc(x);
+                for (int b = 1; b < NS; ++b) {
+                    const bool m = spj == b;
+                    Arho = m ? pArho[b] : Arho;
+                    irho = m ? pirho[b] : irho;
+                    C6 = m ? pC6[b] : C6;
+                    kqq = m ? pkqq[b] : kqq;
+                    F0 = m ? pF0[b] : F0;
+                }
+                T rinv, r, e1, e2, ec;
+                if constexpr (FAST) {
+                    rinv = __builtin_amdgcn_rsqf(r2);
+                    r = r2 * rinv;
+                    e1 = __builtin_amdgcn_exp2f(-r * irho);
+                    e2 = __builtin_amdgcn_exp2f(-r2 * a2l);
+                    const T sx = fmaf(r, s_mul, -1.0f);
+                    T pe = ex[DEG];
+#pragma unroll
+                    for (int k = DEG - 1; k >= 0; --k) pe = fmaf(pe, sx, ex[k]);
+                    ec = e2 * pe;
+                } else {
+                    rinv = t_rsqrt(r2);
+                    r = r2 * rinv;
+                    e1 = t_exp(-r * irho);
+                    const T x = alpha * r;
+                    e2 = t_exp(-x * x);
+                    ec = t_erfc(x);
+                }
                 const T rinv2 = rinv * rinv;
                 const T rinv6 = rinv2 * rinv2 * rinv2;
-                const T F = pp.Arho * e1 - pp.C6 * rinv6 * rinv +
-                            pp.kqq * (ec * rinv2 + g * e2 * rinv) + pp.F0;
+                const T F = Arho * e1 - C6 * rinv6 * rinv + kqq * (ec * rinv2 + g * e2 * rinv) + F0;
                 const T fr = F * rinv;
                 fx += (double)(fr * dx);
                 fy += (double)(fr * dy);
                 fz += (double)(fr * dz);
-                if (want_e)
-                    e += (double)(pp.A * e1 - pp.C * rinv6 + pp.kqq * ec * rinv - pp.F0 * r + pp.E0);
+                if (want_e) {
+                    T A = pA[0], C = pC[0], E0c = pE0[0];
+#pragma unroll
+                    for (int b = 1; b < NS; ++b) {
+                        const bool m = spj == b;
+                        A = m ? pA[b] : A;
+                        C = m ? pC[b] : C;
+                        E0c = m ? pE0[b] : E0c;
+                    }
+                    e += (double)(A * e1 - C * rinv6 + kqq * ec * rinv - F0 * r + E0c);
+                }
             }
+            E0 = E1;
+            E1 = E2;
+            U0 = U1;
+            q += ST;
         }
     }
+    // lanes with the same bead: reduce across chunks (shuffles), then across
+    // the W wavefronts of the atom (LDS)
 #pragma unroll
     for (int off = G; off < 64; off <<= 1) {
         fx += __shfl_xor(fx, off);
@@ -116,9 +202,25 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
         fz += __shfl_xor(fz, off);
         if (want_e) e += __shfl_xor(e, off);
     }
-    // lanes 0..G-1 now hold the totals of bead s
+    if (W > 1) {
+        if (lane < G) {
+            part[slot][wsub][lane][0] = fx;
+            part[slot][wsub][lane][1] = fy;
+            part[slot][wsub][lane][2] = fz;
+            part[slot][wsub][lane][3] = e;
+        }
+        __syncthreads();
+        if (wsub == 0 && lane < G) {
+            for (int w = 1; w < W; ++w) {
+                fx += part[slot][w][lane][0];
+                fy += part[slot][w][lane][1];
+                fz += part[slot][w][lane][2];
+                e += part[slot][w][lane][3];
+            }
+        }
+    }
     double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (active && ch == 0 && s < P) {
+    if (active && wsub == 0 && lane < G && s < P) {
         const double f[3] = {fx, fy, fz};
         T* __restrict__ force = (T*)R.force;
         const double kick = R.kick[spi];
@@ -266,33 +368,56 @@ __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v)
         p[id] = v;
 }
 
-template <typename T>
-void launch_pair_T(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
+template <typename T, int NS, bool FAST, int DEG>
+void launch_pair_G(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
                    int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
-                   int32_t* rebuild_clear, int n_rep)
+                   int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any)
 {
     const dim3 g(n_blocks), b(256);
+    constexpr int W = kWavesPerAtom;
     switch (G) {
-    case 1: hipLaunchKernelGGL((k_force_pair<T, 1>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep); break;
-    case 2: hipLaunchKernelGGL((k_force_pair<T, 2>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep); break;
-    case 4: hipLaunchKernelGGL((k_force_pair<T, 4>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep); break;
-    case 8: hipLaunchKernelGGL((k_force_pair<T, 8>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep); break;
+    case 1: hipLaunchKernelGGL((k_force_pair<T, 1, W, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any); break;
+    case 2: hipLaunchKernelGGL((k_force_pair<T, 2, W, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any); break;
+    case 4: hipLaunchKernelGGL((k_force_pair<T, 4, W, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any); break;
+    case 8: hipLaunchKernelGGL((k_force_pair<T, 8, W, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any); break;
     default: break;
     }
+}
+
+template <typename T, bool FAST, int DEG>
+void launch_pair_T(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
+                   int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
+                   int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any)
+{
+    if (tab.n_species <= 2)
+        launch_pair_G<T, 2, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any);
+    else
+        launch_pair_G<T, 4, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any);
 }
 
 }  // namespace
 
 void launch_forces_pair(hipStream_t st, bool fp64, int G, const RepDev* reps,
                         const BlockEntry* blocks, int n_blocks, const void* table, int32_t flags,
-                        double* partials, int32_t* rebuild_clear, int n_rep)
+                        double* partials, int32_t* rebuild_clear, int n_rep,
+                        int32_t* rebuild_any)
 {
-    if (fp64)
-        launch_pair_T<double>(st, G, reps, blocks, n_blocks, *(const PairTable<double>*)table,
-                              flags, partials, rebuild_clear, n_rep);
-    else
-        launch_pair_T<float>(st, G, reps, blocks, n_blocks, *(const PairTable<float>*)table,
-                             flags, partials, rebuild_clear, n_rep);
+    if (fp64) {
+        launch_pair_T<double, false, 1>(st, G, reps, blocks, n_blocks,
+                                     *(const PairTable<double>*)table, flags, partials,
+                                     rebuild_clear, n_rep, rebuild_any);
+    } else {
+        const PairTable<float>& t = *(const PairTable<float>*)table;
+        if (t.ex_deg == 10)
+            launch_pair_T<float, true, 10>(st, G, reps, blocks, n_blocks, t, flags, partials,
+                                           rebuild_clear, n_rep, rebuild_any);
+        else if (t.ex_deg == kErfcxMaxDeg)
+            launch_pair_T<float, true, kErfcxMaxDeg>(st, G, reps, blocks, n_blocks, t, flags,
+                                                     partials, rebuild_clear, n_rep, rebuild_any);
+        else
+            launch_pair_T<float, false, 1>(st, G, reps, blocks, n_blocks, t, flags, partials,
+                                           rebuild_clear, n_rep, rebuild_any);
+    }
 }
 
 void launch_forces_harmonic(hipStream_t st, bool fp64, const RepDev* reps,

@@ -8,11 +8,12 @@
 // periodic images within range are listed (boxes smaller than twice the
 // cut-off, e.g. 3x3x3 rock-salt cells at r_cut = 9 A, need them).
 //
-// Both kernels run every step and return at once unless the update kernel
-// flagged that some bead moved more than skin / (2 sqrt 3) per component
-// from its reference (then no pair within r_cut can be missing from the
-// list).  The build is all-pairs with j tiles staged in LDS: deterministic
-// order (j ascending, images in a fixed order), rebuilt rarely.
+// The kernel runs every step and returns at once unless the update kernel
+// flagged that some bead left the ball of radius devb_i + skin/2 around its
+// reference.  Pairs are listed within r_cut + skin + dev_i + dev_j (dev: the
+// largest bead-to-centroid distance of the atom at the build), so no pair
+// within r_cut can be missing before that happens.  The build is all-pairs,
+// one wavefront per atom, deterministic order.
 #include "qtb_internal.h"
 
 namespace qtb {
@@ -25,108 +26,146 @@ template <> struct Vec4<double> { using type = double4; };
 __device__ __forceinline__ float bits_f(int32_t b, float) { return __int_as_float(b); }
 __device__ __forceinline__ double bits_f(int32_t b, double) { return __longlong_as_double((long long)b); }
 
-// New references (bead centroids) and positions relative to them.
-template <typename T>
-__global__ void __launch_bounds__(256) k_nlist_refs(const RepDev* __restrict__ reps,
-                                                    const BlockEntry* __restrict__ blocks)
+// Bead centroids of the current positions (the update kernel writes them
+// every step; this pass is for init and set_state).
+__global__ void __launch_bounds__(256) k_centroids(const RepDev* __restrict__ reps,
+                                                   const BlockEntry* __restrict__ blocks)
 {
-    using T4 = typename Vec4<T>::type;
     const BlockEntry be = blocks[blockIdx.x];
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
-    if (*R.rebuild == 0) return;
-    const int i = be.atom0 + threadIdx.x;
     const int N = R.N, P = R.P;
-    if (i >= N) return;
+    const int ii = be.atom0 + threadIdx.x;
+    if (threadIdx.x >= 4 || ii >= N) return;
     double c[3];
     for (int a = 0; a < 3; ++a) {
         double s = 0.0;
-        for (int b = 0; b < P; ++b) s += R.pos[((size_t)b * 3 + a) * N + i];
+        for (int b = 0; b < P; ++b) s += R.pos[((size_t)b * 3 + a) * N + ii];
         c[a] = s / P;
-        R.rref[(size_t)a * N + i] = c[a];
+        R.cnow[(size_t)a * N + ii] = c[a];
     }
-    T4* __restrict__ u = (T4*)R.u;
-    const T spb = bits_f(R.species[i], T());
+    double d2max = 0.0;
     for (int b = 0; b < P; ++b) {
-        T4 v;
-        v.x = (T)(R.pos[((size_t)b * 3 + 0) * N + i] - c[0]);
-        v.y = (T)(R.pos[((size_t)b * 3 + 1) * N + i] - c[1]);
-        v.z = (T)(R.pos[((size_t)b * 3 + 2) * N + i] - c[2]);
-        v.w = spb;
-        u[(size_t)b * N + i] = v;
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double x = R.pos[((size_t)b * 3 + a) * N + ii] - c[a];
+            d2 += x * x;
+        }
+        d2max = fmax(d2max, d2);
     }
+    R.dev[ii] = sqrt(d2max);
 }
 
+// One wavefront per atom i: new reference r_ref_i = current bead centroid,
+// relative positions of its beads, and its list.  Lane l scans atoms
+// j = j0 + l; matches are compacted with a ballot, so entries come out in a
+// fixed order (j chunk, image, lane) whatever the timing.
 template <typename T>
-__global__ void __launch_bounds__(256) k_nlist_build(const RepDev* __restrict__ reps,
-                                                     const BlockEntry* __restrict__ blocks,
-                                                     int32_t* __restrict__ status)
+__global__ void __launch_bounds__(256) k_nlist(const RepDev* __restrict__ reps,
+                                               const BlockEntry* __restrict__ blocks,
+                                               int32_t* __restrict__ status)
 {
     using T4 = typename Vec4<T>::type;
-    __shared__ double sx[256], sy[256], sz[256];
+    __shared__ double tx[256], ty[256], tz[256], td[256];
+    __shared__ double dmax_s[4];
+    if (status[kAnyRebuild] == 0) return;  // nothing to do: one load, then exit
     const BlockEntry be = blocks[blockIdx.x];
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
     if (*R.rebuild == 0) return;  // uniform over the block
-    const int N = R.N;
-    const int i = be.atom0 + threadIdx.x;
-    const bool active = i < N;
-    const double Lx = R.box[0], Ly = R.box[1], Lz = R.box[2];
-    const double R2 = R.r_skin2;
-    const double Rl = sqrt(R2);
-    const int mx = (int)ceil(Rl / Lx - 0.5), my = (int)ceil(Rl / Ly - 0.5),
-              mz = (int)ceil(Rl / Lz - 0.5);
-    double xi = 0.0, yi = 0.0, zi = 0.0;
+    const int N = R.N, P = R.P;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = be.atom0 + wave;
+    const bool active = i < N;    // uniform over the wavefront
+    const double* __restrict__ cx = R.cnow;
+    const double* __restrict__ cy = R.cnow + N;
+    const double* __restrict__ cz = R.cnow + 2 * (size_t)N;
+    double xi = 0.0, yi = 0.0, zi = 0.0, devi = 0.0;
     if (active) {
-        xi = R.rref[i];
-        yi = R.rref[(size_t)N + i];
-        zi = R.rref[(size_t)2 * N + i];
+        xi = cx[i];
+        yi = cy[i];
+        zi = cz[i];
+        devi = R.dev[i];
+        if (lane < 3) R.rref[(size_t)lane * N + i] = R.cnow[(size_t)lane * N + i];
+        if (lane == 0) R.devb[i] = devi;
+        T4* __restrict__ u = (T4*)R.u + (size_t)i * P;
+        const T spb = bits_f(R.species[i], T());
+        for (int b = lane; b < P; b += 64) {
+            T4 v;
+            v.x = (T)(R.pos[((size_t)b * 3 + 0) * N + i] - xi);
+            v.y = (T)(R.pos[((size_t)b * 3 + 1) * N + i] - yi);
+            v.z = (T)(R.pos[((size_t)b * 3 + 2) * N + i] - zi);
+            v.w = spb;
+            u[b] = v;
+        }
     }
+    const double Lx = R.box[0], Ly = R.box[1], Lz = R.box[2];
+    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
+    // image range from the largest pair radius any atom of the block can have
+    double dmax = 0.0;
+    for (int j = threadIdx.x; j < N; j += 256) dmax = fmax(dmax, R.dev[j]);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
+    if (lane == 0) dmax_s[wave] = dmax;
+    __syncthreads();
+    dmax = fmax(fmax(dmax_s[0], dmax_s[1]), fmax(dmax_s[2], dmax_s[3]));
+    const double Rmax = R.r_cs + devi + dmax;
+    const int mx = (int)ceil(Rmax * iLx - 0.5), my = (int)ceil(Rmax * iLy - 0.5),
+              mz = (int)ceil(Rmax * iLz - 0.5);
     T4* __restrict__ ent = (T4*)R.nb_entries + (size_t)i * R.maxnb;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int cnt = 0;
-    for (int j0 = 0; j0 < N; j0 += 256) {
+    // tiles of 256 candidate atoms staged in LDS, shared by the 4 wavefronts
+    for (int t0 = 0; t0 < N; t0 += 256) {
         __syncthreads();
-        const int jl = j0 + threadIdx.x;
+        const int jl = t0 + threadIdx.x;
         if (jl < N) {
-            sx[threadIdx.x] = R.rref[jl];
-            sy[threadIdx.x] = R.rref[(size_t)N + jl];
-            sz[threadIdx.x] = R.rref[(size_t)2 * N + jl];
+            tx[threadIdx.x] = cx[jl];
+            ty[threadIdx.x] = cy[jl];
+            tz[threadIdx.x] = cz[jl];
+            td[threadIdx.x] = R.dev[jl];
         }
         __syncthreads();
         if (!active) continue;
-        const int jn = min(256, N - j0);
-        for (int jj = 0; jj < jn; ++jj) {
-            const int j = j0 + jj;
-            double dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
-            dx -= Lx * rint(dx / Lx);
-            dy -= Ly * rint(dy / Ly);
-            dz -= Lz * rint(dz / Lz);
-            for (int nx = -mx; nx <= mx; ++nx) {
-                const double ex = dx + nx * Lx;
-                const double ex2 = ex * ex;
-                if (ex2 >= R2) continue;
-                for (int ny = -my; ny <= my; ++ny) {
-                    const double ey = dy + ny * Ly;
-                    const double exy2 = ex2 + ey * ey;
-                    if (exy2 >= R2) continue;
-                    for (int nz = -mz; nz <= mz; ++nz) {
-                        const double ez = dz + nz * Lz;
-                        const double r2 = exy2 + ez * ez;
-                        if (r2 >= R2) continue;
-                        if (j == i && nx == 0 && ny == 0 && nz == 0) continue;
-                        if (cnt < R.maxnb) {
-                            T4 v;
-                            v.x = (T)ex;
-                            v.y = (T)ey;
-                            v.z = (T)ez;
-                            v.w = bits_f(j, T());
-                            ent[cnt] = v;
-                        }
-                        ++cnt;
-                    }
-                }
+        const int tn = min(256, N - t0);
+        for (int c0 = 0; c0 < tn; c0 += 64) {
+            const int jj = c0 + lane;
+            const int j = t0 + jj;
+            const bool valid = jj < tn;
+            // pair radius r_cut + skin + dev_i + dev_j
+            const double Rij = R.r_cs + devi + (valid ? td[jj] : 0.0);
+            const double R2 = Rij * Rij;
+            double dx = 0.0, dy = 0.0, dz = 0.0;
+            if (valid) {
+                dx = xi - tx[jj];
+                dy = yi - ty[jj];
+                dz = zi - tz[jj];
+                dx -= Lx * rint(dx * iLx);
+                dy -= Ly * rint(dy * iLy);
+                dz -= Lz * rint(dz * iLz);
             }
+            for (int nx = -mx; nx <= mx; ++nx)
+                for (int ny = -my; ny <= my; ++ny)
+                    for (int nz = -mz; nz <= mz; ++nz) {
+                        const double ex = dx + nx * Lx, ey = dy + ny * Ly, ez = dz + nz * Lz;
+                        const double r2 = ex * ex + ey * ey + ez * ez;
+                        const bool self = (j == i) && nx == 0 && ny == 0 && nz == 0;
+                        const bool hit = valid && r2 < R2 && !self;
+                        const uint64_t mask = __ballot(hit);
+                        if (hit) {
+                            const int slot = cnt + __popcll(mask & below);
+                            if (slot < R.maxnb) {
+                                T4 v;
+                                v.x = (T)ex;
+                                v.y = (T)ey;
+                                v.z = (T)ez;
+                                v.w = bits_f(j, T());
+                                ent[slot] = v;
+                            }
+                        }
+                        cnt += __popcll(mask);
+                    }
         }
     }
-    if (active) {
+    if (active && lane == 0) {
         R.nb_count[i] = min(cnt, R.maxnb);
         if (cnt > R.maxnb) atomicOr(status, kStatusNbOverflow);
     }
@@ -135,17 +174,16 @@ __global__ void __launch_bounds__(256) k_nlist_build(const RepDev* __restrict__ 
 }  // namespace
 
 void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
-                  int n_blocks, int32_t* status)
+                  int n_blocks, int32_t* status, bool centroids)
 {
-    if (fp64) {
-        hipLaunchKernelGGL(k_nlist_refs<double>, dim3(n_blocks), dim3(256), 0, st, reps, blocks);
-        hipLaunchKernelGGL(k_nlist_build<double>, dim3(n_blocks), dim3(256), 0, st, reps, blocks,
+    if (centroids)
+        hipLaunchKernelGGL(k_centroids, dim3(n_blocks), dim3(64), 0, st, reps, blocks);
+    if (fp64)
+        hipLaunchKernelGGL(k_nlist<double>, dim3(n_blocks), dim3(256), 0, st, reps, blocks,
                            status);
-    } else {
-        hipLaunchKernelGGL(k_nlist_refs<float>, dim3(n_blocks), dim3(256), 0, st, reps, blocks);
-        hipLaunchKernelGGL(k_nlist_build<float>, dim3(n_blocks), dim3(256), 0, st, reps, blocks,
+    else
+        hipLaunchKernelGGL(k_nlist<float>, dim3(n_blocks), dim3(256), 0, st, reps, blocks,
                            status);
-    }
 }
 
 }  // namespace qtb

@@ -139,10 +139,11 @@ __global__ void k_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t
 // the concatenated replica dof ranges, stored at ring row m mod R.
 template <typename T>
 __global__ void k_gen_white(const RepDev* __restrict__ reps, const FirTile* __restrict__ tiles,
-                            T* __restrict__ ring, int64_t m0, int R, int64_t n_cols)
+                            T* __restrict__ ring, const int64_t* __restrict__ clock, int64_t off,
+                            int R, int64_t n_cols)
 {
     const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t m = m0 + blockIdx.y;
+    const int64_t m = *clock + off + blockIdx.y;
     if (col >= n_cols) return;
     const int tile = (int)(col / kDofTile);
     const int rep = __builtin_amdgcn_readfirstlane(tiles[tile].rep);
@@ -170,16 +171,29 @@ void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t ta
 }
 
 void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, void* ring,
-                      bool fp64, int64_t m0, int rows, int R, int64_t n_cols, int32_t)
+                      bool fp64, const int64_t* clock, int64_t off, int rows, int R,
+                      int64_t n_cols)
 {
     if (rows <= 0) return;
     dim3 grid((unsigned)((n_cols + 255) / 256), (unsigned)rows);
     if (fp64)
         hipLaunchKernelGGL(k_gen_white<double>, grid, dim3(256), 0, st, reps, tiles,
-                           (double*)ring, m0, R, n_cols);
+                           (double*)ring, clock, off, R, n_cols);
     else
         hipLaunchKernelGGL(k_gen_white<float>, grid, dim3(256), 0, st, reps, tiles,
-                           (float*)ring, m0, R, n_cols);
+                           (float*)ring, clock, off, R, n_cols);
+}
+
+namespace {
+__global__ void k_clock(int64_t* clock, int64_t v, int add)
+{
+    if (threadIdx.x == 0) *clock = add ? *clock + v : v;
+}
+}  // namespace
+
+void launch_clock(hipStream_t st, int64_t* clock, int64_t v, bool add)
+{
+    hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, st, clock, v, add ? 1 : 0);
 }
 
 }  // namespace qtb

@@ -36,10 +36,10 @@ struct Region {
 // Everything the workspace holds, in the order it is carved.
 struct Layout {
     size_t total = 0;
-    Region reps, status, rebuild, tiles, taps, ring, zeta, partials, acc, counts, pairtab;
+    Region reps, status, rebuild, tiles, taps, ring, zeta, partials, acc, counts, pairtab, clock;
     Region blk_upd, blk_nl, blk_force;
     struct Per {
-        Region force, u, rref, r0, eatom, species, homega, nb, nbc, nm, ring;
+        Region force, u, rref, cnow, dev, devb, r0, eatom, species, homega, nb, nbc, nm, ring;
     };
     std::vector<Per> per;
     // derived sizes
@@ -123,7 +123,8 @@ const char* check_inputs(const qtb_potential* pot, const qtb_replica* reps, int 
 
 int estimate_maxnb(const qtb_potential* pot, const qtb_replica& R)
 {
-    const double Rl = pot->r_cut + pot->skin;
+    // bead spread widens the list radius (r_cut + skin + dev_i + dev_j)
+    const double Rl = pot->r_cut + pot->skin + (R.n_beads > 1 ? 1.0 : 0.2);
     const double vol = R.box[0] * R.box[1] * R.box[2];
     const double n_est = 4.0 / 3.0 * kPi * Rl * Rl * Rl * R.n_atoms / vol;
     int m = (int)std::ceil(1.3 * n_est + 48.0);
@@ -161,16 +162,16 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
         byP[reps[r].n_beads].push_back(r);
         byG[bead_group(reps[r].n_beads)].push_back(r);
     }
-    for (auto& kv : byP) {
-        const int P = kv.first;
-        const int per = P <= 8 ? 256 : 64;
-        const int b0 = (int)L.upd.size();
-        for (int r : kv.second)
-            for (int a = 0; a < reps[r].n_atoms; a += per) L.upd.push_back({r, a, 0, 0});
-        L.upd_groups.push_back({P, {b0, (int)L.upd.size()}});
+    {
+        // one launch covers every replica
+        for (int r = 0; r < n_rep; ++r) {
+            const int per = update_block_atoms(reps[r].n_dims, reps[r].n_beads);
+            for (int a = 0; a < reps[r].n_atoms; a += per) L.upd.push_back({r, a, per, 0});
+        }
+        L.upd_groups.push_back({0, {0, (int)L.upd.size()}});
     }
     for (int r = 0; r < n_rep; ++r)
-        for (int a = 0; a < reps[r].n_atoms; a += 256) L.nl.push_back({r, a, 0, 0});
+        for (int a = 0; a < reps[r].n_atoms; a += 4) L.nl.push_back({r, a, 0, 0});
     L.obs_b0.assign(n_rep, 0);
     L.obs_nb.assign(n_rep, 0);
     for (auto& kv : byG) {
@@ -212,6 +213,7 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     size_t cur = 0;
     add(cur, L.reps, sizeof(RepDev) * n_rep);
     add(cur, L.status, 64);
+    add(cur, L.clock, 64);
     add(cur, L.rebuild, sizeof(int32_t) * n_rep);
     add(cur, L.tiles, sizeof(FirTile) * L.tilev.size());
     add(cur, L.taps, zs * (size_t)L.taps_stride * n_rep);
@@ -237,6 +239,9 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
         if (pair) {
             add(cur, p.u, 4 * ts * P * N);
             add(cur, p.rref, 8 * 3 * N);
+            add(cur, p.cnow, 8 * 3 * N);
+            add(cur, p.dev, 8 * N);
+            add(cur, p.devb, 8 * N);
             add(cur, p.nb, 4 * ts * N * (size_t)L.maxnb[r]);
             add(cur, p.nbc, 4 * N);
         } else {
@@ -274,14 +279,53 @@ struct qtb_ctx {
     int64_t block_start = -1;  // global step of the current noise block
     int block_row = 0;
     bool ring_valid = false;
-    int64_t ring_hi = 0;       // last generated ring row (global step)
     std::string err;
+    // one captured noise block of K steps, replayed while nothing changes
+    hipGraphExec_t graph = nullptr;
+    int64_t graph_phase = -1;  // block start modulo obs_every at capture
+    bool graph_failed = false;
+    // profiling: event pairs per phase
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_marks;  // (phase, index of start event)
 
     template <typename X>
     X* at(const Region& r) const { return reinterpret_cast<X*>(ws + r.off); }
 };
 
 namespace {
+
+hipEvent_t next_event(qtb_ctx* c)
+{
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+// RAII marker: event before and after one phase's launches.
+struct Phase {
+    qtb_ctx* c;
+    size_t idx = 0;
+    bool on = false;
+    Phase(qtb_ctx* cc, int ph) : c(cc)
+    {
+        if (!c->prof) return;
+        idx = c->ev_used;
+        hipEvent_t a = next_event(c), b = next_event(c);
+        if (!a || !b) return;
+        (void)hipEventRecord(a, c->st);
+        c->ev_marks.push_back({ph, idx});
+        on = true;
+    }
+    ~Phase()
+    {
+        if (on) (void)hipEventRecord(c->ev_pool[idx + 1], c->st);
+    }
+};
 
 qtb_status fail(qtb_ctx* c, qtb_status s, const std::string& m)
 {
@@ -343,11 +387,57 @@ void fill_pair_table(qtb_ctx* c, PairTable<T>& tab)
             p.A = (T)A;
             p.C = (T)C;
             p.E0 = (T)E0;
+            p.irho2 = (T)(irho * 1.4426950408889634);
         }
     tab.alpha = (T)al;
     tab.g = (T)g;
     tab.rc2 = (T)(rc * rc);
+    tab.a2l = (T)(al * al * 1.4426950408889634);
     tab.n_species = ns;
+    // erfcx on [0, x_max]: Chebyshev interpolation at 48 nodes, truncated where
+    // the tail is below 2e-8 of the constant term, converted to monomials in s.
+    const double xmax = std::max(al * rc, 1e-3);
+    const int nn = 48;
+    std::vector<double> cc(nn, 0.0);
+    for (int j = 0; j < nn; ++j) {
+        double acc = 0.0;
+        for (int q = 0; q < nn; ++q) {
+            const double th = kPi * (q + 0.5) / nn;
+            const double x = 0.5 * (std::cos(th) + 1.0) * xmax;
+            acc += std::erfc(x) * std::exp(x * x) * std::cos(j * th);
+        }
+        cc[j] = 2.0 * acc / nn;
+    }
+    cc[0] *= 0.5;
+    // degree 10 when its Chebyshev tail is below 3e-7 of the constant term
+    // (alpha r_cut up to about 2), else kErfcxMaxDeg, else no fit
+    auto tail_after = [&](int d) {
+        double t = 0.0;
+        for (int j = d + 1; j < nn; ++j) t += std::fabs(cc[j]);
+        return t;
+    };
+    int deg = 10;
+    if (tail_after(10) >= 3e-7 * std::fabs(cc[0])) deg = kErfcxMaxDeg;
+    const bool fit_ok = tail_after(deg) < 5e-7 * std::fabs(cc[0]);
+    // monomial coefficients of sum_j cc[j] T_j(s), j <= deg
+    std::vector<double> mono(deg + 1, 0.0), tm1(deg + 1, 0.0), t0(deg + 1, 0.0), t1(deg + 1, 0.0);
+    tm1[0] = 1.0;            // T_0
+    mono[0] += cc[0];
+    if (deg >= 1) {
+        t0[1] = 1.0;         // T_1
+        mono[1] += cc[1];
+    }
+    for (int j = 2; j <= deg; ++j) {
+        std::fill(t1.begin(), t1.end(), 0.0);
+        for (int q = 0; q < deg; ++q) t1[q + 1] += 2.0 * t0[q];
+        for (int q = 0; q <= deg; ++q) t1[q] -= tm1[q];
+        for (int q = 0; q <= deg; ++q) mono[q] += cc[j] * t1[q];
+        tm1 = t0;
+        t0 = t1;
+    }
+    for (int q = 0; q <= kErfcxMaxDeg; ++q) tab.ex[q] = (T)(q <= deg ? mono[q] : 0.0);
+    tab.ex_deg = fit_ok ? deg : 0;
+    tab.s_mul = (T)(2.0 * al / xmax);
 }
 
 void fill_repdev(qtb_ctx* c, int r)
@@ -360,6 +450,9 @@ void fill_repdev(qtb_ctx* c, int r)
     d.force = c->at<void>(p.force);
     d.u = c->pair ? c->at<void>(p.u) : nullptr;
     d.rref = c->pair ? c->at<double>(p.rref) : nullptr;
+    d.cnow = c->pair ? c->at<double>(p.cnow) : nullptr;
+    d.dev = c->pair ? c->at<double>(p.dev) : nullptr;
+    d.devb = c->pair ? c->at<double>(p.devb) : nullptr;
     d.r0 = c->at<double>(p.r0);
     d.eatom = c->at<double>(p.eatom);
     d.species = c->at<int32_t>(p.species);
@@ -382,8 +475,8 @@ void fill_repdev(qtb_ctx* c, int r)
     d.c1 = std::exp(-R.gamma * R.dt);
     d.kT = c->opt.kB * R.T;
     d.omega_P = std::sqrt((double)R.n_beads) * d.kT / c->opt.hbar;
-    d.u_lim = c->skin / (2.0 * std::sqrt(3.0));
-    d.r_skin2 = (c->rc + c->skin) * (c->rc + c->skin);
+    d.half_skin = 0.5 * c->skin;
+    d.r_cs = c->rc + c->skin;
     for (int a = 0; a < kMaxSpecies; ++a) {
         const double m = a < (int)c->mass.size() ? c->mass[a] * c->opt.mass_unit : 1.0;
         d.mmu[a] = m;
@@ -434,7 +527,8 @@ void launch_forces(qtb_ctx* c, int32_t flags)
         if (c->pair) {
             const void* tab = c->fp64 ? (const void*)&c->tabd : (const void*)&c->tabf;
             launch_forces_pair(c->st, c->fp64, g.first, dreps, fb + b0, nb, tab, flags,
-                               part + (size_t)b0 * kNobs, c->at<int32_t>(L.rebuild), c->n_rep);
+                               part + (size_t)b0 * kNobs, c->at<int32_t>(L.rebuild), c->n_rep,
+                               c->at<int32_t>(L.status) + kAnyRebuild);
         } else {
             launch_forces_harmonic(c->st, c->fp64, dreps, fb + b0, nb, flags,
                                    part + (size_t)b0 * kNobs);
@@ -442,19 +536,20 @@ void launch_forces(qtb_ctx* c, int32_t flags)
     }
 }
 
-void launch_rebuild(qtb_ctx* c)
+void launch_rebuild(qtb_ctx* c, bool centroids = false)
 {
     if (!c->pair) return;
     const Layout& L = c->L;
     launch_nlist(c->st, c->fp64, c->at<RepDev>(L.reps), c->at<BlockEntry>(L.blk_nl),
-                 (int)L.nl.size(), c->at<int32_t>(L.status));
+                 (int)L.nl.size(), c->at<int32_t>(L.status), centroids);
 }
 
 qtb_status refresh_forces(qtb_ctx* c)
 {
     if (c->pair) {
         launch_fill(c->st, c->at<int32_t>(c->L.rebuild), c->n_rep, 1);
-        launch_rebuild(c);
+        launch_fill(c->st, c->at<int32_t>(c->L.status) + kAnyRebuild, 1, 1);
+        launch_rebuild(c, true);
     }
     launch_forces(c, 0);
     QTB_HIP(c, hipGetLastError());
@@ -473,61 +568,148 @@ qtb_status read_status(qtb_ctx* c)
     return QTB_OK;
 }
 
-// Generate white-noise rows (global steps) lo..hi into the ring.
-void gen_rows(qtb_ctx* c, int64_t lo, int64_t hi)
+// White-noise rows clock + off .. clock + off + rows - 1 into the ring.
+void gen_rows(qtb_ctx* c, int64_t off, int64_t rows)
 {
-    if (hi < lo) return;
     const Layout& L = c->L;
-    const int64_t rows = hi - lo + 1;
-    for (int64_t m0 = lo; m0 <= hi; m0 += 1024) {
-        const int rr = (int)std::min<int64_t>(1024, hi - m0 + 1);
+    Phase ph(c, 0);
+    for (int64_t r0 = 0; r0 < rows; r0 += 1024) {
+        const int rr = (int)std::min<int64_t>(1024, rows - r0);
         launch_gen_white(c->st, c->at<RepDev>(L.reps), c->at<FirTile>(L.tiles),
-                         c->at<void>(L.ring), c->opt.fir == QTB_FIR_FP64, m0, rr, L.R, L.n_cols,
-                         (int)L.tilev.size());
+                         c->at<void>(L.ring), c->opt.fir == QTB_FIR_FP64,
+                         c->at<int64_t>(L.clock), off + r0, rr, L.R, L.n_cols);
     }
-    (void)rows;
-    c->ring_hi = hi;
 }
 
-void start_block(qtb_ctx* c)
+// First block after init / set_state / build_filter: put the clock one block
+// behind and fill the history rows of the window.
+void prime_ring(qtb_ctx* c)
+{
+    const int K = c->L.K, maxNf = c->L.max_two_nf / 2;
+    launch_clock(c->st, c->at<int64_t>(c->L.clock), c->step - K, false);
+    gen_rows(c, K - maxNf + 1, 2 * maxNf - 1);
+    c->ring_valid = true;
+}
+
+// Kernels of one step; row = step index inside the noise block.
+void record_step(qtb_ctx* c, int row, bool sample)
+{
+    const Layout& L = c->L;
+    const size_t zs = c->opt.fir == QTB_FIR_FP64 ? 8 : 4;
+    const char* zrow = c->at<char>(L.zeta) + (size_t)row * L.n_cols * zs;
+    const RepDev* dreps = c->at<RepDev>(L.reps);
+    const BlockEntry* ub = c->at<BlockEntry>(L.blk_upd);
+    {
+        Phase ph(c, 2);
+        for (auto& g : L.upd_groups) {
+            const int b0 = g.second.first, nb = g.second.second - g.second.first;
+            if (nb > 0)
+                launch_update(c->st, c->fp64, c->pair, g.first, dreps, ub + b0, nb, zrow,
+                              c->at<int32_t>(L.status));
+        }
+    }
+    if (c->pair) {
+        Phase ph(c, 3);
+        launch_rebuild(c);
+    }
+    {
+        Phase ph(c, 4);
+        launch_forces(c, kKick | (sample ? kSample : 0));
+    }
+    if (sample) {
+        Phase ph(c, 5);
+        launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
+                          c->at<int32_t>(L.counts));
+    }
+}
+
+// Kernels that open a noise block: advance the clock by K, K new white-noise
+// rows, the FIR contraction for steps clock .. clock + K - 1.
+void record_block_start(qtb_ctx* c)
 {
     const Layout& L = c->L;
     const int maxNf = L.max_two_nf / 2;
-    const int64_t nb = c->step;
-    if (!c->ring_valid) {
-        gen_rows(c, nb - maxNf + 1, nb + maxNf - 1);
-        c->ring_valid = true;
-    }
-    gen_rows(c, nb + maxNf, nb + L.K - 1 + maxNf);
+    launch_clock(c->st, c->at<int64_t>(L.clock), L.K, true);
+    gen_rows(c, maxNf, L.K);
+    Phase ph(c, 1);
     launch_fir(c->st, c->opt.fir, L.K, c->at<FirTile>(L.tiles), (int)L.tilev.size(),
-               c->at<void>(L.taps), c->at<void>(L.ring), c->at<void>(L.zeta), L.n_cols, nb, L.R,
-               L.max_two_nf);
-    c->block_start = nb;
-    c->block_row = 0;
+               c->at<void>(L.taps), c->at<void>(L.ring), c->at<void>(L.zeta), L.n_cols,
+               c->at<int64_t>(L.clock), L.R, L.max_two_nf);
+}
+
+bool sample_at(const qtb_ctx* c, int64_t step)
+{
+    return c->opt.obs_every > 0 && ((step + 1) % c->opt.obs_every) == 0;
 }
 
 void one_step(qtb_ctx* c)
 {
     const Layout& L = c->L;
-    if (c->block_start < 0 || c->block_row >= L.K) start_block(c);
-    const size_t zs = c->opt.fir == QTB_FIR_FP64 ? 8 : 4;
-    const char* zrow = c->at<char>(L.zeta) + (size_t)c->block_row * L.n_cols * zs;
-    const RepDev* dreps = c->at<RepDev>(L.reps);
-    const BlockEntry* ub = c->at<BlockEntry>(L.blk_upd);
-    for (auto& g : L.upd_groups) {
-        const int b0 = g.second.first, nb = g.second.second - g.second.first;
-        if (nb > 0)
-            launch_update(c->st, c->fp64, c->pair, g.first, dreps, ub + b0, nb, zrow,
-                          c->at<int32_t>(L.status));
+    if (!c->ring_valid) prime_ring(c);
+    if (c->block_start < 0 || c->block_row >= L.K) {
+        // the clock advances by K per block: re-seat it if this block does not
+        // follow the previous one (first block, new filter, new state)
+        if (c->block_start < 0 || c->block_start + L.K != c->step)
+            launch_clock(c->st, c->at<int64_t>(L.clock), c->step - L.K, false);
+        record_block_start(c);
+        c->block_start = c->step;
+        c->block_row = 0;
     }
-    launch_rebuild(c);
-    const bool sample = c->opt.obs_every > 0 && ((c->step + 1) % c->opt.obs_every) == 0;
-    launch_forces(c, kKick | (sample ? kSample : 0));
-    if (sample)
-        launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
-                          c->at<int32_t>(L.counts));
+    record_step(c, c->block_row, sample_at(c, c->step));
     c->step += 1;
     c->block_row += 1;
+}
+
+void drop_graph(qtb_ctx* c)
+{
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_phase = -1;
+}
+
+// A whole block of K steps as one graph launch.  Valid while the kernel
+// arguments stay the same: they only depend on the workspace layout, the
+// potential table and the sampling pattern inside the block.
+bool graph_block(qtb_ctx* c)
+{
+    const Layout& L = c->L;
+    if (c->graph_failed || c->prof || c->st == nullptr) return false;
+    if (c->opt.flags & QTB_OPT_NO_GRAPH) return false;
+    if (c->opt.obs_every > 0 && L.K % c->opt.obs_every != 0) return false;
+    const int64_t phase = c->opt.obs_every > 0 ? c->step % c->opt.obs_every : 0;
+    if (!c->graph || c->graph_phase != phase) {
+        drop_graph(c);
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            c->graph_failed = true;
+            (void)hipGetLastError();
+            return false;
+        }
+        record_block_start(c);
+        for (int r = 0; r < L.K; ++r) record_step(c, r, sample_at(c, c->step + r));
+        if (hipStreamEndCapture(c->st, &g) != hipSuccess || !g ||
+            hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0) != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            c->graph = nullptr;
+            c->graph_failed = true;
+            (void)hipGetLastError();
+            return false;
+        }
+        (void)hipGraphDestroy(g);
+        c->graph_phase = phase;
+    }
+    if (c->block_start < 0 || c->block_start + L.K != c->step)
+        launch_clock(c->st, c->at<int64_t>(L.clock), c->step - L.K, false);
+    if (hipGraphLaunch(c->graph, c->st) != hipSuccess) {
+        drop_graph(c);
+        c->graph_failed = true;
+        (void)hipGetLastError();
+        return false;
+    }
+    c->block_start = c->step;
+    c->block_row = L.K;
+    c->step += L.K;
+    return true;
 }
 
 }  // namespace
@@ -701,7 +883,16 @@ qtb_status qtb_step(qtb_ctx* c, int64_t n_steps)
     if (n_steps < 0) return fail(c, QTB_E_INVALID, "n_steps must be >= 0");
     for (int r = 0; r < c->n_rep; ++r)
         if (!c->filter_ready[r]) return fail(c, QTB_E_STATE, "qtb_build_filter not called");
-    for (int64_t it = 0; it < n_steps; ++it) one_step(c);
+    int64_t left = n_steps;
+    while (left > 0) {
+        const bool at_boundary = c->ring_valid && (c->block_start < 0 || c->block_row >= c->L.K);
+        if (at_boundary && left >= c->L.K && graph_block(c)) {
+            left -= c->L.K;
+            continue;
+        }
+        one_step(c);
+        left -= 1;
+    }
     QTB_HIP(c, hipGetLastError());
     return QTB_OK;
 }
@@ -846,6 +1037,33 @@ qtb_status qtb_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0
     return QTB_OK;
 }
 
+qtb_status qtb_profile(qtb_ctx* c, int32_t enable)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    c->prof = enable != 0;
+    c->ev_used = 0;
+    c->ev_marks.clear();
+    return QTB_OK;
+}
+
+qtb_status qtb_profile_read(qtb_ctx* c, double* ms, int64_t* launches)
+{
+    if (!c || !ms || !launches) return fail(c, QTB_E_INVALID, "null argument");
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    for (int q = 0; q < QTB_N_PHASES; ++q) {
+        ms[q] = 0.0;
+        launches[q] = 0;
+    }
+    for (auto& m : c->ev_marks) {
+        float t = 0.0f;
+        QTB_HIP(c, hipEventElapsedTime(&t, c->ev_pool[m.second], c->ev_pool[m.second + 1]));
+        ms[m.first] += t;
+        launches[m.first] += 1;
+    }
+    return QTB_OK;
+}
+
 const char* qtb_last_error(const qtb_ctx* c)
 {
     if (c) return c->err.c_str();
@@ -856,6 +1074,8 @@ void qtb_destroy(qtb_ctx* c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    drop_graph(c);
     delete c;
 }
 

@@ -13,7 +13,8 @@ namespace qtb {
 constexpr int kMaxSpecies = QTB_MAX_SPECIES;
 constexpr int kPairs = kMaxSpecies * kMaxSpecies;
 constexpr int kDofTile = 256;      // replica dof ranges are padded to this
-constexpr int kAtomsPerBlock = 4;  // force kernel: one wavefront per atom
+constexpr int kWavesPerAtom = 2;   // force kernel: wavefronts per atom
+constexpr int kAtomsPerBlock = 4 / kWavesPerAtom;  // force kernel block: 4 wavefronts
 constexpr int kNobs = 6;           // ke, U, spring, virial, x2, (unused)
 
 // Pair potential in the form the force kernels evaluate:
@@ -25,12 +26,23 @@ constexpr int kNobs = 6;           // ke, U, spring, virial, x2, (unused)
 template <typename T>
 struct PairParam {
     T Arho, irho, C6, kqq, F0, A, C, E0;
+    T irho2;  // irho log2(e): e^{-r irho} = 2^{-r irho2}
 };
+
+// erfc(x) e^{x^2} on [0, alpha r_cut] as a polynomial of fixed degree in
+// s = x (2/x_max) - 1, fitted on the host (Chebyshev interpolation, then
+// monomial form).  ex_deg is 10 or kErfcxMaxDeg; 0 marks a range the fit
+// cannot cover to 5e-7, where the FP32 kernel calls erfcf instead.
+constexpr int kErfcxMaxDeg = 14;
 
 template <typename T>
 struct PairTable {
     PairParam<T> p[kPairs];
     T alpha, g, rc2;
+    T a2l;     // alpha^2 log2(e): e^{-a^2 r^2} = 2^{-r^2 a2l}
+    T s_mul;   // 2 alpha / x_max
+    T ex[kErfcxMaxDeg + 1];
+    int32_t ex_deg;
     int32_t n_species;
 };
 
@@ -39,7 +51,10 @@ struct RepDev {
     double* pos;         // [P][dims][N]
     double* vel;         // [P][dims][N]
     void* force;         // T [P][dims][N]
-    void* u;             // T4 [P][N]: position minus reference, species bits in .w
+    void* u;             // T4 [N][P]: position minus reference, species bits in .w
+    double* cnow;        // [3][N] bead centroids of the current step (update kernel)
+    double* dev;         // [N] largest bead-to-centroid distance now
+    double* devb;        // [N] the same at the last list build
     double* rref;        // [3][N] reference positions (bead centroids at the last build)
     double* r0;          // [P][dims][N] positions given at init / set_state
     double* eatom;       // [P][N] per-atom energies (evaluate mode)
@@ -55,7 +70,7 @@ struct RepDev {
     int32_t N, P, dims, maxnb;
     int32_t two_nf, noise, obs_block0, obs_nblocks;
     double box[3];
-    double c1, kT, omega_P, u_lim, r_skin2;
+    double c1, kT, omega_P, half_skin, r_cs;  // r_cs = r_cut + skin
     double kick[kMaxSpecies];   // dt / (2 P m mu)
     double sigma[kMaxSpecies];  // sqrt((1 - c1^2) / (m mu))
     double mmu[kMaxSpecies];    // m mu
@@ -81,6 +96,8 @@ struct FirTile {
 };
 
 enum StatusBits : int32_t { kStatusNonfinite = 1, kStatusNbOverflow = 2 };
+// status[kAnyRebuild]: some replica needs its neighbour list rebuilt
+constexpr int kAnyRebuild = 4;
 
 // Kernel-side flags of the force kernels.
 enum ForceFlags : int32_t { kKick = 1, kSample = 2, kEvaluate = 4 };
@@ -88,26 +105,30 @@ enum ForceFlags : int32_t { kKick = 1, kSample = 2, kEvaluate = 4 };
 // ---------------------------------------------------------------- launchers
 // noise.hip
 void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, void* ring,
-                      bool fp64, int64_t m0, int rows, int R, int64_t n_cols, int32_t n_rep_tiles);
+                      bool fp64, const int64_t* clock, int64_t off, int rows, int R,
+                      int64_t n_cols);
+void launch_clock(hipStream_t st, int64_t* clock, int64_t v, bool add);
 void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
                      int64_t n_rows, uint32_t d0, uint32_t n_dof, double* out);
 // fir.hip
 void launch_fir(hipStream_t st, int mode, int K, const FirTile* tiles, int n_tiles,
-                const void* taps, const void* ring, void* zeta, int64_t n_cols, int64_t nb, int R,
-                int max_two_nf);
+                const void* taps, const void* ring, void* zeta, int64_t n_cols, const int64_t* nb,
+                int R, int max_two_nf);
 int fir_pad();
 size_t fir_lds_bytes(int mode, int max_two_nf);
 // update.hip
 void launch_update(hipStream_t st, bool fp64, bool pair, int P, const RepDev* reps,
                    const BlockEntry* blocks, int n_blocks, const void* zeta_row,
                    int32_t* status);
+int update_block_atoms(int dims, int P);
 // nlist.hip
 void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
-                  int n_blocks, int32_t* status);
+                  int n_blocks, int32_t* status, bool centroids);
 // forces.hip
 void launch_forces_pair(hipStream_t st, bool fp64, int G, const RepDev* reps,
                         const BlockEntry* blocks, int n_blocks, const void* table,
-                        int32_t flags, double* partials, int32_t* rebuild_clear, int n_rep);
+                        int32_t flags, double* partials, int32_t* rebuild_clear, int n_rep,
+                        int32_t* rebuild_any);
 void launch_forces_harmonic(hipStream_t st, bool fp64, const RepDev* reps,
                             const BlockEntry* blocks, int n_blocks, int32_t flags,
                             double* partials);

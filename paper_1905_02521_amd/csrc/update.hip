@@ -11,8 +11,8 @@
 //    coloured noise whose spectrum is theta (eq. 7) or kappa_P (eq. 12), as
 //    Sec. 2.3 prescribes for QTB-PIMD.
 //
-// One thread owns one atom with all its beads in registers (P <= 8), so the
-// P x P transforms never leave the register file; larger P uses LDS.
+// Bead-parallel: one thread per (atom, component, bead); the P x P
+// transforms exchange values through LDS.
 // The pair potential also needs the positions relative to the neighbour
 // list reference (FP32 in FP32 mode): they are written here, and the
 // largest component decides whether the list must be rebuilt.
@@ -32,208 +32,163 @@ __device__ __forceinline__ float bits_as<float>(int32_t b) { return __int_as_flo
 template <>
 __device__ __forceinline__ double bits_as<double>(int32_t b) { return __longlong_as_double((long long)b); }
 
-template <int P, typename T, bool PAIR>
-__global__ void __launch_bounds__(256) k_update(const RepDev* __restrict__ reps,
-                                                const BlockEntry* __restrict__ blocks,
-                                                const T* __restrict__ zeta_row,
-                                                int32_t* __restrict__ status)
+// One thread per (atom, Cartesian component, bead).  Consecutive lanes are
+// consecutive atoms, so every state load and store of a wavefront is a
+// contiguous run of the [P][dims][N] arrays; the P x P normal-mode
+// transforms read the partner beads of the same (atom, component) from LDS.
+// A block holds A = BlockEntry::group atoms (A dims P <= kUpdThreads).
+constexpr int kUpdThreads = 384;
+
+template <typename T, bool PAIR>
+__global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict__ reps,
+                                                        const BlockEntry* __restrict__ blocks,
+                                                        const T* __restrict__ zeta_row,
+                                                        int32_t* __restrict__ status)
 {
     using T4 = typename Vec4<T>::type;
+    __shared__ double xr[kUpdThreads], xv[kUpdThreads];
+    __shared__ double Cs[64 * 64];
+    __shared__ double cen[kUpdThreads / 3][3];
+    __shared__ int flags;
     const BlockEntry be = blocks[blockIdx.x];
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
-    const int i = be.atom0 + threadIdx.x;
-    const int N = R.N, dims = R.dims;
-    if (i >= N) return;
-    const int sp = R.species[i];
-    const double kick = R.kick[sp], sig = R.sigma[sp], c1 = R.c1;
-    const T* __restrict__ force = (const T*)R.force;
-    const T* __restrict__ z = zeta_row + R.dof_off;
-    const double* __restrict__ C = R.nm;
-    const double* __restrict__ ring = R.ring;
-    double umax = 0.0;
-    T uc[3][P];
-    bool finite = true;
-    for (int a = 0; a < dims; ++a) {
-        double r[P], v[P], q[P], p[P];
-#pragma unroll
-        for (int s = 0; s < P; ++s) {
-            const size_t idx = ((size_t)s * dims + a) * N + i;
-            r[s] = R.pos[idx];
-            v[s] = R.vel[idx] + kick * (double)force[idx];
+    const int N = R.N, P = R.P, dims = R.dims;
+    const int A = be.group;
+    const int t = threadIdx.x;
+    const int il = t % A, rest = t / A;
+    const int s = rest % P, a = rest / P;        // bead (then mode), component
+    const int i = be.atom0 + il;
+    const bool active = (a < dims) && (i < N);
+    for (int x = t; x < P * P; x += blockDim.x) Cs[x] = R.nm[x];
+    if (t == 0) flags = 0;
+    const size_t idx = ((size_t)s * dims + a) * N + i;
+    // every global load of the thread is issued here, ahead of the barriers
+    double r = 0.0, v = 0.0, z = 0.0, ref3[3] = {0.0, 0.0, 0.0}, devb = 0.0;
+    int sp = 0;
+    if (active) {
+        sp = R.species[i];
+        r = R.pos[idx];
+        v = R.vel[idx];
+        const double f = (double)((const T*)R.force)[idx];
+        z = (double)zeta_row[R.dof_off + ((int64_t)dims * i + a) * P + s];
+        if (PAIR && a == 0) {
+            for (int a2 = 0; a2 < 3; ++a2) ref3[a2] = R.rref[(size_t)a2 * N + i];
+            devb = R.devb[i];
         }
+        double kick = R.kick[0];
 #pragma unroll
+        for (int q = 1; q < kMaxSpecies; ++q) kick = (sp == q) ? R.kick[q] : kick;
+        v += kick * f;
+    }
+    xr[t] = r;
+    xv[t] = v;
+    __syncthreads();
+    // partner of bead b of this (atom, component) sits at (a P + b) A + il
+    const int base = a * P * A + il;
+    double q = 0.0, pm = 0.0;
+    if (active) {
+        for (int b = 0; b < P; ++b) {
+            const double c = Cs[b * P + s];
+            q += c * xr[base + b * A];
+            pm += c * xv[base + b * A];
+        }
+        const int k = s;  // this thread now holds mode k (its noise value z)
+        const double cw = R.ring[k], sw = R.ring[P + k], ws = R.ring[2 * P + k];
+        const double q1 = cw * q + sw * pm;
+        double p1 = ws * q + cw * pm;
+        double sig = R.sigma[0];
+#pragma unroll
+        for (int qq = 1; qq < kMaxSpecies; ++qq) sig = (sp == qq) ? R.sigma[qq] : sig;
+        p1 = R.c1 * p1 + sig * z;
+        q = cw * q1 + sw * p1;
+        pm = ws * q1 + cw * p1;
+    }
+    __syncthreads();
+    xr[t] = q;
+    xv[t] = pm;
+    __syncthreads();
+    if (active) {
+        double rn = 0.0, vn = 0.0;
         for (int k = 0; k < P; ++k) {
-            double qa = 0.0, pa = 0.0;
-#pragma unroll
-            for (int s = 0; s < P; ++s) {
-                qa += C[s * P + k] * r[s];
-                pa += C[s * P + k] * v[s];
-            }
-            q[k] = qa;
-            p[k] = pa;
+            const double c = Cs[s * P + k];
+            rn += c * xr[base + k * A];
+            vn += c * xv[base + k * A];
         }
-        const int64_t dof0 = ((int64_t)dims * i + a) * P;
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const double cw = ring[k], sw = ring[P + k], ws = ring[2 * P + k];
-            double q1 = cw * q[k] + sw * p[k];
-            double p1 = ws * q[k] + cw * p[k];
-            p1 = c1 * p1 + sig * (double)z[dof0 + k];
-            q[k] = cw * q1 + sw * p1;
-            p[k] = ws * q1 + cw * p1;
-        }
-#pragma unroll
-        for (int s = 0; s < P; ++s) {
-            double ra = 0.0, va = 0.0;
-#pragma unroll
-            for (int k = 0; k < P; ++k) {
-                ra += C[s * P + k] * q[k];
-                va += C[s * P + k] * p[k];
-            }
-            const size_t idx = ((size_t)s * dims + a) * N + i;
-            R.pos[idx] = ra;
-            R.vel[idx] = va;
-            finite = finite && __builtin_isfinite(ra) && __builtin_isfinite(va);
-            if (PAIR) {
-                const double du = ra - R.rref[(size_t)a * N + i];
-                uc[a][s] = (T)du;
-                umax = fmax(umax, fabs(du));
-            }
-        }
+        r = rn;
+        v = vn;
+        R.pos[idx] = r;
+        R.vel[idx] = v;
+        if (!(__builtin_isfinite(r) && __builtin_isfinite(v))) atomicOr(&flags, kStatusNonfinite);
     }
     if (PAIR) {
-        T4* __restrict__ u = (T4*)R.u;
-        const T spb = bits_as<T>(sp);
-#pragma unroll
-        for (int s = 0; s < P; ++s) {
+        // centroid per (atom, component); relative positions, bead spread and
+        // the rebuild test per (atom, bead)
+        __syncthreads();
+        xr[t] = r;
+        __syncthreads();
+        if (active && s == 0) {
+            double c = 0.0;
+            for (int b = 0; b < P; ++b) c += xr[base + b * A];
+            c /= P;
+            R.cnow[(size_t)a * N + i] = c;
+            cen[il][a] = c;
+        }
+        __syncthreads();
+        if (active && a == 0) {
+            double u3[3], u2 = 0.0, d2 = 0.0;
+            for (int a2 = 0; a2 < 3; ++a2) {
+                const double x = xr[(a2 * P + s) * A + il];
+                u3[a2] = x - ref3[a2];
+                const double dc = x - cen[il][a2];
+                u2 += u3[a2] * u3[a2];
+                d2 += dc * dc;
+            }
             T4 val;
-            val.x = uc[0][s];
-            val.y = uc[1][s];
-            val.z = uc[2][s];
-            val.w = spb;
-            u[(size_t)s * N + i] = val;
+            val.x = (T)u3[0];
+            val.y = (T)u3[1];
+            val.z = (T)u3[2];
+            val.w = bits_as<T>(sp);
+            ((T4*)R.u)[(size_t)i * P + s] = val;
+            xv[t] = d2;
+            const double lim = devb + R.half_skin;
+            if (!(u2 <= lim * lim)) atomicOr(&flags, 8);
         }
-        if (!(umax <= R.u_lim)) atomicOr(R.rebuild, 1);
-    }
-    if (!finite) atomicOr(status, kStatusNonfinite);
-}
-
-// Any P: per-thread bead arrays in LDS (64 threads per block).
-template <typename T, bool PAIR>
-__global__ void __launch_bounds__(64) k_update_lds(const RepDev* __restrict__ reps,
-                                                   const BlockEntry* __restrict__ blocks,
-                                                   const T* __restrict__ zeta_row,
-                                                   int32_t* __restrict__ status)
-{
-    using T4 = typename Vec4<T>::type;
-    extern __shared__ double shq[];
-    const BlockEntry be = blocks[blockIdx.x];
-    const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
-    const int P = R.P;
-    double* r = shq + (size_t)threadIdx.x * 4 * P;
-    double* v = r + P;
-    double* q = v + P;
-    double* p = q + P;
-    const int i = be.atom0 + threadIdx.x;
-    const int N = R.N, dims = R.dims;
-    if (i >= N) return;
-    const int sp = R.species[i];
-    const double kick = R.kick[sp], sig = R.sigma[sp], c1 = R.c1;
-    const T* __restrict__ force = (const T*)R.force;
-    const T* __restrict__ z = zeta_row + R.dof_off;
-    const double* __restrict__ C = R.nm;
-    const double* __restrict__ ring = R.ring;
-    double umax = 0.0;
-    bool finite = true;
-    T4* __restrict__ u = (T4*)R.u;
-    for (int a = 0; a < dims; ++a) {
-        for (int s = 0; s < P; ++s) {
-            const size_t idx = ((size_t)s * dims + a) * N + i;
-            r[s] = R.pos[idx];
-            v[s] = R.vel[idx] + kick * (double)force[idx];
-        }
-        for (int k = 0; k < P; ++k) {
-            double qa = 0.0, pa = 0.0;
-            for (int s = 0; s < P; ++s) {
-                qa += C[s * P + k] * r[s];
-                pa += C[s * P + k] * v[s];
-            }
-            q[k] = qa;
-            p[k] = pa;
-        }
-        const int64_t dof0 = ((int64_t)dims * i + a) * P;
-        for (int k = 0; k < P; ++k) {
-            const double cw = ring[k], sw = ring[P + k], ws = ring[2 * P + k];
-            double q1 = cw * q[k] + sw * p[k];
-            double p1 = ws * q[k] + cw * p[k];
-            p1 = c1 * p1 + sig * (double)z[dof0 + k];
-            q[k] = cw * q1 + sw * p1;
-            p[k] = ws * q1 + cw * p1;
-        }
-        for (int s = 0; s < P; ++s) {
-            double ra = 0.0, va = 0.0;
-            for (int k = 0; k < P; ++k) {
-                ra += C[s * P + k] * q[k];
-                va += C[s * P + k] * p[k];
-            }
-            const size_t idx = ((size_t)s * dims + a) * N + i;
-            R.pos[idx] = ra;
-            R.vel[idx] = va;
-            finite = finite && __builtin_isfinite(ra) && __builtin_isfinite(va);
-            if (PAIR) {
-                const double du = ra - R.rref[(size_t)a * N + i];
-                umax = fmax(umax, fabs(du));
-                T* comp = (T*)&u[(size_t)s * N + i];
-                comp[a] = (T)du;
-            }
+        __syncthreads();
+        if (t < A && be.atom0 + t < N) {
+            double d2 = 0.0;
+            for (int b = 0; b < P; ++b) d2 = fmax(d2, xv[b * A + t]);
+            R.dev[be.atom0 + t] = sqrt(d2);
         }
     }
-    if (PAIR) {
-        const T spb = bits_as<T>(sp);
-        for (int s = 0; s < P; ++s) ((T*)&u[(size_t)s * N + i])[3] = spb;
-        if (!(umax <= R.u_lim)) atomicOr(R.rebuild, 1);
-    }
-    if (!finite) atomicOr(status, kStatusNonfinite);
-}
-
-template <typename T, bool PAIR>
-void launch_T(hipStream_t st, int P, const RepDev* reps, const BlockEntry* blocks, int n_blocks,
-              const T* zrow, int32_t* status)
-{
-    const dim3 g(n_blocks), b(256);
-    switch (P) {
-#define QTB_UPD(PP) case PP: hipLaunchKernelGGL((k_update<PP, T, PAIR>), g, b, 0, st, reps, blocks, zrow, status); return;
-    QTB_UPD(1) QTB_UPD(2) QTB_UPD(3) QTB_UPD(4) QTB_UPD(5) QTB_UPD(6) QTB_UPD(7) QTB_UPD(8)
-#undef QTB_UPD
-    default: break;
+    __syncthreads();
+    if (t == 0 && flags) {
+        if (flags & 8) {
+            atomicOr(R.rebuild, 1);
+            atomicOr(status + kAnyRebuild, 1);
+        }
+        if (flags & kStatusNonfinite) atomicOr(status, kStatusNonfinite);
     }
 }
 
 }  // namespace
 
-// P <= 8: blocks of 256 atoms.  P > 8: the LDS kernel, whose block table
-// holds 64 atoms per entry.
-void launch_update(hipStream_t st, bool fp64, bool pair, int P, const RepDev* reps,
+// Block tables hold A atoms per entry (in .group), A dims P <= kUpdThreads.
+int update_block_atoms(int dims, int P)
+{
+    int A = kUpdThreads / (dims * P);
+    return A < 1 ? 1 : A;
+}
+
+void launch_update(hipStream_t st, bool fp64, bool pair, int, const RepDev* reps,
                    const BlockEntry* blocks, int n_blocks, const void* zeta_row, int32_t* status)
 {
-    if (P <= 8) {
-        if (fp64) {
-            if (pair) launch_T<double, true>(st, P, reps, blocks, n_blocks, (const double*)zeta_row, status);
-            else launch_T<double, false>(st, P, reps, blocks, n_blocks, (const double*)zeta_row, status);
-        } else {
-            if (pair) launch_T<float, true>(st, P, reps, blocks, n_blocks, (const float*)zeta_row, status);
-            else launch_T<float, false>(st, P, reps, blocks, n_blocks, (const float*)zeta_row, status);
-        }
-        return;
-    }
-    const size_t lds = (size_t)64 * 4 * P * sizeof(double);
-    const dim3 g(n_blocks), b(64);
+    const dim3 g(n_blocks), b(kUpdThreads);
     if (fp64) {
-        if (pair) hipLaunchKernelGGL((k_update_lds<double, true>), g, b, lds, st, reps, blocks, (const double*)zeta_row, status);
-        else hipLaunchKernelGGL((k_update_lds<double, false>), g, b, lds, st, reps, blocks, (const double*)zeta_row, status);
+        if (pair) hipLaunchKernelGGL((k_update<double, true>), g, b, 0, st, reps, blocks, (const double*)zeta_row, status);
+        else hipLaunchKernelGGL((k_update<double, false>), g, b, 0, st, reps, blocks, (const double*)zeta_row, status);
     } else {
-        if (pair) hipLaunchKernelGGL((k_update_lds<float, true>), g, b, lds, st, reps, blocks, (const float*)zeta_row, status);
-        else hipLaunchKernelGGL((k_update_lds<float, false>), g, b, lds, st, reps, blocks, (const float*)zeta_row, status);
+        if (pair) hipLaunchKernelGGL((k_update<float, true>), g, b, 0, st, reps, blocks, (const float*)zeta_row, status);
+        else hipLaunchKernelGGL((k_update<float, false>), g, b, 0, st, reps, blocks, (const float*)zeta_row, status);
     }
 }
 

@@ -22,6 +22,7 @@ NOISE_CLASSICAL, NOISE_QTB, NOISE_QTB_PIMD = 0, 1, 2
 PREC_FP32, PREC_FP64 = 0, 1
 FIR_FP32, FIR_BF16X3, FIR_BF16, FIR_FP64 = 0, 1, 2, 3
 POT_PAIR, POT_HARMONIC = 0, 1
+OPT_NO_GRAPH = 1
 MAX_SPECIES = 4
 
 _STATUS = {1: "QTB_E_INVALID", 2: "QTB_E_NOMEM", 3: "QTB_E_DEVICE", 4: "QTB_E_STATE",
@@ -60,7 +61,8 @@ class qtb_options(ctypes.Structure):
                 ("coulomb_k", ctypes.c_double), ("mass_unit", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("fir", ctypes.c_int32),
                 ("fir_block_K", ctypes.c_int32), ("obs_every", ctypes.c_int32),
-                ("max_two_nf", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("max_two_nf", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class qtb_obs(ctypes.Structure):
@@ -76,7 +78,10 @@ class qtb_obs(ctypes.Structure):
 
 EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
            "qtb_observables", "qtb_get_state", "qtb_set_state", "qtb_evaluate",
-           "qtb_get_noise", "qtb_gaussian", "qtb_last_error", "qtb_destroy", "qtb_version")
+           "qtb_get_noise", "qtb_gaussian", "qtb_profile", "qtb_profile_read",
+           "qtb_last_error", "qtb_destroy", "qtb_version")
+N_PHASES = 6
+PHASES = ("noise", "fir", "update", "nlist", "forces", "obs")
 
 _lib = None
 
@@ -115,6 +120,10 @@ def lib():
     L.qtb_gaussian.restype = ctypes.c_int
     L.qtb_gaussian.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                                ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, vp, vp]
+    L.qtb_profile.restype = ctypes.c_int
+    L.qtb_profile.argtypes = [vp, ctypes.c_int32]
+    L.qtb_profile_read.restype = ctypes.c_int
+    L.qtb_profile_read.argtypes = [vp, _PD, ctypes.POINTER(ctypes.c_int64)]
     L.qtb_last_error.restype = ctypes.c_char_p
     L.qtb_last_error.argtypes = [vp]
     L.qtb_destroy.restype = None
@@ -177,7 +186,8 @@ class Context:
     """Owns the device buffers (torch) of a qtb_ctx and forwards the C calls."""
 
     def __init__(self, potential: dict, replicas: list[Replica], units: dict, *,
-                 prec=PREC_FP32, fir=FIR_BF16X3, fir_block_K=64, obs_every=0, max_two_nf=512):
+                 prec=PREC_FP32, fir=FIR_BF16X3, fir_block_K=64, obs_every=0, max_two_nf=512,
+                 graphs=True, stream=None):
         torch = _torch()
         L = lib()
         self._keep = []
@@ -229,6 +239,7 @@ class Context:
         opt.coulomb_k, opt.mass_unit = units.get("coulomb_k", 0.0), units["mass_unit"]
         opt.prec, opt.fir, opt.fir_block_K = prec, fir, fir_block_K
         opt.obs_every, opt.max_two_nf = obs_every, max_two_nf
+        opt.flags = 0 if graphs else OPT_NO_GRAPH
         self.opt = opt
         nbytes = L.qtb_workspace_bytes(ctypes.byref(pot), self.reps, self.n_rep, ctypes.byref(opt))
         if nbytes == 0:
@@ -237,7 +248,10 @@ class Context:
         # torch's allocator returns 512-byte aligned blocks
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
-        self.stream = current_stream_ptr()
+        # a stream of its own (default priority): graph capture needs a
+        # non-default stream; the C calls that read results synchronise it
+        self.torch_stream = stream if stream is not None else torch.cuda.Stream()
+        self.stream = ctypes.c_void_p(self.torch_stream.cuda_stream)
         self.ctx = ctypes.c_void_p()
         _check(L.qtb_init(ctypes.byref(self.ctx), ctypes.byref(pot), self.reps, self.n_rep,
                           ctypes.byref(opt), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
@@ -286,6 +300,16 @@ class Context:
         n0 = ctypes.c_int64()
         _check(lib().qtb_get_noise(self.ctx, replica, _pd(z), ctypes.byref(n0)), self.ctx)
         return z, n0.value
+
+    def profile(self, enable: bool):
+        _check(lib().qtb_profile(self.ctx, 1 if enable else 0), self.ctx)
+
+    def profile_read(self):
+        ms = np.zeros(N_PHASES)
+        n = np.zeros(N_PHASES, dtype=np.int64)
+        _check(lib().qtb_profile_read(self.ctx, _pd(ms),
+                                      n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), self.ctx)
+        return {PHASES[q]: (float(ms[q]), int(n[q])) for q in range(N_PHASES)}
 
     def close(self):
         if getattr(self, "ctx", None) and self.ctx.value:

@@ -232,3 +232,48 @@ def test_nonfinite_state_detected():
     with pytest.raises(qtb.QtbError) as e:
         ctx.observables(0)
     assert e.value.status == qtb.QTB_E_NONFINITE
+
+
+# ------------------------------------------------------------------ graphs
+@pytest.mark.parametrize("prec,fir", [(qtb.PREC_FP64, qtb.FIR_FP64), (qtb.PREC_FP32, qtb.FIR_BF16X3)])
+def test_graph_replay_matches_eager(prec, fir):
+    """Whole noise blocks replayed as captured graphs give bit-identical states
+    to the eager launches, replay after replay, with host work in between."""
+    beads, sp, box = crystal(3, 4, seed=8, bead_spread=0.02)
+    kw = dict(T=50.0, gamma=5e-3, dt=1.0, noise=2, prec=prec, fir=fir, seed=4, K=64,
+              max_two_nf=256, obs_every=16)
+    g = gpu_crystal_ctx(beads, sp, box, graphs=True, **kw)
+    e = gpu_crystal_ctx(beads, sp, box, graphs=False, **kw)
+    for c in (g, e):
+        c.build_filter(0, 2, 256)
+    for blk in range(4):
+        g.step(64)
+        e.step(64)
+        rg, vg, sg = g.get_state(0)
+        re, ve, se = e.get_state(0)
+        assert sg == se == 64 * (blk + 1)
+        assert np.array_equal(rg, re) and np.array_equal(vg, ve), blk
+        og, oe = g.observables(0), e.observables(0)
+        assert og == oe
+    # a partial block, then graphs again
+    g.step(10); e.step(10)
+    g.step(128); e.step(128)
+    rg, vg, _ = g.get_state(0)
+    re, ve, _ = e.get_state(0)
+    assert np.array_equal(rg, re) and np.array_equal(vg, ve)
+
+
+@pytest.mark.parametrize("prec,tol", [(qtb.PREC_FP64, 1e-9), (qtb.PREC_FP32, 1e-5)])
+def test_trajectory_with_frequent_rebuilds(orc, prec, tol):
+    """A 0.02 A skin forces neighbour-list rebuilds during the run; the
+    trajectory must still follow the oracle (which never misses a pair)."""
+    beads, sp, box = crystal(3, 4, seed=12, bead_spread=0.03)
+    p = W.mgo_potential(skin=0.02)
+    fir = qtb.FIR_FP64 if prec == qtb.PREC_FP64 else qtb.FIR_FP32
+    ctx = gpu_crystal_ctx(beads, sp, box, T=300.0, gamma=2e-3, dt=1.0, noise=2, prec=prec,
+                          fir=fir, seed=21, max_two_nf=128, pot=p)
+    ctx.build_filter(0, 2, 128)
+    osim = orc.Sim(oracle_pair_pot(orc), oracle_units(orc, False), beads.shape[2], 4, 3, box, sp,
+                   300.0, 2e-3, 1.0, 21, 0, 2, 128, beads, n_threads=8)
+    rel, _ = _traj_compare(orc, ctx, osim, 30, scale=0.0421)
+    assert rel <= tol, rel

@@ -122,3 +122,22 @@ def test_neighbour_list_forces_match_bruteforce(orc, U, P):
         for b in range(P):
             _, fb, _ = orc.pair_bruteforce(pot, U, box, sp, beads[b])
             assert np.linalg.norm(f[b] - fb) / np.linalg.norm(fb) < 1e-12
+
+
+def test_neighbour_list_complete_for_spread_ring_polymers(orc, U):
+    """Beads spread far beyond skin/2 from their centroids, tiny skin: the list
+    (built from centroids) must still hold every pair within r_cut, at init
+    and after steps with rebuilds."""
+    pos, sp, box = W.rocksalt(3)
+    P = 4
+    beads = np.stack([W.displaced(pos, 0.12, 40 + b) for b in range(P)])
+    pot = mgo_pot(orc, skin=0.02)
+    s = orc.Sim(pot, U, pos.shape[1], P, 3, box, sp, 300.0, 2e-3, 1.0, 3, 0, 0, 2, beads,
+                n_threads=8)
+    for n in (0, 5, 10):
+        if n:
+            s.run(5)
+        r, _, f, _ = s.state()
+        for b in range(P):
+            _, fb, _ = orc.pair_bruteforce(pot, U, box, sp, r[b])
+            assert np.linalg.norm(f[b] - fb) / np.linalg.norm(fb) < 1e-12, (n, b)
