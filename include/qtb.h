@@ -145,6 +145,9 @@ typedef struct {
  * blocks as captured HIP graphs (graphs are used on a non-default stream when
  * obs_every is 0 or divides fir_block_K). */
 #define QTB_OPT_NO_GRAPH 1
+/* qtb_options.flags: keep the default force-kernel decomposition instead of
+ * timing the candidates on the first qtb_step (the autotuner). */
+#define QTB_OPT_NO_AUTOTUNE 2
 
 /* Means over the samples taken since the previous qtb_observables call of
  * this replica (eq. 5 primitive estimator with instantaneous momenta). */

@@ -212,11 +212,11 @@ void launch_fir_K(hipStream_t st, int mode, const FirTile* tiles, int n_tiles, c
 {
     const int L = max_two_nf + 2 * kPad;
     if (mode == QTB_FIR_FP64) {
-        hipLaunchKernelGGL(k_fir_fp64<K>, dim3(n_tiles), dim3(256), L * sizeof(double), st,
+        launch(k_fir_fp64<K>, dim3(n_tiles), dim3(256), L * sizeof(double), st,
                            tiles, (const double*)taps, (const double*)ring, (double*)zeta,
                            n_cols, nb, R);
     } else if (mode == QTB_FIR_FP32) {
-        hipLaunchKernelGGL(k_fir_f32<K>, dim3(n_tiles * 2), dim3(256), L * sizeof(float), st,
+        launch(k_fir_f32<K>, dim3(n_tiles * 2), dim3(256), L * sizeof(float), st,
                            tiles, (const float*)taps, (const float*)ring, (float*)zeta, n_cols,
                            nb, R);
     } else {
@@ -225,11 +225,11 @@ void launch_fir_K(hipStream_t st, int mode, const FirTile* tiles, int n_tiles, c
         allow_lds(k_fir_bf16<K, true>, lds);
         allow_lds(k_fir_bf16<K, false>, lds);
         if (mode == QTB_FIR_BF16X3)
-            hipLaunchKernelGGL((k_fir_bf16<K, true>), dim3(n_tiles * 2), dim3(256), lds, st,
+            launch((k_fir_bf16<K, true>), dim3(n_tiles * 2), dim3(256), lds, st,
                                tiles, (const float*)taps, (const float*)ring, (float*)zeta,
                                n_cols, nb, R, LR);
         else
-            hipLaunchKernelGGL((k_fir_bf16<K, false>), dim3(n_tiles * 2), dim3(256), lds, st,
+            launch((k_fir_bf16<K, false>), dim3(n_tiles * 2), dim3(256), lds, st,
                                tiles, (const float*)taps, (const float*)ring, (float*)zeta,
                                n_cols, nb, R, LR);
     }

@@ -58,18 +58,18 @@ __device__ __forceinline__ int32_t vbits(d4v x) { return (int32_t)__double_as_lo
 // NS: species count rounded up to 2 or 4 (parameters of the centre atom's
 // row are kept in registers and picked per neighbour with selects).
 // FAST (FP32 only): hardware rsq / exp2 and the fitted erfcx polynomial.
-template <typename T, int G, int W, int NS, bool FAST, int DEG>
+template <typename T, int G, int NS, bool FAST, int DEG>
 __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ reps,
                                                     const BlockEntry* __restrict__ blocks,
                                                     const PairTable<T> tab, int32_t flags,
                                                     double* __restrict__ partials,
                                                     int32_t* __restrict__ rebuild_clear, int n_rep,
-                                                    int32_t* __restrict__ rebuild_any)
+                                                    int32_t* __restrict__ rebuild_any, int W)
 {
     using V4 = typename NV<T>::v4;
     constexpr int NCH = 64 / G;   // neighbour chunks per wavefront
-    constexpr int APB = 4 / W;    // atoms per block (W wavefronts per atom)
-    __shared__ double part[APB][W][G][4];
+    // W wavefronts per atom (1, 2 or 4), 4 / W atoms per block
+    __shared__ double part[4][G][4];
     __shared__ double red[4][kNobs];
     const BlockEntry be = blocks[blockIdx.x];
     const int rep = __builtin_amdgcn_readfirstlane(be.rep);
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
         const T rc2 = tab.rc2, a2l = tab.a2l, s_mul = tab.s_mul, alpha = tab.alpha, g = tab.g;
         gptr<V4> ent = (gptr<V4>)R.nb_entries + (size_t)i * R.maxnb;
         const int cnt = R.nb_count[i];
-        constexpr int ST = NCH * W;
+        const int ST = NCH * W;
         // three-stage pipeline: entry q+2*ST and the neighbour of entry q+ST
         // are loading while the pair of entry q is evaluated
         int q = ch;
@@ -204,18 +204,18 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
     }
     if (W > 1) {
         if (lane < G) {
-            part[slot][wsub][lane][0] = fx;
-            part[slot][wsub][lane][1] = fy;
-            part[slot][wsub][lane][2] = fz;
-            part[slot][wsub][lane][3] = e;
+            part[wave][lane][0] = fx;
+            part[wave][lane][1] = fy;
+            part[wave][lane][2] = fz;
+            part[wave][lane][3] = e;
         }
         __syncthreads();
         if (wsub == 0 && lane < G) {
             for (int w = 1; w < W; ++w) {
-                fx += part[slot][w][lane][0];
-                fy += part[slot][w][lane][1];
-                fz += part[slot][w][lane][2];
-                e += part[slot][w][lane][3];
+                fx += part[wave + w][lane][0];
+                fy += part[wave + w][lane][1];
+                fz += part[wave + w][lane][2];
+                e += part[wave + w][lane][3];
             }
         }
     }
@@ -371,15 +371,14 @@ __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v)
 template <typename T, int NS, bool FAST, int DEG>
 void launch_pair_G(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
                    int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
-                   int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any)
+                   int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any, int W)
 {
     const dim3 g(n_blocks), b(256);
-    constexpr int W = kWavesPerAtom;
     switch (G) {
-    case 1: hipLaunchKernelGGL((k_force_pair<T, 1, W, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any); break;
-    case 2: hipLaunchKernelGGL((k_force_pair<T, 2, W, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any); break;
-    case 4: hipLaunchKernelGGL((k_force_pair<T, 4, W, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any); break;
-    case 8: hipLaunchKernelGGL((k_force_pair<T, 8, W, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any); break;
+    case 1: launch((k_force_pair<T, 1, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W); break;
+    case 2: launch((k_force_pair<T, 2, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W); break;
+    case 4: launch((k_force_pair<T, 4, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W); break;
+    case 8: launch((k_force_pair<T, 8, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W); break;
     default: break;
     }
 }
@@ -387,17 +386,17 @@ void launch_pair_G(hipStream_t st, int G, const RepDev* reps, const BlockEntry* 
 template <typename T, bool FAST, int DEG>
 void launch_pair_T(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
                    int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
-                   int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any)
+                   int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any, int W)
 {
     if (tab.n_species <= 2)
-        launch_pair_G<T, 2, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any);
+        launch_pair_G<T, 2, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W);
     else
-        launch_pair_G<T, 4, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any);
+        launch_pair_G<T, 4, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W);
 }
 
 }  // namespace
 
-void launch_forces_pair(hipStream_t st, bool fp64, int G, const RepDev* reps,
+void launch_forces_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* reps,
                         const BlockEntry* blocks, int n_blocks, const void* table, int32_t flags,
                         double* partials, int32_t* rebuild_clear, int n_rep,
                         int32_t* rebuild_any)
@@ -405,18 +404,18 @@ void launch_forces_pair(hipStream_t st, bool fp64, int G, const RepDev* reps,
     if (fp64) {
         launch_pair_T<double, false, 1>(st, G, reps, blocks, n_blocks,
                                      *(const PairTable<double>*)table, flags, partials,
-                                     rebuild_clear, n_rep, rebuild_any);
+                                     rebuild_clear, n_rep, rebuild_any, W);
     } else {
         const PairTable<float>& t = *(const PairTable<float>*)table;
         if (t.ex_deg == 10)
             launch_pair_T<float, true, 10>(st, G, reps, blocks, n_blocks, t, flags, partials,
-                                           rebuild_clear, n_rep, rebuild_any);
+                                           rebuild_clear, n_rep, rebuild_any, W);
         else if (t.ex_deg == kErfcxMaxDeg)
             launch_pair_T<float, true, kErfcxMaxDeg>(st, G, reps, blocks, n_blocks, t, flags,
-                                                     partials, rebuild_clear, n_rep, rebuild_any);
+                                                     partials, rebuild_clear, n_rep, rebuild_any, W);
         else
             launch_pair_T<float, false, 1>(st, G, reps, blocks, n_blocks, t, flags, partials,
-                                           rebuild_clear, n_rep, rebuild_any);
+                                           rebuild_clear, n_rep, rebuild_any, W);
     }
 }
 
@@ -425,17 +424,17 @@ void launch_forces_harmonic(hipStream_t st, bool fp64, const RepDev* reps,
                             double* partials)
 {
     if (fp64)
-        hipLaunchKernelGGL(k_force_harmonic<double>, dim3(n_blocks), dim3(256), 0, st, reps,
+        launch(k_force_harmonic<double>, dim3(n_blocks), dim3(256), 0, st, reps,
                            blocks, flags, partials);
     else
-        hipLaunchKernelGGL(k_force_harmonic<float>, dim3(n_blocks), dim3(256), 0, st, reps,
+        launch(k_force_harmonic<float>, dim3(n_blocks), dim3(256), 0, st, reps,
                            blocks, flags, partials);
 }
 
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
                        double* acc, int32_t* counts)
 {
-    hipLaunchKernelGGL(k_obs_reduce, dim3((n_rep + 63) / 64), dim3(64), 0, st, reps, n_rep,
+    launch(k_obs_reduce, dim3((n_rep + 63) / 64), dim3(64), 0, st, reps, n_rep,
                        partials, acc, counts);
 }
 
@@ -444,7 +443,7 @@ void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value)
     if (n_words <= 0) return;
     int64_t blocks = (n_words + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, (int32_t*)p, n_words,
+    launch(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, (int32_t*)p, n_words,
                        value);
 }
 

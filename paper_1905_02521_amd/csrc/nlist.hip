@@ -60,17 +60,11 @@ __global__ void __launch_bounds__(256) k_centroids(const RepDev* __restrict__ re
 // j = j0 + l; matches are compacted with a ballot, so entries come out in a
 // fixed order (j chunk, image, lane) whatever the timing.
 template <typename T>
-__global__ void __launch_bounds__(256) k_nlist(const RepDev* __restrict__ reps,
-                                               const BlockEntry* __restrict__ blocks,
-                                               int32_t* __restrict__ status)
+__device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be,
+                                            int32_t* __restrict__ status, double* tx, double* ty,
+                                            double* tz, double* td, double* dmax_s)
 {
     using T4 = typename Vec4<T>::type;
-    __shared__ double tx[256], ty[256], tz[256], td[256];
-    __shared__ double dmax_s[4];
-    if (status[kAnyRebuild] == 0) return;  // nothing to do: one load, then exit
-    const BlockEntry be = blocks[blockIdx.x];
-    const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
-    if (*R.rebuild == 0) return;  // uniform over the block
     const int N = R.N, P = R.P;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = be.atom0 + wave;
@@ -171,19 +165,37 @@ __global__ void __launch_bounds__(256) k_nlist(const RepDev* __restrict__ reps,
     }
 }
 
+// Grid-stride over the block table with at most a few hundred workgroups, so
+// the launch of a step that needs no rebuild costs one flag load per group.
+template <typename T>
+__global__ void __launch_bounds__(256) k_nlist(const RepDev* __restrict__ reps,
+                                               const BlockEntry* __restrict__ blocks,
+                                               int n_entries, int32_t* __restrict__ status)
+{
+    __shared__ double tx[256], ty[256], tz[256], td[256];
+    __shared__ double dmax_s[4];
+    if (status[kAnyRebuild] == 0) return;  // nothing to do: one load, then exit
+    for (int e = blockIdx.x; e < n_entries; e += gridDim.x) {
+        const BlockEntry be = blocks[e];
+        const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+        if (*R.rebuild == 0) continue;  // uniform over the block
+        nlist_entry<T>(R, be, status, tx, ty, tz, td, dmax_s);
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
                   int n_blocks, int32_t* status, bool centroids)
 {
     if (centroids)
-        hipLaunchKernelGGL(k_centroids, dim3(n_blocks), dim3(64), 0, st, reps, blocks);
+        launch(k_centroids, dim3(n_blocks), dim3(64), 0, st, reps, blocks);
+    const int grid = n_blocks < 256 ? n_blocks : 256;
     if (fp64)
-        hipLaunchKernelGGL(k_nlist<double>, dim3(n_blocks), dim3(256), 0, st, reps, blocks,
-                           status);
+        launch(k_nlist<double>, dim3(grid), dim3(256), 0, st, reps, blocks, n_blocks, status);
     else
-        hipLaunchKernelGGL(k_nlist<float>, dim3(n_blocks), dim3(256), 0, st, reps, blocks,
-                           status);
+        launch(k_nlist<float>, dim3(grid), dim3(256), 0, st, reps, blocks, n_blocks, status);
 }
 
 }  // namespace qtb

@@ -166,7 +166,7 @@ void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t ta
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) return;
-    hipLaunchKernelGGL(k_gaussian, dim3((unsigned)blocks), dim3(256), 0, st, seed, stream, tag,
+    launch(k_gaussian, dim3((unsigned)blocks), dim3(256), 0, st, seed, stream, tag,
                        n0, n_rows, d0, n_dof, out);
 }
 
@@ -177,10 +177,10 @@ void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, 
     if (rows <= 0) return;
     dim3 grid((unsigned)((n_cols + 255) / 256), (unsigned)rows);
     if (fp64)
-        hipLaunchKernelGGL(k_gen_white<double>, grid, dim3(256), 0, st, reps, tiles,
+        launch(k_gen_white<double>, grid, dim3(256), 0, st, reps, tiles,
                            (double*)ring, clock, off, R, n_cols);
     else
-        hipLaunchKernelGGL(k_gen_white<float>, grid, dim3(256), 0, st, reps, tiles,
+        launch(k_gen_white<float>, grid, dim3(256), 0, st, reps, tiles,
                            (float*)ring, clock, off, R, n_cols);
 }
 
@@ -193,7 +193,7 @@ __global__ void k_clock(int64_t* clock, int64_t v, int add)
 
 void launch_clock(hipStream_t st, int64_t* clock, int64_t v, bool add)
 {
-    hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, st, clock, v, add ? 1 : 0);
+    launch(k_clock, dim3(1), dim3(64), 0, st, clock, v, add ? 1 : 0);
 }
 
 }  // namespace qtb

@@ -47,7 +47,11 @@ struct Layout {
     int R = 0, K = 0, max_two_nf = 0, taps_stride = 0;
     std::vector<int64_t> dof_off;
     std::vector<int> maxnb;
-    std::vector<BlockEntry> upd, nl, force;
+    std::vector<BlockEntry> upd, nl, force;   // force: table of the chosen W
+    std::vector<BlockEntry> force_w[3];        // W = 1, 2, 4
+    std::vector<std::pair<int, std::pair<int, int>>> force_groups_w[3];
+    std::vector<int> obs_b0_w[3], obs_nb_w[3];
+    size_t max_force_blocks = 1;
     std::vector<std::pair<int, std::pair<int, int>>> upd_groups;    // P -> [b0, b1)
     std::vector<std::pair<int, std::pair<int, int>>> force_groups;  // G -> [b0, b1)
     std::vector<int> obs_b0, obs_nb;
@@ -172,36 +176,42 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     }
     for (int r = 0; r < n_rep; ++r)
         for (int a = 0; a < reps[r].n_atoms; a += 4) L.nl.push_back({r, a, 0, 0});
-    L.obs_b0.assign(n_rep, 0);
-    L.obs_nb.assign(n_rep, 0);
-    for (auto& kv : byG) {
-        const int G = kv.first;
-        const int b0 = (int)L.force.size();
-        for (int r : kv.second) {
-            L.obs_b0[r] = (int)L.force.size();
-            if (pair) {
-                for (int g = 0; g < reps[r].n_beads / G; ++g)
-                    for (int a = 0; a < reps[r].n_atoms; a += kAtomsPerBlock)
-                        L.force.push_back({r, a, g, 0});
-            } else {
-                for (int a = 0; a < reps[r].n_atoms; a += 256) L.force.push_back({r, a, 0, 0});
+    // force tables for every waves-per-atom choice (the autotuner picks one)
+    for (int wi = 0; wi < 3; ++wi) {
+        const int W = 1 << wi, apb = 4 / W;
+        auto& F = L.force_w[wi];
+        auto& FG = L.force_groups_w[wi];
+        F.clear();
+        FG.clear();
+        L.obs_b0_w[wi].assign(n_rep, 0);
+        L.obs_nb_w[wi].assign(n_rep, 0);
+        if (pair) {
+            for (auto& kv : byG) {
+                const int G = kv.first;
+                const int b0 = (int)F.size();
+                for (int r : kv.second) {
+                    L.obs_b0_w[wi][r] = (int)F.size();
+                    for (int g = 0; g < reps[r].n_beads / G; ++g)
+                        for (int a = 0; a < reps[r].n_atoms; a += apb) F.push_back({r, a, g, 0});
+                    L.obs_nb_w[wi][r] = (int)F.size() - L.obs_b0_w[wi][r];
+                }
+                FG.push_back({G, {b0, (int)F.size()}});
             }
-            L.obs_nb[r] = (int)L.force.size() - L.obs_b0[r];
+        } else {
+            for (int r = 0; r < n_rep; ++r) {
+                L.obs_b0_w[wi][r] = (int)F.size();
+                for (int a = 0; a < reps[r].n_atoms; a += 256) F.push_back({r, a, 0, 0});
+                L.obs_nb_w[wi][r] = (int)F.size() - L.obs_b0_w[wi][r];
+            }
+            FG.push_back({0, {0, (int)F.size()}});
         }
-        L.force_groups.push_back({pair ? G : 0, {b0, (int)L.force.size()}});
-        if (!pair) break;  // harmonic: every replica went into the first group
+        L.max_force_blocks = std::max(L.max_force_blocks, F.size());
     }
-    if (!pair) {
-        // harmonic kernel ignores G; rebuild a single group over all replicas
-        L.force.clear();
-        L.force_groups.clear();
-        for (int r = 0; r < n_rep; ++r) {
-            L.obs_b0[r] = (int)L.force.size();
-            for (int a = 0; a < reps[r].n_atoms; a += 256) L.force.push_back({r, a, 0, 0});
-            L.obs_nb[r] = (int)L.force.size() - L.obs_b0[r];
-        }
-        L.force_groups.push_back({0, {0, (int)L.force.size()}});
-    }
+    const int wdef = kWavesPerAtomDefault == 1 ? 0 : (kWavesPerAtomDefault == 2 ? 1 : 2);
+    L.force = L.force_w[wdef];
+    L.force_groups = L.force_groups_w[wdef];
+    L.obs_b0 = L.obs_b0_w[wdef];
+    L.obs_nb = L.obs_nb_w[wdef];
     L.tilev.assign(cols / kDofTile, FirTile{0, 2, 0, 0});
     for (int r = 0; r < n_rep; ++r) {
         const int64_t D = (int64_t)reps[r].n_dims * reps[r].n_atoms * reps[r].n_beads;
@@ -219,13 +229,13 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     add(cur, L.taps, zs * (size_t)L.taps_stride * n_rep);
     add(cur, L.ring, zs * (size_t)L.R * cols);
     add(cur, L.zeta, zs * (size_t)L.K * cols);
-    add(cur, L.partials, sizeof(double) * kNobs * std::max<size_t>(1, L.force.size()));
+    add(cur, L.partials, sizeof(double) * kNobs * L.max_force_blocks);
     add(cur, L.acc, sizeof(double) * kNobs * n_rep);
     add(cur, L.counts, sizeof(int32_t) * n_rep);
     add(cur, L.pairtab, sizeof(PairTable<double>));
     add(cur, L.blk_upd, sizeof(BlockEntry) * std::max<size_t>(1, L.upd.size()));
     add(cur, L.blk_nl, sizeof(BlockEntry) * std::max<size_t>(1, L.nl.size()));
-    add(cur, L.blk_force, sizeof(BlockEntry) * std::max<size_t>(1, L.force.size()));
+    add(cur, L.blk_force, sizeof(BlockEntry) * L.max_force_blocks);
     for (int r = 0; r < n_rep; ++r) {
         const qtb_replica& R = reps[r];
         const size_t N = R.n_atoms, P = R.n_beads, dm = R.n_dims;
@@ -280,6 +290,8 @@ struct qtb_ctx {
     int block_row = 0;
     bool ring_valid = false;
     std::string err;
+    int W = kWavesPerAtomDefault;  // force kernel wavefronts per atom
+    bool tuned = false;
     // one captured noise block of K steps, replayed while nothing changes
     hipGraphExec_t graph = nullptr;
     int64_t graph_phase = -1;  // block start modulo obs_every at capture
@@ -294,6 +306,14 @@ struct qtb_ctx {
     X* at(const Region& r) const { return reinterpret_cast<X*>(ws + r.off); }
 };
 
+namespace qtb {
+LaunchStamp& launch_stamp()
+{
+    static thread_local LaunchStamp ls;
+    return ls;
+}
+}  // namespace qtb
+
 namespace {
 
 hipEvent_t next_event(qtb_ctx* c)
@@ -306,24 +326,34 @@ hipEvent_t next_event(qtb_ctx* c)
     return c->ev_pool[c->ev_used++];
 }
 
-// RAII marker: event before and after one phase's launches.
+// Profiling marker of one phase: its first kernel launch stamps an event pair
+// from its own dispatch (the phase's other launches, if any, are not timed).
+// A phase with several launches (one per replica group) is timed with
+// event markers around all of them instead.
 struct Phase {
     qtb_ctx* c;
     size_t idx = 0;
-    bool on = false;
-    Phase(qtb_ctx* cc, int ph) : c(cc)
+    bool on = false, multi = false;
+    Phase(qtb_ctx* cc, int ph, bool several = false) : c(cc), multi(several)
     {
         if (!c->prof) return;
         idx = c->ev_used;
         hipEvent_t a = next_event(c), b = next_event(c);
         if (!a || !b) return;
-        (void)hipEventRecord(a, c->st);
+        if (multi) (void)hipEventRecord(a, c->st);
+        else launch_stamp() = LaunchStamp{a, b};
         c->ev_marks.push_back({ph, idx});
         on = true;
     }
     ~Phase()
     {
-        if (on) (void)hipEventRecord(c->ev_pool[idx + 1], c->st);
+        if (!on) return;
+        if (multi) {
+            (void)hipEventRecord(c->ev_pool[idx + 1], c->st);
+        } else if (launch_stamp().start) {  // nothing was launched in this phase
+            launch_stamp() = LaunchStamp{};
+            c->ev_marks.pop_back();
+        }
     }
 };
 
@@ -526,7 +556,7 @@ void launch_forces(qtb_ctx* c, int32_t flags)
         if (nb <= 0) continue;
         if (c->pair) {
             const void* tab = c->fp64 ? (const void*)&c->tabd : (const void*)&c->tabf;
-            launch_forces_pair(c->st, c->fp64, g.first, dreps, fb + b0, nb, tab, flags,
+            launch_forces_pair(c->st, c->fp64, g.first, c->W, dreps, fb + b0, nb, tab, flags,
                                part + (size_t)b0 * kNobs, c->at<int32_t>(L.rebuild), c->n_rep,
                                c->at<int32_t>(L.status) + kAnyRebuild);
         } else {
@@ -572,7 +602,7 @@ qtb_status read_status(qtb_ctx* c)
 void gen_rows(qtb_ctx* c, int64_t off, int64_t rows)
 {
     const Layout& L = c->L;
-    Phase ph(c, 0);
+    Phase ph(c, 0, rows > 1024);
     for (int64_t r0 = 0; r0 < rows; r0 += 1024) {
         const int rr = (int)std::min<int64_t>(1024, rows - r0);
         launch_gen_white(c->st, c->at<RepDev>(L.reps), c->at<FirTile>(L.tiles),
@@ -613,7 +643,7 @@ void record_step(qtb_ctx* c, int row, bool sample)
         launch_rebuild(c);
     }
     {
-        Phase ph(c, 4);
+        Phase ph(c, 4, L.force_groups.size() > 1);
         launch_forces(c, kKick | (sample ? kSample : 0));
     }
     if (sample) {
@@ -710,6 +740,67 @@ bool graph_block(qtb_ctx* c)
     c->block_row = L.K;
     c->step += L.K;
     return true;
+}
+
+// Make the force table of W current (host image, device copy, replica
+// observable ranges); drops the captured graph, whose launches embed it.
+qtb_status select_force_table(qtb_ctx* c, int W)
+{
+    Layout& L = c->L;
+    const int wi = W == 1 ? 0 : (W == 2 ? 1 : 2);
+    L.force = L.force_w[wi];
+    L.force_groups = L.force_groups_w[wi];
+    L.obs_b0 = L.obs_b0_w[wi];
+    L.obs_nb = L.obs_nb_w[wi];
+    c->W = W;
+    for (int r = 0; r < c->n_rep; ++r) {
+        c->rd[r].obs_block0 = L.obs_b0[r];
+        c->rd[r].obs_nblocks = L.obs_nb[r];
+    }
+    QTB_HIP(c, hipMemcpyAsync(c->at<void>(L.blk_force), L.force.data(),
+                              sizeof(BlockEntry) * L.force.size(), hipMemcpyHostToDevice, c->st));
+    qtb_status s = upload_tables(c);
+    if (s) return s;
+    drop_graph(c);
+    return QTB_OK;
+}
+
+// Autotuner: time the pair-force kernel of the actual workload for every
+// waves-per-atom choice (forces only, no kick: the state is unchanged) and
+// keep the fastest, best of three launches each (all replica groups).
+qtb_status autotune(qtb_ctx* c)
+{
+    c->tuned = true;
+    if (!c->pair || (c->opt.flags & QTB_OPT_NO_AUTOTUNE)) return QTB_OK;
+    hipEvent_t a = nullptr, b = nullptr;
+    QTB_HIP(c, hipEventCreate(&a));
+    QTB_HIP(c, hipEventCreate(&b));
+    float best = 1e30f;
+    int bestW = c->W;
+    for (int W : {1, 2, 4}) {
+        qtb_status s = select_force_table(c, W);
+        if (s) return s;
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            QTB_HIP(c, hipEventRecord(a, c->st));
+            launch_forces(c, 0);
+            QTB_HIP(c, hipEventRecord(b, c->st));
+            QTB_HIP(c, hipEventSynchronize(b));
+            float t = 0.0f;
+            QTB_HIP(c, hipEventElapsedTime(&t, a, b));
+            tmin = std::min(tmin, t);
+        }
+        if (tmin < best) {
+            best = tmin;
+            bestW = W;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    qtb_status s = select_force_table(c, bestW);
+    if (s) return s;
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    return QTB_OK;
 }
 
 }  // namespace
@@ -883,6 +974,10 @@ qtb_status qtb_step(qtb_ctx* c, int64_t n_steps)
     if (n_steps < 0) return fail(c, QTB_E_INVALID, "n_steps must be >= 0");
     for (int r = 0; r < c->n_rep; ++r)
         if (!c->filter_ready[r]) return fail(c, QTB_E_STATE, "qtb_build_filter not called");
+    if (!c->tuned && n_steps > 0) {
+        qtb_status s = autotune(c);
+        if (s) return s;
+    }
     int64_t left = n_steps;
     while (left > 0) {
         const bool at_boundary = c->ring_valid && (c->block_start < 0 || c->block_row >= c->L.K);

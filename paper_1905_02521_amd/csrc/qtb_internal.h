@@ -2,6 +2,7 @@
 // HIP kernels (gfx950).  Not part of the public ABI (include/qtb.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -13,8 +14,7 @@ namespace qtb {
 constexpr int kMaxSpecies = QTB_MAX_SPECIES;
 constexpr int kPairs = kMaxSpecies * kMaxSpecies;
 constexpr int kDofTile = 256;      // replica dof ranges are padded to this
-constexpr int kWavesPerAtom = 2;   // force kernel: wavefronts per atom
-constexpr int kAtomsPerBlock = 4 / kWavesPerAtom;  // force kernel block: 4 wavefronts
+constexpr int kWavesPerAtomDefault = 2;  // force kernel: wavefronts per atom (1, 2, 4)
 constexpr int kNobs = 6;           // ke, U, spring, virial, x2, (unused)
 
 // Pair potential in the form the force kernels evaluate:
@@ -102,6 +102,25 @@ constexpr int kAnyRebuild = 4;
 // Kernel-side flags of the force kernels.
 enum ForceFlags : int32_t { kKick = 1, kSample = 2, kEvaluate = 4 };
 
+// Profiling: when set, the next launch time-stamps these events from its own
+// dispatch packet (no marker packets around the kernel), then clears them.
+struct LaunchStamp {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchStamp& launch_stamp();
+
+template <typename F, typename... Args>
+inline void launch(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t st, Args... args)
+{
+    LaunchStamp& ls = launch_stamp();
+    if (ls.start) {
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, st, ls.start, ls.stop, 0, args...);
+        ls = LaunchStamp{};
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 // noise.hip
 void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, void* ring,
@@ -125,7 +144,7 @@ int update_block_atoms(int dims, int P);
 void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
                   int n_blocks, int32_t* status, bool centroids);
 // forces.hip
-void launch_forces_pair(hipStream_t st, bool fp64, int G, const RepDev* reps,
+void launch_forces_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* reps,
                         const BlockEntry* blocks, int n_blocks, const void* table,
                         int32_t flags, double* partials, int32_t* rebuild_clear, int n_rep,
                         int32_t* rebuild_any);

@@ -184,11 +184,11 @@ void launch_update(hipStream_t st, bool fp64, bool pair, int, const RepDev* reps
 {
     const dim3 g(n_blocks), b(kUpdThreads);
     if (fp64) {
-        if (pair) hipLaunchKernelGGL((k_update<double, true>), g, b, 0, st, reps, blocks, (const double*)zeta_row, status);
-        else hipLaunchKernelGGL((k_update<double, false>), g, b, 0, st, reps, blocks, (const double*)zeta_row, status);
+        if (pair) launch((k_update<double, true>), g, b, 0, st, reps, blocks, (const double*)zeta_row, status);
+        else launch((k_update<double, false>), g, b, 0, st, reps, blocks, (const double*)zeta_row, status);
     } else {
-        if (pair) hipLaunchKernelGGL((k_update<float, true>), g, b, 0, st, reps, blocks, (const float*)zeta_row, status);
-        else hipLaunchKernelGGL((k_update<float, false>), g, b, 0, st, reps, blocks, (const float*)zeta_row, status);
+        if (pair) launch((k_update<float, true>), g, b, 0, st, reps, blocks, (const float*)zeta_row, status);
+        else launch((k_update<float, false>), g, b, 0, st, reps, blocks, (const float*)zeta_row, status);
     }
 }
 

@@ -23,6 +23,7 @@ PREC_FP32, PREC_FP64 = 0, 1
 FIR_FP32, FIR_BF16X3, FIR_BF16, FIR_FP64 = 0, 1, 2, 3
 POT_PAIR, POT_HARMONIC = 0, 1
 OPT_NO_GRAPH = 1
+OPT_NO_AUTOTUNE = 2
 MAX_SPECIES = 4
 
 _STATUS = {1: "QTB_E_INVALID", 2: "QTB_E_NOMEM", 3: "QTB_E_DEVICE", 4: "QTB_E_STATE",
@@ -187,7 +188,7 @@ class Context:
 
     def __init__(self, potential: dict, replicas: list[Replica], units: dict, *,
                  prec=PREC_FP32, fir=FIR_BF16X3, fir_block_K=64, obs_every=0, max_two_nf=512,
-                 graphs=True, stream=None):
+                 graphs=True, autotune=True, stream=None):
         torch = _torch()
         L = lib()
         self._keep = []
@@ -239,7 +240,7 @@ class Context:
         opt.coulomb_k, opt.mass_unit = units.get("coulomb_k", 0.0), units["mass_unit"]
         opt.prec, opt.fir, opt.fir_block_K = prec, fir, fir_block_K
         opt.obs_every, opt.max_two_nf = obs_every, max_two_nf
-        opt.flags = 0 if graphs else OPT_NO_GRAPH
+        opt.flags = (0 if graphs else OPT_NO_GRAPH) | (0 if autotune else OPT_NO_AUTOTUNE)
         self.opt = opt
         nbytes = L.qtb_workspace_bytes(ctypes.byref(pot), self.reps, self.n_rep, ctypes.byref(opt))
         if nbytes == 0:

@@ -1,0 +1,103 @@
+"""Batched replicas: many replicas of uneven size, bead number, temperature,
+friction and noise kind step together (one launch per kernel covering all
+of them, one graph per noise block).  Each replica must evolve exactly as it
+does alone, and as the oracle says."""
+import numpy as np
+import pytest
+
+from paper_1905_02521_amd import qtb, workloads as W
+from tests.gpu_common import oracle_pair_pot, oracle_units, units_dict
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def replica_specs():
+    # (cells, P, T, gamma, noise, two_nf, stream)
+    return [(2, 1, 300.0, 1e-3, 1, 128, 0), (3, 4, 50.0, 5e-3, 2, 256, 1),
+            (2, 8, 80.0, 2e-2, 2, 128, 2), (3, 3, 120.0, 1e-3, 0, 2, 3),
+            (2, 2, 20.0, 5e-4, 2, 256, 4)]
+
+
+def make_reps(specs, seed=5):
+    reps = []
+    for k, (n, P, T, g, noise, two_nf, stream) in enumerate(specs):
+        pos, sp, box = W.rocksalt(n)
+        beads = np.stack([W.displaced(pos, 0.03, 100 * k + b) for b in range(P)])
+        reps.append((qtb.Replica(pos=beads, species=sp, T=T, gamma=g, dt=1.0, noise=noise,
+                                 box=tuple(box), seed=seed, stream=stream), two_nf))
+    return reps
+
+
+def ctx_for(reps, prec, fir, autotune=False, obs_every=0):
+    p = W.mgo_potential(skin=0.5)
+    c = qtb.Context(qtb.pair_potential_dict(p), [r for r, _ in reps], units_dict(False),
+                    prec=prec, fir=fir, fir_block_K=64, obs_every=obs_every,
+                    max_two_nf=max(t for _, t in reps), autotune=autotune)
+    for k, (r, t) in enumerate(reps):
+        if r.noise:
+            c.build_filter(k, r.noise, t)
+    return c
+
+
+@pytest.mark.parametrize("prec,fir", [(qtb.PREC_FP64, qtb.FIR_FP64),
+                                      (qtb.PREC_FP32, qtb.FIR_BF16X3)])
+def test_batched_equals_each_replica_alone(prec, fir):
+    reps = make_reps(replica_specs())
+    batch = ctx_for(reps, prec, fir)
+    batch.step(150)
+    for k, rep in enumerate(reps):
+        alone = ctx_for([rep], prec, fir)
+        alone.step(150)
+        rb, vb, sb = batch.get_state(k)
+        ra, va, sa = alone.get_state(0)
+        assert sb == sa == 150
+        assert np.array_equal(rb, ra) and np.array_equal(vb, va), k
+        alone.close()
+
+
+def test_batched_matches_oracle(orc):
+    reps = make_reps(replica_specs()[:4])
+    batch = ctx_for(reps, qtb.PREC_FP64, qtb.FIR_FP64, autotune=True)
+    batch.step(12)
+    U = oracle_units(orc, False)
+    pot = oracle_pair_pot(orc, W.mgo_potential(skin=0.5))
+    for k, (r, two_nf) in enumerate(reps):
+        P, _, N = r.pos.shape
+        s = orc.Sim(pot, U, N, P, 3, r.box, r.species, r.T, r.gamma, r.dt, r.seed, r.stream,
+                    r.noise, two_nf, r.pos, n_threads=8)
+        s.run(12)
+        ro, _, _, _ = s.state()
+        rb, _, _ = batch.get_state(k)
+        assert np.sqrt(np.mean((rb - ro) ** 2)) / 0.03 < 1e-9, k
+
+
+def test_autotuner_changes_only_rounding():
+    reps = make_reps(replica_specs()[:3])
+    a = ctx_for(reps, qtb.PREC_FP64, qtb.FIR_FP64, autotune=True)
+    b = ctx_for(reps, qtb.PREC_FP64, qtb.FIR_FP64, autotune=False)
+    a.step(20)
+    b.step(20)
+    for k in range(3):
+        ra, _, _ = a.get_state(k)
+        rb, _, _ = b.get_state(k)
+        assert np.max(np.abs(ra - rb)) < 1e-10
+
+
+def test_batched_observables_per_replica():
+    reps = make_reps(replica_specs())
+    c = ctx_for(reps, qtb.PREC_FP32, qtb.FIR_BF16X3, obs_every=8)
+    c.step(64)
+    for k, (r, _) in enumerate(reps):
+        o = c.observables(k)
+        P, _, N = r.pos.shape
+        assert o["n_samples"] == 8
+        assert np.isfinite(o["e_primitive"])
+        # kinetic temperature of the beads is of the order of T after 64 fs
+        assert 0.0 < o["t_kinetic"] < 20 * r.T

@@ -277,3 +277,17 @@ def test_trajectory_with_frequent_rebuilds(orc, prec, tol):
                    300.0, 2e-3, 1.0, 21, 0, 2, 128, beads, n_threads=8)
     rel, _ = _traj_compare(orc, ctx, osim, 30, scale=0.0421)
     assert rel <= tol, rel
+
+
+def test_profile_reports_every_phase():
+    beads, sp, box = crystal(3, 4, seed=2)
+    ctx = gpu_crystal_ctx(beads, sp, box, T=50.0, gamma=1e-3, dt=1.0, noise=2,
+                          prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3, max_two_nf=128)
+    ctx.build_filter(0, 2, 128)
+    ctx.profile(True)
+    ctx.step(128)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    assert prof["forces"][1] == 128 and prof["update"][1] == 128
+    assert prof["fir"][1] == 2 and prof["noise"][1] >= 2
+    assert all(v[0] > 0 for k, v in prof.items() if v[1] > 0)
