@@ -43,6 +43,104 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 
+# Sources whose change makes a stored HBM-traffic record of the pair kernel stale.
+FORCE_SOURCES = ("paper_1905_02521_amd/csrc/forces.hip", "paper_1905_02521_amd/csrc/qtb_internal.h")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def source_hash(paths=FORCE_SOURCES):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel_prefix="k_force_pair"):
+    """HBM bytes per launch of the pair kernel from the committed counter
+    summary (profiles/*traffic*.md, line 'traffic-record: {json}'), or None
+    when no record exists or the kernel source changed since it was taken."""
+    if not os.path.isdir(PROFILES):
+        return None
+    cur = source_hash()
+    for fn in sorted(os.listdir(PROFILES)):
+        if "traffic" not in fn:
+            continue
+        with open(os.path.join(PROFILES, fn)) as f:
+            for line in f:
+                if line.startswith("traffic-record:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec.get("kernel", "").startswith(kernel_prefix) and rec.get("source") == cur:
+                        return rec
+    return None
+
+
+def _short_name(name):
+    n = name.replace("qtb::(anonymous namespace)::", "")
+    if n.startswith("void "):
+        n = n[5:]
+    return n.split("(")[0]
+
+
+def rocprof_summary(dirs):
+    """Markdown summary of rocprofv3 CSV output: kernel stats of a trace run,
+    or per-kernel mean counter values of --pmc runs.  With a FETCH_SIZE and a
+    WRITE_SIZE run that include the bench's 256 MiB copy (--copy-calibration),
+    the counters are scaled so the copy reads and writes exactly 256 MiB, and a
+    traffic record of the pair kernel is printed."""
+    import csv
+    import collections
+    out = []
+    counters = collections.defaultdict(list)
+    for d in dirs:
+        stats = os.path.join(d, "run_kernel_stats.csv")
+        if os.path.exists(stats):
+            out.append(f"| kernel | calls | avg us | min us | max us | % of GPU time |")
+            out.append("|---|---|---|---|---|---|")
+            for r in csv.DictReader(open(stats)):
+                out.append(f"| {_short_name(r['Name'])} | {r['Calls']} | "
+                           f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                           f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+        cc = os.path.join(d, "run_counter_collection.csv")
+        if os.path.exists(cc):
+            per = collections.defaultdict(float)
+            for r in csv.DictReader(open(cc)):
+                per[(r["Dispatch_Id"], r["Kernel_Name"], r["Counter_Name"])] += float(r["Counter_Value"])
+            for (disp, k, c), v in per.items():
+                counters[(_short_name(k), c)].append(v)
+    if counters:
+        copy_bytes = 256 * 2 ** 20
+        scale = {}
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            v = counters.get(("__amd_rocclr_copyBuffer", c))
+            if v:
+                scale[c] = copy_bytes / (max(v) * 1024.0)
+        out.append("")
+        out.append("| kernel | counter | dispatches | mean per dispatch | scaled bytes |")
+        out.append("|---|---|---|---|---|")
+        for (k, c), v in sorted(counters.items()):
+            m = sum(v) / len(v)
+            sb = f"{m * 1024 * scale[c]:.4g}" if c in scale else ""
+            out.append(f"| {k} | {c} | {len(v)} | {m:.6g} | {sb} |")
+        if scale:
+            out.append("")
+            out.append("copy calibration (bytes per KiB-unit of the counter): " +
+                       ", ".join(f"{c} x{s * 1024:.1f} (factor {s:.4f})" for c, s in scale.items()))
+            fk = [k for (k, c) in counters if k.startswith("k_force_pair")]
+            if fk and all(c in scale for c in ("FETCH_SIZE", "WRITE_SIZE")):
+                k = fk[0]
+                rd = sum(counters[(k, "FETCH_SIZE")]) / len(counters[(k, "FETCH_SIZE")])
+                wr = sum(counters[(k, "WRITE_SIZE")]) / len(counters[(k, "WRITE_SIZE")])
+                rec = {"kernel": k, "source": source_hash(),
+                       "fetch_bytes": rd * 1024 * scale["FETCH_SIZE"],
+                       "write_bytes": wr * 1024 * scale["WRITE_SIZE"]}
+                rec["bytes"] = rec["fetch_bytes"] + rec["write_bytes"]
+                out.append("")
+                out.append("traffic-record: " + json.dumps(rec))
+    return "\n".join(out)
+
+
 def unique_pairs(beads, box, r_cut):
     """Number of distinct pairs (with periodic images) within r_cut, summed
     over beads: the algorithmic unit of the force kernel."""
@@ -111,7 +209,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (HBM counter scale)")
+    ap.add_argument("--rocprof-summary", nargs="+", metavar="DIR",
+                    help="print a markdown summary of rocprofv3 CSV output folders and exit")
     a = ap.parse_args()
+    if a.rocprof_summary:
+        print(rocprof_summary(a.rocprof_summary))
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
@@ -172,6 +275,9 @@ def main():
     D = 3 * ab_per_step
     fir_bytes = a.K * D * FIR_BYTES_PER_DOF_STEP
     fir_gbs = fir_bytes / (fir_ms / max(fir_n, 1) * 1e-3) / 1e9 if fir_n else None
+    # HBM traffic from the committed counter record, valid only for this
+    # workload and only while the pair kernel's source is unchanged
+    traffic = stored_traffic() if a.workload == "mgo-8x8x8-qtbpimd-P8-50K" else None
     phases = {k: {"ms_per_launch": v[0] / max(v[1], 1), "launches": v[1],
                   "ms_per_step": v[0] / a.profile_steps} for k, v in prof.items()}
 
@@ -202,7 +308,8 @@ def main():
                    "r_cut_A": pot.r_cut, "skin_A": pot.skin, "parallelism": "1 GPU"},
         "roofline": {"kernel": "pair forces", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": traffic["bytes"] if traffic else None,
                      "flops_per_launch": flops, "unique_pairs": pairs,
                      "flops_per_pair": FLOPS_PER_PAIR, "ms_per_launch": force_ms},
         "fir": {"achieved_GBs": fir_gbs, "peak_GBs": PEAK_HBM_GBS,
