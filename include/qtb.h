@@ -138,7 +138,8 @@ typedef struct {
     int32_t obs_every;         /* sample observables every n steps (0 = never)   */
     int32_t max_two_nf;        /* largest FIR length any replica will use        */
     int32_t flags;             /* QTB_OPT_* bits                                 */
-    int32_t reserved[2];
+    double ml_r_cut;           /* > 0: reserve the surrogate's buffers for this  */
+                               /* descriptor cut-off (<= r_cut); 0: none         */
 } qtb_options;
 
 /* qtb_options.flags: run every step eagerly instead of replaying whole noise
@@ -148,6 +149,8 @@ typedef struct {
 /* qtb_options.flags: keep the default force-kernel decomposition instead of
  * timing the candidates on the first qtb_step (the autotuner). */
 #define QTB_OPT_NO_AUTOTUNE 2
+/* qtb_options.flags: also reserve the surrogate's training buffers. */
+#define QTB_OPT_ML_TRAIN 4
 
 /* Means over the samples taken since the previous qtb_observables call of
  * this replica (eq. 5 primitive estimator with instantaneous momenta). */
@@ -243,6 +246,98 @@ qtb_status qtb_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0
 #define QTB_N_PHASES 6
 qtb_status qtb_profile(qtb_ctx *ctx, int32_t enable);
 qtb_status qtb_profile_read(qtb_ctx *ctx, double *ms, int64_t *launches);
+
+/* ===================================================================
+ * Learned force surrogate (not part of the paper's method: it replaces the
+ * potential V of eq. 4 and eq. 8 by a sum of atomic energies, so the same
+ * QTB / QTB-PIMD step runs on it).  Fixed architecture, two species:
+ *   per centre atom i and neighbour species b, over every neighbour j (all
+ *   periodic images) with r = |r_j - r_i| < r_c:
+ *     f_c(r) = (cos(pi r / r_c) + 1) / 2
+ *     phi_c(r) = exp(-(r - mu_c)^2 / (2 dr^2)) f_c(r), mu_c = r_min + c dr,
+ *       dr = (r_c - r_min) / 31, c = 0..31
+ *     psi_k(r) = exp(-(r - nu_k)^2 / (2 da^2)) f_c(r), nu_k = r_min + k da,
+ *       da = (r_c - r_min) / 7, k = 0..7
+ *     G[48 b + c]      = sum_j phi_c
+ *     G[48 b + 32 + k] = |sum_j psi_k rhat_j|^2
+ *     G[48 b + 40 + k] = ||sum_j psi_k (rhat_j rhat_j^T - I/3)||_F^2
+ *   per centre species a: x = (G - mu_a) inv_sd_a, h1 = silu(W1 x + b1),
+ *   h2 = silu(W2 h1 + b2), E_i = w3 . h2 + b3 + e0_a  (96 -> 64 -> 64 -> 1)
+ *   V = sum_i E_i, F = -grad V.
+ * Parameters (flat FP32, per species a in order): W1 [64][96], b1 [64],
+ * W2 [64][64], b2 [64], w3 [64], b3 [1]: QTB_ML_PARAMS_PER_SPECIES values,
+ * species 0 first.  The kernels use W1, W2, w3 rounded to BF16 (round to
+ * nearest even) with FP32 arithmetic; biases stay FP32.  The normalisation
+ * (FP64 host array, QTB_ML_NORM values): mu [2][96], inv_sd [2][96], e0 [2].
+ * Training minimises, over the replicas of a context (frames, P = 1):
+ *   L = w_E / B sum_f ((E_f - E_f^ref) / N_f)^2 + w_F / (3 sum_f N_f) sum |F - F^ref|^2
+ * with Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master copy.
+ * =================================================================== */
+#define QTB_ML_FEATURES 96
+#define QTB_ML_HIDDEN 64
+#define QTB_ML_PARAMS_PER_SPECIES 10433
+#define QTB_ML_PARAMS (2 * QTB_ML_PARAMS_PER_SPECIES)
+#define QTB_ML_NORM (2 * 2 * QTB_ML_FEATURES + 2)
+
+typedef struct qtb_ml qtb_ml; /* opaque */
+
+/* Device bytes of a model (weights, Adam moments, gradient, normalisation). */
+size_t qtb_ml_workspace_bytes(void);
+
+/* Create a model in a caller-owned device buffer (256-byte aligned, at least
+ * qtb_ml_workspace_bytes).  0 < r_min < r_c.  Weights start at zero, mu = 0,
+ * inv_sd = 1, e0 = 0. */
+qtb_status qtb_ml_create(qtb_ml **out, double r_cut, double r_min, void *d_workspace,
+                         size_t ws_bytes, void *hip_stream);
+
+/* Weights ~ N(0, 1/fan_in) from the library's Gaussian generator (tag 3,
+ * step 0, dof = parameter index, stream 0), biases 0; resets Adam. */
+qtb_status qtb_ml_init_params(qtb_ml *m, uint64_t seed);
+
+/* Host copies in and out.  h_params: [QTB_ML_PARAMS] FP32 master values;
+ * h_used (get only): the values the kernels use (W rounded to BF16);
+ * h_norm: [QTB_ML_NORM] FP64.  Any pointer may be NULL. */
+qtb_status qtb_ml_set_params(qtb_ml *m, const float *h_params, const double *h_norm);
+qtb_status qtb_ml_get_params(qtb_ml *m, float *h_params, float *h_used, double *h_norm);
+
+/* Step the context with the surrogate's forces (m = NULL: back to the pair
+ * potential).  Every check_every steps (0 = never) the pair potential is
+ * evaluated on the same positions and |F_ml - F_pair|^2 accumulated (the
+ * pair potential judges the surrogate); read with qtb_ml_check.  Needs a
+ * pair-potential context created with ml_r_cut >= the model's r_cut and
+ * FP32 precision. */
+qtb_status qtb_ml_attach(qtb_ctx *ctx, qtb_ml *m, int32_t check_every);
+
+/* Surrogate forces (host [P][3][N]), per-bead energies (host [P]),
+ * descriptors and dE/dG (host [P][N][96] FP32 each) of one replica at its
+ * current positions.  Any output may be NULL.  Does not change the state. */
+qtb_status qtb_ml_evaluate(qtb_ctx *ctx, qtb_ml *m, int32_t replica, double *h_force,
+                           double *h_epot, float *h_desc, float *h_dEdG);
+
+/* Set mu, inv_sd from the descriptors of every centre of every replica
+ * (mean and 1 / max(standard deviation, 1e-3) per centre species and
+ * feature) and e0 = mean over replicas of E_ref / N (both species).
+ * d_eref: device [n_rep] FP64. */
+qtb_status qtb_ml_fit_norm(qtb_ctx *ctx, qtb_ml *m, const double *d_eref);
+
+/* One training step over every replica of ctx (each one frame, P = 1, at
+ * its current positions): loss and gradient, then (update != 0) one Adam
+ * step with learning rate lr.  d_eref: device [n_rep] FP64; d_fref: device
+ * FP64, the replicas' [3][N] reference forces one after another.  loss_out
+ * (nullable) receives L before the update; h_grad (nullable, host
+ * [QTB_ML_PARAMS]) dL/dparams.  Needs QTB_OPT_ML_TRAIN. */
+qtb_status qtb_ml_train_step(qtb_ctx *ctx, qtb_ml *m, const double *d_eref,
+                             const double *d_fref, double w_E, double w_F, double lr,
+                             int32_t update, double *loss_out, float *h_grad);
+
+/* Checks since the last call: root mean square of F_ml - F_pair per
+ * component, the same relative to the RMS of F_pair, and the number of
+ * checks (host outputs; any may be NULL). */
+qtb_status qtb_ml_check(qtb_ctx *ctx, int32_t replica, double *rmse, double *rel_rmse,
+                        int64_t *n_checks);
+
+const char *qtb_ml_last_error(const qtb_ml *m); /* never NULL */
+void qtb_ml_destroy(qtb_ml *m);                  /* NULL is a no-op */
 
 const char *qtb_last_error(const qtb_ctx *ctx); /* never NULL */
 void qtb_destroy(qtb_ctx *ctx);                 /* NULL is a no-op */

@@ -15,6 +15,7 @@
 // in LDS (FP64 accumulators): no atomics, no write conflicts.  The first
 // lanes of the atom finish it: store the force, apply the kick, and on
 // sampling steps form the eq. (5) terms.
+#include "force_epilogue.h"
 #include "qtb_internal.h"
 
 namespace qtb {
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
     const int s = be.group * G + bl;
     const bool want_e = (flags & (kSample | kEvaluate)) != 0;
 
-    if (blockIdx.x == 0) {
+    if (blockIdx.x == 0 && rebuild_clear) {
         for (int r = threadIdx.x; r < n_rep; r += blockDim.x) rebuild_clear[r] = 0;
         if (threadIdx.x == 0) rebuild_any[0] = 0;
     }
@@ -222,47 +223,9 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
     double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (active && wsub == 0 && lane < G && s < P) {
         const double f[3] = {fx, fy, fz};
-        T* __restrict__ force = (T*)R.force;
-        const double kick = R.kick[spi];
-        double vn[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const size_t idx = ((size_t)s * 3 + a) * N + i;
-            force[idx] = (T)f[a];
-            double v = R.vel[idx];
-            if (flags & kKick) {
-                v += kick * f[a];
-                R.vel[idx] = v;
-            }
-            vn[a] = v;
-        }
-        if (flags & kEvaluate) R.eatom[(size_t)s * N + i] = 0.5 * e;
-        if (flags & kSample) {
-            const double m = R.mmu[spi];
-            const int sn = (s + 1 == P) ? 0 : s + 1;
-            double ke = 0.0, spr = 0.0, vir = 0.0, x2 = 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const size_t idx = ((size_t)s * 3 + a) * N + i;
-                const double ra = R.pos[idx];
-                double c = 0.0;
-                for (int b = 0; b < P; ++b) c += R.pos[((size_t)b * 3 + a) * N + i];
-                c /= P;
-                const double dn = ra - R.pos[((size_t)sn * 3 + a) * N + i];
-                const double d0 = ra - R.r0[idx];
-                ke += vn[a] * vn[a];
-                spr += dn * dn;
-                vir += (ra - c) * f[a];
-                x2 += d0 * d0;
-            }
-            ob[0] = 0.5 * m * ke;
-            ob[1] = 0.5 * e / P;
-            ob[2] = (P > 1) ? 0.5 * m * R.omega_P * R.omega_P * spr : 0.0;
-            ob[3] = vir;
-            ob[4] = x2;
-        }
+        force_epilogue<T>(R, i, s, spi, f, 0.5 * e, flags, ob);
     }
-    if (flags & kSample) {
+    if (flags & (kSample | kCompare)) {
 #pragma unroll
         for (int q = 0; q < kNobs; ++q) {
             const double t = wave_sum(ob[q]);

@@ -1,0 +1,1079 @@
+// ml.hip -- descriptor-MLP force surrogate on gfx950.
+//
+// The paper's integrator (eq. 4, eq. 8) needs a potential V; this surrogate
+// supplies V = sum_i E_i with E_i a small network of per-atom descriptors:
+//   f_c(r) = (cos(pi r / r_c) + 1) / 2 for r < r_c
+//   radial    phi_c(r) = exp(-eta_r (r - mu_c)^2) f_c(r), 32 channels on
+//             [r_min, r_c], eta_r = 1 / (2 dr^2)
+//   angular   psi_k(r) = exp(-eta_a (r - nu_k)^2) f_c(r), 8 channels,
+//             A1 = sum_j psi_k rhat_j, A2 = sum_j psi_k (rhat_j rhat_j^T - I/3)
+//   G[b] = (sum_j phi_c, |A1|^2, ||A2||_F^2) over neighbours j of species b
+//   E_i = w3 . silu(W2 silu(W1 x + b1) + b2) + b3 + e0, x = (G - mu) inv_sd
+// Forces F = -dE/dr by the chain rule per pair: dE_i/dd_ij is stored for
+// every neighbour-list entry, and F_k = sum_j (dE_k/dd_kj - dE_j/dd_jk)
+// gathers the reverse entries in a fixed order (deterministic, no atomics).
+// Training (loss on energies and forces) differentiates the forces with
+// respect to the weights: a Jacobian-vector product of the descriptors with
+// dL/dF, then forward mode through the network's input gradient and reverse
+// mode back to the weights.
+//
+// Layout: one wavefront per centre (atom, bead) for the neighbour loops,
+// with the pair geometry staged in LDS and the 64 lanes split over channels
+// (radial: 2 pair slots x 32 channels; angular: 8 pair slots x 8 channels);
+// one lane per hidden unit for the network, weights in LDS.
+#include "force_epilogue.h"
+#include "qtb_internal.h"
+
+namespace qtb {
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kPiF = 3.14159265358979323846f;
+
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+
+__device__ __forceinline__ float bf16f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t to_bf16(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// Wavefront-local LDS ordering (the lanes of one wavefront exchange data).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T> struct V4T;
+template <> struct V4T<float> { using type = float4; };
+template <> struct V4T<double> { using type = double4; };
+
+template <typename T>
+__device__ __forceinline__ int ebits(const typename V4T<T>::type& v);
+template <>
+__device__ __forceinline__ int ebits<float>(const float4& v) { return (int)__float_as_uint(v.w); }
+template <>
+__device__ __forceinline__ int ebits<double>(const double4& v)
+{
+    return (int)(uint32_t)__double_as_longlong(v.w);
+}
+
+__device__ __forceinline__ float wsum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// ------------------------------------------------------- neighbour lists
+// Keep the plain list's entries within r_ml + skin + dev_i + dev_j (the plain
+// list holds every pair within r_cut + skin + the same margins, r_ml <= r_cut).
+template <typename T>
+__global__ void __launch_bounds__(256) k_ml_list(const RepDev* __restrict__ reps,
+                                                 const BlockEntry* __restrict__ blocks,
+                                                 int n_entries, int32_t* __restrict__ status)
+{
+    using T4 = typename V4T<T>::type;
+    if (status[kAnyRebuild] == 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int e = blockIdx.x; e < n_entries; e += gridDim.x) {
+        const BlockEntry be = blocks[e];
+        const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+        if (*R.rebuild == 0 || R.ml_nb == nullptr) continue;
+        const int i = be.atom0 + wave;
+        if (i >= R.N) continue;
+        const T4* __restrict__ ent = (const T4*)R.nb_entries + (size_t)i * R.maxnb;
+        T4* __restrict__ out = (T4*)R.ml_nb + (size_t)i * R.maxml;
+        const int cnt = R.nb_count[i];
+        const double base = R.ml_rcs + R.devb[i];  // r_ml + skin + dev_i
+        int n = 0;
+        for (int k0 = 0; k0 < cnt; k0 += 64) {
+            const int k = k0 + lane;
+            bool hit = false;
+            T4 E;
+            if (k < cnt) {
+                E = ent[k];
+                const double Rij = base + R.devb[ebits<T>(E)];
+                const double r2 = (double)E.x * E.x + (double)E.y * E.y + (double)E.z * E.z;
+                hit = r2 < Rij * Rij;
+            }
+            const uint64_t mask = __ballot(hit);
+            if (hit) {
+                const int slot = n + __popcll(mask & below);
+                if (slot < R.maxml) out[slot] = E;
+            }
+            n += __popcll(mask);
+        }
+        if (lane == 0) {
+            R.ml_nc[i] = min(n, R.maxml);
+            if (n > R.maxml) atomicOr(status, kStatusMlList);
+        }
+    }
+}
+
+// Slot of entry (i -> j, D) in j's list: (j -> i, -D).  Both come from the
+// same FP64 displacement with its sign flipped, so the match is exact.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ml_rev(const RepDev* __restrict__ reps,
+                                                const BlockEntry* __restrict__ blocks,
+                                                int n_entries, int32_t* __restrict__ status)
+{
+    using T4 = typename V4T<T>::type;
+    if (status[kAnyRebuild] == 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e = blockIdx.x; e < n_entries; e += gridDim.x) {
+        const BlockEntry be = blocks[e];
+        const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+        if (*R.rebuild == 0 || R.ml_nb == nullptr) continue;
+        const int i = be.atom0 + wave;
+        if (i >= R.N) continue;
+        const T4* __restrict__ ent = (const T4*)R.ml_nb;
+        const int cnt = R.ml_nc[i];
+        for (int k = lane; k < cnt; k += 64) {
+            const T4 E = ent[(size_t)i * R.maxml + k];
+            const int j = ebits<T>(E);
+            const int cj = R.ml_nc[j];
+            int found = -1;
+            for (int q = 0; q < cj; ++q) {
+                const T4 F = ent[(size_t)j * R.maxml + q];
+                if (ebits<T>(F) == i && F.x == -E.x && F.y == -E.y && F.z == -E.z) {
+                    found = q;
+                    break;
+                }
+            }
+            R.ml_rev[(size_t)i * R.maxml + k] = found < 0 ? 0 : found;
+            if (found < 0) atomicOr(status, kStatusMlList);
+        }
+    }
+}
+
+// ------------------------------------------------------------ descriptors
+// Stage of one chunk of up to 64 pairs within r_ml, per wavefront.
+struct PairStage {
+    float r[64], fc[64], dfc[64], rx[64], ry[64], rz[64], sp[64];
+    float wx[64], wy[64], wz[64];  // JVP direction u_j - u_i (training)
+    int slot[64];                  // list entry of the staged pair
+};
+
+// Stage the pairs of entries k0 .. k0+63 of centre (i, s); returns how many.
+template <typename T, bool DIR>
+__device__ __forceinline__ int stage_pairs(const RepDev& R, const MlDev& m, int i, int s,
+                                           const typename V4T<T>::type ui, int k0, int cnt,
+                                           PairStage& st, int lane, float wix, float wiy,
+                                           float wiz)
+{
+    using T4 = typename V4T<T>::type;
+    const T4* __restrict__ u = (const T4*)R.u;
+    const T4* __restrict__ ent = (const T4*)R.ml_nb + (size_t)i * R.maxml;
+    const int P = R.P;
+    const int k = k0 + lane;
+    bool hit = false;
+    float dx = 0.f, dy = 0.f, dz = 0.f, r2 = 0.f;
+    int j = 0;
+    if (k < cnt) {
+        const T4 E = ent[k];
+        j = ebits<T>(E);
+        const T4 Uj = u[(size_t)j * P + s];
+        // entries hold c_i - c_j (+ image): d_ij = r_j - r_i = (U_j - u_i) - D
+        dx = (float)((Uj.x - ui.x) - E.x);
+        dy = (float)((Uj.y - ui.y) - E.y);
+        dz = (float)((Uj.z - ui.z) - E.z);
+        r2 = dx * dx + dy * dy + dz * dz;
+        hit = r2 < m.r_cut * m.r_cut;
+    }
+    const uint64_t mask = __ballot(hit);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (hit) {
+        const int t = __popcll(mask & below);
+        const float r = __builtin_sqrtf(r2);
+        const float ir = 1.0f / r;
+        const float ang = kPiF * r / m.r_cut;
+        st.r[t] = r;
+        st.fc[t] = 0.5f * (__cosf(ang) + 1.0f);
+        st.dfc[t] = -0.5f * kPiF / m.r_cut * __sinf(ang);
+        st.rx[t] = dx * ir;
+        st.ry[t] = dy * ir;
+        st.rz[t] = dz * ir;
+        st.sp[t] = (float)R.species[j];
+        st.slot[t] = k;
+        if (DIR) {
+            const size_t N = R.N;
+            const float* __restrict__ uu = R.ml_u + (size_t)s * 3 * N;
+            st.wx[t] = uu[j] - wix;
+            st.wy[t] = uu[N + j] - wiy;
+            st.wz[t] = uu[2 * N + j] - wiz;
+        }
+    }
+    wave_sync();
+    return __popcll(mask);
+}
+
+// Centre blocks: 4 atoms (one per wavefront), one bead (BlockEntry.group).
+template <typename T>
+__global__ void __launch_bounds__(256) k_ml_desc(const RepDev* __restrict__ reps, const MlDev m,
+                                                 const BlockEntry* __restrict__ blocks,
+                                                 int32_t* __restrict__ rebuild_clear, int n_rep,
+                                                 int32_t* __restrict__ rebuild_any)
+{
+    using T4 = typename V4T<T>::type;
+    __shared__ PairStage stage[4];
+    if (blockIdx.x == 0 && rebuild_clear) {
+        for (int r = threadIdx.x; r < n_rep; r += blockDim.x) rebuild_clear[r] = 0;
+        if (threadIdx.x == 0) rebuild_any[0] = 0;
+    }
+    const BlockEntry be = blocks[blockIdx.x];
+    const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = be.atom0 + wave, s = be.group;
+    if (i >= R.N) return;  // uniform per wavefront; no block barrier below
+    PairStage& st = stage[wave];
+    const int N = R.N, P = R.P;
+    const T4 ui = ((const T4*)R.u)[(size_t)i * P + s];
+    const int cnt = R.ml_nc[i];
+    // radial lanes: channel c, pair parity h; angular lanes: channel k, slot q
+    const int c = lane & 31, h = lane >> 5;
+    const int ka = lane & 7, qa = lane >> 3;
+    const float mu_c = m.mu0 + m.dr * c;
+    const float nu_k = m.nu0 + m.da * ka;
+    float g0 = 0.f, g1 = 0.f;
+    float a1[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float a2[2][6] = {{0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}};
+    for (int k0 = 0; k0 < cnt; k0 += 64) {
+        const int n = stage_pairs<T, false>(R, m, i, s, ui, k0, cnt, st, lane, 0.f, 0.f, 0.f);
+        for (int t = h; t < n; t += 2) {
+            const float x = st.r[t] - mu_c;
+            const float ph = fexp(-m.eta_r * x * x) * st.fc[t];
+            const bool b1 = st.sp[t] != 0.0f;
+            g0 += b1 ? 0.0f : ph;
+            g1 += b1 ? ph : 0.0f;
+        }
+        for (int t = qa; t < n; t += 8) {
+            const float x = st.r[t] - nu_k;
+            const float ps = fexp(-m.eta_a * x * x) * st.fc[t];
+            const float w1 = st.sp[t] != 0.0f ? ps : 0.0f;
+            const float w0 = ps - w1;
+            const float rx = st.rx[t], ry = st.ry[t], rz = st.rz[t];
+            const float q[6] = {rx * rx - (1.0f / 3.0f), ry * ry - (1.0f / 3.0f),
+                                rz * rz - (1.0f / 3.0f), rx * ry, rx * rz, ry * rz};
+            a1[0][0] += w0 * rx; a1[0][1] += w0 * ry; a1[0][2] += w0 * rz;
+            a1[1][0] += w1 * rx; a1[1][1] += w1 * ry; a1[1][2] += w1 * rz;
+#pragma unroll
+            for (int z = 0; z < 6; ++z) {
+                a2[0][z] += w0 * q[z];
+                a2[1][z] += w1 * q[z];
+            }
+        }
+        wave_sync();  // the next chunk overwrites the stage
+    }
+    g0 += __shfl_xor(g0, 32);
+    g1 += __shfl_xor(g1, 32);
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int z = 0; z < 3; ++z) a1[b][z] += __shfl_xor(a1[b][z], off);
+#pragma unroll
+            for (int z = 0; z < 6; ++z) a2[b][z] += __shfl_xor(a2[b][z], off);
+        }
+    }
+    const size_t cidx = (size_t)s * N + i;
+    float* __restrict__ G = R.ml_G + cidx * kMlFeat;
+    if (lane < 32) {
+        G[lane] = g0;
+        G[kMlFeatSp + lane] = g1;
+    }
+    if (lane < 8) {
+        float* __restrict__ aux = R.ml_aux + cidx * kMlAux;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const float l1 = a1[b][0] * a1[b][0] + a1[b][1] * a1[b][1] + a1[b][2] * a1[b][2];
+            const float l2 = a2[b][0] * a2[b][0] + a2[b][1] * a2[b][1] + a2[b][2] * a2[b][2] +
+                             2.0f * (a2[b][3] * a2[b][3] + a2[b][4] * a2[b][4] + a2[b][5] * a2[b][5]);
+            G[b * kMlFeatSp + kMlRad + lane] = l1;
+            G[b * kMlFeatSp + kMlRad + kMlAng + lane] = l2;
+            float* o = aux + (b * kMlAng + lane) * 9;
+            o[0] = a1[b][0]; o[1] = a1[b][1]; o[2] = a1[b][2];
+#pragma unroll
+            for (int z = 0; z < 6; ++z) o[3 + z] = a2[b][z];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- network
+// Weights of both species in LDS, padded rows (97, 65) so that both the
+// row-wise (forward) and column-wise (backward) reads are conflict-free.
+constexpr int kW1S = kMlFeat + 1;    // 97
+constexpr int kW2S = kMlHidden + 1;  // 65
+constexpr int kMlpWaves = 16;
+constexpr int kCpw = 4;              // centres per wavefront (network kernel)
+
+struct alignas(16) MlpLds {
+    float W1[2][kMlHidden][kW1S];
+    float W2[2][kMlHidden][kW2S];
+    float b1[2][kMlHidden], b2[2][kMlHidden], w3[2][kMlHidden];
+    float b3[4];
+    float mu[2][kMlFeat], isd[2][kMlFeat];
+};
+static_assert(sizeof(MlpLds) % 16 == 0, "stage arrays after the weights must stay 16-byte aligned");
+
+__device__ void load_weights(MlpLds& L, const MlDev& m)
+{
+    for (int t = threadIdx.x; t < 2 * kMlHidden * kMlFeat; t += blockDim.x) {
+        const int a = t / (kMlHidden * kMlFeat), r = t % (kMlHidden * kMlFeat);
+        L.W1[a][r / kMlFeat][r % kMlFeat] = bf16f(m.wq[a * kMlParamsSp + kMlOffW1 + r]);
+    }
+    for (int t = threadIdx.x; t < 2 * kMlHidden * kMlHidden; t += blockDim.x) {
+        const int a = t / (kMlHidden * kMlHidden), r = t % (kMlHidden * kMlHidden);
+        L.W2[a][r / kMlHidden][r % kMlHidden] = bf16f(m.wq[a * kMlParamsSp + kMlOffW2 + r]);
+    }
+    for (int t = threadIdx.x; t < 2 * kMlHidden; t += blockDim.x) {
+        const int a = t / kMlHidden, o = t % kMlHidden;
+        L.b1[a][o] = m.master[a * kMlParamsSp + kMlOffB1 + o];
+        L.b2[a][o] = m.master[a * kMlParamsSp + kMlOffB2 + o];
+        L.w3[a][o] = bf16f(m.wq[a * kMlParamsSp + kMlOffW3 + o]);
+    }
+    if (threadIdx.x < 2) L.b3[threadIdx.x] = m.master[threadIdx.x * kMlParamsSp + kMlOffB3];
+    for (int t = threadIdx.x; t < 2 * kMlFeat; t += blockDim.x) {
+        L.mu[t / kMlFeat][t % kMlFeat] = m.mu[t];
+        L.isd[t / kMlFeat][t % kMlFeat] = m.inv_sd[t];
+    }
+    __syncthreads();
+}
+
+// Network blocks: BlockEntry {rep, first centre (s N + i), count <= 64}.
+// Each wavefront evaluates kCpw centres, lane o = hidden unit o; outputs the
+// atomic energy (without e0) and dE/dG.
+__global__ void __launch_bounds__(1024) k_ml_mlp(const RepDev* __restrict__ reps, const MlDev m,
+                                                 const BlockEntry* __restrict__ blocks,
+                                                 int n_blocks)
+{
+    extern __shared__ float4 lds_raw[];
+    MlpLds& L = *reinterpret_cast<MlpLds*>(lds_raw);
+    float4 (*X)[kMlFeat] = reinterpret_cast<float4 (*)[kMlFeat]>(
+        reinterpret_cast<char*>(lds_raw) + sizeof(MlpLds));                // [wave][96]
+    float4 (*H)[kMlHidden] = reinterpret_cast<float4 (*)[kMlHidden]>(
+        reinterpret_cast<char*>(lds_raw) + sizeof(MlpLds) + sizeof(float4) * kMlpWaves * kMlFeat);
+    load_weights(L, m);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int b = blockIdx.x; b < n_blocks; b += gridDim.x) {
+        const BlockEntry be = blocks[b];
+        const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+        const int N = R.N;
+        const int first = wave * kCpw;
+        if (first >= be.group) continue;  // uniform per wavefront
+        int sp[kCpw];
+        size_t cc[kCpw];
+        bool ok[kCpw];
+#pragma unroll
+        for (int q = 0; q < kCpw; ++q) {
+            ok[q] = first + q < be.group;
+            const int c = be.atom0 + (ok[q] ? first + q : first);
+            cc[q] = (size_t)c;
+            sp[q] = R.species[c % N];
+        }
+        // stage x = (G - mu) inv_sd as [m][q]
+        for (int f = lane; f < kMlFeat; f += 64) {
+            float v[kCpw];
+#pragma unroll
+            for (int q = 0; q < kCpw; ++q)
+                v[q] = (R.ml_G[cc[q] * kMlFeat + f] - L.mu[sp[q]][f]) * L.isd[sp[q]][f];
+            X[wave][f] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        wave_sync();
+        const int o = lane;
+        float z1[kCpw], z2[kCpw];
+#pragma unroll
+        for (int q = 0; q < kCpw; ++q) z1[q] = L.b1[sp[q]][o];
+        for (int f = 0; f < kMlFeat; ++f) {
+            const float w0 = L.W1[0][o][f], w1 = L.W1[1][o][f];
+            const float4 x = X[wave][f];
+            z1[0] += (sp[0] ? w1 : w0) * x.x;
+            z1[1] += (sp[1] ? w1 : w0) * x.y;
+            z1[2] += (sp[2] ? w1 : w0) * x.z;
+            z1[3] += (sp[3] ? w1 : w0) * x.w;
+        }
+        float s1[kCpw];
+        {
+            float hv[kCpw];
+#pragma unroll
+            for (int q = 0; q < kCpw; ++q) {
+                const float sg = sigm(z1[q]);
+                hv[q] = z1[q] * sg;
+                s1[q] = sg * (1.0f + z1[q] * (1.0f - sg));
+            }
+            H[wave][o] = make_float4(hv[0], hv[1], hv[2], hv[3]);
+        }
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < kCpw; ++q) z2[q] = L.b2[sp[q]][o];
+        for (int k = 0; k < kMlHidden; ++k) {
+            const float w0 = L.W2[0][o][k], w1 = L.W2[1][o][k];
+            const float4 hk = H[wave][k];
+            z2[0] += (sp[0] ? w1 : w0) * hk.x;
+            z2[1] += (sp[1] ? w1 : w0) * hk.y;
+            z2[2] += (sp[2] ? w1 : w0) * hk.z;
+            z2[3] += (sp[3] ? w1 : w0) * hk.w;
+        }
+        float d2[kCpw];
+#pragma unroll
+        for (int q = 0; q < kCpw; ++q) {
+            const float sg = sigm(z2[q]);
+            const float w3 = L.w3[sp[q]][o];
+            const float y = wsum(w3 * z2[q] * sg);
+            if (lane == 0 && ok[q]) R.ml_y[cc[q]] = y + L.b3[sp[q]];
+            d2[q] = w3 * sg * (1.0f + z2[q] * (1.0f - sg));
+        }
+        wave_sync();  // everyone has read H
+        H[wave][o] = make_float4(d2[0], d2[1], d2[2], d2[3]);
+        wave_sync();
+        // delta1[k] = silu'(z1[k]) sum_o W2[o][k] delta2[o]   (lane = k)
+        float acc[kCpw] = {0.f, 0.f, 0.f, 0.f};
+        for (int oo = 0; oo < kMlHidden; ++oo) {
+            const float w0 = L.W2[0][oo][lane], w1 = L.W2[1][oo][lane];
+            const float4 dd = H[wave][oo];
+            acc[0] += (sp[0] ? w1 : w0) * dd.x;
+            acc[1] += (sp[1] ? w1 : w0) * dd.y;
+            acc[2] += (sp[2] ? w1 : w0) * dd.z;
+            acc[3] += (sp[3] ? w1 : w0) * dd.w;
+        }
+        wave_sync();
+        H[wave][lane] = make_float4(acc[0] * s1[0], acc[1] * s1[1], acc[2] * s1[2], acc[3] * s1[3]);
+        wave_sync();
+        // dE/dG[f] = inv_sd[f] sum_k W1[k][f] delta1[k]   (lane = f, f + 64)
+        for (int f = lane; f < kMlFeat; f += 64) {
+            float g[kCpw] = {0.f, 0.f, 0.f, 0.f};
+            for (int k = 0; k < kMlHidden; ++k) {
+                const float w0 = L.W1[0][k][f], w1 = L.W1[1][k][f];
+                const float4 dd = H[wave][k];
+                g[0] += (sp[0] ? w1 : w0) * dd.x;
+                g[1] += (sp[1] ? w1 : w0) * dd.y;
+                g[2] += (sp[2] ? w1 : w0) * dd.z;
+                g[3] += (sp[3] ? w1 : w0) * dd.w;
+            }
+#pragma unroll
+            for (int q = 0; q < kCpw; ++q)
+                if (ok[q]) R.ml_g[cc[q] * kMlFeat + f] = g[q] * L.isd[sp[q]][f];
+        }
+        wave_sync();  // H and X are reused by the next tile
+    }
+}
+
+// ------------------------------------------------------------ pair forces
+// dE_i/dd_ij for every list entry of centre (i, s), from dE/dG and A1, A2.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ml_pair(const RepDev* __restrict__ reps, const MlDev m,
+                                                 const BlockEntry* __restrict__ blocks)
+{
+    using T4 = typename V4T<T>::type;
+    __shared__ float gs[4][kMlFeat];
+    __shared__ float as[4][kMlAux];
+    const BlockEntry be = blocks[blockIdx.x];
+    const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = be.atom0 + wave, s = be.group;
+    if (i >= R.N) return;
+    const int N = R.N, P = R.P;
+    const size_t cidx = (size_t)s * N + i;
+    for (int f = lane; f < kMlFeat; f += 64) gs[wave][f] = R.ml_g[cidx * kMlFeat + f];
+    for (int f = lane; f < kMlAux; f += 64) as[wave][f] = R.ml_aux[cidx * kMlAux + f];
+    wave_sync();
+    const T4* __restrict__ u = (const T4*)R.u;
+    const T4* __restrict__ ent = (const T4*)R.ml_nb + (size_t)i * R.maxml;
+    float4* __restrict__ out = (float4*)R.ml_fpair + cidx * R.maxml;
+    const T4 ui = u[(size_t)i * P + s];
+    const int cnt = R.ml_nc[i];
+    const float rc = m.r_cut;
+    for (int k = lane; k < cnt; k += 64) {
+        const T4 E = ent[k];
+        const int j = ebits<T>(E);
+        const T4 Uj = u[(size_t)j * P + s];
+        const float dx = (float)((Uj.x - ui.x) - E.x);
+        const float dy = (float)((Uj.y - ui.y) - E.y);
+        const float dz = (float)((Uj.z - ui.z) - E.z);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        if (r2 < rc * rc) {
+            const int b = R.species[j];
+            const float* __restrict__ g = gs[wave] + b * kMlFeatSp;
+            const float* __restrict__ A = as[wave] + b * kMlAng * 9;
+            const float r = __builtin_sqrtf(r2), ir = 1.0f / r;
+            const float rx = dx * ir, ry = dy * ir, rz = dz * ir;
+            const float ang = kPiF * r / rc;
+            const float fc = 0.5f * (__cosf(ang) + 1.0f);
+            const float dfc = -0.5f * kPiF / rc * __sinf(ang);
+            // radial: dE/dr = sum_c g_c e_c (-2 eta (r - mu_c) f_c + f_c')
+            float S0 = 0.f, S1 = 0.f;
+#pragma unroll 8
+            for (int c = 0; c < kMlRad; ++c) {
+                const float x = r - (m.mu0 + m.dr * c);
+                const float ge = g[c] * fexp(-m.eta_r * x * x);
+                S0 += ge;
+                S1 += ge * x;
+            }
+            float dEdr = -2.0f * m.eta_r * fc * S1 + dfc * S0;
+            float ox = 0.f, oy = 0.f, oz = 0.f;  // terms along w (not rhat)
+#pragma unroll
+            for (int k8 = 0; k8 < kMlAng; ++k8) {
+                const float x = r - (m.nu0 + m.da * k8);
+                const float ea = fexp(-m.eta_a * x * x);
+                const float ps = ea * fc;
+                const float dps = ea * (-2.0f * m.eta_a * x * fc + dfc);
+                const float* a = A + k8 * 9;
+                const float g1 = g[kMlRad + k8], g2 = g[kMlRad + kMlAng + k8];
+                // l = 1: 2 [psi' (rhat.A1) rhat + psi/r (A1 - (rhat.A1) rhat)]
+                const float p = rx * a[0] + ry * a[1] + rz * a[2];
+                dEdr += 2.0f * g1 * dps * p;
+                const float c1 = 2.0f * g1 * ps * ir;
+                ox += c1 * (a[0] - p * rx);
+                oy += c1 * (a[1] - p * ry);
+                oz += c1 * (a[2] - p * rz);
+                // l = 2: 2 [psi' q rhat + 2 psi/r (A2 rhat - q rhat)], q = rhat.A2.rhat
+                const float vx = a[3] * rx + a[6] * ry + a[7] * rz;
+                const float vy = a[6] * rx + a[4] * ry + a[8] * rz;
+                const float vz = a[7] * rx + a[8] * ry + a[5] * rz;
+                const float qq = rx * vx + ry * vy + rz * vz;
+                dEdr += 2.0f * g2 * dps * qq;
+                const float c2 = 4.0f * g2 * ps * ir;
+                ox += c2 * (vx - qq * rx);
+                oy += c2 * (vy - qq * ry);
+                oz += c2 * (vz - qq * rz);
+            }
+            fx = dEdr * rx + ox;
+            fy = dEdr * ry + oy;
+            fz = dEdr * rz + oz;
+        }
+        out[k] = make_float4(fx, fy, fz, 0.0f);
+    }
+}
+
+// F_i = sum_k (dE_i/dd_ik - dE_j/dd_ji) in list order, then the same closing
+// kick / sampling as the pair kernel.  Blocks: the pair kernel's table with
+// one wavefront per atom (G beads per wavefront).
+template <typename T, int G>
+__global__ void __launch_bounds__(256) k_ml_gather(const RepDev* __restrict__ reps,
+                                                   const MlDev m,
+                                                   const BlockEntry* __restrict__ blocks,
+                                                   int32_t flags, double* __restrict__ partials,
+                                                   int apb)
+{
+    using T4 = typename V4T<T>::type;
+    constexpr int NCH = 64 / G;
+    __shared__ double red[4][kNobs];
+    const BlockEntry be = blocks[blockIdx.x];
+    const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int bl = lane % G, ch = lane / G;
+    const int i = be.atom0 + wave;
+    const int N = R.N, P = R.P;
+    const int s = be.group * G + bl;
+    const bool active = wave < apb && i < N;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (active) {
+        const T4* __restrict__ ent = (const T4*)R.ml_nb + (size_t)i * R.maxml;
+        const int* __restrict__ rev = R.ml_rev + (size_t)i * R.maxml;
+        const float4* __restrict__ fp = (const float4*)R.ml_fpair;
+        const int cnt = R.ml_nc[i];
+        const size_t own = ((size_t)s * N + i) * R.maxml;
+        for (int k = ch; k < cnt; k += NCH) {
+            const int j = ebits<T>(ent[k]);
+            const float4 a = fp[own + k];
+            const float4 b = fp[((size_t)s * N + j) * R.maxml + rev[k]];
+            fx += (double)(a.x - b.x);
+            fy += (double)(a.y - b.y);
+            fz += (double)(a.z - b.z);
+        }
+    }
+#pragma unroll
+    for (int off = G; off < 64; off <<= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+    }
+    double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (active && lane < G && s < P) {
+        const int spi = R.species[i];
+        const size_t c = (size_t)s * N + i;
+        const double e_atom = (double)R.ml_y[c] + m.e0[spi];
+        const double f[3] = {fx, fy, fz};
+        force_epilogue<T>(R, i, s, spi, f, e_atom, flags, ob);
+    }
+    if (flags & kSample) {
+#pragma unroll
+        for (int q = 0; q < kNobs; ++q) {
+            double t = ob[q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+            if (lane == 0) red[wave][q] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < kNobs) {
+            const double t = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                             red[3][threadIdx.x];
+            partials[(size_t)blockIdx.x * kNobs + threadIdx.x] = t;
+        }
+    }
+}
+
+// --------------------------------------------------------------- training
+// One block per replica (frames of one bead): E_f = sum eatom, the loss
+// w_E / B (dE / N)^2 + w_F / (3 N_tot) sum |dF|^2, dL/dF into ml_u and
+// dL/dE_f into ml_ebar.
+__global__ void __launch_bounds__(256) k_ml_loss(const RepDev* __restrict__ reps, int n_rep,
+                                                 const double* __restrict__ eref,
+                                                 const double* __restrict__ fref,
+                                                 const int64_t* __restrict__ fref_off, double w_E,
+                                                 double w_F, double n_tot,
+                                                 double* __restrict__ loss_parts)
+{
+    __shared__ double red[4][2];
+    const int r = blockIdx.x;
+    const RepDev& R = reps[r];
+    const int N = R.N;
+    const double* __restrict__ fo = fref + fref_off[r];
+    const float* __restrict__ F = (const float*)R.force;
+    const double cF = 2.0 * w_F / (3.0 * n_tot);
+    double e = 0.0, d2 = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        e += R.eatom[i];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double d = (double)F[(size_t)a * N + i] - fo[(size_t)a * N + i];
+            d2 += d * d;
+            R.ml_u[(size_t)a * N + i] = (float)(cF * d);
+        }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        e += __shfl_xor(e, off);
+        d2 += __shfl_xor(d2, off);
+    }
+    if (lane == 0) {
+        red[wave][0] = e;
+        red[wave][1] = d2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double E = 0.0, D2 = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            E += red[w][0];
+            D2 += red[w][1];
+        }
+        const double dE = E - eref[r];
+        loss_parts[r] = w_E / n_rep * (dE / N) * (dE / N) + w_F / (3.0 * n_tot) * D2;
+        *R.ml_ebar = 2.0 * w_E / n_rep * dE / ((double)N * N);
+    }
+}
+
+// v_i = sum_j (dG_i/dd_ij) (u_j - u_i): the descriptors' derivative along dL/dF.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ml_jvp(const RepDev* __restrict__ reps, const MlDev m,
+                                                const BlockEntry* __restrict__ blocks)
+{
+    using T4 = typename V4T<T>::type;
+    __shared__ PairStage stage[4];
+    const BlockEntry be = blocks[blockIdx.x];
+    const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = be.atom0 + wave, s = be.group;
+    if (i >= R.N) return;
+    PairStage& st = stage[wave];
+    const int N = R.N, P = R.P;
+    const size_t cidx = (size_t)s * N + i;
+    const T4 ui = ((const T4*)R.u)[(size_t)i * P + s];
+    const float* __restrict__ uu = R.ml_u + (size_t)s * 3 * N;
+    const float wix = uu[i], wiy = uu[N + i], wiz = uu[2 * N + i];
+    const int cnt = R.ml_nc[i];
+    const int c = lane & 31, h = lane >> 5;
+    const int ka = lane & 7, qa = lane >> 3;
+    const float mu_c = m.mu0 + m.dr * c;
+    const float nu_k = m.nu0 + m.da * ka;
+    float A[2][9];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int z = 0; z < 9; ++z) A[b][z] = R.ml_aux[cidx * kMlAux + (b * kMlAng + ka) * 9 + z];
+    float v0 = 0.f, v1 = 0.f;                 // radial, per species
+    float l1[2] = {0.f, 0.f}, l2[2] = {0.f, 0.f};
+    for (int k0 = 0; k0 < cnt; k0 += 64) {
+        const int n = stage_pairs<T, true>(R, m, i, s, ui, k0, cnt, st, lane, wix, wiy, wiz);
+        for (int t = h; t < n; t += 2) {
+            const float x = st.r[t] - mu_c;
+            const float e = fexp(-m.eta_r * x * x);
+            const float dph = e * (-2.0f * m.eta_r * x * st.fc[t] + st.dfc[t]);
+            const float rw = st.rx[t] * st.wx[t] + st.ry[t] * st.wy[t] + st.rz[t] * st.wz[t];
+            const bool b1 = st.sp[t] != 0.0f;
+            v0 += b1 ? 0.0f : dph * rw;
+            v1 += b1 ? dph * rw : 0.0f;
+        }
+        for (int t = qa; t < n; t += 8) {
+            const float x = st.r[t] - nu_k;
+            const float ea = fexp(-m.eta_a * x * x);
+            const float ps = ea * st.fc[t];
+            const float dps = ea * (-2.0f * m.eta_a * x * st.fc[t] + st.dfc[t]);
+            const float rx = st.rx[t], ry = st.ry[t], rz = st.rz[t];
+            const float wx = st.wx[t], wy = st.wy[t], wz = st.wz[t];
+            const float ir = 1.0f / st.r[t];
+            const float rw = rx * wx + ry * wy + rz * wz;
+            const int b = st.sp[t] != 0.0f ? 1 : 0;
+            float val1, val2;
+            {
+                const float* a = A[0];
+                const float* a1b = A[1];
+                const float p0 = rx * a[0] + ry * a[1] + rz * a[2];
+                const float p1 = rx * a1b[0] + ry * a1b[1] + rz * a1b[2];
+                const float aw0 = wx * a[0] + wy * a[1] + wz * a[2];
+                const float aw1 = wx * a1b[0] + wy * a1b[1] + wz * a1b[2];
+                const float p = b ? p1 : p0, aw = b ? aw1 : aw0;
+                val1 = 2.0f * (dps * rw * p + ps * ir * (aw - rw * p));
+                float M[6];
+#pragma unroll
+                for (int z = 0; z < 6; ++z) M[z] = b ? A[1][3 + z] : A[0][3 + z];
+                const float vx = M[0] * rx + M[3] * ry + M[4] * rz;
+                const float vy = M[3] * rx + M[1] * ry + M[5] * rz;
+                const float vz = M[4] * rx + M[5] * ry + M[2] * rz;
+                const float qq = rx * vx + ry * vy + rz * vz;
+                const float vw = vx * wx + vy * wy + vz * wz;
+                val2 = 2.0f * (dps * qq * rw + 2.0f * ps * ir * (vw - qq * rw));
+            }
+            l1[0] += b ? 0.0f : val1;
+            l1[1] += b ? val1 : 0.0f;
+            l2[0] += b ? 0.0f : val2;
+            l2[1] += b ? val2 : 0.0f;
+        }
+        wave_sync();
+    }
+    v0 += __shfl_xor(v0, 32);
+    v1 += __shfl_xor(v1, 32);
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            l1[b] += __shfl_xor(l1[b], off);
+            l2[b] += __shfl_xor(l2[b], off);
+        }
+    }
+    float* __restrict__ v = R.ml_v + cidx * kMlFeat;
+    if (lane < 32) {
+        v[lane] = v0;
+        v[kMlFeatSp + lane] = v1;
+    }
+    if (lane < 8) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            v[b * kMlFeatSp + kMlRad + lane] = l1[b];
+            v[b * kMlFeatSp + kMlRad + kMlAng + lane] = l2[b];
+        }
+    }
+}
+
+// Forward (primal and tangent along xd = v inv_sd) and reverse mode of
+// e_bar E_i - dE_i/dx . xd for one centre per wavefront; writes the rows the
+// weight-gradient sums need.
+__global__ void __launch_bounds__(1024) k_ml_train_mlp(const RepDev* __restrict__ reps,
+                                                       const MlDev m,
+                                                       const BlockEntry* __restrict__ blocks,
+                                                       int n_blocks)
+{
+    extern __shared__ float4 lds_raw[];
+    MlpLds& L = *reinterpret_cast<MlpLds*>(lds_raw);
+    float* scratch = reinterpret_cast<float*>(reinterpret_cast<char*>(lds_raw) + sizeof(MlpLds));
+    load_weights(L, m);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float* X = scratch + wave * (4 * kMlFeat);  // x[96], xd[96], then hidden vectors
+    float* XD = X + kMlFeat;
+    float* HA = X + 2 * kMlFeat;                // 64
+    float* HB = HA + kMlHidden;                 // 64
+    for (int b = blockIdx.x; b < n_blocks; b += gridDim.x) {
+        const BlockEntry be = blocks[b];
+        const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+        const int N = R.N;
+        const double ebar = *R.ml_ebar;
+        for (int q = wave; q < be.group; q += kMlpWaves) {
+            const size_t c = (size_t)be.atom0 + q;
+            const int a = R.species[c % N];
+            for (int f = lane; f < kMlFeat; f += 64) {
+                X[f] = (R.ml_G[c * kMlFeat + f] - L.mu[a][f]) * L.isd[a][f];
+                XD[f] = R.ml_v[c * kMlFeat + f] * L.isd[a][f];
+            }
+            wave_sync();
+            const int o = lane;
+            float z1 = L.b1[a][o], z1d = 0.f;
+            for (int f = 0; f < kMlFeat; ++f) {
+                const float w = L.W1[a][o][f];
+                z1 += w * X[f];
+                z1d += w * XD[f];
+            }
+            const float sg1 = sigm(z1);
+            const float h1 = z1 * sg1;
+            const float s1 = sg1 * (1.0f + z1 * (1.0f - sg1));
+            const float t1 = sg1 * (1.0f - sg1) * (2.0f + z1 * (1.0f - 2.0f * sg1));
+            const float h1d = s1 * z1d;
+            HA[o] = h1;
+            HB[o] = h1d;
+            wave_sync();
+            float z2 = L.b2[a][o], z2d = 0.f;
+            for (int k = 0; k < kMlHidden; ++k) {
+                const float w = L.W2[a][o][k];
+                z2 += w * HA[k];
+                z2d += w * HB[k];
+            }
+            const float sg2 = sigm(z2);
+            const float h2 = z2 * sg2;
+            const float s2 = sg2 * (1.0f + z2 * (1.0f - sg2));
+            const float t2 = sg2 * (1.0f - sg2) * (2.0f + z2 * (1.0f - 2.0f * sg2));
+            const float h2d = s2 * z2d;
+            const float w3 = L.w3[a][o];
+            const float e = (float)ebar, om = -1.0f;
+            const float z2b = e * w3 * s2 + om * w3 * t2 * z2d;
+            const float z2db = om * w3 * s2;
+            float* row = R.ml_adj + c * kMlAdj;
+            // rows: xd[96] z1b z1db h1 h1d z2b z2db t3 e
+            row[96 + 4 * 64 + o] = z2b;
+            row[96 + 5 * 64 + o] = z2db;
+            row[96 + 6 * 64 + o] = e * h2 + om * h2d;
+            row[96 + 2 * 64 + o] = h1;
+            row[96 + 3 * 64 + o] = h1d;
+            wave_sync();  // HA / HB reads done
+            HA[o] = z2b;
+            HB[o] = z2db;
+            wave_sync();
+            float h1b = 0.f, h1db = 0.f;  // lane = k
+            for (int oo = 0; oo < kMlHidden; ++oo) {
+                const float w = L.W2[a][oo][lane];
+                h1b += w * HA[oo];
+                h1db += w * HB[oo];
+            }
+            row[96 + lane] = h1b * s1 + h1db * t1 * z1d;
+            row[96 + 64 + lane] = h1db * s1;
+            for (int f = lane; f < kMlFeat; f += 64) row[f] = XD[f];
+            if (lane == 0) row[96 + 7 * 64] = e;
+            wave_sync();  // X, XD, HA, HB are reused by the next centre
+        }
+    }
+}
+
+// dL/dtheta: one thread per parameter, sum over every centre of its species
+// (replicas in order, centres in order).
+__global__ void __launch_bounds__(256) k_ml_wgrad(const RepDev* __restrict__ reps, int n_rep,
+                                                  const MlDev m, float* __restrict__ grad)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlParams) return;
+    const int a = p / kMlParamsSp, off = p % kMlParamsSp;
+    double acc = 0.0;
+    for (int r = 0; r < n_rep; ++r) {
+        const RepDev& R = reps[r];
+        const int N = R.N;
+        const size_t nc = (size_t)R.P * N;
+        for (size_t c = 0; c < nc; ++c) {
+            if (R.species[c % N] != a) continue;
+            const float* row = R.ml_adj + c * kMlAdj;
+            float t;
+            if (off < kMlOffB1) {
+                const int o = off / kMlFeat, f = off % kMlFeat;
+                const float x = (R.ml_G[c * kMlFeat + f] - m.mu[a * kMlFeat + f]) *
+                                m.inv_sd[a * kMlFeat + f];
+                t = row[96 + o] * x + row[96 + 64 + o] * row[f];
+            } else if (off < kMlOffW2) {
+                t = row[96 + (off - kMlOffB1)];
+            } else if (off < kMlOffB2) {
+                const int o = (off - kMlOffW2) / kMlHidden, k = (off - kMlOffW2) % kMlHidden;
+                t = row[96 + 4 * 64 + o] * row[96 + 2 * 64 + k] +
+                    row[96 + 5 * 64 + o] * row[96 + 3 * 64 + k];
+            } else if (off < kMlOffW3) {
+                t = row[96 + 4 * 64 + (off - kMlOffB2)];
+            } else if (off < kMlOffB3) {
+                t = row[96 + 6 * 64 + (off - kMlOffW3)];
+            } else {
+                t = row[96 + 7 * 64];
+            }
+            acc += (double)t;
+        }
+    }
+    grad[p] = (float)acc;
+}
+
+__global__ void k_ml_adam(float* __restrict__ master, uint16_t* __restrict__ wq,
+                          float* __restrict__ m1, float* __restrict__ m2,
+                          const float* __restrict__ grad, int n, float lr, float b1, float b2,
+                          float eps, float c1, float c2)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float g = grad[p];
+    const float a = b1 * m1[p] + (1.0f - b1) * g;
+    const float v = b2 * m2[p] + (1.0f - b2) * g * g;
+    m1[p] = a;
+    m2[p] = v;
+    const float w = master[p] - lr * (a / c1) / (sqrtf(v / c2) + eps);
+    master[p] = w;
+    wq[p] = to_bf16(w);
+}
+
+__global__ void k_ml_round(const float* __restrict__ master, uint16_t* __restrict__ wq, int n)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) wq[p] = to_bf16(master[p]);
+}
+
+// Sums of G and G^2 per (centre species, feature), and centre counts:
+// stats [2][96][2] then [2] (FP64), one thread per (species, feature).
+__global__ void k_ml_stats(const RepDev* __restrict__ reps, int n_rep, double* __restrict__ stats)
+{
+    const int t = threadIdx.x;
+    if (t >= 2 * kMlFeat) return;
+    const int a = t / kMlFeat, f = t % kMlFeat;
+    double s1 = 0.0, s2 = 0.0, n = 0.0;
+    for (int r = 0; r < n_rep; ++r) {
+        const RepDev& R = reps[r];
+        const size_t nc = (size_t)R.P * R.N;
+        for (size_t c = 0; c < nc; ++c) {
+            if (R.species[c % R.N] != a) continue;
+            const double g = R.ml_G[c * kMlFeat + f];
+            s1 += g;
+            s2 += g * g;
+            n += 1.0;
+        }
+    }
+    stats[(a * kMlFeat + f) * 2 + 0] = s1;
+    stats[(a * kMlFeat + f) * 2 + 1] = s2;
+    if (f == 0) stats[2 * kMlFeat * 2 + a] = n;
+}
+
+size_t mlp_lds_bytes() { return sizeof(MlpLds) + sizeof(float4) * kMlpWaves * (kMlFeat + kMlHidden); }
+size_t train_lds_bytes() { return sizeof(MlpLds) + sizeof(float) * kMlpWaves * 4 * kMlFeat; }
+
+// Dynamic LDS above the default limit; once per kernel (done is the caller's flag).
+template <typename K>
+void allow_lds(K kernel, size_t bytes, bool& done)
+{
+    if (!done) {
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+        done = true;
+    }
+}
+
+}  // namespace
+
+void launch_ml_lists(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* nl_blocks,
+                     int n_nl, int32_t* status, bool)
+{
+    const int grid = n_nl < 256 ? n_nl : 256;
+    if (grid <= 0) return;
+    if (fp64) {
+        launch(k_ml_list<double>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status);
+        launch(k_ml_rev<double>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status);
+    } else {
+        launch(k_ml_list<float>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status);
+        launch(k_ml_rev<float>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status);
+    }
+}
+
+void launch_ml_forward(hipStream_t st, bool fp64, const RepDev* reps, const MlDev& m,
+                       const BlockEntry* cblocks, int n_cblocks, const BlockEntry* mblocks,
+                       int n_mblocks, int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any)
+{
+    if (n_cblocks <= 0) return;
+    const size_t lds = mlp_lds_bytes();
+    static bool lds_set = false;
+    allow_lds(k_ml_mlp, lds, lds_set);
+    const int mgrid = n_mblocks < 256 ? n_mblocks : 256;
+    if (fp64) {
+        launch(k_ml_desc<double>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks,
+               rebuild_clear, n_rep, rebuild_any);
+        launch(k_ml_mlp, dim3(mgrid), dim3(1024), (uint32_t)lds, st, reps, m, mblocks, n_mblocks);
+        launch(k_ml_pair<double>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks);
+    } else {
+        launch(k_ml_desc<float>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks,
+               rebuild_clear, n_rep, rebuild_any);
+        launch(k_ml_mlp, dim3(mgrid), dim3(1024), (uint32_t)lds, st, reps, m, mblocks, n_mblocks);
+        launch(k_ml_pair<float>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks);
+    }
+}
+
+template <typename T>
+static void gather_T(hipStream_t st, int G, const RepDev* reps, const MlDev& m,
+                     const BlockEntry* blocks, int n_blocks, int32_t flags, double* partials,
+                     int apb)
+{
+    const dim3 g(n_blocks), b(256);
+    switch (G) {
+    case 1: launch((k_ml_gather<T, 1>), g, b, 0, st, reps, m, blocks, flags, partials, apb); break;
+    case 2: launch((k_ml_gather<T, 2>), g, b, 0, st, reps, m, blocks, flags, partials, apb); break;
+    case 4: launch((k_ml_gather<T, 4>), g, b, 0, st, reps, m, blocks, flags, partials, apb); break;
+    case 8: launch((k_ml_gather<T, 8>), g, b, 0, st, reps, m, blocks, flags, partials, apb); break;
+    default: break;
+    }
+}
+
+void launch_ml_gather(hipStream_t st, bool fp64, int G, int apb, const RepDev* reps,
+                      const MlDev& m, const BlockEntry* blocks, int n_blocks, int32_t flags,
+                      double* partials)
+{
+    if (n_blocks <= 0) return;
+    if (fp64) gather_T<double>(st, G, reps, m, blocks, n_blocks, flags, partials, apb);
+    else gather_T<float>(st, G, reps, m, blocks, n_blocks, flags, partials, apb);
+}
+
+void launch_ml_loss(hipStream_t st, const RepDev* reps, int n_rep, const double* eref,
+                    const double* fref, const int64_t* fref_off, double w_E, double w_F,
+                    double n_atoms_total, double* loss_parts)
+{
+    launch(k_ml_loss, dim3(n_rep), dim3(256), 0, st, reps, n_rep, eref, fref, fref_off, w_E, w_F,
+           n_atoms_total, loss_parts);
+}
+
+void launch_ml_jvp(hipStream_t st, bool fp64, const RepDev* reps, const MlDev& m,
+                   const BlockEntry* cblocks, int n_cblocks)
+{
+    if (n_cblocks <= 0) return;
+    if (fp64) launch(k_ml_jvp<double>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks);
+    else launch(k_ml_jvp<float>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks);
+}
+
+void launch_ml_train_mlp(hipStream_t st, const RepDev* reps, const MlDev& m,
+                         const BlockEntry* mblocks, int n_mblocks)
+{
+    if (n_mblocks <= 0) return;
+    const size_t lds = train_lds_bytes();
+    static bool lds_set = false;
+    allow_lds(k_ml_train_mlp, lds, lds_set);
+    const int grid = n_mblocks < 256 ? n_mblocks : 256;
+    launch(k_ml_train_mlp, dim3(grid), dim3(1024), (uint32_t)lds, st, reps, m, mblocks, n_mblocks);
+}
+
+void launch_ml_wgrad(hipStream_t st, const RepDev* reps, int n_rep, const MlDev& m, float* grad)
+{
+    launch(k_ml_wgrad, dim3((kMlParams + 255) / 256), dim3(256), 0, st, reps, n_rep, m, grad);
+}
+
+void launch_ml_adam(hipStream_t st, float* master, uint16_t* wq, float* mom1, float* mom2,
+                    const float* grad, int n, float lr, float b1, float b2, float eps, float c1,
+                    float c2)
+{
+    launch(k_ml_adam, dim3((n + 255) / 256), dim3(256), 0, st, master, wq, mom1, mom2, grad, n,
+           lr, b1, b2, eps, c1, c2);
+}
+
+void launch_ml_round(hipStream_t st, const float* master, uint16_t* wq, int n)
+{
+    launch(k_ml_round, dim3((n + 255) / 256), dim3(256), 0, st, master, wq, n);
+}
+
+void launch_ml_stats(hipStream_t st, const RepDev* reps, int n_rep, double* stats)
+{
+    launch(k_ml_stats, dim3(1), dim3(256), 0, st, reps, n_rep, stats);
+}
+
+}  // namespace qtb

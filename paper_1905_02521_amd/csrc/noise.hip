@@ -185,11 +185,30 @@ void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, 
 }
 
 namespace {
+// Initial surrogate weights: N(0, 1/fan_in) from the same generator (tag 3,
+// step 0, dof = parameter index); biases zero.
+__global__ void k_ml_init(float* __restrict__ master, uint64_t seed)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlParams) return;
+    const int off = p % kMlParamsSp;
+    double scale = 0.0;
+    if (off < kMlOffB1) scale = 1.0 / sqrt((double)kMlFeat);
+    else if (off >= kMlOffW2 && off < kMlOffB2) scale = 1.0 / sqrt((double)kMlHidden);
+    else if (off >= kMlOffW3 && off < kMlOffB3) scale = 1.0 / sqrt((double)kMlHidden);
+    master[p] = scale == 0.0 ? 0.0f : (float)(scale * white_gauss(seed, 0, (uint32_t)p, 0, 3));
+}
+
 __global__ void k_clock(int64_t* clock, int64_t v, int add)
 {
     if (threadIdx.x == 0) *clock = add ? *clock + v : v;
 }
 }  // namespace
+
+void launch_ml_init(hipStream_t st, float* master, uint64_t seed)
+{
+    launch(k_ml_init, dim3((kMlParams + 255) / 256), dim3(256), 0, st, master, seed);
+}
 
 void launch_clock(hipStream_t st, int64_t* clock, int64_t v, bool add)
 {

@@ -38,15 +38,21 @@ struct Layout {
     size_t total = 0;
     Region reps, status, rebuild, tiles, taps, ring, zeta, partials, acc, counts, pairtab, clock;
     Region blk_upd, blk_nl, blk_force;
+    // surrogate (ml_r_cut > 0)
+    Region blk_mlc, blk_mlm, ml_acc, ml_counts, ml_loss, ml_stats, ml_foff;
     struct Per {
         Region force, u, rref, cnow, dev, devb, r0, eatom, species, homega, nb, nbc, nm, ring;
+        Region mlnb, mlnc, mlrev, mlG, mlaux, mlg, mly, mlfp, mlv, mlu, mladj, mlebar;
     };
     std::vector<Per> per;
     // derived sizes
     int64_t n_cols = 0;
     int R = 0, K = 0, max_two_nf = 0, taps_stride = 0;
     std::vector<int64_t> dof_off;
-    std::vector<int> maxnb;
+    std::vector<int> maxnb, maxml;
+    bool ml = false, ml_train = false;
+    std::vector<BlockEntry> mlc, mlm;     // surrogate: centre blocks, network tiles
+    std::vector<int64_t> foff;            // offsets of the replicas' reference forces
     std::vector<BlockEntry> upd, nl, force;   // force: table of the chosen W
     std::vector<BlockEntry> force_w[3];        // W = 1, 2, 4
     std::vector<std::pair<int, std::pair<int, int>>> force_groups_w[3];
@@ -101,6 +107,12 @@ const char* check_inputs(const qtb_potential* pot, const qtb_replica* reps, int 
     if (opt->fir_block_K != 64 && opt->fir_block_K != 128 && opt->fir_block_K != 256)
         return "fir_block_K must be 64, 128 or 256";
     if (opt->obs_every < 0) return "obs_every must be >= 0";
+    if (!(opt->ml_r_cut >= 0.0)) return "ml_r_cut must be >= 0";
+    if (opt->ml_r_cut > 0.0) {
+        if (pot->kind != QTB_POT_PAIR) return "the surrogate needs the pair-potential kind";
+        if (opt->ml_r_cut > pot->r_cut) return "ml_r_cut must not exceed r_cut";
+        if (pot->n_species > 2) return "the surrogate has two species";
+    }
     if (opt->max_two_nf < 2 || (opt->max_two_nf & 1) || opt->max_two_nf > 8192)
         return "max_two_nf must be even, in [2, 8192]";
     if (opt->fir != QTB_FIR_FP64 && opt->max_two_nf > 4096) return "BF16/FP32 FIR: max_two_nf <= 4096";
@@ -136,6 +148,17 @@ int estimate_maxnb(const qtb_potential* pot, const qtb_replica& R)
     return std::max(m, 64);
 }
 
+int estimate_maxml(const qtb_potential* pot, const qtb_options* opt, const qtb_replica& R,
+                   int maxnb)
+{
+    const double Rl = opt->ml_r_cut + pot->skin + (R.n_beads > 1 ? 1.0 : 0.2);
+    const double vol = R.box[0] * R.box[1] * R.box[2];
+    const double n_est = 4.0 / 3.0 * kPi * Rl * Rl * Rl * R.n_atoms / vol;
+    int m = (int)std::ceil(1.3 * n_est + 48.0);
+    m = (m + 63) / 64 * 64;
+    return std::min(std::max(m, 64), maxnb);
+}
+
 void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qtb_options* opt,
           Layout& L)
 {
@@ -149,6 +172,9 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     L.per.assign(n_rep, {});
     L.dof_off.assign(n_rep, 0);
     L.maxnb.assign(n_rep, 0);
+    L.maxml.assign(n_rep, 0);
+    L.ml = pair && opt->ml_r_cut > 0.0;
+    L.ml_train = L.ml && (opt->flags & QTB_OPT_ML_TRAIN);
     int64_t cols = 0;
     for (int r = 0; r < n_rep; ++r) {
         const qtb_replica& R = reps[r];
@@ -156,6 +182,21 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
         const int64_t D = (int64_t)R.n_dims * R.n_atoms * R.n_beads;
         cols += (D + kDofTile - 1) / kDofTile * kDofTile;
         if (pair) L.maxnb[r] = estimate_maxnb(pot, R);
+        if (L.ml) L.maxml[r] = estimate_maxml(pot, opt, R, L.maxnb[r]);
+    }
+    L.mlc.clear();
+    L.mlm.clear();
+    L.foff.assign(n_rep, 0);
+    if (L.ml) {
+        int64_t fo = 0;
+        for (int r = 0; r < n_rep; ++r) {
+            const int N = reps[r].n_atoms, P = reps[r].n_beads;
+            for (int s = 0; s < P; ++s)
+                for (int a = 0; a < N; a += 4) L.mlc.push_back({r, a, s, 0});
+            for (int c0 = 0; c0 < N * P; c0 += 64) L.mlm.push_back({r, c0, std::min(64, N * P - c0), 0});
+            L.foff[r] = fo;
+            fo += 3 * (int64_t)N * P;
+        }
     }
     L.n_cols = cols;
     // block tables
@@ -236,6 +277,15 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     add(cur, L.blk_upd, sizeof(BlockEntry) * std::max<size_t>(1, L.upd.size()));
     add(cur, L.blk_nl, sizeof(BlockEntry) * std::max<size_t>(1, L.nl.size()));
     add(cur, L.blk_force, sizeof(BlockEntry) * L.max_force_blocks);
+    if (L.ml) {
+        add(cur, L.blk_mlc, sizeof(BlockEntry) * L.mlc.size());
+        add(cur, L.blk_mlm, sizeof(BlockEntry) * L.mlm.size());
+        add(cur, L.ml_acc, sizeof(double) * kNobs * n_rep);
+        add(cur, L.ml_counts, sizeof(int32_t) * n_rep);
+        add(cur, L.ml_loss, sizeof(double) * n_rep);
+        add(cur, L.ml_stats, sizeof(double) * (2 * kMlFeat * 2 + 2));
+        add(cur, L.ml_foff, sizeof(int64_t) * n_rep);
+    }
     for (int r = 0; r < n_rep; ++r) {
         const qtb_replica& R = reps[r];
         const size_t N = R.n_atoms, P = R.n_beads, dm = R.n_dims;
@@ -254,6 +304,23 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
             add(cur, p.devb, 8 * N);
             add(cur, p.nb, 4 * ts * N * (size_t)L.maxnb[r]);
             add(cur, p.nbc, 4 * N);
+            if (L.ml) {
+                const size_t M = L.maxml[r];
+                add(cur, p.mlnb, 4 * ts * N * M);
+                add(cur, p.mlnc, 4 * N);
+                add(cur, p.mlrev, 4 * N * M);
+                add(cur, p.mlG, 4 * P * N * kMlFeat);
+                add(cur, p.mlaux, 4 * P * N * kMlAux);
+                add(cur, p.mlg, 4 * P * N * kMlFeat);
+                add(cur, p.mly, 4 * P * N);
+                add(cur, p.mlfp, 16 * P * N * M);
+                if (L.ml_train) {
+                    add(cur, p.mlv, 4 * P * N * kMlFeat);
+                    add(cur, p.mlu, 4 * P * 3 * N);
+                    add(cur, p.mladj, 4 * P * N * kMlAdj);
+                    add(cur, p.mlebar, 8);
+                }
+            }
         } else {
             add(cur, p.homega, 8 * N);
         }
@@ -292,10 +359,14 @@ struct qtb_ctx {
     std::string err;
     int W = kWavesPerAtomDefault;  // force kernel wavefronts per atom
     bool tuned = false;
-    // one captured noise block of K steps, replayed while nothing changes
-    hipGraphExec_t graph = nullptr;
-    int64_t graph_phase = -1;  // block start modulo obs_every at capture
+    // captured noise blocks of K steps, replayed while nothing changes; one
+    // per sampling / checking pattern (block start modulo obs_every and
+    // modulo the surrogate's check interval)
+    std::vector<std::pair<std::pair<int64_t, int64_t>, hipGraphExec_t>> graphs;
     bool graph_failed = false;
+    // surrogate
+    qtb_ml* ml = nullptr;
+    int32_t ml_check_every = 0;
     // profiling: event pairs per phase
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -305,6 +376,57 @@ struct qtb_ctx {
     template <typename X>
     X* at(const Region& r) const { return reinterpret_cast<X*>(ws + r.off); }
 };
+
+// Surrogate model: weights, Adam moments and normalisation in the caller's
+// device buffer.
+struct qtb_ml {
+    hipStream_t st = nullptr;
+    char* ws = nullptr;
+    Region master, wq, m1, m2, grad, mu, isd, e0;
+    size_t total = 0;
+    double r_cut = 0.0, r_min = 0.0;
+    int64_t t = 0;  // Adam steps taken
+    std::string err;
+    std::vector<double> norm;  // host copy: mu [2][96], inv_sd [2][96], e0 [2]
+
+    template <typename X>
+    X* at(const Region& r) const { return reinterpret_cast<X*>(ws + r.off); }
+    MlDev dev() const
+    {
+        MlDev d{};
+        d.wq = at<uint16_t>(wq);
+        d.master = at<float>(master);
+        d.mu = at<float>(mu);
+        d.inv_sd = at<float>(isd);
+        d.e0 = at<double>(e0);
+        d.r_cut = (float)r_cut;
+        d.r_min = (float)r_min;
+        const double dr = (r_cut - r_min) / (kMlRad - 1), da = (r_cut - r_min) / (kMlAng - 1);
+        d.mu0 = (float)r_min;
+        d.dr = (float)dr;
+        d.eta_r = (float)(1.0 / (2.0 * dr * dr));
+        d.nu0 = (float)r_min;
+        d.da = (float)da;
+        d.eta_a = (float)(1.0 / (2.0 * da * da));
+        return d;
+    }
+};
+
+namespace {
+void ml_layout(qtb_ml& m)
+{
+    size_t cur = 0;
+    add(cur, m.master, 4 * (size_t)kMlParams);
+    add(cur, m.m1, 4 * (size_t)kMlParams);
+    add(cur, m.m2, 4 * (size_t)kMlParams);
+    add(cur, m.grad, 4 * (size_t)kMlParams);
+    add(cur, m.wq, 2 * (size_t)kMlParams);
+    add(cur, m.mu, 4 * 2 * (size_t)kMlFeat);
+    add(cur, m.isd, 4 * 2 * (size_t)kMlFeat);
+    add(cur, m.e0, 8 * 2);
+    m.total = cur;
+}
+}  // namespace
 
 namespace qtb {
 LaunchStamp& launch_stamp()
@@ -515,6 +637,24 @@ void fill_repdev(qtb_ctx* c, int r)
     }
     d.seed = R.seed;
     d.stream = R.stream;
+    if (c->L.ml) {
+        d.ml_nb = c->at<void>(p.mlnb);
+        d.ml_nc = c->at<int32_t>(p.mlnc);
+        d.ml_rev = c->at<int32_t>(p.mlrev);
+        d.ml_G = c->at<float>(p.mlG);
+        d.ml_aux = c->at<float>(p.mlaux);
+        d.ml_g = c->at<float>(p.mlg);
+        d.ml_y = c->at<float>(p.mly);
+        d.ml_fpair = c->at<float>(p.mlfp);
+        d.maxml = c->L.maxml[r];
+        d.ml_rcs = c->opt.ml_r_cut + c->skin;
+        if (c->L.ml_train) {
+            d.ml_v = c->at<float>(p.mlv);
+            d.ml_u = c->at<float>(p.mlu);
+            d.ml_adj = c->at<float>(p.mladj);
+            d.ml_ebar = c->at<double>(p.mlebar);
+        }
+    }
 }
 
 qtb_status upload_tables(qtb_ctx* c)
@@ -544,20 +684,23 @@ qtb_status upload_taps(qtb_ctx* c, int r)
     return upload_taps_T<float>(c, r);
 }
 
-// Force evaluation of every replica (no kick), used at init and set_state.
-void launch_forces(qtb_ctx* c, int32_t flags)
+// Pair-potential (or oscillator) forces of every replica.  kCompare leaves
+// the rebuild flags alone (the surrogate's forward pass cleared them).
+void launch_plain_forces(qtb_ctx* c, int32_t flags)
 {
     const Layout& L = c->L;
     const RepDev* dreps = c->at<RepDev>(L.reps);
     const BlockEntry* fb = c->at<BlockEntry>(L.blk_force);
     double* part = c->at<double>(L.partials);
+    const bool clear = !(flags & kCompare);
     for (auto& g : L.force_groups) {
         const int b0 = g.second.first, nb = g.second.second - g.second.first;
         if (nb <= 0) continue;
         if (c->pair) {
             const void* tab = c->fp64 ? (const void*)&c->tabd : (const void*)&c->tabf;
             launch_forces_pair(c->st, c->fp64, g.first, c->W, dreps, fb + b0, nb, tab, flags,
-                               part + (size_t)b0 * kNobs, c->at<int32_t>(L.rebuild), c->n_rep,
+                               part + (size_t)b0 * kNobs,
+                               clear ? c->at<int32_t>(L.rebuild) : nullptr, c->n_rep,
                                c->at<int32_t>(L.status) + kAnyRebuild);
         } else {
             launch_forces_harmonic(c->st, c->fp64, dreps, fb + b0, nb, flags,
@@ -566,12 +709,42 @@ void launch_forces(qtb_ctx* c, int32_t flags)
     }
 }
 
+// Surrogate forces of every replica with model m: descriptors, network,
+// per-pair derivatives, then the gather with the force kernels' epilogue.
+void launch_ml_forces(qtb_ctx* c, const qtb_ml* m, int32_t flags)
+{
+    const Layout& L = c->L;
+    const RepDev* dreps = c->at<RepDev>(L.reps);
+    const MlDev md = m->dev();
+    launch_ml_forward(c->st, c->fp64, dreps, md, c->at<BlockEntry>(L.blk_mlc), (int)L.mlc.size(),
+                      c->at<BlockEntry>(L.blk_mlm), (int)L.mlm.size(), c->at<int32_t>(L.rebuild),
+                      c->n_rep, c->at<int32_t>(L.status) + kAnyRebuild);
+    const BlockEntry* fb = c->at<BlockEntry>(L.blk_force);
+    double* part = c->at<double>(L.partials);
+    for (auto& g : L.force_groups) {
+        const int b0 = g.second.first, nb = g.second.second - g.second.first;
+        if (nb > 0)
+            launch_ml_gather(c->st, c->fp64, g.first, 4 / c->W, dreps, md, fb + b0, nb, flags,
+                             part + (size_t)b0 * kNobs);
+    }
+}
+
+// Forces of the context's current force provider.
+void launch_forces(qtb_ctx* c, int32_t flags)
+{
+    if (c->ml) launch_ml_forces(c, c->ml, flags);
+    else launch_plain_forces(c, flags);
+}
+
 void launch_rebuild(qtb_ctx* c, bool centroids = false)
 {
     if (!c->pair) return;
     const Layout& L = c->L;
     launch_nlist(c->st, c->fp64, c->at<RepDev>(L.reps), c->at<BlockEntry>(L.blk_nl),
                  (int)L.nl.size(), c->at<int32_t>(L.status), centroids);
+    if (L.ml)  // the surrogate's shorter lists follow every rebuild
+        launch_ml_lists(c->st, c->fp64, c->at<RepDev>(L.reps), c->at<BlockEntry>(L.blk_nl),
+                        (int)L.nl.size(), c->at<int32_t>(L.status), false);
 }
 
 qtb_status refresh_forces(qtb_ctx* c)
@@ -594,6 +767,8 @@ qtb_status read_status(qtb_ctx* c)
     QTB_HIP(c, hipStreamSynchronize(c->st));
     if (st[0] & kStatusNbOverflow)
         return fail(c, QTB_E_NOMEM, "neighbour list overflow: density above the planned maximum");
+    if (st[0] & kStatusMlList)
+        return fail(c, QTB_E_NOMEM, "surrogate neighbour list overflow or unmatched pair");
     if (st[0] & kStatusNonfinite) return fail(c, QTB_E_NONFINITE, "non-finite position or velocity");
     return QTB_OK;
 }
@@ -622,7 +797,7 @@ void prime_ring(qtb_ctx* c)
 }
 
 // Kernels of one step; row = step index inside the noise block.
-void record_step(qtb_ctx* c, int row, bool sample)
+void record_step(qtb_ctx* c, int row, bool sample, bool check)
 {
     const Layout& L = c->L;
     const size_t zs = c->opt.fir == QTB_FIR_FP64 ? 8 : 4;
@@ -639,17 +814,22 @@ void record_step(qtb_ctx* c, int row, bool sample)
         }
     }
     if (c->pair) {
-        Phase ph(c, 3);
+        Phase ph(c, 3, L.ml);
         launch_rebuild(c);
     }
     {
-        Phase ph(c, 4, L.force_groups.size() > 1);
+        Phase ph(c, 4, L.force_groups.size() > 1 || c->ml);
         launch_forces(c, kKick | (sample ? kSample : 0));
     }
     if (sample) {
         Phase ph(c, 5);
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
                           c->at<int32_t>(L.counts));
+    }
+    if (check) {  // the pair potential judges the surrogate on the same positions
+        launch_plain_forces(c, kCompare);
+        launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials),
+                          c->at<double>(L.ml_acc), c->at<int32_t>(L.ml_counts));
     }
 }
 
@@ -672,6 +852,11 @@ bool sample_at(const qtb_ctx* c, int64_t step)
     return c->opt.obs_every > 0 && ((step + 1) % c->opt.obs_every) == 0;
 }
 
+bool check_at(const qtb_ctx* c, int64_t step)
+{
+    return c->ml && c->ml_check_every > 0 && ((step + 1) % c->ml_check_every) == 0;
+}
+
 void one_step(qtb_ctx* c)
 {
     const Layout& L = c->L;
@@ -685,30 +870,37 @@ void one_step(qtb_ctx* c)
         c->block_start = c->step;
         c->block_row = 0;
     }
-    record_step(c, c->block_row, sample_at(c, c->step));
+    record_step(c, c->block_row, sample_at(c, c->step), check_at(c, c->step));
     c->step += 1;
     c->block_row += 1;
 }
 
 void drop_graph(qtb_ctx* c)
 {
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
-    c->graph = nullptr;
-    c->graph_phase = -1;
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
 }
+
+constexpr size_t kMaxGraphs = 32;
 
 // A whole block of K steps as one graph launch.  Valid while the kernel
 // arguments stay the same: they only depend on the workspace layout, the
-// potential table and the sampling pattern inside the block.
+// potential table, the force provider and the sampling / checking pattern
+// inside the block, which is the key of the cached graphs.
 bool graph_block(qtb_ctx* c)
 {
     const Layout& L = c->L;
     if (c->graph_failed || c->prof || c->st == nullptr) return false;
     if (c->opt.flags & QTB_OPT_NO_GRAPH) return false;
     if (c->opt.obs_every > 0 && L.K % c->opt.obs_every != 0) return false;
-    const int64_t phase = c->opt.obs_every > 0 ? c->step % c->opt.obs_every : 0;
-    if (!c->graph || c->graph_phase != phase) {
-        drop_graph(c);
+    const int64_t obs_phase = c->opt.obs_every > 0 ? c->step % c->opt.obs_every : 0;
+    const int64_t chk_phase = (c->ml && c->ml_check_every > 0) ? c->step % c->ml_check_every : 0;
+    const std::pair<int64_t, int64_t> key{obs_phase, chk_phase};
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : c->graphs)
+        if (g.first == key) exec = g.second;
+    if (!exec) {
+        if (c->graphs.size() >= kMaxGraphs) return false;  // too many patterns: run eagerly
         hipGraph_t g = nullptr;
         if (hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             c->graph_failed = true;
@@ -716,21 +908,21 @@ bool graph_block(qtb_ctx* c)
             return false;
         }
         record_block_start(c);
-        for (int r = 0; r < L.K; ++r) record_step(c, r, sample_at(c, c->step + r));
+        for (int r = 0; r < L.K; ++r)
+            record_step(c, r, sample_at(c, c->step + r), check_at(c, c->step + r));
         if (hipStreamEndCapture(c->st, &g) != hipSuccess || !g ||
-            hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
-            c->graph = nullptr;
             c->graph_failed = true;
             (void)hipGetLastError();
             return false;
         }
         (void)hipGraphDestroy(g);
-        c->graph_phase = phase;
+        c->graphs.push_back({key, exec});
     }
     if (c->block_start < 0 || c->block_start + L.K != c->step)
         launch_clock(c->st, c->at<int64_t>(L.clock), c->step - L.K, false);
-    if (hipGraphLaunch(c->graph, c->st) != hipSuccess) {
+    if (hipGraphLaunch(exec, c->st) != hipSuccess) {
         drop_graph(c);
         c->graph_failed = true;
         (void)hipGetLastError();
@@ -771,7 +963,7 @@ qtb_status select_force_table(qtb_ctx* c, int W)
 qtb_status autotune(qtb_ctx* c)
 {
     c->tuned = true;
-    if (!c->pair || (c->opt.flags & QTB_OPT_NO_AUTOTUNE)) return QTB_OK;
+    if (!c->pair || c->ml || (c->opt.flags & QTB_OPT_NO_AUTOTUNE)) return QTB_OK;
     hipEvent_t a = nullptr, b = nullptr;
     QTB_HIP(c, hipEventCreate(&a));
     QTB_HIP(c, hipEventCreate(&b));
@@ -783,7 +975,7 @@ qtb_status autotune(qtb_ctx* c)
         float tmin = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             QTB_HIP(c, hipEventRecord(a, c->st));
-            launch_forces(c, 0);
+            launch_plain_forces(c, 0);
             QTB_HIP(c, hipEventRecord(b, c->st));
             QTB_HIP(c, hipEventSynchronize(b));
             float t = 0.0f;
@@ -927,6 +1119,14 @@ qtb_status qtb_init(qtb_ctx** out, const qtb_potential* pot, const qtb_replica* 
         (s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.blk_force), c->L.force.data(),
                                          sizeof(BlockEntry) * c->L.force.size(), hipMemcpyHostToDevice, c->st), "blk")))
         return bail(s);
+    if (c->L.ml &&
+        ((s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.blk_mlc), c->L.mlc.data(),
+                                          sizeof(BlockEntry) * c->L.mlc.size(), hipMemcpyHostToDevice, c->st), "blk")) ||
+         (s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.blk_mlm), c->L.mlm.data(),
+                                          sizeof(BlockEntry) * c->L.mlm.size(), hipMemcpyHostToDevice, c->st), "blk")) ||
+         (s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.ml_foff), c->L.foff.data(),
+                                          sizeof(int64_t) * n_rep, hipMemcpyHostToDevice, c->st), "foff"))))
+        return bail(s);
     for (int r = 0; r < n_rep; ++r)
         if ((s = upload_taps(c, r))) return bail(s);
     if ((s = refresh_forces(c))) return bail(s);
@@ -1013,7 +1213,7 @@ qtb_status qtb_observables(qtb_ctx* c, int32_t replica, qtb_obs* out)
     if (cnt > 0) {
         const double inv = 1.0 / cnt;
         const double kT = c->opt.kB * R.T;
-        const double ke = acc[0] * inv, U = acc[1] * inv + c->eself[replica],
+        const double ke = acc[0] * inv, U = acc[1] * inv + (c->ml ? 0.0 : c->eself[replica]),
                      spr = acc[2] * inv, vir = acc[3] * inv, x2 = acc[4] * inv;
         const double dof = (double)R.n_dims * R.n_atoms;
         out->kinetic = ke;
@@ -1096,7 +1296,7 @@ qtb_status qtb_evaluate(qtb_ctx* c, int32_t replica, double* h_force, double* h_
         for (int s = 0; s < R.n_beads; ++s) {
             double e = 0.0;
             for (int i = 0; i < R.n_atoms; ++i) e += ea[(size_t)s * R.n_atoms + i];
-            h_epot[s] = e + c->eself[replica];
+            h_epot[s] = e + (c->ml ? 0.0 : c->eself[replica]);
         }
     }
     return read_status(c);
@@ -1157,6 +1357,331 @@ qtb_status qtb_profile_read(qtb_ctx* c, double* ms, int64_t* launches)
         launches[m.first] += 1;
     }
     return QTB_OK;
+}
+
+// ============================================================ surrogate
+static qtb_status ml_fail(qtb_ml* m, qtb_status st, const std::string& msg)
+{
+    if (m) m->err = msg;
+    else g_static_err = msg;
+    return st;
+}
+
+static qtb_status ml_upload_norm(qtb_ml* m)
+{
+    std::vector<float> mu(2 * kMlFeat), isd(2 * kMlFeat);
+    for (int q = 0; q < 2 * kMlFeat; ++q) {
+        mu[q] = (float)m->norm[q];
+        isd[q] = (float)m->norm[2 * kMlFeat + q];
+    }
+    if (hipMemcpyAsync(m->at<void>(m->mu), mu.data(), 4 * mu.size(), hipMemcpyHostToDevice, m->st) ||
+        hipMemcpyAsync(m->at<void>(m->isd), isd.data(), 4 * isd.size(), hipMemcpyHostToDevice, m->st) ||
+        hipMemcpyAsync(m->at<void>(m->e0), m->norm.data() + 4 * kMlFeat, 16, hipMemcpyHostToDevice, m->st) ||
+        hipStreamSynchronize(m->st))
+        return ml_fail(m, QTB_E_DEVICE, "normalisation upload");
+    return QTB_OK;
+}
+
+static void ml_reset_adam(qtb_ml* m)
+{
+    launch_fill(m->st, m->at<void>(m->m1), kMlParams, 0);
+    launch_fill(m->st, m->at<void>(m->m2), kMlParams, 0);
+    m->t = 0;
+}
+
+size_t qtb_ml_workspace_bytes(void)
+{
+    qtb_ml m;
+    ml_layout(m);
+    return m.total;
+}
+
+qtb_status qtb_ml_create(qtb_ml** out, double r_cut, double r_min, void* d_workspace,
+                         size_t ws_bytes, void* hip_stream)
+{
+    if (!out) return ml_fail(nullptr, QTB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!(r_min > 0.0) || !(r_cut > r_min)) return ml_fail(nullptr, QTB_E_INVALID, "need 0 < r_min < r_cut");
+    if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0)
+        return ml_fail(nullptr, QTB_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    qtb_ml* m = new qtb_ml();
+    ml_layout(*m);
+    if (ws_bytes < m->total) {
+        delete m;
+        return ml_fail(nullptr, QTB_E_NOMEM, "model workspace too small");
+    }
+    m->st = (hipStream_t)hip_stream;
+    m->ws = (char*)d_workspace;
+    m->r_cut = r_cut;
+    m->r_min = r_min;
+    m->norm.assign(4 * kMlFeat + 2, 0.0);
+    for (int q = 0; q < 2 * kMlFeat; ++q) m->norm[2 * kMlFeat + q] = 1.0;
+    launch_fill(m->st, m->ws, (int64_t)(m->total / 4), 0);
+    qtb_status s = ml_upload_norm(m);
+    if (s) {
+        std::string e = m->err;
+        delete m;
+        return ml_fail(nullptr, s, e);
+    }
+    *out = m;
+    return QTB_OK;
+}
+
+qtb_status qtb_ml_init_params(qtb_ml* m, uint64_t seed)
+{
+    if (!m) return ml_fail(nullptr, QTB_E_INVALID, "model is NULL");
+    launch_ml_init(m->st, m->at<float>(m->master), seed);
+    launch_ml_round(m->st, m->at<float>(m->master), m->at<uint16_t>(m->wq), kMlParams);
+    ml_reset_adam(m);
+    if (hipStreamSynchronize(m->st) != hipSuccess) return ml_fail(m, QTB_E_DEVICE, "init");
+    return QTB_OK;
+}
+
+qtb_status qtb_ml_set_params(qtb_ml* m, const float* h_params, const double* h_norm)
+{
+    if (!m) return ml_fail(nullptr, QTB_E_INVALID, "model is NULL");
+    if (h_params) {
+        if (hipMemcpyAsync(m->at<void>(m->master), h_params, 4 * (size_t)kMlParams,
+                           hipMemcpyHostToDevice, m->st) != hipSuccess)
+            return ml_fail(m, QTB_E_DEVICE, "params upload");
+        launch_ml_round(m->st, m->at<float>(m->master), m->at<uint16_t>(m->wq), kMlParams);
+        ml_reset_adam(m);
+    }
+    if (h_norm) {
+        for (int q = 0; q < 2 * kMlFeat; ++q)
+            if (!(h_norm[2 * kMlFeat + q] > 0.0)) return ml_fail(m, QTB_E_INVALID, "inv_sd must be > 0");
+        m->norm.assign(h_norm, h_norm + 4 * kMlFeat + 2);
+        return ml_upload_norm(m);
+    }
+    if (hipStreamSynchronize(m->st) != hipSuccess) return ml_fail(m, QTB_E_DEVICE, "set_params");
+    return QTB_OK;
+}
+
+qtb_status qtb_ml_get_params(qtb_ml* m, float* h_params, float* h_used, double* h_norm)
+{
+    if (!m) return ml_fail(nullptr, QTB_E_INVALID, "model is NULL");
+    std::vector<float> master(kMlParams);
+    std::vector<uint16_t> wq(kMlParams);
+    if (hipMemcpyAsync(master.data(), m->at<void>(m->master), 4 * (size_t)kMlParams,
+                       hipMemcpyDeviceToHost, m->st) ||
+        hipMemcpyAsync(wq.data(), m->at<void>(m->wq), 2 * (size_t)kMlParams, hipMemcpyDeviceToHost,
+                       m->st) ||
+        hipStreamSynchronize(m->st))
+        return ml_fail(m, QTB_E_DEVICE, "params download");
+    if (h_params) std::memcpy(h_params, master.data(), 4 * (size_t)kMlParams);
+    if (h_used) {
+        for (int p = 0; p < kMlParams; ++p) {
+            const int off = p % kMlParamsSp;
+            const bool weight = off < kMlOffB1 || (off >= kMlOffW2 && off < kMlOffB2) ||
+                                (off >= kMlOffW3 && off < kMlOffB3);
+            if (weight) {
+                const uint32_t u = (uint32_t)wq[p] << 16;
+                std::memcpy(&h_used[p], &u, 4);
+            } else {
+                h_used[p] = master[p];
+            }
+        }
+    }
+    if (h_norm) std::memcpy(h_norm, m->norm.data(), 8 * m->norm.size());
+    return QTB_OK;
+}
+
+static qtb_status ml_ready(qtb_ctx* c, qtb_ml* m)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (!m) return fail(c, QTB_E_INVALID, "model is NULL");
+    if (!c->L.ml) return fail(c, QTB_E_STATE, "context created without ml_r_cut");
+    if (c->fp64) return fail(c, QTB_E_UNSUPPORTED, "the surrogate runs in FP32 precision only");
+    if (m->r_cut > c->opt.ml_r_cut + 1e-12)
+        return fail(c, QTB_E_INVALID, "model r_cut exceeds the context's ml_r_cut");
+    return QTB_OK;
+}
+
+qtb_status qtb_ml_attach(qtb_ctx* c, qtb_ml* m, int32_t check_every)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (check_every < 0) return fail(c, QTB_E_INVALID, "check_every must be >= 0");
+    if (m) {
+        qtb_status s = ml_ready(c, m);
+        if (s) return s;
+    }
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    c->ml = m;
+    c->ml_check_every = m ? check_every : 0;
+    drop_graph(c);
+    qtb_status s = QTB_OK;
+    if (m) {
+        // one wavefront per atom in the gather: the W = 1 table
+        if ((s = select_force_table(c, 1))) return s;
+        c->tuned = true;
+        launch_fill(c->st, c->at<double>(c->L.ml_acc), 2 * kNobs * c->n_rep, 0);
+        launch_fill(c->st, c->at<int32_t>(c->L.ml_counts), c->n_rep, 0);
+    } else {
+        c->tuned = false;
+    }
+    // forces of the new provider for the next half-kick
+    launch_forces(c, 0);
+    QTB_HIP(c, hipGetLastError());
+    return read_status(c);
+}
+
+qtb_status qtb_ml_evaluate(qtb_ctx* c, qtb_ml* m, int32_t replica, double* h_force,
+                           double* h_epot, float* h_desc, float* h_dEdG)
+{
+    qtb_status s = ml_ready(c, m);
+    if (s) return s;
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    launch_rebuild(c);  // no-op unless a rebuild is pending
+    launch_ml_forces(c, m, kEvaluate);
+    QTB_HIP(c, hipGetLastError());
+    const qtb_replica& R = c->reps[replica];
+    const Layout::Per& p = c->L.per[replica];
+    const size_t N = R.n_atoms, P = R.n_beads;
+    if (h_force) {
+        std::vector<float> tmp(P * 3 * N);
+        QTB_HIP(c, hipMemcpyAsync(tmp.data(), c->at<void>(p.force), 4 * tmp.size(), hipMemcpyDeviceToHost, c->st));
+        QTB_HIP(c, hipStreamSynchronize(c->st));
+        for (size_t q = 0; q < tmp.size(); ++q) h_force[q] = tmp[q];
+    }
+    if (h_epot) {
+        std::vector<double> ea(P * N);
+        QTB_HIP(c, hipMemcpyAsync(ea.data(), c->at<void>(p.eatom), 8 * ea.size(), hipMemcpyDeviceToHost, c->st));
+        QTB_HIP(c, hipStreamSynchronize(c->st));
+        for (size_t b = 0; b < P; ++b) {
+            double e = 0.0;
+            for (size_t i = 0; i < N; ++i) e += ea[b * N + i];
+            h_epot[b] = e;
+        }
+    }
+    if (h_desc)
+        QTB_HIP(c, hipMemcpyAsync(h_desc, c->at<void>(p.mlG), 4 * P * N * kMlFeat, hipMemcpyDeviceToHost, c->st));
+    if (h_dEdG)
+        QTB_HIP(c, hipMemcpyAsync(h_dEdG, c->at<void>(p.mlg), 4 * P * N * kMlFeat, hipMemcpyDeviceToHost, c->st));
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    // the stepping provider's forces back in place for the next half-kick
+    if (c->ml != m) launch_forces(c, 0);
+    QTB_HIP(c, hipGetLastError());
+    return read_status(c);
+}
+
+qtb_status qtb_ml_fit_norm(qtb_ctx* c, qtb_ml* m, const double* d_eref)
+{
+    qtb_status s = ml_ready(c, m);
+    if (s) return s;
+    if (!d_eref) return fail(c, QTB_E_INVALID, "d_eref is NULL");
+    launch_rebuild(c);
+    launch_ml_forces(c, m, kEvaluate);  // descriptors of every centre
+    launch_ml_stats(c->st, c->at<RepDev>(c->L.reps), c->n_rep, c->at<double>(c->L.ml_stats));
+    std::vector<double> st(2 * kMlFeat * 2 + 2), eref(c->n_rep);
+    QTB_HIP(c, hipMemcpyAsync(st.data(), c->at<void>(c->L.ml_stats), 8 * st.size(), hipMemcpyDeviceToHost, c->st));
+    QTB_HIP(c, hipMemcpyAsync(eref.data(), d_eref, 8 * (size_t)c->n_rep, hipMemcpyDeviceToHost, c->st));
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    std::vector<double> norm(4 * kMlFeat + 2, 0.0);
+    for (int a = 0; a < 2; ++a) {
+        const double n = st[2 * kMlFeat * 2 + a];
+        for (int f = 0; f < kMlFeat; ++f) {
+            const double s1 = st[(a * kMlFeat + f) * 2], s2 = st[(a * kMlFeat + f) * 2 + 1];
+            const double mu = n > 0 ? s1 / n : 0.0;
+            const double var = n > 0 ? std::max(s2 / n - mu * mu, 0.0) : 1.0;
+            norm[a * kMlFeat + f] = mu;
+            norm[2 * kMlFeat + a * kMlFeat + f] = 1.0 / std::max(std::sqrt(var), 1e-3);
+        }
+    }
+    double e0 = 0.0;
+    for (int r = 0; r < c->n_rep; ++r) e0 += eref[r] / c->reps[r].n_atoms;
+    e0 /= c->n_rep;
+    norm[4 * kMlFeat] = norm[4 * kMlFeat + 1] = e0;
+    m->norm = norm;
+    s = ml_upload_norm(m);
+    if (s) return fail(c, s, m->err);
+    if (c->ml != m) launch_forces(c, 0);
+    return read_status(c);
+}
+
+qtb_status qtb_ml_train_step(qtb_ctx* c, qtb_ml* m, const double* d_eref, const double* d_fref,
+                             double w_E, double w_F, double lr, int32_t update, double* loss_out,
+                             float* h_grad)
+{
+    qtb_status s = ml_ready(c, m);
+    if (s) return s;
+    if (!c->L.ml_train) return fail(c, QTB_E_STATE, "context created without QTB_OPT_ML_TRAIN");
+    if (!d_eref || !d_fref) return fail(c, QTB_E_INVALID, "reference arrays missing");
+    if (!(w_E >= 0.0) || !(w_F >= 0.0) || !(lr >= 0.0)) return fail(c, QTB_E_INVALID, "weights and lr must be >= 0");
+    double n_tot = 0.0;
+    for (int r = 0; r < c->n_rep; ++r) {
+        if (c->reps[r].n_beads != 1) return fail(c, QTB_E_UNSUPPORTED, "training frames have one bead");
+        n_tot += c->reps[r].n_atoms;
+    }
+    const Layout& L = c->L;
+    const RepDev* dreps = c->at<RepDev>(L.reps);
+    const MlDev md = m->dev();
+    launch_rebuild(c);
+    launch_ml_forces(c, m, kEvaluate);
+    launch_ml_loss(c->st, dreps, c->n_rep, d_eref, d_fref, c->at<int64_t>(L.ml_foff), w_E, w_F,
+                   n_tot, c->at<double>(L.ml_loss));
+    launch_ml_jvp(c->st, c->fp64, dreps, md, c->at<BlockEntry>(L.blk_mlc), (int)L.mlc.size());
+    launch_ml_train_mlp(c->st, dreps, md, c->at<BlockEntry>(L.blk_mlm), (int)L.mlm.size());
+    launch_ml_wgrad(c->st, dreps, c->n_rep, md, m->at<float>(m->grad));
+    if (update) {
+        m->t += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = (float)(1.0 - std::pow(0.9, (double)m->t));
+        const float c2 = (float)(1.0 - std::pow(0.999, (double)m->t));
+        launch_ml_adam(c->st, m->at<float>(m->master), m->at<uint16_t>(m->wq), m->at<float>(m->m1),
+                       m->at<float>(m->m2), m->at<float>(m->grad), kMlParams, (float)lr, b1, b2,
+                       1e-8f, c1, c2);
+    }
+    QTB_HIP(c, hipGetLastError());
+    if (loss_out) {
+        std::vector<double> parts(c->n_rep);
+        QTB_HIP(c, hipMemcpyAsync(parts.data(), c->at<void>(L.ml_loss), 8 * parts.size(), hipMemcpyDeviceToHost, c->st));
+        QTB_HIP(c, hipStreamSynchronize(c->st));
+        double t = 0.0;
+        for (double x : parts) t += x;
+        *loss_out = t;
+    }
+    if (h_grad) {
+        QTB_HIP(c, hipMemcpyAsync(h_grad, m->at<void>(m->grad), 4 * (size_t)kMlParams, hipMemcpyDeviceToHost, c->st));
+        QTB_HIP(c, hipStreamSynchronize(c->st));
+    }
+    if (c->ml != m) launch_forces(c, 0);
+    return read_status(c);
+}
+
+qtb_status qtb_ml_check(qtb_ctx* c, int32_t replica, double* rmse, double* rel_rmse,
+                        int64_t* n_checks)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (!c->L.ml) return fail(c, QTB_E_STATE, "context created without ml_r_cut");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    double acc[kNobs];
+    int32_t cnt = 0;
+    QTB_HIP(c, hipMemcpyAsync(acc, c->at<double>(c->L.ml_acc) + (size_t)replica * kNobs, sizeof(acc),
+                              hipMemcpyDeviceToHost, c->st));
+    QTB_HIP(c, hipMemcpyAsync(&cnt, c->at<int32_t>(c->L.ml_counts) + replica, 4, hipMemcpyDeviceToHost, c->st));
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    launch_fill(c->st, c->at<double>(c->L.ml_acc) + (size_t)replica * kNobs, 2 * kNobs, 0);
+    launch_fill(c->st, c->at<int32_t>(c->L.ml_counts) + replica, 1, 0);
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    const qtb_replica& R = c->reps[replica];
+    const double n = 3.0 * R.n_atoms * R.n_beads * std::max(cnt, 1);
+    if (rmse) *rmse = cnt ? std::sqrt(acc[0] / n) : 0.0;
+    if (rel_rmse) *rel_rmse = (cnt && acc[1] > 0) ? std::sqrt(acc[0] / acc[1]) : 0.0;
+    if (n_checks) *n_checks = cnt;
+    return QTB_OK;
+}
+
+const char* qtb_ml_last_error(const qtb_ml* m)
+{
+    if (m) return m->err.c_str();
+    return g_static_err.c_str();
+}
+
+void qtb_ml_destroy(qtb_ml* m)
+{
+    if (!m) return;
+    (void)hipStreamSynchronize(m->st);
+    delete m;
 }
 
 const char* qtb_last_error(const qtb_ctx* c)

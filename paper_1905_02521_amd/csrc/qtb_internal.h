@@ -77,6 +77,55 @@ struct RepDev {
     uint64_t seed;
     uint32_t stream;
     int32_t pad;
+    // descriptor-MLP surrogate (null unless the context reserved it)
+    void* ml_nb;          // T4 [N][maxml]: like nb_entries, within r_ml + skin + margins
+    int32_t* ml_nc;       // [N]
+    int32_t* ml_rev;      // [N][maxml]: slot of the reverse entry in the neighbour's list
+    float* ml_G;          // [P][N][96] descriptors
+    float* ml_aux;        // [P][N][144] A1 [2][8][3], A2 [2][8][6]
+    float* ml_g;          // [P][N][96] dE_i/dG_i
+    float* ml_y;          // [P][N] atomic energies without e0
+    float* ml_fpair;      // float4 [P][N][maxml]: dE_i/dd_ij per list entry
+    float* ml_v;          // [P][N][96] training: J (u_j - u_i)
+    float* ml_u;          // [P][3][N] training: dL/dF
+    float* ml_adj;        // [P][N][kMlAdj] training: per-centre adjoint rows
+    double* ml_ebar;      // [1] training: dL/dE of this replica
+    int32_t maxml;
+    int32_t ml_pad;
+    double ml_rcs;        // r_ml + skin
+};
+
+// ------------------------------------------------ descriptor-MLP surrogate
+constexpr int kMlSpecies = 2;
+constexpr int kMlRad = 32;                       // radial channels per species
+constexpr int kMlAng = 8;                        // angular channels (l = 1, 2 each)
+constexpr int kMlFeatSp = kMlRad + 2 * kMlAng;   // 48
+constexpr int kMlFeat = kMlSpecies * kMlFeatSp;  // 96
+constexpr int kMlHidden = 64;
+constexpr int kMlAux = kMlSpecies * kMlAng * 9;  // A1 (3) + A2 (6) per species, channel
+// one species' trainable block: W1 [64][96], b1, W2 [64][64], b2, w3, b3
+constexpr int kMlOffW1 = 0;
+constexpr int kMlOffB1 = kMlOffW1 + kMlHidden * kMlFeat;
+constexpr int kMlOffW2 = kMlOffB1 + kMlHidden;
+constexpr int kMlOffB2 = kMlOffW2 + kMlHidden * kMlHidden;
+constexpr int kMlOffW3 = kMlOffB2 + kMlHidden;
+constexpr int kMlOffB3 = kMlOffW3 + kMlHidden;
+constexpr int kMlParamsSp = kMlOffB3 + 1;        // 10433
+constexpr int kMlParams = kMlSpecies * kMlParamsSp;
+// adjoint row of one centre (training): xd[96] z1b[64] z1db[64] h1[64]
+// h1d[64] z2b[64] z2db[64] t3[64] e[1] (pad to 576)
+constexpr int kMlAdj = 576;
+
+// Model as the kernels see it (device pointers into the model workspace).
+struct MlDev {
+    const uint16_t* wq;     // [kMlParams] BF16 weights (biases too, only read as FP32)
+    const float* master;    // [kMlParams] FP32 master copy (biases are read from here)
+    const float* mu;        // [2][96]
+    const float* inv_sd;    // [2][96]
+    const double* e0;       // [2]
+    float r_cut, r_min;
+    float mu0, dr, eta_r;   // radial grid
+    float nu0, da, eta_a;   // angular grid
 };
 
 // Work tables: replica and first atom per block (uniform per block).
@@ -95,12 +144,14 @@ struct FirTile {
     int32_t pad;
 };
 
-enum StatusBits : int32_t { kStatusNonfinite = 1, kStatusNbOverflow = 2 };
+enum StatusBits : int32_t { kStatusNonfinite = 1, kStatusNbOverflow = 2, kStatusMlList = 8 };
 // status[kAnyRebuild]: some replica needs its neighbour list rebuilt
 constexpr int kAnyRebuild = 4;
 
 // Kernel-side flags of the force kernels.
-enum ForceFlags : int32_t { kKick = 1, kSample = 2, kEvaluate = 4 };
+// kCompare: leave force and state untouched, accumulate |F - F_stored|^2 and
+// |F|^2 into observable slots 0 and 1 (the surrogate's check).
+enum ForceFlags : int32_t { kKick = 1, kSample = 2, kEvaluate = 4, kCompare = 8 };
 
 // Profiling: when set, the next launch time-stamps these events from its own
 // dispatch packet (no marker packets around the kernel), then clears them.
@@ -154,5 +205,30 @@ void launch_forces_harmonic(hipStream_t st, bool fp64, const RepDev* reps,
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
                        double* acc, int32_t* counts);
 void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value);
+// ml.hip
+void launch_ml_lists(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* nl_blocks,
+                     int n_nl, int32_t* status, bool force);
+void launch_ml_forward(hipStream_t st, bool fp64, const RepDev* reps, const MlDev& m,
+                       const BlockEntry* cblocks, int n_cblocks, const BlockEntry* mblocks,
+                       int n_mblocks, int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any);
+// apb: atoms per block of the force table in use (4 / waves per atom)
+void launch_ml_gather(hipStream_t st, bool fp64, int G, int apb, const RepDev* reps,
+                      const MlDev& m, const BlockEntry* blocks, int n_blocks, int32_t flags,
+                      double* partials);
+void launch_ml_loss(hipStream_t st, const RepDev* reps, int n_rep, const double* eref,
+                    const double* fref, const int64_t* fref_off, double w_E, double w_F,
+                    double n_atoms_total, double* loss_parts);
+void launch_ml_jvp(hipStream_t st, bool fp64, const RepDev* reps, const MlDev& m,
+                   const BlockEntry* cblocks, int n_cblocks);
+void launch_ml_train_mlp(hipStream_t st, const RepDev* reps, const MlDev& m,
+                         const BlockEntry* mblocks, int n_mblocks);
+void launch_ml_wgrad(hipStream_t st, const RepDev* reps, int n_rep, const MlDev& m,
+                     float* grad);
+void launch_ml_adam(hipStream_t st, float* master, uint16_t* wq, float* mom1, float* mom2,
+                    const float* grad, int n, float lr, float b1, float b2, float eps,
+                    float c1, float c2);
+void launch_ml_round(hipStream_t st, const float* master, uint16_t* wq, int n);
+void launch_ml_init(hipStream_t st, float* master, uint64_t seed);
+void launch_ml_stats(hipStream_t st, const RepDev* reps, int n_rep, double* stats);
 
 }  // namespace qtb

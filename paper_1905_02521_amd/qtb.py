@@ -24,7 +24,12 @@ FIR_FP32, FIR_BF16X3, FIR_BF16, FIR_FP64 = 0, 1, 2, 3
 POT_PAIR, POT_HARMONIC = 0, 1
 OPT_NO_GRAPH = 1
 OPT_NO_AUTOTUNE = 2
+OPT_ML_TRAIN = 4
 MAX_SPECIES = 4
+ML_FEATURES = 96
+ML_PARAMS_PER_SPECIES = 10433
+ML_PARAMS = 2 * ML_PARAMS_PER_SPECIES
+ML_NORM = 2 * 2 * ML_FEATURES + 2
 
 _STATUS = {1: "QTB_E_INVALID", 2: "QTB_E_NOMEM", 3: "QTB_E_DEVICE", 4: "QTB_E_STATE",
            5: "QTB_E_NONFINITE", 6: "QTB_E_UNSUPPORTED"}
@@ -63,7 +68,7 @@ class qtb_options(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("fir", ctypes.c_int32),
                 ("fir_block_K", ctypes.c_int32), ("obs_every", ctypes.c_int32),
                 ("max_two_nf", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("ml_r_cut", ctypes.c_double)]
 
 
 class qtb_obs(ctypes.Structure):
@@ -80,7 +85,10 @@ class qtb_obs(ctypes.Structure):
 EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
            "qtb_observables", "qtb_get_state", "qtb_set_state", "qtb_evaluate",
            "qtb_get_noise", "qtb_gaussian", "qtb_profile", "qtb_profile_read",
-           "qtb_last_error", "qtb_destroy", "qtb_version")
+           "qtb_last_error", "qtb_destroy", "qtb_version",
+           "qtb_ml_workspace_bytes", "qtb_ml_create", "qtb_ml_init_params", "qtb_ml_set_params",
+           "qtb_ml_get_params", "qtb_ml_attach", "qtb_ml_evaluate", "qtb_ml_fit_norm",
+           "qtb_ml_train_step", "qtb_ml_check", "qtb_ml_last_error", "qtb_ml_destroy")
 N_PHASES = 6
 PHASES = ("noise", "fir", "update", "nlist", "forces", "obs")
 
@@ -131,6 +139,33 @@ def lib():
     L.qtb_destroy.argtypes = [vp]
     L.qtb_version.restype = ctypes.c_char_p
     L.qtb_version.argtypes = []
+    _PF = ctypes.POINTER(ctypes.c_float)
+    L.qtb_ml_workspace_bytes.restype = ctypes.c_size_t
+    L.qtb_ml_workspace_bytes.argtypes = []
+    L.qtb_ml_create.restype = ctypes.c_int
+    L.qtb_ml_create.argtypes = [ctypes.POINTER(vp), ctypes.c_double, ctypes.c_double, vp,
+                                ctypes.c_size_t, vp]
+    L.qtb_ml_init_params.restype = ctypes.c_int
+    L.qtb_ml_init_params.argtypes = [vp, ctypes.c_uint64]
+    L.qtb_ml_set_params.restype = ctypes.c_int
+    L.qtb_ml_set_params.argtypes = [vp, _PF, _PD]
+    L.qtb_ml_get_params.restype = ctypes.c_int
+    L.qtb_ml_get_params.argtypes = [vp, _PF, _PF, _PD]
+    L.qtb_ml_attach.restype = ctypes.c_int
+    L.qtb_ml_attach.argtypes = [vp, vp, ctypes.c_int32]
+    L.qtb_ml_evaluate.restype = ctypes.c_int
+    L.qtb_ml_evaluate.argtypes = [vp, vp, ctypes.c_int32, _PD, _PD, _PF, _PF]
+    L.qtb_ml_fit_norm.restype = ctypes.c_int
+    L.qtb_ml_fit_norm.argtypes = [vp, vp, vp]
+    L.qtb_ml_train_step.restype = ctypes.c_int
+    L.qtb_ml_train_step.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int32, _PD, _PF]
+    L.qtb_ml_check.restype = ctypes.c_int
+    L.qtb_ml_check.argtypes = [vp, ctypes.c_int32, _PD, _PD, ctypes.POINTER(ctypes.c_int64)]
+    L.qtb_ml_last_error.restype = ctypes.c_char_p
+    L.qtb_ml_last_error.argtypes = [vp]
+    L.qtb_ml_destroy.restype = None
+    L.qtb_ml_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -188,7 +223,7 @@ class Context:
 
     def __init__(self, potential: dict, replicas: list[Replica], units: dict, *,
                  prec=PREC_FP32, fir=FIR_BF16X3, fir_block_K=64, obs_every=0, max_two_nf=512,
-                 graphs=True, autotune=True, stream=None):
+                 graphs=True, autotune=True, stream=None, ml_r_cut=0.0, ml_train=False):
         torch = _torch()
         L = lib()
         self._keep = []
@@ -240,7 +275,9 @@ class Context:
         opt.coulomb_k, opt.mass_unit = units.get("coulomb_k", 0.0), units["mass_unit"]
         opt.prec, opt.fir, opt.fir_block_K = prec, fir, fir_block_K
         opt.obs_every, opt.max_two_nf = obs_every, max_two_nf
-        opt.flags = (0 if graphs else OPT_NO_GRAPH) | (0 if autotune else OPT_NO_AUTOTUNE)
+        opt.flags = (0 if graphs else OPT_NO_GRAPH) | (0 if autotune else OPT_NO_AUTOTUNE) | \
+            (OPT_ML_TRAIN if ml_train else 0)
+        opt.ml_r_cut = ml_r_cut
         self.opt = opt
         nbytes = L.qtb_workspace_bytes(ctypes.byref(pot), self.reps, self.n_rep, ctypes.byref(opt))
         if nbytes == 0:
@@ -312,6 +349,46 @@ class Context:
                                       n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), self.ctx)
         return {PHASES[q]: (float(ms[q]), int(n[q])) for q in range(N_PHASES)}
 
+    # -- surrogate --------------------------------------------------------------
+    def ml_attach(self, model, check_every=0):
+        self._model = model
+        _check(lib().qtb_ml_attach(self.ctx, model.m if model is not None else None,
+                                   int(check_every)), self.ctx)
+
+    def ml_evaluate(self, model, replica=0):
+        """Surrogate forces [P][3][N], energies [P], descriptors and dE/dG [P][N][96]."""
+        P, dims, N = self.shapes[replica]
+        f = np.zeros((P, dims, N))
+        e = np.zeros(P)
+        G = np.zeros((P, N, ML_FEATURES), dtype=np.float32)
+        g = np.zeros((P, N, ML_FEATURES), dtype=np.float32)
+        PF = ctypes.POINTER(ctypes.c_float)
+        _check(lib().qtb_ml_evaluate(self.ctx, model.m, replica, _pd(f), _pd(e),
+                                     G.ctypes.data_as(PF), g.ctypes.data_as(PF)), self.ctx)
+        return f, e, G, g
+
+    def ml_fit_norm(self, model, d_eref):
+        _check(lib().qtb_ml_fit_norm(self.ctx, model.m, ctypes.c_void_p(d_eref.data_ptr())),
+               self.ctx)
+
+    def ml_train_step(self, model, d_eref, d_fref, w_E, w_F, lr, update=True, want_grad=False):
+        """One loss / gradient / Adam step over the replicas (frames) of this context."""
+        loss = ctypes.c_double()
+        grad = np.zeros(ML_PARAMS, dtype=np.float32) if want_grad else None
+        _check(lib().qtb_ml_train_step(
+            self.ctx, model.m, ctypes.c_void_p(d_eref.data_ptr()),
+            ctypes.c_void_p(d_fref.data_ptr()), float(w_E), float(w_F), float(lr),
+            1 if update else 0, ctypes.byref(loss),
+            grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if want_grad else None), self.ctx)
+        return (loss.value, grad) if want_grad else loss.value
+
+    def ml_check(self, replica=0):
+        rmse, rel = ctypes.c_double(), ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().qtb_ml_check(self.ctx, replica, ctypes.byref(rmse), ctypes.byref(rel),
+                                  ctypes.byref(n)), self.ctx)
+        return rmse.value, rel.value, n.value
+
     def close(self):
         if getattr(self, "ctx", None) and self.ctx.value:
             lib().qtb_destroy(self.ctx)
@@ -329,3 +406,56 @@ def pair_potential_dict(p) -> dict:
     return dict(kind=POT_PAIR, mass=p.mass, charge=p.charge, buck_A=p.buck_A,
                 buck_rho=p.buck_rho, buck_C=p.buck_C, dsf_alpha=p.dsf_alpha, r_cut=p.r_cut,
                 skin=p.skin)
+
+
+class Model:
+    """A surrogate model in a torch-owned device buffer (qtb_ml)."""
+
+    def __init__(self, r_cut=6.0, r_min=0.5, stream=None):
+        torch = _torch()
+        L = lib()
+        nbytes = L.qtb_ml_workspace_bytes()
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        self.torch_stream = stream if stream is not None else torch.cuda.Stream()
+        self.m = ctypes.c_void_p()
+        _check_ml(L.qtb_ml_create(ctypes.byref(self.m), r_cut, r_min,
+                                  ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                  ctypes.c_void_p(self.torch_stream.cuda_stream)), None)
+        self.r_cut, self.r_min = r_cut, r_min
+
+    def init_params(self, seed):
+        _check_ml(lib().qtb_ml_init_params(self.m, seed), self.m)
+
+    def set_params(self, params=None, norm=None):
+        PF = ctypes.POINTER(ctypes.c_float)
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        n = None if norm is None else np.ascontiguousarray(norm, dtype=np.float64)
+        _check_ml(lib().qtb_ml_set_params(self.m, None if p is None else p.ctypes.data_as(PF),
+                                          None if n is None else _pd(n)), self.m)
+
+    def get_params(self):
+        """(master FP32, values the kernels use, normalisation FP64)."""
+        PF = ctypes.POINTER(ctypes.c_float)
+        p = np.zeros(ML_PARAMS, dtype=np.float32)
+        u = np.zeros(ML_PARAMS, dtype=np.float32)
+        n = np.zeros(ML_NORM)
+        _check_ml(lib().qtb_ml_get_params(self.m, p.ctypes.data_as(PF), u.ctypes.data_as(PF),
+                                          _pd(n)), self.m)
+        return p, u, n
+
+    def close(self):
+        if getattr(self, "m", None) and self.m.value:
+            lib().qtb_ml_destroy(self.m)
+            self.m = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_ml(status, m):
+    if status != QTB_OK:
+        raise QtbError(status, lib().qtb_ml_last_error(m).decode())

@@ -1,0 +1,170 @@
+"""Surrogate (descriptor MLP) on the GPU against the FP64 oracle.
+
+The oracle gets exactly the parameter values the kernels use (weights
+rounded to BF16, FP32 biases).  Bars: descriptors, energies and forces of
+the FP32 kernels within 2e-5 relative (norm-wise: sums of about 100 FP32
+terms per descriptor, 96- and 64-term FP32 dot products in the network),
+the loss within 1e-5 and its gradient within 2e-4 norm-wise (the gradient
+sums products of FP32 adjoints over every centre).
+"""
+import numpy as np
+import pytest
+
+from paper_1905_02521_amd import workloads as W
+
+from oracle import ml_oracle as M
+
+pytestmark = pytest.mark.gpu
+
+RC, RMIN = 6.0, 0.5
+
+
+def _qtb():
+    from paper_1905_02521_amd import qtb
+    return qtb
+
+
+def frames_ctx(frames, sp, box, train=False, T=300.0, noise=0, graphs=True):
+    qtb = _qtb()
+    pot = W.mgo_potential()
+    reps = [qtb.Replica(pos=f[None] if f.ndim == 2 else f, species=sp, T=T, gamma=1e-3, dt=1.0,
+                        noise=noise, box=tuple(box), seed=7, stream=k)
+            for k, f in enumerate(frames)]
+    return qtb.Context(qtb.pair_potential_dict(pot), reps, dict(W.METAL_UNITS),
+                       prec=qtb.PREC_FP32, fir=qtb.FIR_FP32, max_two_nf=512, ml_r_cut=RC,
+                       ml_train=train, graphs=graphs)
+
+
+def random_norm(seed):
+    rng = np.random.default_rng(seed)
+    mu = rng.normal(0.5, 0.3, (2, 96))
+    isd = rng.uniform(0.3, 1.5, (2, 96))
+    e0 = np.array([-10.5, -9.25])
+    return np.concatenate([mu.ravel(), isd.ravel(), e0]), {"mu": mu, "inv_sd": isd, "e0": e0}
+
+
+def make_model(seed=3, norm_seed=4):
+    qtb = _qtb()
+    m = qtb.Model(RC, RMIN)
+    m.init_params(seed)
+    flat, norm = random_norm(norm_seed)
+    m.set_params(None, flat)
+    _, used, _ = m.get_params()
+    return m, used.astype(np.float64), norm
+
+
+def crystal_frame(n, seed, sigma=0.1):
+    pos, sp, box = W.rocksalt(n)
+    return W.displaced(pos, sigma, seed), sp, box
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+@pytest.mark.parametrize("n_cells", [2, 3])
+def test_descriptors_energy_forces_match_oracle(n_cells):
+    pos, sp, box = crystal_frame(n_cells, 11)
+    ctx = frames_ctx([pos], sp, box)
+    m, used, norm = make_model()
+    f, e, G, g = ctx.ml_evaluate(m, 0)
+    Go, _, _, _ = M.descriptors(pos, sp, box, RC, RMIN)
+    assert rel(G[0], Go) < 2e-5
+    Eo, Fo, Eat = M.energy_forces(used, norm, pos, sp, box, RC, RMIN)
+    assert abs(e[0] - Eo) < 2e-5 * np.sum(np.abs(Eat))
+    assert rel(f[0], Fo) < 2e-5
+    _, dGo = M.mlp(M.unpack(used), norm, Go, sp)
+    assert rel(g[0], dGo) < 2e-5
+
+
+def test_ring_polymer_beads_are_independent_frames():
+    pos, sp, box = crystal_frame(3, 12)
+    P = 4
+    beads = np.stack([W.displaced(pos, 0.05, 30 + b) for b in range(P)])
+    ctx = frames_ctx([beads], sp, box)
+    m, used, norm = make_model(5, 6)
+    f, e, _, _ = ctx.ml_evaluate(m, 0)
+    for b in range(P):
+        Eo, Fo, Eat = M.energy_forces(used, norm, beads[b], sp, box, RC, RMIN)
+        assert rel(f[b], Fo) < 2e-5, b
+        assert abs(e[b] - Eo) < 2e-5 * np.sum(np.abs(Eat)), b
+
+
+def test_loss_and_gradient_match_oracle():
+    qtb = _qtb()
+    import torch
+    frames = []
+    for k in range(2):
+        pos, sp, box = crystal_frame(2, 20 + k, sigma=0.12)
+        frames.append(pos)
+    ctx = frames_ctx(frames, sp, box, train=True)
+    m, used, norm = make_model(8, 9)
+    rng = np.random.default_rng(10)
+    N = len(sp)
+    e_ref = rng.normal(-600.0, 3.0, 2)
+    f_ref = rng.normal(0.0, 0.5, (2, 3, N))
+    d_e = torch.tensor(e_ref, dtype=torch.float64, device="cuda")
+    d_f = torch.tensor(f_ref.ravel(), dtype=torch.float64, device="cuda")
+    wE, wF = 0.7, 1.3
+    loss, grad = ctx.ml_train_step(m, d_e, d_f, wE, wF, 0.0, update=False, want_grad=True)
+    Lo, go = M.loss_and_grad(used, norm, frames, sp, box, e_ref, f_ref, wE, wF, RC, RMIN)
+    assert abs(loss - Lo) < 1e-5 * Lo
+    assert rel(grad, go) < 2e-4
+    # per block of the parameter vector as well (no block may hide in the norm)
+    n = M.params_per_species()
+    o = 0
+    for name, shape in M.layer_sizes():
+        k = int(np.prod(shape))
+        for a in range(2):
+            sl = slice(a * n + o, a * n + o + k)
+            assert rel(grad[sl], go[sl]) < 1e-3, (name, a)
+        o += k
+
+
+def test_adam_step_from_the_gpu_gradient():
+    import torch
+    pos, sp, box = crystal_frame(2, 31, sigma=0.12)
+    ctx = frames_ctx([pos], sp, box, train=True)
+    m, _, _ = make_model(12, 13)
+    master0, _, _ = m.get_params()
+    d_e = torch.tensor([-300.0], dtype=torch.float64, device="cuda")
+    d_f = torch.zeros(3 * len(sp), dtype=torch.float64, device="cuda")
+    lr = 1e-3
+    _, g = ctx.ml_train_step(m, d_e, d_f, 1.0, 1.0, lr, update=True, want_grad=True)
+    master1, used1, _ = m.get_params()
+    # first Adam step: m_hat = g, v_hat = g^2
+    expect, _, _ = M.adam(master0.astype(np.float64), g.astype(np.float64), 0.0, 0.0, 1, lr)
+    assert np.max(np.abs(master1 - expect)) < 1e-6
+    # the kernels use the BF16 rounding of the new master weights
+    W1 = slice(0, 64 * 96)
+    w = master1[W1].view(np.uint32)
+    r = ((w + 0x7FFF + ((w >> 16) & 1)) >> 16) << 16
+    assert np.array_equal(used1[W1].view(np.uint32), r.astype(np.uint32))
+
+
+def test_graph_replay_and_check_with_the_surrogate():
+    """Stepping on surrogate forces: graph-replayed blocks equal eager steps
+    bit for bit, and the pair potential's check sees the same force error as
+    a direct comparison at the end."""
+    qtb = _qtb()
+    pos, sp, box = crystal_frame(3, 40, sigma=0.05)
+    outs = []
+    for graphs in (True, False):
+        ctx = frames_ctx([pos], sp, box, T=200.0, noise=1, graphs=graphs)
+        ctx.build_filter(0, 1, 256)
+        m, _, _ = make_model(14, 15)
+        ctx.ml_attach(m, check_every=32)
+        ctx.step(128)
+        r, v, _ = ctx.get_state(0)
+        rmse, relerr, n = ctx.ml_check(0)
+        outs.append((r, v, rmse, n))
+        if graphs:
+            fm, _, _, _ = ctx.ml_evaluate(m, 0)
+            ctx.ml_attach(None)
+            fp, _ = ctx.evaluate(0)
+            direct = np.sqrt(np.mean((fm - fp) ** 2))
+            assert n == 4 and rmse > 0
+            # same order as the last check (positions moved a little since)
+            assert 0.5 < rmse / direct < 2.0
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
