@@ -194,16 +194,131 @@ def cpu_baseline(w, beads, sp, box, pot, budget_s=15.0):
                       f"{t:.1f} s, FP64, {threads} OpenMP threads"}
 
 
+def surrogate_bench(a):
+    """The learned surrogate on the 20x20x20-cell crystal x P = 4 (QTB-PIMD,
+    300 K): trained on the GPU on frames of the method's own pair-potential
+    runs of the 4x4x4 crystal at 300 / 600 / 1000 K, then timed against the
+    pair potential on the same workload, with the pair potential's check of
+    the force error every 64 steps."""
+    import torch
+    from paper_1905_02521_amd import qtb, workloads as W
+    pot = W.mgo_potential(skin=a.skin)
+    U = dict(W.METAL_UNITS)
+    t_gen = time.perf_counter()
+    frames = []
+    for T, seed in ((300.0, 1), (600.0, 2), (1000.0, 3)):
+        pos, sp, box = W.rocksalt(4)
+        rep = qtb.Replica(pos=W.displaced(pos, 0.0421, seed)[None], species=sp, T=T, gamma=5e-3,
+                          dt=1.0, noise=0, box=tuple(box), seed=seed)
+        ctx = qtb.Context(qtb.pair_potential_dict(pot), [rep], U, prec=qtb.PREC_FP32,
+                          fir=qtb.FIR_FP32)
+        ctx.step(500)
+        for _ in range(16):
+            ctx.step(25)
+            frames.append(ctx.get_state(0)[0][0])
+        ctx.close()
+    perm = np.random.default_rng(0).permutation(len(frames))
+    sets = {"train": [frames[k] for k in perm[:36]], "test": [frames[k] for k in perm[36:]]}
+    ctxs, labels = {}, {}
+    for name, fr in sets.items():
+        reps = [qtb.Replica(pos=f[None], species=sp, T=300.0, gamma=1e-3, dt=1.0, noise=0,
+                            box=tuple(box), seed=1, stream=k) for k, f in enumerate(fr)]
+        ctxs[name] = qtb.Context(qtb.pair_potential_dict(pot), reps, U, prec=qtb.PREC_FP32,
+                                 fir=qtb.FIR_FP32, ml_r_cut=6.0, ml_train=(name == "train"))
+        ev = [ctxs[name].evaluate(k) for k in range(len(fr))]
+        labels[name] = (np.array([f[0] for f, _ in ev]), np.array([e[0] for _, e in ev]))
+    Ftr, Etr = labels["train"]
+    d_e = torch.tensor(Etr, dtype=torch.float64, device="cuda")
+    d_f = torch.tensor(Ftr.reshape(-1), dtype=torch.float64, device="cuda")
+    model = qtb.Model(6.0, 0.5)
+    model.init_params(1)
+    ctxs["train"].ml_fit_norm(model, d_e)
+    t_train = time.perf_counter()
+    n_train = 600
+    for it in range(n_train):
+        ctxs["train"].ml_train_step(model, d_e, d_f, 1.0, 1.0, 3e-3 if it < 400 else 1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    Fte, Ete = labels["test"]
+    err = ref = 0.0
+    de = []
+    for k in range(len(sets["test"])):
+        f, e, _, _ = ctxs["test"].ml_evaluate(model, k)
+        err += np.sum((f[0] - Fte[k]) ** 2)
+        ref += np.sum(Fte[k] ** 2)
+        de.append((e[0] - Ete[k]) / len(sp))
+    n_at = len(sp)
+    test_rmse = math.sqrt(err / (3 * n_at * len(sets["test"])))
+    test_rel = math.sqrt(err / ref)
+    test_e = float(np.sqrt(np.mean(np.square(de))))
+    for c in ctxs.values():
+        c.close()
+    # production workload
+    n, P = 20, 4
+    pos, sp2, box2 = W.rocksalt(n)
+    rep = qtb.Replica(pos=W.beads_from(W.displaced(pos, 0.0421, 4), P), species=sp2, T=300.0,
+                      gamma=1e-3, dt=1.0, noise=2, box=tuple(box2), seed=4)
+    ctx = qtb.Context(qtb.pair_potential_dict(pot), [rep], U, prec=qtb.PREC_FP32,
+                      fir=qtb.FIR_BF16X3, ml_r_cut=6.0)
+    ctx.build_filter(0, 2, 512)
+    ab = n ** 3 * 8 * P
+    ctx.step(128)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(512)
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / 512
+    ctx.ml_attach(model, check_every=64)
+    ctx.step(128)
+    ctx.ml_check(0)
+    torch.cuda.synchronize()
+    steps = 256
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    ml_s = (time.perf_counter() - t0) / steps
+    rmse, rel, n_chk = ctx.ml_check(0)
+    ctx.profile(True)
+    ctx.step(16)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+    out = {
+        "metric": "atom-bead-steps/s per GPU (surrogate forces + QTB noise + update)",
+        "value": ab / ml_s, "unit": "atom-bead-steps/s", "n_gpus": 1, "steps": steps,
+        "ms_per_step": ml_s * 1e3, "higher_is_better": True, "dtype": "f32 (bf16 weights)",
+        "data": "synthetic (seeded rock-salt crystal; training frames from the method's own "
+                "pair-potential runs)",
+        "config": {"workload": "surrogate-20x20x20-P4", "atoms": n ** 3 * 8, "beads": P,
+                   "atom_beads_per_step": ab, "T_K": 300.0, "noise": "QTB-PIMD kappa_P",
+                   "r_ml_A": 6.0, "network": "96-64-64-1 silu per species"},
+        "plain": {"value": ab / plain_s, "ms_per_step": plain_s * 1e3},
+        "surrogate_over_plain": plain_s / ml_s,
+        "accuracy": {"test_force_rmse_eV_A": test_rmse, "test_force_rel_rmse": test_rel,
+                     "test_energy_rmse_eV_per_atom": test_e,
+                     "run_check_force_rmse_eV_A": rmse, "run_check_rel_rmse": rel,
+                     "run_checks": n_chk},
+        "training": {"frames": 36, "atoms_per_frame": n_at, "adam_steps": n_train,
+                     "ms_per_step": t_train / n_train * 1e3,
+                     "wall_s_total": time.perf_counter() - t_gen},
+        "phases_ms_per_step": {k: v[0] / 16 for k, v in prof.items()},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="mgo-8x8x8-qtbpimd-P8-50K",
-                    help="a named single workload, or batched-64 (the T / gamma / P sweep)")
+                    help="a named single workload, batched-64 (the T / gamma / P sweep) or "
+                         "surrogate-20x20x20-P4 (the learned force surrogate)")
     ap.add_argument("--fir", default="bf16x3", choices=["fp32", "bf16x3", "bf16", "fp64"])
     ap.add_argument("--K", type=int, default=64)
-    ap.add_argument("--skin", type=float, default=1.0)
+    ap.add_argument("--skin", type=float, default=None,
+                    help="Verlet skin (A); default 0.4 for one crystal (fastest measured), "
+                         "1.0 for the sweep (hot replicas)")
     ap.add_argument("--profile-steps", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -224,6 +339,11 @@ def main():
     from paper_1905_02521_amd import qtb, workloads as W
 
     torch.cuda.set_device(0)
+    if a.skin is None:
+        a.skin = 1.0 if (a.workload.startswith("batched") or a.workload.startswith("surrogate")) else 0.4
+    if a.workload.startswith("surrogate"):
+        surrogate_bench(a)
+        return
     batched = a.workload.startswith("batched")
     works = W.batched_sweep(int(a.workload.split("-")[1])) if batched else [W.workload(a.workload)]
     pot = W.mgo_potential(skin=a.skin)

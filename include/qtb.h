@@ -151,6 +151,12 @@ typedef struct {
 #define QTB_OPT_NO_AUTOTUNE 2
 /* qtb_options.flags: also reserve the surrogate's training buffers. */
 #define QTB_OPT_ML_TRAIN 4
+/* qtb_options.flags: one kernel per step (forces, list rebuild and update
+ * fused; pair potential with P = 1, 2, 4 or 8 for every replica).  The
+ * results equal the separate kernels' bit for bit, except for rounding in
+ * steps that rebuild a list.  Off by default: on gfx950 the fused kernel's
+ * update tail costs more than the two launches it saves. */
+#define QTB_OPT_FUSE 8
 
 /* Means over the samples taken since the previous qtb_observables call of
  * this replica (eq. 5 primitive estimator with instantaneous momenta). */

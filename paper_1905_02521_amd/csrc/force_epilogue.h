@@ -7,13 +7,29 @@
 
 namespace qtb {
 
+// State read from global memory (the separate force kernel).
+struct GlobalState {
+    const RepDev& R;
+    int i;
+    __device__ __forceinline__ double pos(int b, int a) const
+    {
+        return R.pos[((size_t)b * 3 + a) * R.N + i];
+    }
+    __device__ __forceinline__ double vel(int b, int a) const
+    {
+        return R.vel[((size_t)b * 3 + a) * R.N + i];
+    }
+};
+
 // e_atom: this atom's share of the bead potential V(r^(s)).
 // ob (kNobs slots): kinetic, V/P, spring, virial, x^2 in kSample mode;
 // |F - F_stored|^2 and |F|^2 in kCompare mode (nothing is written then).
-template <typename T>
-__device__ __forceinline__ void force_epilogue(const RepDev& R, int i, int s, int spi,
-                                               const double f[3], double e_atom, int32_t flags,
-                                               double* ob)
+// vn receives the velocity after the kick; STORE_V: write it back.
+template <typename T, bool STORE_V = true, typename Src>
+__device__ __forceinline__ void force_epilogue_src(const RepDev& R, int i, int s, int spi,
+                                                   const double f[3], double e_atom,
+                                                   int32_t flags, double* ob, const Src& src,
+                                                   double* vn)
 {
     const int N = R.N, P = R.P;
     T* __restrict__ force = (T*)R.force;
@@ -27,15 +43,14 @@ __device__ __forceinline__ void force_epilogue(const RepDev& R, int i, int s, in
         return;
     }
     const double kick = R.kick[spi];
-    double vn[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const size_t idx = ((size_t)s * 3 + a) * N + i;
         force[idx] = (T)f[a];
-        double v = R.vel[idx];
+        double v = src.vel(s, a);
         if (flags & kKick) {
-            v += kick * f[a];
-            R.vel[idx] = v;
+            v = __builtin_fma(kick, f[a], v);  // half-kick B(dt/2)
+            if (STORE_V) R.vel[idx] = v;
         }
         vn[a] = v;
     }
@@ -47,16 +62,16 @@ __device__ __forceinline__ void force_epilogue(const RepDev& R, int i, int s, in
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const size_t idx = ((size_t)s * 3 + a) * N + i;
-            const double ra = R.pos[idx];
+            const double ra = src.pos(s, a);
             double c = 0.0;
-            for (int b = 0; b < P; ++b) c += R.pos[((size_t)b * 3 + a) * N + i];
+            for (int b = 0; b < P; ++b) c += src.pos(b, a);
             c /= P;
-            const double dn = ra - R.pos[((size_t)sn * 3 + a) * N + i];
+            const double dn = ra - src.pos(sn, a);
             const double d0 = ra - R.r0[idx];
-            ke += vn[a] * vn[a];
-            spr += dn * dn;
-            vir += (ra - c) * f[a];
-            x2 += d0 * d0;
+            ke = __builtin_fma(vn[a], vn[a], ke);
+            spr = __builtin_fma(dn, dn, spr);
+            vir = __builtin_fma(ra - c, f[a], vir);
+            x2 = __builtin_fma(d0, d0, x2);
         }
         ob[0] = 0.5 * m * ke;
         ob[1] = e_atom / P;
@@ -64,6 +79,15 @@ __device__ __forceinline__ void force_epilogue(const RepDev& R, int i, int s, in
         ob[3] = vir;
         ob[4] = x2;
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void force_epilogue(const RepDev& R, int i, int s, int spi,
+                                               const double f[3], double e_atom, int32_t flags,
+                                               double* ob)
+{
+    double vn[3];
+    force_epilogue_src<T, true>(R, i, s, spi, f, e_atom, flags, ob, GlobalState{R, i}, vn);
 }
 
 }  // namespace qtb

@@ -17,6 +17,7 @@
 // sampling steps form the eq. (5) terms.
 #include "force_epilogue.h"
 #include "qtb_internal.h"
+#include "ring_step.h"
 
 namespace qtb {
 namespace {
@@ -53,149 +54,178 @@ template <> struct NV<double> { using v4 = d4v; };
 template <typename X>
 using gptr = const __attribute__((address_space(1))) X*;
 
+template <typename T> __device__ __forceinline__ T as_bits_t(int32_t b);
+template <> __device__ __forceinline__ float as_bits_t<float>(int32_t b) { return __int_as_float(b); }
+template <> __device__ __forceinline__ double as_bits_t<double>(int32_t b)
+{
+    return __longlong_as_double((long long)b);
+}
+
 __device__ __forceinline__ int32_t vbits(f4v x) { return __float_as_int(x.w); }
 __device__ __forceinline__ int32_t vbits(d4v x) { return (int32_t)__double_as_longlong(x.w); }
+
+// Positions of step n for the pair loop: relative coordinates u (current
+// parity) measured from the list's references.  RECON: the lists were just
+// rebuilt around the current centroids c, so a neighbour's relative position
+// is rebuilt as (r_ref + u) - c from the previous references (all read-only
+// while the kernel runs; the owners update their own data in place).
+// POSREF: the lists were just rebuilt and the positions are read-only in
+// this kernel: relative positions are (T)(r - c) from the FP64 positions, as
+// the list kernel computes them.
+enum PosMode { kPosDirect = 0, kPosRecon = 1, kPosRef = 2 };
+
+template <typename T, int MODE>
+struct PairPos {
+    using V4 = typename NV<T>::v4;
+    gptr<V4> u;
+    gptr<double> rref, cen;
+    int N, P;
+    gptr<double> pos;
+    gptr<int32_t> species;
+    __device__ __forceinline__ V4 at(int j, int s) const
+    {
+        V4 v;
+        if constexpr (MODE == kPosRef) {
+            const size_t b = (size_t)s * 3 * N + j;
+            v.x = (T)(pos[b] - cen[j]);
+            v.y = (T)(pos[b + N] - cen[N + j]);
+            v.z = (T)(pos[b + 2 * (size_t)N] - cen[2 * (size_t)N + j]);
+            v.w = as_bits_t<T>(species[j]);
+        } else {
+            v = u[(size_t)j * P + s];
+            if constexpr (MODE == kPosRecon) {
+                const double x = (rref[j] + (double)v.x) - cen[j];
+                const double y = (rref[N + j] + (double)v.y) - cen[N + j];
+                const double z = (rref[2 * (size_t)N + j] + (double)v.z) - cen[2 * (size_t)N + j];
+                v.x = (T)x;
+                v.y = (T)y;
+                v.z = (T)z;
+            }
+        }
+        return v;
+    }
+};
 
 // NS: species count rounded up to 2 or 4 (parameters of the centre atom's
 // row are kept in registers and picked per neighbour with selects).
 // FAST (FP32 only): hardware rsq / exp2 and the fitted erfcx polynomial.
-template <typename T, int G, int NS, bool FAST, int DEG>
-__global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ reps,
-                                                    const BlockEntry* __restrict__ blocks,
-                                                    const PairTable<T> tab, int32_t flags,
-                                                    double* __restrict__ partials,
-                                                    int32_t* __restrict__ rebuild_clear, int n_rep,
-                                                    int32_t* __restrict__ rebuild_any, int W)
+// Force (FP64 sums) and, if want_e, energy of bead s of atom i over the list
+// entries ch, ch + ST, ...; spi receives the atom's species.
+template <typename T, int NS, bool FAST, int DEG, int MODE>
+__device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& tab,
+                                         const PairPos<T, MODE>& pp, int i, int s, int ch,
+                                         int ST, bool want_e, double& fx, double& fy, double& fz,
+                                         double& e, int& spi)
 {
     using V4 = typename NV<T>::v4;
-    constexpr int NCH = 64 / G;   // neighbour chunks per wavefront
-    // W wavefronts per atom (1, 2 or 4), 4 / W atoms per block
-    __shared__ double part[4][G][4];
-    __shared__ double red[4][kNobs];
-    const BlockEntry be = blocks[blockIdx.x];
-    const int rep = __builtin_amdgcn_readfirstlane(be.rep);
-    const RepDev& R = reps[rep];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = wave / W, wsub = wave % W;
-    const int bl = lane % G, ch = lane / G + wsub * NCH;
-    const int i = be.atom0 + slot;
-    const int N = R.N, P = R.P;
-    const bool active = i < N;
-    const int s = be.group * G + bl;
-    const bool want_e = (flags & (kSample | kEvaluate)) != 0;
-
-    if (blockIdx.x == 0 && rebuild_clear) {
-        for (int r = threadIdx.x; r < n_rep; r += blockDim.x) rebuild_clear[r] = 0;
-        if (threadIdx.x == 0) rebuild_any[0] = 0;
+    const V4 ui = pp.at(i, s);
+    spi = vbits(ui);
+    const int row = __builtin_amdgcn_readfirstlane(spi) * kMaxSpecies;
+    T pArho[NS], pirho[NS], pC6[NS], pkqq[NS], pF0[NS], pA[NS], pC[NS], pE0[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) {
+        const PairParam<T>& q = tab.p[row + b];
+        pArho[b] = q.Arho;
+        pirho[b] = FAST ? q.irho2 : q.irho;
+        pC6[b] = q.C6;
+        pkqq[b] = q.kqq;
+        pF0[b] = q.F0;
+        pA[b] = q.A;
+        pC[b] = q.C;
+        pE0[b] = q.E0;
     }
-
-    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
-    int spi = 0;
-    if (active) {
-        // u is atom-major [N][P]: the G beads of a neighbour share cache lines
-        gptr<V4> u = (gptr<V4>)R.u + s;
-        const V4 ui = u[(size_t)i * P];
-        spi = vbits(ui);
-        const int row = __builtin_amdgcn_readfirstlane(spi) * kMaxSpecies;
-        T pArho[NS], pirho[NS], pC6[NS], pkqq[NS], pF0[NS], pA[NS], pC[NS], pE0[NS];
+    // keep the neighbour-species parameters in VGPRs for the whole loop
+    // (selects on gfx950 take at most one SGPR operand)
 #pragma unroll
-        for (int b = 0; b < NS; ++b) {
-            const PairParam<T>& q = tab.p[row + b];
-            pArho[b] = q.Arho;
-            pirho[b] = FAST ? q.irho2 : q.irho;
-            pC6[b] = q.C6;
-            pkqq[b] = q.kqq;
-            pF0[b] = q.F0;
-            pA[b] = q.A;
-            pC[b] = q.C;
-            pE0[b] = q.E0;
-        }
-        // keep the neighbour-species parameters in VGPRs for the whole loop
-        // (selects on gfx950 take at most one SGPR operand)
+    for (int b = 0; b < NS; ++b) {
+        asm volatile("" : "+v"(pArho[b]), "+v"(pirho[b]), "+v"(pC6[b]), "+v"(pkqq[b]),
+                     "+v"(pF0[b]));
+    }
+    T ex[DEG + 1];
 #pragma unroll
-        for (int b = 0; b < NS; ++b) {
-            asm volatile("" : "+v"(pArho[b]), "+v"(pirho[b]), "+v"(pC6[b]), "+v"(pkqq[b]),
-                         "+v"(pF0[b]));
-        }
-        T ex[DEG + 1];
+    for (int k = 0; k <= DEG; ++k) ex[k] = tab.ex[k];
+    const T rc2 = tab.rc2, a2l = tab.a2l, s_mul = tab.s_mul, alpha = tab.alpha, g = tab.g;
+    gptr<V4> ent = (gptr<V4>)R.nb_entries + (size_t)i * R.maxnb;
+    const int cnt = R.nb_count[i];
+    // three-stage pipeline: entry q+2*ST and the neighbour of entry q+ST
+    // are loading while the pair of entry q is evaluated
+    int q = ch;
+    V4 E0 = ent[q < cnt ? q : 0];
+    V4 E1 = ent[q + ST < cnt ? q + ST : 0];
+    V4 U0 = pp.at(vbits(E0), s);
+    while (q < cnt) {
+        const int q2 = q + 2 * ST;
+        const V4 E2 = ent[q2 < cnt ? q2 : 0];
+        const V4 U1 = pp.at(vbits(E1), s);
+        const T dx = (E0.x + ui.x) - U0.x;
+        const T dy = (E0.y + ui.y) - U0.y;
+        const T dz = (E0.z + ui.z) - U0.z;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < rc2) {
+            const int spj = vbits(U0);
+            T Arho = pArho[0], irho = pirho[0], C6 = pC6[0], kqq = pkqq[0], F0 = pF0[0];
 #pragma unroll
-        for (int k = 0; k <= DEG; ++k) ex[k] = tab.ex[k];
-        const T rc2 = tab.rc2, a2l = tab.a2l, s_mul = tab.s_mul, alpha = tab.alpha, g = tab.g;
-        gptr<V4> ent = (gptr<V4>)R.nb_entries + (size_t)i * R.maxnb;
-        const int cnt = R.nb_count[i];
-        const int ST = NCH * W;
-        // three-stage pipeline: entry q+2*ST and the neighbour of entry q+ST
-        // are loading while the pair of entry q is evaluated
-        int q = ch;
-        V4 E0 = ent[q < cnt ? q : 0];
-        V4 E1 = ent[q + ST < cnt ? q + ST : 0];
-        V4 U0 = u[(size_t)vbits(E0) * P];
-        while (q < cnt) {
-            const int q2 = q + 2 * ST;
-            const V4 E2 = ent[q2 < cnt ? q2 : 0];
-            const V4 U1 = u[(size_t)vbits(E1) * P];
-            const T dx = (E0.x + ui.x) - U0.x;
-            const T dy = (E0.y + ui.y) - U0.y;
-            const T dz = (E0.z + ui.z) - U0.z;
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < rc2) {
-                const int spj = vbits(U0);
-                T Arho = pArho[0], irho = pirho[0], C6 = pC6[0], kqq = pkqq[0], F0 = pF0[0];
+            for (int b = 1; b < NS; ++b) {
+                const bool m = spj == b;
+                Arho = m ? pArho[b] : Arho;
+                irho = m ? pirho[b] : irho;
+                C6 = m ? pC6[b] : C6;
+                kqq = m ? pkqq[b] : kqq;
+                F0 = m ? pF0[b] : F0;
+            }
+            T rinv, r, e1, e2, ec;
+            if constexpr (FAST) {
+                rinv = __builtin_amdgcn_rsqf(r2);
+                r = r2 * rinv;
+                e1 = __builtin_amdgcn_exp2f(-r * irho);
+                e2 = __builtin_amdgcn_exp2f(-r2 * a2l);
+                const T sx = fmaf(r, s_mul, -1.0f);
+                T pe = ex[DEG];
+#pragma unroll
+                for (int k = DEG - 1; k >= 0; --k) pe = fmaf(pe, sx, ex[k]);
+                ec = e2 * pe;
+            } else {
+                rinv = t_rsqrt(r2);
+                r = r2 * rinv;
+                e1 = t_exp(-r * irho);
+                const T x = alpha * r;
+                e2 = t_exp(-x * x);
+                ec = t_erfc(x);
+            }
+            const T rinv2 = rinv * rinv;
+            const T rinv6 = rinv2 * rinv2 * rinv2;
+            const T F = Arho * e1 - C6 * rinv6 * rinv + kqq * (ec * rinv2 + g * e2 * rinv) + F0;
+            const T fr = F * rinv;
+            fx += (double)(fr * dx);
+            fy += (double)(fr * dy);
+            fz += (double)(fr * dz);
+            if (want_e) {
+                T A = pA[0], C = pC[0], E0c = pE0[0];
 #pragma unroll
                 for (int b = 1; b < NS; ++b) {
                     const bool m = spj == b;
-                    Arho = m ? pArho[b] : Arho;
-                    irho = m ? pirho[b] : irho;
-                    C6 = m ? pC6[b] : C6;
-                    kqq = m ? pkqq[b] : kqq;
-                    F0 = m ? pF0[b] : F0;
+                    A = m ? pA[b] : A;
+                    C = m ? pC[b] : C;
+                    E0c = m ? pE0[b] : E0c;
                 }
-                T rinv, r, e1, e2, ec;
-                if constexpr (FAST) {
-                    rinv = __builtin_amdgcn_rsqf(r2);
-                    r = r2 * rinv;
-                    e1 = __builtin_amdgcn_exp2f(-r * irho);
-                    e2 = __builtin_amdgcn_exp2f(-r2 * a2l);
-                    const T sx = fmaf(r, s_mul, -1.0f);
-                    T pe = ex[DEG];
-#pragma unroll
-                    for (int k = DEG - 1; k >= 0; --k) pe = fmaf(pe, sx, ex[k]);
-                    ec = e2 * pe;
-                } else {
-                    rinv = t_rsqrt(r2);
-                    r = r2 * rinv;
-                    e1 = t_exp(-r * irho);
-                    const T x = alpha * r;
-                    e2 = t_exp(-x * x);
-                    ec = t_erfc(x);
-                }
-                const T rinv2 = rinv * rinv;
-                const T rinv6 = rinv2 * rinv2 * rinv2;
-                const T F = Arho * e1 - C6 * rinv6 * rinv + kqq * (ec * rinv2 + g * e2 * rinv) + F0;
-                const T fr = F * rinv;
-                fx += (double)(fr * dx);
-                fy += (double)(fr * dy);
-                fz += (double)(fr * dz);
-                if (want_e) {
-                    T A = pA[0], C = pC[0], E0c = pE0[0];
-#pragma unroll
-                    for (int b = 1; b < NS; ++b) {
-                        const bool m = spj == b;
-                        A = m ? pA[b] : A;
-                        C = m ? pC[b] : C;
-                        E0c = m ? pE0[b] : E0c;
-                    }
-                    e += (double)(A * e1 - C * rinv6 + kqq * ec * rinv - F0 * r + E0c);
-                }
+                e += (double)(A * e1 - C * rinv6 + kqq * ec * rinv - F0 * r + E0c);
             }
-            E0 = E1;
-            E1 = E2;
-            U0 = U1;
-            q += ST;
         }
+        E0 = E1;
+        E1 = E2;
+        U0 = U1;
+        q += ST;
     }
-    // lanes with the same bead: reduce across chunks (shuffles), then across
-    // the W wavefronts of the atom (LDS)
+}
+
+// Lanes with the same bead: reduce across chunks (shuffles), then across the
+// W wavefronts of the atom (LDS part[wave][bead][4]); the sums end in the
+// lanes < G of the atom's first wavefront.
+template <int G>
+__device__ __forceinline__ void reduce_atom(double& fx, double& fy, double& fz, double& e,
+                                            bool want_e, int W, int wave, int wsub, int lane,
+                                            double (*part)[G][4])
+{
 #pragma unroll
     for (int off = G; off < 64; off <<= 1) {
         fx += __shfl_xor(fx, off);
@@ -220,24 +250,412 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
             }
         }
     }
+}
+
+// Block sums of the observable slots into partials[blockIdx.x].
+__device__ __forceinline__ void block_partials(const double* ob, int wave, int lane,
+                                               double (*red)[kNobs], double* partials)
+{
+#pragma unroll
+    for (int q = 0; q < kNobs; ++q) {
+        const double t = wave_sum(ob[q]);
+        if (lane == 0) red[wave][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNobs) {
+        const double t = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                         red[3][threadIdx.x];
+        partials[(size_t)blockIdx.x * kNobs + threadIdx.x] = t;
+    }
+}
+
+// Rebuild the list of atom i (one wavefront, all bead groups share it) from
+// the current centroids c and spreads dev (read-only in this kernel): pairs
+// within r_cut + skin + dev_i + dev_j, every periodic image, ballot-compacted
+// in a fixed order.  All four wavefronts of the block help stage candidate
+// tiles in LDS; only waves with active set list.
+template <typename T>
+__device__ void rebuild_list(const RepDev& R, int i, bool active, const double* cx,
+                             const double* cy, const double* cz, const double* dv,
+                             int32_t* status, double* tx, double* ty, double* tz, double* td,
+                             double* dmax_s)
+{
+    using V4 = typename NV<T>::v4;
+    const int N = R.N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double xi = 0.0, yi = 0.0, zi = 0.0, devi = 0.0;
+    if (active) {
+        xi = cx[i];
+        yi = cy[i];
+        zi = cz[i];
+        devi = dv[i];
+    }
+    const double Lx = R.box[0], Ly = R.box[1], Lz = R.box[2];
+    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
+    double dmax = 0.0;
+    for (int j = threadIdx.x; j < N; j += 256) dmax = fmax(dmax, dv[j]);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
+    if (lane == 0) dmax_s[wave] = dmax;
+    __syncthreads();
+    dmax = fmax(fmax(dmax_s[0], dmax_s[1]), fmax(dmax_s[2], dmax_s[3]));
+    const double Rmax = R.r_cs + devi + dmax;
+    const int mx = (int)ceil(Rmax * iLx - 0.5), my = (int)ceil(Rmax * iLy - 0.5),
+              mz = (int)ceil(Rmax * iLz - 0.5);
+    V4* __restrict__ ent = (V4*)R.nb_entries + (size_t)i * R.maxnb;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int cnt = 0;
+    for (int t0 = 0; t0 < N; t0 += 256) {
+        __syncthreads();
+        const int jl = t0 + threadIdx.x;
+        if (jl < N) {
+            tx[threadIdx.x] = cx[jl];
+            ty[threadIdx.x] = cy[jl];
+            tz[threadIdx.x] = cz[jl];
+            td[threadIdx.x] = dv[jl];
+        }
+        __syncthreads();
+        if (!active) continue;
+        const int tn = min(256, N - t0);
+        for (int c0 = 0; c0 < tn; c0 += 64) {
+            const int jj = c0 + lane;
+            const int j = t0 + jj;
+            const bool valid = jj < tn;
+            const double Rij = R.r_cs + devi + (valid ? td[jj] : 0.0);
+            const double R2 = Rij * Rij;
+            double dx = 0.0, dy = 0.0, dz = 0.0;
+            if (valid) {
+                dx = xi - tx[jj];
+                dy = yi - ty[jj];
+                dz = zi - tz[jj];
+                dx -= Lx * rint(dx * iLx);
+                dy -= Ly * rint(dy * iLy);
+                dz -= Lz * rint(dz * iLz);
+            }
+            for (int nx = -mx; nx <= mx; ++nx)
+                for (int ny = -my; ny <= my; ++ny)
+                    for (int nz = -mz; nz <= mz; ++nz) {
+                        const double ex = dx + nx * Lx, ey = dy + ny * Ly, ez = dz + nz * Lz;
+                        const double r2 = ex * ex + ey * ey + ez * ez;
+                        const bool self = (j == i) && nx == 0 && ny == 0 && nz == 0;
+                        const bool hit = valid && r2 < R2 && !self;
+                        const uint64_t mask = __ballot(hit);
+                        if (hit) {
+                            const int sl = cnt + __popcll(mask & below);
+                            if (sl < R.maxnb) {
+                                V4 v;
+                                v.x = (T)ex;
+                                v.y = (T)ey;
+                                v.z = (T)ez;
+                                v.w = as_bits_t<T>(j);
+                                ent[sl] = v;
+                            }
+                        }
+                        cnt += __popcll(mask);
+                    }
+        }
+    }
+    if (active && lane == 0) {
+        R.nb_count[i] = min(cnt, R.maxnb);
+        if (cnt > R.maxnb) atomicOr(status, kStatusNbOverflow);
+    }
+    __syncthreads();
+}
+
+template <typename T, int G, int NS, bool FAST, int DEG>
+__global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ reps,
+                                                    const BlockEntry* __restrict__ blocks,
+                                                    const PairTable<T> tab, int32_t flags,
+                                                    double* __restrict__ partials, int clear,
+                                                    int n_rep, int32_t* __restrict__ status,
+                                                    const StepRef sync, int W)
+{
+    using V4 = typename NV<T>::v4;
+    using T4 = typename Vec4<T>::type;
+    constexpr int NCH = 64 / G;   // neighbour chunks per wavefront
+    // W wavefronts per atom (1, 2 or 4), 4 / W atoms per block
+    __shared__ double part[4][G][4];
+    __shared__ double red[4][kNobs];
+    __shared__ double tx[256], ty[256], tz[256], td[256];
+    __shared__ double dmax_s[4];
+    const BlockEntry be = blocks[blockIdx.x];
+    const int rep = __builtin_amdgcn_readfirstlane(be.rep);
+    const RepDev& R = reps[rep];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = wave / W, wsub = wave % W;
+    const int bl = lane % G, ch = lane / G + wsub * NCH;
+    const int i = be.atom0 + slot;
+    const int N = R.N, P = R.P;
+    const bool active = i < N;
+    const int s = be.group * G + bl;
+    const bool want_e = (flags & (kSample | kEvaluate)) != 0;
+    const StepIdx si = step_index(sync);
+    // clear == 1: the list kernel ran before; this step's and the previous
+    // step's flags are done.  clear == 2: rebuild the lists here if this step
+    // flagged it (no list kernel); its flag stays set for the other
+    // workgroups and is cleared by the next step's force pass.
+    const bool rebuild = clear == 2 && R.rflag[si.f] != 0;  // uniform over the block
+    if (blockIdx.x == 0 && clear) {
+        const int fold = si.f == 0 ? 2 : si.f - 1;
+        for (int r = threadIdx.x; r < n_rep; r += blockDim.x) {
+            if (clear == 1) reps[r].rflag[si.f] = 0;
+            reps[r].rflag[fold] = 0;
+        }
+        if (threadIdx.x == 0) {
+            if (clear == 1) status[kAnyRebuild + si.f] = 0;
+            status[kAnyRebuild + fold] = 0;
+        }
+    }
+    const double* __restrict__ cen = R.cnb[si.p];
+    if (rebuild) {
+        rebuild_list<T>(R, i, active && wsub == 0, cen, cen + N, cen + 2 * (size_t)N,
+                        R.devn[si.p], status, tx, ty, tz, td, dmax_s);
+        if (active && wsub == 0) {
+            // new references and relative positions of the atom, as the list kernel
+            if (lane < 3) R.rrefb[si.p][(size_t)lane * N + i] = cen[(size_t)lane * N + i];
+            if (lane == 0) R.devbb[si.p][i] = R.devn[si.p][i];
+            const T spb = as_bits_t<T>(R.species[i]);
+            for (int b = lane; b < P; b += 64) {
+                T4 v;
+                v.x = (T)(R.pos[((size_t)b * 3 + 0) * N + i] - cen[i]);
+                v.y = (T)(R.pos[((size_t)b * 3 + 1) * N + i] - cen[N + i]);
+                v.z = (T)(R.pos[((size_t)b * 3 + 2) * N + i] - cen[2 * (size_t)N + i]);
+                v.w = spb;
+                ((T4*)R.ub[si.p])[(size_t)i * P + b] = v;
+            }
+        }
+    }
+    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+    int spi = 0;
+    if (active) {
+        if (rebuild) {
+            const PairPos<T, kPosRef> pp{nullptr, nullptr, (gptr<double>)cen, N, P,
+                                         (gptr<double>)R.pos, (gptr<int32_t>)R.species};
+            pair_sum<T, NS, FAST, DEG, kPosRef>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy, fz,
+                                                e, spi);
+        } else {
+            // u is atom-major [N][P]: the G beads of a neighbour share cache lines
+            const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[si.p] + 0, nullptr, nullptr, N, P,
+                                            nullptr, nullptr};
+            pair_sum<T, NS, FAST, DEG, kPosDirect>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
+                                                   fz, e, spi);
+        }
+    }
+    reduce_atom<G>(fx, fy, fz, e, want_e, W, wave, wsub, lane, part);
     double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (active && wsub == 0 && lane < G && s < P) {
         const double f[3] = {fx, fy, fz};
         force_epilogue<T>(R, i, s, spi, f, 0.5 * e, flags, ob);
     }
-    if (flags & (kSample | kCompare)) {
-#pragma unroll
-        for (int q = 0; q < kNobs; ++q) {
-            const double t = wave_sum(ob[q]);
-            if (lane == 0) red[wave][q] = t;
-        }
-        __syncthreads();
-        if (threadIdx.x < kNobs) {
-            const double t = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                             red[3][threadIdx.x];
-            partials[(size_t)blockIdx.x * kNobs + threadIdx.x] = t;
+    if (flags & (kSample | kCompare)) block_partials(ob, wave, lane, red, partials);
+}
+
+// One step of the pair potential for P = G <= 8 beads (all beads of an atom
+// in one wavefront), n = the step counter:
+//   [rebuild the lists if step n flagged it] -> forces at x_n -> closing
+//   half-kick of step n-1 (and its sampling) -> opening half-kick of step n
+//   -> normal modes, A(dt/2) O(dt) A(dt/2) with zeta_row -> x_{n+1}.
+// Neighbours read u, centroids and references of parity n & 1; the owner
+// writes its atom's data for step n + 1 into parity (n + 1) & 1 and updates
+// its positions and velocities in place.  Bit for bit the same arithmetic
+// as the separate update and force kernels.
+template <typename T, int G, int NS, bool FAST, int DEG>
+__global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ reps,
+                                                   const BlockEntry* __restrict__ blocks,
+                                                   const PairTable<T> tab, int32_t flags,
+                                                   double* __restrict__ partials, int n_rep,
+                                                   int32_t* __restrict__ status,
+                                                   const StepRef sync, int W,
+                                                   const T* __restrict__ zeta_row)
+{
+    using V4 = typename NV<T>::v4;
+    using T4 = typename Vec4<T>::type;
+    constexpr int NCH = 64 / G;
+    __shared__ double part[4][G][4];
+    __shared__ double red[4][kNobs];
+    __shared__ double tx[256], ty[256], tz[256], td[256];
+    __shared__ double dmax_s[4];
+    // the update's inputs, staged before the force loop: C, the ring
+    // propagators, and per (atom slot, component, bead / mode) positions,
+    // velocities and noise
+    __shared__ double Cs[G * G], ringS[3 * G];
+    __shared__ double xs[4][3][G], vs[4][3][G], zsh[4][3][G];
+    const StepIdx si = step_index(sync);
+    const int pin = si.p, pout = si.p ^ 1;
+    const int fnext = si.f == 2 ? 0 : si.f + 1, fold = si.f == 0 ? 2 : si.f - 1;
+    if (blockIdx.x == 0) {  // flags of step n - 1 are not read again until step n + 2
+        for (int r = threadIdx.x; r < n_rep; r += blockDim.x) reps[r].rflag[fold] = 0;
+        if (threadIdx.x == 0) status[kAnyRebuild + fold] = 0;
+    }
+    const BlockEntry be = blocks[blockIdx.x];
+    const int rep = __builtin_amdgcn_readfirstlane(be.rep);
+    const RepDev& R = reps[rep];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = wave / W, wsub = wave % W;
+    const int bl = lane % G, ch = lane / G + wsub * NCH;
+    const int i = be.atom0 + slot;
+    const int N = R.N, P = R.P;
+    const bool active = i < N;
+    const int s = bl;  // G = P: the wavefront holds every bead
+    const bool want_e = (flags & kSample) != 0;
+    {
+        const int apb = 4 / W;
+        for (int t = threadIdx.x; t < G * G; t += blockDim.x) Cs[t] = R.nm[t];
+        for (int t = threadIdx.x; t < 3 * G; t += blockDim.x) ringS[t] = R.ring[t];
+        for (int t = threadIdx.x; t < apb * 3 * G; t += blockDim.x) {
+            const int sl = t / (3 * G), rem = t % (3 * G), a = rem / G, b = rem % G;
+            const int ii = be.atom0 + sl;
+            if (ii < N) {
+                const size_t idx = ((size_t)b * 3 + a) * N + ii;
+                xs[sl][a][b] = R.pos[idx];
+                vs[sl][a][b] = R.vel[idx];
+                zsh[sl][a][b] = (double)zeta_row[R.dof_off + ((int64_t)3 * ii + a) * P + b];
+            }
         }
     }
+    __syncthreads();
+    const bool rebuild = R.rflag[si.f] != 0;  // uniform over the block
+    const double* __restrict__ cin = R.cnb[pin];
+    const double* __restrict__ rin = R.rrefb[pin];
+    if (rebuild)
+        rebuild_list<T>(R, i, active && wsub == 0, cin, cin + N, cin + 2 * (size_t)N, R.devn[pin],
+                        status, tx, ty, tz, td, dmax_s);
+    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+    int spi = 0;
+    if (active) {
+        if (rebuild) {
+            const PairPos<T, kPosRecon> pp{(gptr<V4>)R.ub[pin] + 0, (gptr<double>)rin,
+                                           (gptr<double>)cin, N, P, nullptr, nullptr};
+            pair_sum<T, NS, FAST, DEG, kPosRecon>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
+                                                  fz, e, spi);
+        } else {
+            const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[pin] + 0, nullptr, nullptr, N, P,
+                                            nullptr, nullptr};
+            pair_sum<T, NS, FAST, DEG, kPosDirect>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
+                                                   fz, e, spi);
+        }
+    }
+    reduce_atom<G>(fx, fy, fz, e, want_e, W, wave, wsub, lane, part);
+    double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int my_flags = 0;
+    // the atom's wavefront, lanes 0 .. P-1 = beads: wavefront-uniform branch.
+    if (active && wsub == 0) {
+        const bool own = lane < G;
+        struct LdsState {
+            const double (*x)[G];
+            const double (*v)[G];
+            __device__ __forceinline__ double pos(int b, int a) const { return x[a][b]; }
+            __device__ __forceinline__ double vel(int b, int a) const { return v[a][b]; }
+        };
+        const LdsState src{xs[slot], vs[slot]};
+        double vc[3] = {0.0, 0.0, 0.0};   // velocities after the closing half-kick
+        double fT[3] = {0.0, 0.0, 0.0};
+        if (own) {
+            const double f[3] = {fx, fy, fz};
+            force_epilogue_src<T, false>(R, i, s, spi, f, 0.5 * e, kKick | (flags & kSample), ob,
+                                         src, vc);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fT[a] = (double)(T)f[a];  // the stored force
+        }
+        const int k = s;  // after the transform this lane holds mode k
+        double cw = 0.0, sw = 0.0, ws = 0.0, kick = 0.0, sig = 0.0;
+        if (own) {
+            cw = ringS[k];
+            sw = ringS[P + k];
+            ws = ringS[2 * P + k];
+            kick = R.kick[spi];
+            sig = R.sigma[spi];
+        }
+        double rn[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const size_t idx = ((size_t)s * 3 + a) * N + i;
+            double r = 0.0, v = 0.0;
+            if (own) {
+                r = xs[slot][a][s];
+                v = half_kick(vc[a], kick, fT[a]);  // opening half-kick of step n
+            }
+            double q = 0.0, pm = 0.0;
+#pragma unroll
+            for (int b = 0; b < G; ++b) {
+                const double c = own ? Cs[b * P + k] : 0.0;
+                q = nm_acc(q, c, xs[slot][a][b]);
+                pm = nm_acc(pm, c, __shfl(v, b));
+            }
+            if (own) mode_aoa(q, pm, cw, sw, ws, R.c1, sig, zsh[slot][a][k]);
+            double x = 0.0, y = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < G; ++kk) {
+                const double c = own ? Cs[s * P + kk] : 0.0;
+                x = nm_acc(x, c, __shfl(q, kk));
+                y = nm_acc(y, c, __shfl(pm, kk));
+            }
+            if (own) {
+                R.pos[idx] = x;
+                R.vel[idx] = y;
+                if (!(__builtin_isfinite(x) && __builtin_isfinite(y))) my_flags |= kStatusNonfinite;
+            }
+            rn[a] = x;
+        }
+        // centroid (bead order), new references, relative positions, spread
+        double cen[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int b = 0; b < G; ++b) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) cen[a] += __shfl(rn[a], b);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) cen[a] /= P;
+        if (own) {
+            double ref[3], devb;
+            if (rebuild) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ref[a] = cin[(size_t)a * N + i];
+                devb = R.devn[pin][i];
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ref[a] = rin[(size_t)a * N + i];
+                devb = R.devbb[pin][i];
+            }
+            double u3[3], u2 = 0.0, d2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                u3[a] = rn[a] - ref[a];
+                u2 = nm_acc(u2, u3[a], u3[a]);
+                const double dc = rn[a] - cen[a];
+                d2 = nm_acc(d2, dc, dc);
+            }
+            T4 val;
+            val.x = (T)u3[0];
+            val.y = (T)u3[1];
+            val.z = (T)u3[2];
+            val.w = as_bits_t<T>(spi);
+            ((T4*)R.ub[pout])[(size_t)i * P + s] = val;
+            const double lim = devb + R.half_skin;
+            if (!(u2 <= lim * lim)) my_flags |= 8;
+            double dm = d2;
+            for (int b = 0; b < G; ++b) dm = fmax(dm, __shfl(d2, b));
+            if (lane == 0) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    R.cnb[pout][(size_t)a * N + i] = cen[a];
+                    R.rrefb[pout][(size_t)a * N + i] = ref[a];
+                }
+                R.devn[pout][i] = sqrt(dm);
+                R.devbb[pout][i] = devb;
+            }
+        }
+    }
+    // flags of the step: one atomic per wavefront
+    for (int off = 1; off < 64; off <<= 1) my_flags |= __shfl_xor(my_flags, off);
+    if (lane == 0 && my_flags) {
+        if (my_flags & 8) {
+            atomicOr(R.rflag + fnext, 1);
+            atomicOr(status + kAnyRebuild + fnext, 1);
+        }
+        if (my_flags & kStatusNonfinite) atomicOr(status, kStatusNonfinite);
+    }
+    if (flags & kSample) block_partials(ob, wave, lane, red, partials);
 }
 
 // Independent oscillators: V = sum_i 1/2 m omega_i^2 |x_i|^2 per bead.
@@ -309,19 +727,31 @@ __global__ void __launch_bounds__(256) k_force_harmonic(const RepDev* __restrict
     }
 }
 
-// Per replica, in block order (deterministic): acc += sum of block partials.
-__global__ void k_obs_reduce(const RepDev* __restrict__ reps, int n_rep,
-                             const double* __restrict__ partials, double* __restrict__ acc,
-                             int32_t* __restrict__ counts)
+// Per replica (one workgroup each): acc += sum of the replica's block
+// partials.  Thread t sums blocks t, t + 256, ... in order, then a fixed
+// tree in LDS: the same order on every run and for a replica alone or in a
+// batch (the assignment is relative to the replica's first block).
+__global__ void __launch_bounds__(256) k_obs_reduce(const RepDev* __restrict__ reps, int n_rep,
+                                                    const double* __restrict__ partials,
+                                                    double* __restrict__ acc,
+                                                    int32_t* __restrict__ counts)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double red[kNobs][256];
+    const int r = blockIdx.x;
     if (r >= n_rep) return;
     const RepDev& R = reps[r];
     double t[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int b = R.obs_block0; b < R.obs_block0 + R.obs_nblocks; ++b)
-        for (int q = 0; q < kNobs; ++q) t[q] += partials[(size_t)b * kNobs + q];
-    for (int q = 0; q < kNobs; ++q) acc[(size_t)r * kNobs + q] += t[q];
-    counts[r] += 1;
+    for (int b = threadIdx.x; b < R.obs_nblocks; b += blockDim.x)
+        for (int q = 0; q < kNobs; ++q) t[q] += partials[(size_t)(R.obs_block0 + b) * kNobs + q];
+    for (int q = 0; q < kNobs; ++q) red[q][threadIdx.x] = t[q];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int q = 0; q < kNobs; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < kNobs) acc[(size_t)r * kNobs + threadIdx.x] += red[threadIdx.x][0];
+    if (threadIdx.x == 0) counts[r] += 1;
 }
 
 __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v)
@@ -334,14 +764,14 @@ __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v)
 template <typename T, int NS, bool FAST, int DEG>
 void launch_pair_G(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
                    int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
-                   int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any, int W)
+                   int clear, int n_rep, int32_t* status, StepRef sync, int W)
 {
     const dim3 g(n_blocks), b(256);
     switch (G) {
-    case 1: launch((k_force_pair<T, 1, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W); break;
-    case 2: launch((k_force_pair<T, 2, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W); break;
-    case 4: launch((k_force_pair<T, 4, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W); break;
-    case 8: launch((k_force_pair<T, 8, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W); break;
+    case 1: launch((k_force_pair<T, 1, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    case 2: launch((k_force_pair<T, 2, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    case 4: launch((k_force_pair<T, 4, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    case 8: launch((k_force_pair<T, 8, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
     default: break;
     }
 }
@@ -349,36 +779,83 @@ void launch_pair_G(hipStream_t st, int G, const RepDev* reps, const BlockEntry* 
 template <typename T, bool FAST, int DEG>
 void launch_pair_T(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
                    int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
-                   int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any, int W)
+                   int clear, int n_rep, int32_t* status, StepRef sync, int W)
 {
     if (tab.n_species <= 2)
-        launch_pair_G<T, 2, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W);
+        launch_pair_G<T, 2, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, clear, n_rep, status, sync, W);
     else
-        launch_pair_G<T, 4, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, rebuild_clear, n_rep, rebuild_any, W);
+        launch_pair_G<T, 4, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, clear, n_rep, status, sync, W);
 }
 
 }  // namespace
 
 void launch_forces_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* reps,
                         const BlockEntry* blocks, int n_blocks, const void* table, int32_t flags,
-                        double* partials, int32_t* rebuild_clear, int n_rep,
-                        int32_t* rebuild_any)
+                        double* partials, int clear, int n_rep, int32_t* status,
+                        StepRef sync)
 {
     if (fp64) {
         launch_pair_T<double, false, 1>(st, G, reps, blocks, n_blocks,
                                      *(const PairTable<double>*)table, flags, partials,
-                                     rebuild_clear, n_rep, rebuild_any, W);
+                                     clear, n_rep, status, sync, W);
     } else {
         const PairTable<float>& t = *(const PairTable<float>*)table;
         if (t.ex_deg == 10)
             launch_pair_T<float, true, 10>(st, G, reps, blocks, n_blocks, t, flags, partials,
-                                           rebuild_clear, n_rep, rebuild_any, W);
+                                           clear, n_rep, status, sync, W);
         else if (t.ex_deg == kErfcxMaxDeg)
             launch_pair_T<float, true, kErfcxMaxDeg>(st, G, reps, blocks, n_blocks, t, flags,
-                                                     partials, rebuild_clear, n_rep, rebuild_any, W);
+                                                     partials, clear, n_rep, status, sync, W);
         else
             launch_pair_T<float, false, 1>(st, G, reps, blocks, n_blocks, t, flags, partials,
-                                           rebuild_clear, n_rep, rebuild_any, W);
+                                           clear, n_rep, status, sync, W);
+    }
+}
+
+template <typename T, int NS, bool FAST, int DEG>
+void launch_step_G(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
+                   int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
+                   int n_rep, int32_t* status, StepRef sync, int W, const T* zrow)
+{
+    const dim3 g(n_blocks), b(256);
+    switch (G) {
+    case 1: launch((k_step_pair<T, 1, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
+    case 2: launch((k_step_pair<T, 2, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
+    case 4: launch((k_step_pair<T, 4, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
+    case 8: launch((k_step_pair<T, 8, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
+    default: break;
+    }
+}
+
+template <typename T, bool FAST, int DEG>
+void launch_step_T(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
+                   int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
+                   int n_rep, int32_t* status, StepRef sync, int W, const T* zrow)
+{
+    if (tab.n_species <= 2)
+        launch_step_G<T, 2, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, n_rep, status, sync, W, zrow);
+    else
+        launch_step_G<T, 4, FAST, DEG>(st, G, reps, blocks, n_blocks, tab, flags, partials, n_rep, status, sync, W, zrow);
+}
+
+void launch_step_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* reps,
+                      const BlockEntry* blocks, int n_blocks, const void* table, int32_t flags,
+                      double* partials, int n_rep, int32_t* status, StepRef sync,
+                      const void* zeta_row)
+{
+    if (fp64) {
+        launch_step_T<double, false, 1>(st, G, reps, blocks, n_blocks,
+                                        *(const PairTable<double>*)table, flags, partials, n_rep,
+                                        status, sync, W, (const double*)zeta_row);
+    } else {
+        const PairTable<float>& t = *(const PairTable<float>*)table;
+        const float* z = (const float*)zeta_row;
+        if (t.ex_deg == 10)
+            launch_step_T<float, true, 10>(st, G, reps, blocks, n_blocks, t, flags, partials, n_rep, status, sync, W, z);
+        else if (t.ex_deg == kErfcxMaxDeg)
+            launch_step_T<float, true, kErfcxMaxDeg>(st, G, reps, blocks, n_blocks, t, flags, partials, n_rep, status, sync, W, z);
+        else
+            launch_step_T<float, false, 1>(st, G, reps, blocks, n_blocks, t, flags, partials, n_rep, status, sync, W, z);
     }
 }
 
@@ -397,8 +874,7 @@ void launch_forces_harmonic(hipStream_t st, bool fp64, const RepDev* reps,
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
                        double* acc, int32_t* counts)
 {
-    launch(k_obs_reduce, dim3((n_rep + 63) / 64), dim3(64), 0, st, reps, n_rep,
-                       partials, acc, counts);
+    launch(k_obs_reduce, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, acc, counts);
 }
 
 void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value)

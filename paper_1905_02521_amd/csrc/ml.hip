@@ -78,22 +78,25 @@ __device__ __forceinline__ float wsum(float v)
 template <typename T>
 __global__ void __launch_bounds__(256) k_ml_list(const RepDev* __restrict__ reps,
                                                  const BlockEntry* __restrict__ blocks,
-                                                 int n_entries, int32_t* __restrict__ status)
+                                                 int n_entries, int32_t* __restrict__ status,
+                                                 const StepRef sync)
 {
     using T4 = typename V4T<T>::type;
-    if (status[kAnyRebuild] == 0) return;
+    const StepIdx si = step_index(sync);
+    if (status[kAnyRebuild + si.f] == 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int e = blockIdx.x; e < n_entries; e += gridDim.x) {
         const BlockEntry be = blocks[e];
         const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
-        if (*R.rebuild == 0 || R.ml_nb == nullptr) continue;
+        if (R.rflag[si.f] == 0 || R.ml_nb == nullptr) continue;
         const int i = be.atom0 + wave;
         if (i >= R.N) continue;
+        const double* __restrict__ devb = R.devbb[si.p];
         const T4* __restrict__ ent = (const T4*)R.nb_entries + (size_t)i * R.maxnb;
         T4* __restrict__ out = (T4*)R.ml_nb + (size_t)i * R.maxml;
         const int cnt = R.nb_count[i];
-        const double base = R.ml_rcs + R.devb[i];  // r_ml + skin + dev_i
+        const double base = R.ml_rcs + devb[i];  // r_ml + skin + dev_i
         int n = 0;
         for (int k0 = 0; k0 < cnt; k0 += 64) {
             const int k = k0 + lane;
@@ -101,7 +104,7 @@ __global__ void __launch_bounds__(256) k_ml_list(const RepDev* __restrict__ reps
             T4 E;
             if (k < cnt) {
                 E = ent[k];
-                const double Rij = base + R.devb[ebits<T>(E)];
+                const double Rij = base + devb[ebits<T>(E)];
                 const double r2 = (double)E.x * E.x + (double)E.y * E.y + (double)E.z * E.z;
                 hit = r2 < Rij * Rij;
             }
@@ -124,15 +127,17 @@ __global__ void __launch_bounds__(256) k_ml_list(const RepDev* __restrict__ reps
 template <typename T>
 __global__ void __launch_bounds__(256) k_ml_rev(const RepDev* __restrict__ reps,
                                                 const BlockEntry* __restrict__ blocks,
-                                                int n_entries, int32_t* __restrict__ status)
+                                                int n_entries, int32_t* __restrict__ status,
+                                                const StepRef sync)
 {
     using T4 = typename V4T<T>::type;
-    if (status[kAnyRebuild] == 0) return;
+    const StepIdx si = step_index(sync);
+    if (status[kAnyRebuild + si.f] == 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int e = blockIdx.x; e < n_entries; e += gridDim.x) {
         const BlockEntry be = blocks[e];
         const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
-        if (*R.rebuild == 0 || R.ml_nb == nullptr) continue;
+        if (R.rflag[si.f] == 0 || R.ml_nb == nullptr) continue;
         const int i = be.atom0 + wave;
         if (i >= R.N) continue;
         const T4* __restrict__ ent = (const T4*)R.ml_nb;
@@ -168,10 +173,9 @@ template <typename T, bool DIR>
 __device__ __forceinline__ int stage_pairs(const RepDev& R, const MlDev& m, int i, int s,
                                            const typename V4T<T>::type ui, int k0, int cnt,
                                            PairStage& st, int lane, float wix, float wiy,
-                                           float wiz)
+                                           float wiz, const typename V4T<T>::type* u)
 {
     using T4 = typename V4T<T>::type;
-    const T4* __restrict__ u = (const T4*)R.u;
     const T4* __restrict__ ent = (const T4*)R.ml_nb + (size_t)i * R.maxml;
     const int P = R.P;
     const int k = k0 + lane;
@@ -219,15 +223,16 @@ __device__ __forceinline__ int stage_pairs(const RepDev& R, const MlDev& m, int 
 // Centre blocks: 4 atoms (one per wavefront), one bead (BlockEntry.group).
 template <typename T>
 __global__ void __launch_bounds__(256) k_ml_desc(const RepDev* __restrict__ reps, const MlDev m,
-                                                 const BlockEntry* __restrict__ blocks,
-                                                 int32_t* __restrict__ rebuild_clear, int n_rep,
-                                                 int32_t* __restrict__ rebuild_any)
+                                                 const BlockEntry* __restrict__ blocks, int n_rep,
+                                                 int32_t* __restrict__ status,
+                                                 const StepRef sync)
 {
     using T4 = typename V4T<T>::type;
     __shared__ PairStage stage[4];
-    if (blockIdx.x == 0 && rebuild_clear) {
-        for (int r = threadIdx.x; r < n_rep; r += blockDim.x) rebuild_clear[r] = 0;
-        if (threadIdx.x == 0) rebuild_any[0] = 0;
+    const StepIdx si = step_index(sync);
+    if (blockIdx.x == 0) {  // this step's rebuild (if any) is done
+        for (int r = threadIdx.x; r < n_rep; r += blockDim.x) reps[r].rflag[si.f] = 0;
+        if (threadIdx.x == 0) status[kAnyRebuild + si.f] = 0;
     }
     const BlockEntry be = blocks[blockIdx.x];
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
@@ -236,7 +241,8 @@ __global__ void __launch_bounds__(256) k_ml_desc(const RepDev* __restrict__ reps
     if (i >= R.N) return;  // uniform per wavefront; no block barrier below
     PairStage& st = stage[wave];
     const int N = R.N, P = R.P;
-    const T4 ui = ((const T4*)R.u)[(size_t)i * P + s];
+    const T4* __restrict__ u = (const T4*)R.ub[si.p];
+    const T4 ui = u[(size_t)i * P + s];
     const int cnt = R.ml_nc[i];
     // radial lanes: channel c, pair parity h; angular lanes: channel k, slot q
     const int c = lane & 31, h = lane >> 5;
@@ -247,7 +253,7 @@ __global__ void __launch_bounds__(256) k_ml_desc(const RepDev* __restrict__ reps
     float a1[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
     float a2[2][6] = {{0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}};
     for (int k0 = 0; k0 < cnt; k0 += 64) {
-        const int n = stage_pairs<T, false>(R, m, i, s, ui, k0, cnt, st, lane, 0.f, 0.f, 0.f);
+        const int n = stage_pairs<T, false>(R, m, i, s, ui, k0, cnt, st, lane, 0.f, 0.f, 0.f, u);
         for (int t = h; t < n; t += 2) {
             const float x = st.r[t] - mu_c;
             const float ph = fexp(-m.eta_r * x * x) * st.fc[t];
@@ -468,96 +474,118 @@ __global__ void __launch_bounds__(1024) k_ml_mlp(const RepDev* __restrict__ reps
 }
 
 // ------------------------------------------------------------ pair forces
-// dE_i/dd_ij for every list entry of centre (i, s), from dE/dG and A1, A2.
+// dE_i/dd_ij for the list entries of centre (i, s) within r_ml.  The entries
+// in range are compacted first (ballot, LDS), so the lanes work on pairs
+// that count; their slots are kept for the gather.
+constexpr int kMaxStage = 512;  // in-range entries of one centre (<= maxml)
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_ml_pair(const RepDev* __restrict__ reps, const MlDev m,
-                                                 const BlockEntry* __restrict__ blocks)
+                                                 const BlockEntry* __restrict__ blocks,
+                                                 const StepRef sync)
 {
     using T4 = typename V4T<T>::type;
     __shared__ float gs[4][kMlFeat];
     __shared__ float as[4][kMlAux];
+    __shared__ float4 st[4][kMaxStage];   // staged d_ij (x, y, z), slot bits in .w
     const BlockEntry be = blocks[blockIdx.x];
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = be.atom0 + wave, s = be.group;
     if (i >= R.N) return;
+    float4* __restrict__ stage = st[wave];
     const int N = R.N, P = R.P;
     const size_t cidx = (size_t)s * N + i;
     for (int f = lane; f < kMlFeat; f += 64) gs[wave][f] = R.ml_g[cidx * kMlFeat + f];
     for (int f = lane; f < kMlAux; f += 64) as[wave][f] = R.ml_aux[cidx * kMlAux + f];
-    wave_sync();
-    const T4* __restrict__ u = (const T4*)R.u;
+    const T4* __restrict__ u = (const T4*)R.ub[step_index(sync).p];
     const T4* __restrict__ ent = (const T4*)R.ml_nb + (size_t)i * R.maxml;
-    float4* __restrict__ out = (float4*)R.ml_fpair + cidx * R.maxml;
     const T4 ui = u[(size_t)i * P + s];
     const int cnt = R.ml_nc[i];
     const float rc = m.r_cut;
-    for (int k = lane; k < cnt; k += 64) {
-        const T4 E = ent[k];
-        const int j = ebits<T>(E);
-        const T4 Uj = u[(size_t)j * P + s];
-        const float dx = (float)((Uj.x - ui.x) - E.x);
-        const float dy = (float)((Uj.y - ui.y) - E.y);
-        const float dz = (float)((Uj.z - ui.z) - E.z);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        float fx = 0.f, fy = 0.f, fz = 0.f;
-        if (r2 < rc * rc) {
-            const int b = R.species[j];
-            const float* __restrict__ g = gs[wave] + b * kMlFeatSp;
-            const float* __restrict__ A = as[wave] + b * kMlAng * 9;
-            const float r = __builtin_sqrtf(r2), ir = 1.0f / r;
-            const float rx = dx * ir, ry = dy * ir, rz = dz * ir;
-            const float ang = kPiF * r / rc;
-            const float fc = 0.5f * (__cosf(ang) + 1.0f);
-            const float dfc = -0.5f * kPiF / rc * __sinf(ang);
-            // radial: dE/dr = sum_c g_c e_c (-2 eta (r - mu_c) f_c + f_c')
-            float S0 = 0.f, S1 = 0.f;
-#pragma unroll 8
-            for (int c = 0; c < kMlRad; ++c) {
-                const float x = r - (m.mu0 + m.dr * c);
-                const float ge = g[c] * fexp(-m.eta_r * x * x);
-                S0 += ge;
-                S1 += ge * x;
-            }
-            float dEdr = -2.0f * m.eta_r * fc * S1 + dfc * S0;
-            float ox = 0.f, oy = 0.f, oz = 0.f;  // terms along w (not rhat)
-#pragma unroll
-            for (int k8 = 0; k8 < kMlAng; ++k8) {
-                const float x = r - (m.nu0 + m.da * k8);
-                const float ea = fexp(-m.eta_a * x * x);
-                const float ps = ea * fc;
-                const float dps = ea * (-2.0f * m.eta_a * x * fc + dfc);
-                const float* a = A + k8 * 9;
-                const float g1 = g[kMlRad + k8], g2 = g[kMlRad + kMlAng + k8];
-                // l = 1: 2 [psi' (rhat.A1) rhat + psi/r (A1 - (rhat.A1) rhat)]
-                const float p = rx * a[0] + ry * a[1] + rz * a[2];
-                dEdr += 2.0f * g1 * dps * p;
-                const float c1 = 2.0f * g1 * ps * ir;
-                ox += c1 * (a[0] - p * rx);
-                oy += c1 * (a[1] - p * ry);
-                oz += c1 * (a[2] - p * rz);
-                // l = 2: 2 [psi' q rhat + 2 psi/r (A2 rhat - q rhat)], q = rhat.A2.rhat
-                const float vx = a[3] * rx + a[6] * ry + a[7] * rz;
-                const float vy = a[6] * rx + a[4] * ry + a[8] * rz;
-                const float vz = a[7] * rx + a[8] * ry + a[5] * rz;
-                const float qq = rx * vx + ry * vy + rz * vz;
-                dEdr += 2.0f * g2 * dps * qq;
-                const float c2 = 4.0f * g2 * ps * ir;
-                ox += c2 * (vx - qq * rx);
-                oy += c2 * (vy - qq * ry);
-                oz += c2 * (vz - qq * rz);
-            }
-            fx = dEdr * rx + ox;
-            fy = dEdr * ry + oy;
-            fz = dEdr * rz + oz;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int n = 0;
+    for (int k0 = 0; k0 < cnt; k0 += 64) {
+        const int k = k0 + lane;
+        bool hit = false;
+        float dx = 0.f, dy = 0.f, dz = 0.f;
+        if (k < cnt) {
+            const T4 E = ent[k];
+            const T4 Uj = u[(size_t)ebits<T>(E) * P + s];
+            dx = (float)((Uj.x - ui.x) - E.x);
+            dy = (float)((Uj.y - ui.y) - E.y);
+            dz = (float)((Uj.z - ui.z) - E.z);
+            hit = dx * dx + dy * dy + dz * dz < rc * rc;
         }
-        out[k] = make_float4(fx, fy, fz, 0.0f);
+        const uint64_t mask = __ballot(hit);
+        const int q = n + __popcll(mask & below);
+        if (hit && q < kMaxStage) stage[q] = make_float4(dx, dy, dz, __int_as_float(k));
+        n += __popcll(mask);
+    }
+    n = min(n, kMaxStage);
+    int* __restrict__ in_slots = R.ml_in + cidx * R.maxml;
+    if (lane == 0) R.ml_nin[cidx] = n;
+    wave_sync();
+    float4* __restrict__ out = (float4*)R.ml_fpair + cidx * R.maxml;
+    for (int q = lane; q < n; q += 64) {
+        const float4 D = stage[q];
+        const int k = __float_as_int(D.w);
+        const float dx = D.x, dy = D.y, dz = D.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const int b = R.species[ebits<T>(ent[k])];
+        const float* __restrict__ g = gs[wave] + b * kMlFeatSp;
+        const float* __restrict__ A = as[wave] + b * kMlAng * 9;
+        const float r = __builtin_sqrtf(r2), ir = 1.0f / r;
+        const float rx = dx * ir, ry = dy * ir, rz = dz * ir;
+        const float ang = kPiF * r / rc;
+        const float fc = 0.5f * (__cosf(ang) + 1.0f);
+        const float dfc = -0.5f * kPiF / rc * __sinf(ang);
+        // radial: dE/dr = sum_c g_c e_c (-2 eta (r - mu_c) f_c + f_c')
+        float S0 = 0.f, S1 = 0.f;
+#pragma unroll 8
+        for (int c = 0; c < kMlRad; ++c) {
+            const float x = r - (m.mu0 + m.dr * c);
+            const float ge = g[c] * fexp(-m.eta_r * x * x);
+            S0 += ge;
+            S1 += ge * x;
+        }
+        float dEdr = -2.0f * m.eta_r * fc * S1 + dfc * S0;
+        float ox = 0.f, oy = 0.f, oz = 0.f;  // terms off the pair axis
+#pragma unroll
+        for (int k8 = 0; k8 < kMlAng; ++k8) {
+            const float x = r - (m.nu0 + m.da * k8);
+            const float ea = fexp(-m.eta_a * x * x);
+            const float ps = ea * fc;
+            const float dps = ea * (-2.0f * m.eta_a * x * fc + dfc);
+            const float* a = A + k8 * 9;
+            const float g1 = g[kMlRad + k8], g2 = g[kMlRad + kMlAng + k8];
+            // l = 1: 2 [psi' (rhat.A1) rhat + psi/r (A1 - (rhat.A1) rhat)]
+            const float p = rx * a[0] + ry * a[1] + rz * a[2];
+            dEdr += 2.0f * g1 * dps * p;
+            const float c1 = 2.0f * g1 * ps * ir;
+            ox += c1 * (a[0] - p * rx);
+            oy += c1 * (a[1] - p * ry);
+            oz += c1 * (a[2] - p * rz);
+            // l = 2: 2 [psi' q rhat + 2 psi/r (A2 rhat - q rhat)], q = rhat.A2.rhat
+            const float vx = a[3] * rx + a[6] * ry + a[7] * rz;
+            const float vy = a[6] * rx + a[4] * ry + a[8] * rz;
+            const float vz = a[7] * rx + a[8] * ry + a[5] * rz;
+            const float qq = rx * vx + ry * vy + rz * vz;
+            dEdr += 2.0f * g2 * dps * qq;
+            const float c2 = 4.0f * g2 * ps * ir;
+            ox += c2 * (vx - qq * rx);
+            oy += c2 * (vy - qq * ry);
+            oz += c2 * (vz - qq * rz);
+        }
+        out[k] = make_float4(dEdr * rx + ox, dEdr * ry + oy, dEdr * rz + oz, 0.0f);
+        in_slots[q] = k;
     }
 }
 
-// F_i = sum_k (dE_i/dd_ik - dE_j/dd_ji) in list order, then the same closing
-// kick / sampling as the pair kernel.  Blocks: the pair kernel's table with
-// one wavefront per atom (G beads per wavefront).
+// F_i = sum over the entries in range (d_ij is exactly -d_ji, so both sides
+// agree on which they are) of dE_i/dd_ij - dE_j/dd_ji, in list order, then
+// the same closing kick / sampling as the pair kernel.  Blocks: the pair
+// kernel's table (apb atoms, G beads per wavefront).
 template <typename T, int G>
 __global__ void __launch_bounds__(256) k_ml_gather(const RepDev* __restrict__ reps,
                                                    const MlDev m,
@@ -575,17 +603,19 @@ __global__ void __launch_bounds__(256) k_ml_gather(const RepDev* __restrict__ re
     const int i = be.atom0 + wave;
     const int N = R.N, P = R.P;
     const int s = be.group * G + bl;
-    const bool active = wave < apb && i < N;
+    const bool active = wave < apb && i < N && s < P;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (active) {
         const T4* __restrict__ ent = (const T4*)R.ml_nb + (size_t)i * R.maxml;
         const int* __restrict__ rev = R.ml_rev + (size_t)i * R.maxml;
         const float4* __restrict__ fp = (const float4*)R.ml_fpair;
-        const int cnt = R.ml_nc[i];
-        const size_t own = ((size_t)s * N + i) * R.maxml;
-        for (int k = ch; k < cnt; k += NCH) {
+        const size_t c = (size_t)s * N + i;
+        const int* __restrict__ in_slots = R.ml_in + c * R.maxml;
+        const int n = R.ml_nin[c];
+        for (int q = ch; q < n; q += NCH) {
+            const int k = in_slots[q];
             const int j = ebits<T>(ent[k]);
-            const float4 a = fp[own + k];
+            const float4 a = fp[c * R.maxml + k];
             const float4 b = fp[((size_t)s * N + j) * R.maxml + rev[k]];
             fx += (double)(a.x - b.x);
             fy += (double)(a.y - b.y);
@@ -599,7 +629,7 @@ __global__ void __launch_bounds__(256) k_ml_gather(const RepDev* __restrict__ re
         fz += __shfl_xor(fz, off);
     }
     double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (active && lane < G && s < P) {
+    if (active && lane < G) {
         const int spi = R.species[i];
         const size_t c = (size_t)s * N + i;
         const double e_atom = (double)R.ml_y[c] + m.e0[spi];
@@ -677,7 +707,8 @@ __global__ void __launch_bounds__(256) k_ml_loss(const RepDev* __restrict__ reps
 // v_i = sum_j (dG_i/dd_ij) (u_j - u_i): the descriptors' derivative along dL/dF.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ml_jvp(const RepDev* __restrict__ reps, const MlDev m,
-                                                const BlockEntry* __restrict__ blocks)
+                                                const BlockEntry* __restrict__ blocks,
+                                                const StepRef sync)
 {
     using T4 = typename V4T<T>::type;
     __shared__ PairStage stage[4];
@@ -689,7 +720,8 @@ __global__ void __launch_bounds__(256) k_ml_jvp(const RepDev* __restrict__ reps,
     PairStage& st = stage[wave];
     const int N = R.N, P = R.P;
     const size_t cidx = (size_t)s * N + i;
-    const T4 ui = ((const T4*)R.u)[(size_t)i * P + s];
+    const T4* __restrict__ u = (const T4*)R.ub[step_index(sync).p];
+    const T4 ui = u[(size_t)i * P + s];
     const float* __restrict__ uu = R.ml_u + (size_t)s * 3 * N;
     const float wix = uu[i], wiy = uu[N + i], wiz = uu[2 * N + i];
     const int cnt = R.ml_nc[i];
@@ -705,7 +737,7 @@ __global__ void __launch_bounds__(256) k_ml_jvp(const RepDev* __restrict__ reps,
     float v0 = 0.f, v1 = 0.f;                 // radial, per species
     float l1[2] = {0.f, 0.f}, l2[2] = {0.f, 0.f};
     for (int k0 = 0; k0 < cnt; k0 += 64) {
-        const int n = stage_pairs<T, true>(R, m, i, s, ui, k0, cnt, st, lane, wix, wiy, wiz);
+        const int n = stage_pairs<T, true>(R, m, i, s, ui, k0, cnt, st, lane, wix, wiy, wiz, u);
         for (int t = h; t < n; t += 2) {
             const float x = st.r[t] - mu_c;
             const float e = fexp(-m.eta_r * x * x);
@@ -862,44 +894,124 @@ __global__ void __launch_bounds__(1024) k_ml_train_mlp(const RepDev* __restrict_
     }
 }
 
-// dL/dtheta: one thread per parameter, sum over every centre of its species
-// (replicas in order, centres in order).
-__global__ void __launch_bounds__(256) k_ml_wgrad(const RepDev* __restrict__ reps, int n_rep,
-                                                  const MlDev m, float* __restrict__ grad)
+// dL/dtheta as outer-product sums over the centres of one species:
+//   W1 += z1b x^T + z1db xd^T, W2 += z2b h1^T + z2db h1d^T, b1 += z1b,
+//   b2 += z2b, w3 += t3, b3 += e.
+// Workgroup (g, a) takes the network tiles g, g + kWgBlocks, ... in order,
+// stages 16 centres at a time in LDS and accumulates a 4x6 block of W1 and a
+// 4x4 block of W2 per thread in FP32; its partial sums go to part[g][a], and
+// k_ml_wgrad_sum adds the kWgBlocks partials in order in FP64.
+constexpr int kWgStage = 16;
+
+struct WgLds {
+    float x[kWgStage][kMlFeat], xd[kWgStage][kMlFeat];
+    float z1b[kWgStage][kMlHidden], z1db[kWgStage][kMlHidden];
+    float h1[kWgStage][kMlHidden], h1d[kWgStage][kMlHidden];
+    float z2b[kWgStage][kMlHidden], z2db[kWgStage][kMlHidden], t3[kWgStage][kMlHidden];
+    float e[kWgStage];
+    int ok[kWgStage];
+};
+
+__global__ void __launch_bounds__(256) k_ml_wgrad_part(const RepDev* __restrict__ reps,
+                                                       const MlDev m,
+                                                       const BlockEntry* __restrict__ blocks,
+                                                       int n_blocks, float* __restrict__ part)
+{
+    __shared__ WgLds L;
+    const int a = blockIdx.y, t = threadIdx.x;
+    const int og = t >> 4, mg = t & 15;     // W1: rows 4 og.., cols 6 mg..; W2: cols 4 mg..
+    float w1[4][6], w2[4][4];
+    for (int i = 0; i < 4; ++i) {
+        for (int j = 0; j < 6; ++j) w1[i][j] = 0.f;
+        for (int j = 0; j < 4; ++j) w2[i][j] = 0.f;
+    }
+    float vb1 = 0.f, vb2 = 0.f, vw3 = 0.f, vb3 = 0.f;
+    for (int b = blockIdx.x; b < n_blocks; b += gridDim.x) {
+        const BlockEntry be = blocks[b];
+        const RepDev& R = reps[be.rep];
+        const int N = R.N;
+        for (int q0 = 0; q0 < be.group; q0 += kWgStage) {
+            __syncthreads();  // previous stage consumed
+            for (int idx = t; idx < kWgStage * (2 * kMlFeat + 7 * kMlHidden + 1); idx += blockDim.x) {
+                const int qi = idx / (2 * kMlFeat + 7 * kMlHidden + 1);
+                const int k = idx % (2 * kMlFeat + 7 * kMlHidden + 1);
+                const int q = q0 + qi;
+                const bool valid = q < be.group;
+                const size_t c = (size_t)be.atom0 + (valid ? q : 0);
+                const int sp = R.species[c % N];
+                if (k == 0) L.ok[qi] = valid && sp == a;
+                const float* row = R.ml_adj + c * kMlAdj;
+                if (k < kMlFeat) {
+                    L.x[qi][k] = (R.ml_G[c * kMlFeat + k] - m.mu[sp * kMlFeat + k]) *
+                                 m.inv_sd[sp * kMlFeat + k];
+                } else if (k < 2 * kMlFeat) {
+                    L.xd[qi][k - kMlFeat] = row[k - kMlFeat];
+                } else if (k < 2 * kMlFeat + 7 * kMlHidden) {
+                    const int kk = k - 2 * kMlFeat, blk = kk / kMlHidden, o = kk % kMlHidden;
+                    const float v = row[kMlFeat + kk];
+                    float* dst = blk == 0 ? L.z1b[qi] : blk == 1 ? L.z1db[qi] : blk == 2 ? L.h1[qi]
+                               : blk == 3 ? L.h1d[qi] : blk == 4 ? L.z2b[qi] : blk == 5 ? L.z2db[qi]
+                               : L.t3[qi];
+                    dst[o] = v;
+                } else {
+                    L.e[qi] = row[kMlFeat + 7 * kMlHidden];
+                }
+            }
+            __syncthreads();
+            for (int qi = 0; qi < kWgStage; ++qi) {
+                if (!L.ok[qi]) continue;  // uniform over the workgroup
+                float zb[4], zdb[4], yb[4], ydb[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    zb[i] = L.z1b[qi][4 * og + i];
+                    zdb[i] = L.z1db[qi][4 * og + i];
+                    yb[i] = L.z2b[qi][4 * og + i];
+                    ydb[i] = L.z2db[qi][4 * og + i];
+                }
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    const float x = L.x[qi][6 * mg + j], xd = L.xd[qi][6 * mg + j];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) w1[i][j] += zb[i] * x + zdb[i] * xd;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float h = L.h1[qi][4 * mg + j], hd = L.h1d[qi][4 * mg + j];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) w2[i][j] += yb[i] * h + ydb[i] * hd;
+                }
+                if (t < kMlHidden) {
+                    vb1 += L.z1b[qi][t];
+                    vb2 += L.z2b[qi][t];
+                    vw3 += L.t3[qi][t];
+                }
+                if (t == 0) vb3 += L.e[qi];
+            }
+        }
+    }
+    float* out = part + ((size_t)blockIdx.x * kMlSpecies + a) * kMlParamsSp;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) out[kMlOffW1 + (4 * og + i) * kMlFeat + 6 * mg + j] = w1[i][j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[kMlOffW2 + (4 * og + i) * kMlHidden + 4 * mg + j] = w2[i][j];
+    }
+    if (t < kMlHidden) {
+        out[kMlOffB1 + t] = vb1;
+        out[kMlOffB2 + t] = vb2;
+        out[kMlOffW3 + t] = vw3;
+    }
+    if (t == 0) out[kMlOffB3] = vb3;
+}
+
+__global__ void k_ml_wgrad_sum(const float* __restrict__ part, int n_part, float* __restrict__ grad)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kMlParams) return;
     const int a = p / kMlParamsSp, off = p % kMlParamsSp;
     double acc = 0.0;
-    for (int r = 0; r < n_rep; ++r) {
-        const RepDev& R = reps[r];
-        const int N = R.N;
-        const size_t nc = (size_t)R.P * N;
-        for (size_t c = 0; c < nc; ++c) {
-            if (R.species[c % N] != a) continue;
-            const float* row = R.ml_adj + c * kMlAdj;
-            float t;
-            if (off < kMlOffB1) {
-                const int o = off / kMlFeat, f = off % kMlFeat;
-                const float x = (R.ml_G[c * kMlFeat + f] - m.mu[a * kMlFeat + f]) *
-                                m.inv_sd[a * kMlFeat + f];
-                t = row[96 + o] * x + row[96 + 64 + o] * row[f];
-            } else if (off < kMlOffW2) {
-                t = row[96 + (off - kMlOffB1)];
-            } else if (off < kMlOffB2) {
-                const int o = (off - kMlOffW2) / kMlHidden, k = (off - kMlOffW2) % kMlHidden;
-                t = row[96 + 4 * 64 + o] * row[96 + 2 * 64 + k] +
-                    row[96 + 5 * 64 + o] * row[96 + 3 * 64 + k];
-            } else if (off < kMlOffW3) {
-                t = row[96 + 4 * 64 + (off - kMlOffB2)];
-            } else if (off < kMlOffB3) {
-                t = row[96 + 6 * 64 + (off - kMlOffW3)];
-            } else {
-                t = row[96 + 7 * 64];
-            }
-            acc += (double)t;
-        }
-    }
+    for (int g = 0; g < n_part; ++g) acc += (double)part[((size_t)g * kMlSpecies + a) * kMlParamsSp + off];
     grad[p] = (float)acc;
 }
 
@@ -927,17 +1039,19 @@ __global__ void k_ml_round(const float* __restrict__ master, uint16_t* __restric
 }
 
 // Sums of G and G^2 per (centre species, feature), and centre counts:
-// stats [2][96][2] then [2] (FP64), one thread per (species, feature).
-__global__ void k_ml_stats(const RepDev* __restrict__ reps, int n_rep, double* __restrict__ stats)
+// stats [2][96][2] then [2] (FP64).  One workgroup per (species, feature):
+// thread t takes centres t, t + 256, ... of every replica in order, then a
+// fixed tree in LDS.
+__global__ void __launch_bounds__(256) k_ml_stats(const RepDev* __restrict__ reps, int n_rep,
+                                                  double* __restrict__ stats)
 {
-    const int t = threadIdx.x;
-    if (t >= 2 * kMlFeat) return;
-    const int a = t / kMlFeat, f = t % kMlFeat;
+    __shared__ double red[3][256];
+    const int a = blockIdx.x / kMlFeat, f = blockIdx.x % kMlFeat;
     double s1 = 0.0, s2 = 0.0, n = 0.0;
     for (int r = 0; r < n_rep; ++r) {
         const RepDev& R = reps[r];
         const size_t nc = (size_t)R.P * R.N;
-        for (size_t c = 0; c < nc; ++c) {
+        for (size_t c = threadIdx.x; c < nc; c += blockDim.x) {
             if (R.species[c % R.N] != a) continue;
             const double g = R.ml_G[c * kMlFeat + f];
             s1 += g;
@@ -945,9 +1059,20 @@ __global__ void k_ml_stats(const RepDev* __restrict__ reps, int n_rep, double* _
             n += 1.0;
         }
     }
-    stats[(a * kMlFeat + f) * 2 + 0] = s1;
-    stats[(a * kMlFeat + f) * 2 + 1] = s2;
-    if (f == 0) stats[2 * kMlFeat * 2 + a] = n;
+    red[0][threadIdx.x] = s1;
+    red[1][threadIdx.x] = s2;
+    red[2][threadIdx.x] = n;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        stats[(a * kMlFeat + f) * 2 + 0] = red[0][0];
+        stats[(a * kMlFeat + f) * 2 + 1] = red[1][0];
+        if (f == 0) stats[2 * kMlFeat * 2 + a] = red[2][0];
+    }
 }
 
 size_t mlp_lds_bytes() { return sizeof(MlpLds) + sizeof(float4) * kMlpWaves * (kMlFeat + kMlHidden); }
@@ -967,22 +1092,22 @@ void allow_lds(K kernel, size_t bytes, bool& done)
 }  // namespace
 
 void launch_ml_lists(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* nl_blocks,
-                     int n_nl, int32_t* status, bool)
+                     int n_nl, int32_t* status, StepRef sync)
 {
     const int grid = n_nl < 256 ? n_nl : 256;
     if (grid <= 0) return;
     if (fp64) {
-        launch(k_ml_list<double>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status);
-        launch(k_ml_rev<double>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status);
+        launch(k_ml_list<double>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status, sync);
+        launch(k_ml_rev<double>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status, sync);
     } else {
-        launch(k_ml_list<float>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status);
-        launch(k_ml_rev<float>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status);
+        launch(k_ml_list<float>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status, sync);
+        launch(k_ml_rev<float>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status, sync);
     }
 }
 
 void launch_ml_forward(hipStream_t st, bool fp64, const RepDev* reps, const MlDev& m,
                        const BlockEntry* cblocks, int n_cblocks, const BlockEntry* mblocks,
-                       int n_mblocks, int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any)
+                       int n_mblocks, int n_rep, int32_t* status, StepRef sync)
 {
     if (n_cblocks <= 0) return;
     const size_t lds = mlp_lds_bytes();
@@ -991,14 +1116,14 @@ void launch_ml_forward(hipStream_t st, bool fp64, const RepDev* reps, const MlDe
     const int mgrid = n_mblocks < 256 ? n_mblocks : 256;
     if (fp64) {
         launch(k_ml_desc<double>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks,
-               rebuild_clear, n_rep, rebuild_any);
+               n_rep, status, sync);
         launch(k_ml_mlp, dim3(mgrid), dim3(1024), (uint32_t)lds, st, reps, m, mblocks, n_mblocks);
-        launch(k_ml_pair<double>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks);
+        launch(k_ml_pair<double>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks, sync);
     } else {
         launch(k_ml_desc<float>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks,
-               rebuild_clear, n_rep, rebuild_any);
+               n_rep, status, sync);
         launch(k_ml_mlp, dim3(mgrid), dim3(1024), (uint32_t)lds, st, reps, m, mblocks, n_mblocks);
-        launch(k_ml_pair<float>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks);
+        launch(k_ml_pair<float>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks, sync);
     }
 }
 
@@ -1035,11 +1160,11 @@ void launch_ml_loss(hipStream_t st, const RepDev* reps, int n_rep, const double*
 }
 
 void launch_ml_jvp(hipStream_t st, bool fp64, const RepDev* reps, const MlDev& m,
-                   const BlockEntry* cblocks, int n_cblocks)
+                   const BlockEntry* cblocks, int n_cblocks, StepRef sync)
 {
     if (n_cblocks <= 0) return;
-    if (fp64) launch(k_ml_jvp<double>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks);
-    else launch(k_ml_jvp<float>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks);
+    if (fp64) launch(k_ml_jvp<double>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks, sync);
+    else launch(k_ml_jvp<float>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks, sync);
 }
 
 void launch_ml_train_mlp(hipStream_t st, const RepDev* reps, const MlDev& m,
@@ -1053,9 +1178,13 @@ void launch_ml_train_mlp(hipStream_t st, const RepDev* reps, const MlDev& m,
     launch(k_ml_train_mlp, dim3(grid), dim3(1024), (uint32_t)lds, st, reps, m, mblocks, n_mblocks);
 }
 
-void launch_ml_wgrad(hipStream_t st, const RepDev* reps, int n_rep, const MlDev& m, float* grad)
+void launch_ml_wgrad(hipStream_t st, const RepDev* reps, const MlDev& m,
+                     const BlockEntry* mblocks, int n_mblocks, float* part, float* grad)
 {
-    launch(k_ml_wgrad, dim3((kMlParams + 255) / 256), dim3(256), 0, st, reps, n_rep, m, grad);
+    launch(k_ml_wgrad_part, dim3(kWgBlocks, kMlSpecies), dim3(256), 0, st, reps, m, mblocks,
+           n_mblocks, part);
+    launch(k_ml_wgrad_sum, dim3((kMlParams + 255) / 256), dim3(256), 0, st, part, (int)kWgBlocks,
+           grad);
 }
 
 void launch_ml_adam(hipStream_t st, float* master, uint16_t* wq, float* mom1, float* mom2,
@@ -1073,7 +1202,7 @@ void launch_ml_round(hipStream_t st, const float* master, uint16_t* wq, int n)
 
 void launch_ml_stats(hipStream_t st, const RepDev* reps, int n_rep, double* stats)
 {
-    launch(k_ml_stats, dim3(1), dim3(256), 0, st, reps, n_rep, stats);
+    launch(k_ml_stats, dim3(2 * kMlFeat), dim3(256), 0, st, reps, n_rep, stats);
 }
 
 }  // namespace qtb

@@ -29,8 +29,10 @@ __device__ __forceinline__ double bits_f(int32_t b, double) { return __longlong_
 // Bead centroids of the current positions (the update kernel writes them
 // every step; this pass is for init and set_state).
 __global__ void __launch_bounds__(256) k_centroids(const RepDev* __restrict__ reps,
-                                                   const BlockEntry* __restrict__ blocks)
+                                                   const BlockEntry* __restrict__ blocks,
+                                                   const StepRef sync)
 {
+    const int p = step_index(sync).p;
     const BlockEntry be = blocks[blockIdx.x];
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
     const int N = R.N, P = R.P;
@@ -41,7 +43,7 @@ __global__ void __launch_bounds__(256) k_centroids(const RepDev* __restrict__ re
         double s = 0.0;
         for (int b = 0; b < P; ++b) s += R.pos[((size_t)b * 3 + a) * N + ii];
         c[a] = s / P;
-        R.cnow[(size_t)a * N + ii] = c[a];
+        R.cnb[p][(size_t)a * N + ii] = c[a];
     }
     double d2max = 0.0;
     for (int b = 0; b < P; ++b) {
@@ -52,7 +54,7 @@ __global__ void __launch_bounds__(256) k_centroids(const RepDev* __restrict__ re
         }
         d2max = fmax(d2max, d2);
     }
-    R.dev[ii] = sqrt(d2max);
+    R.devn[p][ii] = sqrt(d2max);
 }
 
 // One wavefront per atom i: new reference r_ref_i = current bead centroid,
@@ -60,7 +62,7 @@ __global__ void __launch_bounds__(256) k_centroids(const RepDev* __restrict__ re
 // j = j0 + l; matches are compacted with a ballot, so entries come out in a
 // fixed order (j chunk, image, lane) whatever the timing.
 template <typename T>
-__device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be,
+__device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be, const int p,
                                             int32_t* __restrict__ status, double* tx, double* ty,
                                             double* tz, double* td, double* dmax_s)
 {
@@ -69,18 +71,19 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = be.atom0 + wave;
     const bool active = i < N;    // uniform over the wavefront
-    const double* __restrict__ cx = R.cnow;
-    const double* __restrict__ cy = R.cnow + N;
-    const double* __restrict__ cz = R.cnow + 2 * (size_t)N;
+    const double* __restrict__ cx = R.cnb[p];
+    const double* __restrict__ cy = R.cnb[p] + N;
+    const double* __restrict__ cz = R.cnb[p] + 2 * (size_t)N;
+    const double* __restrict__ devp = R.devn[p];
     double xi = 0.0, yi = 0.0, zi = 0.0, devi = 0.0;
     if (active) {
         xi = cx[i];
         yi = cy[i];
         zi = cz[i];
-        devi = R.dev[i];
-        if (lane < 3) R.rref[(size_t)lane * N + i] = R.cnow[(size_t)lane * N + i];
-        if (lane == 0) R.devb[i] = devi;
-        T4* __restrict__ u = (T4*)R.u + (size_t)i * P;
+        devi = devp[i];
+        if (lane < 3) R.rrefb[p][(size_t)lane * N + i] = R.cnb[p][(size_t)lane * N + i];
+        if (lane == 0) R.devbb[p][i] = devi;
+        T4* __restrict__ u = (T4*)R.ub[p] + (size_t)i * P;
         const T spb = bits_f(R.species[i], T());
         for (int b = lane; b < P; b += 64) {
             T4 v;
@@ -95,7 +98,7 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
     const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
     // image range from the largest pair radius any atom of the block can have
     double dmax = 0.0;
-    for (int j = threadIdx.x; j < N; j += 256) dmax = fmax(dmax, R.dev[j]);
+    for (int j = threadIdx.x; j < N; j += 256) dmax = fmax(dmax, devp[j]);
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
     if (lane == 0) dmax_s[wave] = dmax;
@@ -115,7 +118,7 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
             tx[threadIdx.x] = cx[jl];
             ty[threadIdx.x] = cy[jl];
             tz[threadIdx.x] = cz[jl];
-            td[threadIdx.x] = R.dev[jl];
+            td[threadIdx.x] = devp[jl];
         }
         __syncthreads();
         if (!active) continue;
@@ -170,32 +173,51 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
 template <typename T>
 __global__ void __launch_bounds__(256) k_nlist(const RepDev* __restrict__ reps,
                                                const BlockEntry* __restrict__ blocks,
-                                               int n_entries, int32_t* __restrict__ status)
+                                               int n_entries, int32_t* __restrict__ status,
+                                               const StepRef sync)
 {
     __shared__ double tx[256], ty[256], tz[256], td[256];
     __shared__ double dmax_s[4];
-    if (status[kAnyRebuild] == 0) return;  // nothing to do: one load, then exit
+    const StepIdx si = step_index(sync);
+    if (status[kAnyRebuild + si.f] == 0) return;  // nothing to do: one load, then exit
     for (int e = blockIdx.x; e < n_entries; e += gridDim.x) {
         const BlockEntry be = blocks[e];
         const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
-        if (*R.rebuild == 0) continue;  // uniform over the block
-        nlist_entry<T>(R, be, status, tx, ty, tz, td, dmax_s);
+        if (R.rflag[si.f] == 0) continue;  // uniform over the block
+        nlist_entry<T>(R, be, si.p, status, tx, ty, tz, td, dmax_s);
         __syncthreads();
     }
 }
 
 }  // namespace
 
+namespace {
+// Flag every replica's list for a rebuild at the current step.
+__global__ void k_mark_rebuild(const RepDev* __restrict__ reps, int n_rep,
+                               int32_t* __restrict__ status, const StepRef sync)
+{
+    const int f = step_index(sync).f;
+    for (int r = threadIdx.x; r < n_rep; r += blockDim.x) reps[r].rflag[f] = 1;
+    if (threadIdx.x == 0) status[kAnyRebuild + f] = 1;
+}
+}  // namespace
+
+void launch_mark_rebuild(hipStream_t st, const RepDev* reps, int n_rep, int32_t* status,
+                         StepRef sync)
+{
+    launch(k_mark_rebuild, dim3(1), dim3(256), 0, st, reps, n_rep, status, sync);
+}
+
 void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
-                  int n_blocks, int32_t* status, bool centroids)
+                  int n_blocks, int32_t* status, bool centroids, StepRef sync)
 {
     if (centroids)
-        launch(k_centroids, dim3(n_blocks), dim3(64), 0, st, reps, blocks);
+        launch(k_centroids, dim3(n_blocks), dim3(64), 0, st, reps, blocks, sync);
     const int grid = n_blocks < 256 ? n_blocks : 256;
     if (fp64)
-        launch(k_nlist<double>, dim3(grid), dim3(256), 0, st, reps, blocks, n_blocks, status);
+        launch(k_nlist<double>, dim3(grid), dim3(256), 0, st, reps, blocks, n_blocks, status, sync);
     else
-        launch(k_nlist<float>, dim3(grid), dim3(256), 0, st, reps, blocks, n_blocks, status);
+        launch(k_nlist<float>, dim3(grid), dim3(256), 0, st, reps, blocks, n_blocks, status, sync);
 }
 
 }  // namespace qtb

@@ -39,10 +39,11 @@ struct Layout {
     Region reps, status, rebuild, tiles, taps, ring, zeta, partials, acc, counts, pairtab, clock;
     Region blk_upd, blk_nl, blk_force;
     // surrogate (ml_r_cut > 0)
-    Region blk_mlc, blk_mlm, ml_acc, ml_counts, ml_loss, ml_stats, ml_foff;
+    Region blk_mlc, blk_mlm, ml_acc, ml_counts, ml_loss, ml_stats, ml_foff, ml_wpart;
     struct Per {
-        Region force, u, rref, cnow, dev, devb, r0, eatom, species, homega, nb, nbc, nm, ring;
-        Region mlnb, mlnc, mlrev, mlG, mlaux, mlg, mly, mlfp, mlv, mlu, mladj, mlebar;
+        Region force, r0, eatom, species, homega, nb, nbc, nm, ring;
+        Region u[2], rref[2], cnow[2], dev[2], devb[2];  // by step parity
+        Region mlnb, mlnc, mlrev, mlG, mlaux, mlg, mly, mlfp, mlin, mlnin, mlv, mlu, mladj, mlebar;
     };
     std::vector<Per> per;
     // derived sizes
@@ -54,6 +55,7 @@ struct Layout {
     std::vector<BlockEntry> mlc, mlm;     // surrogate: centre blocks, network tiles
     std::vector<int64_t> foff;            // offsets of the replicas' reference forces
     std::vector<BlockEntry> upd, nl, force;   // force: table of the chosen W
+    int upd_threads = 128;
     std::vector<BlockEntry> force_w[3];        // W = 1, 2, 4
     std::vector<std::pair<int, std::pair<int, int>>> force_groups_w[3];
     std::vector<int> obs_b0_w[3], obs_nb_w[3];
@@ -156,7 +158,7 @@ int estimate_maxml(const qtb_potential* pot, const qtb_options* opt, const qtb_r
     const double n_est = 4.0 / 3.0 * kPi * Rl * Rl * Rl * R.n_atoms / vol;
     int m = (int)std::ceil(1.3 * n_est + 48.0);
     m = (m + 63) / 64 * 64;
-    return std::min(std::max(m, 64), maxnb);
+    return std::min(std::min(std::max(m, 64), maxnb), 512);
 }
 
 void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qtb_options* opt,
@@ -209,11 +211,17 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     }
     {
         // one launch covers every replica
+        int maxP = 1, maxDP = 1;
         for (int r = 0; r < n_rep; ++r) {
-            const int per = update_block_atoms(reps[r].n_dims, reps[r].n_beads);
+            maxP = std::max(maxP, reps[r].n_beads);
+            maxDP = std::max(maxDP, reps[r].n_dims * reps[r].n_beads);
+        }
+        L.upd_threads = update_threads(maxDP);
+        for (int r = 0; r < n_rep; ++r) {
+            const int per = update_block_atoms(reps[r].n_dims, reps[r].n_beads, L.upd_threads);
             for (int a = 0; a < reps[r].n_atoms; a += per) L.upd.push_back({r, a, per, 0});
         }
-        L.upd_groups.push_back({0, {0, (int)L.upd.size()}});
+        L.upd_groups.push_back({maxP, {0, (int)L.upd.size()}});
     }
     for (int r = 0; r < n_rep; ++r)
         for (int a = 0; a < reps[r].n_atoms; a += 4) L.nl.push_back({r, a, 0, 0});
@@ -265,7 +273,7 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     add(cur, L.reps, sizeof(RepDev) * n_rep);
     add(cur, L.status, 64);
     add(cur, L.clock, 64);
-    add(cur, L.rebuild, sizeof(int32_t) * n_rep);
+    add(cur, L.rebuild, sizeof(int32_t) * 3 * n_rep);
     add(cur, L.tiles, sizeof(FirTile) * L.tilev.size());
     add(cur, L.taps, zs * (size_t)L.taps_stride * n_rep);
     add(cur, L.ring, zs * (size_t)L.R * cols);
@@ -285,6 +293,7 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
         add(cur, L.ml_loss, sizeof(double) * n_rep);
         add(cur, L.ml_stats, sizeof(double) * (2 * kMlFeat * 2 + 2));
         add(cur, L.ml_foff, sizeof(int64_t) * n_rep);
+        if (L.ml_train) add(cur, L.ml_wpart, sizeof(float) * (size_t)kWgBlocks * kMlParams);
     }
     for (int r = 0; r < n_rep; ++r) {
         const qtb_replica& R = reps[r];
@@ -297,11 +306,13 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
         add(cur, p.nm, 8 * P * P);
         add(cur, p.ring, 8 * 3 * P);
         if (pair) {
-            add(cur, p.u, 4 * ts * P * N);
-            add(cur, p.rref, 8 * 3 * N);
-            add(cur, p.cnow, 8 * 3 * N);
-            add(cur, p.dev, 8 * N);
-            add(cur, p.devb, 8 * N);
+            for (int q = 0; q < 2; ++q) {
+                add(cur, p.u[q], 4 * ts * P * N);
+                add(cur, p.rref[q], 8 * 3 * N);
+                add(cur, p.cnow[q], 8 * 3 * N);
+                add(cur, p.dev[q], 8 * N);
+                add(cur, p.devb[q], 8 * N);
+            }
             add(cur, p.nb, 4 * ts * N * (size_t)L.maxnb[r]);
             add(cur, p.nbc, 4 * N);
             if (L.ml) {
@@ -314,6 +325,8 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
                 add(cur, p.mlg, 4 * P * N * kMlFeat);
                 add(cur, p.mly, 4 * P * N);
                 add(cur, p.mlfp, 16 * P * N * M);
+                add(cur, p.mlin, 4 * P * N * M);
+                add(cur, p.mlnin, 4 * P * N);
                 if (L.ml_train) {
                     add(cur, p.mlv, 4 * P * N * kMlFeat);
                     add(cur, p.mlu, 4 * P * 3 * N);
@@ -367,6 +380,12 @@ struct qtb_ctx {
     // surrogate
     qtb_ml* ml = nullptr;
     int32_t ml_check_every = 0;
+    // one-kernel steps: a step's closing half-kick is pending (open) between
+    // the step kernels of one qtb_step call; the call ends with a force pass
+    bool open = false;
+    // step of the kernels being recorded: host step (rec_row < 0), or the
+    // device clock (first step of the noise block) + rec_row + rec_extra
+    int rec_row = -1, rec_extra = 0;
     // profiling: event pairs per phase
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -425,6 +444,14 @@ void ml_layout(qtb_ml& m)
     add(cur, m.isd, 4 * 2 * (size_t)kMlFeat);
     add(cur, m.e0, 8 * 2);
     m.total = cur;
+}
+}  // namespace
+
+namespace {
+StepRef step_ref(const qtb_ctx* c)
+{
+    if (c->rec_row < 0) return StepRef{nullptr, c->step};
+    return StepRef{c->at<int64_t>(c->L.clock), (int64_t)c->rec_row + c->rec_extra};
 }
 }  // namespace
 
@@ -600,11 +627,13 @@ void fill_repdev(qtb_ctx* c, int r)
     d.pos = R.d_pos;
     d.vel = R.d_vel;
     d.force = c->at<void>(p.force);
-    d.u = c->pair ? c->at<void>(p.u) : nullptr;
-    d.rref = c->pair ? c->at<double>(p.rref) : nullptr;
-    d.cnow = c->pair ? c->at<double>(p.cnow) : nullptr;
-    d.dev = c->pair ? c->at<double>(p.dev) : nullptr;
-    d.devb = c->pair ? c->at<double>(p.devb) : nullptr;
+    for (int q = 0; q < 2; ++q) {
+        d.ub[q] = c->pair ? c->at<void>(p.u[q]) : nullptr;
+        d.rrefb[q] = c->pair ? c->at<double>(p.rref[q]) : nullptr;
+        d.cnb[q] = c->pair ? c->at<double>(p.cnow[q]) : nullptr;
+        d.devn[q] = c->pair ? c->at<double>(p.dev[q]) : nullptr;
+        d.devbb[q] = c->pair ? c->at<double>(p.devb[q]) : nullptr;
+    }
     d.r0 = c->at<double>(p.r0);
     d.eatom = c->at<double>(p.eatom);
     d.species = c->at<int32_t>(p.species);
@@ -613,7 +642,7 @@ void fill_repdev(qtb_ctx* c, int r)
     d.nb_count = c->pair ? c->at<int32_t>(p.nbc) : nullptr;
     d.nm = c->at<double>(p.nm);
     d.ring = c->at<double>(p.ring);
-    d.rebuild = c->at<int32_t>(c->L.rebuild) + r;
+    d.rflag = c->at<int32_t>(c->L.rebuild) + 3 * r;
     d.dof_off = c->L.dof_off[r];
     d.N = R.n_atoms;
     d.P = R.n_beads;
@@ -646,6 +675,8 @@ void fill_repdev(qtb_ctx* c, int r)
         d.ml_g = c->at<float>(p.mlg);
         d.ml_y = c->at<float>(p.mly);
         d.ml_fpair = c->at<float>(p.mlfp);
+        d.ml_in = c->at<int32_t>(p.mlin);
+        d.ml_nin = c->at<int32_t>(p.mlnin);
         d.maxml = c->L.maxml[r];
         d.ml_rcs = c->opt.ml_r_cut + c->skin;
         if (c->L.ml_train) {
@@ -686,22 +717,23 @@ qtb_status upload_taps(qtb_ctx* c, int r)
 
 // Pair-potential (or oscillator) forces of every replica.  kCompare leaves
 // the rebuild flags alone (the surrogate's forward pass cleared them).
-void launch_plain_forces(qtb_ctx* c, int32_t flags)
+// inline_rebuild: the force kernel rebuilds flagged lists itself (no list
+// kernel launched before it).
+void launch_plain_forces(qtb_ctx* c, int32_t flags, bool inline_rebuild = false)
 {
     const Layout& L = c->L;
     const RepDev* dreps = c->at<RepDev>(L.reps);
     const BlockEntry* fb = c->at<BlockEntry>(L.blk_force);
     double* part = c->at<double>(L.partials);
-    const bool clear = !(flags & kCompare);
+    const int clear = (flags & kCompare) ? 0 : (inline_rebuild ? 2 : 1);
     for (auto& g : L.force_groups) {
         const int b0 = g.second.first, nb = g.second.second - g.second.first;
         if (nb <= 0) continue;
         if (c->pair) {
             const void* tab = c->fp64 ? (const void*)&c->tabd : (const void*)&c->tabf;
             launch_forces_pair(c->st, c->fp64, g.first, c->W, dreps, fb + b0, nb, tab, flags,
-                               part + (size_t)b0 * kNobs,
-                               clear ? c->at<int32_t>(L.rebuild) : nullptr, c->n_rep,
-                               c->at<int32_t>(L.status) + kAnyRebuild);
+                               part + (size_t)b0 * kNobs, clear, c->n_rep,
+                               c->at<int32_t>(L.status), step_ref(c));
         } else {
             launch_forces_harmonic(c->st, c->fp64, dreps, fb + b0, nb, flags,
                                    part + (size_t)b0 * kNobs);
@@ -717,8 +749,8 @@ void launch_ml_forces(qtb_ctx* c, const qtb_ml* m, int32_t flags)
     const RepDev* dreps = c->at<RepDev>(L.reps);
     const MlDev md = m->dev();
     launch_ml_forward(c->st, c->fp64, dreps, md, c->at<BlockEntry>(L.blk_mlc), (int)L.mlc.size(),
-                      c->at<BlockEntry>(L.blk_mlm), (int)L.mlm.size(), c->at<int32_t>(L.rebuild),
-                      c->n_rep, c->at<int32_t>(L.status) + kAnyRebuild);
+                      c->at<BlockEntry>(L.blk_mlm), (int)L.mlm.size(), c->n_rep,
+                      c->at<int32_t>(L.status), step_ref(c));
     const BlockEntry* fb = c->at<BlockEntry>(L.blk_force);
     double* part = c->at<double>(L.partials);
     for (auto& g : L.force_groups) {
@@ -741,17 +773,26 @@ void launch_rebuild(qtb_ctx* c, bool centroids = false)
     if (!c->pair) return;
     const Layout& L = c->L;
     launch_nlist(c->st, c->fp64, c->at<RepDev>(L.reps), c->at<BlockEntry>(L.blk_nl),
-                 (int)L.nl.size(), c->at<int32_t>(L.status), centroids);
+                 (int)L.nl.size(), c->at<int32_t>(L.status), centroids, step_ref(c));
     if (L.ml)  // the surrogate's shorter lists follow every rebuild
         launch_ml_lists(c->st, c->fp64, c->at<RepDev>(L.reps), c->at<BlockEntry>(L.blk_nl),
-                        (int)L.nl.size(), c->at<int32_t>(L.status), false);
+                        (int)L.nl.size(), c->at<int32_t>(L.status), step_ref(c));
+}
+
+// Rebuild every list now (the one-kernel steps keep only the pair
+// potential's lists current; the surrogate's follow this call).
+void force_rebuild(qtb_ctx* c)
+{
+    launch_mark_rebuild(c->st, c->at<RepDev>(c->L.reps), c->n_rep, c->at<int32_t>(c->L.status),
+                        step_ref(c));
+    launch_rebuild(c);
 }
 
 qtb_status refresh_forces(qtb_ctx* c)
 {
     if (c->pair) {
-        launch_fill(c->st, c->at<int32_t>(c->L.rebuild), c->n_rep, 1);
-        launch_fill(c->st, c->at<int32_t>(c->L.status) + kAnyRebuild, 1, 1);
+        launch_mark_rebuild(c->st, c->at<RepDev>(c->L.reps), c->n_rep, c->at<int32_t>(c->L.status),
+                            step_ref(c));
         launch_rebuild(c, true);
     }
     launch_forces(c, 0);
@@ -799,6 +840,8 @@ void prime_ring(qtb_ctx* c)
 // Kernels of one step; row = step index inside the noise block.
 void record_step(qtb_ctx* c, int row, bool sample, bool check)
 {
+    c->rec_row = row;  // the update works on step row, the rest on row + 1
+    c->rec_extra = 0;
     const Layout& L = c->L;
     const size_t zs = c->opt.fir == QTB_FIR_FP64 ? 8 : 4;
     const char* zrow = c->at<char>(L.zeta) + (size_t)row * L.n_cols * zs;
@@ -809,17 +852,22 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
         for (auto& g : L.upd_groups) {
             const int b0 = g.second.first, nb = g.second.second - g.second.first;
             if (nb > 0)
-                launch_update(c->st, c->fp64, c->pair, g.first, dreps, ub + b0, nb, zrow,
-                              c->at<int32_t>(L.status));
+                launch_update(c->st, c->fp64, c->pair, g.first, L.upd_threads, dreps, ub + b0, nb, zrow,
+                              c->at<int32_t>(L.status), step_ref(c));
         }
     }
-    if (c->pair) {
+    c->rec_extra = 1;
+    // the pair potential's force kernel rebuilds flagged lists itself; the
+    // surrogate's lists follow the list kernel
+    const bool inline_rebuild = c->pair && !L.ml && !c->ml;
+    if (c->pair && !inline_rebuild) {
         Phase ph(c, 3, L.ml);
         launch_rebuild(c);
     }
     {
         Phase ph(c, 4, L.force_groups.size() > 1 || c->ml);
-        launch_forces(c, kKick | (sample ? kSample : 0));
+        if (inline_rebuild) launch_plain_forces(c, kKick | (sample ? kSample : 0), true);
+        else launch_forces(c, kKick | (sample ? kSample : 0));
     }
     if (sample) {
         Phase ph(c, 5);
@@ -831,6 +879,94 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials),
                           c->at<double>(L.ml_acc), c->at<int32_t>(L.ml_counts));
     }
+    c->rec_row = -1;
+    c->rec_extra = 0;
+}
+
+bool sample_at(const qtb_ctx* c, int64_t step)
+{
+    return c->opt.obs_every > 0 && ((step + 1) % c->opt.obs_every) == 0;
+}
+
+bool check_at(const qtb_ctx* c, int64_t step)
+{
+    return c->ml && c->ml_check_every > 0 && ((step + 1) % c->ml_check_every) == 0;
+}
+
+// One kernel per step: pair potential, one bead group with G = P for every
+// replica (P = 1, 2, 4, 8), pair-potential forces.
+bool fused_step(const qtb_ctx* c)
+{
+    if (!c->pair || c->ml || !(c->opt.flags & QTB_OPT_FUSE)) return false;
+    if (c->L.force_groups.size() != 1) return false;
+    const int G = c->L.force_groups[0].first;
+    for (const auto& R : c->reps)
+        if (R.n_beads != G) return false;
+    return true;
+}
+
+// Step row of the noise block with one kernel: the forces at the current
+// positions close the previous step (sampling it if asked), then this step's
+// update.  The first step of a run has no pending close: the update alone.
+void record_fused(qtb_ctx* c, int row, bool sample_prev)
+{
+    const Layout& L = c->L;
+    c->rec_row = row;
+    c->rec_extra = 0;
+    const size_t zs = c->opt.fir == QTB_FIR_FP64 ? 8 : 4;
+    const char* zrow = c->at<char>(L.zeta) + (size_t)row * L.n_cols * zs;
+    const RepDev* dreps = c->at<RepDev>(L.reps);
+    if (!c->open) {
+        Phase ph(c, 2);
+        const BlockEntry* ub = c->at<BlockEntry>(L.blk_upd);
+        for (auto& g : L.upd_groups) {
+            const int b0 = g.second.first, nb = g.second.second - g.second.first;
+            if (nb > 0)
+                launch_update(c->st, c->fp64, true, g.first, L.upd_threads, dreps, ub + b0, nb, zrow,
+                              c->at<int32_t>(L.status), step_ref(c));
+        }
+        c->open = true;
+        c->rec_row = -1;
+        return;
+    }
+    {
+        Phase ph(c, 4);
+        const auto& g = L.force_groups[0];
+        const void* tab = c->fp64 ? (const void*)&c->tabd : (const void*)&c->tabf;
+        launch_step_pair(c->st, c->fp64, g.first, c->W, dreps,
+                         c->at<BlockEntry>(L.blk_force) + g.second.first,
+                         g.second.second - g.second.first, tab, sample_prev ? kSample : 0,
+                         c->at<double>(L.partials), c->n_rep, c->at<int32_t>(L.status),
+                         step_ref(c), zrow);
+    }
+    if (sample_prev) {
+        Phase ph(c, 5);
+        launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
+                          c->at<int32_t>(L.counts));
+    }
+    c->rec_row = -1;
+}
+
+// End of a run of one-kernel steps: list check, forces, closing half-kick.
+void close_steps(qtb_ctx* c)
+{
+    if (!c->open) return;
+    const Layout& L = c->L;
+    const bool sample = sample_at(c, c->step - 1);
+    {
+        Phase ph(c, 3);
+        launch_rebuild(c);
+    }
+    {
+        Phase ph(c, 4);
+        launch_forces(c, kKick | (sample ? kSample : 0));
+    }
+    if (sample) {
+        Phase ph(c, 5);
+        launch_obs_reduce(c->st, c->at<RepDev>(L.reps), c->n_rep, c->at<double>(L.partials),
+                          c->at<double>(L.acc), c->at<int32_t>(L.counts));
+    }
+    c->open = false;
 }
 
 // Kernels that open a noise block: advance the clock by K, K new white-noise
@@ -847,15 +983,6 @@ void record_block_start(qtb_ctx* c)
                c->at<int64_t>(L.clock), L.R, L.max_two_nf);
 }
 
-bool sample_at(const qtb_ctx* c, int64_t step)
-{
-    return c->opt.obs_every > 0 && ((step + 1) % c->opt.obs_every) == 0;
-}
-
-bool check_at(const qtb_ctx* c, int64_t step)
-{
-    return c->ml && c->ml_check_every > 0 && ((step + 1) % c->ml_check_every) == 0;
-}
 
 void one_step(qtb_ctx* c)
 {
@@ -870,7 +997,10 @@ void one_step(qtb_ctx* c)
         c->block_start = c->step;
         c->block_row = 0;
     }
-    record_step(c, c->block_row, sample_at(c, c->step), check_at(c, c->step));
+    if (fused_step(c))
+        record_fused(c, c->block_row, sample_at(c, c->step - 1));
+    else
+        record_step(c, c->block_row, sample_at(c, c->step), check_at(c, c->step));
     c->step += 1;
     c->block_row += 1;
 }
@@ -895,7 +1025,9 @@ bool graph_block(qtb_ctx* c)
     if (c->opt.obs_every > 0 && L.K % c->opt.obs_every != 0) return false;
     const int64_t obs_phase = c->opt.obs_every > 0 ? c->step % c->opt.obs_every : 0;
     const int64_t chk_phase = (c->ml && c->ml_check_every > 0) ? c->step % c->ml_check_every : 0;
-    const std::pair<int64_t, int64_t> key{obs_phase, chk_phase};
+    const bool fused = fused_step(c);
+    // the sequence also depends on whether a step's close is pending
+    const std::pair<int64_t, int64_t> key{obs_phase, chk_phase * 4 + (fused ? 2 : 0) + (c->open ? 1 : 0)};
     hipGraphExec_t exec = nullptr;
     for (auto& g : c->graphs)
         if (g.first == key) exec = g.second;
@@ -908,8 +1040,12 @@ bool graph_block(qtb_ctx* c)
             return false;
         }
         record_block_start(c);
-        for (int r = 0; r < L.K; ++r)
-            record_step(c, r, sample_at(c, c->step + r), check_at(c, c->step + r));
+        const bool open0 = c->open;
+        for (int r = 0; r < L.K; ++r) {
+            if (fused) record_fused(c, r, sample_at(c, c->step + r - 1));
+            else record_step(c, r, sample_at(c, c->step + r), check_at(c, c->step + r));
+        }
+        c->open = open0;  // capture records, it does not run
         if (hipStreamEndCapture(c->st, &g) != hipSuccess || !g ||
             hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
@@ -931,6 +1067,7 @@ bool graph_block(qtb_ctx* c)
     c->block_start = c->step;
     c->block_row = L.K;
     c->step += L.K;
+    if (fused) c->open = true;
     return true;
 }
 
@@ -1188,6 +1325,7 @@ qtb_status qtb_step(qtb_ctx* c, int64_t n_steps)
         one_step(c);
         left -= 1;
     }
+    close_steps(c);
     QTB_HIP(c, hipGetLastError());
     return QTB_OK;
 }
@@ -1520,6 +1658,7 @@ qtb_status qtb_ml_attach(qtb_ctx* c, qtb_ml* m, int32_t check_every)
         c->tuned = false;
     }
     // forces of the new provider for the next half-kick
+    if (m) force_rebuild(c);
     launch_forces(c, 0);
     QTB_HIP(c, hipGetLastError());
     return read_status(c);
@@ -1531,7 +1670,7 @@ qtb_status qtb_ml_evaluate(qtb_ctx* c, qtb_ml* m, int32_t replica, double* h_for
     qtb_status s = ml_ready(c, m);
     if (s) return s;
     if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
-    launch_rebuild(c);  // no-op unless a rebuild is pending
+    force_rebuild(c);
     launch_ml_forces(c, m, kEvaluate);
     QTB_HIP(c, hipGetLastError());
     const qtb_replica& R = c->reps[replica];
@@ -1569,7 +1708,7 @@ qtb_status qtb_ml_fit_norm(qtb_ctx* c, qtb_ml* m, const double* d_eref)
     qtb_status s = ml_ready(c, m);
     if (s) return s;
     if (!d_eref) return fail(c, QTB_E_INVALID, "d_eref is NULL");
-    launch_rebuild(c);
+    force_rebuild(c);
     launch_ml_forces(c, m, kEvaluate);  // descriptors of every centre
     launch_ml_stats(c->st, c->at<RepDev>(c->L.reps), c->n_rep, c->at<double>(c->L.ml_stats));
     std::vector<double> st(2 * kMlFeat * 2 + 2), eref(c->n_rep);
@@ -1615,13 +1754,15 @@ qtb_status qtb_ml_train_step(qtb_ctx* c, qtb_ml* m, const double* d_eref, const 
     const Layout& L = c->L;
     const RepDev* dreps = c->at<RepDev>(L.reps);
     const MlDev md = m->dev();
-    launch_rebuild(c);
+    force_rebuild(c);
     launch_ml_forces(c, m, kEvaluate);
     launch_ml_loss(c->st, dreps, c->n_rep, d_eref, d_fref, c->at<int64_t>(L.ml_foff), w_E, w_F,
                    n_tot, c->at<double>(L.ml_loss));
-    launch_ml_jvp(c->st, c->fp64, dreps, md, c->at<BlockEntry>(L.blk_mlc), (int)L.mlc.size());
+    launch_ml_jvp(c->st, c->fp64, dreps, md, c->at<BlockEntry>(L.blk_mlc), (int)L.mlc.size(),
+                  step_ref(c));
     launch_ml_train_mlp(c->st, dreps, md, c->at<BlockEntry>(L.blk_mlm), (int)L.mlm.size());
-    launch_ml_wgrad(c->st, dreps, c->n_rep, md, m->at<float>(m->grad));
+    launch_ml_wgrad(c->st, dreps, md, c->at<BlockEntry>(L.blk_mlm), (int)L.mlm.size(),
+                    c->at<float>(L.ml_wpart), m->at<float>(m->grad));
     if (update) {
         m->t += 1;
         const float b1 = 0.9f, b2 = 0.999f;

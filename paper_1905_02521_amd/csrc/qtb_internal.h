@@ -51,11 +51,14 @@ struct RepDev {
     double* pos;         // [P][dims][N]
     double* vel;         // [P][dims][N]
     void* force;         // T [P][dims][N]
-    void* u;             // T4 [N][P]: position minus reference, species bits in .w
-    double* cnow;        // [3][N] bead centroids of the current step (update kernel)
-    double* dev;         // [N] largest bead-to-centroid distance now
-    double* devb;        // [N] the same at the last list build
-    double* rref;        // [3][N] reference positions (bead centroids at the last build)
+    // Data that other atoms read are kept twice, by step parity (sync step
+    // counter & 1), so one kernel can read a step's values while it writes
+    // the next step's:
+    void* ub[2];         // T4 [N][P]: position minus reference, species bits in .w
+    double* cnb[2];      // [3][N] bead centroids
+    double* devn[2];     // [N] largest bead-to-centroid distance
+    double* rrefb[2];    // [3][N] reference positions (bead centroids at the last build)
+    double* devbb[2];    // [N] bead spread at the last build
     double* r0;          // [P][dims][N] positions given at init / set_state
     double* eatom;       // [P][N] per-atom energies (evaluate mode)
     const int32_t* species;  // [N]
@@ -64,7 +67,7 @@ struct RepDev {
     int32_t* nb_count;       // [N]
     const double* nm;        // [P][P] orthonormal normal-mode matrix C[s][k]
     const double* ring;      // [3][P]: cos(w h), sin(w h)/w, -w sin(w h), h = dt/2
-    int32_t* rebuild;        // neighbour-list rebuild flag
+    int32_t* rflag;          // [3] neighbour-list rebuild flags, by step mod 3
     int64_t dof_off;         // first column in the global noise arrays
     int64_t step_off;        // replica step = global step + step_off
     int32_t N, P, dims, maxnb;
@@ -85,7 +88,9 @@ struct RepDev {
     float* ml_aux;        // [P][N][144] A1 [2][8][3], A2 [2][8][6]
     float* ml_g;          // [P][N][96] dE_i/dG_i
     float* ml_y;          // [P][N] atomic energies without e0
-    float* ml_fpair;      // float4 [P][N][maxml]: dE_i/dd_ij per list entry
+    float* ml_fpair;      // float4 [P][N][maxml]: dE_i/dd_ij per list entry (in range)
+    int32_t* ml_in;       // [P][N][maxml]: list slots within r_ml this step
+    int32_t* ml_nin;      // [P][N]
     float* ml_v;          // [P][N][96] training: J (u_j - u_i)
     float* ml_u;          // [P][3][N] training: dL/dF
     float* ml_adj;        // [P][N][kMlAdj] training: per-centre adjoint rows
@@ -115,6 +120,8 @@ constexpr int kMlParams = kMlSpecies * kMlParamsSp;
 // adjoint row of one centre (training): xd[96] z1b[64] z1db[64] h1[64]
 // h1d[64] z2b[64] z2db[64] t3[64] e[1] (pad to 576)
 constexpr int kMlAdj = 576;
+// workgroups per species of the weight-gradient sums (partials kept apart)
+constexpr int kWgBlocks = 64;
 
 // Model as the kernels see it (device pointers into the model workspace).
 struct MlDev {
@@ -145,8 +152,27 @@ struct FirTile {
 };
 
 enum StatusBits : int32_t { kStatusNonfinite = 1, kStatusNbOverflow = 2, kStatusMlList = 8 };
-// status[kAnyRebuild]: some replica needs its neighbour list rebuilt
+// status[kAnyRebuild + step mod 3]: some replica needs its neighbour list rebuilt
 constexpr int kAnyRebuild = 4;
+
+// Step bookkeeping shared by the kernels: the step n of the positions a
+// kernel works on is *clk + off (clk: the device noise clock, the first step
+// of the current noise block, so a captured block replays with the right
+// steps) or off alone (clk null: launches outside a block).
+struct StepRef {
+    const int64_t* clk;
+    int64_t off;
+};
+struct StepIdx {
+    int p;  // parity n & 1: which copy of the double-kept data is current
+    int f;  // n mod 3: which rebuild flag is current
+};
+__device__ __forceinline__ StepIdx step_index(const StepRef r)
+{
+    const int64_t n = (r.clk ? *r.clk : 0) + r.off;
+    const int64_t m = n % 3;
+    return StepIdx{(int)(n & 1), (int)(m < 0 ? m + 3 : m)};
+}
 
 // Kernel-side flags of the force kernels.
 // kCompare: leave force and state untouched, accumulate |F - F_stored|^2 and
@@ -187,18 +213,30 @@ void launch_fir(hipStream_t st, int mode, int K, const FirTile* tiles, int n_til
 int fir_pad();
 size_t fir_lds_bytes(int mode, int max_two_nf);
 // update.hip
-void launch_update(hipStream_t st, bool fp64, bool pair, int P, const RepDev* reps,
-                   const BlockEntry* blocks, int n_blocks, const void* zeta_row,
-                   int32_t* status);
-int update_block_atoms(int dims, int P);
+// P: the largest bead count, threads: update_threads(largest dims P).
+void launch_update(hipStream_t st, bool fp64, bool pair, int P, int threads,
+                   const RepDev* reps, const BlockEntry* blocks, int n_blocks,
+                   const void* zeta_row, int32_t* status, StepRef sync);
+int update_threads(int max_dims_beads);
+int update_block_atoms(int dims, int P, int threads);
 // nlist.hip
 void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
-                  int n_blocks, int32_t* status, bool centroids);
+                  int n_blocks, int32_t* status, bool centroids, StepRef sync);
+void launch_mark_rebuild(hipStream_t st, const RepDev* reps, int n_rep, int32_t* status,
+                         StepRef sync);
 // forces.hip
+// clear: reset this step's rebuild flags (the list is up to date).
 void launch_forces_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* reps,
                         const BlockEntry* blocks, int n_blocks, const void* table,
-                        int32_t flags, double* partials, int32_t* rebuild_clear, int n_rep,
-                        int32_t* rebuild_any);
+                        int32_t flags, double* partials, int clear, int n_rep,
+                        int32_t* status, StepRef sync);
+// One kernel per step (pair potential, P <= 8, bead group G = P): rebuild
+// the lists if flagged, forces, closing half-kick, sampling, then the next
+// step's opening half-kick, normal-mode A-O-A with zeta_row.
+void launch_step_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* reps,
+                      const BlockEntry* blocks, int n_blocks, const void* table, int32_t flags,
+                      double* partials, int n_rep, int32_t* status, StepRef sync,
+                      const void* zeta_row);
 void launch_forces_harmonic(hipStream_t st, bool fp64, const RepDev* reps,
                             const BlockEntry* blocks, int n_blocks, int32_t flags,
                             double* partials);
@@ -207,10 +245,10 @@ void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const doub
 void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value);
 // ml.hip
 void launch_ml_lists(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* nl_blocks,
-                     int n_nl, int32_t* status, bool force);
+                     int n_nl, int32_t* status, StepRef sync);
 void launch_ml_forward(hipStream_t st, bool fp64, const RepDev* reps, const MlDev& m,
                        const BlockEntry* cblocks, int n_cblocks, const BlockEntry* mblocks,
-                       int n_mblocks, int32_t* rebuild_clear, int n_rep, int32_t* rebuild_any);
+                       int n_mblocks, int n_rep, int32_t* status, StepRef sync);
 // apb: atoms per block of the force table in use (4 / waves per atom)
 void launch_ml_gather(hipStream_t st, bool fp64, int G, int apb, const RepDev* reps,
                       const MlDev& m, const BlockEntry* blocks, int n_blocks, int32_t flags,
@@ -219,11 +257,12 @@ void launch_ml_loss(hipStream_t st, const RepDev* reps, int n_rep, const double*
                     const double* fref, const int64_t* fref_off, double w_E, double w_F,
                     double n_atoms_total, double* loss_parts);
 void launch_ml_jvp(hipStream_t st, bool fp64, const RepDev* reps, const MlDev& m,
-                   const BlockEntry* cblocks, int n_cblocks);
+                   const BlockEntry* cblocks, int n_cblocks, StepRef sync);
 void launch_ml_train_mlp(hipStream_t st, const RepDev* reps, const MlDev& m,
                          const BlockEntry* mblocks, int n_mblocks);
-void launch_ml_wgrad(hipStream_t st, const RepDev* reps, int n_rep, const MlDev& m,
-                     float* grad);
+// part: kWgBlocks x kMlParams floats of scratch (partial sums)
+void launch_ml_wgrad(hipStream_t st, const RepDev* reps, const MlDev& m,
+                     const BlockEntry* mblocks, int n_mblocks, float* part, float* grad);
 void launch_ml_adam(hipStream_t st, float* master, uint16_t* wq, float* mom1, float* mom2,
                     const float* grad, int n, float lr, float b1, float b2, float eps,
                     float c1, float c2);

@@ -17,6 +17,7 @@
 // list reference (FP32 in FP32 mode): they are written here, and the
 // largest component decides whether the list must be rebuilt.
 #include "qtb_internal.h"
+#include "ring_step.h"
 
 namespace qtb {
 namespace {
@@ -37,21 +38,27 @@ __device__ __forceinline__ double bits_as<double>(int32_t b) { return __longlong
 // contiguous run of the [P][dims][N] arrays; the P x P normal-mode
 // transforms read the partner beads of the same (atom, component) from LDS.
 // A block holds A = BlockEntry::group atoms (A dims P <= kUpdThreads).
+// 384 threads (P up to 64 beads in 3D).  Smaller workgroups, several per
+// compute unit, measured slower on gfx950 for the 4096-atom x 8-bead case.
 constexpr int kUpdThreads = 384;
 
 template <typename T, bool PAIR>
 __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict__ reps,
                                                         const BlockEntry* __restrict__ blocks,
                                                         const T* __restrict__ zeta_row,
-                                                        int32_t* __restrict__ status)
+                                                        int32_t* __restrict__ status,
+                                                        const StepRef sync)
 {
     using T4 = typename Vec4<T>::type;
     __shared__ double xr[kUpdThreads], xv[kUpdThreads];
-    __shared__ double Cs[64 * 64];
+    extern __shared__ double Cs[];  // [P][P], dynamic
     __shared__ double cen[kUpdThreads / 3][3];
     __shared__ int flags;
     const BlockEntry be = blocks[blockIdx.x];
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+    const StepIdx si = step_index(sync);
+    const int pin = si.p, pout = si.p ^ 1;        // this step's data, the next step's
+    const int fnext = si.f == 2 ? 0 : si.f + 1;   // (step + 1) mod 3
     const int N = R.N, P = R.P, dims = R.dims;
     const int A = be.group;
     const int t = threadIdx.x;
@@ -72,13 +79,17 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
         const double f = (double)((const T*)R.force)[idx];
         z = (double)zeta_row[R.dof_off + ((int64_t)dims * i + a) * P + s];
         if (PAIR && a == 0) {
-            for (int a2 = 0; a2 < 3; ++a2) ref3[a2] = R.rref[(size_t)a2 * N + i];
-            devb = R.devb[i];
+            for (int a2 = 0; a2 < 3; ++a2) ref3[a2] = R.rrefb[pin][(size_t)a2 * N + i];
+            devb = R.devbb[pin][i];
+            if (s == 0) {  // the references carry over to the next step
+                for (int a2 = 0; a2 < 3; ++a2) R.rrefb[pout][(size_t)a2 * N + i] = ref3[a2];
+                R.devbb[pout][i] = devb;
+            }
         }
         double kick = R.kick[0];
 #pragma unroll
         for (int q = 1; q < kMaxSpecies; ++q) kick = (sp == q) ? R.kick[q] : kick;
-        v += kick * f;
+        v = half_kick(v, kick, f);
     }
     xr[t] = r;
     xv[t] = v;
@@ -89,19 +100,15 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
     if (active) {
         for (int b = 0; b < P; ++b) {
             const double c = Cs[b * P + s];
-            q += c * xr[base + b * A];
-            pm += c * xv[base + b * A];
+            q = nm_acc(q, c, xr[base + b * A]);
+            pm = nm_acc(pm, c, xv[base + b * A]);
         }
         const int k = s;  // this thread now holds mode k (its noise value z)
         const double cw = R.ring[k], sw = R.ring[P + k], ws = R.ring[2 * P + k];
-        const double q1 = cw * q + sw * pm;
-        double p1 = ws * q + cw * pm;
         double sig = R.sigma[0];
 #pragma unroll
         for (int qq = 1; qq < kMaxSpecies; ++qq) sig = (sp == qq) ? R.sigma[qq] : sig;
-        p1 = R.c1 * p1 + sig * z;
-        q = cw * q1 + sw * p1;
-        pm = ws * q1 + cw * p1;
+        mode_aoa(q, pm, cw, sw, ws, R.c1, sig, z);
     }
     __syncthreads();
     xr[t] = q;
@@ -111,8 +118,8 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
         double rn = 0.0, vn = 0.0;
         for (int k = 0; k < P; ++k) {
             const double c = Cs[s * P + k];
-            rn += c * xr[base + k * A];
-            vn += c * xv[base + k * A];
+            rn = nm_acc(rn, c, xr[base + k * A]);
+            vn = nm_acc(vn, c, xv[base + k * A]);
         }
         r = rn;
         v = vn;
@@ -130,7 +137,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
             double c = 0.0;
             for (int b = 0; b < P; ++b) c += xr[base + b * A];
             c /= P;
-            R.cnow[(size_t)a * N + i] = c;
+            R.cnb[pout][(size_t)a * N + i] = c;
             cen[il][a] = c;
         }
         __syncthreads();
@@ -140,15 +147,15 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
                 const double x = xr[(a2 * P + s) * A + il];
                 u3[a2] = x - ref3[a2];
                 const double dc = x - cen[il][a2];
-                u2 += u3[a2] * u3[a2];
-                d2 += dc * dc;
+                u2 = nm_acc(u2, u3[a2], u3[a2]);
+                d2 = nm_acc(d2, dc, dc);
             }
             T4 val;
             val.x = (T)u3[0];
             val.y = (T)u3[1];
             val.z = (T)u3[2];
             val.w = bits_as<T>(sp);
-            ((T4*)R.u)[(size_t)i * P + s] = val;
+            ((T4*)R.ub[pout])[(size_t)i * P + s] = val;
             xv[t] = d2;
             const double lim = devb + R.half_skin;
             if (!(u2 <= lim * lim)) atomicOr(&flags, 8);
@@ -157,14 +164,14 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
         if (t < A && be.atom0 + t < N) {
             double d2 = 0.0;
             for (int b = 0; b < P; ++b) d2 = fmax(d2, xv[b * A + t]);
-            R.dev[be.atom0 + t] = sqrt(d2);
+            R.devn[pout][be.atom0 + t] = sqrt(d2);
         }
     }
     __syncthreads();
     if (t == 0 && flags) {
         if (flags & 8) {
-            atomicOr(R.rebuild, 1);
-            atomicOr(status + kAnyRebuild, 1);
+            atomicOr(R.rflag + fnext, 1);
+            atomicOr(status + kAnyRebuild + fnext, 1);
         }
         if (flags & kStatusNonfinite) atomicOr(status, kStatusNonfinite);
     }
@@ -173,22 +180,26 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
 }  // namespace
 
 // Block tables hold A atoms per entry (in .group), A dims P <= kUpdThreads.
-int update_block_atoms(int dims, int P)
+int update_threads(int) { return kUpdThreads; }
+
+int update_block_atoms(int dims, int P, int threads)
 {
-    int A = kUpdThreads / (dims * P);
+    int A = threads / (dims * P);
     return A < 1 ? 1 : A;
 }
 
-void launch_update(hipStream_t st, bool fp64, bool pair, int, const RepDev* reps,
-                   const BlockEntry* blocks, int n_blocks, const void* zeta_row, int32_t* status)
+void launch_update(hipStream_t st, bool fp64, bool pair, int P, int threads,
+                   const RepDev* reps, const BlockEntry* blocks, int n_blocks,
+                   const void* zeta_row, int32_t* status, StepRef sync)
 {
-    const dim3 g(n_blocks), b(kUpdThreads);
+    const dim3 g(n_blocks), b(threads);
+    const uint32_t lds = 8u * (uint32_t)P * (uint32_t)P;  // the largest P of the launch
     if (fp64) {
-        if (pair) launch((k_update<double, true>), g, b, 0, st, reps, blocks, (const double*)zeta_row, status);
-        else launch((k_update<double, false>), g, b, 0, st, reps, blocks, (const double*)zeta_row, status);
+        if (pair) launch((k_update<double, true>), g, b, lds, st, reps, blocks, (const double*)zeta_row, status, sync);
+        else launch((k_update<double, false>), g, b, lds, st, reps, blocks, (const double*)zeta_row, status, sync);
     } else {
-        if (pair) launch((k_update<float, true>), g, b, 0, st, reps, blocks, (const float*)zeta_row, status);
-        else launch((k_update<float, false>), g, b, 0, st, reps, blocks, (const float*)zeta_row, status);
+        if (pair) launch((k_update<float, true>), g, b, lds, st, reps, blocks, (const float*)zeta_row, status, sync);
+        else launch((k_update<float, false>), g, b, lds, st, reps, blocks, (const float*)zeta_row, status, sync);
     }
 }
 

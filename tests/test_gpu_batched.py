@@ -35,11 +35,11 @@ def make_reps(specs, seed=5):
     return reps
 
 
-def ctx_for(reps, prec, fir, autotune=False, obs_every=0):
+def ctx_for(reps, prec, fir, autotune=False, obs_every=0, fuse=False):
     p = W.mgo_potential(skin=0.5)
     c = qtb.Context(qtb.pair_potential_dict(p), [r for r, _ in reps], units_dict(False),
                     prec=prec, fir=fir, fir_block_K=64, obs_every=obs_every,
-                    max_two_nf=max(t for _, t in reps), autotune=autotune)
+                    max_two_nf=max(t for _, t in reps), autotune=autotune, fuse=fuse)
     for k, (r, t) in enumerate(reps):
         if r.noise:
             c.build_filter(k, r.noise, t)
