@@ -44,7 +44,8 @@ PEAK_HBM_GBS = 8000.0
 
 
 # Sources whose change makes a stored HBM-traffic record of the pair kernel stale.
-FORCE_SOURCES = ("paper_1905_02521_amd/csrc/forces.hip", "paper_1905_02521_amd/csrc/qtb_internal.h")
+FORCE_SOURCES = ("paper_1905_02521_amd/csrc/forces.hip", "paper_1905_02521_amd/csrc/qtb_internal.h",
+                 "paper_1905_02521_amd/csrc/force_epilogue.h", "paper_1905_02521_amd/csrc/ring_step.h")
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -123,6 +124,19 @@ def rocprof_summary(dirs):
             m = sum(v) / len(v)
             sb = f"{m * 1024 * scale[c]:.4g}" if c in scale else ""
             out.append(f"| {k} | {c} | {len(v)} | {m:.6g} | {sb} |")
+        # VALU activity of the pair kernel (rocprof's VALUBusy / VALUUtilization;
+        # GRBM_GUI_ACTIVE is summed over the 8 XCDs, so one XCD's busy cycles
+        # are the sum / 8)
+        fk = [k for (k, c) in counters if k.startswith("k_force_pair")]
+        have = {c for (k, c) in counters if fk and k == fk[0]}
+        if fk and {"SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE", "SQ_THREAD_CYCLES_VALU"} <= have:
+            k = fk[0]
+            mean = lambda c: sum(counters[(k, c)]) / len(counters[(k, c)])
+            busy = 100.0 * mean("SQ_ACTIVE_INST_VALU") / 256 / (mean("GRBM_GUI_ACTIVE") / 8)
+            util = 100.0 * mean("SQ_THREAD_CYCLES_VALU") / (mean("SQ_ACTIVE_INST_VALU") * 64)
+            out.append("")
+            out.append(f"{k}: VALUBusy {busy:.1f} % (VALU-active cycles per CU over one XCD's busy "
+                       f"cycles), VALUUtilization {util:.1f} % (active lanes per VALU cycle)")
         if scale:
             out.append("")
             out.append("copy calibration (bytes per KiB-unit of the counter): " +
