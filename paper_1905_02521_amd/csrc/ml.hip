@@ -123,7 +123,12 @@ __global__ void __launch_bounds__(256) k_ml_list(const RepDev* __restrict__ reps
 }
 
 // Slot of entry (i -> j, D) in j's list: (j -> i, -D).  Both come from the
-// same FP64 displacement with its sign flipped, so the match is exact.
+// same FP64 displacement with its sign flipped, so the match is exact.  The
+// plain list (and so this filtered one) holds its entries in ascending
+// 64-atom chunks of the neighbour index, so a binary search finds i's chunk in
+// j's list and a short scan of that chunk the entry; a full scan backs it up.
+// One wavefront per atom over the whole block table: this runs only after a
+// rebuild, and its dependent loads need the occupancy.
 template <typename T>
 __global__ void __launch_bounds__(256) k_ml_rev(const RepDev* __restrict__ reps,
                                                 const BlockEntry* __restrict__ blocks,
@@ -142,17 +147,33 @@ __global__ void __launch_bounds__(256) k_ml_rev(const RepDev* __restrict__ reps,
         if (i >= R.N) continue;
         const T4* __restrict__ ent = (const T4*)R.ml_nb;
         const int cnt = R.ml_nc[i];
+        const int key = i >> 6;
         for (int k = lane; k < cnt; k += 64) {
             const T4 E = ent[(size_t)i * R.maxml + k];
             const int j = ebits<T>(E);
             const int cj = R.ml_nc[j];
+            const T4* __restrict__ lj = ent + (size_t)j * R.maxml;
+            int lo = 0, hi = cj;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((ebits<T>(lj[mid]) >> 6) < key)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
             int found = -1;
-            for (int q = 0; q < cj; ++q) {
-                const T4 F = ent[(size_t)j * R.maxml + q];
-                if (ebits<T>(F) == i && F.x == -E.x && F.y == -E.y && F.z == -E.z) {
+            for (int q = lo; q < cj; ++q) {
+                const T4 F = lj[q];
+                const int m = ebits<T>(F);
+                if ((m >> 6) != key) break;
+                if (m == i && F.x == -E.x && F.y == -E.y && F.z == -E.z) {
                     found = q;
                     break;
                 }
+            }
+            for (int q = 0; found < 0 && q < cj; ++q) {
+                const T4 F = lj[q];
+                if (ebits<T>(F) == i && F.x == -E.x && F.y == -E.y && F.z == -E.z) found = q;
             }
             R.ml_rev[(size_t)i * R.maxml + k] = found < 0 ? 0 : found;
             if (found < 0) atomicOr(status, kStatusMlList);
@@ -1098,10 +1119,10 @@ void launch_ml_lists(hipStream_t st, bool fp64, const RepDev* reps, const BlockE
     if (grid <= 0) return;
     if (fp64) {
         launch(k_ml_list<double>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status, sync);
-        launch(k_ml_rev<double>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status, sync);
+        launch(k_ml_rev<double>, dim3(n_nl), dim3(256), 0, st, reps, nl_blocks, n_nl, status, sync);
     } else {
         launch(k_ml_list<float>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status, sync);
-        launch(k_ml_rev<float>, dim3(grid), dim3(256), 0, st, reps, nl_blocks, n_nl, status, sync);
+        launch(k_ml_rev<float>, dim3(n_nl), dim3(256), 0, st, reps, nl_blocks, n_nl, status, sync);
     }
 }
 

@@ -779,15 +779,6 @@ void launch_rebuild(qtb_ctx* c, bool centroids = false)
                         (int)L.nl.size(), c->at<int32_t>(L.status), step_ref(c));
 }
 
-// Rebuild every list now (the one-kernel steps keep only the pair
-// potential's lists current; the surrogate's follow this call).
-void force_rebuild(qtb_ctx* c)
-{
-    launch_mark_rebuild(c->st, c->at<RepDev>(c->L.reps), c->n_rep, c->at<int32_t>(c->L.status),
-                        step_ref(c));
-    launch_rebuild(c);
-}
-
 qtb_status refresh_forces(qtb_ctx* c)
 {
     if (c->pair) {
@@ -897,7 +888,9 @@ bool check_at(const qtb_ctx* c, int64_t step)
 // replica (P = 1, 2, 4, 8), pair-potential forces.
 bool fused_step(const qtb_ctx* c)
 {
-    if (!c->pair || c->ml || !(c->opt.flags & QTB_OPT_FUSE)) return false;
+    // (contexts with surrogate buffers keep the separate list kernel, whose
+    // rebuilds also refresh the surrogate's lists)
+    if (!c->pair || c->ml || c->L.ml || !(c->opt.flags & QTB_OPT_FUSE)) return false;
     if (c->L.force_groups.size() != 1) return false;
     const int G = c->L.force_groups[0].first;
     for (const auto& R : c->reps)
@@ -1658,7 +1651,7 @@ qtb_status qtb_ml_attach(qtb_ctx* c, qtb_ml* m, int32_t check_every)
         c->tuned = false;
     }
     // forces of the new provider for the next half-kick
-    if (m) force_rebuild(c);
+    if (m) launch_rebuild(c);
     launch_forces(c, 0);
     QTB_HIP(c, hipGetLastError());
     return read_status(c);
@@ -1670,7 +1663,7 @@ qtb_status qtb_ml_evaluate(qtb_ctx* c, qtb_ml* m, int32_t replica, double* h_for
     qtb_status s = ml_ready(c, m);
     if (s) return s;
     if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
-    force_rebuild(c);
+    launch_rebuild(c);  // no-op unless a rebuild is pending
     launch_ml_forces(c, m, kEvaluate);
     QTB_HIP(c, hipGetLastError());
     const qtb_replica& R = c->reps[replica];
@@ -1708,7 +1701,7 @@ qtb_status qtb_ml_fit_norm(qtb_ctx* c, qtb_ml* m, const double* d_eref)
     qtb_status s = ml_ready(c, m);
     if (s) return s;
     if (!d_eref) return fail(c, QTB_E_INVALID, "d_eref is NULL");
-    force_rebuild(c);
+    launch_rebuild(c);
     launch_ml_forces(c, m, kEvaluate);  // descriptors of every centre
     launch_ml_stats(c->st, c->at<RepDev>(c->L.reps), c->n_rep, c->at<double>(c->L.ml_stats));
     std::vector<double> st(2 * kMlFeat * 2 + 2), eref(c->n_rep);
@@ -1754,7 +1747,7 @@ qtb_status qtb_ml_train_step(qtb_ctx* c, qtb_ml* m, const double* d_eref, const 
     const Layout& L = c->L;
     const RepDev* dreps = c->at<RepDev>(L.reps);
     const MlDev md = m->dev();
-    force_rebuild(c);
+    launch_rebuild(c);
     launch_ml_forces(c, m, kEvaluate);
     launch_ml_loss(c->st, dreps, c->n_rep, d_eref, d_fref, c->at<int64_t>(L.ml_foff), w_E, w_F,
                    n_tot, c->at<double>(L.ml_loss));
