@@ -206,7 +206,9 @@ qtb_status qtb_step(qtb_ctx *ctx, int64_t n_steps);
 
 /* Synchronise the stream and return the observables of one replica.
  * Returns QTB_E_NONFINITE if a NaN/Inf was found in any state since the last
- * check, QTB_E_NOMEM if a neighbour list overflowed. */
+ * check or a bead spread grew past the list search's limit of 8 periodic
+ * images per direction (a diverged trajectory), QTB_E_NOMEM if a neighbour
+ * list overflowed. */
 qtb_status qtb_observables(qtb_ctx *ctx, int32_t replica, qtb_obs *out);
 
 /* Copy a replica's state to / from host arrays [P][n_dims][N]; set_state

@@ -105,8 +105,10 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
     __syncthreads();
     dmax = fmax(fmax(dmax_s[0], dmax_s[1]), fmax(dmax_s[2], dmax_s[3]));
     const double Rmax = R.r_cs + devi + dmax;
-    const int mx = (int)ceil(Rmax * iLx - 0.5), my = (int)ceil(Rmax * iLy - 0.5),
-              mz = (int)ceil(Rmax * iLz - 0.5);
+    bool over = false;
+    const int mx = image_range(Rmax, iLx, over), my = image_range(Rmax, iLy, over),
+              mz = image_range(Rmax, iLz, over);
+    if (over && active && lane == 0) atomicOr(status, kStatusRange);
     T4* __restrict__ ent = (T4*)R.nb_entries + (size_t)i * R.maxnb;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int cnt = 0;

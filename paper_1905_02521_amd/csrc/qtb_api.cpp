@@ -797,6 +797,9 @@ qtb_status read_status(qtb_ctx* c)
     QTB_HIP(c, hipMemcpyAsync(st, c->at<int32_t>(c->L.status), sizeof(st), hipMemcpyDeviceToHost,
                               c->st));
     QTB_HIP(c, hipStreamSynchronize(c->st));
+    if (st[0] & kStatusRange)  // first: a diverged state also overflows the lists
+        return fail(c, QTB_E_NONFINITE,
+                    "diverged state: pair range beyond the periodic-image limit of the list search");
     if (st[0] & kStatusNbOverflow)
         return fail(c, QTB_E_NOMEM, "neighbour list overflow: density above the planned maximum");
     if (st[0] & kStatusMlList)

@@ -151,7 +151,29 @@ struct FirTile {
     int32_t pad;
 };
 
-enum StatusBits : int32_t { kStatusNonfinite = 1, kStatusNbOverflow = 2, kStatusMlList = 8 };
+enum StatusBits : int32_t {
+    kStatusNonfinite = 1,
+    kStatusNbOverflow = 2,
+    kStatusMlList = 8,
+    kStatusRange = 16,  // pair range beyond kMaxImages periodic images (diverged state)
+};
+// Periodic images searched per direction when a list is built: enough for
+// any box wider than r_cut / 8; a larger range (a diverging trajectory's
+// bead spread) is clamped to it and reported through kStatusRange, so the
+// search always ends.
+constexpr int kMaxImages = 8;
+
+// Image range ceil(R / L - 1/2) along one direction, clamped to
+// [0, kMaxImages] (also for non-finite R); over is set when clamped.
+__device__ __forceinline__ int image_range(double R, double inv_L, bool& over)
+{
+    const double m = ceil(R * inv_L - 0.5);
+    if (!(m <= (double)kMaxImages)) {
+        over = true;
+        return kMaxImages;
+    }
+    return m > 0.0 ? (int)m : 0;
+}
 // status[kAnyRebuild + step mod 3]: some replica needs its neighbour list rebuilt
 constexpr int kAnyRebuild = 4;
 

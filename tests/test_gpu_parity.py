@@ -234,6 +234,22 @@ def test_nonfinite_state_detected():
     assert e.value.status == qtb.QTB_E_NONFINITE
 
 
+def test_diverged_bead_spread_is_reported():
+    """A bead far from its atom's centroid (as in a diverging trajectory) asks
+    the list search for more periodic images than it covers: the search is
+    clamped and the next check reports the state instead of looping."""
+    beads, sp, box = crystal(2, 2, seed=3)
+    ctx = gpu_crystal_ctx(beads, sp, box, T=50.0, gamma=1e-3, dt=1.0, noise=0,
+                          prec=qtb.PREC_FP32, fir=qtb.FIR_FP32, autotune=False)
+    r, v, st = ctx.get_state(0)
+    r[1, 0, 0] += 500.0
+    with pytest.raises(qtb.QtbError) as e:
+        ctx.set_state(0, r, v, st)
+        ctx.step(1)
+        ctx.observables(0)
+    assert e.value.status == qtb.QTB_E_NONFINITE
+
+
 # ------------------------------------------------------------------ graphs
 @pytest.mark.parametrize("prec,fir", [(qtb.PREC_FP64, qtb.FIR_FP64), (qtb.PREC_FP32, qtb.FIR_BF16X3)])
 def test_graph_replay_matches_eager(prec, fir):
