@@ -57,6 +57,73 @@ __global__ void __launch_bounds__(256) k_centroids(const RepDev* __restrict__ re
     R.devn[p][ii] = sqrt(d2max);
 }
 
+// Squared lower bound of the periodic distance from (x, y, z) to the box
+// b = (lo xyz, hi xyz): per axis, the distance of the point's nearest image
+// to the interval (0 when the interval spans the period).
+__device__ __forceinline__ double box_dist2(double x, double y, double z, const double* b,
+                                            double Lx, double Ly, double Lz, double iLx,
+                                            double iLy, double iLz)
+{
+    auto axis = [](double p, double lo, double hi, double L, double iL) {
+        const double h = 0.5 * (hi - lo);
+        if (h >= 0.5 * L) return 0.0;
+        double d = p - 0.5 * (lo + hi);
+        d -= L * rint(d * iL);
+        return fmax(fabs(d) - h, 0.0);
+    };
+    const double dx = axis(x, b[0], b[3], Lx, iLx), dy = axis(y, b[1], b[4], Ly, iLy),
+                 dz = axis(z, b[2], b[5], Lz, iLz);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Bounds of the centroids of each tile of kListTile atoms and the largest
+// spread in it, for the list kernel's pruning; one block per tile.
+__global__ void __launch_bounds__(256) k_tile_box(const RepDev* __restrict__ reps,
+                                                 const BlockEntry* __restrict__ tiles,
+                                                 int n_tiles, const int32_t* __restrict__ status,
+                                                 const StepRef sync)
+{
+    __shared__ double red[7][4];
+    const StepIdx si = step_index(sync);
+    if (status[kAnyRebuild + si.f] == 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e = blockIdx.x; e < n_tiles; e += gridDim.x) {
+        const BlockEntry be = tiles[e];
+        const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+        if (R.rflag[si.f] == 0) continue;  // uniform over the block
+        const int N = R.N;
+        const int j = be.atom0 + threadIdx.x;
+        double v[7];
+        if (j < N) {
+            for (int a = 0; a < 3; ++a) v[a] = v[3 + a] = R.cnb[si.p][(size_t)a * N + j];
+            v[6] = R.devn[si.p][j];
+        } else {
+            const int j0 = be.atom0;  // a real atom of the tile: neutral for min/max
+            for (int a = 0; a < 3; ++a) v[a] = v[3 + a] = R.cnb[si.p][(size_t)a * N + j0];
+            v[6] = 0.0;
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                v[a] = fmin(v[a], __shfl_xor(v[a], off));
+                v[3 + a] = fmax(v[3 + a], __shfl_xor(v[3 + a], off));
+            }
+            v[6] = fmax(v[6], __shfl_xor(v[6], off));
+        }
+        __syncthreads();
+        if (lane == 0)
+            for (int a = 0; a < 7; ++a) red[a][wave] = v[a];
+        __syncthreads();
+        if (threadIdx.x < 7) {
+            const int a = threadIdx.x;
+            double r = red[a][0];
+            for (int w = 1; w < 4; ++w) r = (a < 3) ? fmin(r, red[a][w]) : fmax(r, red[a][w]);
+            R.tbox[(size_t)(be.atom0 / kListTile) * 8 + a] = r;
+        }
+    }
+}
+
 // One wavefront per atom i: new reference r_ref_i = current bead centroid,
 // relative positions of its beads, and its list.  Lane l scans atoms
 // j = j0 + l; matches are compacted with a ballot, so entries come out in a
@@ -112,9 +179,18 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
     T4* __restrict__ ent = (T4*)R.nb_entries + (size_t)i * R.maxnb;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int cnt = 0;
-    // tiles of 256 candidate atoms staged in LDS, shared by the 4 wavefronts
-    for (int t0 = 0; t0 < N; t0 += 256) {
-        __syncthreads();
+    // tiles of 256 candidate atoms staged in LDS, shared by the 4 wavefronts;
+    // a tile whose centroid bounds (widened by the spreads) are out of range
+    // of all four atoms of the block is skipped, which leaves the entries and
+    // their order unchanged
+    for (int t0 = 0; t0 < N; t0 += kListTile) {
+        bool far = true;
+        if (active) {
+            const double* b = R.tbox + (size_t)(t0 / kListTile) * 8;
+            const double Rt = R.r_cs + devi + b[6];
+            far = box_dist2(xi, yi, zi, b, Lx, Ly, Lz, iLx, iLy, iLz) >= Rt * Rt;
+        }
+        if (__syncthreads_and(far)) continue;
         const int jl = t0 + threadIdx.x;
         if (jl < N) {
             tx[threadIdx.x] = cx[jl];
@@ -211,10 +287,13 @@ void launch_mark_rebuild(hipStream_t st, const RepDev* reps, int n_rep, int32_t*
 }
 
 void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
-                  int n_blocks, int32_t* status, bool centroids, StepRef sync)
+                  int n_blocks, const BlockEntry* tiles, int n_tiles, int32_t* status,
+                  bool centroids, StepRef sync)
 {
     if (centroids)
         launch(k_centroids, dim3(n_blocks), dim3(64), 0, st, reps, blocks, sync);
+    launch(k_tile_box, dim3(n_tiles < 256 ? n_tiles : 256), dim3(256), 0, st, reps, tiles,
+           n_tiles, status, sync);
     const int grid = n_blocks < 256 ? n_blocks : 256;
     if (fp64)
         launch(k_nlist<double>, dim3(grid), dim3(256), 0, st, reps, blocks, n_blocks, status, sync);

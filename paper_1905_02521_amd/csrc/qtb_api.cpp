@@ -37,12 +37,13 @@ struct Region {
 struct Layout {
     size_t total = 0;
     Region reps, status, rebuild, tiles, taps, ring, zeta, partials, acc, counts, pairtab, clock;
-    Region blk_upd, blk_nl, blk_force;
+    Region blk_upd, blk_nl, blk_force, blk_tb;
     // surrogate (ml_r_cut > 0)
     Region blk_mlc, blk_mlm, ml_acc, ml_counts, ml_loss, ml_stats, ml_foff, ml_wpart;
     struct Per {
         Region force, r0, eatom, species, homega, nb, nbc, nm, ring;
         Region u[2], rref[2], cnow[2], dev[2], devb[2];  // by step parity
+        Region tbox;
         Region mlnb, mlnc, mlrev, mlG, mlaux, mlg, mly, mlfp, mlin, mlnin, mlv, mlu, mladj, mlebar;
     };
     std::vector<Per> per;
@@ -55,6 +56,7 @@ struct Layout {
     std::vector<BlockEntry> mlc, mlm;     // surrogate: centre blocks, network tiles
     std::vector<int64_t> foff;            // offsets of the replicas' reference forces
     std::vector<BlockEntry> upd, nl, force;   // force: table of the chosen W
+    std::vector<BlockEntry> tb;               // candidate tiles of the list kernel
     int upd_threads = 128;
     std::vector<BlockEntry> force_w[3];        // W = 1, 2, 4
     std::vector<std::pair<int, std::pair<int, int>>> force_groups_w[3];
@@ -202,7 +204,7 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     }
     L.n_cols = cols;
     // block tables
-    L.upd.clear(); L.nl.clear(); L.force.clear();
+    L.upd.clear(); L.nl.clear(); L.force.clear(); L.tb.clear();
     L.upd_groups.clear(); L.force_groups.clear();
     std::map<int, std::vector<int>> byP, byG;
     for (int r = 0; r < n_rep; ++r) {
@@ -223,8 +225,10 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
         }
         L.upd_groups.push_back({maxP, {0, (int)L.upd.size()}});
     }
-    for (int r = 0; r < n_rep; ++r)
+    for (int r = 0; r < n_rep; ++r) {
         for (int a = 0; a < reps[r].n_atoms; a += 4) L.nl.push_back({r, a, 0, 0});
+        for (int a = 0; a < reps[r].n_atoms; a += kListTile) L.tb.push_back({r, a, 0, 0});
+    }
     // force tables for every waves-per-atom choice (the autotuner picks one)
     for (int wi = 0; wi < 3; ++wi) {
         const int W = 1 << wi, apb = 4 / W;
@@ -284,6 +288,7 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     add(cur, L.pairtab, sizeof(PairTable<double>));
     add(cur, L.blk_upd, sizeof(BlockEntry) * std::max<size_t>(1, L.upd.size()));
     add(cur, L.blk_nl, sizeof(BlockEntry) * std::max<size_t>(1, L.nl.size()));
+    add(cur, L.blk_tb, sizeof(BlockEntry) * std::max<size_t>(1, L.tb.size()));
     add(cur, L.blk_force, sizeof(BlockEntry) * L.max_force_blocks);
     if (L.ml) {
         add(cur, L.blk_mlc, sizeof(BlockEntry) * L.mlc.size());
@@ -313,6 +318,7 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
                 add(cur, p.dev[q], 8 * N);
                 add(cur, p.devb[q], 8 * N);
             }
+            add(cur, p.tbox, 8 * 8 * ((N + kListTile - 1) / kListTile));
             add(cur, p.nb, 4 * ts * N * (size_t)L.maxnb[r]);
             add(cur, p.nbc, 4 * N);
             if (L.ml) {
@@ -640,6 +646,7 @@ void fill_repdev(qtb_ctx* c, int r)
     d.homega = c->pair ? nullptr : c->at<double>(p.homega);
     d.nb_entries = c->pair ? c->at<void>(p.nb) : nullptr;
     d.nb_count = c->pair ? c->at<int32_t>(p.nbc) : nullptr;
+    d.tbox = c->pair ? c->at<double>(p.tbox) : nullptr;
     d.nm = c->at<double>(p.nm);
     d.ring = c->at<double>(p.ring);
     d.rflag = c->at<int32_t>(c->L.rebuild) + 3 * r;
@@ -717,6 +724,15 @@ qtb_status upload_taps(qtb_ctx* c, int r)
 
 // Pair-potential (or oscillator) forces of every replica.  kCompare leaves
 // the rebuild flags alone (the surrogate's forward pass cleared them).
+// Whether steps rebuild lists in the list kernel (else inside the force kernel).
+bool list_kernel(const qtb_ctx* c)
+{
+    if (c->ml || c->L.ml) return true;
+    for (const auto& R : c->reps)
+        if (R.n_atoms > kInlineRebuildMaxAtoms) return true;
+    return false;
+}
+
 // inline_rebuild: the force kernel rebuilds flagged lists itself (no list
 // kernel launched before it).
 void launch_plain_forces(qtb_ctx* c, int32_t flags, bool inline_rebuild = false)
@@ -773,7 +789,8 @@ void launch_rebuild(qtb_ctx* c, bool centroids = false)
     if (!c->pair) return;
     const Layout& L = c->L;
     launch_nlist(c->st, c->fp64, c->at<RepDev>(L.reps), c->at<BlockEntry>(L.blk_nl),
-                 (int)L.nl.size(), c->at<int32_t>(L.status), centroids, step_ref(c));
+                 (int)L.nl.size(), c->at<BlockEntry>(L.blk_tb), (int)L.tb.size(),
+                 c->at<int32_t>(L.status), centroids, step_ref(c));
     if (L.ml)  // the surrogate's shorter lists follow every rebuild
         launch_ml_lists(c->st, c->fp64, c->at<RepDev>(L.reps), c->at<BlockEntry>(L.blk_nl),
                         (int)L.nl.size(), c->at<int32_t>(L.status), step_ref(c));
@@ -851,11 +868,12 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
         }
     }
     c->rec_extra = 1;
-    // the pair potential's force kernel rebuilds flagged lists itself; the
-    // surrogate's lists follow the list kernel
-    const bool inline_rebuild = c->pair && !L.ml && !c->ml;
+    // the pair potential's force kernel rebuilds flagged lists itself, except
+    // for large replicas (the list kernel prunes its scan by tile bounds) and
+    // with surrogate buffers (the surrogate's lists follow the list kernel)
+    const bool inline_rebuild = c->pair && !list_kernel(c);
     if (c->pair && !inline_rebuild) {
-        Phase ph(c, 3, L.ml);
+        Phase ph(c, 3, true);  // tile bounds and list kernels (+ surrogate lists)
         launch_rebuild(c);
     }
     {
@@ -893,7 +911,7 @@ bool fused_step(const qtb_ctx* c)
 {
     // (contexts with surrogate buffers keep the separate list kernel, whose
     // rebuilds also refresh the surrogate's lists)
-    if (!c->pair || c->ml || c->L.ml || !(c->opt.flags & QTB_OPT_FUSE)) return false;
+    if (!c->pair || list_kernel(c) || !(c->opt.flags & QTB_OPT_FUSE)) return false;
     if (c->L.force_groups.size() != 1) return false;
     const int G = c->L.force_groups[0].first;
     for (const auto& R : c->reps)
@@ -950,7 +968,7 @@ void close_steps(qtb_ctx* c)
     const Layout& L = c->L;
     const bool sample = sample_at(c, c->step - 1);
     {
-        Phase ph(c, 3);
+        Phase ph(c, 3, true);
         launch_rebuild(c);
     }
     {
@@ -1249,6 +1267,8 @@ qtb_status qtb_init(qtb_ctx** out, const qtb_potential* pot, const qtb_replica* 
                                          sizeof(BlockEntry) * c->L.upd.size(), hipMemcpyHostToDevice, c->st), "blk")) ||
         (s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.blk_nl), c->L.nl.data(),
                                          sizeof(BlockEntry) * c->L.nl.size(), hipMemcpyHostToDevice, c->st), "blk")) ||
+        (s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.blk_tb), c->L.tb.data(),
+                                         sizeof(BlockEntry) * c->L.tb.size(), hipMemcpyHostToDevice, c->st), "blk")) ||
         (s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.blk_force), c->L.force.data(),
                                          sizeof(BlockEntry) * c->L.force.size(), hipMemcpyHostToDevice, c->st), "blk")))
         return bail(s);

@@ -68,6 +68,8 @@ struct RepDev {
     const double* nm;        // [P][P] orthonormal normal-mode matrix C[s][k]
     const double* ring;      // [3][P]: cos(w h), sin(w h)/w, -w sin(w h), h = dt/2
     int32_t* rflag;          // [3] neighbour-list rebuild flags, by step mod 3
+    double* tbox;            // [ceil(N/kListTile)][8] per candidate tile: centroid
+                             // bounds lo xyz, hi xyz, largest spread (list kernel)
     int64_t dof_off;         // first column in the global noise arrays
     int64_t step_off;        // replica step = global step + step_off
     int32_t N, P, dims, maxnb;
@@ -162,6 +164,12 @@ enum StatusBits : int32_t {
 // bead spread) is clamped to it and reported through kStatusRange, so the
 // search always ends.
 constexpr int kMaxImages = 8;
+// Candidate atoms per tile of the list kernel's scan (staged in LDS).
+constexpr int kListTile = 256;
+// Replicas above this many atoms build their lists in the list kernel, whose
+// scan skips candidate tiles out of range by their bounding boxes; smaller
+// ones rebuild inside the force kernel (one launch less per step).
+constexpr int kInlineRebuildMaxAtoms = 16384;
 
 // Image range ceil(R / L - 1/2) along one direction, clamped to
 // [0, kMaxImages] (also for non-finite R); over is set when clamped.
@@ -243,7 +251,8 @@ int update_threads(int max_dims_beads);
 int update_block_atoms(int dims, int P, int threads);
 // nlist.hip
 void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
-                  int n_blocks, int32_t* status, bool centroids, StepRef sync);
+                  int n_blocks, const BlockEntry* tiles, int n_tiles, int32_t* status,
+                  bool centroids, StepRef sync);
 void launch_mark_rebuild(hipStream_t st, const RepDev* reps, int n_rep, int32_t* status,
                          StepRef sync);
 // forces.hip

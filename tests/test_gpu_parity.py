@@ -297,6 +297,27 @@ def test_trajectory_with_frequent_rebuilds(orc, prec, tol):
     assert rel <= tol, rel
 
 
+@pytest.mark.parametrize("prec,tol", [(qtb.PREC_FP32, 1e-5), (qtb.PREC_FP64, 1e-9)])
+def test_large_replica_list_kernel_with_rebuilds(orc, prec, tol):
+    """17 576 atoms (13x13x13 cells) take the list kernel, whose scan skips
+    candidate tiles by their centroid bounds; with a 0.02 A skin it rebuilds
+    during the run, and the trajectory still follows the oracle."""
+    beads, sp, box = crystal(13, 1, seed=14)
+    assert beads.shape[2] > 16384
+    p = W.mgo_potential(skin=0.02)
+    fir = qtb.FIR_FP64 if prec == qtb.PREC_FP64 else qtb.FIR_FP32
+    ctx = gpu_crystal_ctx(beads, sp, box, T=300.0, gamma=2e-3, dt=1.0, noise=1, prec=prec,
+                          fir=fir, seed=22, max_two_nf=128, pot=p)
+    ctx.build_filter(0, 1, 128)
+    ctx.profile(True)
+    osim = orc.Sim(oracle_pair_pot(orc), oracle_units(orc, False), beads.shape[2], 1, 3, box, sp,
+                   300.0, 2e-3, 1.0, 22, 0, 1, 128, beads, n_threads=8)
+    rel, _ = _traj_compare(orc, ctx, osim, 30, scale=0.0421)
+    prof = ctx.profile_read()
+    assert prof["nlist"][1] > 0  # the list kernel ran
+    assert rel <= tol, rel
+
+
 @pytest.mark.parametrize("fuse", [True, False])
 def test_profile_reports_every_phase(fuse):
     beads, sp, box = crystal(3, 4, seed=2)
