@@ -320,6 +320,62 @@ def surrogate_bench(a):
     print(json.dumps(out))
 
 
+def pimd_compare_bench(a):
+    """QTB (P = 1, theta noise), QTB-PIMD (P = 8, kappa_P noise) and classical
+    PIMD (P = 32, white noise) on the 4x4x4 MgO crystal at 50 K, gamma = 1/ps:
+    the time per step of each and the eq. 5 energies per atom (block means),
+    beside the paper's statement that QTB needs about a twentieth of the PIMD
+    computation time (its hardware and workload are not stated)."""
+    import torch
+    from paper_1905_02521_amd import qtb, workloads as W
+    pot = W.mgo_potential(skin=1.0)
+    U = dict(W.METAL_UNITS)
+    pos, sp, box = W.rocksalt(4)
+    base = W.displaced(pos, 0.0421, 2)
+    N = len(sp)
+    n_eq, block, n_blocks = 4000, 1000, a.blocks
+    out_runs = {}
+    for name, P, noise in (("qtb", 1, 1), ("qtb-pimd", 8, 2), ("pimd", 32, 0)):
+        rep = qtb.Replica(pos=W.beads_from(base, P), species=sp, T=50.0, gamma=1e-3, dt=1.0,
+                          noise=noise, box=tuple(box), seed=2)
+        ctx = qtb.Context(qtb.pair_potential_dict(pot), [rep], U, prec=qtb.PREC_FP32,
+                          fir=qtb.FIR_BF16X3, obs_every=8, max_two_nf=512)
+        if noise:
+            ctx.build_filter(0, noise, 512)
+        ctx.step(n_eq)
+        ctx.observables(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        blocks = {"e_primitive": [], "e_virial": [], "t_kinetic": []}
+        for _ in range(n_blocks):
+            ctx.step(block)
+            o = ctx.observables(0)
+            for k in blocks:
+                blocks[k].append(o[k])
+        dt = (time.perf_counter() - t0) / (n_blocks * block)
+        ctx.close()
+        r = {"beads": P, "ms_per_step": dt * 1e3, "atom_bead_steps_per_s": N * P / dt}
+        for k, v in blocks.items():
+            v = np.asarray(v) / (N if k != "t_kinetic" else 1)
+            r[k] = [float(v.mean()), float(v.std(ddof=1) / math.sqrt(len(v)))]
+        out_runs[name] = r
+    out = {
+        "metric": "QTB vs QTB-PIMD vs PIMD: time per step and eq. 5 energies per atom",
+        "unit": "ms/step; eV/atom (mean, standard error of block means); K",
+        "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+        "data": "synthetic (seeded rock-salt crystal, numpy PCG64 displacements)",
+        "config": {"workload": "mgo-4x4x4-50K-qtb-vs-pimd", "atoms": N, "T_K": 50.0,
+                   "gamma_per_ps": 1.0, "two_nf": 512, "equilibration_steps": n_eq,
+                   "blocks": n_blocks, "block_steps": block},
+        "runs": out_runs,
+        "pimd_over_qtb_time": out_runs["pimd"]["ms_per_step"] / out_runs["qtb"]["ms_per_step"],
+        "pimd_over_qtbpimd_time": (out_runs["pimd"]["ms_per_step"] /
+                                   out_runs["qtb-pimd"]["ms_per_step"]),
+        "paper": "QTB about 20x cheaper than PIMD (abstract; hardware and workload not stated)",
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,9 +383,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="mgo-8x8x8-qtbpimd-P8-50K",
                     help="a named single workload, batched-64 (the T / gamma / P sweep) or "
-                         "surrogate-20x20x20-P4 (the learned force surrogate)")
+                         "surrogate-20x20x20-P4 (the learned force surrogate) or qtb-vs-pimd "
+                         "(QTB, QTB-PIMD and PIMD cost and energies on one crystal)")
     ap.add_argument("--fir", default="bf16x3", choices=["fp32", "bf16x3", "bf16", "fp64"])
     ap.add_argument("--K", type=int, default=64)
+    ap.add_argument("--blocks", type=int, default=40,
+                    help="qtb-vs-pimd: measured blocks of 1000 steps per method")
     ap.add_argument("--skin", type=float, default=None,
                     help="Verlet skin (A); default 0.4 for one crystal (fastest measured), "
                          "1.0 for the sweep (hot replicas)")
@@ -355,6 +414,8 @@ def main():
     torch.cuda.set_device(0)
     if a.skin is None:
         a.skin = 1.0 if (a.workload.startswith("batched") or a.workload.startswith("surrogate")) else 0.4
+    if a.workload == "qtb-vs-pimd":
+        return pimd_compare_bench(a)
     if a.workload.startswith("surrogate"):
         surrogate_bench(a)
         return
