@@ -252,8 +252,9 @@ __device__ __forceinline__ void reduce_atom(double& fx, double& fy, double& fz, 
     }
 }
 
-// Block sums of the observable slots into partials[blockIdx.x].
-__device__ __forceinline__ void block_partials(const double* ob, int wave, int lane,
+// Block sums of the observable slots into partials[lb] (lb: the block's
+// table entry).
+__device__ __forceinline__ void block_partials(const double* ob, int wave, int lane, int lb,
                                                double (*red)[kNobs], double* partials)
 {
 #pragma unroll
@@ -265,7 +266,7 @@ __device__ __forceinline__ void block_partials(const double* ob, int wave, int l
     if (threadIdx.x < kNobs) {
         const double t = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
                          red[3][threadIdx.x];
-        partials[(size_t)blockIdx.x * kNobs + threadIdx.x] = t;
+        partials[(size_t)lb * kNobs + threadIdx.x] = t;
     }
 }
 
@@ -380,7 +381,8 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
     __shared__ double red[4][kNobs];
     __shared__ double tx[256], ty[256], tz[256], td[256];
     __shared__ double dmax_s[4];
-    const BlockEntry be = blocks[blockIdx.x];
+    const int lb = xcd_block();
+    const BlockEntry be = blocks[lb];
     const int rep = __builtin_amdgcn_readfirstlane(be.rep);
     const RepDev& R = reps[rep];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -449,7 +451,7 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
         const double f[3] = {fx, fy, fz};
         force_epilogue<T>(R, i, s, spi, f, 0.5 * e, flags, ob);
     }
-    if (flags & (kSample | kCompare)) block_partials(ob, wave, lane, red, partials);
+    if (flags & (kSample | kCompare)) block_partials(ob, wave, lane, lb, red, partials);
 }
 
 // One step of the pair potential for P = G <= 8 beads (all beads of an atom
@@ -489,7 +491,8 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
         for (int r = threadIdx.x; r < n_rep; r += blockDim.x) reps[r].rflag[fold] = 0;
         if (threadIdx.x == 0) status[kAnyRebuild + fold] = 0;
     }
-    const BlockEntry be = blocks[blockIdx.x];
+    const int lb = xcd_block();
+    const BlockEntry be = blocks[lb];
     const int rep = __builtin_amdgcn_readfirstlane(be.rep);
     const RepDev& R = reps[rep];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -657,7 +660,7 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
         }
         if (my_flags & kStatusNonfinite) atomicOr(status, kStatusNonfinite);
     }
-    if (flags & kSample) block_partials(ob, wave, lane, red, partials);
+    if (flags & kSample) block_partials(ob, wave, lane, lb, red, partials);
 }
 
 // Independent oscillators: V = sum_i 1/2 m omega_i^2 |x_i|^2 per bead.

@@ -255,7 +255,8 @@ __global__ void __launch_bounds__(256) k_ml_desc(const RepDev* __restrict__ reps
         for (int r = threadIdx.x; r < n_rep; r += blockDim.x) reps[r].rflag[si.f] = 0;
         if (threadIdx.x == 0) status[kAnyRebuild + si.f] = 0;
     }
-    const BlockEntry be = blocks[blockIdx.x];
+    const int lb = xcd_block();
+    const BlockEntry be = blocks[lb];
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = be.atom0 + wave, s = be.group;
@@ -341,7 +342,6 @@ __global__ void __launch_bounds__(256) k_ml_desc(const RepDev* __restrict__ reps
 constexpr int kW1S = kMlFeat + 1;    // 97
 constexpr int kW2S = kMlHidden + 1;  // 65
 constexpr int kMlpWaves = 16;
-constexpr int kCpw = 4;              // centres per wavefront (network kernel)
 
 struct alignas(16) MlpLds {
     float W1[2][kMlHidden][kW1S];
@@ -376,121 +376,285 @@ __device__ void load_weights(MlpLds& L, const MlDev& m)
     __syncthreads();
 }
 
-// Network blocks: BlockEntry {rep, first centre (s N + i), count <= 64}.
-// Each wavefront evaluates kCpw centres, lane o = hidden unit o; outputs the
-// atomic energy (without e0) and dE/dG.
-__global__ void __launch_bounds__(1024) k_ml_mlp(const RepDev* __restrict__ reps, const MlDev m,
-                                                 const BlockEntry* __restrict__ blocks,
-                                                 int n_blocks)
+// ------------------------------------------------------ network, matrix cores
+// The same network for 32 centres per wavefront on v_mfma_f32_32x32x16_bf16.
+// The weights are BF16 numbers; each FP32 activation enters as three BF16
+// parts hi + mid + lo (equal to it to FP32 rounding), so every product with a
+// weight is exact and the sums are FP32, as in the vector form.  Both
+// species' weights are applied and each centre (row) keeps its own species'
+// result.  Per layer, the activations of the 32 centres sit in the
+// wavefront's LDS tile T[centre][unit] (A operand rows) and the weights in
+// LDS in both orientations (B operand columns).
+// Operand layout of 32x32x16: lane l gives A row (l & 31) and B column
+// (l & 31) for k = 8 (l >> 5) .. +7; the accumulator element r of lane l is
+// C[8 (r >> 2) + 4 (l >> 5) + (r & 3)][l & 31].
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTS = 100;    // row stride (floats) of a wavefront's activation tile
+constexpr int kWR1 = 104;   // row stride (BF16) of W1 [o][f]
+constexpr int kWR = 72;     // row stride (BF16) of W1T [f][o], W2 [o][k], W2T [k][o]
+constexpr int kMfmaWaves = 4;
+
+struct alignas(16) MfmaLds {
+    uint16_t W1[2][kMlHidden][kWR1];
+    uint16_t W1T[2][kMlFeat][kWR];
+    uint16_t W2[2][kMlHidden][kWR];
+    uint16_t W2T[2][kMlHidden][kWR];
+    float b1[2][kMlHidden], b2[2][kMlHidden], w3[2][kMlHidden];
+    float b3[4];
+    float mu[2][kMlFeat], isd[2][kMlFeat];
+    int sp[kMfmaWaves][32];
+};
+static_assert(sizeof(MfmaLds) % 16 == 0, "the activation tiles after the weights stay aligned");
+
+__device__ __forceinline__ float bf16v(uint32_t h) { return __uint_as_float(h << 16); }
+
+// x (8 FP32 values) as three BF16 operands with x = hi + mid + lo to FP32
+// rounding (each part rounded to nearest even from the remainder).
+__device__ __forceinline__ void split3(const float4 x0, const float4 x1, bf16x8& hi, bf16x8& mid,
+                                       bf16x8& lo)
+{
+    const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const __bf16 h = (__bf16)x[q];
+        const float r = x[q] - (float)h;
+        const __bf16 m = (__bf16)r;
+        hi[q] = h;
+        mid[q] = m;
+        lo[q] = (__bf16)(r - (float)m);
+    }
+}
+
+__device__ __forceinline__ bf16x8 ldb(const uint16_t* p)
+{
+    return __builtin_bit_cast(bf16x8, *(const u32x4*)p);
+}
+
+// acc += A . B with A the three-part activations and B one weight fragment.
+__device__ __forceinline__ void mfma3(f32x16& acc, const bf16x8& hi, const bf16x8& mid,
+                                      const bf16x8& lo, const bf16x8& b)
+{
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi, b, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mid, b, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo, b, acc, 0, 0, 0);
+}
+
+__device__ void load_weights_mfma(MfmaLds& L, const MlDev& m)
+{
+    for (int t = threadIdx.x; t < 2 * kMlHidden * kMlFeat; t += blockDim.x) {
+        const int a = t / (kMlHidden * kMlFeat), r = t % (kMlHidden * kMlFeat);
+        const int o = r / kMlFeat, f = r % kMlFeat;
+        const uint16_t w = m.wq[a * kMlParamsSp + kMlOffW1 + r];
+        L.W1[a][o][f] = w;
+        L.W1T[a][f][o] = w;
+    }
+    for (int t = threadIdx.x; t < 2 * kMlHidden * kMlHidden; t += blockDim.x) {
+        const int a = t / (kMlHidden * kMlHidden), r = t % (kMlHidden * kMlHidden);
+        const int o = r / kMlHidden, k = r % kMlHidden;
+        const uint16_t w = m.wq[a * kMlParamsSp + kMlOffW2 + r];
+        L.W2[a][o][k] = w;
+        L.W2T[a][k][o] = w;
+    }
+    for (int t = threadIdx.x; t < 2 * kMlHidden; t += blockDim.x) {
+        const int a = t / kMlHidden, o = t % kMlHidden;
+        L.b1[a][o] = m.master[a * kMlParamsSp + kMlOffB1 + o];
+        L.b2[a][o] = m.master[a * kMlParamsSp + kMlOffB2 + o];
+        L.w3[a][o] = bf16f(m.wq[a * kMlParamsSp + kMlOffW3 + o]);
+    }
+    if (threadIdx.x < 2) L.b3[threadIdx.x] = m.master[threadIdx.x * kMlParamsSp + kMlOffB3];
+    for (int t = threadIdx.x; t < 2 * kMlFeat; t += blockDim.x) {
+        L.mu[t / kMlFeat][t % kMlFeat] = m.mu[t];
+        L.isd[t / kMlFeat][t % kMlFeat] = m.inv_sd[t];
+    }
+    __syncthreads();
+}
+
+// Network blocks: BlockEntry {rep, first centre (s N + i), count <= 64}; each
+// holds two tiles of 32 centres, one wavefront per tile.  Outputs the atomic
+// energy (without e0) and dE/dG.
+__global__ void __launch_bounds__(256) k_ml_mlp_mfma(const RepDev* __restrict__ reps,
+                                                     const MlDev m,
+                                                     const BlockEntry* __restrict__ blocks,
+                                                     int n_blocks)
 {
     extern __shared__ float4 lds_raw[];
-    MlpLds& L = *reinterpret_cast<MlpLds*>(lds_raw);
-    float4 (*X)[kMlFeat] = reinterpret_cast<float4 (*)[kMlFeat]>(
-        reinterpret_cast<char*>(lds_raw) + sizeof(MlpLds));                // [wave][96]
-    float4 (*H)[kMlHidden] = reinterpret_cast<float4 (*)[kMlHidden]>(
-        reinterpret_cast<char*>(lds_raw) + sizeof(MlpLds) + sizeof(float4) * kMlpWaves * kMlFeat);
-    load_weights(L, m);
+    MfmaLds& L = *reinterpret_cast<MfmaLds*>(lds_raw);
+    load_weights_mfma(L, m);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int b = blockIdx.x; b < n_blocks; b += gridDim.x) {
-        const BlockEntry be = blocks[b];
+    const int li = lane & 31, lk = lane >> 5;
+    float (*T)[kTS] = reinterpret_cast<float (*)[kTS]>(reinterpret_cast<char*>(lds_raw) +
+                                                     sizeof(MfmaLds) +
+                                                     sizeof(float) * 32 * kTS * wave);
+    int* spw = L.sp[wave];
+    const int n_tiles = 2 * n_blocks;
+    for (int t = blockIdx.x * kMfmaWaves + wave; t < n_tiles; t += gridDim.x * kMfmaWaves) {
+        const BlockEntry be = blocks[t >> 1];
+        const int c0 = 32 * (t & 1);
+        if (c0 >= be.group) continue;  // uniform per wavefront
         const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
         const int N = R.N;
-        const int first = wave * kCpw;
-        if (first >= be.group) continue;  // uniform per wavefront
-        int sp[kCpw];
-        size_t cc[kCpw];
-        bool ok[kCpw];
-#pragma unroll
-        for (int q = 0; q < kCpw; ++q) {
-            ok[q] = first + q < be.group;
-            const int c = be.atom0 + (ok[q] ? first + q : first);
-            cc[q] = (size_t)c;
-            sp[q] = R.species[c % N];
-        }
-        // stage x = (G - mu) inv_sd as [m][q]
-        for (int f = lane; f < kMlFeat; f += 64) {
-            float v[kCpw];
-#pragma unroll
-            for (int q = 0; q < kCpw; ++q)
-                v[q] = (R.ml_G[cc[q] * kMlFeat + f] - L.mu[sp[q]][f]) * L.isd[sp[q]][f];
-            X[wave][f] = make_float4(v[0], v[1], v[2], v[3]);
-        }
+        const int nv = min(32, be.group - c0);
+        const int cbase = be.atom0 + c0;  // centre of row q: cbase + (q < nv ? q : 0)
+        if (lane < 32) spw[lane] = R.species[(cbase + (lane < nv ? lane : 0)) % N];
         wave_sync();
-        const int o = lane;
-        float z1[kCpw], z2[kCpw];
-#pragma unroll
-        for (int q = 0; q < kCpw; ++q) z1[q] = L.b1[sp[q]][o];
-        for (int f = 0; f < kMlFeat; ++f) {
-            const float w0 = L.W1[0][o][f], w1 = L.W1[1][o][f];
-            const float4 x = X[wave][f];
-            z1[0] += (sp[0] ? w1 : w0) * x.x;
-            z1[1] += (sp[1] ? w1 : w0) * x.y;
-            z1[2] += (sp[2] ? w1 : w0) * x.z;
-            z1[3] += (sp[3] ? w1 : w0) * x.w;
-        }
-        float s1[kCpw];
         {
-            float hv[kCpw];
+            // all 48 loads of a lane in flight at once (one wavefront per SIMD)
+            float gv[32][2];
 #pragma unroll
-            for (int q = 0; q < kCpw; ++q) {
-                const float sg = sigm(z1[q]);
-                hv[q] = z1[q] * sg;
-                s1[q] = sg * (1.0f + z1[q] * (1.0f - sg));
-            }
-            H[wave][o] = make_float4(hv[0], hv[1], hv[2], hv[3]);
-        }
-        wave_sync();
-#pragma unroll
-        for (int q = 0; q < kCpw; ++q) z2[q] = L.b2[sp[q]][o];
-        for (int k = 0; k < kMlHidden; ++k) {
-            const float w0 = L.W2[0][o][k], w1 = L.W2[1][o][k];
-            const float4 hk = H[wave][k];
-            z2[0] += (sp[0] ? w1 : w0) * hk.x;
-            z2[1] += (sp[1] ? w1 : w0) * hk.y;
-            z2[2] += (sp[2] ? w1 : w0) * hk.z;
-            z2[3] += (sp[3] ? w1 : w0) * hk.w;
-        }
-        float d2[kCpw];
-#pragma unroll
-        for (int q = 0; q < kCpw; ++q) {
-            const float sg = sigm(z2[q]);
-            const float w3 = L.w3[sp[q]][o];
-            const float y = wsum(w3 * z2[q] * sg);
-            if (lane == 0 && ok[q]) R.ml_y[cc[q]] = y + L.b3[sp[q]];
-            d2[q] = w3 * sg * (1.0f + z2[q] * (1.0f - sg));
-        }
-        wave_sync();  // everyone has read H
-        H[wave][o] = make_float4(d2[0], d2[1], d2[2], d2[3]);
-        wave_sync();
-        // delta1[k] = silu'(z1[k]) sum_o W2[o][k] delta2[o]   (lane = k)
-        float acc[kCpw] = {0.f, 0.f, 0.f, 0.f};
-        for (int oo = 0; oo < kMlHidden; ++oo) {
-            const float w0 = L.W2[0][oo][lane], w1 = L.W2[1][oo][lane];
-            const float4 dd = H[wave][oo];
-            acc[0] += (sp[0] ? w1 : w0) * dd.x;
-            acc[1] += (sp[1] ? w1 : w0) * dd.y;
-            acc[2] += (sp[2] ? w1 : w0) * dd.z;
-            acc[3] += (sp[3] ? w1 : w0) * dd.w;
-        }
-        wave_sync();
-        H[wave][lane] = make_float4(acc[0] * s1[0], acc[1] * s1[1], acc[2] * s1[2], acc[3] * s1[3]);
-        wave_sync();
-        // dE/dG[f] = inv_sd[f] sum_k W1[k][f] delta1[k]   (lane = f, f + 64)
-        for (int f = lane; f < kMlFeat; f += 64) {
-            float g[kCpw] = {0.f, 0.f, 0.f, 0.f};
-            for (int k = 0; k < kMlHidden; ++k) {
-                const float w0 = L.W1[0][k][f], w1 = L.W1[1][k][f];
-                const float4 dd = H[wave][k];
-                g[0] += (sp[0] ? w1 : w0) * dd.x;
-                g[1] += (sp[1] ? w1 : w0) * dd.y;
-                g[2] += (sp[2] ? w1 : w0) * dd.z;
-                g[3] += (sp[3] ? w1 : w0) * dd.w;
+            for (int q = 0; q < 32; ++q) {
+                const float* __restrict__ g = R.ml_G + (size_t)(cbase + (q < nv ? q : 0)) * kMlFeat;
+                gv[q][0] = g[lane];
+                gv[q][1] = lane < kMlFeat - 64 ? g[64 + lane] : 0.0f;
             }
 #pragma unroll
-            for (int q = 0; q < kCpw; ++q)
-                if (ok[q]) R.ml_g[cc[q] * kMlFeat + f] = g[q] * L.isd[sp[q]][f];
+            for (int q = 0; q < 32; ++q) {
+                const int a = spw[q];
+                T[q][lane] = (gv[q][0] - L.mu[a][lane]) * L.isd[a][lane];
+                if (lane < kMlFeat - 64)
+                    T[q][64 + lane] = (gv[q][1] - L.mu[a][64 + lane]) * L.isd[a][64 + lane];
+            }
         }
-        wave_sync();  // H and X are reused by the next tile
+        // species of the accumulator rows of this lane: bit r set for species 1
+        uint32_t s1m = 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            s1m |= (uint32_t)(spw[8 * (r >> 2) + 4 * lk + (r & 3)] != 0) << r;
+        wave_sync();
+        f32x16 acc[2][2];
+        bf16x8 ah, am, al;
+        // layer 1: z1[c][o] = sum_f x[c][f] W1[o][f]
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][nt][r] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < kMlFeat / 16; ++ks) {
+            const int k0 = 16 * ks + 8 * lk;
+            split3(*(const float4*)&T[li][k0], *(const float4*)&T[li][k0 + 4], ah, am, al);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    mfma3(acc[a][nt], ah, am, al, ldb(&L.W1[a][32 * nt + li][k0]));
+        }
+        wave_sync();  // all rows read before the tile is overwritten
+        float s1v[2][16];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int q = 8 * (r >> 2) + 4 * lk + (r & 3), o = 32 * nt + li;
+                const int a = (s1m >> r) & 1;
+                const float z = (a ? acc[1][nt][r] : acc[0][nt][r]) + L.b1[a][o];
+                const float sg = sigm(z);
+                s1v[nt][r] = sg * (1.0f + z * (1.0f - sg));
+                T[q][o] = z * sg;
+            }
+        wave_sync();
+        // layer 2: z2[c][o] = sum_k h1[c][k] W2[o][k]
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][nt][r] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < kMlHidden / 16; ++ks) {
+            const int k0 = 16 * ks + 8 * lk;
+            split3(*(const float4*)&T[li][k0], *(const float4*)&T[li][k0 + 4], ah, am, al);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    mfma3(acc[a][nt], ah, am, al, ldb(&L.W2[a][32 * nt + li][k0]));
+        }
+        wave_sync();
+        float d2v[2][16];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int q = 8 * (r >> 2) + 4 * lk + (r & 3), o = 32 * nt + li;
+                const int a = (s1m >> r) & 1;
+                const float z = (a ? acc[1][nt][r] : acc[0][nt][r]) + L.b2[a][o];
+                const float sg = sigm(z);
+                const float w3 = L.w3[a][o];
+                d2v[nt][r] = w3 * sg * (1.0f + z * (1.0f - sg));
+                T[q][o] = w3 * (z * sg);
+            }
+        wave_sync();
+        if (lane < nv) {  // E_i - b3 - e0 = sum_o w3 h2, in unit order
+            float y = 0.0f;
+            for (int o = 0; o < kMlHidden; ++o) y += T[lane][o];
+            R.ml_y[cbase + lane] = y + L.b3[spw[lane]];
+        }
+        wave_sync();
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) T[8 * (r >> 2) + 4 * lk + (r & 3)][32 * nt + li] = d2v[nt][r];
+        wave_sync();
+        // delta1[c][k] = s1[c][k] sum_o delta2[c][o] W2[o][k]
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][nt][r] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < kMlHidden / 16; ++ks) {
+            const int k0 = 16 * ks + 8 * lk;
+            split3(*(const float4*)&T[li][k0], *(const float4*)&T[li][k0 + 4], ah, am, al);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    mfma3(acc[a][nt], ah, am, al, ldb(&L.W2T[a][32 * nt + li][k0]));
+        }
+        wave_sync();
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int a = (s1m >> r) & 1;
+                T[8 * (r >> 2) + 4 * lk + (r & 3)][32 * nt + li] =
+                    (a ? acc[1][nt][r] : acc[0][nt][r]) * s1v[nt][r];
+            }
+        wave_sync();
+        // dE/dG[c][f] = inv_sd[f] sum_k delta1[c][k] W1[k][f]
+        f32x16 acc3[2][3];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int nt = 0; nt < 3; ++nt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc3[a][nt][r] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < kMlHidden / 16; ++ks) {
+            const int k0 = 16 * ks + 8 * lk;
+            split3(*(const float4*)&T[li][k0], *(const float4*)&T[li][k0 + 4], ah, am, al);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int nt = 0; nt < 3; ++nt)
+                    mfma3(acc3[a][nt], ah, am, al, ldb(&L.W1T[a][32 * nt + li][k0]));
+        }
+#pragma unroll
+        for (int nt = 0; nt < 3; ++nt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int q = 8 * (r >> 2) + 4 * lk + (r & 3), f = 32 * nt + li;
+                const int a = (s1m >> r) & 1;
+                if (q < nv)
+                    R.ml_g[(size_t)(cbase + q) * kMlFeat + f] =
+                        (a ? acc3[1][nt][r] : acc3[0][nt][r]) * L.isd[a][f];
+            }
+        wave_sync();  // the tile is reused by the next tile of this wavefront
     }
 }
 
@@ -509,7 +673,8 @@ __global__ void __launch_bounds__(256) k_ml_pair(const RepDev* __restrict__ reps
     __shared__ float gs[4][kMlFeat];
     __shared__ float as[4][kMlAux];
     __shared__ float4 st[4][kMaxStage];   // staged d_ij (x, y, z), slot bits in .w
-    const BlockEntry be = blocks[blockIdx.x];
+    const int lb = xcd_block();
+    const BlockEntry be = blocks[lb];
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = be.atom0 + wave, s = be.group;
@@ -617,7 +782,8 @@ __global__ void __launch_bounds__(256) k_ml_gather(const RepDev* __restrict__ re
     using T4 = typename V4T<T>::type;
     constexpr int NCH = 64 / G;
     __shared__ double red[4][kNobs];
-    const BlockEntry be = blocks[blockIdx.x];
+    const int lb = xcd_block();
+    const BlockEntry be = blocks[lb];
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int bl = lane % G, ch = lane / G;
@@ -669,7 +835,7 @@ __global__ void __launch_bounds__(256) k_ml_gather(const RepDev* __restrict__ re
         if (threadIdx.x < kNobs) {
             const double t = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
                              red[3][threadIdx.x];
-            partials[(size_t)blockIdx.x * kNobs + threadIdx.x] = t;
+            partials[(size_t)lb * kNobs + threadIdx.x] = t;
         }
     }
 }
@@ -1096,7 +1262,7 @@ __global__ void __launch_bounds__(256) k_ml_stats(const RepDev* __restrict__ rep
     }
 }
 
-size_t mlp_lds_bytes() { return sizeof(MlpLds) + sizeof(float4) * kMlpWaves * (kMlFeat + kMlHidden); }
+size_t mfma_lds_bytes() { return sizeof(MfmaLds) + sizeof(float) * 32 * kTS * kMfmaWaves; }
 size_t train_lds_bytes() { return sizeof(MlpLds) + sizeof(float) * kMlpWaves * 4 * kMlFeat; }
 
 // Dynamic LDS above the default limit; once per kernel (done is the caller's flag).
@@ -1131,19 +1297,22 @@ void launch_ml_forward(hipStream_t st, bool fp64, const RepDev* reps, const MlDe
                        int n_mblocks, int n_rep, int32_t* status, StepRef sync)
 {
     if (n_cblocks <= 0) return;
-    const size_t lds = mlp_lds_bytes();
+    const size_t lds = mfma_lds_bytes();
     static bool lds_set = false;
-    allow_lds(k_ml_mlp, lds, lds_set);
-    const int mgrid = n_mblocks < 256 ? n_mblocks : 256;
+    allow_lds(k_ml_mlp_mfma, lds, lds_set);
+    const int tiles4 = (2 * n_mblocks + kMfmaWaves - 1) / kMfmaWaves;
+    const int mgrid = tiles4 < 256 ? tiles4 : 256;
     if (fp64) {
         launch(k_ml_desc<double>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks,
                n_rep, status, sync);
-        launch(k_ml_mlp, dim3(mgrid), dim3(1024), (uint32_t)lds, st, reps, m, mblocks, n_mblocks);
+        launch(k_ml_mlp_mfma, dim3(mgrid), dim3(256), (uint32_t)lds, st, reps, m, mblocks,
+               n_mblocks);
         launch(k_ml_pair<double>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks, sync);
     } else {
         launch(k_ml_desc<float>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks,
                n_rep, status, sync);
-        launch(k_ml_mlp, dim3(mgrid), dim3(1024), (uint32_t)lds, st, reps, m, mblocks, n_mblocks);
+        launch(k_ml_mlp_mfma, dim3(mgrid), dim3(256), (uint32_t)lds, st, reps, m, mblocks,
+               n_mblocks);
         launch(k_ml_pair<float>, dim3(n_cblocks), dim3(256), 0, st, reps, m, cblocks, sync);
     }
 }

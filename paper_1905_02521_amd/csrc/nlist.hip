@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(256) k_tile_box(const RepDev* __restrict__ rep
 template <typename T>
 __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be, const int p,
                                             int32_t* __restrict__ status, double* tx, double* ty,
-                                            double* tz, double* td, double* dmax_s)
+                                            double* tz, double* td, double* dmax_s,
+                                            uint8_t* skip)
 {
     using T4 = typename Vec4<T>::type;
     const int N = R.N, P = R.P;
@@ -182,15 +183,50 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
     // tiles of 256 candidate atoms staged in LDS, shared by the 4 wavefronts;
     // a tile whose centroid bounds (widened by the spreads) are out of range
     // of all four atoms of the block is skipped, which leaves the entries and
-    // their order unchanged
-    for (int t0 = 0; t0 < N; t0 += kListTile) {
-        bool far = true;
-        if (active) {
-            const double* b = R.tbox + (size_t)(t0 / kListTile) * 8;
-            const double Rt = R.r_cs + devi + b[6];
-            far = box_dist2(xi, yi, zi, b, Lx, Ly, Lz, iLx, iLy, iLz) >= Rt * Rt;
+    // their order unchanged.  The block first tests every tile (one thread
+    // per tile) and keeps the verdicts in LDS.
+    const int n_t = (N + kListTile - 1) / kListTile;
+    const bool pre = n_t <= kMaxListTiles;
+    if (pre) {
+        // centroids and spreads of the block's atoms (block-uniform loads)
+        double ax[4], ay[4], az[4], ad[4];
+        bool av[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int a = be.atom0 + w;
+            av[w] = a < N;
+            const int ac = av[w] ? a : be.atom0;
+            ax[w] = cx[ac];
+            ay[w] = cy[ac];
+            az[w] = cz[ac];
+            ad[w] = devp[ac];
         }
-        if (__syncthreads_and(far)) continue;
+        for (int t = threadIdx.x; t < n_t; t += blockDim.x) {
+            const double* b = R.tbox + (size_t)t * 8;
+            bool far = true;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const double Rt = R.r_cs + ad[w] + b[6];
+                far = far && (!av[w] ||
+                              box_dist2(ax[w], ay[w], az[w], b, Lx, Ly, Lz, iLx, iLy, iLz) >= Rt * Rt);
+            }
+            skip[t] = far ? 1 : 0;
+        }
+        __syncthreads();
+    }
+    for (int t0 = 0; t0 < N; t0 += kListTile) {
+        if (pre) {
+            if (skip[t0 / kListTile]) continue;  // the same verdict in every thread
+            __syncthreads();
+        } else {
+            bool far = true;
+            if (active) {
+                const double* b = R.tbox + (size_t)(t0 / kListTile) * 8;
+                const double Rt = R.r_cs + devi + b[6];
+                far = box_dist2(xi, yi, zi, b, Lx, Ly, Lz, iLx, iLy, iLz) >= Rt * Rt;
+            }
+            if (__syncthreads_and(far)) continue;
+        }
         const int jl = t0 + threadIdx.x;
         if (jl < N) {
             tx[threadIdx.x] = cx[jl];
@@ -246,8 +282,8 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
     }
 }
 
-// Grid-stride over the block table with at most a few hundred workgroups, so
-// the launch of a step that needs no rebuild costs one flag load per group.
+// Grid-stride over the block table with at most 2048 workgroups, so the
+// launch of a step that needs no rebuild costs one flag load per group.
 template <typename T>
 __global__ void __launch_bounds__(256) k_nlist(const RepDev* __restrict__ reps,
                                                const BlockEntry* __restrict__ blocks,
@@ -255,6 +291,7 @@ __global__ void __launch_bounds__(256) k_nlist(const RepDev* __restrict__ reps,
                                                const StepRef sync)
 {
     __shared__ double tx[256], ty[256], tz[256], td[256];
+    __shared__ uint8_t skip[kMaxListTiles];
     __shared__ double dmax_s[4];
     const StepIdx si = step_index(sync);
     if (status[kAnyRebuild + si.f] == 0) return;  // nothing to do: one load, then exit
@@ -262,7 +299,7 @@ __global__ void __launch_bounds__(256) k_nlist(const RepDev* __restrict__ reps,
         const BlockEntry be = blocks[e];
         const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
         if (R.rflag[si.f] == 0) continue;  // uniform over the block
-        nlist_entry<T>(R, be, si.p, status, tx, ty, tz, td, dmax_s);
+        nlist_entry<T>(R, be, si.p, status, tx, ty, tz, td, dmax_s, skip);
         __syncthreads();
     }
 }
@@ -294,7 +331,9 @@ void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntr
         launch(k_centroids, dim3(n_blocks), dim3(64), 0, st, reps, blocks, sync);
     launch(k_tile_box, dim3(n_tiles < 256 ? n_tiles : 256), dim3(256), 0, st, reps, tiles,
            n_tiles, status, sync);
-    const int grid = n_blocks < 256 ? n_blocks : 256;
+    // a list build is rare but long for large replicas: enough groups to
+    // fill the chip; a step without a rebuild costs one flag load per group
+    const int grid = n_blocks < 2048 ? n_blocks : 2048;
     if (fp64)
         launch(k_nlist<double>, dim3(grid), dim3(256), 0, st, reps, blocks, n_blocks, status, sync);
     else

@@ -137,6 +137,18 @@ struct MlDev {
     float nu0, da, eta_a;   // angular grid
 };
 
+// Workgroups are dealt to the 8 XCDs in turn (hardware block b runs on XCD
+// b % 8), each with its own L2.  Kernels that gather from neighbouring atoms
+// process table entry xcd_block() instead of blockIdx.x, so that each XCD
+// works through one contiguous eighth of the table and its L2 holds the
+// neighbours of its own region.  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int xcd_block()
+{
+    const int b = blockIdx.x, n = gridDim.x;
+    const int q = n >> 3, r = n & 7, x = b & 7, pos = b >> 3;
+    return x < r ? x * (q + 1) + pos : r * (q + 1) + (x - r) * q + pos;
+}
+
 // Work tables: replica and first atom per block (uniform per block).
 struct BlockEntry {
     int32_t rep;
@@ -166,6 +178,9 @@ enum StatusBits : int32_t {
 constexpr int kMaxImages = 8;
 // Candidate atoms per tile of the list kernel's scan (staged in LDS).
 constexpr int kListTile = 256;
+// Tiles whose out-of-range verdicts a list block precomputes in LDS (replicas
+// of up to kListTile * kMaxListTiles atoms; larger ones test tile by tile).
+constexpr int kMaxListTiles = 4096;
 // Replicas above this many atoms build their lists in the list kernel, whose
 // scan skips candidate tiles out of range by their bounding boxes; smaller
 // ones rebuild inside the force kernel (one launch less per step).
