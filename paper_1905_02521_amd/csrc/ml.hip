@@ -663,6 +663,7 @@ __global__ void __launch_bounds__(256) k_ml_mlp_mfma(const RepDev* __restrict__ 
 // in range are compacted first (ballot, LDS), so the lanes work on pairs
 // that count; their slots are kept for the gather.
 constexpr int kMaxStage = 512;  // in-range entries of one centre (<= maxml)
+constexpr int kRadWin = 7;      // radial channels on each side of the nearest (pair forces)
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_ml_pair(const RepDev* __restrict__ reps, const MlDev m,
@@ -689,6 +690,8 @@ __global__ void __launch_bounds__(256) k_ml_pair(const RepDev* __restrict__ reps
     const T4 ui = u[(size_t)i * P + s];
     const int cnt = R.ml_nc[i];
     const float rc = m.r_cut;
+    const float idr = 1.0f / m.dr;
+    const float em2 = fexp(-2.0f * m.eta_r * m.dr * m.dr);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int n = 0;
     for (int k0 = 0; k0 < cnt; k0 += 64) {
@@ -726,14 +729,36 @@ __global__ void __launch_bounds__(256) k_ml_pair(const RepDev* __restrict__ reps
         const float ang = kPiF * r / rc;
         const float fc = 0.5f * (__cosf(ang) + 1.0f);
         const float dfc = -0.5f * kPiF / rc * __sinf(ang);
-        // radial: dE/dr = sum_c g_c e_c (-2 eta (r - mu_c) f_c + f_c')
+        // radial: dE/dr = sum_c g_c e_c (-2 eta (r - mu_c) f_c + f_c'), over the
+        // channels within kRadWin spacings of r (the others are below
+        // e^{-eta (kRadWin dr)^2} = e^{-24.5} of the nearest).  From the
+        // nearest channel outwards, e_{c+-1} = e_c q and q changes by the
+        // factor e^{-2 eta dr^2} per channel, so three exponentials serve all.
         float S0 = 0.f, S1 = 0.f;
-#pragma unroll 8
-        for (int c = 0; c < kMlRad; ++c) {
-            const float x = r - (m.mu0 + m.dr * c);
-            const float ge = g[c] * fexp(-m.eta_r * x * x);
-            S0 += ge;
-            S1 += ge * x;
+        {
+            const int cn = min(max((int)rintf((r - m.mu0) * idr), 0), kMlRad - 1);
+            const float x0 = r - (m.mu0 + m.dr * cn);
+            const float e0 = fexp(-m.eta_r * x0 * x0);
+            const float b = 2.0f * m.eta_r * m.dr;
+            const float h = m.eta_r * m.dr * m.dr;
+            S0 = g[cn] * e0;
+            S1 = S0 * x0;
+            float eu = e0, qu = fexp(b * x0 - h), xu = x0;   // towards larger c
+            float ed = e0, qd = fexp(-b * x0 - h), xd = x0;  // towards smaller c
+#pragma unroll
+            for (int k = 1; k <= kRadWin; ++k) {
+                eu *= qu;
+                qu *= em2;
+                xu -= m.dr;
+                ed *= qd;
+                qd *= em2;
+                xd += m.dr;
+                const int cu = cn + k, cd = cn - k;
+                const float gu = cu < kMlRad ? g[min(cu, kMlRad - 1)] * eu : 0.0f;
+                const float gd = cd >= 0 ? g[max(cd, 0)] * ed : 0.0f;
+                S0 += gu + gd;
+                S1 += gu * xu + gd * xd;
+            }
         }
         float dEdr = -2.0f * m.eta_r * fc * S1 + dfc * S0;
         float ox = 0.f, oy = 0.f, oz = 0.f;  // terms off the pair axis
