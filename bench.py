@@ -97,11 +97,22 @@ def rocprof_summary(dirs):
     for d in dirs:
         stats = os.path.join(d, "run_kernel_stats.csv")
         if os.path.exists(stats):
-            out.append(f"| kernel | calls | avg us | min us | max us | % of GPU time |")
-            out.append("|---|---|---|---|---|---|")
+            # medians from the per-dispatch trace (the average includes the rare
+            # long launches, e.g. steps that rebuild neighbour lists)
+            med = {}
+            trace = os.path.join(d, "run_kernel_trace.csv")
+            if os.path.exists(trace):
+                durs = collections.defaultdict(list)
+                for r in csv.DictReader(open(trace)):
+                    durs[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+                med = {k: sorted(v)[len(v) // 2] for k, v in durs.items()}
+            out.append(f"| kernel | calls | avg us | median us | min us | max us | % of GPU time |")
+            out.append("|---|---|---|---|---|---|---|")
             for r in csv.DictReader(open(stats)):
+                m = med.get(r["Name"])
+                ms = f"{m / 1e3:.2f}" if m is not None else ""
                 out.append(f"| {_short_name(r['Name'])} | {r['Calls']} | "
-                           f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                           f"{float(r['AverageNs']) / 1e3:.2f} | {ms} | {float(r['MinNs']) / 1e3:.2f} | "
                            f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
         cc = os.path.join(d, "run_counter_collection.csv")
         if os.path.exists(cc):
