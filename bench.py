@@ -36,6 +36,14 @@ sys.path.insert(0, ROOT)
 # exp 2, erfc 1, r^-2 / r^-6 3, force magnitude 11, F/r 1, force on i 6,
 # reaction on j 3 (Newton's third law) -> 43 flops.
 FLOPS_PER_PAIR = 43
+# The same pair in VALU lane-slots (one per instruction, FMA fused; rsqrt,
+# the two exponentials and erfc at four slots each, quarter rate):
+# displacement 6, r^2 3, rsqrt 4, r 1, Buckingham exp 5, Gaussian exp 5,
+# erfc 4, r^-2 / r^-6 3, force magnitude 6, F/r 1, force on i 3, reaction 3
+# -> 44 slots.  Lane-slot peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no
+# packed FP32: the build disables it).
+SLOTS_PER_PAIR = 44
+PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
 # Algorithmic HBM bytes of the FIR per dof-step: one white-noise value read and
 # one coloured-noise value written, FP32 each.
 FIR_BYTES_PER_DOF_STEP = 8
@@ -517,7 +525,12 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": traffic["bytes"] if traffic else None,
                      "flops_per_launch": flops, "unique_pairs": pairs,
-                     "flops_per_pair": FLOPS_PER_PAIR, "ms_per_launch": force_ms},
+                     "flops_per_pair": FLOPS_PER_PAIR, "ms_per_launch": force_ms,
+                     "slot_roofline": {
+                         "slots_per_pair": SLOTS_PER_PAIR,
+                         "achieved_slots_per_s": pairs * SLOTS_PER_PAIR / (force_ms * 1e-3),
+                         "peak_slots_per_s": PEAK_LANE_SLOTS,
+                         "frac": pairs * SLOTS_PER_PAIR / (force_ms * 1e-3) / PEAK_LANE_SLOTS}},
         "fir": {"achieved_GBs": fir_gbs, "peak_GBs": PEAK_HBM_GBS,
                 "frac": (fir_gbs / PEAK_HBM_GBS) if fir_gbs else None,
                 "bytes_per_launch": fir_bytes,
