@@ -49,7 +49,12 @@ class Pot(ctypes.Structure):
                 ("buck_rho", ctypes.c_double * (MAX_SPECIES * MAX_SPECIES)),
                 ("buck_C", ctypes.c_double * (MAX_SPECIES * MAX_SPECIES)),
                 ("dsf_alpha", ctypes.c_double), ("r_cut", ctypes.c_double),
-                ("skin", ctypes.c_double)]
+                ("skin", ctypes.c_double),
+                ("os_V0", ctypes.c_double * MAX_SPECIES),
+                ("os_d", ctypes.c_double * MAX_SPECIES)]
+
+
+POT_PAIR, POT_HARMONIC, POT_MORSE, POT_DOUBLE_WELL = 0, 1, 2, 3
 
 
 _lib = None
@@ -115,7 +120,7 @@ def make_units(hbar, kB, coulomb_k=0.0, mass_unit=1.0) -> Units:
 
 
 def make_pot(kind=0, mass=(1.0,), charge=(0.0,), buck_A=None, buck_rho=None, buck_C=None,
-             dsf_alpha=0.0, r_cut=1.0, skin=0.0) -> Pot:
+             dsf_alpha=0.0, r_cut=1.0, skin=0.0, V0=None, d=None) -> Pot:
     ns = len(mass)
     p = Pot()
     p.kind = kind
@@ -128,6 +133,9 @@ def make_pot(kind=0, mass=(1.0,), charge=(0.0,), buck_A=None, buck_rho=None, buc
         p.buck_rho[ab] = buck_rho[ab] if buck_rho is not None else 1.0
         p.buck_C[ab] = buck_C[ab] if buck_C is not None else 0.0
     p.dsf_alpha, p.r_cut, p.skin = dsf_alpha, r_cut, skin
+    for a in range(ns):
+        p.os_V0[a] = V0[a] if V0 is not None else 0.0
+        p.os_d[a] = d[a] if d is not None else 1.0
     return p
 
 

@@ -511,6 +511,20 @@ static int nlist_stale(const orc_sim *s)
     return 0;
 }
 
+/* On-site potential of one dof and its force F = -dV/dx (the kinds above). */
+static double onsite_eval(const orc_pot *p, int sp, double x, double *F)
+{
+    double V0 = p->os_V0[sp], d = p->os_d[sp];
+    if (p->kind == ORC_POT_MORSE) {
+        double e = exp(-x / d);
+        *F = -2.0 * V0 * (1.0 - e) * e / d;
+        return V0 * (1.0 - e) * (1.0 - e);
+    }
+    double y = x / d, w = y * y - 1.0;  /* double well */
+    *F = -4.0 * V0 * w * y / d;
+    return V0 * w * w;
+}
+
 /* f = -grad V(r^(s)) for every bead s (physical force, no 1/P); epot[s] = V. */
 static void compute_forces(orc_sim *s)
 {
@@ -525,6 +539,20 @@ static void compute_forces(orc_sim *s)
                     double x = s->r[(b * dims + d) * N + i];
                     s->f[(b * dims + d) * N + i] = -k * x;
                     e += 0.5 * k * x * x;
+                }
+            s->epot[b] = e;
+        }
+        return;
+    }
+    if (s->pot.kind == ORC_POT_MORSE || s->pot.kind == ORC_POT_DOUBLE_WELL) {
+        for (int b = 0; b < P; ++b) {
+            double e = 0.0;
+            for (int d = 0; d < dims; ++d)
+                for (int i = 0; i < N; ++i) {
+                    double F;
+                    double x = s->r[(b * dims + d) * N + i];
+                    e += onsite_eval(&s->pot, s->species[i], x, &F);
+                    s->f[(b * dims + d) * N + i] = F;
                 }
             s->epot[b] = e;
         }

@@ -57,7 +57,11 @@ double orc_zeta(const double *h, int two_nf, uint64_t seed, uint32_t stream,
                 int64_t n, uint32_t d);
 
 /* ---------------------------------------------------------------- potential */
-enum { ORC_POT_PAIR = 0, ORC_POT_HARMONIC = 1 };
+/* On-site kinds (independent oscillators, every dof alone), per species V0, d:
+ *   MORSE        V(x) = V0 (1 - exp(-x/d))^2         (well at x = 0)
+ *   DOUBLE_WELL  V(x) = V0 ((x/d)^2 - 1)^2           (wells at x = +-d)
+ * The anharmonicity of eq. (13) is C = hbar^2 / (2 m V0 d^2). */
+enum { ORC_POT_PAIR = 0, ORC_POT_HARMONIC = 1, ORC_POT_MORSE = 2, ORC_POT_DOUBLE_WELL = 3 };
 #define ORC_MAX_SPECIES 4
 typedef struct {
     int kind;
@@ -68,6 +72,8 @@ typedef struct {
     double buck_rho[ORC_MAX_SPECIES * ORC_MAX_SPECIES];
     double buck_C[ORC_MAX_SPECIES * ORC_MAX_SPECIES];
     double dsf_alpha, r_cut, skin;
+    double os_V0[ORC_MAX_SPECIES];  /* on-site kinds: energy scale */
+    double os_d[ORC_MAX_SPECIES];   /* on-site kinds: length scale */
 } orc_pot;
 
 /* Buckingham (shifted force) + damped shifted force Coulomb, summed over every

@@ -84,3 +84,44 @@ def ho_energy_discrete(omega, m, P, kT, hbar, gamma, dt, taps):
         x2 += q2
         ke += 0.5 * m * v2
     return E, x2 / P, ke
+
+
+# ------------------------------------------------------------ anharmonic 1D
+def morse_potential(x, V0, d):
+    return V0 * (1.0 - np.exp(-x / d)) ** 2
+
+
+def double_well_potential(x, V0, d):
+    return V0 * ((x / d) ** 2 - 1.0) ** 2
+
+
+def schrodinger_levels(V, m, hbar, x):
+    """Eigenvalues of -hbar^2/(2m) d^2/dx^2 + V(x) on the uniform grid x with
+    zero boundary values (second-order finite differences, symmetric
+    tridiagonal, scipy eigh_tridiagonal)."""
+    from scipy.linalg import eigh_tridiagonal
+    h = x[1] - x[0]
+    t = hbar * hbar / (2.0 * m * h * h)
+    return eigh_tridiagonal(2.0 * t + V, -t * np.ones(len(x) - 1), eigvals_only=True)
+
+
+def quantum_mean_energy(levels, kT):
+    """Canonical <E> = sum E_n e^{-E_n/kT} / Z over the given levels."""
+    w = np.exp(-(levels - levels[0]) / kT)
+    return float(np.sum(levels * w) / np.sum(w))
+
+
+def morse_levels_exact(V0, d, m, hbar, n_max):
+    """Textbook bound-state energies of the Morse oscillator (measured from
+    the well bottom): E_n = hw (n + 1/2) - (hw)^2 (n + 1/2)^2 / (4 V0),
+    w = sqrt(2 V0 / (m d^2)), for n below the dissociation limit."""
+    w = math.sqrt(2.0 * V0 / (m * d * d))
+    n = np.arange(n_max)
+    return hbar * w * (n + 0.5) - (hbar * w) ** 2 * (n + 0.5) ** 2 / (4.0 * V0)
+
+
+def classical_mean(V, f, x, kT):
+    """Classical canonical <f(x)> for one dof with potential V on the grid x
+    (trapezoid rule)."""
+    w = np.exp(-(V - V.min()) / kT)
+    return float(np.trapezoid(f * w, x) / np.trapezoid(w, x))
