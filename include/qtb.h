@@ -76,8 +76,10 @@ typedef enum {
 } qtb_fir;
 
 typedef enum {
-    QTB_POT_PAIR = 0,     /* Buckingham + damped shifted force Coulomb, 3D, periodic */
-    QTB_POT_HARMONIC = 1  /* independent oscillators V = 1/2 m omega_i^2 x^2 per dof  */
+    QTB_POT_PAIR = 0,        /* Buckingham + damped shifted force Coulomb, 3D, periodic */
+    QTB_POT_HARMONIC = 1,    /* independent oscillators V = 1/2 m omega_i^2 x^2 per dof  */
+    QTB_POT_MORSE = 2,       /* independent dofs, V = V0 (1 - exp(-x/d))^2              */
+    QTB_POT_DOUBLE_WELL = 3  /* independent dofs, V = V0 ((x/d)^2 - 1)^2               */
 } qtb_pot_kind;
 
 #define QTB_MAX_SPECIES 4
@@ -87,7 +89,10 @@ typedef enum {
  * potential; the pair kind is V = sum_pairs [Buckingham in shifted-force form
  * at r_cut: A exp(-r/rho) - C/r^6] + damped shifted force Coulomb (alpha,
  * r_cut) including its self term.  Pairs are summed over every periodic
- * image within r_cut (boxes smaller than 2 r_cut are handled).
+ * image within r_cut (boxes smaller than 2 r_cut are handled).  The Morse and
+ * double-well kinds are the one-dimensional anharmonic models of Sec. 3: every
+ * dof is an independent oscillator with the anharmonicity
+ * C = hbar^2 / (2 m V0 d^2) of eq. 13; like the harmonic kind they take no box.
  * Host pointers; copied at qtb_init.
  */
 typedef struct {
@@ -101,6 +106,8 @@ typedef struct {
     double dsf_alpha;          /* damping parameter, 1/length                   */
     double r_cut;              /* cut-off, > 0                                  */
     double skin;               /* Verlet skin, >= 0                             */
+    const double *onsite_V0;   /* [n_species] energy, > 0 (Morse, double well)  */
+    const double *onsite_d;    /* [n_species] length, > 0 (Morse, double well)  */
 } qtb_potential;
 
 /*

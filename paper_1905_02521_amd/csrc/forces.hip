@@ -663,11 +663,31 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
     if (flags & kSample) block_partials(ob, wave, lane, lb, red, partials);
 }
 
-// Independent oscillators: V = sum_i 1/2 m omega_i^2 |x_i|^2 per bead.
-template <typename T>
-__global__ void __launch_bounds__(256) k_force_harmonic(const RepDev* __restrict__ reps,
-                                                        const BlockEntry* __restrict__ blocks,
-                                                        int32_t flags, double* __restrict__ partials)
+// On-site potential of one dof, V(x) and F = -dV/dx (FP64): harmonic with
+// k = m omega_i^2, Morse V0 (1 - e^{-x/d})^2, double well V0 ((x/d)^2 - 1)^2.
+template <int KIND>
+__device__ __forceinline__ double onsite(double x, double k, double V0, double d, double& F)
+{
+    if constexpr (KIND == QTB_POT_HARMONIC) {
+        F = -k * x;
+        return 0.5 * k * x * x;
+    } else if constexpr (KIND == QTB_POT_MORSE) {
+        const double e = exp(-x / d);
+        F = -2.0 * V0 * (1.0 - e) * e / d;
+        return V0 * (1.0 - e) * (1.0 - e);
+    } else {
+        const double y = x / d, w = y * y - 1.0;
+        F = -4.0 * V0 * w * y / d;
+        return V0 * w * w;
+    }
+}
+
+// Independent oscillators (every dof alone): V = sum over dofs of the
+// on-site potential per bead.
+template <typename T, int KIND>
+__global__ void __launch_bounds__(256) k_force_onsite(const RepDev* __restrict__ reps,
+                                                      const BlockEntry* __restrict__ blocks,
+                                                      int32_t flags, double* __restrict__ partials)
 {
     __shared__ double red[4][kNobs];
     const BlockEntry be = blocks[blockIdx.x];
@@ -677,8 +697,9 @@ __global__ void __launch_bounds__(256) k_force_harmonic(const RepDev* __restrict
     double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (i < N) {
         const int sp = R.species[i];
-        const double m = R.mmu[sp], w = R.homega[i], kick = R.kick[sp];
-        const double k = m * w * w;
+        const double m = R.mmu[sp], kick = R.kick[sp];
+        const double k = KIND == QTB_POT_HARMONIC ? m * R.homega[i] * R.homega[i] : 0.0;
+        const double V0 = R.osV0[sp], dl = R.osd[sp];
         double ke = 0.0, U = 0.0, spr = 0.0, vir = 0.0, x2 = 0.0;
         for (int a = 0; a < dims; ++a) {
             double c = 0.0;
@@ -687,7 +708,8 @@ __global__ void __launch_bounds__(256) k_force_harmonic(const RepDev* __restrict
             for (int s = 0; s < P; ++s) {
                 const size_t idx = ((size_t)s * dims + a) * N + i;
                 const double x = R.pos[idx];
-                const double f = -k * x;
+                double f;
+                const double Vx = onsite<KIND>(x, k, V0, dl, f);
                 ((T*)R.force)[idx] = (T)f;
                 double v = R.vel[idx];
                 if (flags & kKick) {
@@ -699,13 +721,13 @@ __global__ void __launch_bounds__(256) k_force_harmonic(const RepDev* __restrict
                     const double dn = x - R.pos[((size_t)sn * dims + a) * N + i];
                     const double d0 = x - R.r0[idx];
                     ke += 0.5 * m * v * v;
-                    U += 0.5 * k * x * x;
+                    U += Vx;
                     spr += dn * dn;
                     vir += (x - c) * f;
                     x2 += d0 * d0;
                     if (flags & kEvaluate) {
                         double* ea = R.eatom + (size_t)s * N + i;
-                        *ea = (a == 0 ? 0.0 : *ea) + 0.5 * k * x * x;
+                        *ea = (a == 0 ? 0.0 : *ea) + Vx;
                     }
                 }
             }
@@ -864,16 +886,30 @@ void launch_step_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* rep
     }
 }
 
-void launch_forces_harmonic(hipStream_t st, bool fp64, const RepDev* reps,
-                            const BlockEntry* blocks, int n_blocks, int32_t flags,
-                            double* partials)
+void launch_forces_onsite(hipStream_t st, bool fp64, int kind, const RepDev* reps,
+                          const BlockEntry* blocks, int n_blocks, int32_t flags,
+                          double* partials)
 {
-    if (fp64)
-        launch(k_force_harmonic<double>, dim3(n_blocks), dim3(256), 0, st, reps,
-                           blocks, flags, partials);
-    else
-        launch(k_force_harmonic<float>, dim3(n_blocks), dim3(256), 0, st, reps,
-                           blocks, flags, partials);
+    const dim3 g(n_blocks), b(256);
+    if (fp64) {
+        if (kind == QTB_POT_MORSE)
+            launch((k_force_onsite<double, QTB_POT_MORSE>), g, b, 0, st, reps, blocks, flags, partials);
+        else if (kind == QTB_POT_DOUBLE_WELL)
+            launch((k_force_onsite<double, QTB_POT_DOUBLE_WELL>), g, b, 0, st, reps, blocks, flags,
+                   partials);
+        else
+            launch((k_force_onsite<double, QTB_POT_HARMONIC>), g, b, 0, st, reps, blocks, flags,
+                   partials);
+    } else {
+        if (kind == QTB_POT_MORSE)
+            launch((k_force_onsite<float, QTB_POT_MORSE>), g, b, 0, st, reps, blocks, flags, partials);
+        else if (kind == QTB_POT_DOUBLE_WELL)
+            launch((k_force_onsite<float, QTB_POT_DOUBLE_WELL>), g, b, 0, st, reps, blocks, flags,
+                   partials);
+        else
+            launch((k_force_onsite<float, QTB_POT_HARMONIC>), g, b, 0, st, reps, blocks, flags,
+                   partials);
+    }
 }
 
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,

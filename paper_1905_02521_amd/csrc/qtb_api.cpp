@@ -88,11 +88,17 @@ const char* check_inputs(const qtb_potential* pot, const qtb_replica* reps, int 
 {
     if (!pot || !reps || !opt) return "null argument";
     if (n_rep < 1) return "n_rep must be >= 1";
-    if (pot->kind != QTB_POT_PAIR && pot->kind != QTB_POT_HARMONIC) return "unknown potential kind";
+    if (pot->kind < QTB_POT_PAIR || pot->kind > QTB_POT_DOUBLE_WELL) return "unknown potential kind";
     if (pot->n_species < 1 || pot->n_species > QTB_MAX_SPECIES) return "n_species out of range";
     if (!pot->mass) return "mass table missing";
     for (int a = 0; a < pot->n_species; ++a)
         if (!(pot->mass[a] > 0.0)) return "masses must be > 0";
+    if (pot->kind == QTB_POT_MORSE || pot->kind == QTB_POT_DOUBLE_WELL) {
+        if (!pot->onsite_V0 || !pot->onsite_d) return "on-site potential tables missing";
+        for (int a = 0; a < pot->n_species; ++a)
+            if (!(pot->onsite_V0[a] > 0.0) || !(pot->onsite_d[a] > 0.0))
+                return "onsite_V0 and onsite_d must be > 0";
+    }
     if (pot->kind == QTB_POT_PAIR) {
         if (!pot->charge || !pot->buck_A || !pot->buck_rho || !pot->buck_C)
             return "pair potential tables missing";
@@ -360,6 +366,8 @@ struct qtb_ctx {
     std::vector<qtb_replica> reps;
     std::vector<std::vector<int32_t>> species;
     std::vector<std::vector<double>> homega;
+    int kind = QTB_POT_PAIR;
+    std::vector<double> osV0, osd;  // on-site kinds, per species
     std::vector<double> mass, charge, bA, brho, bC;
     double alpha = 0, rc = 0, skin = 0;
     Layout L;
@@ -670,6 +678,8 @@ void fill_repdev(qtb_ctx* c, int r)
         d.mmu[a] = m;
         d.kick[a] = R.dt / (2.0 * R.n_beads * m);
         d.sigma[a] = std::sqrt((1.0 - d.c1 * d.c1) / m);
+        d.osV0[a] = a < (int)c->osV0.size() ? c->osV0[a] : 0.0;
+        d.osd[a] = a < (int)c->osd.size() ? c->osd[a] : 1.0;
     }
     d.seed = R.seed;
     d.stream = R.stream;
@@ -751,8 +761,8 @@ void launch_plain_forces(qtb_ctx* c, int32_t flags, bool inline_rebuild = false)
                                part + (size_t)b0 * kNobs, clear, c->n_rep,
                                c->at<int32_t>(L.status), step_ref(c));
         } else {
-            launch_forces_harmonic(c->st, c->fp64, dreps, fb + b0, nb, flags,
-                                   part + (size_t)b0 * kNobs);
+            launch_forces_onsite(c->st, c->fp64, c->kind, dreps, fb + b0, nb, flags,
+                                 part + (size_t)b0 * kNobs);
         }
     }
 }
@@ -1174,6 +1184,11 @@ qtb_status qtb_init(qtb_ctx** out, const qtb_potential* pot, const qtb_replica* 
     c->st = (hipStream_t)hip_stream;
     c->fp64 = opt->prec == QTB_PREC_FP64;
     c->pair = pot->kind == QTB_POT_PAIR;
+    c->kind = pot->kind;
+    if (!c->pair && pot->kind != QTB_POT_HARMONIC) {
+        c->osV0.assign(pot->onsite_V0, pot->onsite_V0 + pot->n_species);
+        c->osd.assign(pot->onsite_d, pot->onsite_d + pot->n_species);
+    }
     c->n_rep = n_rep;
     c->reps.assign(reps, reps + n_rep);
     const int ns = pot->n_species;
@@ -1219,7 +1234,8 @@ qtb_status qtb_init(qtb_ctx** out, const qtb_potential* pot, const qtb_replica* 
     for (int r = 0; r < n_rep; ++r) {
         const qtb_replica& R = reps[r];
         c->species[r].assign(R.species, R.species + R.n_atoms);
-        if (!c->pair) c->homega[r].assign(R.harm_omega, R.harm_omega + R.n_atoms);
+        if (c->kind == QTB_POT_HARMONIC) c->homega[r].assign(R.harm_omega, R.harm_omega + R.n_atoms);
+        else if (!c->pair) c->homega[r].assign(R.n_atoms, 0.0);
         fill_repdev(c, r);
         const Layout::Per& p = c->L.per[r];
         const int P = R.n_beads;

@@ -79,6 +79,8 @@ struct RepDev {
     double kick[kMaxSpecies];   // dt / (2 P m mu)
     double sigma[kMaxSpecies];  // sqrt((1 - c1^2) / (m mu))
     double mmu[kMaxSpecies];    // m mu
+    double osV0[kMaxSpecies];   // on-site kinds: energy scale V0
+    double osd[kMaxSpecies];    // on-site kinds: length scale d
     uint64_t seed;
     uint32_t stream;
     int32_t pad;
@@ -283,9 +285,9 @@ void launch_step_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* rep
                       const BlockEntry* blocks, int n_blocks, const void* table, int32_t flags,
                       double* partials, int n_rep, int32_t* status, StepRef sync,
                       const void* zeta_row);
-void launch_forces_harmonic(hipStream_t st, bool fp64, const RepDev* reps,
-                            const BlockEntry* blocks, int n_blocks, int32_t flags,
-                            double* partials);
+void launch_forces_onsite(hipStream_t st, bool fp64, int kind, const RepDev* reps,
+                          const BlockEntry* blocks, int n_blocks, int32_t flags,
+                          double* partials);
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
                        double* acc, int32_t* counts);
 void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value);

@@ -21,7 +21,7 @@ QTB_OK, QTB_E_INVALID, QTB_E_NOMEM, QTB_E_DEVICE, QTB_E_STATE, QTB_E_NONFINITE, 
 NOISE_CLASSICAL, NOISE_QTB, NOISE_QTB_PIMD = 0, 1, 2
 PREC_FP32, PREC_FP64 = 0, 1
 FIR_FP32, FIR_BF16X3, FIR_BF16, FIR_FP64 = 0, 1, 2, 3
-POT_PAIR, POT_HARMONIC = 0, 1
+POT_PAIR, POT_HARMONIC, POT_MORSE, POT_DOUBLE_WELL = 0, 1, 2, 3
 OPT_NO_GRAPH = 1
 OPT_NO_AUTOTUNE = 2
 OPT_ML_TRAIN = 4
@@ -50,7 +50,7 @@ class qtb_potential(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_species", ctypes.c_int32),
                 ("mass", _PD), ("charge", _PD), ("buck_A", _PD), ("buck_rho", _PD),
                 ("buck_C", _PD), ("dsf_alpha", ctypes.c_double), ("r_cut", ctypes.c_double),
-                ("skin", ctypes.c_double)]
+                ("skin", ctypes.c_double), ("onsite_V0", _PD), ("onsite_d", _PD)]
 
 
 class qtb_replica(ctypes.Structure):
@@ -244,6 +244,10 @@ class Context:
             pot.dsf_alpha = potential["dsf_alpha"]
             pot.r_cut = potential["r_cut"]
             pot.skin = potential["skin"]
+        elif pot.kind in (POT_MORSE, POT_DOUBLE_WELL):
+            tabs = [arr(potential[k]) for k in ("V0", "d")]
+            self._keep += tabs
+            pot.onsite_V0, pot.onsite_d = (_pd(t) for t in tabs)
         self.pot = pot
         self.n_rep = len(replicas)
         self.reps = (qtb_replica * self.n_rep)()

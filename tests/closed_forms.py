@@ -125,3 +125,16 @@ def classical_mean(V, f, x, kT):
     (trapezoid rule)."""
     w = np.exp(-(V - V.min()) / kT)
     return float(np.trapezoid(f * w, x) / np.trapezoid(w, x))
+
+
+def quantum_mean_potential(V, m, hbar, x, kT, n_levels):
+    """Canonical <V> and <E> from the lowest n_levels eigenpairs of the grid
+    Hamiltonian of schrodinger_levels (<n|V|n> as the grid sum of psi_n^2 V)."""
+    from scipy.linalg import eigh_tridiagonal
+    h = x[1] - x[0]
+    t = hbar * hbar / (2.0 * m * h * h)
+    E, psi = eigh_tridiagonal(2.0 * t + V, -t * np.ones(len(x) - 1), select="i",
+                              select_range=(0, n_levels - 1))
+    Vn = np.sum(psi * psi * V[:, None], axis=0) / np.sum(psi * psi, axis=0)
+    w = np.exp(-(E - E[0]) / kT)
+    return float(np.sum(Vn * w) / np.sum(w)), float(np.sum(E * w) / np.sum(w))
