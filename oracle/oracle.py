@@ -139,6 +139,33 @@ def make_pot(kind=0, mass=(1.0,), charge=(0.0,), buck_A=None, buck_rho=None, buc
     return p
 
 
+# ---------------------------------------------------------------- spectra
+def vdos(v, seg, weight=None):
+    """Velocity density of states from the velocity time series, the
+    time-correlation route that Sec. 3 names as QTB's advantage: by the
+    Wiener-Khinchin theorem the power spectrum of v is the Fourier transform
+    of its autocorrelation.  v[t, j] holds dof j at sample t; the series is
+    cut into whole segments of seg samples (a trailing part is dropped), and
+    each segment's periodogram |V_k|^2 / seg, V_k = sum_t v_t e^{-2 pi i k t /
+    seg}, is weighted by weight[j] (masses: 1 if None), summed over dofs and
+    averaged over segments.  Returns (phi_k, S_k) for k = 0 .. seg/2, phi_k =
+    2 pi k / seg in radians per sample, and the number of segments; the mean
+    of S over all seg frequencies (both halves) is sum_j weight_j <v_j^2>, so
+    with masses as weights it is twice the mean kinetic energy."""
+    v = np.asarray(v, dtype=np.float64)
+    if v.ndim == 1:
+        v = v[:, None]
+    n_seg = v.shape[0] // seg
+    w = np.ones(v.shape[1]) if weight is None else np.asarray(weight, dtype=np.float64)
+    S = np.zeros(seg // 2 + 1)
+    for q in range(n_seg):
+        V = np.fft.rfft(v[q * seg:(q + 1) * seg], axis=0)
+        S += (np.abs(V) ** 2 / seg) @ w
+    if n_seg:
+        S /= n_seg
+    return 2.0 * np.pi * np.arange(seg // 2 + 1) / seg, S, n_seg
+
+
 # ---------------------------------------------------------------- functions
 def theta(omega, T, units: Units):
     return lib().orc_theta(float(omega), float(T), ctypes.byref(units))

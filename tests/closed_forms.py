@@ -138,3 +138,22 @@ def quantum_mean_potential(V, m, hbar, x, kT, n_levels):
     Vn = np.sum(psi * psi * V[:, None], axis=0) / np.sum(psi * psi, axis=0)
     w = np.exp(-(E - E[0]) / kT)
     return float(np.sum(Vn * w) / np.sum(w)), float(np.sum(E * w) / np.sum(w))
+
+
+# ------------------------------------------------------- velocity spectrum
+def velocity_spectrum_discrete(M, b, taps, phi):
+    """Exact power spectrum of v_n for the discrete linear scheme
+    z_{n+1} = M z_n + b zeta_n, z = (x, v), driven by zeta = h * w (unit white
+    w): S_v(phi) = |[(e^{i phi} I - M)^{-1} b]_v|^2 |sum_k h_k e^{-i k phi}|^2,
+    normalised so that <v^2> = (1/2 pi) int_{-pi}^{pi} S_v d phi."""
+    taps = np.asarray(taps, dtype=np.float64)
+    L = len(taps)
+    k = np.arange(L) - L // 2   # taps h_k for k = -Nf .. Nf - 1
+    phi = np.asarray(phi, dtype=np.float64)
+    Hz = np.exp(-1j * np.outer(phi, k)) @ taps
+    out = np.empty(len(phi))
+    I = np.eye(2)
+    for q, p in enumerate(phi):
+        g = np.linalg.solve(np.exp(1j * p) * I - M, b)
+        out[q] = abs(g[1]) ** 2 * abs(Hz[q]) ** 2
+    return out
