@@ -251,6 +251,60 @@ qtb_status qtb_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0
                         void *hip_stream);
 
 /*
+ * Velocity density of states (Sec. 3: time-correlation functions are directly
+ * accessible in QTB-MD, unlike in PIMD and QTB-PIMD, and the vibrational DOS
+ * is the check to make when gamma is raised against zero-point-energy
+ * leakage).  By the Wiener-Khinchin theorem the spectrum of the velocity
+ * series is the Fourier transform of its autocorrelation; it is estimated by
+ * segment periodograms,
+ *   S_k = (1/n_seg) sum_segments sum_j w_j |sum_{t<seg} v_{t,j} e^{-2 pi i k t / seg}|^2 / seg,
+ * k = 0 .. seg/2 (frequency 2 pi k / (seg * sampling interval)), FP64, with
+ * w_j the mass of dof j (m * mass_unit, the energy units of qtb_obs): the
+ * mean of S over all seg frequencies (k and seg - k both counted) is then
+ * twice the mean kinetic energy of the sampled velocities.  seg: a power of
+ * two, 16..4096.
+ */
+
+/* Device bytes of a spectrum workspace for n_dof dofs: recorder = 1 for
+ * qtb_vdos_attach (two segments of trace, FP64), 0 for qtb_vdos_spectrum.
+ * 0 on bad input. */
+size_t qtb_vdos_workspace_bytes(int32_t n_dof, int32_t seg, int32_t recorder);
+
+/* The spectrum of a device series d_v [n_samples][n_dof] (FP64, row t =
+ * sample t) with device weights d_weight [n_dof], over its n_samples / seg
+ * whole segments (a trailing partial segment is ignored; with none, S = 0):
+ * d_spec (device, [seg/2 + 1]) receives S.  d_workspace: device, 256-byte
+ * aligned, qtb_vdos_workspace_bytes(n_dof, seg, 0) bytes.  Enqueued on
+ * hip_stream; returns without waiting. */
+qtb_status qtb_vdos_spectrum(const double *d_v, int64_t n_samples, int32_t n_dof,
+                             const double *d_weight, int32_t seg, double *d_spec,
+                             void *d_workspace, size_t ws_bytes, void *hip_stream);
+
+/* Attach a velocity recorder to a replica with P = 1 (QTB_E_INVALID for
+ * P > 1: ring-polymer bead velocities carry no physical time correlations).
+ * From now on every observable sample (every obs_every steps; QTB_E_STATE
+ * when obs_every is 0) also stores the replica's velocities [n_dims][N] in
+ * the recorder's trace, and each completed segment of seg samples is
+ * transformed on the context's stream during qtb_step.  Requires
+ * seg * obs_every >= fir_block_K.  d_workspace: device, 256-byte aligned,
+ * qtb_vdos_workspace_bytes(n_dims N, seg, 1) bytes, caller-owned, in use
+ * until qtb_vdos_detach.  Attaching again replaces the recorder.
+ * qtb_set_state of the replica restarts it (the series is cut there). */
+qtb_status qtb_vdos_attach(qtb_ctx *ctx, int32_t replica, int32_t seg, void *d_workspace,
+                           size_t ws_bytes);
+
+/* Synchronise and return the replica's spectrum S (host [seg/2 + 1], zeros
+ * before the first complete segment) averaged over the n_seg segments since
+ * the recorder (re)started; restart != 0 then starts afresh (dropping a
+ * partly filled segment).  Status errors as qtb_observables.  Either output
+ * may be NULL. */
+qtb_status qtb_vdos_read(qtb_ctx *ctx, int32_t replica, double *h_spec, int64_t *n_seg,
+                         int32_t restart);
+
+/* Stop recording (synchronises; the workspace is the caller's again). */
+qtb_status qtb_vdos_detach(qtb_ctx *ctx, int32_t replica);
+
+/*
  * Diagnostics: while enabled, qtb_step records a HIP event pair around every
  * kernel phase on the context's stream (steps then run without graph
  * replay).  qtb_profile_read synchronises and returns, per phase, the total

@@ -21,7 +21,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libqtb.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["noise.hip", "fir.hip", "update.hip", "nlist.hip", "forces.hip", "ml.hip",
+SOURCES = ["noise.hip", "fir.hip", "update.hip", "nlist.hip", "forces.hip", "ml.hip", "vdos.hip",
            "filter_design.cpp", "qtb_api.cpp"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -24,7 +24,8 @@ struct GlobalState {
 // e_atom: this atom's share of the bead potential V(r^(s)).
 // ob (kNobs slots): kinetic, V/P, spring, virial, x^2 in kSample mode;
 // |F - F_stored|^2 and |F|^2 in kCompare mode (nothing is written then).
-// vn receives the velocity after the kick; STORE_V: write it back.
+// vn receives the velocity after the kick; STORE_V: write it back.  A sample
+// also stores vn into the replica's velocity recorder, if one is attached.
 template <typename T, bool STORE_V = true, typename Src>
 __device__ __forceinline__ void force_epilogue_src(const RepDev& R, int i, int s, int spi,
                                                    const double f[3], double e_atom,
@@ -78,6 +79,11 @@ __device__ __forceinline__ void force_epilogue_src(const RepDev& R, int i, int s
         ob[2] = (P > 1) ? 0.5 * m * R.omega_P * R.omega_P * spr : 0.0;
         ob[3] = vir;
         ob[4] = x2;
+        if (R.vt) {  // velocity recorder (P = 1)
+            const size_t row = (size_t)(*R.vt_n % R.vt_cap);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) R.vt[(row * 3 + a) * N + i] = vn[a];
+        }
     }
 }
 

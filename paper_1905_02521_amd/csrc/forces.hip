@@ -700,6 +700,9 @@ __global__ void __launch_bounds__(256) k_force_onsite(const RepDev* __restrict__
         const double m = R.mmu[sp], kick = R.kick[sp];
         const double k = KIND == QTB_POT_HARMONIC ? m * R.homega[i] * R.homega[i] : 0.0;
         const double V0 = R.osV0[sp], dl = R.osd[sp];
+        double* vrow = ((flags & kSample) && R.vt)
+                           ? R.vt + (size_t)(*R.vt_n % R.vt_cap) * dims * N + i
+                           : nullptr;  // velocity recorder (P = 1)
         double ke = 0.0, U = 0.0, spr = 0.0, vir = 0.0, x2 = 0.0;
         for (int a = 0; a < dims; ++a) {
             double c = 0.0;
@@ -716,6 +719,7 @@ __global__ void __launch_bounds__(256) k_force_onsite(const RepDev* __restrict__
                     v += kick * f;
                     R.vel[idx] = v;
                 }
+                if (vrow) vrow[(size_t)a * N] = v;
                 if (flags & (kSample | kEvaluate)) {
                     const int sn = (s + 1 == P) ? 0 : s + 1;
                     const double dn = x - R.pos[((size_t)sn * dims + a) * N + i];
@@ -761,7 +765,7 @@ __global__ void __launch_bounds__(256) k_force_onsite(const RepDev* __restrict__
 __global__ void __launch_bounds__(256) k_obs_reduce(const RepDev* __restrict__ reps, int n_rep,
                                                     const double* __restrict__ partials,
                                                     double* __restrict__ acc,
-                                                    int32_t* __restrict__ counts)
+                                                    int32_t* __restrict__ counts, int tick)
 {
     __shared__ double red[kNobs][256];
     const int r = blockIdx.x;
@@ -778,7 +782,10 @@ __global__ void __launch_bounds__(256) k_obs_reduce(const RepDev* __restrict__ r
         __syncthreads();
     }
     if (threadIdx.x < kNobs) acc[(size_t)r * kNobs + threadIdx.x] += red[threadIdx.x][0];
-    if (threadIdx.x == 0) counts[r] += 1;
+    if (threadIdx.x == 0) {
+        counts[r] += 1;
+        if (tick && R.vt) *R.vt_n += 1;  // the forces of this sample wrote its row
+    }
 }
 
 __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v)
@@ -913,9 +920,10 @@ void launch_forces_onsite(hipStream_t st, bool fp64, int kind, const RepDev* rep
 }
 
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
-                       double* acc, int32_t* counts)
+                       double* acc, int32_t* counts, bool tick)
 {
-    launch(k_obs_reduce, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, acc, counts);
+    launch(k_obs_reduce, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, acc, counts,
+           tick ? 1 : 0);
 }
 
 void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value)

@@ -358,6 +358,51 @@ std::string g_static_err;
 }  // namespace
 
 // ------------------------------------------------------------------ context
+namespace {
+// Byte offsets of a velocity-spectrum workspace (the recorder's, or the
+// standalone transform's without trace, weights and counter).
+struct VdosLayout {
+    size_t trace = 0, spec = 0, part = 0, tw = 0, w = 0, cnt = 0, total = 0;
+};
+
+VdosLayout vdos_layout(int n_dof, int seg, bool recorder)
+{
+    const VdosPlan p = vdos_plan(n_dof, seg);
+    VdosLayout l;
+    size_t cur = 0;
+    auto take = [&cur](size_t bytes) {
+        const size_t o = cur;
+        cur += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    l.part = take(8 * (size_t)p.grid * p.nk);
+    l.tw = take(16 * (size_t)(seg / 2));
+    if (recorder) {
+        l.trace = take(8 * 2 * (size_t)seg * n_dof);
+        l.spec = take(8 * (size_t)p.nk);
+        l.w = take(8 * (size_t)n_dof);
+        l.cnt = take(8);
+    }
+    l.total = cur;
+    return l;
+}
+
+// Velocity recorder of one replica, in the caller's device buffer.  The
+// trace holds two segments: a segment is transformed once complete, while
+// the steps go on filling the other half.
+struct VdosRec {
+    bool on = false;
+    char* ws = nullptr;
+    VdosPlan plan{};
+    VdosLayout lay{};
+    int n_dof = 0;
+    int64_t start = 0;  // global step of the (re)start: samples count from there
+    int64_t n_seg = 0;  // segments transformed since
+    template <typename X>
+    X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
+};
+}  // namespace
+
 struct qtb_ctx {
     qtb_options opt{};
     hipStream_t st = nullptr;
@@ -397,6 +442,7 @@ struct qtb_ctx {
     // one-kernel steps: a step's closing half-kick is pending (open) between
     // the step kernels of one qtb_step call; the call ends with a force pass
     bool open = false;
+    std::vector<VdosRec> vdos;  // per replica
     // step of the kernels being recorded: host step (rec_row < 0), or the
     // device clock (first step of the noise block) + rec_row + rec_extra
     int rec_row = -1, rec_extra = 0;
@@ -894,12 +940,12 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
     if (sample) {
         Phase ph(c, 5);
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
-                          c->at<int32_t>(L.counts));
+                          c->at<int32_t>(L.counts), true);
     }
     if (check) {  // the pair potential judges the surrogate on the same positions
         launch_plain_forces(c, kCompare);
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials),
-                          c->at<double>(L.ml_acc), c->at<int32_t>(L.ml_counts));
+                          c->at<double>(L.ml_acc), c->at<int32_t>(L.ml_counts), false);
     }
     c->rec_row = -1;
     c->rec_extra = 0;
@@ -966,7 +1012,7 @@ void record_fused(qtb_ctx* c, int row, bool sample_prev)
     if (sample_prev) {
         Phase ph(c, 5);
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
-                          c->at<int32_t>(L.counts));
+                          c->at<int32_t>(L.counts), true);
     }
     c->rec_row = -1;
 }
@@ -988,7 +1034,7 @@ void close_steps(qtb_ctx* c)
     if (sample) {
         Phase ph(c, 5);
         launch_obs_reduce(c->st, c->at<RepDev>(L.reps), c->n_rep, c->at<double>(L.partials),
-                          c->at<double>(L.acc), c->at<int32_t>(L.counts));
+                          c->at<double>(L.acc), c->at<int32_t>(L.counts), true);
     }
     c->open = false;
 }
@@ -1159,6 +1205,45 @@ qtb_status autotune(qtb_ctx* c)
 }  // namespace
 
 // ====================================================================== ABI
+namespace {
+int64_t floor_div(int64_t a, int64_t b)
+{
+    const int64_t q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+// Transform every recorder segment completed by the work enqueued so far.
+// The samples of steps before the last one are complete; so is the last
+// step's unless its closing force pass is still pending (one-kernel steps).
+void vdos_flush(qtb_ctx* c)
+{
+    const int64_t end = c->step - (c->open ? 1 : 0);
+    for (int r = 0; r < c->n_rep; ++r) {
+        VdosRec& v = c->vdos[r];
+        if (!v.on || end <= v.start) continue;
+        const int64_t e = c->opt.obs_every;
+        const int64_t done = floor_div(end, e) - floor_div(v.start, e);  // steps s with (s + 1) % e == 0
+        const int seg = v.plan.seg;
+        while (v.n_seg < done / seg) {
+            const double* base = v.at<double>(v.lay.trace) + (size_t)(v.n_seg & 1) * seg * v.n_dof;
+            launch_vdos_segment(c->st, v.plan, base, v.n_dof, v.at<double>(v.lay.w),
+                                v.at<double>(v.lay.tw), v.at<double>(v.lay.part),
+                                v.at<double>(v.lay.spec), 1.0 / seg, v.n_seg > 0);
+            ++v.n_seg;
+        }
+    }
+}
+
+void vdos_restart(qtb_ctx* c, int r)
+{
+    VdosRec& v = c->vdos[r];
+    launch_fill(c->st, v.at<void>(v.lay.cnt), 2, 0);
+    launch_fill(c->st, v.at<void>(v.lay.spec), 2 * (int64_t)v.plan.nk, 0);
+    v.start = c->step;
+    v.n_seg = 0;
+}
+}  // namespace
+
 extern "C" {
 
 size_t qtb_workspace_bytes(const qtb_potential* pot, const qtb_replica* reps, int32_t n_rep,
@@ -1216,6 +1301,7 @@ qtb_status qtb_init(qtb_ctx** out, const qtb_potential* pot, const qtb_replica* 
     c->taps.assign(n_rep, {});
     c->eself.assign(n_rep, 0.0);
     c->rd.assign(n_rep, RepDev{});
+    c->vdos.assign(n_rep, VdosRec{});
     c->species.resize(n_rep);
     c->homega.resize(n_rep);
     if (c->pair) {
@@ -1352,12 +1438,15 @@ qtb_status qtb_step(qtb_ctx* c, int64_t n_steps)
         const bool at_boundary = c->ring_valid && (c->block_start < 0 || c->block_row >= c->L.K);
         if (at_boundary && left >= c->L.K && graph_block(c)) {
             left -= c->L.K;
+            vdos_flush(c);
             continue;
         }
         one_step(c);
         left -= 1;
+        vdos_flush(c);
     }
     close_steps(c);
+    vdos_flush(c);
     QTB_HIP(c, hipGetLastError());
     return QTB_OK;
 }
@@ -1433,6 +1522,7 @@ qtb_status qtb_set_state(qtb_ctx* c, int32_t replica, const double* h_pos, const
         if (s) return s;
     }
     launch_fill(c->st, c->at<int32_t>(c->L.status), 1, 0);
+    if (c->vdos[replica].on) vdos_restart(c, replica);  // the series starts afresh
     qtb_status s = refresh_forces(c);
     if (s) return s;
     return read_status(c);
@@ -1499,6 +1589,116 @@ qtb_status qtb_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0
     launch_gaussian((hipStream_t)hip_stream, seed, stream, tag, n0, n_rows, d0, n_dof, d_out);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(nullptr, QTB_E_DEVICE, hipGetErrorString(e));
+    return QTB_OK;
+}
+
+size_t qtb_vdos_workspace_bytes(int32_t n_dof, int32_t seg, int32_t recorder)
+{
+    if (n_dof < 1 || seg < kVdosMinSeg || seg > kVdosMaxSeg || (seg & (seg - 1))) return 0;
+    return vdos_layout(n_dof, seg, recorder != 0).total;
+}
+
+qtb_status qtb_vdos_spectrum(const double* d_v, int64_t n_samples, int32_t n_dof,
+                             const double* d_weight, int32_t seg, double* d_spec, void* d_workspace,
+                             size_t ws_bytes, void* hip_stream)
+{
+    if (!d_v || !d_weight || !d_spec || n_samples < 0)
+        return fail(nullptr, QTB_E_INVALID, "bad spectrum arguments");
+    const size_t need = qtb_vdos_workspace_bytes(n_dof, seg, 0);
+    if (need == 0) return fail(nullptr, QTB_E_INVALID, "n_dof >= 1 and seg a power of two in [16, 4096]");
+    if (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < need)
+        return fail(nullptr, QTB_E_NOMEM, "spectrum workspace missing, misaligned or too small");
+    const hipStream_t st = (hipStream_t)hip_stream;
+    const VdosPlan p = vdos_plan(n_dof, seg);
+    const VdosLayout l = vdos_layout(n_dof, seg, false);
+    char* ws = (char*)d_workspace;
+    const int64_t n_seg = n_samples / seg;
+    if (n_seg == 0) {
+        launch_fill(st, d_spec, 2 * (int64_t)p.nk, 0);
+    } else {
+        launch_vdos_twiddle(st, (double*)(ws + l.tw), seg);
+        for (int64_t q = 0; q < n_seg; ++q)
+            launch_vdos_segment(st, p, d_v + (size_t)q * seg * n_dof, n_dof, d_weight,
+                                (const double*)(ws + l.tw), (double*)(ws + l.part), d_spec,
+                                1.0 / ((double)seg * (double)n_seg), q > 0);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, QTB_E_DEVICE, hipGetErrorString(e));
+    return QTB_OK;
+}
+
+qtb_status qtb_vdos_attach(qtb_ctx* c, int32_t replica, int32_t seg, void* d_workspace,
+                           size_t ws_bytes)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    const qtb_replica& R = c->reps[replica];
+    if (R.n_beads != 1)
+        return fail(c, QTB_E_INVALID,
+                    "velocity recorder needs P = 1: bead velocities carry no time correlations");
+    if (c->opt.obs_every <= 0)
+        return fail(c, QTB_E_STATE, "velocity recorder samples every obs_every steps, which is 0");
+    const int n_dof = R.n_dims * R.n_atoms;
+    const size_t need = qtb_vdos_workspace_bytes(n_dof, seg, 1);
+    if (need == 0) return fail(c, QTB_E_INVALID, "seg must be a power of two in [16, 4096]");
+    if ((int64_t)seg * c->opt.obs_every < c->L.K)
+        return fail(c, QTB_E_INVALID, "seg * obs_every must be at least fir_block_K");
+    if (!d_workspace || ((uintptr_t)d_workspace & 255) || ws_bytes < need)
+        return fail(c, QTB_E_NOMEM, "recorder workspace missing, misaligned or too small");
+    if (c->vdos[replica].on) QTB_HIP(c, hipStreamSynchronize(c->st));  // the old buffer's work
+    VdosRec& v = c->vdos[replica];
+    v = VdosRec{};
+    v.on = true;
+    v.ws = (char*)d_workspace;
+    v.plan = vdos_plan(n_dof, seg);
+    v.lay = vdos_layout(n_dof, seg, true);
+    v.n_dof = n_dof;
+    RepDev& d = c->rd[replica];
+    d.vt = v.at<double>(v.lay.trace);
+    d.vt_n = v.at<int64_t>(v.lay.cnt);
+    d.vt_cap = 2 * seg;
+    qtb_status s = upload_tables(c);
+    if (s) return s;
+    launch_vdos_twiddle(c->st, v.at<double>(v.lay.tw), seg);
+    launch_vdos_weights(c->st, c->at<RepDev>(c->L.reps), replica, n_dof, v.at<double>(v.lay.w));
+    vdos_restart(c, replica);
+    QTB_HIP(c, hipGetLastError());
+    return QTB_OK;
+}
+
+qtb_status qtb_vdos_read(qtb_ctx* c, int32_t replica, double* h_spec, int64_t* n_seg,
+                         int32_t restart)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    VdosRec& v = c->vdos[replica];
+    if (!v.on) return fail(c, QTB_E_STATE, "no velocity recorder attached to this replica");
+    std::vector<double> buf(v.plan.nk);
+    QTB_HIP(c, hipMemcpyAsync(buf.data(), v.at<double>(v.lay.spec), 8 * buf.size(),
+                              hipMemcpyDeviceToHost, c->st));
+    const qtb_status s = read_status(c);  // synchronises
+    const int64_t n = v.n_seg;
+    if (h_spec)
+        for (int k = 0; k < v.plan.nk; ++k) h_spec[k] = n > 0 ? buf[k] / (double)n : 0.0;
+    if (n_seg) *n_seg = n;
+    if (restart) vdos_restart(c, replica);
+    return s;
+}
+
+qtb_status qtb_vdos_detach(qtb_ctx* c, int32_t replica)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    if (!c->vdos[replica].on) return QTB_OK;
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    c->vdos[replica] = VdosRec{};
+    RepDev& d = c->rd[replica];
+    d.vt = nullptr;
+    d.vt_n = nullptr;
+    d.vt_cap = 0;
+    qtb_status s = upload_tables(c);
+    if (s) return s;
+    QTB_HIP(c, hipStreamSynchronize(c->st));  // the buffer is the caller's again
     return QTB_OK;
 }
 

@@ -102,6 +102,13 @@ struct RepDev {
     int32_t maxml;
     int32_t ml_pad;
     double ml_rcs;        // r_ml + skin
+    // velocity recorder (P = 1; null when off): every sample also stores the
+    // velocities, row (vt_n mod vt_cap) of vt [vt_cap][dims][N]; the sample
+    // reduction advances vt_n
+    double* vt;
+    int64_t* vt_n;
+    int32_t vt_cap;
+    int32_t vt_pad;
 };
 
 // ------------------------------------------------ descriptor-MLP surrogate
@@ -288,9 +295,23 @@ void launch_step_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* rep
 void launch_forces_onsite(hipStream_t st, bool fp64, int kind, const RepDev* reps,
                           const BlockEntry* blocks, int n_blocks, int32_t flags,
                           double* partials);
+// tick: a sample (advances the velocity recorders), not a surrogate check
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
-                       double* acc, int32_t* counts);
+                       double* acc, int32_t* counts, bool tick);
 void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value);
+// vdos.hip
+constexpr int kVdosMinSeg = 16, kVdosMaxSeg = 4096;  // samples per segment, powers of two
+struct VdosPlan {
+    int seg, L2, cw, n_groups, grid, nk;  // cw complex columns per group, nk = seg/2 + 1
+};
+VdosPlan vdos_plan(int n_dof, int seg);
+void launch_vdos_twiddle(hipStream_t st, double* tw, int seg);
+// One segment [seg][n_dof] at v: spec[k] = (accumulate ? spec[k] : 0) +
+// scale * sum_j w_j |V_jk|^2; partials: plan.grid x plan.nk doubles.
+void launch_vdos_segment(hipStream_t st, const VdosPlan& p, const double* v, int n_dof,
+                         const double* weight, const double* tw, double* partials, double* spec,
+                         double scale, bool accumulate);
+void launch_vdos_weights(hipStream_t st, const RepDev* reps, int r, int n_dof, double* w);
 // ml.hip
 void launch_ml_lists(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* nl_blocks,
                      int n_nl, int32_t* status, StepRef sync);

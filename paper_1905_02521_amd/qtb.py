@@ -86,6 +86,8 @@ class qtb_obs(ctypes.Structure):
 EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
            "qtb_observables", "qtb_get_state", "qtb_set_state", "qtb_evaluate",
            "qtb_get_noise", "qtb_gaussian", "qtb_profile", "qtb_profile_read",
+           "qtb_vdos_workspace_bytes", "qtb_vdos_spectrum", "qtb_vdos_attach", "qtb_vdos_read",
+           "qtb_vdos_detach",
            "qtb_last_error", "qtb_destroy", "qtb_version",
            "qtb_ml_workspace_bytes", "qtb_ml_create", "qtb_ml_init_params", "qtb_ml_set_params",
            "qtb_ml_get_params", "qtb_ml_attach", "qtb_ml_evaluate", "qtb_ml_fit_norm",
@@ -130,6 +132,18 @@ def lib():
     L.qtb_gaussian.restype = ctypes.c_int
     L.qtb_gaussian.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                                ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, vp, vp]
+    L.qtb_vdos_workspace_bytes.restype = ctypes.c_size_t
+    L.qtb_vdos_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.qtb_vdos_spectrum.restype = ctypes.c_int
+    L.qtb_vdos_spectrum.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int32, vp,
+                                    vp, ctypes.c_size_t, vp]
+    L.qtb_vdos_attach.restype = ctypes.c_int
+    L.qtb_vdos_attach.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t]
+    L.qtb_vdos_read.restype = ctypes.c_int
+    L.qtb_vdos_read.argtypes = [vp, ctypes.c_int32, _PD, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.c_int32]
+    L.qtb_vdos_detach.restype = ctypes.c_int
+    L.qtb_vdos_detach.argtypes = [vp, ctypes.c_int32]
     L.qtb_profile.restype = ctypes.c_int
     L.qtb_profile.argtypes = [vp, ctypes.c_int32]
     L.qtb_profile_read.restype = ctypes.c_int
@@ -199,6 +213,24 @@ def qtb_gaussian(seed, stream, tag, n0, n_rows, d0, n_dof, out=None):
         out = torch.empty((n_rows, n_dof), dtype=torch.float64, device="cuda")
     _check(lib().qtb_gaussian(seed, stream, tag, n0, n_rows, d0, n_dof,
                               ctypes.c_void_p(out.data_ptr()), current_stream_ptr()))
+    return out
+
+
+# ---------------------------------------------------------------- spectra
+def vdos_spectrum(v, weight, seg):
+    """Velocity spectrum S[k], k = 0..seg/2, of a device series v [n_samples,
+    n_dof] (float64) with device weights [n_dof], over its whole segments."""
+    torch = _torch()
+    n_samples, n_dof = v.shape
+    nbytes = lib().qtb_vdos_workspace_bytes(n_dof, seg, 0)
+    if nbytes == 0:
+        raise QtbError(QTB_E_INVALID, "qtb_vdos_workspace_bytes rejected the sizes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=v.device)
+    out = torch.empty(seg // 2 + 1, dtype=torch.float64, device=v.device)
+    _check(lib().qtb_vdos_spectrum(ctypes.c_void_p(v.data_ptr()), n_samples, n_dof,
+                                   ctypes.c_void_p(weight.data_ptr()), seg,
+                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                   nbytes, current_stream_ptr()))
     return out
 
 
@@ -354,6 +386,32 @@ class Context:
         _check(lib().qtb_profile_read(self.ctx, _pd(ms),
                                       n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), self.ctx)
         return {PHASES[q]: (float(ms[q]), int(n[q])) for q in range(N_PHASES)}
+
+    # -- velocity spectrum ------------------------------------------------------
+    def vdos_attach(self, replica, seg):
+        torch = _torch()
+        P, dims, N = self.shapes[replica]
+        nbytes = lib().qtb_vdos_workspace_bytes(dims * N, seg, 1)
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        _check(lib().qtb_vdos_attach(self.ctx, replica, seg, ctypes.c_void_p(ws.data_ptr()),
+                                     nbytes), self.ctx)
+        if not hasattr(self, "_vdos_ws"):
+            self._vdos_ws = {}
+        self._vdos_ws[replica] = (ws, seg)
+
+    def vdos_read(self, replica=0, restart=False):
+        """(S [seg/2 + 1], number of segments averaged)."""
+        seg = getattr(self, "_vdos_ws", {}).get(replica, (None, 16))[1]
+        S = np.zeros(seg // 2 + 1)
+        n = ctypes.c_int64()
+        _check(lib().qtb_vdos_read(self.ctx, replica, _pd(S), ctypes.byref(n),
+                                   1 if restart else 0), self.ctx)
+        return S, n.value
+
+    def vdos_detach(self, replica=0):
+        _check(lib().qtb_vdos_detach(self.ctx, replica), self.ctx)
+        getattr(self, "_vdos_ws", {}).pop(replica, None)
 
     # -- surrogate --------------------------------------------------------------
     def ml_attach(self, model, check_every=0):

@@ -1,0 +1,207 @@
+"""Velocity density of states on the GPU (Sec. 3: QTB-MD gives direct access
+to time-correlation functions; the DOS is the check to make at high gamma).
+
+Parity (FP64, against the oracle's segment periodograms):
+* the standalone transform on seeded series: one dof, odd dof counts, a
+  ragged trailing segment, no whole segment, the largest segment, a crystal's
+  worth of dofs; every bin within 1e-12 of the largest;
+* the recorder on QTB trajectories: harmonic oscillators (odd count) and the
+  MgO crystal with separate and with one-kernel steps, against the spectra of
+  the oracle's own trajectories; restart and set_state cut the series;
+* Parseval on the GPU: the spectrum's mean over all frequencies is twice the
+  mean kinetic energy the observables report over the same samples.
+Statistics: the spectrum of QTB oscillators lies within the block-mean errors
+of the exact spectrum of the discrete scheme (linear response, Fejer window).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1905_02521_amd import qtb, workloads as W
+from tests.closed_forms import baoab_mode_map
+from tests.gpu_common import (crystal, gpu_crystal_ctx, gpu_ho_ctx, oracle_pair_pot,
+                              oracle_units)
+from tests.test_oracle_vdos import expected_periodogram
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qtb.lib()
+
+
+def full_mean(S):
+    """Mean over all seg frequencies of a spectrum given for k = 0 .. seg/2."""
+    seg = 2 * (len(S) - 1)
+    return (S[0] + S[-1] + 2.0 * np.sum(S[1:-1])) / seg
+
+
+@pytest.mark.parametrize("n_samples,n_dof,seg", [
+    (64, 1, 16), (100, 7, 16), (3 * 256 + 5, 301, 256), (2048, 3 * 4096, 1024),
+    (4096, 3, 4096), (8192, 2, 4096), (10, 5, 16), (5 * 64, 4097, 64)])
+def test_spectrum_matches_oracle(orc, n_samples, n_dof, seg):
+    import torch
+    rng = np.random.default_rng(n_samples * 7 + n_dof)
+    v = rng.normal(size=(n_samples, n_dof)) * rng.uniform(0.2, 3.0, n_dof)
+    w = rng.uniform(0.5, 40.0, n_dof)
+    dv = torch.from_numpy(v).cuda()
+    dw = torch.from_numpy(w).cuda()
+    S = qtb.vdos_spectrum(dv, dw, seg).cpu().numpy()
+    _, So, n_seg = orc.vdos(v, seg, w)
+    assert S.shape == So.shape == (seg // 2 + 1,)
+    if n_seg == 0:
+        assert np.all(S == 0.0)
+        return
+    err = np.max(np.abs(S - So)) / np.max(So)
+    print(f"n_samples {n_samples} n_dof {n_dof} seg {seg}: max rel error {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_spectrum_rejects_bad_sizes():
+    import torch
+    v = torch.zeros((64, 4), dtype=torch.float64, device="cuda")
+    w = torch.ones(4, dtype=torch.float64, device="cuda")
+    for seg in (8, 24, 8192):
+        with pytest.raises(qtb.QtbError):
+            qtb.vdos_spectrum(v, w, seg)
+
+
+def _osc_setup(n, P=1, obs_every=2, T=0.25, gamma=0.2, dt=0.1, two_nf=256, omega=1.0, seed=4):
+    om = np.full(n, omega) * (1.0 + 0.5 * np.arange(n) / max(n - 1, 1))
+    ctx = gpu_ho_ctx(om, P, T=T, gamma=gamma, dt=dt, noise=1 if P == 1 else 2,
+                     prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, seed=seed, max_two_nf=two_nf,
+                     obs_every=obs_every, pos=np.full((P, 1, n), 0.3))
+    taps = ctx.build_filter(0, 1 if P == 1 else 2, two_nf)
+    return ctx, om, taps
+
+
+def test_recorder_matches_oracle_oscillators(orc):
+    """257 oscillators (omega 1..1.5), QTB, FP64, a sample every 2 steps,
+    segments of 32 samples: 1000 steps give 15 segments (and 20 samples of a
+    16th); the oracle's trajectory sampled the same way gives the same
+    spectrum."""
+    n, every, seg, two_nf, T, gamma, dt = 257, 2, 32, 256, 0.25, 0.2, 0.1
+    ctx, om, _ = _osc_setup(n, obs_every=every, T=T, gamma=gamma, dt=dt, two_nf=two_nf)
+    ctx.vdos_attach(0, seg)
+    ctx.step(1000)
+    S, n_seg = ctx.vdos_read(0)
+    assert n_seg == 15
+    osim = orc.Sim(orc.make_pot(1, (1.0,)), oracle_units(orc, True), n, 1, 1, None,
+                   np.zeros(n, np.int32), T, gamma, dt, 4, 0, 1, two_nf, np.full((1, 1, n), 0.3),
+                   harm_omega=om, n_threads=8)
+    v = np.empty((500, n))
+    for t in range(500):
+        osim.run(every)
+        v[t] = osim.state()[1][0, 0]
+    _, So, n_o = orc.vdos(v, seg)
+    assert n_o == 15
+    err = np.max(np.abs(S - So)) / np.max(So)
+    print(f"oscillators: max rel error {err:.2e}")
+    assert err <= 1e-8
+    # restart: the next segments count afresh, from the current step
+    ctx.vdos_read(0, restart=True)
+    ctx.step(2 * seg * every + 3)
+    S2, n2 = ctx.vdos_read(0)
+    assert n2 == 2
+    v2 = np.empty((2 * seg, n))
+    for t in range(2 * seg):
+        osim.run(every)
+        v2[t] = osim.state()[1][0, 0]
+    assert np.max(np.abs(S2 - orc.vdos(v2, seg)[1])) <= 1e-8 * np.max(S2)
+    # set_state cuts the series
+    r, vv, st = ctx.get_state(0)
+    ctx.set_state(0, r, vv, st)
+    assert ctx.vdos_read(0)[1] == 0
+    ctx.vdos_detach(0)
+    ctx.step(10)
+    with pytest.raises(qtb.QtbError):
+        ctx.vdos_read(0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("fuse", [False, True])
+def test_recorder_matches_oracle_crystal(orc, fuse):
+    """MgO 4x4x4 (512 atoms), QTB, FP64, every step sampled, segments of 64:
+    130 steps give 2 segments; weights are the masses (amu times the mass
+    unit).  The one-kernel step samples a step inside the next step's kernel:
+    the recorder must store the same velocities."""
+    beads, sp, box = crystal(4, 1, seed=3)
+    T, gamma, dt, seed, two_nf, seg = 100.0, 5e-3, 1.0, 9, 512, 64
+    ctx = gpu_crystal_ctx(beads, sp, box, T=T, gamma=gamma, dt=dt, noise=1, prec=qtb.PREC_FP64,
+                          fir=qtb.FIR_FP64, seed=seed, max_two_nf=two_nf, obs_every=1, fuse=fuse)
+    ctx.build_filter(0, 1, two_nf)
+    ctx.vdos_attach(0, seg)
+    ctx.observables(0)
+    ctx.step(2 * seg)
+    S, n_seg = ctx.vdos_read(0)
+    obs = ctx.observables(0)
+    assert n_seg == 2 and obs["n_samples"] == 2 * seg
+    # Parseval over exactly the same samples: mean of S = 2 <K>
+    assert abs(full_mean(S) - 2 * obs["kinetic"]) <= 1e-12 * abs(full_mean(S))
+    osim = orc.Sim(oracle_pair_pot(orc), oracle_units(orc, False), 512, 1, 3, box, sp, T, gamma,
+                   dt, seed, 0, 1, two_nf, beads, n_threads=8)
+    v = np.empty((2 * seg, 3 * 512))
+    for t in range(2 * seg):
+        osim.run(1)
+        v[t] = osim.state()[1][0].reshape(-1)
+    p = W.mgo_potential()
+    w = np.tile(np.asarray(p.mass)[sp] * W.METAL_UNITS["mass_unit"], 3)
+    _, So, _ = orc.vdos(v, seg, w)
+    err = np.max(np.abs(S - So)) / np.max(So)
+    print(f"crystal fuse={fuse}: max rel error {err:.2e}")
+    assert err <= 1e-8
+    ctx.close()
+
+
+def test_recorder_rejects_bad_use():
+    ctx, _, _ = _osc_setup(16, P=4, obs_every=2)
+    with pytest.raises(qtb.QtbError):   # bead velocities: no time correlations
+        ctx.vdos_attach(0, 64)
+    ctx.close()
+    ctx, _, _ = _osc_setup(16, obs_every=0)
+    with pytest.raises(qtb.QtbError):   # nothing is sampled
+        ctx.vdos_attach(0, 64)
+    ctx.close()
+    ctx, _, _ = _osc_setup(16, obs_every=1)
+    for seg in (32, 48, 8192):           # seg * obs_every below the noise block; not 2^k; too long
+        with pytest.raises(qtb.QtbError):
+            ctx.vdos_attach(0, seg)
+    with pytest.raises(qtb.QtbError):
+        ctx.vdos_read(0)
+    ctx.close()
+
+
+def test_oscillator_vdos_matches_linear_response():
+    """4096 oscillators, omega = 1, k_B T = 0.25, gamma = 0.2, dt = 0.1, QTB
+    filter 2Nf = 256, every step sampled, segments of 256: 16 blocks of 4
+    segments; each bin of the block mean within 4.5 standard errors of the
+    exact expected periodogram, and the mean z^2 near 1."""
+    n, seg, T, gamma, dt, two_nf = 4096, 256, 0.25, 0.2, 0.1, 256
+    ctx = gpu_ho_ctx(np.full(n, 1.0), 1, T=T, gamma=gamma, dt=dt, noise=1, prec=qtb.PREC_FP64,
+                     fir=qtb.FIR_FP64, seed=12, max_two_nf=two_nf, obs_every=1)
+    taps = ctx.build_filter(0, 1, two_nf)
+    ctx.step(2000)
+    ctx.vdos_attach(0, seg)
+    blocks = []
+    for _ in range(16):
+        ctx.step(4 * seg)
+        S, nb = ctx.vdos_read(0, restart=True)
+        assert nb == 4
+        blocks.append(S / n)
+    ctx.close()
+    blocks = np.array(blocks)
+    mean, se = blocks.mean(axis=0), blocks.std(axis=0, ddof=1) / math.sqrt(len(blocks))
+    c1 = math.exp(-gamma * dt)
+    M, b = baoab_mode_map(1.0, 0.0, c1, math.sqrt(1 - c1 * c1), dt)
+    v2, Ek = expected_periodogram(M, b, taps, seg)
+    z = (mean - Ek) / se
+    print(f"<v^2> exact {v2:.5f}, from S {full_mean(mean):.5f}; max |z| {np.max(np.abs(z)):.2f}, "
+          f"mean z^2 {np.mean(z * z):.3f}")
+    assert np.max(np.abs(z)) < 4.5
+    assert 0.6 < np.mean(z * z) < 1.5
+    assert abs(full_mean(mean) / v2 - 1) < 0.01
