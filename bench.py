@@ -395,6 +395,86 @@ def pimd_compare_bench(a):
     print(json.dumps(out))
 
 
+def vdos_bench(a):
+    """Velocity density of states on the 8x8x8 MgO crystal (4096 atoms, QTB,
+    P = 1, 50 K, gamma = 1/ps, every step sampled, segments of 1024 samples):
+    the step time with sampling alone and with the velocity recorder attached
+    (the recorder's cost inside the step kernels plus one transform per
+    segment), and the transform by itself on a seeded trace of the same shape
+    (12288 dofs x 1024 samples, FP64): its time per segment and its rate
+    against HBM, counting one read of the segment as the algorithmic traffic."""
+    import torch
+    from paper_1905_02521_amd import qtb, workloads as W
+    pot = W.mgo_potential(skin=0.4)
+    pos, sp, box = W.rocksalt(8)
+    base = W.displaced(pos, 0.0421, 2)
+    N, seg, n_seg = len(sp), 1024, 8
+    n_dof = 3 * N
+    # one context (one force-kernel decomposition): sampling alone, then with
+    # the recorder attached, then sampling alone again
+    rep = qtb.Replica(pos=W.beads_from(base, 1), species=sp, T=50.0, gamma=1e-3, dt=1.0,
+                      noise=1, box=tuple(box), seed=2)
+    ctx = qtb.Context(qtb.pair_potential_dict(pot), [rep], W.METAL_UNITS, prec=qtb.PREC_FP32,
+                      fir=qtb.FIR_BF16X3, obs_every=1, max_two_nf=512)
+    ctx.build_filter(0, 1, 512)
+    ctx.step(a.warmup)
+    times = {"sampling": [], "recorder": []}
+    for name in ("sampling", "recorder", "sampling"):
+        if name == "recorder":
+            ctx.vdos_attach(0, seg)
+        ctx.observables(0)
+        t0 = time.perf_counter()
+        ctx.step(seg * n_seg)
+        if name == "recorder":
+            assert ctx.vdos_read(0)[1] == n_seg
+        ctx.observables(0)
+        times[name].append((time.perf_counter() - t0) / (seg * n_seg))
+        if name == "recorder":
+            ctx.vdos_detach(0)
+    ctx.close()
+    times = {k: sum(v) / len(v) for k, v in times.items()}
+    # the transform alone, timed with events on the stream it runs on, on
+    # the recorder's layout (one row of dofs per sample) and on contiguous
+    # series per dof
+    g = torch.Generator(device="cpu").manual_seed(7)
+    wts = torch.full((n_dof,), 24.3, dtype=torch.float64, device="cuda")
+    t_seg = {}
+    for layout in ("dof_major", "sample_major"):
+        shape = (n_dof, seg * n_seg) if layout == "dof_major" else (seg * n_seg, n_dof)
+        v = torch.randn(shape, generator=g, dtype=torch.float64).cuda()
+        for _ in range(3):
+            qtb.vdos_spectrum(v, wts, seg, dof_major=layout == "dof_major")
+        torch.cuda.synchronize()
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            qtb.vdos_spectrum(v, wts, seg, dof_major=layout == "dof_major")
+        e1.record()
+        torch.cuda.synchronize()
+        t_seg[layout] = e0.elapsed_time(e1) * 1e-3 / (reps * n_seg)
+        del v
+    bytes_seg = 8.0 * seg * n_dof
+    out = {
+        "metric": "velocity spectrum: recorder overhead per step, transform rate",
+        "unit": "ms/step; us/segment; GB/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+        "data": "synthetic (seeded rock-salt crystal; seeded Gaussian trace)",
+        "config": {"workload": "mgo-8x8x8-qtb-50K-vdos", "atoms": N, "dofs": n_dof,
+                   "segment_samples": seg, "segments": n_seg},
+        "ms_per_step_sampling": times["sampling"] * 1e3,
+        "ms_per_step_recorder": times["recorder"] * 1e3,
+        "recorder_overhead": times["recorder"] / times["sampling"] - 1.0,
+        "transform_us_per_segment": t_seg["sample_major"] * 1e6,
+        "transform_us_per_segment_dof_major": t_seg["dof_major"] * 1e6,
+        "transform": {"bound": "hbm", "achieved": bytes_seg / t_seg["sample_major"] / 1e9,
+                      "peak": 8000.0, "unit": "GB/s",
+                      "frac": bytes_seg / t_seg["sample_major"] / 8e12,
+                      "bytes_per_segment": bytes_seg},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,7 +483,8 @@ def main():
     ap.add_argument("--workload", default="mgo-8x8x8-qtbpimd-P8-50K",
                     help="a named single workload, batched-64 (the T / gamma / P sweep) or "
                          "surrogate-20x20x20-P4 (the learned force surrogate) or qtb-vs-pimd "
-                         "(QTB, QTB-PIMD and PIMD cost and energies on one crystal)")
+                         "(QTB, QTB-PIMD and PIMD cost and energies on one crystal) or vdos "
+                         "(the velocity spectrum's recorder and transform)")
     ap.add_argument("--fir", default="bf16x3", choices=["fp32", "bf16x3", "bf16", "fp64"])
     ap.add_argument("--K", type=int, default=64)
     ap.add_argument("--blocks", type=int, default=40,
@@ -435,6 +516,8 @@ def main():
         a.skin = 1.0 if (a.workload.startswith("batched") or a.workload.startswith("surrogate")) else 0.4
     if a.workload == "qtb-vs-pimd":
         return pimd_compare_bench(a)
+    if a.workload == "vdos":
+        return vdos_bench(a)
     if a.workload.startswith("surrogate"):
         surrogate_bench(a)
         return

@@ -262,7 +262,8 @@ qtb_status qtb_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0
  * w_j the mass of dof j (m * mass_unit, the energy units of qtb_obs): the
  * mean of S over all seg frequencies (k and seg - k both counted) is then
  * twice the mean kinetic energy of the sampled velocities.  seg: a power of
- * two, 16..4096.
+ * two, 16..4096.  The transform is a radix-2 FFT in LDS; partial sums are
+ * added in a fixed order, so results repeat bit for bit.
  */
 
 /* Device bytes of a spectrum workspace for n_dof dofs: recorder = 1 for
@@ -270,15 +271,18 @@ qtb_status qtb_gaussian(uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0
  * 0 on bad input. */
 size_t qtb_vdos_workspace_bytes(int32_t n_dof, int32_t seg, int32_t recorder);
 
-/* The spectrum of a device series d_v [n_samples][n_dof] (FP64, row t =
- * sample t) with device weights d_weight [n_dof], over its n_samples / seg
- * whole segments (a trailing partial segment is ignored; with none, S = 0):
- * d_spec (device, [seg/2 + 1]) receives S.  d_workspace: device, 256-byte
- * aligned, qtb_vdos_workspace_bytes(n_dof, seg, 0) bytes.  Enqueued on
- * hip_stream; returns without waiting. */
+/* The spectrum of a device series (FP64): sample t of dof j at
+ * d_v[t * sample_stride + j * dof_stride] (strides in elements, >= 1:
+ * [n_samples][n_dof] row-major is (n_dof, 1), [n_dof][n_samples] is
+ * (1, n_samples)), with device weights d_weight [n_dof], over its
+ * n_samples / seg whole segments (a trailing partial segment is ignored;
+ * with none, S = 0): d_spec (device, [seg/2 + 1]) receives S.  d_workspace:
+ * device, 256-byte aligned, qtb_vdos_workspace_bytes(n_dof, seg, 0) bytes.
+ * Enqueued on hip_stream; returns without waiting. */
 qtb_status qtb_vdos_spectrum(const double *d_v, int64_t n_samples, int32_t n_dof,
-                             const double *d_weight, int32_t seg, double *d_spec,
-                             void *d_workspace, size_t ws_bytes, void *hip_stream);
+                             int64_t sample_stride, int64_t dof_stride, const double *d_weight,
+                             int32_t seg, double *d_spec, void *d_workspace, size_t ws_bytes,
+                             void *hip_stream);
 
 /* Attach a velocity recorder to a replica with P = 1 (QTB_E_INVALID for
  * P > 1: ring-polymer bead velocities carry no physical time correlations).

@@ -21,16 +21,25 @@ struct GlobalState {
     }
 };
 
+// The velocity recorder's row [dims][N] that a sampling force pass fills
+// (null: none).  Kernels read it before the force loop, so that the two
+// dependent loads overlap the force arithmetic instead of the kernel's tail.
+__device__ __forceinline__ double* recorder_row(const RepDev& R, int32_t flags)
+{
+    if (!(flags & kSample) || !R.vt) return nullptr;
+    return R.vt + (*R.vt_n % R.vt_cap) * R.dims * R.N;
+}
+
 // e_atom: this atom's share of the bead potential V(r^(s)).
 // ob (kNobs slots): kinetic, V/P, spring, virial, x^2 in kSample mode;
 // |F - F_stored|^2 and |F|^2 in kCompare mode (nothing is written then).
 // vn receives the velocity after the kick; STORE_V: write it back.  A sample
-// also stores vn into the replica's velocity recorder, if one is attached.
+// also stores vn into the velocity recorder's row vrec (recorder_row).
 template <typename T, bool STORE_V = true, typename Src>
 __device__ __forceinline__ void force_epilogue_src(const RepDev& R, int i, int s, int spi,
                                                    const double f[3], double e_atom,
                                                    int32_t flags, double* ob, const Src& src,
-                                                   double* vn)
+                                                   double* vn, double* vrec)
 {
     const int N = R.N, P = R.P;
     T* __restrict__ force = (T*)R.force;
@@ -79,10 +88,9 @@ __device__ __forceinline__ void force_epilogue_src(const RepDev& R, int i, int s
         ob[2] = (P > 1) ? 0.5 * m * R.omega_P * R.omega_P * spr : 0.0;
         ob[3] = vir;
         ob[4] = x2;
-        if (R.vt) {  // velocity recorder (P = 1)
-            const size_t row = (size_t)(*R.vt_n % R.vt_cap);
+        if (vrec) {  // velocity recorder (P = 1)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) R.vt[(row * 3 + a) * N + i] = vn[a];
+            for (int a = 0; a < 3; ++a) vrec[(size_t)a * N + i] = vn[a];
         }
     }
 }
@@ -90,10 +98,10 @@ __device__ __forceinline__ void force_epilogue_src(const RepDev& R, int i, int s
 template <typename T>
 __device__ __forceinline__ void force_epilogue(const RepDev& R, int i, int s, int spi,
                                                const double f[3], double e_atom, int32_t flags,
-                                               double* ob)
+                                               double* ob, double* vrec)
 {
     double vn[3];
-    force_epilogue_src<T, true>(R, i, s, spi, f, e_atom, flags, ob, GlobalState{R, i}, vn);
+    force_epilogue_src<T, true>(R, i, s, spi, f, e_atom, flags, ob, GlobalState{R, i}, vn, vrec);
 }
 
 }  // namespace qtb

@@ -393,6 +393,7 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
     const bool active = i < N;
     const int s = be.group * G + bl;
     const bool want_e = (flags & (kSample | kEvaluate)) != 0;
+    double* const vrec = recorder_row(R, flags);
     const StepIdx si = step_index(sync);
     // clear == 1: the list kernel ran before; this step's and the previous
     // step's flags are done.  clear == 2: rebuild the lists here if this step
@@ -449,7 +450,7 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
     double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (active && wsub == 0 && lane < G && s < P) {
         const double f[3] = {fx, fy, fz};
-        force_epilogue<T>(R, i, s, spi, f, 0.5 * e, flags, ob);
+        force_epilogue<T>(R, i, s, spi, f, 0.5 * e, flags, ob, vrec);
     }
     if (flags & (kSample | kCompare)) block_partials(ob, wave, lane, lb, red, partials);
 }
@@ -503,6 +504,7 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
     const bool active = i < N;
     const int s = bl;  // G = P: the wavefront holds every bead
     const bool want_e = (flags & kSample) != 0;
+    double* const vrec = recorder_row(R, flags);
     {
         const int apb = 4 / W;
         for (int t = threadIdx.x; t < G * G; t += blockDim.x) Cs[t] = R.nm[t];
@@ -558,7 +560,7 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
         if (own) {
             const double f[3] = {fx, fy, fz};
             force_epilogue_src<T, false>(R, i, s, spi, f, 0.5 * e, kKick | (flags & kSample), ob,
-                                         src, vc);
+                                         src, vc, vrec);
 #pragma unroll
             for (int a = 0; a < 3; ++a) fT[a] = (double)(T)f[a];  // the stored force
         }
@@ -700,9 +702,8 @@ __global__ void __launch_bounds__(256) k_force_onsite(const RepDev* __restrict__
         const double m = R.mmu[sp], kick = R.kick[sp];
         const double k = KIND == QTB_POT_HARMONIC ? m * R.homega[i] * R.homega[i] : 0.0;
         const double V0 = R.osV0[sp], dl = R.osd[sp];
-        double* vrow = ((flags & kSample) && R.vt)
-                           ? R.vt + (size_t)(*R.vt_n % R.vt_cap) * dims * N + i
-                           : nullptr;  // velocity recorder (P = 1)
+        double* vrow = recorder_row(R, flags);  // velocity recorder (P = 1)
+        if (vrow) vrow += i;
         double ke = 0.0, U = 0.0, spr = 0.0, vir = 0.0, x2 = 0.0;
         for (int a = 0; a < dims; ++a) {
             double c = 0.0;

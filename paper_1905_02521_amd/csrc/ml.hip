@@ -816,6 +816,7 @@ __global__ void __launch_bounds__(256) k_ml_gather(const RepDev* __restrict__ re
     const int N = R.N, P = R.P;
     const int s = be.group * G + bl;
     const bool active = wave < apb && i < N && s < P;
+    double* const vrec = recorder_row(R, flags);
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (active) {
         const T4* __restrict__ ent = (const T4*)R.ml_nb + (size_t)i * R.maxml;
@@ -846,7 +847,7 @@ __global__ void __launch_bounds__(256) k_ml_gather(const RepDev* __restrict__ re
         const size_t c = (size_t)s * N + i;
         const double e_atom = (double)R.ml_y[c] + m.e0[spi];
         const double f[3] = {fx, fy, fz};
-        force_epilogue<T>(R, i, s, spi, f, e_atom, flags, ob);
+        force_epilogue<T>(R, i, s, spi, f, e_atom, flags, ob, vrec);
     }
     if (flags & kSample) {
 #pragma unroll

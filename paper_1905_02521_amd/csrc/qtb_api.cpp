@@ -362,7 +362,7 @@ namespace {
 // Byte offsets of a velocity-spectrum workspace (the recorder's, or the
 // standalone transform's without trace, weights and counter).
 struct VdosLayout {
-    size_t trace = 0, spec = 0, part = 0, tw = 0, w = 0, cnt = 0, total = 0;
+    size_t trace = 0, spec = 0, part = 0, stage = 0, tw = 0, w = 0, cnt = 0, total = 0;
 };
 
 VdosLayout vdos_layout(int n_dof, int seg, bool recorder)
@@ -376,11 +376,12 @@ VdosLayout vdos_layout(int n_dof, int seg, bool recorder)
         return o;
     };
     l.part = take(8 * (size_t)p.grid * p.nk);
+    l.stage = take(8 * (size_t)p.stage_rows * p.nk);
     l.tw = take(16 * (size_t)(seg / 2));
+    l.w = take(8 * (size_t)n_dof);  // square roots of the weights
     if (recorder) {
         l.trace = take(8 * 2 * (size_t)seg * n_dof);
         l.spec = take(8 * (size_t)p.nk);
-        l.w = take(8 * (size_t)n_dof);
         l.cnt = take(8);
     }
     l.total = cur;
@@ -388,8 +389,8 @@ VdosLayout vdos_layout(int n_dof, int seg, bool recorder)
 }
 
 // Velocity recorder of one replica, in the caller's device buffer.  The
-// trace holds two segments: a segment is transformed once complete, while
-// the steps go on filling the other half.
+// trace [2 seg][dof] holds two segments: a segment is transformed once
+// complete, while the steps go on filling the other half.
 struct VdosRec {
     bool on = false;
     char* ws = nullptr;
@@ -1226,8 +1227,9 @@ void vdos_flush(qtb_ctx* c)
         const int seg = v.plan.seg;
         while (v.n_seg < done / seg) {
             const double* base = v.at<double>(v.lay.trace) + (size_t)(v.n_seg & 1) * seg * v.n_dof;
-            launch_vdos_segment(c->st, v.plan, base, v.n_dof, v.at<double>(v.lay.w),
-                                v.at<double>(v.lay.tw), v.at<double>(v.lay.part),
+            launch_vdos_segment(c->st, v.plan, base, v.n_dof, 1, v.n_dof,
+                                v.at<double>(v.lay.w), v.at<double>(v.lay.tw),
+                                v.at<double>(v.lay.part), v.at<double>(v.lay.stage),
                                 v.at<double>(v.lay.spec), 1.0 / seg, v.n_seg > 0);
             ++v.n_seg;
         }
@@ -1599,10 +1601,11 @@ size_t qtb_vdos_workspace_bytes(int32_t n_dof, int32_t seg, int32_t recorder)
 }
 
 qtb_status qtb_vdos_spectrum(const double* d_v, int64_t n_samples, int32_t n_dof,
-                             const double* d_weight, int32_t seg, double* d_spec, void* d_workspace,
-                             size_t ws_bytes, void* hip_stream)
+                             int64_t sample_stride, int64_t dof_stride, const double* d_weight,
+                             int32_t seg, double* d_spec, void* d_workspace, size_t ws_bytes,
+                             void* hip_stream)
 {
-    if (!d_v || !d_weight || !d_spec || n_samples < 0)
+    if (!d_v || !d_weight || !d_spec || n_samples < 0 || sample_stride < 1 || dof_stride < 1)
         return fail(nullptr, QTB_E_INVALID, "bad spectrum arguments");
     const size_t need = qtb_vdos_workspace_bytes(n_dof, seg, 0);
     if (need == 0) return fail(nullptr, QTB_E_INVALID, "n_dof >= 1 and seg a power of two in [16, 4096]");
@@ -1617,9 +1620,11 @@ qtb_status qtb_vdos_spectrum(const double* d_v, int64_t n_samples, int32_t n_dof
         launch_fill(st, d_spec, 2 * (int64_t)p.nk, 0);
     } else {
         launch_vdos_twiddle(st, (double*)(ws + l.tw), seg);
+        launch_vdos_sqrt(st, d_weight, n_dof, (double*)(ws + l.w));
         for (int64_t q = 0; q < n_seg; ++q)
-            launch_vdos_segment(st, p, d_v + (size_t)q * seg * n_dof, n_dof, d_weight,
-                                (const double*)(ws + l.tw), (double*)(ws + l.part), d_spec,
+            launch_vdos_segment(st, p, d_v + q * seg * sample_stride, sample_stride, dof_stride,
+                                n_dof, (const double*)(ws + l.w), (const double*)(ws + l.tw),
+                                (double*)(ws + l.part), (double*)(ws + l.stage), d_spec,
                                 1.0 / ((double)seg * (double)n_seg), q > 0);
     }
     const hipError_t e = hipGetLastError();

@@ -303,15 +303,20 @@ void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value);
 constexpr int kVdosMinSeg = 16, kVdosMaxSeg = 4096;  // samples per segment, powers of two
 struct VdosPlan {
     int seg, L2, cw, n_groups, grid, nk;  // cw complex columns per group, nk = seg/2 + 1
+    int stage_rows;                       // rows of the first summing pass (0: one pass)
 };
 VdosPlan vdos_plan(int n_dof, int seg);
 void launch_vdos_twiddle(hipStream_t st, double* tw, int seg);
-// One segment [seg][n_dof] at v: spec[k] = (accumulate ? spec[k] : 0) +
-// scale * sum_j w_j |V_jk|^2; partials: plan.grid x plan.nk doubles.
-void launch_vdos_segment(hipStream_t st, const VdosPlan& p, const double* v, int n_dof,
-                         const double* weight, const double* tw, double* partials, double* spec,
-                         double scale, bool accumulate);
-void launch_vdos_weights(hipStream_t st, const RepDev* reps, int r, int n_dof, double* w);
+// One segment: sample t of dof j at v[t ts + j js]; spec[k] = (accumulate ?
+// spec[k] : 0) + scale * sum_j w_j |V_jk|^2, given sqrt_w[j] = sqrt(w_j).
+// partials: plan.grid x plan.nk doubles, stage: plan.stage_rows x plan.nk.
+void launch_vdos_segment(hipStream_t st, const VdosPlan& p, const double* v, int64_t ts,
+                         int64_t js, int n_dof, const double* sqrt_w, const double* tw,
+                         double* partials, double* stage, double* spec, double scale,
+                         bool accumulate);
+// sqrt_w of a replica's dofs ([dims][N]: the square roots of the masses)
+void launch_vdos_weights(hipStream_t st, const RepDev* reps, int r, int n_dof, double* sqrt_w);
+void launch_vdos_sqrt(hipStream_t st, const double* w, int n, double* sqrt_w);
 // ml.hip
 void launch_ml_lists(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* nl_blocks,
                      int n_nl, int32_t* status, StepRef sync);

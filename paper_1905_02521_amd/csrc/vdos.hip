@@ -9,25 +9,52 @@
 // k = 0 .. seg/2, with w_j the mass of dof j (S then averages to twice the
 // kinetic energy over all seg frequencies).
 //
-// The series sits in HBM one sample per row ([t][n_dof], the order the step
-// kernels write it, one coalesced row per sample).  A block transforms
-// groups of CW complex columns in LDS: complex column q packs the real dofs
-// 2q and 2q + 1, each scaled by the square root of its weight, so that
-// w_a |A_k|^2 + w_b |B_k|^2 = (|Z_k|^2 + |Z_{-k}|^2) / 2 gives two real
-// spectra from one complex FFT.  Radix-2 decimation in time, FP64, the
-// input loaded in bit-reversed order; twiddles from a table computed once.
-// Each block keeps the sum of its groups' periodograms in its own row of
-// partials, summed over blocks in a fixed order by k_vdos_reduce: the result
-// does not depend on scheduling.
+// The series is read with a sample stride and a dof stride.  The recorder
+// keeps one row of dofs per sample ([samples][dof], the row a step writes
+// with coalesced stores); a block reads rows of its 2 CW dofs.  A block
+// transforms groups of CW complex columns in LDS: complex column q packs the
+// real dofs 2q and 2q + 1, each scaled by the square root of its weight, so
+// that w_a |A_k|^2 + w_b |B_k|^2 = (|Z_k|^2 + |Z_{-k}|^2) / 2 gives two real
+// spectra from one complex FFT.  FP64, in place, decimation in frequency on
+// the naturally ordered input, two radix-2 stages at a time (a radix-4
+// butterfly with one LDS round trip per pair of stages), the bins then read
+// in bit-reversed order; twiddles from a table computed once.  Each block
+// keeps the sum of its groups' periodograms in its own row of partials; two
+// fixed-order passes sum the rows: the result does not depend on scheduling.
 #include "qtb_internal.h"
 
 namespace qtb {
 
 namespace {
 
-// complex points per block (64 KiB of LDS)
-constexpr int kVdosPoints = 4096;
-constexpr int kVdosMaxGrid = 2048;
+// complex points per block: 32 KiB of LDS (four blocks per CU) up to
+// segments of 2048 samples, one 4096-point column (64 KiB) above
+constexpr int kVdosPoints = 2048;
+constexpr size_t kVdosLdsBytes = 65536;
+constexpr int kVdosBatch = 8;
+constexpr int kVdosMaxGrid = 1024;
+constexpr int kVdosStageRows = 32;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 w)
+{
+    return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+
+// Two decimation-in-frequency stages (spans 2 h2 and h2) on the four points
+// z[0], z[h2], z[2 h2], z[3 h2]: w1 = W_{4 h2}^pos, w2 = W_{2 h2}^pos.
+__device__ __forceinline__ void dif4(double2& a, double2& b, double2& c, double2& d, double2 w1,
+                                     double2 w2)
+{
+    const double2 a1 = make_double2(a.x + c.x, a.y + c.y);
+    const double2 c1 = cmul(make_double2(a.x - c.x, a.y - c.y), w1);
+    const double2 b1 = make_double2(b.x + d.x, b.y + d.y);
+    const double2 e = cmul(make_double2(b.x - d.x, b.y - d.y), w1);
+    const double2 d1 = make_double2(e.y, -e.x);  // times W_4 = -i
+    a = make_double2(a1.x + b1.x, a1.y + b1.y);
+    b = cmul(make_double2(a1.x - b1.x, a1.y - b1.y), w2);
+    c = make_double2(c1.x + d1.x, c1.y + d1.y);
+    d = cmul(make_double2(c1.x - d1.x, c1.y - d1.y), w2);
+}
 
 __global__ void __launch_bounds__(256) k_vdos_twiddle(double2* __restrict__ tw, int seg)
 {
@@ -39,73 +66,154 @@ __global__ void __launch_bounds__(256) k_vdos_twiddle(double2* __restrict__ tw, 
     }
 }
 
-__global__ void __launch_bounds__(256) k_vdos_fft(const double* __restrict__ v, int n_dof,
-                                                  const double* __restrict__ weight,
-                                                  const double2* __restrict__ tw, int L2, int cw,
-                                                  int n_groups, double* __restrict__ partials)
+// LDS_TW: the twiddle table is copied into LDS behind the columns.  Groups
+// follow the XCD-aware block order: groups g and g + 1, which share the HBM
+// lines of a row of samples, run on one XCD at the same time.
+template <bool LDS_TW>
+__global__ void __launch_bounds__(256) k_vdos_fft(const double* __restrict__ v, int64_t ts,
+                                                  int64_t js, int n_dof,
+                                                  const double* __restrict__ tw_g, int L2, int cw,
+                                                  int n_groups, const double* __restrict__ sqrt_w,
+                                                  double* __restrict__ partials)
 {
-    extern __shared__ double2 zb[];  // [cw][seg]
+    extern __shared__ double2 zb[];  // [cw][seg], then the twiddles if LDS_TW
     const int seg = 1 << L2, hseg = seg >> 1, ncol = 2 * cw;
     const int lc = __builtin_ctz(ncol);
-    double* __restrict__ prow = partials + (size_t)blockIdx.x * (hseg + 1);
-    for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
+    const bool time_major = ts == 1;  // each dof's samples contiguous
+    const int n_b = cw << (L2 - 2);   // radix-4 butterflies per pair of stages
+    const int lb = xcd_block();
+    const double2* __restrict__ twg = reinterpret_cast<const double2*>(tw_g);
+    const size_t tw_off = (size_t)cw * seg;
+    if (LDS_TW)  // made visible by the barrier after the first group's load
+        for (int k = threadIdx.x; k < hseg; k += blockDim.x) zb[tw_off + k] = twg[k];
+    auto tw = [&](int k) -> double2 {
+        if constexpr (LDS_TW) return zb[tw_off + k];
+        else return twg[k];
+    };
+    double* __restrict__ prow = partials + (size_t)lb * (hseg + 1);
+    for (int g = lb; g < n_groups; g += gridDim.x) {
         const int c0 = g * ncol;
-        // rows of ncol consecutive dofs (one coalesced segment per sample)
-        for (int e = threadIdx.x; e < seg * ncol; e += blockDim.x) {
-            const int t = e >> lc, c = e & (ncol - 1), j = c0 + c;
-            double x = 0.0;
-            if (j < n_dof) x = v[(size_t)t * n_dof + j] * sqrt(weight[j]);
-            const int rt = (int)(__builtin_bitreverse32((uint32_t)t) >> (32 - L2));
-            reinterpret_cast<double*>(zb + (size_t)(c >> 1) * seg + rt)[c & 1] = x;
+        // batches of kVdosBatch loads in flight per thread, then the LDS stores
+        const int total = seg * ncol;
+        for (int e0 = threadIdx.x; e0 < total; e0 += kVdosBatch * blockDim.x) {
+            // unconditional loads (indices clamped into range), all in flight
+            // together; out-of-range elements are zeroed afterwards
+            double x[kVdosBatch], wj[kVdosBatch];
+#pragma unroll
+            for (int u = 0; u < kVdosBatch; ++u) {
+                const int e = min(e0 + u * (int)blockDim.x, total - 1);
+                const int t = time_major ? (e & (seg - 1)) : (e >> lc);
+                const int c = time_major ? (e >> L2) : (e & (ncol - 1));
+                const int j = min(c0 + c, n_dof - 1);
+                x[u] = v[(int64_t)t * ts + (int64_t)j * js];
+                wj[u] = sqrt_w[j];
+            }
+#pragma unroll
+            for (int u = 0; u < kVdosBatch; ++u) {
+                const int e = e0 + u * blockDim.x;
+                if (e < total) {
+                    const int t = time_major ? (e & (seg - 1)) : (e >> lc);
+                    const int c = time_major ? (e >> L2) : (e & (ncol - 1));
+                    reinterpret_cast<double*>(zb + (size_t)(c >> 1) * seg + t)[c & 1] =
+                        (c0 + c < n_dof) ? x[u] * wj[u] : 0.0;
+                }
+            }
         }
         __syncthreads();
-        for (int s = 0; s < L2; ++s) {
-            const int half = 1 << s;
-            for (int b = threadIdx.x; b < cw * hseg; b += blockDim.x) {
-                const int q = b >> (L2 - 1), jb = b & (hseg - 1), pos = jb & (half - 1);
-                const int i0 = ((jb >> s) << (s + 1)) + pos, i1 = i0 + half;
-                const double2 w = tw[pos << (L2 - 1 - s)];
-                double2* z = zb + (size_t)q * seg;
-                const double2 a = z[i0], u = z[i1];
-                const double tr = w.x * u.x - w.y * u.y, ti = w.x * u.y + w.y * u.x;
-                z[i0] = make_double2(a.x + tr, a.y + ti);
-                z[i1] = make_double2(a.x - tr, a.y - ti);
+        int s = L2;
+        for (; s >= 2; s -= 2) {
+            const int lh2 = s - 2, h2 = 1 << lh2;
+            // two butterflies per thread and pass: their LDS loads overlap
+            for (int b0 = threadIdx.x; b0 < n_b; b0 += 2 * blockDim.x) {
+                const int b1 = b0 + blockDim.x;
+                const bool two = b1 < n_b;
+                double2 *z0, *z1;
+                double2 w10, w20, w11, w21;
+                {
+                    const int q = b0 >> (L2 - 2), jb = b0 & ((seg >> 2) - 1), pos = jb & (h2 - 1);
+                    z0 = zb + (size_t)q * seg + ((jb >> lh2) << s) + pos;
+                    w10 = tw(pos << (L2 - s));
+                    w20 = tw(pos << (L2 - s + 1));
+                }
+                {
+                    const int bb = two ? b1 : b0;
+                    const int q = bb >> (L2 - 2), jb = bb & ((seg >> 2) - 1), pos = jb & (h2 - 1);
+                    z1 = zb + (size_t)q * seg + ((jb >> lh2) << s) + pos;
+                    w11 = tw(pos << (L2 - s));
+                    w21 = tw(pos << (L2 - s + 1));
+                }
+                double2 a0 = z0[0], p0 = z0[h2], c0v = z0[2 * h2], d0 = z0[3 * h2];
+                double2 a1 = z1[0], p1 = z1[h2], c1v = z1[2 * h2], d1 = z1[3 * h2];
+                dif4(a0, p0, c0v, d0, w10, w20);
+                dif4(a1, p1, c1v, d1, w11, w21);
+                z0[0] = a0;
+                z0[h2] = p0;
+                z0[2 * h2] = c0v;
+                z0[3 * h2] = d0;
+                if (two) {
+                    z1[0] = a1;
+                    z1[h2] = p1;
+                    z1[2 * h2] = c1v;
+                    z1[3 * h2] = d1;
+                }
             }
             __syncthreads();
         }
+        if (s == 1) {  // odd number of stages: the last one has span 1
+            for (int m = threadIdx.x; m < cw * hseg; m += blockDim.x) {
+                double2* z = zb + 2 * (size_t)m;
+                const double2 a = z[0], b = z[1];
+                z[0] = make_double2(a.x + b.x, a.y + b.y);
+                z[1] = make_double2(a.x - b.x, a.y - b.y);
+            }
+            __syncthreads();
+        }
+        // bin k sits at the bit reverse of k
         for (int k = threadIdx.x; k <= hseg; k += blockDim.x) {
-            const int km = (seg - k) & (seg - 1);
+            const int rk = (int)(__builtin_bitreverse32((uint32_t)k) >> (32 - L2));
+            const int rm = (int)(__builtin_bitreverse32((uint32_t)((seg - k) & (seg - 1))) >> (32 - L2));
             double p = 0.0;
             for (int q = 0; q < cw; ++q) {
-                const double2 a = zb[(size_t)q * seg + k], u = zb[(size_t)q * seg + km];
+                const double2 a = zb[(size_t)q * seg + rk], u = zb[(size_t)q * seg + rm];
                 p += a.x * a.x + a.y * a.y + u.x * u.x + u.y * u.y;
             }
-            prow[k] = (g == (int)blockIdx.x) ? 0.5 * p : prow[k] + 0.5 * p;
+            prow[k] = (g == lb) ? 0.5 * p : prow[k] + 0.5 * p;
         }
         __syncthreads();  // the next group overwrites the LDS columns
     }
 }
 
-// spec[k] = (accumulate ? spec[k] : 0) + scale * sum over rows of partials
-__global__ void __launch_bounds__(256) k_vdos_reduce(const double* __restrict__ partials, int rows,
-                                                     int nk, double* __restrict__ spec, double scale,
-                                                     int accumulate)
+// Rows r = y, y + n_out, y + 2 n_out, ... of in [rows][nk], summed in that
+// order: out[y][k] for n_out > 1; for n_out = 1 the final spectrum,
+// spec[k] = (accumulate ? spec[k] : 0) + scale * sum.
+__global__ void __launch_bounds__(256) k_vdos_reduce(const double* __restrict__ in, int rows,
+                                                     int nk, double* __restrict__ out, int n_out,
+                                                     double scale, int accumulate)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (k >= nk) return;
     double s = 0.0;
-    for (int r = 0; r < rows; ++r) s += partials[(size_t)r * nk + k];
-    spec[k] = (accumulate ? spec[k] : 0.0) + scale * s;
+#pragma unroll 8
+    for (int r = y; r < rows; r += n_out) s += in[(size_t)r * nk + k];
+    if (n_out > 1) out[(size_t)y * nk + k] = s;
+    else out[k] = (accumulate ? out[k] : 0.0) + scale * s;
 }
 
-// w[a N + i] = m mu of atom i's species (the recorder's trace layout)
+// sw[a N + i] = sqrt(m mu) of atom i's species (the recorder's trace layout)
 __global__ void __launch_bounds__(256) k_vdos_weights(const RepDev* __restrict__ reps, int r,
-                                                      double* __restrict__ w)
+                                                      double* __restrict__ sw)
 {
     const RepDev& R = reps[r];
     const int n = R.dims * R.N;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
-        w[j] = R.mmu[R.species[j % R.N]];
+        sw[j] = sqrt(R.mmu[R.species[j % R.N]]);
+}
+
+__global__ void __launch_bounds__(256) k_vdos_sqrt(const double* __restrict__ w, int n,
+                                                   double* __restrict__ sw)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        sw[j] = sqrt(w[j]);
 }
 
 }  // namespace
@@ -122,6 +230,7 @@ VdosPlan vdos_plan(int n_dof, int seg)
     p.n_groups = (n_pairs + p.cw - 1) / p.cw;
     p.grid = p.n_groups < kVdosMaxGrid ? p.n_groups : kVdosMaxGrid;
     p.nk = seg / 2 + 1;
+    p.stage_rows = p.grid > kVdosStageRows ? kVdosStageRows : 0;
     return p;
 }
 
@@ -131,22 +240,43 @@ void launch_vdos_twiddle(hipStream_t st, double* tw, int seg)
            reinterpret_cast<double2*>(tw), seg);
 }
 
-void launch_vdos_segment(hipStream_t st, const VdosPlan& p, const double* v, int n_dof,
-                         const double* weight, const double* tw, double* partials, double* spec,
-                         double scale, bool accumulate)
+void launch_vdos_segment(hipStream_t st, const VdosPlan& p, const double* v, int64_t ts,
+                         int64_t js, int n_dof, const double* sqrt_w, const double* tw,
+                         double* partials, double* stage, double* spec, double scale,
+                         bool accumulate)
 {
-    const uint32_t lds = (uint32_t)(sizeof(double2) * (size_t)p.cw * p.seg);
-    launch(k_vdos_fft, dim3(p.grid), dim3(256), lds, st, v, n_dof, weight,
-           reinterpret_cast<const double2*>(tw), p.L2, p.cw, p.n_groups, partials);
-    launch(k_vdos_reduce, dim3((p.nk + 255) / 256), dim3(256), 0, st, (const double*)partials,
-           p.grid, p.nk, spec, scale, accumulate ? 1 : 0);
+    const size_t cols = sizeof(double2) * (size_t)p.cw * p.seg, tws = sizeof(double2) * (p.seg / 2);
+    if (cols + tws <= kVdosLdsBytes)
+        launch(k_vdos_fft<true>, dim3(p.grid), dim3(256), (uint32_t)(cols + tws), st, v, ts, js,
+               n_dof, tw, p.L2, p.cw, p.n_groups, sqrt_w, partials);
+    else
+        launch(k_vdos_fft<false>, dim3(p.grid), dim3(256), (uint32_t)cols, st, v, ts, js, n_dof,
+               tw, p.L2, p.cw, p.n_groups, sqrt_w, partials);
+    const unsigned bx = (unsigned)((p.nk + 255) / 256);
+    const double* rows = partials;
+    int n_rows = p.grid;
+    if (p.stage_rows > 0) {
+        launch(k_vdos_reduce, dim3(bx, (unsigned)p.stage_rows), dim3(256), 0, st, rows, n_rows,
+               p.nk, stage, p.stage_rows, 1.0, 0);
+        rows = stage;
+        n_rows = p.stage_rows;
+    }
+    launch(k_vdos_reduce, dim3(bx, 1u), dim3(256), 0, st, rows, n_rows, p.nk, spec, 1, scale,
+           accumulate ? 1 : 0);
 }
 
-void launch_vdos_weights(hipStream_t st, const RepDev* reps, int r, int n_dof, double* w)
+void launch_vdos_weights(hipStream_t st, const RepDev* reps, int r, int n_dof, double* sw)
 {
     int blocks = (n_dof + 255) / 256;
     if (blocks > 1024) blocks = 1024;
-    launch(k_vdos_weights, dim3(blocks), dim3(256), 0, st, reps, r, w);
+    launch(k_vdos_weights, dim3(blocks), dim3(256), 0, st, reps, r, sw);
+}
+
+void launch_vdos_sqrt(hipStream_t st, const double* w, int n, double* sw)
+{
+    int blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    launch(k_vdos_sqrt, dim3(blocks), dim3(256), 0, st, w, n, sw);
 }
 
 }  // namespace qtb

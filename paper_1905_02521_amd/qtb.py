@@ -135,8 +135,9 @@ def lib():
     L.qtb_vdos_workspace_bytes.restype = ctypes.c_size_t
     L.qtb_vdos_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.qtb_vdos_spectrum.restype = ctypes.c_int
-    L.qtb_vdos_spectrum.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int32, vp,
-                                    vp, ctypes.c_size_t, vp]
+    L.qtb_vdos_spectrum.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                    ctypes.c_int64, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t,
+                                    vp]
     L.qtb_vdos_attach.restype = ctypes.c_int
     L.qtb_vdos_attach.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t]
     L.qtb_vdos_read.restype = ctypes.c_int
@@ -217,17 +218,22 @@ def qtb_gaussian(seed, stream, tag, n0, n_rows, d0, n_dof, out=None):
 
 
 # ---------------------------------------------------------------- spectra
-def vdos_spectrum(v, weight, seg):
-    """Velocity spectrum S[k], k = 0..seg/2, of a device series v [n_samples,
-    n_dof] (float64) with device weights [n_dof], over its whole segments."""
+def vdos_spectrum(v, weight, seg, dof_major=False):
+    """Velocity spectrum S[k], k = 0..seg/2, of a device series (float64)
+    v [n_samples, n_dof] (or [n_dof, n_samples] with dof_major) with device
+    weights [n_dof], over its whole segments."""
     torch = _torch()
-    n_samples, n_dof = v.shape
+    if dof_major:
+        n_dof, n_samples = v.shape
+    else:
+        n_samples, n_dof = v.shape
+    ts, js = v.stride() if not dof_major else v.stride()[::-1]
     nbytes = lib().qtb_vdos_workspace_bytes(n_dof, seg, 0)
     if nbytes == 0:
         raise QtbError(QTB_E_INVALID, "qtb_vdos_workspace_bytes rejected the sizes")
     ws = torch.empty(nbytes, dtype=torch.uint8, device=v.device)
     out = torch.empty(seg // 2 + 1, dtype=torch.float64, device=v.device)
-    _check(lib().qtb_vdos_spectrum(ctypes.c_void_p(v.data_ptr()), n_samples, n_dof,
+    _check(lib().qtb_vdos_spectrum(ctypes.c_void_p(v.data_ptr()), n_samples, n_dof, ts, js,
                                    ctypes.c_void_p(weight.data_ptr()), seg,
                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                    nbytes, current_stream_ptr()))

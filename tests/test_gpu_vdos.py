@@ -2,9 +2,9 @@
 to time-correlation functions; the DOS is the check to make at high gamma).
 
 Parity (FP64, against the oracle's segment periodograms):
-* the standalone transform on seeded series: one dof, odd dof counts, a
-  ragged trailing segment, no whole segment, the largest segment, a crystal's
-  worth of dofs; every bin within 1e-12 of the largest;
+* the standalone transform on seeded series in both layouts: one dof, odd
+  dof counts, a ragged trailing segment, no whole segment, the largest
+  segment, a crystal's worth of dofs; every bin within 1e-12 of the largest;
 * the recorder on QTB trajectories: harmonic oscillators (odd count) and the
   MgO crystal with separate and with one-kernel steps, against the spectra of
   the oracle's own trajectories; restart and set_state cut the series;
@@ -41,17 +41,20 @@ def full_mean(S):
     return (S[0] + S[-1] + 2.0 * np.sum(S[1:-1])) / seg
 
 
+@pytest.mark.parametrize("dof_major", [False, True])
 @pytest.mark.parametrize("n_samples,n_dof,seg", [
     (64, 1, 16), (100, 7, 16), (3 * 256 + 5, 301, 256), (2048, 3 * 4096, 1024),
     (4096, 3, 4096), (8192, 2, 4096), (10, 5, 16), (5 * 64, 4097, 64)])
-def test_spectrum_matches_oracle(orc, n_samples, n_dof, seg):
+def test_spectrum_matches_oracle(orc, n_samples, n_dof, seg, dof_major):
+    """Both layouts: [samples][dofs] (read row by row) and [dofs][samples]
+    (each dof's series contiguous, the recorder's layout)."""
     import torch
     rng = np.random.default_rng(n_samples * 7 + n_dof)
     v = rng.normal(size=(n_samples, n_dof)) * rng.uniform(0.2, 3.0, n_dof)
     w = rng.uniform(0.5, 40.0, n_dof)
-    dv = torch.from_numpy(v).cuda()
+    dv = torch.from_numpy(np.ascontiguousarray(v.T) if dof_major else v).cuda()
     dw = torch.from_numpy(w).cuda()
-    S = qtb.vdos_spectrum(dv, dw, seg).cpu().numpy()
+    S = qtb.vdos_spectrum(dv, dw, seg, dof_major=dof_major).cpu().numpy()
     _, So, n_seg = orc.vdos(v, seg, w)
     assert S.shape == So.shape == (seg // 2 + 1,)
     if n_seg == 0:
@@ -205,3 +208,82 @@ def test_oscillator_vdos_matches_linear_response():
     assert np.max(np.abs(z)) < 4.5
     assert 0.6 < np.mean(z * z) < 1.5
     assert abs(full_mean(mean) / v2 - 1) < 0.01
+
+
+def _crystal_dos(noise, gamma, T=100.0, seg=2048, n_seg=16, two_nf=1024, eq=6000):
+    beads, sp, box = crystal(4, 1, seed=3)
+    ctx = gpu_crystal_ctx(beads, sp, box, T=T, gamma=gamma, dt=1.0, noise=noise,
+                          prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3, seed=5, max_two_nf=two_nf,
+                          obs_every=1)
+    taps = ctx.build_filter(0, noise, two_nf) if noise else None
+    ctx.step(eq)
+    ctx.vdos_attach(0, seg)
+    ctx.step(seg * n_seg)
+    S, n = ctx.vdos_read(0)
+    ctx.close()
+    assert n == n_seg
+    return S, taps
+
+
+def test_high_friction_dos_tail_broadening_and_zpel():
+    """MgO 4x4x4 (512 atoms) at 100 K, production precision, dt = 1 fs,
+    every step sampled, 16 segments of 2048 after 6000 steps, classical
+    Langevin and QTB at gamma = 0.001, 0.005, 0.02, 0.05 / fs.  The claims of
+    Sec. 3 on raising gamma, measured on the spectrum:
+    * the spurious high-frequency tail: above four times the top of the
+      phonon band the atoms answer the bath as free particles, so the tail's
+      weight is the friction response of the discrete scheme to the noise
+      spectrum (closed form) within a few per cent; with QTB noise it carries
+      several times the classical tail's share of the kinetic energy;
+    * broadening: the main peak's width grows several-fold;
+    * zero-point-energy leakage at small gamma: against the harmonic share
+      (classical spectrum times theta(omega) / k_B T, eq. 1) the low band of
+      the QTB spectrum holds too much and the top band too little; raising
+      gamma removes most of the imbalance."""
+    from tests.closed_forms import theta_coth, velocity_spectrum_discrete
+    gammas = (0.001, 0.005, 0.02, 0.05)
+    kT, hbar, dt, seg, n_dof = W.METAL_UNITS["kB"] * 100.0, W.METAL_UNITS["hbar"], 1.0, 2048, 1536
+    res = {(nz, g): _crystal_dos(nz, g) for nz in (0, 1) for g in gammas}
+    w = 2 * np.pi * np.arange(seg // 2 + 1) / (seg * dt)
+    S0 = res[(0, 0.001)][0]
+    k_top = int(np.max(np.nonzero(S0 > 0.01 * S0.max())))   # top of the phonon band
+    k0 = 4 * k_top
+    tail = lambda S: (2 * np.sum(S[k0:-1]) + S[-1]) / seg
+    ratio, frac, width = {}, {}, {}
+    for (nz, g), (S, taps) in res.items():
+        c1 = math.exp(-g * dt)
+        M, b = baoab_mode_map(0.0, 0.0, c1, math.sqrt(1 - c1 * c1), dt)
+        Sf = velocity_spectrum_discrete(M, b, taps if nz else [math.sqrt(kT)], w[1:] * dt)
+        ratio[(nz, g)] = tail(S) / (n_dof * tail(np.concatenate([[0.0], Sf])))
+        frac[(nz, g)] = tail(S) / full_mean(S)
+        k = int(np.argmax(S))
+        lo, hi = k, k
+        while lo > 0 and S[lo] > S[k] / 2:
+            lo -= 1
+        while S[hi] > S[k] / 2:
+            hi += 1
+        width[(nz, g)] = w[hi] - w[lo]
+        print(f"noise {nz} gamma {g}: tail/free-particle {ratio[(nz, g)]:.4f}, tail share of 2K "
+              f"{frac[(nz, g)]:.4f}, main-peak FWHM {width[(nz, g)]:.4f} rad/fs")
+    for g in gammas:
+        assert 0.98 < ratio[(1, g)] < 1.06
+        if g >= 0.02:
+            assert 0.98 < ratio[(0, g)] < 1.06
+        assert frac[(1, g)] > 5 * frac[(0, g)]
+    for nz in (0, 1):
+        assert all(frac[(nz, a)] < frac[(nz, b)] for a, b in zip(gammas[:-1], gammas[1:]))
+    assert width[(1, 0.05)] > 4 * width[(1, 0.001)]
+    # leakage: QTB band weight against classical weight x theta / k_B T
+    th = np.array([theta_coth(x, kT, hbar) for x in w[1:k_top + 1]]) / kT
+    edges = [0.0, 0.06, 0.09, 0.12, w[k_top]]
+    share = {}
+    for g in gammas:
+        Sc, Sq = res[(0, g)][0][1:k_top + 1], res[(1, g)][0][1:k_top + 1]
+        share[g] = [np.sum(Sq[m]) / np.sum((Sc * th)[m])
+                    for m in ((w[1:k_top + 1] > a) & (w[1:k_top + 1] <= b)
+                              for a, b in zip(edges[:-1], edges[1:]))]
+        print(f"gamma {g}: QTB / harmonic share by band {np.round(share[g], 3)}")
+    whole = np.sum(res[(1, 0.001)][0][1:k_top + 1]) / np.sum(res[(0, 0.001)][0][1:k_top + 1] * th)
+    assert abs(whole - 1) < 0.02           # in-band total: the harmonic energy theta(omega)
+    assert share[0.001][0] > 1.15 and share[0.001][-1] < 0.85
+    assert abs(share[0.05][0] - 1) < 0.06 and abs(share[0.05][-1] - 1) < 0.03
