@@ -215,6 +215,44 @@ def zeta(h: np.ndarray, seed, stream, n, d):
     return lib().orc_zeta(_pd(h), len(h), seed, stream, n, d)
 
 
+def noise_spectrum(kind, T, P, dt, n, units: Units) -> np.ndarray:
+    """Target spectrum of the random force on the grid omega_j = 2 pi j / (n dt),
+    j = 0 .. n/2: k_B T (white), theta (eq. 1, QTB) or kappa_P (eq. 10-12)."""
+    kT = units.kB * T
+    out = np.empty(n // 2 + 1)
+    for j in range(n // 2 + 1):
+        w = 2.0 * np.pi * j / (n * dt)
+        out[j] = kT if kind == 0 else (theta(w, T, units) if kind == 1 or P == 1
+                                       else kappa(w, T, P, units))
+    return out
+
+
+def eq9_block(S, seed, stream, row0, n_dof):
+    """One block of n steps of coloured noise by the paper's generator (eq. 9):
+    random Fourier amplitudes (a_j + i b_j) sqrt(S_j n / 2) on the grid
+    omega_j = 2 pi j / (n dt), then the inverse discrete Fourier transform.
+    The paper leaves the construction of a real force implicit; here the
+    amplitudes of the negative frequencies are the complex conjugates of the
+    positive ones (Hermitian), and the two self-conjugate terms j = 0 and
+    j = n/2 are real with amplitude a_j sqrt(S_j n), so that every mode
+    carries E|R_j|^2 = n S_j and the noise has the discrete spectrum S.
+    a_j, b_j are the library's counter-based unit Gaussians at step row0 + j
+    (tags 1 and 2).  S: [n/2 + 1]; returns zeta [n][n_dof]."""
+    S = np.asarray(S, dtype=np.float64)
+    n = 2 * (len(S) - 1)
+    h = n // 2
+    a = gauss_fill(seed, row0, h + 1, 0, n_dof, stream, 1)
+    b = gauss_fill(seed, row0, h + 1, 0, n_dof, stream, 2)
+    X = np.zeros((n, n_dof), dtype=np.complex128)
+    amp = np.sqrt(S * n / 2.0)
+    for j in range(1, h):
+        X[j] = amp[j] * (a[j] + 1j * b[j])
+        X[n - j] = np.conj(X[j])
+    X[0] = np.sqrt(S[0] * n) * a[0]
+    X[h] = np.sqrt(S[h] * n) * a[h]
+    return np.fft.ifft(X, axis=0).real
+
+
 def nm_matrix(P) -> np.ndarray:
     C = np.zeros((P, P))
     lib().orc_nm_matrix(P, _pd(C))

@@ -157,3 +157,31 @@ def velocity_spectrum_discrete(M, b, taps, phi):
         g = np.linalg.solve(np.exp(1j * p) * I - M, b)
         out[q] = abs(g[1]) ** 2 * abs(Hz[q]) ** 2
     return out
+
+
+def block_noise_autocovariance(S_half, L):
+    """Time-averaged autocovariance, lags 0 .. L-1, of noise made in independent
+    blocks of n steps by the inverse DFT of Hermitian random amplitudes with
+    E|R_j|^2 = n S_j: within a block the covariance is circular,
+    c(tau) = (1/n) sum_j S_j cos(2 pi j tau / n); a pair at lag tau shares a
+    block for a fraction 1 - tau/n of the positions and is independent
+    otherwise."""
+    S_half = np.asarray(S_half, dtype=np.float64)
+    n = 2 * (len(S_half) - 1)
+    S = np.concatenate([S_half, S_half[-2:0:-1]])
+    c = np.fft.ifft(S).real
+    tau = np.arange(L)
+    return np.where(tau < n, (1.0 - tau / n) * c[tau % n], 0.0)
+
+
+def stationary_moments_cov(M, b, R):
+    """Second moments of z_{n+1} = M z_n + b zeta_n for noise with the
+    (time-averaged) autocovariance R[tau], tau = 0 .. len(R) - 1."""
+    X0 = solve_discrete_lyapunov(M, np.outer(b, b))
+    S = R[0] * X0
+    Mt = np.eye(len(b))
+    for t in range(1, len(R)):
+        Mt = Mt @ M
+        if R[t] != 0.0:
+            S += R[t] * (X0 @ Mt.T + Mt @ X0)
+    return S
