@@ -487,6 +487,9 @@ def main():
                          "(the velocity spectrum's recorder and transform)")
     ap.add_argument("--fir", default="bf16x3", choices=["fp32", "bf16x3", "bf16", "fp64"])
     ap.add_argument("--K", type=int, default=64)
+    ap.add_argument("--noise-blocks", action="store_true",
+                    help="make the coloured noise with the paper's block generator (eq. 9, "
+                         "blocks of max two_nf steps) instead of the streaming FIR")
     ap.add_argument("--blocks", type=int, default=40,
                     help="qtb-vs-pimd: measured blocks of 1000 steps per method")
     ap.add_argument("--skin", type=float, default=None,
@@ -534,7 +537,8 @@ def main():
         reps.append(qtb.Replica(pos=beads, species=sp, T=w.T, gamma=w.gamma, dt=w.dt,
                                 noise=w.noise, box=tuple(box), seed=w.seed, stream=w.stream))
     ctx = qtb.Context(qtb.pair_potential_dict(pot), reps, W.METAL_UNITS, prec=prec, fir=fir,
-                      fir_block_K=a.K, obs_every=0, max_two_nf=max(max(w.two_nf, 2) for w in works))
+                      fir_block_K=a.K, obs_every=0, max_two_nf=max(max(w.two_nf, 2) for w in works),
+                      noise_blocks=a.noise_blocks)
     for k, w in enumerate(works):
         if w.noise:
             ctx.build_filter(k, w.noise, w.two_nf)
@@ -571,7 +575,7 @@ def main():
     fir_ms, fir_n = prof["fir"]
     D = 3 * ab_per_step
     fir_bytes = a.K * D * FIR_BYTES_PER_DOF_STEP
-    fir_gbs = fir_bytes / (fir_ms / max(fir_n, 1) * 1e-3) / 1e9 if fir_n else None
+    fir_gbs = fir_bytes / (fir_ms / max(fir_n, 1) * 1e-3) / 1e9 if fir_n and not a.noise_blocks else None
     # HBM traffic from the committed counter record, valid only for this
     # workload and only while the pair kernel's source is unchanged
     traffic = stored_traffic() if a.workload == "mgo-8x8x8-qtbpimd-P8-50K" else None
@@ -600,6 +604,7 @@ def main():
                    "noise": "QTB-PIMD kappa_P" if w.noise == 2 and not batched else
                             ("QTB theta" if not batched else "QTB theta (P=1) / kappa_P (P>1)"),
                    "two_nf": sorted(set(x.two_nf for x in works)), "fir": a.fir,
+                   "noise_generator": "eq. 9 blocks" if a.noise_blocks else "streaming FIR",
                    "fir_block_K": a.K,
                    "forces": "fp32" if prec == qtb.PREC_FP32 else "fp64", "state": "fp64",
                    "r_cut_A": pot.r_cut, "skin_A": pot.skin, "parallelism": "1 GPU"},
@@ -614,10 +619,10 @@ def main():
                          "achieved_slots_per_s": pairs * SLOTS_PER_PAIR / (force_ms * 1e-3),
                          "peak_slots_per_s": PEAK_LANE_SLOTS,
                          "frac": pairs * SLOTS_PER_PAIR / (force_ms * 1e-3) / PEAK_LANE_SLOTS}},
-        "fir": {"achieved_GBs": fir_gbs, "peak_GBs": PEAK_HBM_GBS,
-                "frac": (fir_gbs / PEAK_HBM_GBS) if fir_gbs else None,
-                "bytes_per_launch": fir_bytes,
-                "ms_per_launch": fir_ms / max(fir_n, 1)},
+        "fir": None if a.noise_blocks else {
+            "achieved_GBs": fir_gbs, "peak_GBs": PEAK_HBM_GBS,
+            "frac": (fir_gbs / PEAK_HBM_GBS) if fir_gbs else None,
+            "bytes_per_launch": fir_bytes, "ms_per_launch": fir_ms / max(fir_n, 1)},
         "phases": phases,
     }
     if not a.no_cpu:

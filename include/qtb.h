@@ -164,6 +164,19 @@ typedef struct {
  * steps that rebuild a list.  Off by default: on gfx950 the fused kernel's
  * update tail costs more than the two launches it saves. */
 #define QTB_OPT_FUSE 8
+/* qtb_options.flags: make the coloured noise with the paper's block generator
+ * (eq. 9) instead of the streaming FIR: for each block of n = max_two_nf
+ * steps (global steps B n .. B n + n - 1) and each dof, random Fourier
+ * amplitudes (a_j + i b_j) sqrt(n S_j / 2) on the grid omega_j = 2 pi j / (n dt)
+ * (a_j, b_j the library's Gaussians at the replica step of the block's first
+ * step + j, tags 1 and 2), completed Hermitian (mode n - j the conjugate of
+ * mode j; modes 0 and n/2 real, a_j sqrt(n S_j)), then an inverse DFT.  S is
+ * the filter's spectrum (theta, kappa_P or k_B T) on the same grid.
+ * Blocks are independent: the noise has the target spectrum inside a block
+ * and no correlation across block boundaries.  n must be a power of two in
+ * [fir_block_K, 4096]; qtb_build_filter's two_nf must equal n; the noise
+ * precision follows prec; not with QTB_OPT_FUSE. */
+#define QTB_OPT_NOISE_BLOCKS 16
 
 /* Means over the samples taken since the previous qtb_observables call of
  * this replica (eq. 5 primitive estimator with instantaneous momenta). */

@@ -104,6 +104,23 @@ double design_kappa(double omega, double T, int P, double hbar, double kB)
     return kT * kappa_red(G, hbar * std::fabs(omega) / kT);
 }
 
+// The target spectrum S_j of the random force on the grid
+// omega_j = pi j / (Nf dt), j = 0 .. Nf (2 Nf = two_nf): k_BT (kind 0),
+// theta (eq. 1, kind 1) or kappa_P (eq. 10-12, kind 2).
+void design_spectrum(int kind, double T, int P, double dt, int two_nf, double hbar, double kB,
+                     double* S)
+{
+    const int Nf = two_nf / 2;
+    const double kT = kB * T;
+    KappaGrid G;
+    if (kind == 2 && P > 1) G = make_grid(P);
+    for (int j = 0; j <= Nf; ++j) {
+        const double w = kPi * j / (Nf * dt);
+        const double X = hbar * w / kT;
+        S[j] = kind == 0 ? kT : ((kind == 2 && P > 1) ? kT * kappa_red(G, X) : kT * theta_red(X));
+    }
+}
+
 // kind: 0 white (kT), 1 theta, 2 kappa_P.  out[k + Nf], k = -Nf .. Nf-1.
 void design_taps(int kind, double T, int P, double dt, int two_nf, double hbar, double kB,
                  double* out)
@@ -116,14 +133,8 @@ void design_taps(int kind, double T, int P, double dt, int two_nf, double hbar, 
         return;
     }
     std::vector<double> H(Nf + 1);
-    KappaGrid G;
-    if (kind == 2 && P > 1) G = make_grid(P);
-    for (int j = 0; j <= Nf; ++j) {
-        const double w = kPi * j / (Nf * dt);
-        const double X = hbar * w / kT;
-        const double S = (kind == 2 && P > 1) ? kT * kappa_red(G, X) : kT * theta_red(X);
-        H[j] = std::sqrt(S);
-    }
+    design_spectrum(kind, T, P, dt, two_nf, hbar, kB, H.data());
+    for (int j = 0; j <= Nf; ++j) H[j] = std::sqrt(H[j]);
     std::vector<double> ctab(two_nf);
     for (int m = 0; m < two_nf; ++m) ctab[m] = std::cos(kPi * m / Nf);
     for (int k = -Nf; k < Nf; ++k) {

@@ -14,6 +14,7 @@
 // of the atanh series to s^22/23, e ln2 with the fdlibm hi/lo split.
 // cos: quadrant q = round(4u) taken on the integer, r = 4u - q exact,
 // x = r pi/2 (hi/lo), Taylor series of cos and sin to x^18 / x^19.
+#include "fft_lds.h"
 #include "qtb_internal.h"
 
 #pragma clang fp contract(off)
@@ -185,6 +186,106 @@ void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, 
 }
 
 namespace {
+
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b)
+{
+    const int64_t q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+// The paper's generator (eq. 9): one block of n steps of coloured noise per
+// dof from random Fourier amplitudes on the grid omega_j = 2 pi j / (n dt),
+// then an inverse transform.  Mode j of a dof has the amplitude
+// A_j (a_j + i b_j), A_j = sqrt(n S_j / 2), and its mirror n - j the complex
+// conjugate, so the noise is real (the paper leaves this implicit); the
+// self-conjugate modes 0 and n/2 are real, A_j a_j with A_j = sqrt(n S_j).
+// a_j, b_j: the library's unit Gaussians at (replica step of the block's
+// first step + j, dof, tags 1 and 2).  Noise block B (global steps
+// B n .. B n + n - 1) lives in half B mod 2 of the [2 n][n_cols] buffer, so a
+// K-step noise block that crosses a boundary finds both; blockIdx.y = 0 / 1
+// makes the block of the K-step block's first / last step, unless the marker
+// of its half says it is there already (the launch then costs one early
+// exit per block: the grid is capped and strides over the column groups).
+// Two real dofs share one complex transform (x + i y), computed as
+// conj(FFT(conj Z)) / n in LDS.
+template <typename T>
+__global__ void __launch_bounds__(256) k_eq9(const RepDev* __restrict__ reps,
+                                             const FirTile* __restrict__ tiles,
+                                             const double* __restrict__ amp, int amp_stride,
+                                             const double* __restrict__ tw_g, int L2, int cw,
+                                             T* __restrict__ zeta, int64_t n_cols,
+                                             const int64_t* __restrict__ clock,
+                                             const int64_t* __restrict__ marker, int K,
+                                             int64_t n_groups)
+{
+    extern __shared__ double2 zb[];  // [cw][n]
+    const int n = 1 << L2, h = n >> 1;
+    const int64_t s0 = *clock;
+    const int64_t B = floor_div(s0 + (blockIdx.y ? K - 1 : 0), n);
+    if (blockIdx.y == 1 && B == floor_div(s0, n)) return;
+    const int half = (int)(B & 1);
+    if (marker[half] == B) return;
+    for (int64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
+        const int64_t c0 = g * 2 * cw;  // first real column of the group
+        const int rep = __builtin_amdgcn_readfirstlane(tiles[c0 / kDofTile].rep);
+        const RepDev& R = reps[rep];
+        const double* __restrict__ A = amp + (size_t)rep * amp_stride;
+        const int64_t D = (int64_t)R.dims * R.N * R.P;
+        const int64_t row0 = B * n + R.step_off;
+        for (int e = threadIdx.x; e < cw * (h + 1); e += blockDim.x) {
+            const int q = e / (h + 1), j = e - q * (h + 1);
+            const int64_t dx = c0 + 2 * q - R.dof_off, dy = dx + 1;
+            const bool inner = j > 0 && j < h;
+            double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
+            if (dx < D) {
+                ax = white_gauss(R.seed, row0 + j, (uint32_t)dx, R.stream, 1);
+                if (inner) bx = white_gauss(R.seed, row0 + j, (uint32_t)dx, R.stream, 2);
+            }
+            if (dy < D) {
+                ay = white_gauss(R.seed, row0 + j, (uint32_t)dy, R.stream, 1);
+                if (inner) by = white_gauss(R.seed, row0 + j, (uint32_t)dy, R.stream, 2);
+            }
+            const double Aj = A[j];
+            const double xr = Aj * ax, xi = Aj * bx, yr = Aj * ay, yi = Aj * by;
+            // Z_j = X_j + i Y_j and Z_{n-j} = conj(X_j) + i conj(Y_j), stored conjugated
+            double2* z = zb + (size_t)q * n;
+            z[j] = make_double2(xr - yi, -(xi + yr));
+            if (inner) z[n - j] = make_double2(xr + yi, xi - yr);
+        }
+        __syncthreads();
+        auto tw = [&](int k) -> double2 { return reinterpret_cast<const double2*>(tw_g)[k]; };
+        fft_dif_lds(zb, cw, L2, tw);
+        const double inv = 1.0 / (double)n;
+        T* __restrict__ out = zeta + (size_t)half * n * n_cols + c0;
+        for (int e = threadIdx.x; e < n * cw; e += blockDim.x) {
+            const int t = e / cw, q = e - t * cw;
+            const double2 F = zb[(size_t)q * n + bit_reverse(t, L2)];
+            out[(size_t)t * n_cols + 2 * q] = (T)(F.x * inv);
+            out[(size_t)t * n_cols + 2 * q + 1] = (T)(-F.y * inv);
+        }
+        __syncthreads();  // the next group overwrites the LDS columns
+    }
+}
+
+// After k_eq9: record which noise block each half holds (invalidate: none).
+__global__ void k_eq9_mark(const int64_t* __restrict__ clock, int64_t* __restrict__ marker, int n,
+                           int K, int invalidate)
+{
+    if (threadIdx.x != 0) return;
+    if (invalidate) {
+        marker[0] = marker[1] = INT64_MIN;
+        return;
+    }
+    const int64_t s0 = *clock;
+    for (int y = 0; y < 2; ++y) {
+        const int64_t B = floor_div(s0 + (y ? K - 1 : 0), n);
+        marker[B & 1] = B;
+    }
+}
+
+}  // namespace
+
+namespace {
 // Initial surrogate weights: N(0, 1/fan_in) from the same generator (tag 3,
 // step 0, dof = parameter index); biases zero.
 __global__ void k_ml_init(float* __restrict__ master, uint64_t seed)
@@ -208,6 +309,37 @@ __global__ void k_clock(int64_t* clock, int64_t v, int add)
 void launch_ml_init(hipStream_t st, float* master, uint64_t seed)
 {
     launch(k_ml_init, dim3((kMlParams + 255) / 256), dim3(256), 0, st, master, seed);
+}
+
+void launch_eq9(hipStream_t st, bool fp64, const RepDev* reps, const FirTile* tiles,
+                const double* amp, int amp_stride, const double* tw, int n, void* zeta,
+                int64_t n_cols, const int64_t* clock, int64_t* marker, int K)
+{
+    const int L2 = __builtin_ctz((unsigned)n);
+    const int cw = eq9_columns(n);
+    const int64_t n_groups = n_cols / (2 * cw);
+    const dim3 grid((unsigned)(n_groups < 2048 ? n_groups : 2048), 2u), block(256);
+    const uint32_t lds = (uint32_t)(sizeof(double2) * (size_t)cw * n);
+    if (fp64)
+        launch(k_eq9<double>, grid, block, lds, st, reps, tiles, amp, amp_stride, tw, L2, cw,
+               (double*)zeta, n_cols, (const int64_t*)clock, (const int64_t*)marker, K, n_groups);
+    else
+        launch(k_eq9<float>, grid, block, lds, st, reps, tiles, amp, amp_stride, tw, L2, cw,
+               (float*)zeta, n_cols, (const int64_t*)clock, (const int64_t*)marker, K, n_groups);
+    launch(k_eq9_mark, dim3(1), dim3(64), 0, st, clock, marker, n, K, 0);
+}
+
+void launch_eq9_invalidate(hipStream_t st, int64_t* marker)
+{
+    launch(k_eq9_mark, dim3(1), dim3(64), 0, st, (const int64_t*)nullptr, marker, 1, 1, 1);
+}
+
+int eq9_columns(int n)
+{
+    // complex columns per block: 2048 points (32 KiB of LDS), within one
+    // 256-column tile of a replica
+    const int cw = 2048 / n;
+    return cw < 1 ? 1 : (cw > kDofTile / 2 ? kDofTile / 2 : cw);
 }
 
 void launch_clock(hipStream_t st, int64_t* clock, int64_t v, bool add)

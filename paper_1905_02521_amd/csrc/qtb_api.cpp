@@ -18,6 +18,8 @@ namespace qtb {
 double design_theta(double omega, double T, double hbar, double kB);
 void design_taps(int kind, double T, int P, double dt, int two_nf, double hbar, double kB,
                  double* out);
+void design_spectrum(int kind, double T, int P, double dt, int two_nf, double hbar, double kB,
+                     double* S);
 }  // namespace qtb
 
 using namespace qtb;
@@ -37,6 +39,7 @@ struct Region {
 struct Layout {
     size_t total = 0;
     Region reps, status, rebuild, tiles, taps, ring, zeta, partials, acc, counts, pairtab, clock;
+    Region eq9amp, eq9tw, eq9mark;  // block noise (eq. 9): amplitudes, twiddles, block markers
     Region blk_upd, blk_nl, blk_force, blk_tb;
     // surrogate (ml_r_cut > 0)
     Region blk_mlc, blk_mlm, ml_acc, ml_counts, ml_loss, ml_stats, ml_foff, ml_wpart;
@@ -50,6 +53,8 @@ struct Layout {
     // derived sizes
     int64_t n_cols = 0;
     int R = 0, K = 0, max_two_nf = 0, taps_stride = 0;
+    bool eq9 = false;  // block noise: zeta is a [2 n][n_cols] ring, n = max_two_nf
+    int64_t zeta_rows = 0;
     std::vector<int64_t> dof_off;
     std::vector<int> maxnb, maxml;
     bool ml = false, ml_train = false;
@@ -126,6 +131,12 @@ const char* check_inputs(const qtb_potential* pot, const qtb_replica* reps, int 
     if (opt->max_two_nf < 2 || (opt->max_two_nf & 1) || opt->max_two_nf > 8192)
         return "max_two_nf must be even, in [2, 8192]";
     if (opt->fir != QTB_FIR_FP64 && opt->max_two_nf > 4096) return "BF16/FP32 FIR: max_two_nf <= 4096";
+    if (opt->flags & QTB_OPT_NOISE_BLOCKS) {
+        const int n = opt->max_two_nf;
+        if ((n & (n - 1)) || n < opt->fir_block_K || n > 4096)
+            return "block noise: max_two_nf must be a power of two in [fir_block_K, 4096]";
+        if (opt->flags & QTB_OPT_FUSE) return "block noise does not combine with the one-kernel step";
+    }
     for (int r = 0; r < n_rep; ++r) {
         const qtb_replica& R = reps[r];
         if (R.n_atoms < 1 || R.n_beads < 1 || R.n_beads > 64) return "replica sizes out of range";
@@ -177,6 +188,8 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     const size_t zs = opt->fir == QTB_FIR_FP64 ? 8 : 4;     // ring / zeta element
     L.K = opt->fir_block_K;
     L.max_two_nf = opt->max_two_nf;
+    L.eq9 = (opt->flags & QTB_OPT_NOISE_BLOCKS) != 0;
+    L.zeta_rows = L.eq9 ? 2 * (int64_t)opt->max_two_nf : L.K;
     L.R = L.K + opt->max_two_nf;
     L.taps_stride = opt->max_two_nf + 2 * fir_pad();
     L.per.assign(n_rep, {});
@@ -286,8 +299,13 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     add(cur, L.rebuild, sizeof(int32_t) * 3 * n_rep);
     add(cur, L.tiles, sizeof(FirTile) * L.tilev.size());
     add(cur, L.taps, zs * (size_t)L.taps_stride * n_rep);
-    add(cur, L.ring, zs * (size_t)L.R * cols);
-    add(cur, L.zeta, zs * (size_t)L.K * cols);
+    add(cur, L.ring, L.eq9 ? 0 : zs * (size_t)L.R * cols);
+    add(cur, L.zeta, zs * (size_t)L.zeta_rows * cols);
+    if (L.eq9) {
+        add(cur, L.eq9amp, sizeof(double) * (size_t)(opt->max_two_nf / 2 + 1) * n_rep);
+        add(cur, L.eq9tw, 2 * sizeof(double) * (size_t)(opt->max_two_nf / 2));
+        add(cur, L.eq9mark, 64);
+    }
     add(cur, L.partials, sizeof(double) * kNobs * L.max_force_blocks);
     add(cur, L.acc, sizeof(double) * kNobs * n_rep);
     add(cur, L.counts, sizeof(int32_t) * n_rep);
@@ -444,6 +462,7 @@ struct qtb_ctx {
     // the step kernels of one qtb_step call; the call ends with a force pass
     bool open = false;
     std::vector<VdosRec> vdos;  // per replica
+    std::vector<double> eq9amp;  // block noise: amplitudes [n_rep][n/2 + 1] (host copy)
     // step of the kernels being recorded: host step (rec_row < 0), or the
     // device clock (first step of the noise block) + rec_row + rec_extra
     int rec_row = -1, rec_extra = 0;
@@ -761,6 +780,21 @@ qtb_status upload_tables(qtb_ctx* c)
     return QTB_OK;
 }
 
+// Block noise (eq. 9): amplitudes of replica r's Fourier modes on the grid
+// omega_j = 2 pi j / (n dt), j = 0 .. n/2, n = max_two_nf: sqrt(n S_j / 2),
+// and sqrt(n S_j) for the self-conjugate modes j = 0 and n/2.
+qtb_status upload_eq9_amp(qtb_ctx* c, int r, int kind)
+{
+    const int n = c->L.max_two_nf, h = n / 2;
+    const qtb_replica& R = c->reps[r];
+    double* A = c->eq9amp.data() + (size_t)r * (h + 1);
+    design_spectrum(kind, R.T, R.n_beads, R.dt, n, c->opt.hbar, c->opt.kB, A);
+    for (int j = 0; j <= h; ++j) A[j] = std::sqrt((j == 0 || j == h ? 1.0 : 0.5) * n * A[j]);
+    QTB_HIP(c, hipMemcpyAsync(c->at<double>(c->L.eq9amp) + (size_t)r * (h + 1), A,
+                              8 * (size_t)(h + 1), hipMemcpyHostToDevice, c->st));
+    return QTB_OK;
+}
+
 template <typename Z>
 qtb_status upload_taps_T(qtb_ctx* c, int r)
 {
@@ -901,7 +935,7 @@ void prime_ring(qtb_ctx* c)
 {
     const int K = c->L.K, maxNf = c->L.max_two_nf / 2;
     launch_clock(c->st, c->at<int64_t>(c->L.clock), c->step - K, false);
-    gen_rows(c, K - maxNf + 1, 2 * maxNf - 1);
+    if (!c->L.eq9) gen_rows(c, K - maxNf + 1, 2 * maxNf - 1);  // block noise keeps no history
     c->ring_valid = true;
 }
 
@@ -912,7 +946,9 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
     c->rec_extra = 0;
     const Layout& L = c->L;
     const size_t zs = c->opt.fir == QTB_FIR_FP64 ? 8 : 4;
-    const char* zrow = c->at<char>(L.zeta) + (size_t)row * L.n_cols * zs;
+    // block noise: the update finds its row in the [2 n] ring from the step
+    const char* zrow = c->at<char>(L.zeta) + (L.eq9 ? 0 : (size_t)row * L.n_cols * zs);
+    const int64_t zmod = L.eq9 ? L.zeta_rows : 0;
     const RepDev* dreps = c->at<RepDev>(L.reps);
     const BlockEntry* ub = c->at<BlockEntry>(L.blk_upd);
     {
@@ -921,7 +957,7 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
             const int b0 = g.second.first, nb = g.second.second - g.second.first;
             if (nb > 0)
                 launch_update(c->st, c->fp64, c->pair, g.first, L.upd_threads, dreps, ub + b0, nb, zrow,
-                              c->at<int32_t>(L.status), step_ref(c));
+                              c->at<int32_t>(L.status), step_ref(c), zmod, L.n_cols);
         }
     }
     c->rec_extra = 1;
@@ -994,7 +1030,7 @@ void record_fused(qtb_ctx* c, int row, bool sample_prev)
             const int b0 = g.second.first, nb = g.second.second - g.second.first;
             if (nb > 0)
                 launch_update(c->st, c->fp64, true, g.first, L.upd_threads, dreps, ub + b0, nb, zrow,
-                              c->at<int32_t>(L.status), step_ref(c));
+                              c->at<int32_t>(L.status), step_ref(c), 0, L.n_cols);
         }
         c->open = true;
         c->rec_row = -1;
@@ -1047,6 +1083,14 @@ void record_block_start(qtb_ctx* c)
     const Layout& L = c->L;
     const int maxNf = L.max_two_nf / 2;
     launch_clock(c->st, c->at<int64_t>(L.clock), L.K, true);
+    if (L.eq9) {  // block noise: the paper's generator, whole blocks of n steps when due
+        Phase ph(c, 1, true);
+        launch_eq9(c->st, c->opt.fir == QTB_FIR_FP64, c->at<RepDev>(L.reps), c->at<FirTile>(L.tiles),
+                   c->at<double>(L.eq9amp), maxNf + 1, c->at<double>(L.eq9tw), L.max_two_nf,
+                   c->at<void>(L.zeta), L.n_cols, c->at<int64_t>(L.clock),
+                   c->at<int64_t>(L.eq9mark), L.K);
+        return;
+    }
     gen_rows(c, maxNf, L.K);
     Phase ph(c, 1);
     launch_fir(c->st, c->opt.fir, L.K, c->at<FirTile>(L.tiles), (int)L.tilev.size(),
@@ -1366,6 +1410,13 @@ qtb_status qtb_init(qtb_ctx** out, const qtb_potential* pot, const qtb_replica* 
                           opt->coulomb_k * q2;
         }
     }
+    if (c->L.eq9) {  // block noise: white amplitudes until a filter is built
+        c->eq9amp.assign((size_t)n_rep * (c->L.max_two_nf / 2 + 1), 0.0);
+        for (int r = 0; r < n_rep; ++r)
+            if ((s = upload_eq9_amp(c, r, QTB_NOISE_CLASSICAL))) return bail(s);
+        launch_vdos_twiddle(c->st, c->at<double>(c->L.eq9tw), c->L.max_two_nf);
+        launch_eq9_invalidate(c->st, c->at<int64_t>(c->L.eq9mark));
+    }
     if ((s = upload_tables(c))) return bail(s);
     if ((s = hip_check(c, hipMemcpyAsync(c->at<void>(c->L.blk_upd), c->L.upd.data(),
                                          sizeof(BlockEntry) * c->L.upd.size(), hipMemcpyHostToDevice, c->st), "blk")) ||
@@ -1400,6 +1451,8 @@ qtb_status qtb_build_filter(qtb_ctx* c, int32_t replica, int32_t kind, int32_t t
     if (kind < 0 || kind > 2) return fail(c, QTB_E_INVALID, "bad noise kind");
     if (two_nf < 2 || (two_nf & 1) || two_nf > c->opt.max_two_nf)
         return fail(c, QTB_E_INVALID, "two_nf must be even and in [2, max_two_nf]");
+    if (c->L.eq9 && two_nf != c->opt.max_two_nf)
+        return fail(c, QTB_E_INVALID, "block noise: two_nf must equal max_two_nf (the block length)");
     const int r0 = replica < 0 ? 0 : replica, r1 = replica < 0 ? c->n_rep : replica + 1;
     for (int r = r0; r < r1; ++r)
         if (c->reps[r].noise != kind)
@@ -1414,11 +1467,13 @@ qtb_status qtb_build_filter(qtb_ctx* c, int32_t replica, int32_t kind, int32_t t
             if (t.rep == r) t.two_nf = two_nf;
         qtb_status s = upload_taps(c, r);
         if (s) return s;
+        if (c->L.eq9 && (s = upload_eq9_amp(c, r, kind))) return s;
         c->filter_ready[r] = true;
         if (taps_out && replica >= 0) std::memcpy(taps_out, c->taps[r].data(), 8 * (size_t)two_nf);
     }
     qtb_status s = upload_tables(c);
     if (s) return s;
+    if (c->L.eq9) launch_eq9_invalidate(c->st, c->at<int64_t>(c->L.eq9mark));
     QTB_HIP(c, hipStreamSynchronize(c->st));
     // the current noise block (if any) was filtered with the old taps: restart
     c->block_start = -1;
@@ -1520,6 +1575,7 @@ qtb_status qtb_set_state(qtb_ctx* c, int32_t replica, const double* h_pos, const
         c->rd[replica].step_off = off;
         c->ring_valid = false;
         c->block_start = -1;
+        if (c->L.eq9) launch_eq9_invalidate(c->st, c->at<int64_t>(c->L.eq9mark));
         qtb_status s = upload_tables(c);
         if (s) return s;
     }
@@ -1574,9 +1630,22 @@ qtb_status qtb_get_noise(qtb_ctx* c, int32_t replica, double* h_zeta, int64_t* n
     const size_t zs = c->opt.fir == QTB_FIR_FP64 ? 8 : 4;
     const int K = c->L.K;
     std::vector<char> buf((size_t)K * D * zs);
-    QTB_HIP(c, hipMemcpy2DAsync(buf.data(), D * zs,
-                                c->at<char>(c->L.zeta) + c->L.dof_off[replica] * zs,
-                                c->L.n_cols * zs, D * zs, K, hipMemcpyDeviceToHost, c->st));
+    if (c->L.eq9) {  // rows (block_start + r) mod 2n of the block-noise ring
+        const int64_t Z = c->L.zeta_rows;
+        for (int r = 0; r < K;) {
+            int64_t m = (c->block_start + r) % Z;
+            if (m < 0) m += Z;
+            const int run = (int)std::min<int64_t>(K - r, Z - m);
+            QTB_HIP(c, hipMemcpy2DAsync(buf.data() + (size_t)r * D * zs, D * zs,
+                                        c->at<char>(c->L.zeta) + (m * c->L.n_cols + c->L.dof_off[replica]) * zs,
+                                        c->L.n_cols * zs, D * zs, run, hipMemcpyDeviceToHost, c->st));
+            r += run;
+        }
+    } else {
+        QTB_HIP(c, hipMemcpy2DAsync(buf.data(), D * zs,
+                                    c->at<char>(c->L.zeta) + c->L.dof_off[replica] * zs,
+                                    c->L.n_cols * zs, D * zs, K, hipMemcpyDeviceToHost, c->st));
+    }
     QTB_HIP(c, hipStreamSynchronize(c->st));
     for (size_t q = 0; q < (size_t)K * D; ++q)
         h_zeta[q] = zs == 8 ? ((double*)buf.data())[q] : (double)((float*)buf.data())[q];

@@ -258,6 +258,16 @@ void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, 
                       bool fp64, const int64_t* clock, int64_t off, int rows, int R,
                       int64_t n_cols);
 void launch_clock(hipStream_t st, int64_t* clock, int64_t v, bool add);
+// Block noise (eq. 9, n = 2^L2 steps per block, n >= K): makes the noise
+// blocks that the K-step noise block starting at *clock needs and has not got,
+// in the [2 n][n_cols] buffer zeta (half B mod 2 holds block B); marker [2]
+// names the block each half holds.  amp: per replica [amp_stride] amplitudes
+// A_j, j = 0 .. n/2; tw: e^{-2 pi i k / n}, k < n/2 (double2).
+void launch_eq9(hipStream_t st, bool fp64, const RepDev* reps, const FirTile* tiles,
+                const double* amp, int amp_stride, const double* tw, int n, void* zeta,
+                int64_t n_cols, const int64_t* clock, int64_t* marker, int K);
+void launch_eq9_invalidate(hipStream_t st, int64_t* marker);
+int eq9_columns(int n);
 void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
                      int64_t n_rows, uint32_t d0, uint32_t n_dof, double* out);
 // fir.hip
@@ -268,9 +278,12 @@ int fir_pad();
 size_t fir_lds_bytes(int mode, int max_two_nf);
 // update.hip
 // P: the largest bead count, threads: update_threads(largest dims P).
+// zmod > 0 (block noise): zeta_row is the base of a [zmod][n_cols] ring and
+// the step's row is (step mod zmod); zmod = 0: zeta_row is the step's row.
 void launch_update(hipStream_t st, bool fp64, bool pair, int P, int threads,
                    const RepDev* reps, const BlockEntry* blocks, int n_blocks,
-                   const void* zeta_row, int32_t* status, StepRef sync);
+                   const void* zeta_row, int32_t* status, StepRef sync, int64_t zmod,
+                   int64_t n_cols);
 int update_threads(int max_dims_beads);
 int update_block_atoms(int dims, int P, int threads);
 // nlist.hip

@@ -47,7 +47,8 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
                                                         const BlockEntry* __restrict__ blocks,
                                                         const T* __restrict__ zeta_row,
                                                         int32_t* __restrict__ status,
-                                                        const StepRef sync)
+                                                        const StepRef sync, int64_t zmod,
+                                                        int64_t n_cols)
 {
     using T4 = typename Vec4<T>::type;
     __shared__ double xr[kUpdThreads], xv[kUpdThreads];
@@ -77,7 +78,13 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
         r = R.pos[idx];
         v = R.vel[idx];
         const double f = (double)((const T*)R.force)[idx];
-        z = (double)zeta_row[R.dof_off + ((int64_t)dims * i + a) * P + s];
+        const T* zr = zeta_row;
+        if (zmod > 0) {  // block noise: the row of this step in the [zmod] ring
+            int64_t m = ((sync.clk ? *sync.clk : 0) + sync.off) % zmod;
+            if (m < 0) m += zmod;
+            zr += m * n_cols;
+        }
+        z = (double)zr[R.dof_off + ((int64_t)dims * i + a) * P + s];
         if (PAIR && a == 0) {
             for (int a2 = 0; a2 < 3; ++a2) ref3[a2] = R.rrefb[pin][(size_t)a2 * N + i];
             devb = R.devbb[pin][i];
@@ -190,16 +197,17 @@ int update_block_atoms(int dims, int P, int threads)
 
 void launch_update(hipStream_t st, bool fp64, bool pair, int P, int threads,
                    const RepDev* reps, const BlockEntry* blocks, int n_blocks,
-                   const void* zeta_row, int32_t* status, StepRef sync)
+                   const void* zeta_row, int32_t* status, StepRef sync, int64_t zmod,
+                   int64_t n_cols)
 {
     const dim3 g(n_blocks), b(threads);
     const uint32_t lds = 8u * (uint32_t)P * (uint32_t)P;  // the largest P of the launch
     if (fp64) {
-        if (pair) launch((k_update<double, true>), g, b, lds, st, reps, blocks, (const double*)zeta_row, status, sync);
-        else launch((k_update<double, false>), g, b, lds, st, reps, blocks, (const double*)zeta_row, status, sync);
+        if (pair) launch((k_update<double, true>), g, b, lds, st, reps, blocks, (const double*)zeta_row, status, sync, zmod, n_cols);
+        else launch((k_update<double, false>), g, b, lds, st, reps, blocks, (const double*)zeta_row, status, sync, zmod, n_cols);
     } else {
-        if (pair) launch((k_update<float, true>), g, b, lds, st, reps, blocks, (const float*)zeta_row, status, sync);
-        else launch((k_update<float, false>), g, b, lds, st, reps, blocks, (const float*)zeta_row, status, sync);
+        if (pair) launch((k_update<float, true>), g, b, lds, st, reps, blocks, (const float*)zeta_row, status, sync, zmod, n_cols);
+        else launch((k_update<float, false>), g, b, lds, st, reps, blocks, (const float*)zeta_row, status, sync, zmod, n_cols);
     }
 }
 

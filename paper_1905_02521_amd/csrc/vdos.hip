@@ -21,6 +21,7 @@
 // in bit-reversed order; twiddles from a table computed once.  Each block
 // keeps the sum of its groups' periodograms in its own row of partials; two
 // fixed-order passes sum the rows: the result does not depend on scheduling.
+#include "fft_lds.h"
 #include "qtb_internal.h"
 
 namespace qtb {
@@ -34,27 +35,6 @@ constexpr size_t kVdosLdsBytes = 65536;
 constexpr int kVdosBatch = 8;
 constexpr int kVdosMaxGrid = 1024;
 constexpr int kVdosStageRows = 32;
-
-__device__ __forceinline__ double2 cmul(double2 a, double2 w)
-{
-    return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
-}
-
-// Two decimation-in-frequency stages (spans 2 h2 and h2) on the four points
-// z[0], z[h2], z[2 h2], z[3 h2]: w1 = W_{4 h2}^pos, w2 = W_{2 h2}^pos.
-__device__ __forceinline__ void dif4(double2& a, double2& b, double2& c, double2& d, double2 w1,
-                                     double2 w2)
-{
-    const double2 a1 = make_double2(a.x + c.x, a.y + c.y);
-    const double2 c1 = cmul(make_double2(a.x - c.x, a.y - c.y), w1);
-    const double2 b1 = make_double2(b.x + d.x, b.y + d.y);
-    const double2 e = cmul(make_double2(b.x - d.x, b.y - d.y), w1);
-    const double2 d1 = make_double2(e.y, -e.x);  // times W_4 = -i
-    a = make_double2(a1.x + b1.x, a1.y + b1.y);
-    b = cmul(make_double2(a1.x - b1.x, a1.y - b1.y), w2);
-    c = make_double2(c1.x + d1.x, c1.y + d1.y);
-    d = cmul(make_double2(c1.x - d1.x, c1.y - d1.y), w2);
-}
 
 __global__ void __launch_bounds__(256) k_vdos_twiddle(double2* __restrict__ tw, int seg)
 {
@@ -80,7 +60,6 @@ __global__ void __launch_bounds__(256) k_vdos_fft(const double* __restrict__ v, 
     const int seg = 1 << L2, hseg = seg >> 1, ncol = 2 * cw;
     const int lc = __builtin_ctz(ncol);
     const bool time_major = ts == 1;  // each dof's samples contiguous
-    const int n_b = cw << (L2 - 2);   // radix-4 butterflies per pair of stages
     const int lb = xcd_block();
     const double2* __restrict__ twg = reinterpret_cast<const double2*>(tw_g);
     const size_t tw_off = (size_t)cw * seg;
@@ -120,58 +99,10 @@ __global__ void __launch_bounds__(256) k_vdos_fft(const double* __restrict__ v, 
             }
         }
         __syncthreads();
-        int s = L2;
-        for (; s >= 2; s -= 2) {
-            const int lh2 = s - 2, h2 = 1 << lh2;
-            // two butterflies per thread and pass: their LDS loads overlap
-            for (int b0 = threadIdx.x; b0 < n_b; b0 += 2 * blockDim.x) {
-                const int b1 = b0 + blockDim.x;
-                const bool two = b1 < n_b;
-                double2 *z0, *z1;
-                double2 w10, w20, w11, w21;
-                {
-                    const int q = b0 >> (L2 - 2), jb = b0 & ((seg >> 2) - 1), pos = jb & (h2 - 1);
-                    z0 = zb + (size_t)q * seg + ((jb >> lh2) << s) + pos;
-                    w10 = tw(pos << (L2 - s));
-                    w20 = tw(pos << (L2 - s + 1));
-                }
-                {
-                    const int bb = two ? b1 : b0;
-                    const int q = bb >> (L2 - 2), jb = bb & ((seg >> 2) - 1), pos = jb & (h2 - 1);
-                    z1 = zb + (size_t)q * seg + ((jb >> lh2) << s) + pos;
-                    w11 = tw(pos << (L2 - s));
-                    w21 = tw(pos << (L2 - s + 1));
-                }
-                double2 a0 = z0[0], p0 = z0[h2], c0v = z0[2 * h2], d0 = z0[3 * h2];
-                double2 a1 = z1[0], p1 = z1[h2], c1v = z1[2 * h2], d1 = z1[3 * h2];
-                dif4(a0, p0, c0v, d0, w10, w20);
-                dif4(a1, p1, c1v, d1, w11, w21);
-                z0[0] = a0;
-                z0[h2] = p0;
-                z0[2 * h2] = c0v;
-                z0[3 * h2] = d0;
-                if (two) {
-                    z1[0] = a1;
-                    z1[h2] = p1;
-                    z1[2 * h2] = c1v;
-                    z1[3 * h2] = d1;
-                }
-            }
-            __syncthreads();
-        }
-        if (s == 1) {  // odd number of stages: the last one has span 1
-            for (int m = threadIdx.x; m < cw * hseg; m += blockDim.x) {
-                double2* z = zb + 2 * (size_t)m;
-                const double2 a = z[0], b = z[1];
-                z[0] = make_double2(a.x + b.x, a.y + b.y);
-                z[1] = make_double2(a.x - b.x, a.y - b.y);
-            }
-            __syncthreads();
-        }
+        fft_dif_lds(zb, cw, L2, tw);
         // bin k sits at the bit reverse of k
         for (int k = threadIdx.x; k <= hseg; k += blockDim.x) {
-            const int rk = (int)(__builtin_bitreverse32((uint32_t)k) >> (32 - L2));
-            const int rm = (int)(__builtin_bitreverse32((uint32_t)((seg - k) & (seg - 1))) >> (32 - L2));
+            const int rk = bit_reverse(k, L2), rm = bit_reverse((seg - k) & (seg - 1), L2);
             double p = 0.0;
             for (int q = 0; q < cw; ++q) {
                 const double2 a = zb[(size_t)q * seg + rk], u = zb[(size_t)q * seg + rm];
