@@ -274,7 +274,7 @@ def pair_bruteforce(pot: Pot, units: Units, box, species, pos):
 
 
 OBS_NAMES = ("kinetic", "potential", "spring", "e_primitive", "e_virial",
-             "t_kinetic", "x2_mean", "step")
+             "t_kinetic", "x2_mean", "step", "pressure", "virial_pair")
 
 
 class Sim:
@@ -301,7 +301,7 @@ class Sim:
 
     def run(self, n_steps, obs_every=0):
         nmax = (n_steps // obs_every) if obs_every > 0 else 0
-        obs = np.zeros((max(nmax, 1), 8))
+        obs = np.zeros((max(nmax, 1), len(OBS_NAMES)))
         n = lib().orc_sim_run(self.h, n_steps, obs_every, _pd(obs))
         return obs[:n]
 
@@ -313,7 +313,7 @@ class Sim:
         return r, v, f, st.value
 
     def observe(self):
-        o = np.zeros(8)
+        o = np.zeros(len(OBS_NAMES))
         lib().orc_sim_observe(self.h, _pd(o))
         return o
 

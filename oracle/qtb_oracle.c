@@ -418,6 +418,7 @@ struct orc_sim {
     double *taps;
     double *r, *v, *f, *r0; /* [P][dims][N] */
     double *epot;           /* [P] physical potential energy of each bead */
+    double *wpair;          /* [P] pair virial of each bead: sum over pairs of F(r) r */
     int64_t step;
     double *C, *wk;         /* NM matrix, free-ring frequencies */
     double *wring;          /* [two_nf][D], row m lives in slot m mod two_nf */
@@ -562,12 +563,13 @@ static void compute_forces(orc_sim *s)
     double rc = s->pot.r_cut;
     double eself = self_energy(&s->pot, &s->u, N, s->species);
     double *ei = (double *)malloc(sizeof(double) * N);
+    double *wi = (double *)malloc(sizeof(double) * N);
     for (int b = 0; b < P; ++b) {
         const double *x = s->r + (size_t)b * 3 * N;
         double *fo = s->f + (size_t)b * 3 * N;
 #pragma omp parallel for schedule(dynamic, 16) num_threads(s->nthreads)
         for (int i = 0; i < N; ++i) {
-            double fx = 0, fy = 0, fz = 0, e = 0;
+            double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
             for (int q = s->nb_start[i]; q < s->nb_start[i + 1]; ++q) {
                 int j = s->nb_j[q];
                 double dx = x[i] - x[j] - s->nb_shift[3 * q + 0];
@@ -578,16 +580,20 @@ static void compute_forces(orc_sim *s)
                 double r = sqrt(r2), F;
                 double V = pair_eval(&s->pot, &s->u, s->species[i], s->species[j], r, &F);
                 e += 0.5 * V;
+                w += 0.5 * F * r; /* each pair is listed from both sides */
                 fx += F * dx / r; fy += F * dy / r; fz += F * dz / r;
             }
             fo[i] = fx; fo[N + i] = fy; fo[2 * N + i] = fz;
             ei[i] = e;
+            wi[i] = w;
         }
-        double E = 0.0;
-        for (int i = 0; i < N; ++i) E += ei[i];
+        double E = 0.0, Wp = 0.0;
+        for (int i = 0; i < N; ++i) { E += ei[i]; Wp += wi[i]; }
         s->epot[b] = E + eself;
+        s->wpair[b] = Wp;
     }
     free(ei);
+    free(wi);
 }
 
 static void fill_noise_row(orc_sim *s, int64_t m)
@@ -630,6 +636,7 @@ orc_sim *orc_sim_new(const orc_pot *pot, const orc_units *u, int N, int P, int d
     if (vel0) memcpy(s->v, vel0, sizeof(double) * nst);
     else memset(s->v, 0, sizeof(double) * nst);
     s->epot = (double *)calloc(P, sizeof(double));
+    s->wpair = (double *)calloc(P, sizeof(double));
     s->step = step0;
     s->C = (double *)malloc(sizeof(double) * P * P);
     orc_nm_matrix(P, s->C);
@@ -655,7 +662,7 @@ void orc_sim_free(orc_sim *s)
 {
     if (!s) return;
     free(s->species); free(s->homega); free(s->taps);
-    free(s->r); free(s->v); free(s->f); free(s->r0); free(s->epot);
+    free(s->r); free(s->v); free(s->f); free(s->r0); free(s->epot); free(s->wpair);
     free(s->C); free(s->wk); free(s->wring);
     free(s->rref); free(s->nb_start); free(s->nb_j); free(s->nb_shift);
     free(s);
@@ -663,7 +670,11 @@ void orc_sim_free(orc_sim *s)
 
 /* eq. (5) primitive estimator with instantaneous momenta, plus the centroid
  * virial estimator, kinetic temperature and mean square displacement from the
- * initial positions. */
+ * initial positions; for the pair potential the pressure by the primitive
+ * (thermodynamic) estimator, the volume derivative of the ring-polymer
+ * partition function with the instantaneous momenta standing in for
+ * N P dims k_B T:  p = (2 K - 2 U_spring + (1/P) sum_s W_s) / (3 V), with
+ * W_s = sum over pairs of F(r) r at bead s (P = 1: the virial pressure). */
 void orc_sim_observe(orc_sim *s, double *o)
 {
     int N = s->N, P = s->P, dims = s->dims;
@@ -699,11 +710,17 @@ void orc_sim_observe(orc_sim *s, double *o)
     o[5] = 2.0 * ke / (dims * (double)N * P * s->u.kB);
     o[6] = x2 / ((double)dims * N * P);
     o[7] = (double)s->step;
+    double W = 0.0;
+    for (int b = 0; b < P; ++b) W += s->wpair[b];
+    double V = s->box[0] * s->box[1] * s->box[2];
+    o[8] = (s->pot.kind == ORC_POT_PAIR && V > 0.0)
+               ? (2.0 * ke - 2.0 * spring + W / P) / (3.0 * V) : 0.0;
+    o[9] = W;
 }
 
 double orc_sim_hamiltonian(orc_sim *s)
 {
-    double o[8];
+    double o[ORC_NOBS];
     orc_sim_observe(s, o);
     return o[0] + o[2] + o[1];
 }
@@ -795,7 +812,7 @@ int orc_sim_run(orc_sim *s, int64_t n_steps, int obs_every, double *obs_out)
         /* slide the white-noise window: row n+1+Nf replaces row n+1-Nf */
         fill_noise_row(s, n + 1 + Nf);
         if (obs_every > 0 && (s->step % obs_every) == 0 && obs_out) {
-            orc_sim_observe(s, obs_out + 8 * nobs);
+            orc_sim_observe(s, obs_out + ORC_NOBS * nobs);
             ++nobs;
         }
     }

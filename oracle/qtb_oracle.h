@@ -96,14 +96,17 @@ orc_sim *orc_sim_new(const orc_pot *pot, const orc_units *u, int N, int P, int d
                      uint64_t seed, uint32_t stream, int noise_kind, int two_nf,
                      const double *pos0, const double *vel0, int64_t step0,
                      int n_threads);
-/* Run n steps; every obs_every steps write 8 observables to obs_out
- * (kinetic, potential, spring, e_primitive, e_virial, t_kinetic, x2_mean, step). */
+/* Observables per sample: kinetic, potential, spring, e_primitive, e_virial,
+ * t_kinetic, x2_mean, step, pressure (pair kind; 0 otherwise), pair virial
+ * sum_s W_s. */
+#define ORC_NOBS 10
+/* Run n steps; every obs_every steps write ORC_NOBS observables to obs_out. */
 int orc_sim_run(orc_sim *s, int64_t n_steps, int obs_every, double *obs_out);
 void orc_sim_get(const orc_sim *s, double *pos, double *vel, double *force, int64_t *step);
 const double *orc_sim_taps(const orc_sim *s, int *two_nf);
 void orc_sim_free(orc_sim *s);
-/* Observables of the current state (same 8 numbers as above). */
-void orc_sim_observe(orc_sim *s, double *obs8);
+/* Observables of the current state (the same ORC_NOBS numbers). */
+void orc_sim_observe(orc_sim *s, double *obs);
 /* Hamiltonian of the ring polymer, sum p^2/2m + sum_s [V_s/P + springs]. */
 double orc_sim_hamiltonian(orc_sim *s);
 
