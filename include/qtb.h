@@ -189,6 +189,11 @@ typedef struct {
     double e_virial;           /* centroid virial estimator (dims N k_B T / 2 + ...) */
     double t_kinetic;          /* 2 kinetic / (dims N P k_B)                      */
     double x2_mean;            /* mean of (r - r(init))^2 over beads, dims, atoms */
+    double virial_pair;        /* sum_s W_s, W_s = sum over pairs of F(r) r at bead s */
+    double pressure;           /* (2 kinetic - 2 spring + virial_pair / P) / (3 V):   */
+                               /* the volume derivative of the (ring-polymer)        */
+                               /* partition function, instantaneous momenta (pair    */
+                               /* potential only; 0 for other kinds and surrogates)  */
     int32_t n_samples;
 } qtb_obs;
 

@@ -109,13 +109,14 @@ struct PairPos {
 // NS: species count rounded up to 2 or 4 (parameters of the centre atom's
 // row are kept in registers and picked per neighbour with selects).
 // FAST (FP32 only): hardware rsq / exp2 and the fitted erfcx polynomial.
-// Force (FP64 sums) and, if want_e, energy of bead s of atom i over the list
-// entries ch, ch + ST, ...; spi receives the atom's species.
+// Force (FP64 sums) and, if want_e, energy and pair virial sum F(r) r of bead
+// s of atom i over the list entries ch, ch + ST, ...; spi receives the atom's
+// species.
 template <typename T, int NS, bool FAST, int DEG, int MODE>
 __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& tab,
                                          const PairPos<T, MODE>& pp, int i, int s, int ch,
                                          int ST, bool want_e, double& fx, double& fy, double& fz,
-                                         double& e, int& spi)
+                                         double& e, double& w, int& spi)
 {
     using V4 = typename NV<T>::v4;
     const V4 ui = pp.at(i, s);
@@ -209,6 +210,7 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                     E0c = m ? pE0[b] : E0c;
                 }
                 e += (double)(A * e1 - C * rinv6 + kqq * ec * rinv - F0 * r + E0c);
+                w += (double)(F * r);
             }
         }
         E0 = E1;
@@ -223,15 +225,18 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
 // lanes < G of the atom's first wavefront.
 template <int G>
 __device__ __forceinline__ void reduce_atom(double& fx, double& fy, double& fz, double& e,
-                                            bool want_e, int W, int wave, int wsub, int lane,
-                                            double (*part)[G][4])
+                                            double& vir, bool want_e, int W, int wave, int wsub,
+                                            int lane, double (*part)[G][5])
 {
 #pragma unroll
     for (int off = G; off < 64; off <<= 1) {
         fx += __shfl_xor(fx, off);
         fy += __shfl_xor(fy, off);
         fz += __shfl_xor(fz, off);
-        if (want_e) e += __shfl_xor(e, off);
+        if (want_e) {
+            e += __shfl_xor(e, off);
+            vir += __shfl_xor(vir, off);
+        }
     }
     if (W > 1) {
         if (lane < G) {
@@ -239,6 +244,7 @@ __device__ __forceinline__ void reduce_atom(double& fx, double& fy, double& fz, 
             part[wave][lane][1] = fy;
             part[wave][lane][2] = fz;
             part[wave][lane][3] = e;
+            part[wave][lane][4] = vir;
         }
         __syncthreads();
         if (wsub == 0 && lane < G) {
@@ -247,6 +253,7 @@ __device__ __forceinline__ void reduce_atom(double& fx, double& fy, double& fz, 
                 fy += part[wave + w][lane][1];
                 fz += part[wave + w][lane][2];
                 e += part[wave + w][lane][3];
+                vir += part[wave + w][lane][4];
             }
         }
     }
@@ -365,8 +372,13 @@ __device__ void rebuild_list(const RepDev& R, int i, bool active, const double* 
     __syncthreads();
 }
 
-template <typename T, int G, int NS, bool FAST, int DEG>
-__global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ reps,
+// Occupancy targets (measured on the 4096-atom x P = 8 workload): the plain
+// FP32 force pass at eight wavefronts per SIMD (64 registers, a few spilled)
+// ran 27.9 us against 28.6 at five; the sampling pass keeps five without
+// spills; FP64 is left to the compiler.
+template <typename T, int G, int NS, bool FAST, int DEG, bool WE>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (WE ? 5 : 8)))) k_force_pair(const RepDev* __restrict__ reps,
                                                     const BlockEntry* __restrict__ blocks,
                                                     const PairTable<T> tab, int32_t flags,
                                                     double* __restrict__ partials, int clear,
@@ -377,7 +389,7 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
     using T4 = typename Vec4<T>::type;
     constexpr int NCH = 64 / G;   // neighbour chunks per wavefront
     // W wavefronts per atom (1, 2 or 4), 4 / W atoms per block
-    __shared__ double part[4][G][4];
+    __shared__ double part[4][G][5];
     __shared__ double red[4][kNobs];
     __shared__ double tx[256], ty[256], tz[256], td[256];
     __shared__ double dmax_s[4];
@@ -392,7 +404,10 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
     const int N = R.N, P = R.P;
     const bool active = i < N;
     const int s = be.group * G + bl;
-    const bool want_e = (flags & (kSample | kEvaluate)) != 0;
+    // energies and the pair virial only in the instantiation that samples or
+    // evaluates (WE = flags & (kSample | kEvaluate)): the plain force pass
+    // keeps fewer registers live
+    constexpr bool want_e = WE;
     double* const vrec = recorder_row(R, flags);
     const StepIdx si = step_index(sync);
     // clear == 1: the list kernel ran before; this step's and the previous
@@ -430,27 +445,28 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
             }
         }
     }
-    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, vir = 0.0;
     int spi = 0;
     if (active) {
         if (rebuild) {
             const PairPos<T, kPosRef> pp{nullptr, nullptr, (gptr<double>)cen, N, P,
                                          (gptr<double>)R.pos, (gptr<int32_t>)R.species};
             pair_sum<T, NS, FAST, DEG, kPosRef>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy, fz,
-                                                e, spi);
+                                                e, vir, spi);
         } else {
             // u is atom-major [N][P]: the G beads of a neighbour share cache lines
             const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[si.p] + 0, nullptr, nullptr, N, P,
                                             nullptr, nullptr};
             pair_sum<T, NS, FAST, DEG, kPosDirect>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
-                                                   fz, e, spi);
+                                                   fz, e, vir, spi);
         }
     }
-    reduce_atom<G>(fx, fy, fz, e, want_e, W, wave, wsub, lane, part);
+    reduce_atom<G>(fx, fy, fz, e, vir, want_e, W, wave, wsub, lane, part);
     double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (active && wsub == 0 && lane < G && s < P) {
         const double f[3] = {fx, fy, fz};
         force_epilogue<T>(R, i, s, spi, f, 0.5 * e, flags, ob, vrec);
+        if (flags & kSample) ob[5] = 0.5 * vir;  // each pair is listed from both sides
     }
     if (flags & (kSample | kCompare)) block_partials(ob, wave, lane, lb, red, partials);
 }
@@ -464,7 +480,7 @@ __global__ void __launch_bounds__(256) k_force_pair(const RepDev* __restrict__ r
 // writes its atom's data for step n + 1 into parity (n + 1) & 1 and updates
 // its positions and velocities in place.  Bit for bit the same arithmetic
 // as the separate update and force kernels.
-template <typename T, int G, int NS, bool FAST, int DEG>
+template <typename T, int G, int NS, bool FAST, int DEG, bool WE>
 __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ reps,
                                                    const BlockEntry* __restrict__ blocks,
                                                    const PairTable<T> tab, int32_t flags,
@@ -476,7 +492,7 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
     using V4 = typename NV<T>::v4;
     using T4 = typename Vec4<T>::type;
     constexpr int NCH = 64 / G;
-    __shared__ double part[4][G][4];
+    __shared__ double part[4][G][5];
     __shared__ double red[4][kNobs];
     __shared__ double tx[256], ty[256], tz[256], td[256];
     __shared__ double dmax_s[4];
@@ -503,7 +519,7 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
     const int N = R.N, P = R.P;
     const bool active = i < N;
     const int s = bl;  // G = P: the wavefront holds every bead
-    const bool want_e = (flags & kSample) != 0;
+    constexpr bool want_e = WE;  // = flags & kSample (the launcher's choice)
     double* const vrec = recorder_row(R, flags);
     {
         const int apb = 4 / W;
@@ -527,22 +543,22 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
     if (rebuild)
         rebuild_list<T>(R, i, active && wsub == 0, cin, cin + N, cin + 2 * (size_t)N, R.devn[pin],
                         status, tx, ty, tz, td, dmax_s);
-    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, vir = 0.0;
     int spi = 0;
     if (active) {
         if (rebuild) {
             const PairPos<T, kPosRecon> pp{(gptr<V4>)R.ub[pin] + 0, (gptr<double>)rin,
                                            (gptr<double>)cin, N, P, nullptr, nullptr};
             pair_sum<T, NS, FAST, DEG, kPosRecon>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
-                                                  fz, e, spi);
+                                                  fz, e, vir, spi);
         } else {
             const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[pin] + 0, nullptr, nullptr, N, P,
                                             nullptr, nullptr};
             pair_sum<T, NS, FAST, DEG, kPosDirect>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
-                                                   fz, e, spi);
+                                                   fz, e, vir, spi);
         }
     }
-    reduce_atom<G>(fx, fy, fz, e, want_e, W, wave, wsub, lane, part);
+    reduce_atom<G>(fx, fy, fz, e, vir, want_e, W, wave, wsub, lane, part);
     double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int my_flags = 0;
     // the atom's wavefront, lanes 0 .. P-1 = beads: wavefront-uniform branch.
@@ -561,6 +577,7 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
             const double f[3] = {fx, fy, fz};
             force_epilogue_src<T, false>(R, i, s, spi, f, 0.5 * e, kKick | (flags & kSample), ob,
                                          src, vc, vrec);
+            if (flags & kSample) ob[5] = 0.5 * vir;
 #pragma unroll
             for (int a = 0; a < 3; ++a) fT[a] = (double)(T)f[a];  // the stored force
         }
@@ -796,19 +813,31 @@ __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v)
         p[id] = v;
 }
 
+template <typename T, int NS, bool FAST, int DEG, bool WE>
+void launch_pair_GW(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
+                    int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
+                    int clear, int n_rep, int32_t* status, StepRef sync, int W)
+{
+    const dim3 g(n_blocks), b(256);
+    switch (G) {
+    case 1: launch((k_force_pair<T, 1, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    case 2: launch((k_force_pair<T, 2, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    case 4: launch((k_force_pair<T, 4, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    case 8: launch((k_force_pair<T, 8, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    default: break;
+    }
+}
 template <typename T, int NS, bool FAST, int DEG>
 void launch_pair_G(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
                    int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
                    int clear, int n_rep, int32_t* status, StepRef sync, int W)
 {
-    const dim3 g(n_blocks), b(256);
-    switch (G) {
-    case 1: launch((k_force_pair<T, 1, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
-    case 2: launch((k_force_pair<T, 2, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
-    case 4: launch((k_force_pair<T, 4, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
-    case 8: launch((k_force_pair<T, 8, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
-    default: break;
-    }
+    if (flags & (kSample | kEvaluate))
+        launch_pair_GW<T, NS, FAST, DEG, true>(st, G, reps, blocks, n_blocks, tab, flags, partials,
+                                               clear, n_rep, status, sync, W);
+    else
+        launch_pair_GW<T, NS, FAST, DEG, false>(st, G, reps, blocks, n_blocks, tab, flags, partials,
+                                                clear, n_rep, status, sync, W);
 }
 
 template <typename T, bool FAST, int DEG>
@@ -847,19 +876,31 @@ void launch_forces_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* r
     }
 }
 
+template <typename T, int NS, bool FAST, int DEG, bool WE>
+void launch_step_GW(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
+                    int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
+                    int n_rep, int32_t* status, StepRef sync, int W, const T* zrow)
+{
+    const dim3 g(n_blocks), b(256);
+    switch (G) {
+    case 1: launch((k_step_pair<T, 1, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
+    case 2: launch((k_step_pair<T, 2, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
+    case 4: launch((k_step_pair<T, 4, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
+    case 8: launch((k_step_pair<T, 8, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
+    default: break;
+    }
+}
 template <typename T, int NS, bool FAST, int DEG>
 void launch_step_G(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
                    int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
                    int n_rep, int32_t* status, StepRef sync, int W, const T* zrow)
 {
-    const dim3 g(n_blocks), b(256);
-    switch (G) {
-    case 1: launch((k_step_pair<T, 1, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
-    case 2: launch((k_step_pair<T, 2, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
-    case 4: launch((k_step_pair<T, 4, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
-    case 8: launch((k_step_pair<T, 8, NS, FAST, DEG>), g, b, 0, st, reps, blocks, tab, flags, partials, n_rep, status, sync, W, zrow); break;
-    default: break;
-    }
+    if (flags & kSample)
+        launch_step_GW<T, NS, FAST, DEG, true>(st, G, reps, blocks, n_blocks, tab, flags, partials,
+                                               n_rep, status, sync, W, zrow);
+    else
+        launch_step_GW<T, NS, FAST, DEG, false>(st, G, reps, blocks, n_blocks, tab, flags, partials,
+                                                n_rep, status, sync, W, zrow);
 }
 
 template <typename T, bool FAST, int DEG>

@@ -1539,6 +1539,11 @@ qtb_status qtb_observables(qtb_ctx* c, int32_t replica, qtb_obs* out)
         out->e_virial = 0.5 * dof * kT - vir / (2.0 * R.n_beads) + U;
         out->t_kinetic = 2.0 * ke / (dof * R.n_beads * c->opt.kB);
         out->x2_mean = x2 / (dof * R.n_beads);
+        if (c->pair && !c->ml) {
+            const double wp = acc[5] * inv, V = R.box[0] * R.box[1] * R.box[2];
+            out->virial_pair = wp;
+            out->pressure = (2.0 * ke - 2.0 * spr + wp / R.n_beads) / (3.0 * V);
+        }
     }
     return s;
 }

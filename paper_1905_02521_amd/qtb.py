@@ -78,6 +78,7 @@ class qtb_obs(ctypes.Structure):
                 ("potential", ctypes.c_double), ("spring", ctypes.c_double),
                 ("e_primitive", ctypes.c_double), ("e_virial", ctypes.c_double),
                 ("t_kinetic", ctypes.c_double), ("x2_mean", ctypes.c_double),
+                ("virial_pair", ctypes.c_double), ("pressure", ctypes.c_double),
                 ("n_samples", ctypes.c_int32)]
 
     def as_dict(self):

@@ -1,0 +1,130 @@
+"""Lattice parameter against temperature and its isotope shift (the QTB-MD
+application of Sec. 2.2, Fig. 6: the lattice parameters of 7LiH and 7LiD),
+measured on the MgO model crystal from the pressure of constant-volume runs.
+
+For each temperature, noise and isotope the batched context runs the 4x4x4
+crystal (512 atoms) at seven lattice parameters (16 blocks of 5000 steps);
+the zero of the mean pressure p(a) (primitive virial estimator, instantaneous
+momenta; a quadratic through the three points around the sign change) is the
+equilibrium lattice parameter.  Classical Langevin dynamics gives no isotope
+effect and a lattice parameter growing from the static one; QTB gives
+a zero-point expansion at low temperature and a lighter-isotope crystal with
+the larger lattice parameter, the difference fading as T rises.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1905_02521_amd import qtb, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TEMPS = (50.0, 150.0, 300.0, 600.0)
+LATTICE = np.round(np.linspace(4.22, 4.28, 7), 4)
+ISOTOPES = {"24Mg16O": (23.985, 15.995), "26Mg18O": (25.983, 17.999)}
+GAMMA, DT, TWO_NF, EVERY, N_EQ, BLOCK, N_BLOCKS = 1e-3, 1.0, 512, 8, 6000, 5000, 16
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qtb.lib()
+
+
+def pressure_blocks(masses, seed=3):
+    """Block means of the pressure (eV / A^3) for every (noise, T, a)."""
+    p = W.mgo_potential(skin=1.0)
+    potd = qtb.pair_potential_dict(p)
+    potd["mass"] = masses
+    keys, reps = [], []
+    for noise in (0, 1):
+        for T in TEMPS:
+            for k, a in enumerate(LATTICE):
+                pos, sp, box = W.rocksalt(4, float(a))
+                beads = W.beads_from(W.displaced(pos, 0.01 * a, seed + k), 1)
+                reps.append(qtb.Replica(pos=beads, species=sp, T=T, gamma=GAMMA, dt=DT,
+                                        noise=noise, box=tuple(box), seed=seed,
+                                        stream=len(reps)))
+                keys.append((noise, T, float(a)))
+    ctx = qtb.Context(potd, reps, dict(W.METAL_UNITS), prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3,
+                      obs_every=EVERY, max_two_nf=TWO_NF)
+    for r, (noise, _, _) in enumerate(keys):
+        if noise:
+            ctx.build_filter(r, noise, TWO_NF)
+    ctx.step(N_EQ)
+    for r in range(len(keys)):
+        ctx.observables(r)
+    out = {k: [] for k in keys}
+    for _ in range(N_BLOCKS):
+        ctx.step(BLOCK)
+        for r, k in enumerate(keys):
+            out[k].append(ctx.observables(r)["pressure"])
+    ctx.close()
+    return out
+
+
+def equilibrium_lattice(blocks, noise, T):
+    """Zero of the quadratic through <p> at the three lattice parameters
+    around the sign change (p(a) is far from quadratic over the whole scan,
+    and a fit of all points would trade its misfit against the block errors);
+    the standard error by propagating the three block standard errors."""
+    a = LATTICE
+    m = np.array([np.mean(blocks[(noise, T, float(x))]) for x in a])
+    se = np.array([np.std(blocks[(noise, T, float(x))], ddof=1) / math.sqrt(N_BLOCKS) for x in a])
+    k = int(np.argmin(np.abs(m)))
+    k = min(max(k, 1), len(a) - 2)
+    sl = slice(k - 1, k + 2)
+
+    def root(pv):
+        c = np.polyfit(a[sl] - a[k], pv, 2)
+        r = np.roots(c)
+        r = r[np.isreal(r)].real
+        return a[k] + r[np.argmin(np.abs(r))]
+
+    r0 = root(m[sl])
+    grad = []
+    for j in range(3):
+        d = np.zeros(3)
+        d[j] = 1e-6
+        grad.append((root(m[sl] + d) - r0) / 1e-6)
+    return float(r0), float(math.sqrt(np.sum((np.array(grad) * se[sl]) ** 2)))
+
+
+def test_lattice_parameter_and_isotope_shift():
+    res = {}
+    for name, masses in ISOTOPES.items():
+        blocks = pressure_blocks(masses)
+        for noise in (0, 1):
+            for T in TEMPS:
+                res[(name, noise, T)] = equilibrium_lattice(blocks, noise, T)
+    light, heavy = ISOTOPES
+    print("T (K) | classical 24Mg16O, 26Mg18O | QTB 24Mg16O, 26Mg18O | QTB isotope shift (mA)")
+    for T in TEMPS:
+        cl = [res[(n, 0, T)] for n in (light, heavy)]
+        qt = [res[(n, 1, T)] for n in (light, heavy)]
+        sh = (qt[0][0] - qt[1][0]) * 1e3, math.hypot(qt[0][1], qt[1][1]) * 1e3
+        print(f"{T:5.0f} | {cl[0][0]:.5f}+-{cl[0][1]:.5f} {cl[1][0]:.5f}+-{cl[1][1]:.5f} | "
+              f"{qt[0][0]:.5f}+-{qt[0][1]:.5f} {qt[1][0]:.5f}+-{qt[1][1]:.5f} | "
+              f"{sh[0]:+.3f}+-{sh[1]:.3f}")
+    def shift(noise, T):
+        (a1, s1), (a2, s2) = res[(light, noise, T)], res[(heavy, noise, T)]
+        return a1 - a2, math.hypot(s1, s2)
+    for T in TEMPS:   # classical configurations do not depend on the masses
+        d, s = shift(0, T)
+        assert abs(d) < 4 * s + 5e-5, (T, d, s)
+    d50, s50 = shift(1, 50.0)
+    d600, s600 = shift(1, 600.0)
+    assert d50 > 4 * s50                      # the lighter crystal is larger
+    assert d600 < d50 - 2 * math.hypot(s50, s600)   # and the shift fades with T
+    # zero-point expansion: at 50 K QTB sits well above the classical value,
+    # and QTB's lattice parameter grows less from 50 to 150 K than classically
+    (aq50, sq50), (ac50, sc50) = res[(light, 1, 50.0)], res[(light, 0, 50.0)]
+    assert aq50 - ac50 > 10 * math.hypot(sq50, sc50)
+    dq = res[(light, 1, 150.0)][0] - aq50
+    dc = res[(light, 0, 150.0)][0] - ac50
+    assert dq < dc
+    # classical thermal expansion from the static lattice parameter
+    assert res[(light, 0, 600.0)][0] > res[(light, 0, 50.0)][0]

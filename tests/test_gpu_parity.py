@@ -190,8 +190,9 @@ def test_observables_match_oracle(orc, P, noise):
     g = ctx.observables(0)
     assert g["n_samples"] == 8
     o = obs.mean(axis=0)
-    names = ["kinetic", "potential", "spring", "e_primitive", "e_virial", "t_kinetic", "x2_mean"]
-    for q, nm in enumerate(names):
+    for nm in ("kinetic", "potential", "spring", "e_primitive", "e_virial", "t_kinetic",
+               "x2_mean", "virial_pair", "pressure"):
+        q = orc.OBS_NAMES.index(nm)
         assert abs(g[nm] - o[q]) <= 1e-9 * max(1.0, abs(o[q])), (nm, g[nm], o[q])
 
 
