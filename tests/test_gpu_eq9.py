@@ -125,3 +125,39 @@ def test_block_noise_oscillator_energy_matches_exact():
           f"exact (FIR, same grid) {E_fir:.5f}, theta {th:.5f}")
     assert abs(m - E_blocks) < 2.5 * se
     assert abs(E_blocks - E_fir) > 4 * se    # the two generators are told apart
+
+
+def test_block_noise_batched_replicas(orc):
+    """Three replicas in one context (QTB P = 1, QTB-PIMD P = 4, classical
+    P = 2; different T, dt, seeds, streams and dof counts, so their columns
+    share 256-column tiles' boundaries differently): each replica's noise is
+    its own oracle eq. 9 block."""
+    n, K = 256, 64
+    specs = [(1, 1, 0.3, 0.25, 11, 37), (4, 2, 0.5, 0.1, 12, 21), (2, 0, 0.8, 0.2, 13, 50)]
+    reps = []
+    for P, noise, T, dt, seed, N in specs:
+        om = np.linspace(0.5, 2.5, N)
+        reps.append(qtb.Replica(pos=np.full((P, 1, N), 0.1), species=np.zeros(N, np.int32), T=T,
+                                gamma=0.2, dt=dt, noise=noise, seed=seed, stream=seed % 5,
+                                harm_omega=om))
+    ctx = qtb.Context(dict(kind=qtb.POT_HARMONIC, mass=(1.0,)), reps, units_dict(True),
+                      prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, fir_block_K=K, max_two_nf=n,
+                      noise_blocks=True)
+    for r, (P, noise, *_rest) in enumerate(specs):
+        if noise:
+            ctx.build_filter(r, noise, n)
+    got = [[] for _ in specs]
+    for _ in range(n // K + 2):   # into the second block
+        ctx.step(K)
+        for r in range(len(specs)):
+            got[r].append(ctx.get_noise(r)[0])
+    ctx.close()
+    U = orc.make_units(1.0, 1.0)
+    for r, (P, noise, T, dt, seed, N) in enumerate(specs):
+        z = np.concatenate(got[r])
+        S = orc.noise_spectrum(noise, T, P, dt, n, U)
+        ref = np.concatenate([orc.eq9_block(S, seed, seed % 5, B * n, N * P) for B in range(2)])
+        ref = ref[: len(z)]
+        err = np.max(np.abs(z - ref)) / np.std(ref)
+        print(f"replica {r} (P={P}, noise={noise}): {err:.2e}")
+        assert err <= 1e-12

@@ -20,7 +20,7 @@ import pytest
 
 from paper_1905_02521_amd import qtb, workloads as W
 from tests.closed_forms import baoab_mode_map
-from tests.gpu_common import (crystal, gpu_crystal_ctx, gpu_ho_ctx, oracle_pair_pot,
+from tests.gpu_common import (crystal, gpu_crystal_ctx, gpu_ho_ctx, oracle_pair_pot, units_dict,
                               oracle_units)
 from tests.test_oracle_vdos import expected_periodogram
 
@@ -287,3 +287,42 @@ def test_high_friction_dos_tail_broadening_and_zpel():
     assert abs(whole - 1) < 0.02           # in-band total: the harmonic energy theta(omega)
     assert share[0.001][0] > 1.15 and share[0.001][-1] < 0.85
     assert abs(share[0.05][0] - 1) < 0.06 and abs(share[0.05][-1] - 1) < 0.03
+
+
+def test_recorders_on_batched_replicas(orc):
+    """Two recorded replicas and one unrecorded in one context (oscillators of
+    different counts, seeds and segment lengths): each spectrum is the
+    oracle's for that replica's own trajectory."""
+    every, T, gamma, dt, two_nf = 1, 0.25, 0.2, 0.1, 256
+    specs = [(33, 7, 64), (50, 8, None), (17, 9, 128)]   # (N, seed, seg or no recorder)
+    reps, oms = [], []
+    for N, seed, _ in specs:
+        om = 1.0 + 0.3 * np.arange(N) / N
+        oms.append(om)
+        reps.append(qtb.Replica(pos=np.full((1, 1, N), 0.3), species=np.zeros(N, np.int32), T=T,
+                                gamma=gamma, dt=dt, noise=1, seed=seed, stream=0, harm_omega=om))
+    ctx = qtb.Context(dict(kind=qtb.POT_HARMONIC, mass=(1.0,)), reps, units_dict(True),
+                      prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, obs_every=every, max_two_nf=two_nf)
+    for r in range(len(specs)):
+        ctx.build_filter(r, 1, two_nf)
+    for r, (_, _, seg) in enumerate(specs):
+        if seg:
+            ctx.vdos_attach(r, seg)
+    ctx.step(300)
+    for r, (N, seed, seg) in enumerate(specs):
+        if not seg:
+            continue
+        S, n_seg = ctx.vdos_read(r)
+        assert n_seg == 300 // seg
+        osim = orc.Sim(orc.make_pot(1, (1.0,)), oracle_units(orc, True), N, 1, 1, None,
+                       np.zeros(N, np.int32), T, gamma, dt, seed, 0, 1, two_nf,
+                       np.full((1, 1, N), 0.3), harm_omega=oms[r], n_threads=4)
+        v = np.empty((n_seg * seg, N))
+        for t in range(n_seg * seg):
+            osim.run(every)
+            v[t] = osim.state()[1][0, 0]
+        So = orc.vdos(v, seg)[1]
+        err = np.max(np.abs(S - So)) / np.max(So)
+        print(f"replica {r}: {err:.2e}")
+        assert err <= 1e-8
+    ctx.close()
