@@ -108,6 +108,9 @@ def lib():
         L.orc_sim_taps.restype = _PD
         L.orc_sim_taps.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
         L.orc_nm_matrix.argtypes = [ctypes.c_int, _PD]
+        L.orc_sim_set_barostat.restype = ctypes.c_int
+        L.orc_sim_set_barostat.argtypes = [ctypes.c_void_p, _D, _D, _D]
+        L.orc_sim_box.argtypes = [ctypes.c_void_p, _PD]
     return _lib
 
 
@@ -316,6 +319,15 @@ class Sim:
         o = np.zeros(len(OBS_NAMES))
         lib().orc_sim_observe(self.h, _pd(o))
         return o
+
+    def set_barostat(self, P0, tau_p, beta_T):
+        if lib().orc_sim_set_barostat(self.h, float(P0), float(tau_p), float(beta_T)):
+            raise ValueError("oracle refused the barostat (P = 1 and the pair kind only)")
+
+    def box(self):
+        b = np.zeros(3)
+        lib().orc_sim_box(self.h, _pd(b))
+        return b
 
     def hamiltonian(self):
         return lib().orc_sim_hamiltonian(self.h)

@@ -428,6 +428,9 @@ struct orc_sim {
     int *nb_start, *nb_j, nb_cap;
     double *nb_shift;       /* [3 * entries] */
     int nthreads;
+    /* stochastic cell rescaling (isotropic barostat, P = 1, pair kind) */
+    int npt, nb_force;
+    double npt_P0, npt_tau, npt_beta;
 };
 
 static int64_t pmod(int64_t a, int64_t m) { int64_t r = a % m; return r < 0 ? r + m : r; }
@@ -440,6 +443,7 @@ static int64_t pmod(int64_t a, int64_t m) { int64_t r = a % m; return r < 0 ? r 
  */
 static void nlist_build(orc_sim *s)
 {
+    s->nb_force = 0;
     int N = s->N, P = s->P;
     for (int d = 0; d < 3; ++d)
         for (int i = 0; i < N; ++i) {
@@ -499,6 +503,7 @@ static void nlist_build(orc_sim *s)
 static int nlist_stale(const orc_sim *s)
 {
     int N = s->N;
+    if (s->nb_force) return 1; /* the box changed */
     double lim = 0.5 * s->pot.skin + s->nb_dev;
     for (int b = 0; b < s->P; ++b)
         for (int i = 0; i < N; ++i) {
@@ -726,6 +731,59 @@ double orc_sim_hamiltonian(orc_sim *s)
 }
 
 /*
+ * Isotropic stochastic cell rescaling (after Bernetti and Bussi, J. Chem.
+ * Phys. 153, 114107 (2020)): one Euler-Maruyama (Ito) step of eps = ln V
+ * after the step of step index n,
+ *   d eps = -(beta_T / tau_p) (P0 - p) dt + sqrt(2 k_B T beta_T dt / (V tau_p)) g,
+ * p the instantaneous virial pressure (2K + W) / (3V) of the closed step,
+ * g the unit Gaussian at (step n, dof 0, tag 4); positions and box scale by
+ * s = e^{d eps / 3}, velocities by 1 / s, and the neighbour list is rebuilt.
+ * With the diffusion in eps proportional to 1 / V, the Ito drift needs no
+ * separate k_B T / V term: the stationary law is V^N e^{-P0 V / k_B T} for
+ * an ideal gas (pinned).  (The paper cites a Langevin barostat for its
+ * constant-pressure runs without giving one; this is the reading used.)
+ */
+static void barostat_step(orc_sim *s, int64_t n)
+{
+    int N = s->N;
+    double mu = s->u.mass_unit, kT = s->u.kB * s->T;
+    double ke = 0.0;
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < N; ++i) {
+            double m = s->pot.mass[s->species[i]] * mu;
+            double v = s->v[(size_t)d * N + i];
+            ke += 0.5 * m * v * v;
+        }
+    double V = s->box[0] * s->box[1] * s->box[2];
+    double p = (2.0 * ke + s->wpair[0]) / (3.0 * V);
+    double g = orc_gauss(s->seed, n, 0, s->stream, 4);
+    double deps = -(s->npt_beta / s->npt_tau) * (s->npt_P0 - p) * s->dt +
+                  sqrt(2.0 * kT * s->npt_beta * s->dt / (V * s->npt_tau)) * g;
+    double sc = exp(deps / 3.0);
+    for (int d = 0; d < 3; ++d) s->box[d] *= sc;
+    for (size_t q = 0; q < (size_t)3 * N; ++q) {
+        s->r[q] *= sc;
+        s->v[q] /= sc;
+    }
+    s->nb_force = 1;
+}
+
+int orc_sim_set_barostat(orc_sim *s, double P0, double tau_p, double beta_T)
+{
+    if (s->P != 1 || s->pot.kind != ORC_POT_PAIR || !(tau_p > 0.0) || !(beta_T > 0.0)) return 1;
+    s->npt = 1;
+    s->npt_P0 = P0;
+    s->npt_tau = tau_p;
+    s->npt_beta = beta_T;
+    return 0;
+}
+
+void orc_sim_box(const orc_sim *s, double *box)
+{
+    for (int d = 0; d < 3; ++d) box[d] = s->box[d];
+}
+
+/*
  * One step = B(dt/2) -> normal modes -> A(dt/2) -> O(dt) -> A(dt/2) ->
  * back to beads -> forces -> B(dt/2).  B uses the bead force -(1/P) grad V
  * of eq. (4) with bead mass m; A integrates the ring springs of eq. (3)-(4)
@@ -815,6 +873,7 @@ int orc_sim_run(orc_sim *s, int64_t n_steps, int obs_every, double *obs_out)
             orc_sim_observe(s, obs_out + ORC_NOBS * nobs);
             ++nobs;
         }
+        if (s->npt) barostat_step(s, n);
     }
     return nobs;
 }

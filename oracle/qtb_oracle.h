@@ -107,6 +107,12 @@ const double *orc_sim_taps(const orc_sim *s, int *two_nf);
 void orc_sim_free(orc_sim *s);
 /* Observables of the current state (the same ORC_NOBS numbers). */
 void orc_sim_observe(orc_sim *s, double *obs);
+/* Isotropic stochastic cell rescaling after every step (P = 1, pair kind):
+ * target pressure P0, relaxation time tau_p, compressibility beta_T (the
+ * caller's units).  Returns nonzero if refused. */
+int orc_sim_set_barostat(orc_sim *s, double P0, double tau_p, double beta_T);
+/* Current box lengths. */
+void orc_sim_box(const orc_sim *s, double *box);
 /* Hamiltonian of the ring polymer, sum p^2/2m + sum_s [V_s/P + springs]. */
 double orc_sim_hamiltonian(orc_sim *s);
 
