@@ -1,9 +1,7 @@
 """Pin of the oracle's isotropic stochastic cell rescaling (the barostat of
 the constant-pressure runs behind Fig. 6): for an ideal gas the isothermal-
 isobaric ensemble has p(V) ~ V^N exp(-P0 V / k_B T), so <V> = (N + 1) k_B T / P0
-and Var V / <V>^2 = 1 / (N + 1).  (An extra k_B T / V in the drift, as in the
-Stratonovich-style form, gives V^(N+1): <V> 1.6 % high here, which this
-test resolves.)"""
+and Var V / <V>^2 = 1 / (N + 1)."""
 import math
 
 import numpy as np
