@@ -194,6 +194,8 @@ typedef struct {
                                /* the volume derivative of the (ring-polymer)        */
                                /* partition function, instantaneous momenta (pair    */
                                /* potential only; 0 for other kinds and surrogates)  */
+                               /* averaged over the samples, each at its own volume  */
+    double volume;             /* mean box volume of the samples (pair potential)    */
     int32_t n_samples;
 } qtb_obs;
 
@@ -325,6 +327,35 @@ qtb_status qtb_vdos_read(qtb_ctx *ctx, int32_t replica, double *h_spec, int64_t 
 
 /* Stop recording (synchronises; the workspace is the caller's again). */
 qtb_status qtb_vdos_detach(qtb_ctx *ctx, int32_t replica);
+
+/*
+ * Constant pressure.  Sec. 2.1 extends the equations of motion to the
+ * isothermal-isobaric ensemble with a Langevin barostat, and Sec. 2.2 (Fig. 6)
+ * applies QTB-MD at constant pressure to the lattice parameter of a crystal
+ * and its isotope shift.  Here the box of a replica follows isotropic
+ * stochastic cell rescaling (Bernetti and Bussi, J. Chem. Phys. 153, 114107
+ * (2020)), one Euler-Maruyama step of eps = ln V after every step:
+ *   d eps = -(beta_T / tau_p) (P0 - p) dt + sqrt(2 k_B T beta_T dt / (V tau_p)) g,
+ * p = (2 K + W) / (3 V) the instantaneous virial pressure of the step just
+ * closed (K kinetic energy, W = sum over pairs of F(r) r), g a unit Gaussian
+ * of the replica's counter-based stream (step n, dof 0, tag 4); positions
+ * and box are scaled by s = e^{d eps / 3}, velocities by 1 / s, and the
+ * neighbour list is rebuilt at the next step.  Units: P0 in energy / length^3,
+ * tau_p in time, beta_T (isothermal compressibility) in length^3 / energy.
+ *
+ * qtb_barostat: enable (enable != 0) or disable the barostat of a replica.
+ * QTB_E_INVALID unless the potential is the pair potential, the context has
+ * no surrogate buffers, the replica has P = 1 and three dimensions, every
+ * replica is small enough for the force kernel's own list rebuild, the
+ * one-kernel step (QTB_OPT_FUSE) is off, and tau_p, beta_T > 0.  Synchronises.
+ * While it runs, every step's force pass also computes the observables.
+ *
+ * qtb_get_box: synchronise and copy the replica's current box lengths
+ * (host double[3]); status errors as qtb_observables.
+ */
+qtb_status qtb_barostat(qtb_ctx *ctx, int32_t replica, double P0, double tau_p, double beta_T,
+                        int32_t enable);
+qtb_status qtb_get_box(qtb_ctx *ctx, int32_t replica, double *h_box);
 
 /*
  * Diagnostics: while enabled, qtb_step records a HIP event pair around every

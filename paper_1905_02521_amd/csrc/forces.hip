@@ -783,7 +783,8 @@ __global__ void __launch_bounds__(256) k_force_onsite(const RepDev* __restrict__
 __global__ void __launch_bounds__(256) k_obs_reduce(const RepDev* __restrict__ reps, int n_rep,
                                                     const double* __restrict__ partials,
                                                     double* __restrict__ acc,
-                                                    int32_t* __restrict__ counts, int tick)
+                                                    int32_t* __restrict__ counts, int tick,
+                                                    int pair)
 {
     __shared__ double red[kNobs][256];
     const int r = blockIdx.x;
@@ -799,10 +800,18 @@ __global__ void __launch_bounds__(256) k_obs_reduce(const RepDev* __restrict__ r
             for (int q = 0; q < kNobs; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x < kNobs) acc[(size_t)r * kNobs + threadIdx.x] += red[threadIdx.x][0];
+    double* a = acc + (size_t)r * kAcc;
+    if (threadIdx.x < kNobs) a[threadIdx.x] += red[threadIdx.x][0];
     if (threadIdx.x == 0) {
         counts[r] += 1;
         if (tick && R.vt) *R.vt_n += 1;  // the forces of this sample wrote its row
+        if (pair) {
+            // volume of this sample's box (it changes under the barostat) and
+            // the primitive pressure (2K - 2 U_spring + W / P) / (3V)
+            const double V = R.box[0] * R.box[1] * R.box[2];
+            a[6] += V;
+            a[7] += (2.0 * red[0][0] - 2.0 * red[2][0] + red[5][0] / R.P) / (3.0 * V);
+        }
     }
 }
 
@@ -962,10 +971,10 @@ void launch_forces_onsite(hipStream_t st, bool fp64, int kind, const RepDev* rep
 }
 
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
-                       double* acc, int32_t* counts, bool tick)
+                       double* acc, int32_t* counts, bool tick, bool pair)
 {
     launch(k_obs_reduce, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, acc, counts,
-           tick ? 1 : 0);
+           tick ? 1 : 0, pair ? 1 : 0);
 }
 
 void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value)

@@ -267,6 +267,68 @@ __global__ void __launch_bounds__(256) k_eq9(const RepDev* __restrict__ reps,
     }
 }
 
+// Isotropic stochastic cell rescaling (after Bernetti and Bussi, J. Chem.
+// Phys. 153, 114107 (2020)), one block per replica: the virial pressure
+// p = (2K + W) / (3V) of the step just closed from the force pass's block
+// sums (fixed order), then one Euler-Maruyama (Ito) step of eps = ln V,
+//   d eps = -(beta_T / tau_p) (P0 - p) dt + sqrt(2 k_B T beta_T dt / (V tau_p)) g,
+// g the unit Gaussian at (replica step n, dof 0, tag 4).  With the
+// diffusion in eps proportional to 1/V this samples V^N e^{-P0 V / k_B T} for
+// an ideal gas.  The box scales by s = e^{d eps / 3}; the list is rebuilt at
+// the next force pass (its reference displacements hold the old box).
+__global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int n_rep,
+                                                  const double* __restrict__ partials,
+                                                  const StepRef sync)
+{
+    __shared__ double red[2][256];
+    const int r = blockIdx.x;
+    if (r >= n_rep) return;
+    RepDev& R = reps[r];
+    if (!R.npt) return;
+    double ke = 0.0, w = 0.0;
+    for (int b = threadIdx.x; b < R.obs_nblocks; b += blockDim.x) {
+        ke += partials[(size_t)(R.obs_block0 + b) * kNobs + 0];
+        w += partials[(size_t)(R.obs_block0 + b) * kNobs + 5];
+    }
+    red[0][threadIdx.x] = ke;
+    red[1][threadIdx.x] = w;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t n = (sync.clk ? *sync.clk : 0) + sync.off;
+        const double V = R.box[0] * R.box[1] * R.box[2];
+        const double p = (2.0 * red[0][0] + red[1][0]) / (3.0 * V);
+        const double g = white_gauss(R.seed, n + R.step_off, 0u, R.stream, 4);
+        const double deps = -(R.npt_beta / R.npt_tau) * (R.npt_P0 - p) * R.dt +
+                            sqrt(2.0 * R.kT * R.npt_beta * R.dt / (V * R.npt_tau)) * g;
+        const double sc = exp(deps / 3.0);
+        for (int a = 0; a < 3; ++a) R.box[a] *= sc;
+        R.npt_s = sc;
+        int64_t f = (n + 2) % 3;  // the next step's force pass rebuilds the list
+        if (f < 0) f += 3;
+        R.rflag[f] = 1;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_npt_scale(const RepDev* __restrict__ reps, int n_rep)
+{
+    const RepDev& R = reps[blockIdx.y];
+    if (!R.npt) return;
+    const int64_t n = (int64_t)R.P * R.dims * R.N;
+    const double sc = R.npt_s, isc = 1.0 / sc;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        R.pos[q] *= sc;
+        R.vel[q] *= isc;
+    }
+}
+
 // After k_eq9: record which noise block each half holds (invalidate: none).
 __global__ void k_eq9_mark(const int64_t* __restrict__ clock, int64_t* __restrict__ marker, int n,
                            int K, int invalidate)
@@ -327,6 +389,16 @@ void launch_eq9(hipStream_t st, bool fp64, const RepDev* reps, const FirTile* ti
         launch(k_eq9<float>, grid, block, lds, st, reps, tiles, amp, amp_stride, tw, L2, cw,
                (float*)zeta, n_cols, (const int64_t*)clock, (const int64_t*)marker, K, n_groups);
     launch(k_eq9_mark, dim3(1), dim3(64), 0, st, clock, marker, n, K, 0);
+}
+
+void launch_barostat(hipStream_t st, RepDev* reps, int n_rep, const double* partials,
+                     StepRef sync, int64_t max_dof)
+{
+    launch(k_barostat, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, sync);
+    int64_t bx = (max_dof + 255) / 256;
+    if (bx > 256) bx = 256;
+    launch(k_npt_scale, dim3((unsigned)bx, (unsigned)n_rep), dim3(256), 0, st,
+           (const RepDev*)reps, n_rep);
 }
 
 void launch_eq9_invalidate(hipStream_t st, int64_t* marker)

@@ -307,7 +307,7 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
         add(cur, L.eq9mark, 64);
     }
     add(cur, L.partials, sizeof(double) * kNobs * L.max_force_blocks);
-    add(cur, L.acc, sizeof(double) * kNobs * n_rep);
+    add(cur, L.acc, sizeof(double) * kAcc * n_rep);
     add(cur, L.counts, sizeof(int32_t) * n_rep);
     add(cur, L.pairtab, sizeof(PairTable<double>));
     add(cur, L.blk_upd, sizeof(BlockEntry) * std::max<size_t>(1, L.upd.size()));
@@ -317,7 +317,7 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     if (L.ml) {
         add(cur, L.blk_mlc, sizeof(BlockEntry) * L.mlc.size());
         add(cur, L.blk_mlm, sizeof(BlockEntry) * L.mlm.size());
-        add(cur, L.ml_acc, sizeof(double) * kNobs * n_rep);
+        add(cur, L.ml_acc, sizeof(double) * kAcc * n_rep);
         add(cur, L.ml_counts, sizeof(int32_t) * n_rep);
         add(cur, L.ml_loss, sizeof(double) * n_rep);
         add(cur, L.ml_stats, sizeof(double) * (2 * kMlFeat * 2 + 2));
@@ -749,6 +749,7 @@ void fill_repdev(qtb_ctx* c, int r)
     }
     d.seed = R.seed;
     d.stream = R.stream;
+    d.dt = R.dt;
     if (c->L.ml) {
         d.ml_nb = c->at<void>(p.mlnb);
         d.ml_nc = c->at<int32_t>(p.mlnc);
@@ -771,8 +772,35 @@ void fill_repdev(qtb_ctx* c, int r)
     }
 }
 
+bool npt_any(const qtb_ctx* c)
+{
+    for (const auto& d : c->rd)
+        if (d.npt) return true;
+    return false;
+}
+
+// Under the barostat the device copy of a replica's box is the current one:
+// bring it back to the host tables (synchronises).
+qtb_status sync_boxes(qtb_ctx* c)
+{
+    if (!npt_any(c)) return QTB_OK;
+    std::vector<RepDev> dev(c->n_rep);
+    QTB_HIP(c, hipMemcpyAsync(dev.data(), c->at<void>(c->L.reps), sizeof(RepDev) * c->n_rep,
+                              hipMemcpyDeviceToHost, c->st));
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    for (int r = 0; r < c->n_rep; ++r) {
+        if (!c->rd[r].npt) continue;
+        for (int a = 0; a < 3; ++a) {
+            c->rd[r].box[a] = dev[r].box[a];
+            c->reps[r].box[a] = dev[r].box[a];
+        }
+    }
+    return QTB_OK;
+}
+
 qtb_status upload_tables(qtb_ctx* c)
 {
+    if (qtb_status s = sync_boxes(c)) return s;
     QTB_HIP(c, hipMemcpyAsync(c->at<void>(c->L.reps), c->rd.data(), sizeof(RepDev) * c->n_rep,
                               hipMemcpyHostToDevice, c->st));
     QTB_HIP(c, hipMemcpyAsync(c->at<void>(c->L.tiles), c->L.tilev.data(),
@@ -969,20 +997,32 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
         Phase ph(c, 3, true);  // tile bounds and list kernels (+ surrogate lists)
         launch_rebuild(c);
     }
+    // the barostat needs the kinetic energy and the pair virial of every step
+    const bool npt = npt_any(c);
+    const int32_t fflags = kKick | (sample || npt ? kSample : 0);
     {
         Phase ph(c, 4, L.force_groups.size() > 1 || c->ml);
-        if (inline_rebuild) launch_plain_forces(c, kKick | (sample ? kSample : 0), true);
-        else launch_forces(c, kKick | (sample ? kSample : 0));
+        if (inline_rebuild) launch_plain_forces(c, fflags, true);
+        else launch_forces(c, fflags);
     }
     if (sample) {
         Phase ph(c, 5);
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
-                          c->at<int32_t>(L.counts), true);
+                          c->at<int32_t>(L.counts), true, c->pair && !c->ml);
+    }
+    if (npt) {  // after the sample: observables see the box the step ran in
+        Phase ph(c, 5);
+        c->rec_extra = 0;  // step n itself
+        int64_t max_dof = 0;
+        for (const auto& R : c->reps)
+            max_dof = std::max<int64_t>(max_dof, (int64_t)R.n_beads * R.n_dims * R.n_atoms);
+        launch_barostat(c->st, c->at<RepDev>(L.reps), c->n_rep, c->at<double>(L.partials),
+                        step_ref(c), max_dof);
     }
     if (check) {  // the pair potential judges the surrogate on the same positions
         launch_plain_forces(c, kCompare);
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials),
-                          c->at<double>(L.ml_acc), c->at<int32_t>(L.ml_counts), false);
+                          c->at<double>(L.ml_acc), c->at<int32_t>(L.ml_counts), false, false);
     }
     c->rec_row = -1;
     c->rec_extra = 0;
@@ -1049,7 +1089,7 @@ void record_fused(qtb_ctx* c, int row, bool sample_prev)
     if (sample_prev) {
         Phase ph(c, 5);
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
-                          c->at<int32_t>(L.counts), true);
+                          c->at<int32_t>(L.counts), true, c->pair && !c->ml);
     }
     c->rec_row = -1;
 }
@@ -1071,7 +1111,7 @@ void close_steps(qtb_ctx* c)
     if (sample) {
         Phase ph(c, 5);
         launch_obs_reduce(c->st, c->at<RepDev>(L.reps), c->n_rep, c->at<double>(L.partials),
-                          c->at<double>(L.acc), c->at<int32_t>(L.counts), true);
+                          c->at<double>(L.acc), c->at<int32_t>(L.counts), true, c->pair && !c->ml);
     }
     c->open = false;
 }
@@ -1512,14 +1552,14 @@ qtb_status qtb_observables(qtb_ctx* c, int32_t replica, qtb_obs* out)
 {
     if (!c || !out) return fail(c, QTB_E_INVALID, "null argument");
     if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
-    double acc[kNobs];
+    double acc[kAcc];
     int32_t cnt = 0;
-    QTB_HIP(c, hipMemcpyAsync(acc, c->at<double>(c->L.acc) + (size_t)replica * kNobs,
+    QTB_HIP(c, hipMemcpyAsync(acc, c->at<double>(c->L.acc) + (size_t)replica * kAcc,
                               sizeof(acc), hipMemcpyDeviceToHost, c->st));
     QTB_HIP(c, hipMemcpyAsync(&cnt, c->at<int32_t>(c->L.counts) + replica, 4,
                               hipMemcpyDeviceToHost, c->st));
     qtb_status s = read_status(c);
-    launch_fill(c->st, c->at<double>(c->L.acc) + (size_t)replica * kNobs, 2 * kNobs, 0);
+    launch_fill(c->st, c->at<double>(c->L.acc) + (size_t)replica * kAcc, 2 * kAcc, 0);
     launch_fill(c->st, c->at<int32_t>(c->L.counts) + replica, 1, 0);
     QTB_HIP(c, hipStreamSynchronize(c->st));
     const qtb_replica& R = c->reps[replica];
@@ -1540,9 +1580,9 @@ qtb_status qtb_observables(qtb_ctx* c, int32_t replica, qtb_obs* out)
         out->t_kinetic = 2.0 * ke / (dof * R.n_beads * c->opt.kB);
         out->x2_mean = x2 / (dof * R.n_beads);
         if (c->pair && !c->ml) {
-            const double wp = acc[5] * inv, V = R.box[0] * R.box[1] * R.box[2];
-            out->virial_pair = wp;
-            out->pressure = (2.0 * ke - 2.0 * spr + wp / R.n_beads) / (3.0 * V);
+            out->virial_pair = acc[5] * inv;
+            out->volume = acc[6] * inv;
+            out->pressure = acc[7] * inv;
         }
     }
     return s;
@@ -1781,6 +1821,48 @@ qtb_status qtb_vdos_detach(qtb_ctx* c, int32_t replica)
     return QTB_OK;
 }
 
+qtb_status qtb_barostat(qtb_ctx* c, int32_t replica, double P0, double tau_p, double beta_T,
+                        int32_t enable)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    if (enable) {
+        if (!c->pair || c->ml || c->L.ml)
+            return fail(c, QTB_E_INVALID, "barostat: pair potential without surrogate buffers only");
+        if (c->reps[replica].n_beads != 1 || c->reps[replica].n_dims != 3)
+            return fail(c, QTB_E_INVALID, "barostat: P = 1 and three dimensions only");
+        if (list_kernel(c))
+            return fail(c, QTB_E_INVALID, "barostat: replicas above the inline-rebuild size");
+        if (c->opt.flags & QTB_OPT_FUSE)
+            return fail(c, QTB_E_INVALID, "barostat: not with the one-kernel step");
+        if (!(tau_p > 0.0) || !(beta_T > 0.0) || !std::isfinite(P0))
+            return fail(c, QTB_E_INVALID, "barostat: tau_p and beta_T must be positive");
+    }
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    if (qtb_status s = sync_boxes(c)) return s;
+    RepDev& d = c->rd[replica];
+    d.npt = enable ? 1 : 0;
+    d.npt_P0 = enable ? P0 : 0.0;
+    d.npt_tau = enable ? tau_p : 0.0;
+    d.npt_beta = enable ? beta_T : 0.0;
+    d.npt_s = 1.0;
+    drop_graph(c);  // the step sequence changes
+    qtb_status s = upload_tables(c);
+    if (s) return s;
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    return QTB_OK;
+}
+
+qtb_status qtb_get_box(qtb_ctx* c, int32_t replica, double* h_box)
+{
+    if (!c || !h_box) return fail(c, QTB_E_INVALID, "null argument");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    if (qtb_status s = sync_boxes(c)) return s;
+    for (int a = 0; a < 3; ++a) h_box[a] = c->reps[replica].box[a];
+    return read_status(c);
+}
+
 qtb_status qtb_profile(qtb_ctx* c, int32_t enable)
 {
     if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
@@ -1963,7 +2045,7 @@ qtb_status qtb_ml_attach(qtb_ctx* c, qtb_ml* m, int32_t check_every)
         // one wavefront per atom in the gather: the W = 1 table
         if ((s = select_force_table(c, 1))) return s;
         c->tuned = true;
-        launch_fill(c->st, c->at<double>(c->L.ml_acc), 2 * kNobs * c->n_rep, 0);
+        launch_fill(c->st, c->at<double>(c->L.ml_acc), 2 * kAcc * c->n_rep, 0);
         launch_fill(c->st, c->at<int32_t>(c->L.ml_counts), c->n_rep, 0);
     } else {
         c->tuned = false;
@@ -2108,11 +2190,11 @@ qtb_status qtb_ml_check(qtb_ctx* c, int32_t replica, double* rmse, double* rel_r
     if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
     double acc[kNobs];
     int32_t cnt = 0;
-    QTB_HIP(c, hipMemcpyAsync(acc, c->at<double>(c->L.ml_acc) + (size_t)replica * kNobs, sizeof(acc),
+    QTB_HIP(c, hipMemcpyAsync(acc, c->at<double>(c->L.ml_acc) + (size_t)replica * kAcc, sizeof(acc),
                               hipMemcpyDeviceToHost, c->st));
     QTB_HIP(c, hipMemcpyAsync(&cnt, c->at<int32_t>(c->L.ml_counts) + replica, 4, hipMemcpyDeviceToHost, c->st));
     QTB_HIP(c, hipStreamSynchronize(c->st));
-    launch_fill(c->st, c->at<double>(c->L.ml_acc) + (size_t)replica * kNobs, 2 * kNobs, 0);
+    launch_fill(c->st, c->at<double>(c->L.ml_acc) + (size_t)replica * kAcc, 2 * kAcc, 0);
     launch_fill(c->st, c->at<int32_t>(c->L.ml_counts) + replica, 1, 0);
     QTB_HIP(c, hipStreamSynchronize(c->st));
     const qtb_replica& R = c->reps[replica];

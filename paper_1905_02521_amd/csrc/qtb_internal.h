@@ -15,7 +15,10 @@ constexpr int kMaxSpecies = QTB_MAX_SPECIES;
 constexpr int kPairs = kMaxSpecies * kMaxSpecies;
 constexpr int kDofTile = 256;      // replica dof ranges are padded to this
 constexpr int kWavesPerAtomDefault = 2;  // force kernel: wavefronts per atom (1, 2, 4)
-constexpr int kNobs = 6;           // ke, U, spring, virial, x2, (unused)
+constexpr int kNobs = 6;           // ke, U, spring, virial, x2, pair virial
+// sample accumulators: the kNobs slots, then (pair potential) volume and the
+// pressure of each sample
+constexpr int kAcc = 8;
 
 // Pair potential in the form the force kernels evaluate:
 //   F(r) = -dV/dr = Arho e^{-r irho} - C6 r^-7
@@ -108,7 +111,12 @@ struct RepDev {
     double* vt;
     int64_t* vt_n;
     int32_t vt_cap;
-    int32_t vt_pad;
+    // isotropic stochastic cell rescaling after every step (P = 1, pair
+    // potential); box[] above is then the current box, updated on the device
+    int32_t npt;
+    double npt_P0, npt_tau, npt_beta;  // target pressure, relaxation time, compressibility
+    double npt_s;                      // this step's length scale factor
+    double dt;
 };
 
 // ------------------------------------------------ descriptor-MLP surrogate
@@ -267,6 +275,12 @@ void launch_eq9(hipStream_t st, bool fp64, const RepDev* reps, const FirTile* ti
                 const double* amp, int amp_stride, const double* tw, int n, void* zeta,
                 int64_t n_cols, const int64_t* clock, int64_t* marker, int K);
 void launch_eq9_invalidate(hipStream_t st, int64_t* marker);
+// Cell rescaling of the replicas with npt set, after the force pass of step
+// n (sync gives n; partials hold that pass's block sums): new box, scale
+// factor, list rebuild flagged for step n + 1; then positions and velocities
+// scaled (max_dof: the largest P dims N).
+void launch_barostat(hipStream_t st, RepDev* reps, int n_rep, const double* partials,
+                     StepRef sync, int64_t max_dof);
 int eq9_columns(int n);
 void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
                      int64_t n_rows, uint32_t d0, uint32_t n_dof, double* out);
@@ -308,9 +322,10 @@ void launch_step_pair(hipStream_t st, bool fp64, int G, int W, const RepDev* rep
 void launch_forces_onsite(hipStream_t st, bool fp64, int kind, const RepDev* reps,
                           const BlockEntry* blocks, int n_blocks, int32_t flags,
                           double* partials);
-// tick: a sample (advances the velocity recorders), not a surrogate check
+// tick: a sample (advances the velocity recorders), not a surrogate check;
+// pair: the pair potential (the volume and pressure slots are filled)
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
-                       double* acc, int32_t* counts, bool tick);
+                       double* acc, int32_t* counts, bool tick, bool pair);
 void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value);
 // vdos.hip
 constexpr int kVdosMinSeg = 16, kVdosMaxSeg = 4096;  // samples per segment, powers of two

@@ -79,7 +79,7 @@ class qtb_obs(ctypes.Structure):
                 ("e_primitive", ctypes.c_double), ("e_virial", ctypes.c_double),
                 ("t_kinetic", ctypes.c_double), ("x2_mean", ctypes.c_double),
                 ("virial_pair", ctypes.c_double), ("pressure", ctypes.c_double),
-                ("n_samples", ctypes.c_int32)]
+                ("volume", ctypes.c_double), ("n_samples", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -89,7 +89,7 @@ EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
            "qtb_observables", "qtb_get_state", "qtb_set_state", "qtb_evaluate",
            "qtb_get_noise", "qtb_gaussian", "qtb_profile", "qtb_profile_read",
            "qtb_vdos_workspace_bytes", "qtb_vdos_spectrum", "qtb_vdos_attach", "qtb_vdos_read",
-           "qtb_vdos_detach",
+           "qtb_vdos_detach", "qtb_barostat", "qtb_get_box",
            "qtb_last_error", "qtb_destroy", "qtb_version",
            "qtb_ml_workspace_bytes", "qtb_ml_create", "qtb_ml_init_params", "qtb_ml_set_params",
            "qtb_ml_get_params", "qtb_ml_attach", "qtb_ml_evaluate", "qtb_ml_fit_norm",
@@ -147,6 +147,11 @@ def lib():
                                 ctypes.c_int32]
     L.qtb_vdos_detach.restype = ctypes.c_int
     L.qtb_vdos_detach.argtypes = [vp, ctypes.c_int32]
+    L.qtb_barostat.restype = ctypes.c_int
+    L.qtb_barostat.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_int32]
+    L.qtb_get_box.restype = ctypes.c_int
+    L.qtb_get_box.argtypes = [vp, ctypes.c_int32, _PD]
     L.qtb_profile.restype = ctypes.c_int
     L.qtb_profile.argtypes = [vp, ctypes.c_int32]
     L.qtb_profile_read.restype = ctypes.c_int
@@ -421,6 +426,18 @@ class Context:
     def vdos_detach(self, replica=0):
         _check(lib().qtb_vdos_detach(self.ctx, replica), self.ctx)
         getattr(self, "_vdos_ws", {}).pop(replica, None)
+
+    # -- constant pressure --------------------------------------------------------
+    def barostat(self, replica, P0, tau_p, beta_T, enable=True):
+        """Isotropic stochastic cell rescaling of a replica's box (P0 in
+        energy / length^3, tau_p in time, beta_T in length^3 / energy)."""
+        _check(lib().qtb_barostat(self.ctx, replica, float(P0), float(tau_p), float(beta_T),
+                                  1 if enable else 0), self.ctx)
+
+    def box(self, replica=0):
+        b = np.zeros(3)
+        _check(lib().qtb_get_box(self.ctx, replica, _pd(b)), self.ctx)
+        return b
 
     # -- surrogate --------------------------------------------------------------
     def ml_attach(self, model, check_every=0):

@@ -1,0 +1,160 @@
+"""Constant pressure on the GPU: isotropic stochastic cell rescaling of the
+box after every step (the isothermal-isobaric extension of Sec. 2.1, used for
+the lattice parameters of Sec. 2.2, Fig. 6).
+
+* Parity: an FP64 QTB trajectory of the compressed MgO crystal under a
+  barostat fast enough to expand the box by several tenths of a per cent in
+  74 steps follows the oracle's (same counter-based Gaussians, tag 4 for the
+  barostat) in positions, velocities, box and the sampled pressure to 1e-9,
+  through eager steps and a replayed graph block; switching the barostat off
+  freezes the box again.
+* Statistics: at P0 = 0 the mean lattice parameter of 512-atom crystals
+  (production precision; classical Langevin at 300 K, QTB at 50 K for two
+  isotopes) agrees with the zero of the constant-volume equation of state
+  p(a) measured by the equation-of-state test of the same potential and
+  settings, and so does the isotope shift.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1905_02521_amd import qtb, workloads as W
+from tests.gpu_common import crystal, gpu_crystal_ctx, oracle_pair_pot, oracle_units
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qtb.lib()
+
+
+def test_barostat_trajectory_matches_oracle(orc):
+    beads, sp, box = crystal(3, 1, seed=7)
+    T, gamma, dt, seed, two_nf = 300.0, 5e-3, 1.0, 13, 256
+    P0, tau_p, beta_T = 0.0, 20.0, 0.5   # eV/A^3, fs, A^3/eV
+    ctx = gpu_crystal_ctx(beads, sp, box, T=T, gamma=gamma, dt=dt, noise=1, prec=qtb.PREC_FP64,
+                          fir=qtb.FIR_FP64, seed=seed, max_two_nf=two_nf, obs_every=5)
+    ctx.build_filter(0, 1, two_nf)
+    ctx.barostat(0, P0, tau_p, beta_T)
+    osim = orc.Sim(oracle_pair_pot(orc), oracle_units(orc, False), beads.shape[2], 1, 3, box, sp,
+                   T, gamma, dt, seed, 0, 1, two_nf, beads, n_threads=8)
+    osim.set_barostat(P0, tau_p, beta_T)
+    ip = orc.OBS_NAMES.index("pressure")
+    obs_o = []
+    for n in (10, 64):   # eager steps, then one graph block of K = 64
+        ctx.step(n)
+        obs_o.append(osim.run(n, 5))
+        r, v, st = ctx.get_state(0)
+        ro, vo, _, sto = osim.state()
+        assert st == sto
+        b, bo = ctx.box(0), osim.box()
+        print(f"step {st}: box {b[0]:.8f} (oracle {bo[0]:.8f}, start {box[0]:.8f})")
+        assert np.max(np.abs(b - bo)) <= 1e-12 * bo[0]
+        assert np.sqrt(np.mean((r - ro) ** 2)) <= 1e-9 * 0.0421
+        assert np.sqrt(np.mean((v - vo) ** 2)) <= 1e-9 * np.sqrt(np.mean(vo ** 2))
+    assert abs(b[0] / box[0] - 1.0) > 2e-3          # the box did move
+    g = ctx.observables(0)
+    o = np.concatenate(obs_o)
+    assert g["n_samples"] == len(o) == 14
+    assert abs(g["pressure"] - o[:, ip].mean()) <= 1e-9 * abs(o[:, ip]).max()
+    assert g["volume"] > 0.0
+    # off again: the box stays where it is
+    ctx.barostat(0, 0.0, 1.0, 1.0, enable=False)
+    b0 = ctx.box(0)
+    ctx.step(20)
+    assert np.array_equal(ctx.box(0), b0)
+    ctx.close()
+
+
+def test_barostat_rejected_where_unsupported():
+    beads, sp, box = crystal(2, 4, seed=1)
+    ctx = gpu_crystal_ctx(beads, sp, box, T=100.0, gamma=1e-3, dt=1.0, noise=2,
+                          prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, max_two_nf=128)
+    with pytest.raises(qtb.QtbError):   # P = 4
+        ctx.barostat(0, 0.0, 100.0, 1.0)
+    ctx.close()
+    beads, sp, box = crystal(2, 1, seed=1)
+    ctx = gpu_crystal_ctx(beads, sp, box, T=100.0, gamma=1e-3, dt=1.0, noise=1,
+                          prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, max_two_nf=128)
+    for args in ((0.0, 0.0, 1.0), (0.0, 100.0, -1.0), (float("nan"), 100.0, 1.0)):
+        with pytest.raises(qtb.QtbError):
+            ctx.barostat(0, *args)
+    with pytest.raises(qtb.QtbError):
+        ctx.barostat(1, 0.0, 100.0, 1.0)
+    ctx.close()
+    ctx = gpu_crystal_ctx(beads, sp, box, T=100.0, gamma=1e-3, dt=1.0, noise=1,
+                          prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, max_two_nf=128, fuse=True)
+    with pytest.raises(qtb.QtbError):   # not with the one-kernel step
+        ctx.barostat(0, 0.0, 100.0, 1.0)
+    ctx.close()
+
+
+# zeros of the constant-volume p(a) (same potential, precision, dt, gamma
+# and filter length) with their standard errors, from the equation-of-state
+# scan: 24Mg16O classical at 300 K and QTB at 50 K, 26Mg18O QTB at 50 K
+LIGHT, HEAVY = (23.985, 15.995), (25.983, 17.999)
+EOS_A = {(LIGHT, 0, 300.0): (4.24713, 6e-5), (LIGHT, 1, 50.0): (4.24768, 5e-5),
+         (HEAVY, 1, 50.0): (4.24660, 7e-5)}
+EOS_SHIFT_50K = (1.08e-3, 0.09e-3)   # QTB 24Mg16O minus 26Mg18O at 50 K
+
+
+def npt_lattice_blocks(masses, conds):
+    """Eight 512-atom replicas per (noise, T) (different seeds) at P0 = 0,
+    tau_p = 500 fs, beta_T = 1 A^3/eV (close to MgO's); 20 000 steps of
+    equilibration, then the lattice parameter V^(1/3) / 4 of the replicas'
+    mean volume in 16 blocks of 5000 steps."""
+    potd = qtb.pair_potential_dict(W.mgo_potential(skin=1.0))
+    potd["mass"] = masses
+    keys, reps = [], []
+    for noise, T in conds:
+        for k in range(8):
+            pos, sp, box = W.rocksalt(4, 4.24)
+            beads = W.beads_from(W.displaced(pos, 0.01, 40 + k), 1)
+            reps.append(qtb.Replica(pos=beads, species=sp, T=T, gamma=1e-3, dt=1.0, noise=noise,
+                                    box=tuple(box), seed=100 + len(reps), stream=len(reps)))
+            keys.append((noise, T))
+    ctx = qtb.Context(potd, reps, dict(W.METAL_UNITS), prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3,
+                      obs_every=8, max_two_nf=512)
+    for r, (noise, _) in enumerate(keys):
+        if noise:
+            ctx.build_filter(r, noise, 512)
+        ctx.barostat(r, 0.0, 500.0, 1.0)
+    ctx.step(20_000)
+    for r in range(len(keys)):
+        ctx.observables(r)
+    blocks = {c: [] for c in conds}
+    for _ in range(16):
+        ctx.step(5000)
+        vol = {c: [] for c in conds}
+        for r, k in enumerate(keys):
+            vol[k].append(ctx.observables(r)["volume"])
+        for c in conds:
+            blocks[c].append(np.mean(vol[c]) ** (1.0 / 3.0) / 4.0)
+    ctx.close()
+    return {c: np.array(b) for c, b in blocks.items()}
+
+
+def test_npt_lattice_parameter_matches_equation_of_state():
+    res = {}
+    for masses in (LIGHT, HEAVY):
+        conds = [(n, T) for (m, n, T) in EOS_A if m == masses]
+        for c, b in npt_lattice_blocks(masses, conds).items():
+            res[(masses,) + c] = (b.mean(), b.std(ddof=1) / math.sqrt(len(b)))
+    for k, (a_eos, se_eos) in EOS_A.items():
+        m, se = res[k]
+        print(f"masses {k[0]} noise {k[1]} T {k[2]:.0f} K: <a> NPT {m:.5f} +- {se:.5f}, "
+              f"EOS {a_eos:.5f} +- {se_eos:.5f}")
+        assert se < 3e-4
+        assert abs(m - a_eos) < 4 * math.hypot(se, se_eos), (k, m, a_eos)
+    # the isotope shift at constant pressure: the lighter crystal is larger
+    (a1, s1), (a2, s2) = res[(LIGHT, 1, 50.0)], res[(HEAVY, 1, 50.0)]
+    d, sd = a1 - a2, math.hypot(s1, s2)
+    print(f"QTB 50 K isotope shift at P = 0: {d * 1e3:+.3f} +- {sd * 1e3:.3f} mA "
+          f"(equation of state {EOS_SHIFT_50K[0] * 1e3:+.2f} +- {EOS_SHIFT_50K[1] * 1e3:.2f})")
+    assert d > 4 * sd
+    assert abs(d - EOS_SHIFT_50K[0]) < 4 * math.hypot(sd, EOS_SHIFT_50K[1])
