@@ -475,6 +475,79 @@ def vdos_bench(a):
     print(json.dumps(out))
 
 
+def npt_bench(a):
+    """Constant pressure on the 8x8x8 MgO crystal (4096 atoms, QTB, P = 1,
+    300 K, gamma = 1/ps, FP32 forces, BF16x3 noise): wall time per step at
+    constant volume and under the barostat (P0 = 0, tau_p = 500 fs,
+    beta_T = 1 A^3/eV), where every step also samples K and the pair virial,
+    rebuilds the neighbour lists and runs the cell-rescaling kernels; GPU
+    time per phase from the dispatch stamps of 256 further steps; and the
+    oracle with the same barostat on the host cores."""
+    from paper_1905_02521_amd import qtb, workloads as W
+    pot = W.mgo_potential(skin=0.4)
+    pos, sp, box = W.rocksalt(8)
+    base = W.displaced(pos, 0.0421, 2)
+    N = len(sp)
+    T, gamma, dt, P0, tau_p, beta_T = 300.0, 1e-3, 1.0, 0.0, 500.0, 1.0
+    rep = qtb.Replica(pos=W.beads_from(base, 1), species=sp, T=T, gamma=gamma, dt=dt, noise=1,
+                      box=tuple(box), seed=2)
+    ctx = qtb.Context(qtb.pair_potential_dict(pot), [rep], W.METAL_UNITS, prec=qtb.PREC_FP32,
+                      fir=qtb.FIR_BF16X3, obs_every=64, max_two_nf=512)
+    ctx.build_filter(0, 1, 512)
+    ctx.step(a.warmup)
+    t_step, phases = {}, {}
+    for name in ("nvt", "npt"):
+        if name == "npt":
+            ctx.barostat(0, P0, tau_p, beta_T)
+            ctx.step(a.warmup)
+        ctx.observables(0)   # synchronises
+        t0 = time.perf_counter()
+        ctx.step(a.steps)
+        ctx.observables(0)
+        t_step[name] = (time.perf_counter() - t0) / a.steps
+        ctx.profile(True)
+        ctx.step(256)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        phases[name] = {k: v[0] / 256 for k, v in prof.items() if v[1] > 0}
+    box_end = ctx.box(0)
+    ctx.close()
+    out = {
+        "metric": "atom-steps/s at constant pressure (forces+QTB noise+update+barostat)",
+        "value": N / t_step["npt"], "unit": "atom-steps/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": t_step["npt"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded rock-salt crystal, numpy PCG64 displacements)",
+        "config": {"workload": "mgo-8x8x8-qtb-300K-npt", "atoms": N, "P0_eV_A3": P0,
+                   "tau_p_fs": tau_p, "beta_T_A3_eV": beta_T, "skin_A": 0.4},
+        "ms_per_step_nvt": t_step["nvt"] * 1e3,
+        "npt_cost": t_step["npt"] / t_step["nvt"] - 1.0,
+        "phases_ms_per_step": {"nvt": phases["nvt"], "npt": phases["npt"]},
+        "box_end_A": float(box_end[0]),
+    }
+    if not a.no_cpu:
+        from oracle import oracle as orc
+        threads = min(os.cpu_count() or 1, 16)
+        U = orc.make_units(**W.METAL_UNITS)
+        opot = orc.make_pot(0, pot.mass, pot.charge, pot.buck_A, pot.buck_rho, pot.buck_C,
+                            pot.dsf_alpha, pot.r_cut, pot.skin)
+        sim = orc.Sim(opot, U, N, 1, 3, box, sp, T, gamma, dt, 2, 0, 1, 512,
+                      W.beads_from(base, 1), n_threads=threads)
+        sim.set_barostat(P0, tau_p, beta_T)
+        sim.run(1)
+        n, t = 0, 0.0
+        while t < a.cpu_seconds and n < 10000:
+            t0 = time.perf_counter()
+            sim.run(20)
+            t += time.perf_counter() - t0
+            n += 20
+        out["cpu_baseline"] = {"value": N * n / t, "unit": "atom-steps/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{n} steps of the same workload with the barostat "
+                                         f"({N} atoms), {t:.1f} s, FP64, {threads} OpenMP threads"}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -484,7 +557,8 @@ def main():
                     help="a named single workload, batched-64 (the T / gamma / P sweep) or "
                          "surrogate-20x20x20-P4 (the learned force surrogate) or qtb-vs-pimd "
                          "(QTB, QTB-PIMD and PIMD cost and energies on one crystal) or vdos "
-                         "(the velocity spectrum's recorder and transform)")
+                         "(the velocity spectrum's recorder and transform) or npt (the step "
+                         "at constant pressure)")
     ap.add_argument("--fir", default="bf16x3", choices=["fp32", "bf16x3", "bf16", "fp64"])
     ap.add_argument("--K", type=int, default=64)
     ap.add_argument("--noise-blocks", action="store_true",
@@ -521,6 +595,8 @@ def main():
         return pimd_compare_bench(a)
     if a.workload == "vdos":
         return vdos_bench(a)
+    if a.workload == "npt":
+        return npt_bench(a)
     if a.workload.startswith("surrogate"):
         surrogate_bench(a)
         return

@@ -303,7 +303,9 @@ class Sim:
             raise ValueError("oracle rejected the replica description")
 
     def run(self, n_steps, obs_every=0):
-        nmax = (n_steps // obs_every) if obs_every > 0 else 0
+        # samples fall on steps divisible by obs_every: a run that starts off
+        # that grid can hold one more than n_steps // obs_every
+        nmax = (n_steps // obs_every + 1) if obs_every > 0 else 0
         obs = np.zeros((max(nmax, 1), len(OBS_NAMES)))
         n = lib().orc_sim_run(self.h, n_steps, obs_every, _pd(obs))
         return obs[:n]

@@ -4,10 +4,11 @@ the lattice parameters of Sec. 2.2, Fig. 6).
 
 * Parity: an FP64 QTB trajectory of the compressed MgO crystal under a
   barostat fast enough to expand the box by several tenths of a per cent in
-  74 steps follows the oracle's (same counter-based Gaussians, tag 4 for the
+  128 steps follows the oracle's (same counter-based Gaussians, tag 4 for the
   barostat) in positions, velocities, box and the sampled pressure to 1e-9,
   through eager steps and a replayed graph block; switching the barostat off
-  freezes the box again.
+  freezes the box again.  Beside it, constant-volume replicas of the same
+  context (QTB-PIMD and classical) still follow their oracle runs.
 * Statistics: at P0 = 0 the mean lattice parameter of 512-atom crystals
   (production precision; classical Langevin at 300 K, QTB at 50 K for two
   isotopes) agrees with the zero of the constant-volume equation of state
@@ -38,7 +39,7 @@ def test_barostat_trajectory_matches_oracle(orc):
     T, gamma, dt, seed, two_nf = 300.0, 5e-3, 1.0, 13, 256
     P0, tau_p, beta_T = 0.0, 20.0, 0.5   # eV/A^3, fs, A^3/eV
     ctx = gpu_crystal_ctx(beads, sp, box, T=T, gamma=gamma, dt=dt, noise=1, prec=qtb.PREC_FP64,
-                          fir=qtb.FIR_FP64, seed=seed, max_two_nf=two_nf, obs_every=5)
+                          fir=qtb.FIR_FP64, seed=seed, max_two_nf=two_nf, obs_every=4)
     ctx.build_filter(0, 1, two_nf)
     ctx.barostat(0, P0, tau_p, beta_T)
     osim = orc.Sim(oracle_pair_pot(orc), oracle_units(orc, False), beads.shape[2], 1, 3, box, sp,
@@ -46,9 +47,11 @@ def test_barostat_trajectory_matches_oracle(orc):
     osim.set_barostat(P0, tau_p, beta_T)
     ip = orc.OBS_NAMES.index("pressure")
     obs_o = []
-    for n in (10, 64):   # eager steps, then one graph block of K = 64
+    # the first noise block runs eagerly (10 + 54 steps), the second is a
+    # replayed graph of K = 64 steps
+    for n in (10, 54, 64):
         ctx.step(n)
-        obs_o.append(osim.run(n, 5))
+        obs_o.append(osim.run(n, 4))
         r, v, st = ctx.get_state(0)
         ro, vo, _, sto = osim.state()
         assert st == sto
@@ -60,7 +63,7 @@ def test_barostat_trajectory_matches_oracle(orc):
     assert abs(b[0] / box[0] - 1.0) > 2e-3          # the box did move
     g = ctx.observables(0)
     o = np.concatenate(obs_o)
-    assert g["n_samples"] == len(o) == 14
+    assert g["n_samples"] == len(o) == 32
     assert abs(g["pressure"] - o[:, ip].mean()) <= 1e-9 * abs(o[:, ip]).max()
     assert g["volume"] > 0.0
     # off again: the box stays where it is
@@ -68,6 +71,48 @@ def test_barostat_trajectory_matches_oracle(orc):
     b0 = ctx.box(0)
     ctx.step(20)
     assert np.array_equal(ctx.box(0), b0)
+    ctx.close()
+
+
+def test_barostat_beside_constant_volume_replicas(orc):
+    """One context, three replicas: QTB P = 1 under the barostat, QTB-PIMD
+    P = 4 and classical P = 1 at constant volume (different seeds, streams,
+    temperatures and sizes).  Every replica follows its own oracle run; the
+    constant-volume boxes stay put although every step now samples."""
+    specs = [(3, 1, 1, 300.0, 21, True), (2, 4, 2, 100.0, 22, False), (3, 1, 0, 200.0, 23, False)]
+    reps, inputs = [], []
+    for k, (n, P, noise, T, seed, _) in enumerate(specs):
+        beads, sp, box = crystal(n, P, seed=seed, bead_spread=0.02 if P > 1 else 0.0)
+        inputs.append((beads, sp, box))
+        reps.append(qtb.Replica(pos=beads, species=sp, T=T, gamma=5e-3, dt=1.0, noise=noise,
+                                box=tuple(box), seed=seed, stream=k))
+    ctx = qtb.Context(qtb.pair_potential_dict(W.mgo_potential()), reps, dict(W.METAL_UNITS),
+                      prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, max_two_nf=256, obs_every=4)
+    sims = []
+    for k, ((n, P, noise, T, seed, npt), (beads, sp, box)) in enumerate(zip(specs, inputs)):
+        if noise:
+            ctx.build_filter(k, noise, 256)
+        sim = orc.Sim(oracle_pair_pot(orc), oracle_units(orc, False), beads.shape[2], P, 3, box,
+                      sp, T, 5e-3, 1.0, seed, k, noise, 256 if noise else 2, beads, n_threads=8)
+        if npt:
+            ctx.barostat(k, 0.0, 20.0, 0.5)
+            sim.set_barostat(0.0, 20.0, 0.5)
+        sims.append(sim)
+    ctx.step(64)   # eagerly
+    ctx.step(64)   # one graph replay
+    for k, sim in enumerate(sims):
+        sim.run(128)
+        r, v, st = ctx.get_state(k)
+        ro, vo, _, sto = sim.state()
+        assert st == sto == 128
+        b, bo = ctx.box(k), sim.box()
+        assert np.max(np.abs(b - bo)) <= 1e-12 * bo[0], (k, b, bo)
+        if not specs[k][5]:
+            assert np.array_equal(b, np.asarray(inputs[k][2], dtype=np.float64))
+        err = np.sqrt(np.mean((r - ro) ** 2))
+        print(f"replica {k}: box {b[0]:.8f}, position rms difference {err:.2e}")
+        assert err <= 1e-9 * 0.0421
+        assert np.sqrt(np.mean((v - vo) ** 2)) <= 1e-9 * np.sqrt(np.mean(vo ** 2))
     ctx.close()
 
 
