@@ -1,0 +1,125 @@
+"""Parity at the full size of the QTB-PIMD step the benchmark times: MgO
+8x8x8 (4096 atoms) x P = 8 beads, 50 K, kappa_P filter 2Nf = 512, FP32
+forces, BF16x3 FIR blocked over K = 64 steps, skin 0.4 A, autotuned force
+decomposition, graph-replayed noise blocks (the benchmark's configuration,
+same seeded inputs).
+
+* Trajectory: the first 10 steps against the oracle's FP64 run of the same
+  crystal, to the FP32 bar of the small trajectory test.
+* Noise: the coloured noise of the third block (a graph replay) on sampled
+  column ranges (first, middle and last tiles, beads and components mixed)
+  against the oracle's convolution of its own white noise with its own taps,
+  to the BF16x3 per-element bound.
+* Forces after 192 steps: all 4096 atoms of two beads against the oracle's
+  brute-force forces at the GPU's positions (1e-5 relative).
+* Graph replay: 192 steps with graph-replayed blocks and the same steps
+  taken eagerly give bit-identical positions and velocities.
+"""
+import numpy as np
+import pytest
+
+from paper_1905_02521_amd import qtb, workloads as W
+from tests.gpu_common import oracle_pair_pot, oracle_units
+
+pytestmark = pytest.mark.gpu
+
+WORKLOAD = "mgo-8x8x8-qtbpimd-P8-50K"
+SKIN, K = 0.4, 64
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qtb.lib()
+
+
+def bench_context(graphs=True, autotune=True):
+    """The benchmark's context for its default workload."""
+    w = W.workload(WORKLOAD)
+    pot = W.mgo_potential(skin=SKIN)
+    beads, sp, box = W.crystal_inputs(w)
+    rep = qtb.Replica(pos=beads, species=sp, T=w.T, gamma=w.gamma, dt=w.dt, noise=w.noise,
+                      box=tuple(box), seed=w.seed, stream=w.stream)
+    ctx = qtb.Context(qtb.pair_potential_dict(pot), [rep], W.METAL_UNITS, prec=qtb.PREC_FP32,
+                      fir=qtb.FIR_BF16X3, fir_block_K=K, obs_every=0, max_two_nf=w.two_nf,
+                      graphs=graphs, autotune=autotune)
+    ctx.build_filter(0, w.noise, w.two_nf)
+    return ctx, w, pot, beads, sp, box
+
+
+def zeta_columns(orc, taps, seed, stream, n0, d0, count):
+    """zeta_{n,d} for n in [n0, n0 + K), d in [d0, d0 + count): the oracle's
+    white noise convolved with the taps, and the sum of |h_k w_{n-k}|."""
+    two_nf = len(taps)
+    Nf = two_nf // 2
+    w = orc.gauss_fill(seed, n0 - Nf + 1, K + two_nf - 1, d0, count, stream, 0)
+    out = np.zeros((K, count))
+    mag = np.zeros((K, count))
+    for k in range(-Nf, Nf):
+        rows = w[(Nf - 1 - k):(Nf - 1 - k) + K]
+        out += taps[k + Nf] * rows
+        mag += abs(taps[k + Nf]) * np.abs(rows)
+    return out, mag
+
+
+def test_full_size_step_matches_oracle(orc):
+    ctx, w, pot, beads, sp, box = bench_context()
+    P, N = beads.shape[0], beads.shape[2]
+    U = oracle_units(orc, False)
+    # first 10 steps against the oracle's FP64 run
+    osim = orc.Sim(oracle_pair_pot(orc, pot), U, N, P, 3, box, sp, w.T, w.gamma, w.dt, w.seed,
+                   w.stream, w.noise, w.two_nf, beads, n_threads=16)
+    ctx.step(10)
+    osim.run(10)
+    r, v, st = ctx.get_state(0)
+    ro, vo, _, sto = osim.state()
+    assert st == sto == 10
+    rel = np.sqrt(np.mean((r - ro) ** 2)) / 0.0421
+    print(f"10 steps at 4096 x 8: position rms difference / 0.0421 A = {rel:.2e}")
+    assert rel <= 1e-5
+    del osim
+    # the third noise block is a graph replay
+    ctx.step(54)
+    ctx.step(64)
+    ctx.step(64)
+    z, n0 = ctx.get_noise(0)
+    assert n0 == 128
+    taps = orc.taps(w.noise, w.T, P, w.dt, w.two_nf, U)
+    D = 3 * N * P
+    worst = 0.0
+    for d0 in (0, D // 2 - 77, D - 256):
+        ref, mag = zeta_columns(orc, taps, w.seed, w.stream, n0, d0, 256)
+        worst = max(worst, float(np.max(np.abs(z[:, d0:d0 + 256] - ref) / mag)))
+    bound = 3 * 2.0**-16 + (w.two_nf + 4) * 2.0**-24
+    print(f"noise of the replayed block: max |zeta - oracle| / sum|h w| = {worst:.2e} "
+          f"(bound {bound:.2e})")
+    assert worst <= bound
+    # forces at the GPU's positions after 192 steps
+    r, v, st = ctx.get_state(0)
+    assert st == 192
+    f, _ = ctx.evaluate(0)
+    opot = oracle_pair_pot(orc, pot)
+    for s in (0, 5):
+        _, fo, _ = orc.pair_bruteforce(opot, U, box, sp, r[s])
+        rel = np.linalg.norm(f[s] - fo) / np.linalg.norm(fo)
+        print(f"bead {s}: force relative difference {rel:.2e}")
+        assert rel <= 1e-5
+    ctx.close()
+
+
+def test_full_size_graph_replay_is_bit_identical():
+    """192 steps with two graph-replayed noise blocks and the same steps taken
+    eagerly give bit-identical states (one fixed force decomposition: the
+    autotuner's timing-based choice could differ between two contexts)."""
+    states = []
+    for graphs in (True, False):
+        ctx, *_ = bench_context(graphs=graphs, autotune=False)
+        for n in (10, 54, 64, 64):
+            ctx.step(n)
+        states.append(ctx.get_state(0))
+        ctx.close()
+    (r, v, st), (r2, v2, st2) = states
+    assert st == st2 == 192
+    assert np.array_equal(r, r2) and np.array_equal(v, v2)
