@@ -14,6 +14,8 @@ same seeded inputs).
   brute-force forces at the GPU's positions (1e-5 relative).
 * Graph replay: 192 steps with graph-replayed blocks and the same steps
   taken eagerly give bit-identical positions and velocities.
+* The 64-replica sweep at its full size: sampled replicas against the
+  oracle (trajectory and forces).
 """
 import numpy as np
 import pytest
@@ -123,3 +125,53 @@ def test_full_size_graph_replay_is_bit_identical():
     (r, v, st), (r2, v2, st2) = states
     assert st == st2 == 192
     assert np.array_equal(r, r2) and np.array_equal(v, v2)
+
+
+def test_full_size_batched_sweep_matches_oracle(orc):
+    """The 64-replica sweep in the benchmark's launch configuration for it
+    (193 024 atoms, 808 808 atom-beads per step; skin 1.0 A, FP32 forces,
+    BF16x3 FIR, K = 64, autotuned): four sampled replicas (the smallest, the
+    largest, a 2Nf = 2048 filter at 34 K, 1000 K) follow their own oracle runs
+    for 12 steps; after 192 steps the forces on all atoms of one bead of the
+    largest replica match brute force at the GPU's positions."""
+    works = W.batched_sweep(64)
+    pot = W.mgo_potential(skin=1.0)
+    inputs, reps = [], []
+    for w in works:
+        beads, sp, box = W.crystal_inputs(w)
+        inputs.append((beads, sp, box))
+        reps.append(qtb.Replica(pos=beads, species=sp, T=w.T, gamma=w.gamma, dt=w.dt,
+                                noise=w.noise, box=tuple(box), seed=w.seed, stream=w.stream))
+    ctx = qtb.Context(qtb.pair_potential_dict(pot), reps, W.METAL_UNITS, prec=qtb.PREC_FP32,
+                      fir=qtb.FIR_BF16X3, fir_block_K=K, obs_every=0,
+                      max_two_nf=max(w.two_nf for w in works))
+    for k, w in enumerate(works):
+        if w.noise:
+            ctx.build_filter(k, w.noise, w.two_nf)
+    ctx.step(12)
+    U = oracle_units(orc, False)
+    opot = oracle_pair_pot(orc, pot)
+    for k in (9, 28, 2, 47):
+        w = works[k]
+        beads, sp, box = inputs[k]
+        P, N = beads.shape[0], beads.shape[2]
+        sim = orc.Sim(opot, U, N, P, 3, box, sp, w.T, w.gamma, w.dt, w.seed, w.stream, w.noise,
+                      w.two_nf, beads, n_threads=16)
+        sim.run(12)
+        ro, _, _, sto = sim.state()
+        del sim
+        r, _, st = ctx.get_state(k)
+        assert st == sto == 12
+        rel = np.sqrt(np.mean((r - ro) ** 2)) / 0.0421
+        print(f"replica {k} ({N} atoms x {P}, {w.T:.0f} K): 12-step position difference {rel:.2e}")
+        assert rel <= 1e-5, k
+    for n in (52, 64, 64):
+        ctx.step(n)
+    r, _, st = ctx.get_state(28)
+    assert st == 192
+    f, _ = ctx.evaluate(28)
+    _, fo, _ = orc.pair_bruteforce(opot, U, inputs[28][2], inputs[28][1], r[3])
+    rel = np.linalg.norm(f[3] - fo) / np.linalg.norm(fo)
+    print(f"replica 28 bead 3 after 192 steps: force relative difference {rel:.2e}")
+    assert rel <= 1e-5
+    ctx.close()
