@@ -16,6 +16,8 @@ same seeded inputs).
   taken eagerly give bit-identical positions and velocities.
 * The 64-replica sweep at its full size: sampled replicas against the
   oracle (trajectory and forces).
+* The surrogate's 64 000-atom x P = 4 workload: pair and surrogate forces
+  and energies of a tiled crystal against the oracles' small periodic cell.
 """
 import numpy as np
 import pytest
@@ -174,4 +176,51 @@ def test_full_size_batched_sweep_matches_oracle(orc):
     rel = np.linalg.norm(f[3] - fo) / np.linalg.norm(fo)
     print(f"replica 28 bead 3 after 192 steps: force relative difference {rel:.2e}")
     assert rel <= 1e-5
+    ctx.close()
+
+
+def test_full_size_surrogate_crystal_matches_oracle(orc):
+    """The surrogate's production workload at its full size: 20x20x20 cells
+    (64 000 atoms) x P = 4 beads with the surrogate buffers (list kernel,
+    r_ml = 6 A, skin 1.0 A, FP32).  Each bead is the 4x4x4 crystal with its
+    own seeded displacements tiled 5 x 5 x 5 times, so every atom's force is
+    its image's force in the periodic 512-atom crystal, which the oracles
+    compute whole: the pair potential (brute force over all images) and the
+    descriptor network (random weights and normalisation) both within their
+    small-size bars, and the bead energies 125 times the small crystal's."""
+    from oracle import ml_oracle as M
+    from tests.test_gpu_ml import RC, RMIN, make_model
+    P, reps_side = 4, 5
+    pos_s, sp_s, box_s = W.rocksalt(4)
+    small = [W.displaced(pos_s, 0.08, 60 + b) for b in range(P)]
+    shifts = np.array([[ix, iy, iz] for ix in range(reps_side) for iy in range(reps_side)
+                       for iz in range(reps_side)], dtype=np.float64) * np.asarray(box_s)
+    n_s = len(sp_s)
+    big = np.stack([np.concatenate([f + sh[:, None] for sh in shifts], axis=1) for f in small])
+    sp = np.tile(sp_s, len(shifts))
+    box = tuple(reps_side * np.asarray(box_s))
+    pot = W.mgo_potential(skin=1.0)
+    rep = qtb.Replica(pos=big, species=sp, T=300.0, gamma=1e-3, dt=1.0, noise=2, box=box, seed=4)
+    ctx = qtb.Context(qtb.pair_potential_dict(pot), [rep], W.METAL_UNITS, prec=qtb.PREC_FP32,
+                      fir=qtb.FIR_BF16X3, ml_r_cut=RC)
+    assert big.shape == (P, 3, 64000)
+    U = oracle_units(orc, False)
+    opot = oracle_pair_pot(orc, pot)
+    f, e = ctx.evaluate(0)
+    m, used, norm = make_model()
+    fm, em, _, _ = ctx.ml_evaluate(m, 0)
+    for b in range(P):
+        eo, fo, _ = orc.pair_bruteforce(opot, U, box_s, sp_s, small[b])
+        ref = np.tile(fo, (1, len(shifts)))
+        rel = np.linalg.norm(f[b] - ref) / np.linalg.norm(ref)
+        rel_e = abs(e[b] - len(shifts) * eo) / abs(len(shifts) * eo)
+        Eo, Fo, Eat = M.energy_forces(used, norm, small[b], sp_s, box_s, RC, RMIN)
+        refm = np.tile(Fo, (1, len(shifts)))
+        relm = np.linalg.norm(fm[b] - refm) / np.linalg.norm(refm)
+        rel_em = abs(em[b] - len(shifts) * Eo) / (len(shifts) * np.sum(np.abs(Eat)))
+        print(f"bead {b}: pair forces {rel:.2e}, energy {rel_e:.2e}; "
+              f"surrogate forces {relm:.2e}, energy {rel_em:.2e}")
+        assert rel <= 1e-5 and rel_e <= 1e-6
+        assert relm < 2e-5 and rel_em < 2e-5
+    assert n_s * len(shifts) == 64000
     ctx.close()
