@@ -339,9 +339,13 @@ qtb_status qtb_vdos_detach(qtb_ctx *ctx, int32_t replica);
  * p = (2 K + W) / (3 V) the instantaneous virial pressure of the step just
  * closed (K kinetic energy, W = sum over pairs of F(r) r), g a unit Gaussian
  * of the replica's counter-based stream (step n, dof 0, tag 4); positions
- * and box are scaled by s = e^{d eps / 3}, velocities by 1 / s, and the
- * neighbour list is rebuilt at the next step.  Units: P0 in energy / length^3,
- * tau_p in time, beta_T (isothermal compressibility) in length^3 / energy.
+ * and box are scaled by s = e^{d eps / 3}, velocities by 1 / s.  The
+ * neighbour lists follow the box by a scale factor and are rebuilt when the
+ * compression since their build uses up half of the skin.  The list capacity
+ * is planned for the initial density: compressing the box by more than about
+ * 20 % in volume can overflow it (QTB_E_NOMEM at the next synchronising call).
+ * Units: P0 in energy / length^3, tau_p in time, beta_T (isothermal
+ * compressibility) in length^3 / energy.
  *
  * qtb_barostat: enable (enable != 0) or disable the barostat of a replica.
  * QTB_E_INVALID unless the potential is the pair potential, the context has
@@ -349,6 +353,8 @@ qtb_status qtb_vdos_detach(qtb_ctx *ctx, int32_t replica);
  * replica is small enough for the force kernel's own list rebuild, the
  * one-kernel step (QTB_OPT_FUSE) is off, and tau_p, beta_T > 0.  Synchronises.
  * While it runs, every step's force pass also computes the observables.
+ * Switching it off rebuilds the neighbour lists and recomputes the forces of
+ * every replica at the current positions (as qtb_set_state does).
  *
  * qtb_get_box: synchronise and copy the replica's current box lengths
  * (host double[3]); status errors as qtb_observables.

@@ -148,6 +148,9 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
     const T rc2 = tab.rc2, a2l = tab.a2l, s_mul = tab.s_mul, alpha = tab.alpha, g = tab.g;
     gptr<V4> ent = (gptr<V4>)R.nb_entries + (size_t)i * R.maxnb;
     const int cnt = R.nb_count[i];
+    // entries of a list built before the box last changed scale with it
+    // (entries built in this pass, MODE kPosRef, have the current geometry)
+    const T lsc = (T)R.npt_S;
     // three-stage pipeline: entry q+2*ST and the neighbour of entry q+ST
     // are loading while the pair of entry q is evaluated
     int q = ch;
@@ -158,9 +161,20 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
         const int q2 = q + 2 * ST;
         const V4 E2 = ent[q2 < cnt ? q2 : 0];
         const V4 U1 = pp.at(vbits(E1), s);
-        const T dx = (E0.x + ui.x) - U0.x;
-        const T dy = (E0.y + ui.y) - U0.y;
-        const T dz = (E0.z + ui.z) - U0.z;
+        T dx, dy, dz;
+        if constexpr (MODE == kPosRef) {
+            dx = (E0.x + ui.x) - U0.x;
+            dy = (E0.y + ui.y) - U0.y;
+            dz = (E0.z + ui.z) - U0.z;
+        } else if constexpr (sizeof(T) == 4) {  // lsc = 1: the same bits as E + u
+            dx = __builtin_fmaf(E0.x, lsc, ui.x) - U0.x;
+            dy = __builtin_fmaf(E0.y, lsc, ui.y) - U0.y;
+            dz = __builtin_fmaf(E0.z, lsc, ui.z) - U0.z;
+        } else {
+            dx = __builtin_fma(E0.x, lsc, ui.x) - U0.x;
+            dy = __builtin_fma(E0.y, lsc, ui.y) - U0.y;
+            dz = __builtin_fma(E0.z, lsc, ui.z) - U0.z;
+        }
         const T r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < rc2) {
             const int spj = vbits(U0);

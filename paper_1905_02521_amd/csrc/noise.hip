@@ -274,8 +274,8 @@ __global__ void __launch_bounds__(256) k_eq9(const RepDev* __restrict__ reps,
 //   d eps = -(beta_T / tau_p) (P0 - p) dt + sqrt(2 k_B T beta_T dt / (V tau_p)) g,
 // g the unit Gaussian at (replica step n, dof 0, tag 4).  With the
 // diffusion in eps proportional to 1/V this samples V^N e^{-P0 V / k_B T} for
-// an ideal gas.  The box scales by s = e^{d eps / 3}; the list is rebuilt at
-// the next force pass (its reference displacements hold the old box).
+// an ideal gas.  The box scales by s = e^{d eps / 3}; the neighbour lists
+// follow through npt_S (below) until the compression eats into the skin.
 __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int n_rep,
                                                   const double* __restrict__ partials,
                                                   const StepRef sync)
@@ -310,9 +310,20 @@ __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int
         const double sc = exp(deps / 3.0);
         for (int a = 0; a < 3; ++a) R.box[a] *= sc;
         R.npt_s = sc;
-        int64_t f = (n + 2) % 3;  // the next step's force pass rebuilds the list
-        if (f < 0) f += 3;
-        R.rflag[f] = 1;
+        // The lists keep the geometry of their build, scaled by npt_S.  A pair
+        // left out at the build lay beyond r_c + skin, and lies beyond
+        // npt_S (r_c + skin) now: while npt_S < 1 the displacement allowed
+        // before a rebuild shrinks by (1 - npt_S)(r_c + skin) / 2.  Past half
+        // of the skin the next step's force pass rebuilds.
+        int64_t f1 = (n + 1) % 3, f2 = (n + 2) % 3;
+        if (f1 < 0) f1 += 3;
+        if (f2 < 0) f2 += 3;
+        const bool rebuilt = R.rflag[f1] != 0;  // this step's force pass rebuilt
+        const double S = (rebuilt ? 1.0 : R.npt_S) * sc;
+        R.npt_S = S;
+        const double hs = R.half_skin0 - fmax(0.0, 1.0 - S) * 0.5 * R.r_cs;
+        R.half_skin = hs;
+        if (hs < 0.5 * R.half_skin0) R.rflag[f2] = 1;
     }
 }
 

@@ -461,6 +461,7 @@ struct qtb_ctx {
     // one-kernel steps: a step's closing half-kick is pending (open) between
     // the step kernels of one qtb_step call; the call ends with a force pass
     bool open = false;
+    bool npt_used = false;      // a barostat has run: the device table holds the boxes
     std::vector<VdosRec> vdos;  // per replica
     std::vector<double> eq9amp;  // block noise: amplitudes [n_rep][n/2 + 1] (host copy)
     // step of the kernels being recorded: host step (rec_row < 0), or the
@@ -738,6 +739,8 @@ void fill_repdev(qtb_ctx* c, int r)
     d.kT = c->opt.kB * R.T;
     d.omega_P = std::sqrt((double)R.n_beads) * d.kT / c->opt.hbar;
     d.half_skin = 0.5 * c->skin;
+    d.half_skin0 = d.half_skin;
+    d.npt_S = 1.0;
     d.r_cs = c->rc + c->skin;
     for (int a = 0; a < kMaxSpecies; ++a) {
         const double m = a < (int)c->mass.size() ? c->mass[a] * c->opt.mass_unit : 1.0;
@@ -779,33 +782,41 @@ bool npt_any(const qtb_ctx* c)
     return false;
 }
 
-// Under the barostat the device copy of a replica's box is the current one:
-// bring it back to the host tables (synchronises).
+// Once a barostat has run, the device copy of the replica table holds the
+// current boxes, list scales and rebuild thresholds: bring them back to the
+// host tables (synchronises).
 qtb_status sync_boxes(qtb_ctx* c)
 {
-    if (!npt_any(c)) return QTB_OK;
+    if (!c->npt_used) return QTB_OK;
     std::vector<RepDev> dev(c->n_rep);
     QTB_HIP(c, hipMemcpyAsync(dev.data(), c->at<void>(c->L.reps), sizeof(RepDev) * c->n_rep,
                               hipMemcpyDeviceToHost, c->st));
     QTB_HIP(c, hipStreamSynchronize(c->st));
     for (int r = 0; r < c->n_rep; ++r) {
-        if (!c->rd[r].npt) continue;
         for (int a = 0; a < 3; ++a) {
             c->rd[r].box[a] = dev[r].box[a];
             c->reps[r].box[a] = dev[r].box[a];
         }
+        c->rd[r].npt_S = dev[r].npt_S;
+        c->rd[r].half_skin = dev[r].half_skin;
     }
+    return QTB_OK;
+}
+
+// Host tables to the device as they are (the caller has synchronised them).
+qtb_status upload_tables_raw(qtb_ctx* c)
+{
+    QTB_HIP(c, hipMemcpyAsync(c->at<void>(c->L.reps), c->rd.data(), sizeof(RepDev) * c->n_rep,
+                              hipMemcpyHostToDevice, c->st));
+    QTB_HIP(c, hipMemcpyAsync(c->at<void>(c->L.tiles), c->L.tilev.data(),
+                              sizeof(FirTile) * c->L.tilev.size(), hipMemcpyHostToDevice, c->st));
     return QTB_OK;
 }
 
 qtb_status upload_tables(qtb_ctx* c)
 {
     if (qtb_status s = sync_boxes(c)) return s;
-    QTB_HIP(c, hipMemcpyAsync(c->at<void>(c->L.reps), c->rd.data(), sizeof(RepDev) * c->n_rep,
-                              hipMemcpyHostToDevice, c->st));
-    QTB_HIP(c, hipMemcpyAsync(c->at<void>(c->L.tiles), c->L.tilev.data(),
-                              sizeof(FirTile) * c->L.tilev.size(), hipMemcpyHostToDevice, c->st));
-    return QTB_OK;
+    return upload_tables_raw(c);
 }
 
 // Block noise (eq. 9): amplitudes of replica r's Fourier modes on the grid
@@ -917,6 +928,14 @@ void launch_rebuild(qtb_ctx* c, bool centroids = false)
 
 qtb_status refresh_forces(qtb_ctx* c)
 {
+    if (c->npt_used) {  // every list is rebuilt from the current geometry
+        if (qtb_status s = sync_boxes(c)) return s;
+        for (auto& d : c->rd) {
+            d.npt_S = 1.0;
+            d.half_skin = d.half_skin0;
+        }
+        if (qtb_status s = upload_tables_raw(c)) return s;
+    }
     if (c->pair) {
         launch_mark_rebuild(c->st, c->at<RepDev>(c->L.reps), c->n_rep, c->at<int32_t>(c->L.status),
                             step_ref(c));
@@ -1841,6 +1860,7 @@ qtb_status qtb_barostat(qtb_ctx* c, int32_t replica, double P0, double tau_p, do
     QTB_HIP(c, hipStreamSynchronize(c->st));
     if (qtb_status s = sync_boxes(c)) return s;
     RepDev& d = c->rd[replica];
+    if (enable) c->npt_used = true;
     d.npt = enable ? 1 : 0;
     d.npt_P0 = enable ? P0 : 0.0;
     d.npt_tau = enable ? tau_p : 0.0;
@@ -1849,8 +1869,11 @@ qtb_status qtb_barostat(qtb_ctx* c, int32_t replica, double P0, double tau_p, do
     drop_graph(c);  // the step sequence changes
     qtb_status s = upload_tables(c);
     if (s) return s;
+    // switched off: nothing follows the lists' scale any more, so they are
+    // rebuilt from the current geometry (forces recomputed there)
+    if (!enable && d.npt_S != 1.0 && (s = refresh_forces(c))) return s;
     QTB_HIP(c, hipStreamSynchronize(c->st));
-    return QTB_OK;
+    return read_status(c);
 }
 
 qtb_status qtb_get_box(qtb_ctx* c, int32_t replica, double* h_box)

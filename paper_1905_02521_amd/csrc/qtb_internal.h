@@ -78,6 +78,8 @@ struct RepDev {
     int32_t N, P, dims, maxnb;
     int32_t two_nf, noise, obs_block0, obs_nblocks;
     double box[3];
+    // half_skin: the displacement from the reference that triggers a list
+    // rebuild (lowered under the barostat while the box is compressed)
     double c1, kT, omega_P, half_skin, r_cs;  // r_cs = r_cut + skin
     double kick[kMaxSpecies];   // dt / (2 P m mu)
     double sigma[kMaxSpecies];  // sqrt((1 - c1^2) / (m mu))
@@ -117,6 +119,12 @@ struct RepDev {
     double npt_P0, npt_tau, npt_beta;  // target pressure, relaxation time, compressibility
     double npt_s;                      // this step's length scale factor
     double dt;
+    // length scale of the box relative to the last list build (1 without a
+    // barostat): list entries and reference centroids keep the geometry of
+    // the build; a pair's displacement is npt_S * entry + u_i - u_j with
+    // u = r - npt_S * reference
+    double npt_S;
+    double half_skin0;                 // half the skin
 };
 
 // ------------------------------------------------ descriptor-MLP surrogate

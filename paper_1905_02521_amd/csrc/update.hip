@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
             double u3[3], u2 = 0.0, d2 = 0.0;
             for (int a2 = 0; a2 < 3; ++a2) {
                 const double x = xr[(a2 * P + s) * A + il];
-                u3[a2] = x - ref3[a2];
+                u3[a2] = __builtin_fma(-R.npt_S, ref3[a2], x);  // npt_S = 1: x - ref
                 const double dc = x - cen[il][a2];
                 u2 = nm_acc(u2, u3[a2], u3[a2]);
                 d2 = nm_acc(d2, dc, dc);

@@ -34,15 +34,21 @@ def _gpu():
     qtb.lib()
 
 
-def test_barostat_trajectory_matches_oracle(orc):
+@pytest.mark.parametrize("P0", [0.0, 0.2])   # eV/A^3: expansion; compression
+def test_barostat_trajectory_matches_oracle(orc, P0):
+    """Skin 0.3 A: the lists follow the box through their scale factor, and
+    under P0 = 0.2 the compression (a few per cent in length) eats into the
+    skin past half of it, so that the force pass rebuilds them (the oracle
+    rebuilds at every step)."""
     beads, sp, box = crystal(3, 1, seed=7)
+    pot = W.mgo_potential(skin=0.3)
     T, gamma, dt, seed, two_nf = 300.0, 5e-3, 1.0, 13, 256
-    P0, tau_p, beta_T = 0.0, 20.0, 0.5   # eV/A^3, fs, A^3/eV
+    tau_p, beta_T = 20.0, 0.5   # fs, A^3/eV
     ctx = gpu_crystal_ctx(beads, sp, box, T=T, gamma=gamma, dt=dt, noise=1, prec=qtb.PREC_FP64,
-                          fir=qtb.FIR_FP64, seed=seed, max_two_nf=two_nf, obs_every=4)
+                          fir=qtb.FIR_FP64, seed=seed, max_two_nf=two_nf, obs_every=4, pot=pot)
     ctx.build_filter(0, 1, two_nf)
     ctx.barostat(0, P0, tau_p, beta_T)
-    osim = orc.Sim(oracle_pair_pot(orc), oracle_units(orc, False), beads.shape[2], 1, 3, box, sp,
+    osim = orc.Sim(oracle_pair_pot(orc, pot), oracle_units(orc, False), beads.shape[2], 1, 3, box, sp,
                    T, gamma, dt, seed, 0, 1, two_nf, beads, n_threads=8)
     osim.set_barostat(P0, tau_p, beta_T)
     ip = orc.OBS_NAMES.index("pressure")
@@ -61,6 +67,7 @@ def test_barostat_trajectory_matches_oracle(orc):
         assert np.sqrt(np.mean((r - ro) ** 2)) <= 1e-9 * 0.0421
         assert np.sqrt(np.mean((v - vo) ** 2)) <= 1e-9 * np.sqrt(np.mean(vo ** 2))
     assert abs(b[0] / box[0] - 1.0) > 2e-3          # the box did move
+    assert (b[0] > box[0]) == (P0 == 0.0)
     g = ctx.observables(0)
     o = np.concatenate(obs_o)
     assert g["n_samples"] == len(o) == 32
