@@ -35,3 +35,35 @@ def test_ideal_gas_volume_distribution(orc):
           f"sd/mean {vols.std() / vols.mean():.3f} (exact {1 / math.sqrt(N + 1):.3f})")
     assert abs(m - V_target) < 4 * se
     assert abs(vols.std() / vols.mean() * math.sqrt(N + 1) - 1) < 0.25
+
+
+def test_zero_temperature_relaxation_is_the_euler_map(orc):
+    """At T = 0 the noise vanishes and a perfect rock-salt lattice stays
+    perfect (its forces cancel by symmetry, the velocities stay zero), so the
+    box follows the deterministic map L_{n+1} = L_n exp(-(beta_T / tau_p)
+    (P0 - W(L_n) / (3 L_n^3)) dt / 3), with the pair virial W taken here from
+    the trace of the brute-force virial tensor of the scaled lattice.  The
+    oracle's box must follow that map step by step: the sign of the drift,
+    the 1/3 of the length scale and the pressure's virial term all enter."""
+    from paper_1905_02521_amd import workloads as W
+    from tests.gpu_common import oracle_pair_pot
+    pos, sp, box = W.rocksalt(3, 4.21)
+    U = oracle_units(orc, False)
+    pot = oracle_pair_pot(orc)
+    P0, tau, beta, dt = 0.01, 20.0, 0.5, 1.0
+    sim = orc.Sim(pot, U, pos.shape[1], 1, 3, box, sp, 0.0, 1e-3, dt, 3, 0, 0, 2, pos[None],
+                  n_threads=8)
+    sim.set_barostat(P0, tau, beta)
+    L = float(box[0])
+    for _ in range(12):
+        s = L / box[0]
+        _, _, vir = orc.pair_bruteforce(pot, U, np.asarray(box) * s, sp, pos * s)
+        p = np.trace(vir) / (3 * L ** 3)
+        L *= math.exp(-(beta / tau) * (P0 - p) * dt / 3.0)
+        sim.run(1)
+        b = sim.box()
+        assert abs(b[0] - L) <= 1e-12 * L, (b[0], L)
+    r, v, _, _ = sim.state()
+    assert np.max(np.abs(v)) < 1e-9
+    print(f"box after 12 steps: {L:.10f} (start {box[0]:.4f}), static pressure {p:.5f} eV/A^3")
+    assert abs(L / box[0] - 1) > 1e-4   # the lattice did relax
