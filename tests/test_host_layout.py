@@ -1,0 +1,101 @@
+"""Host logic of the C ABI, on the CPU (no device call): qtb_workspace_bytes
+checks the description (0 for anything qtb_init would reject with
+QTB_E_INVALID) and plans the workspace.  The replica's device pointers are
+only tested for NULL here, so stand-in addresses are enough."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from paper_1905_02521_amd import qtb, workloads as W
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(qtb.LIB_PATH):
+        pytest.skip("libqtb.so not built")
+    return qtb.lib()
+
+
+def describe(reps, *, pot=None, prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3, K=64, max_two_nf=512,
+             flags=0, ml_r_cut=0.0):
+    """ctypes structures for a pair-potential description; reps: list of
+    dicts (N, P, dims, T, box, species, noise)."""
+    p = pot or W.mgo_potential(skin=0.4)
+    d = qtb.pair_potential_dict(p)
+    keep = []
+    arr = lambda x: keep.append(np.ascontiguousarray(x, dtype=np.float64)) or keep[-1]
+    P = qtb.qtb_potential()
+    P.kind, P.n_species = qtb.POT_PAIR, len(d["mass"])
+    P.mass = qtb._pd(arr(d["mass"]))
+    P.charge, P.buck_A, P.buck_rho, P.buck_C = (qtb._pd(arr(d[k]))
+                                                for k in ("charge", "buck_A", "buck_rho", "buck_C"))
+    P.dsf_alpha, P.r_cut, P.skin = d["dsf_alpha"], d["r_cut"], d["skin"]
+    R = (qtb.qtb_replica * max(len(reps), 1))()
+    for k, r in enumerate(reps):
+        sp = np.ascontiguousarray(r["species"], dtype=np.int32)
+        keep.append(sp)
+        R[k].n_atoms, R[k].n_beads, R[k].n_dims, R[k].noise = r["N"], r["P"], r.get("dims", 3), r.get("noise", 1)
+        for a in range(3):
+            R[k].box[a] = r["box"][a]
+        R[k].T, R[k].gamma, R[k].dt = r.get("T", 100.0), 1e-3, 1.0
+        R[k].species = sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        R[k].d_pos = R[k].d_vel = 0x100000   # never dereferenced by the host plan
+    o = qtb.qtb_options()
+    U = W.METAL_UNITS
+    o.hbar, o.kB, o.coulomb_k, o.mass_unit = U["hbar"], U["kB"], U.get("coulomb_k", 0.0), U["mass_unit"]
+    o.prec, o.fir, o.fir_block_K, o.max_two_nf, o.flags, o.ml_r_cut = prec, fir, K, max_two_nf, flags, ml_r_cut
+    return P, R, len(reps), o, keep
+
+
+def crystal_rep(n_cells, P, **kw):
+    pos, sp, box = W.rocksalt(n_cells)
+    return dict(N=len(sp), P=P, box=box, species=sp, **kw)
+
+
+def nbytes(L, reps, **kw):
+    P, R, n, o, keep = describe(reps, **kw)
+    return L.qtb_workspace_bytes(ctypes.byref(P), R, n, ctypes.byref(o))
+
+
+def test_benchmark_workspace_size(L):
+    """4096 atoms x P = 8, 512 taps, BF16x3: about a quarter of a gigabyte,
+    dominated by the white-noise ring (576 rows x 98 304 columns x 4 B)."""
+    b = nbytes(L, [crystal_rep(8, 8)])
+    ring = 576 * 98304 * 4
+    print(f"workspace {b / 1e9:.3f} GB, ring {ring / 1e9:.3f} GB")
+    assert ring < b < 2 * ring
+    assert b % 256 == 0
+
+
+def test_workspace_grows_with_the_work(L):
+    b1 = nbytes(L, [crystal_rep(4, 1)])
+    b4 = nbytes(L, [crystal_rep(4, 4)])
+    b_big = nbytes(L, [crystal_rep(6, 4)])
+    b_two = nbytes(L, [crystal_rep(4, 4), crystal_rep(4, 4)])
+    assert 0 < b1 < b4 < b_big and b4 < b_two
+    assert nbytes(L, [crystal_rep(4, 1)], max_two_nf=2048) > b1
+
+
+@pytest.mark.parametrize("change", [
+    dict(rep=dict(N=0)), dict(rep=dict(P=0)), dict(rep=dict(P=65)), dict(rep=dict(dims=1)),
+    dict(rep=dict(T=0.0)), dict(rep=dict(noise=3)), dict(rep=dict(box=(0.0, 16.84, 16.84))),
+    dict(rep=dict(species="bad")), dict(opt=dict(K=32)), dict(opt=dict(max_two_nf=511)),
+    dict(opt=dict(max_two_nf=8192)), dict(opt=dict(prec=qtb.PREC_FP64)),
+    dict(opt=dict(flags=qtb.OPT_NOISE_BLOCKS, max_two_nf=768)),
+    dict(opt=dict(flags=qtb.OPT_NOISE_BLOCKS | qtb.OPT_FUSE)),
+    dict(opt=dict(ml_r_cut=12.0)), dict(n_rep=0)])
+def test_rejected_descriptions_plan_nothing(L, change):
+    rep = crystal_rep(4, 1)
+    assert nbytes(L, [rep]) > 0
+    r = dict(rep)
+    for k, v in change.get("rep", {}).items():
+        if k == "species":
+            sp = np.array(rep["species"])
+            sp[7] = 5   # beyond the two species
+            r["species"] = sp
+        else:
+            r[k] = v
+    reps = [] if change.get("n_rep") == 0 else [r]
+    assert nbytes(L, reps, **change.get("opt", {})) == 0
