@@ -568,7 +568,8 @@ def main():
                     help="qtb-vs-pimd: measured blocks of 1000 steps per method")
     ap.add_argument("--skin", type=float, default=None,
                     help="Verlet skin (A); default 0.4 for one crystal (fastest measured), "
-                         "1.0 for the sweep (hot replicas)")
+                         "1.3 for the sweep (hot replicas: measured 0.5-1.6, best 1.3-1.45), "
+                         "1.0 for the surrogate")
     ap.add_argument("--profile-steps", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -590,7 +591,8 @@ def main():
 
     torch.cuda.set_device(0)
     if a.skin is None:
-        a.skin = 1.0 if (a.workload.startswith("batched") or a.workload.startswith("surrogate")) else 0.4
+        a.skin = (1.3 if a.workload.startswith("batched") else
+                  1.0 if a.workload.startswith("surrogate") else 0.4)
     if a.workload == "qtb-vs-pimd":
         return pimd_compare_bench(a)
     if a.workload == "vdos":
