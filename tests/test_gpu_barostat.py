@@ -10,8 +10,8 @@ the lattice parameters of Sec. 2.2, Fig. 6).
   freezes the box again.  Beside it, constant-volume replicas of the same
   context (QTB-PIMD and classical) still follow their oracle runs.
 * Statistics: at P0 = 0 the mean lattice parameter of 512-atom crystals
-  (production precision; classical Langevin at 300 K, QTB at 50 K for two
-  isotopes) agrees with the zero of the constant-volume equation of state
+  (production precision; classical Langevin and QTB at 50 and 300 K, QTB at
+  50 K for a second isotope) agrees with the zero of the constant-volume equation of state
   p(a) measured by the equation-of-state test of the same potential and
   settings, and so does the isotope shift.
 """
@@ -148,9 +148,10 @@ def test_barostat_rejected_where_unsupported():
 
 # zeros of the constant-volume p(a) (same potential, precision, dt, gamma
 # and filter length) with their standard errors, from the equation-of-state
-# scan: 24Mg16O classical at 300 K and QTB at 50 K, 26Mg18O QTB at 50 K
+# scan: 24Mg16O classical and QTB at 50 and 300 K, 26Mg18O QTB at 50 K
 LIGHT, HEAVY = (23.985, 15.995), (25.983, 17.999)
-EOS_A = {(LIGHT, 0, 300.0): (4.24713, 6e-5), (LIGHT, 1, 50.0): (4.24768, 5e-5),
+EOS_A = {(LIGHT, 0, 50.0): (4.23092, 1e-5), (LIGHT, 0, 300.0): (4.24713, 6e-5),
+         (LIGHT, 1, 50.0): (4.24768, 5e-5), (LIGHT, 1, 300.0): (4.25493, 8e-5),
          (HEAVY, 1, 50.0): (4.24660, 7e-5)}
 EOS_SHIFT_50K = (1.08e-3, 0.09e-3)   # QTB 24Mg16O minus 26Mg18O at 50 K
 
