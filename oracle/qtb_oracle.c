@@ -675,7 +675,14 @@ void orc_sim_free(orc_sim *s)
 
 /* eq. (5) primitive estimator with instantaneous momenta, plus the centroid
  * virial estimator, kinetic temperature and mean square displacement from the
- * initial positions; for the pair potential the pressure by the primitive
+ * initial positions.  The centroid virial estimator replaces the kinetic
+ * energy of the P - 1 internal ring modes by minus half the centroid virial,
+ *   E_vir = K_c - (1/2P) sum_s (r_s - r_c) . F_s + (1/P) sum_s V(r_s),
+ * with K_c = sum_i (1/2) m P |v_c,i|^2 the kinetic energy of the centroid
+ * (normal mode k = 0) measured from the instantaneous velocities: k_B T / 2
+ * per dof under white noise, kappa_P(omega / sqrt(P)) / 2 under the QTB-PIMD
+ * noise of eq. (12), so that a harmonic oscillator gives theta exactly by
+ * eq. (10).  For the pair potential the pressure by the primitive
  * (thermodynamic) estimator, the volume derivative of the ring-polymer
  * partition function with the instantaneous momenta standing in for
  * N P dims k_B T:  p = (2 K - 2 U_spring + (1/P) sum_s W_s) / (3 V), with
@@ -685,7 +692,15 @@ void orc_sim_observe(orc_sim *s, double *o)
     int N = s->N, P = s->P, dims = s->dims;
     double mu = s->u.mass_unit;
     double wP = sqrt((double)P) * s->u.kB * s->T / s->u.hbar;
-    double ke = 0.0, spring = 0.0, x2 = 0.0, vir = 0.0;
+    double ke = 0.0, spring = 0.0, x2 = 0.0, vir = 0.0, kec = 0.0;
+    for (int d = 0; d < dims; ++d)
+        for (int i = 0; i < N; ++i) {
+            double m = s->pot.mass[s->species[i]] * mu;
+            double vc = 0.0;
+            for (int b = 0; b < P; ++b) vc += s->v[((size_t)b * dims + d) * N + i];
+            vc /= P;
+            kec += 0.5 * m * P * vc * vc;
+        }
     for (int b = 0; b < P; ++b)
         for (int d = 0; d < dims; ++d)
             for (int i = 0; i < N; ++i) {
@@ -706,12 +721,11 @@ void orc_sim_observe(orc_sim *s, double *o)
             }
     double U = 0.0;
     for (int b = 0; b < P; ++b) U += s->epot[b] / P;
-    double kT = s->u.kB * s->T;
     o[0] = ke;
     o[1] = U;
     o[2] = spring;
     o[3] = ke - spring + U;
-    o[4] = 0.5 * dims * N * kT - vir / (2.0 * P) + U;
+    o[4] = kec - vir / (2.0 * P) + U;
     o[5] = 2.0 * ke / (dims * (double)N * P * s->u.kB);
     o[6] = x2 / ((double)dims * N * P);
     o[7] = (double)s->step;

@@ -86,6 +86,30 @@ def ho_energy_discrete(omega, m, P, kT, hbar, gamma, dt, taps):
     return E, x2 / P, ke
 
 
+def ho_virial_discrete(omega, m, P, kT, hbar, gamma, dt, taps):
+    """Exact stationary <E_vir> of the same scheme for a 1D harmonic oscillator.
+
+    For V = m w^2 x^2 / 2 the centroid virial estimator is, state by state,
+    K_c + (m w^2 / 2) x_c^2 + (m w^2 / P) sum_s (x_s - x_c)^2, with K_c the
+    kinetic energy of the centroid mode.  In normal modes (q_0 = sqrt(P) x_c,
+    sum_{k>0} q_k^2 = sum_s (x_s - x_c)^2) its mean is
+    m <v_0^2> / 2 + (m w^2 / 2P) <q_0^2> + (m w^2 / P) sum_{k>0} <q_k^2>,
+    each moment the exact stationary one of the mode's linear map."""
+    c1 = math.exp(-gamma * dt)
+    sigma = math.sqrt((1 - c1 * c1) / m)
+    wP = math.sqrt(P) * kT / hbar
+    E = 0.0
+    for k in range(P):
+        wf = 2 * wP * math.sin(math.pi * k / P)
+        M, b = baoab_mode_map(omega * omega / P, wf, c1, sigma, dt)
+        S = stationary_moments(M, b, taps)
+        if k == 0:
+            E += 0.5 * m * S[1, 1] + 0.5 * m * omega * omega / P * S[0, 0]
+        else:
+            E += m * omega * omega / P * S[0, 0]
+    return E
+
+
 # ------------------------------------------------------------ anharmonic 1D
 def morse_potential(x, V0, d):
     return V0 * (1.0 - np.exp(-x / d)) ** 2
