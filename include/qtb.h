@@ -143,7 +143,8 @@ typedef struct {
     int32_t fir;               /* qtb_fir                                        */
     int32_t fir_block_K;       /* steps per noise block: multiple of 64, >= 64   */
     int32_t obs_every;         /* sample observables every n steps (0 = never)   */
-    int32_t max_two_nf;        /* largest FIR length any replica will use        */
+    int32_t max_two_nf;        /* largest FIR length any replica will use, a     */
+                               /* power of two in [2, 8192]                      */
     int32_t flags;             /* QTB_OPT_* bits                                 */
     double ml_r_cut;           /* > 0: reserve the surrogate's buffers for this  */
                                /* descriptor cut-off (<= r_cut); 0: none         */
@@ -181,12 +182,14 @@ typedef struct {
 /* Means over the samples taken since the previous qtb_observables call of
  * this replica (eq. 5 primitive estimator with instantaneous momenta). */
 typedef struct {
-    int64_t step;              /* step counter at the call                        */
+    int64_t step;              /* the replica's step counter at the call (as get_state) */
     double kinetic;            /* sum_s sum_i p^2 / 2m                            */
     double potential;          /* sum_s V(r^(s)) / P                              */
     double spring;             /* sum_s sum_i m omega_P^2 (r_s - r_s+1)^2 / 2     */
     double e_primitive;        /* kinetic - spring + potential (eq. 5)            */
-    double e_virial;           /* centroid virial estimator (dims N k_B T / 2 + ...) */
+    double e_virial;           /* centroid virial estimator: K_c - sum_s (r_s - r_c).F_s */
+                               /* / 2P + potential, K_c = sum_i m P |v_c,i|^2 / 2 the    */
+                               /* measured centroid (mode k = 0) kinetic energy          */
     double t_kinetic;          /* 2 kinetic / (dims N P k_B)                      */
     double x2_mean;            /* mean of (r - r(init))^2 over beads, dims, atoms */
     double virial_pair;        /* sum_s W_s, W_s = sum over pairs of F(r) r at bead s */
@@ -221,12 +224,23 @@ qtb_status qtb_init(qtb_ctx **out, const qtb_potential *pot, const qtb_replica *
  * solving eq. 10-11), sampled on omega_j = pi j / (Nf dt), j = 0..Nf: the
  * taps are the 2Nf-point inverse DFT of sqrt(S_j), so the realised noise
  * spectrum equals S on that grid.  FP64 on the host, then copied to the
- * device in the precision of the FIR mode.  two_nf: even, 2..max_two_nf.
+ * device in the precision of the FIR mode.  two_nf: a power of two in
+ * [2, max_two_nf], else QTB_E_INVALID.
  * taps_out (nullable, host, [two_nf]) receives h_k for k = -Nf..Nf-1.
  * kind must equal the replica's noise.
  */
 qtb_status qtb_build_filter(qtb_ctx *ctx, int32_t replica, int32_t kind, int32_t two_nf,
                             double *taps_out);
+
+/* The same FIR design without a context, on the host only (no device
+ * call): the taps h_k, k = -Nf..Nf-1, of kind CLASSICAL (sqrt(k_B T) at
+ * k = 0), QTB (theta of eq. 1) or QTB_PIMD (kappa_P of eq. 10-11 for n_beads
+ * beads) at temperature T and step dt, in the caller's units (hbar, kB).
+ * two_nf: a power of two in [2, 8192]; n_beads in [1, 64]; taps_out: host
+ * [two_nf], caller-owned.  QTB_E_INVALID on a bad argument (nothing
+ * written), QTB_E_NONFINITE if the design overflowed. */
+qtb_status qtb_filter_taps(int32_t kind, double T, int32_t n_beads, double dt, int32_t two_nf,
+                           double hbar, double kB, double *taps_out);
 
 /* Enqueue n_steps integrator steps of every replica; returns without waiting. */
 qtb_status qtb_step(qtb_ctx *ctx, int64_t n_steps);
@@ -239,8 +253,13 @@ qtb_status qtb_step(qtb_ctx *ctx, int64_t n_steps);
 qtb_status qtb_observables(qtb_ctx *ctx, int32_t replica, qtb_obs *out);
 
 /* Copy a replica's state to / from host arrays [P][n_dims][N]; set_state
- * also sets the replica's step counter, rebuilds its neighbour list and
- * recomputes its forces.  Either pointer may be NULL (that half unchanged). */
+ * also sets the replica's step counter, rebuilds its neighbour list,
+ * recomputes its forces and opens a new noise block at that step.  Either
+ * pointer may be NULL (that half unchanged).  Positions, velocities and the
+ * step are the whole state of a replica: a context created from a
+ * checkpoint taken with get_state (same seed, stream, filter and options)
+ * continues bit for bit like the context that set the same checkpoint back
+ * with set_state. */
 qtb_status qtb_get_state(qtb_ctx *ctx, int32_t replica, double *h_pos, double *h_vel,
                          int64_t *step);
 qtb_status qtb_set_state(qtb_ctx *ctx, int32_t replica, const double *h_pos,

@@ -24,6 +24,13 @@ CFLAGS = ["-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
           "-fno-fast-math", "-mavx2", "-mfma", "-std=c11"]
 
 
+# AddressSanitizer and UndefinedBehaviorSanitizer build of the same source,
+# loaded instead of liboracle.so when QTB_ORACLE_LIB names it (a Python
+# process that preloads gcc's libasan; see tests/test_sanitizers.py).
+SAN_FLAGS = ["-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=undefined",
+             "-fno-omit-frame-pointer", "-g"]
+
+
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (always, when force=True)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -31,6 +38,14 @@ def build(force: bool = False) -> str:
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_sanitized(out_dir: str) -> str:
+    """Compile the oracle with the sanitizers into out_dir; returns the path."""
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "liboracle_san.so")
+    subprocess.check_call(["gcc", *CFLAGS, *SAN_FLAGS, "-o", out, _SRC, "-lm"])
+    return out
 
 
 class Units(ctypes.Structure):
@@ -67,7 +82,8 @@ _PP = ctypes.POINTER(Pot)
 def lib():
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
+        path = os.environ.get("QTB_ORACLE_LIB") or build()
+        _lib = ctypes.CDLL(path)
         L = _lib
         L.orc_theta.restype = _D
         L.orc_theta.argtypes = [_D, _D, _PU]

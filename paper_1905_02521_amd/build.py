@@ -38,11 +38,19 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *COMMON, *PER_FILE.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
+# Host-code sanitizers (AddressSanitizer, UndefinedBehaviorSanitizer) for a
+# checking build of the same sources: every flag applies to the host pass only
+# (-Xarch_host), the GPU code is compiled as usual.
+SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+       "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    cmd = [hipcc(), *COMMON, *PER_FILE.get(src, []), *extra, "-c", os.path.join(CSRC, src),
+           "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [hipcc(), *[c for c in COMMON if not c.startswith("--offload-arch")],
+        cmd = [hipcc(), *[c for c in COMMON if not c.startswith("--offload-arch")], *extra,
                "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -50,19 +58,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 8, verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int = 8, verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile and link libqtb.so next to this file; sanitize=True instead
+    writes _build/san/libqtb_san.so with the host-code sanitizers (for the
+    CPU tests that load it in a process preloading clang's ASan runtime)."""
+    bdir = os.path.join(BUILD, "san") if sanitize else BUILD
+    out = os.path.join(bdir, "libqtb_san.so") if sanitize else OUT
+    extra = SAN if sanitize else []
+    os.makedirs(bdir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = OUT + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+        objs = list(ex.map(lambda f: _compile(f, bdir, extra), SOURCES))
+    tmp = out + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *extra,
+           *(["-shared-libsan"] if sanitize else []), "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print("built", OUT)
-    return OUT
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -476,7 +476,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (WE ? 5 : 8)))) k_force_
         }
     }
     reduce_atom<G>(fx, fy, fz, e, vir, want_e, W, wave, wsub, lane, part);
-    double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (active && wsub == 0 && lane < G && s < P) {
         const double f[3] = {fx, fy, fz};
         force_epilogue<T>(R, i, s, spi, f, 0.5 * e, flags, ob, vrec);
@@ -573,7 +573,7 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
         }
     }
     reduce_atom<G>(fx, fy, fz, e, vir, want_e, W, wave, wsub, lane, part);
-    double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int my_flags = 0;
     // the atom's wavefront, lanes 0 .. P-1 = beads: wavefront-uniform branch.
     if (active && wsub == 0) {
@@ -594,6 +594,19 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
             if (flags & kSample) ob[5] = 0.5 * vir;
 #pragma unroll
             for (int a = 0; a < 3; ++a) fT[a] = (double)(T)f[a];  // the stored force
+        }
+        if (flags & kSample) {
+            // kinetic energy of the centroid, (1/2) m |sum_s v_s|^2 / P: the
+            // wavefront holds every bead (G = P), lanes >= G hold zeros
+            double ck = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double vs = 0.0;
+#pragma unroll
+                for (int b = 0; b < G; ++b) vs += __shfl(vc[a], b);
+                ck = __builtin_fma(vs, vs, ck);
+            }
+            if (lane == 0) ob[6] = 0.5 * R.mmu[spi] * ck / P;
         }
         const int k = s;  // after the transform this lane holds mode k
         double cw = 0.0, sw = 0.0, ws = 0.0, kick = 0.0, sig = 0.0;
@@ -727,7 +740,7 @@ __global__ void __launch_bounds__(256) k_force_onsite(const RepDev* __restrict__
     const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
     const int i = be.atom0 + threadIdx.x;
     const int N = R.N, P = R.P, dims = R.dims;
-    double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (i < N) {
         const int sp = R.species[i];
         const double m = R.mmu[sp], kick = R.kick[sp];
@@ -790,6 +803,41 @@ __global__ void __launch_bounds__(256) k_force_onsite(const RepDev* __restrict__
     }
 }
 
+// Kinetic energy of the ring-polymer centroids (normal mode k = 0),
+// sum_i (1/2) m_i |sum_s v_i^(s)|^2 / P = sum_i (1/2) m_i P |v_c,i|^2, of
+// replica blockIdx.y in chunks of kCentroidChunk atoms (chunk blockIdx.x);
+// fixed-order sums, one value per chunk into cpart[rep][cchunks].
+__global__ void __launch_bounds__(kCentroidChunk) k_centroid_ke(const RepDev* __restrict__ reps,
+                                                                double* __restrict__ cpart,
+                                                                int cchunks)
+{
+    __shared__ double red[kCentroidChunk / 64];
+    const int r = blockIdx.y;
+    const RepDev& R = reps[r];
+    const int i0 = blockIdx.x * kCentroidChunk;
+    if (i0 >= R.N) return;  // uniform: chunks past the replica's atoms stay unread
+    const int i = i0 + threadIdx.x;
+    double k = 0.0;
+    if (i < R.N) {
+        const int N = R.N, P = R.P, dims = R.dims;
+        for (int a = 0; a < dims; ++a) {
+            double vs = 0.0;
+            for (int b = 0; b < P; ++b) vs += R.vel[((size_t)b * dims + a) * N + i];
+            k = __builtin_fma(vs, vs, k);
+        }
+        k *= 0.5 * R.mmu[R.species[i]] / P;
+    }
+    k = wave_sum(k);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[wave] = k;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kCentroidChunk / 64; ++w) t += red[w];
+        cpart[(size_t)r * cchunks + blockIdx.x] = t;
+    }
+}
+
 // Per replica (one workgroup each): acc += sum of the replica's block
 // partials.  Thread t sums blocks t, t + 256, ... in order, then a fixed
 // tree in LDS: the same order on every run and for a replica alone or in a
@@ -798,13 +846,14 @@ __global__ void __launch_bounds__(256) k_obs_reduce(const RepDev* __restrict__ r
                                                     const double* __restrict__ partials,
                                                     double* __restrict__ acc,
                                                     int32_t* __restrict__ counts, int tick,
-                                                    int pair)
+                                                    int pair, const double* __restrict__ cpart,
+                                                    int cchunks)
 {
     __shared__ double red[kNobs][256];
     const int r = blockIdx.x;
     if (r >= n_rep) return;
     const RepDev& R = reps[r];
-    double t[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double t[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < R.obs_nblocks; b += blockDim.x)
         for (int q = 0; q < kNobs; ++q) t[q] += partials[(size_t)(R.obs_block0 + b) * kNobs + q];
     for (int q = 0; q < kNobs; ++q) red[q][threadIdx.x] = t[q];
@@ -819,12 +868,18 @@ __global__ void __launch_bounds__(256) k_obs_reduce(const RepDev* __restrict__ r
     if (threadIdx.x == 0) {
         counts[r] += 1;
         if (tick && R.vt) *R.vt_n += 1;  // the forces of this sample wrote its row
+        if (cpart) {  // centroid kinetic energy, chunks in order
+            double kc = 0.0;
+            const int nc = (R.N + kCentroidChunk - 1) / kCentroidChunk;
+            for (int q = 0; q < nc; ++q) kc += cpart[(size_t)r * cchunks + q];
+            a[6] += kc;
+        }
         if (pair) {
             // volume of this sample's box (it changes under the barostat) and
             // the primitive pressure (2K - 2 U_spring + W / P) / (3V)
             const double V = R.box[0] * R.box[1] * R.box[2];
-            a[6] += V;
-            a[7] += (2.0 * red[0][0] - 2.0 * red[2][0] + red[5][0] / R.P) / (3.0 * V);
+            a[kNobs] += V;
+            a[kNobs + 1] += (2.0 * red[0][0] - 2.0 * red[2][0] + red[5][0] / R.P) / (3.0 * V);
         }
     }
 }
@@ -985,10 +1040,14 @@ void launch_forces_onsite(hipStream_t st, bool fp64, int kind, const RepDev* rep
 }
 
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
-                       double* acc, int32_t* counts, bool tick, bool pair)
+                       double* acc, int32_t* counts, bool tick, bool pair, double* cpart,
+                       int cchunks)
 {
+    if (cpart)
+        launch(k_centroid_ke, dim3(cchunks, n_rep), dim3(kCentroidChunk), 0, st, reps, cpart,
+               cchunks);
     launch(k_obs_reduce, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, acc, counts,
-           tick ? 1 : 0, pair ? 1 : 0);
+           tick ? 1 : 0, pair ? 1 : 0, (const double*)cpart, cchunks);
 }
 
 void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value)

@@ -841,7 +841,7 @@ __global__ void __launch_bounds__(256) k_ml_gather(const RepDev* __restrict__ re
         fy += __shfl_xor(fy, off);
         fz += __shfl_xor(fz, off);
     }
-    double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (active && lane < G) {
         const int spi = R.species[i];
         const size_t c = (size_t)s * N + i;

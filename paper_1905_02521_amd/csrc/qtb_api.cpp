@@ -39,6 +39,7 @@ struct Region {
 struct Layout {
     size_t total = 0;
     Region reps, status, rebuild, tiles, taps, ring, zeta, partials, acc, counts, pairtab, clock;
+    Region cpart;  // [n_rep][cchunks] centroid kinetic energy per chunk of atoms
     Region eq9amp, eq9tw, eq9mark;  // block noise (eq. 9): amplitudes, twiddles, block markers
     Region blk_upd, blk_nl, blk_force, blk_tb;
     // surrogate (ml_r_cut > 0)
@@ -53,6 +54,7 @@ struct Layout {
     // derived sizes
     int64_t n_cols = 0;
     int R = 0, K = 0, max_two_nf = 0, taps_stride = 0;
+    int cchunks = 1;  // chunks of kCentroidChunk atoms in the largest replica
     bool eq9 = false;  // block noise: zeta is a [2 n][n_cols] ring, n = max_two_nf
     int64_t zeta_rows = 0;
     std::vector<int64_t> dof_off;
@@ -128,8 +130,8 @@ const char* check_inputs(const qtb_potential* pot, const qtb_replica* reps, int 
         if (opt->ml_r_cut > pot->r_cut) return "ml_r_cut must not exceed r_cut";
         if (pot->n_species > 2) return "the surrogate has two species";
     }
-    if (opt->max_two_nf < 2 || (opt->max_two_nf & 1) || opt->max_two_nf > 8192)
-        return "max_two_nf must be even, in [2, 8192]";
+    if (opt->max_two_nf < 2 || (opt->max_two_nf & (opt->max_two_nf - 1)) || opt->max_two_nf > 8192)
+        return "max_two_nf must be a power of two in [2, 8192]";
     if (opt->fir != QTB_FIR_FP64 && opt->max_two_nf > 4096) return "BF16/FP32 FIR: max_two_nf <= 4096";
     if (opt->flags & QTB_OPT_NOISE_BLOCKS) {
         const int n = opt->max_two_nf;
@@ -308,6 +310,12 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     }
     add(cur, L.partials, sizeof(double) * kNobs * L.max_force_blocks);
     add(cur, L.acc, sizeof(double) * kAcc * n_rep);
+    {
+        int32_t nmax = 1;
+        for (int r = 0; r < n_rep; ++r) nmax = std::max(nmax, reps[r].n_atoms);
+        L.cchunks = (nmax + kCentroidChunk - 1) / kCentroidChunk;
+    }
+    add(cur, L.cpart, sizeof(double) * (size_t)L.cchunks * n_rep);
     add(cur, L.counts, sizeof(int32_t) * n_rep);
     add(cur, L.pairtab, sizeof(PairTable<double>));
     add(cur, L.blk_upd, sizeof(BlockEntry) * std::max<size_t>(1, L.upd.size()));
@@ -1027,7 +1035,8 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
     if (sample) {
         Phase ph(c, 5);
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
-                          c->at<int32_t>(L.counts), true, c->pair && !c->ml);
+                          c->at<int32_t>(L.counts), true, c->pair && !c->ml,
+                          c->at<double>(L.cpart), L.cchunks);
     }
     if (npt) {  // after the sample: observables see the box the step ran in
         Phase ph(c, 5);
@@ -1041,7 +1050,8 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
     if (check) {  // the pair potential judges the surrogate on the same positions
         launch_plain_forces(c, kCompare);
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials),
-                          c->at<double>(L.ml_acc), c->at<int32_t>(L.ml_counts), false, false);
+                          c->at<double>(L.ml_acc), c->at<int32_t>(L.ml_counts), false, false,
+                          nullptr, 0);
     }
     c->rec_row = -1;
     c->rec_extra = 0;
@@ -1105,10 +1115,10 @@ void record_fused(qtb_ctx* c, int row, bool sample_prev)
                          c->at<double>(L.partials), c->n_rep, c->at<int32_t>(L.status),
                          step_ref(c), zrow);
     }
-    if (sample_prev) {
+    if (sample_prev) {  // the one-kernel step sums the centroid kinetic energy itself
         Phase ph(c, 5);
         launch_obs_reduce(c->st, dreps, c->n_rep, c->at<double>(L.partials), c->at<double>(L.acc),
-                          c->at<int32_t>(L.counts), true, c->pair && !c->ml);
+                          c->at<int32_t>(L.counts), true, c->pair && !c->ml, nullptr, 0);
     }
     c->rec_row = -1;
 }
@@ -1130,7 +1140,8 @@ void close_steps(qtb_ctx* c)
     if (sample) {
         Phase ph(c, 5);
         launch_obs_reduce(c->st, c->at<RepDev>(L.reps), c->n_rep, c->at<double>(L.partials),
-                          c->at<double>(L.acc), c->at<int32_t>(L.counts), true, c->pair && !c->ml);
+                          c->at<double>(L.acc), c->at<int32_t>(L.counts), true, c->pair && !c->ml,
+                          c->at<double>(L.cpart), L.cchunks);
     }
     c->open = false;
 }
@@ -1508,8 +1519,8 @@ qtb_status qtb_build_filter(qtb_ctx* c, int32_t replica, int32_t kind, int32_t t
     if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
     if (replica < -1 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
     if (kind < 0 || kind > 2) return fail(c, QTB_E_INVALID, "bad noise kind");
-    if (two_nf < 2 || (two_nf & 1) || two_nf > c->opt.max_two_nf)
-        return fail(c, QTB_E_INVALID, "two_nf must be even and in [2, max_two_nf]");
+    if (two_nf < 2 || (two_nf & (two_nf - 1)) || two_nf > c->opt.max_two_nf)
+        return fail(c, QTB_E_INVALID, "two_nf must be a power of two in [2, max_two_nf]");
     if (c->L.eq9 && two_nf != c->opt.max_two_nf)
         return fail(c, QTB_E_INVALID, "block noise: two_nf must equal max_two_nf (the block length)");
     const int r0 = replica < 0 ? 0 : replica, r1 = replica < 0 ? c->n_rep : replica + 1;
@@ -1583,25 +1594,26 @@ qtb_status qtb_observables(qtb_ctx* c, int32_t replica, qtb_obs* out)
     QTB_HIP(c, hipStreamSynchronize(c->st));
     const qtb_replica& R = c->reps[replica];
     std::memset(out, 0, sizeof(*out));
-    out->step = c->step + (int64_t)0;
+    out->step = c->step + c->rd[replica].step_off;  // the replica's own step counter
     out->n_samples = cnt;
     if (cnt > 0) {
         const double inv = 1.0 / cnt;
-        const double kT = c->opt.kB * R.T;
         const double ke = acc[0] * inv, U = acc[1] * inv + (c->ml ? 0.0 : c->eself[replica]),
-                     spr = acc[2] * inv, vir = acc[3] * inv, x2 = acc[4] * inv;
+                     spr = acc[2] * inv, vir = acc[3] * inv, x2 = acc[4] * inv,
+                     kec = acc[6] * inv;
         const double dof = (double)R.n_dims * R.n_atoms;
         out->kinetic = ke;
         out->potential = U;
         out->spring = spr;
         out->e_primitive = ke - spr + U;
-        out->e_virial = 0.5 * dof * kT - vir / (2.0 * R.n_beads) + U;
+        // centroid virial estimator with the measured centroid kinetic energy
+        out->e_virial = kec - vir / (2.0 * R.n_beads) + U;
         out->t_kinetic = 2.0 * ke / (dof * R.n_beads * c->opt.kB);
         out->x2_mean = x2 / (dof * R.n_beads);
         if (c->pair && !c->ml) {
             out->virial_pair = acc[5] * inv;
-            out->volume = acc[6] * inv;
-            out->pressure = acc[7] * inv;
+            out->volume = acc[kNobs] * inv;
+            out->pressure = acc[kNobs + 1] * inv;
         }
     }
     return s;
@@ -1635,11 +1647,14 @@ qtb_status qtb_set_state(qtb_ctx* c, int32_t replica, const double* h_pos, const
     }
     if (h_vel) QTB_HIP(c, hipMemcpyAsync(R.d_vel, h_vel, n, hipMemcpyHostToDevice, c->st));
     const int64_t off = step - c->step;
+    // the next step opens a new noise block at the restored step, as the
+    // first step of a new context would: a state restored from a checkpoint
+    // then continues bit for bit like a context created from it
+    c->ring_valid = false;
+    c->block_start = -1;
+    if (c->L.eq9) launch_eq9_invalidate(c->st, c->at<int64_t>(c->L.eq9mark));
     if (off != c->rd[replica].step_off) {
         c->rd[replica].step_off = off;
-        c->ring_valid = false;
-        c->block_start = -1;
-        if (c->L.eq9) launch_eq9_invalidate(c->st, c->at<int64_t>(c->L.eq9mark));
         qtb_status s = upload_tables(c);
         if (s) return s;
     }
@@ -2254,6 +2269,20 @@ void qtb_destroy(qtb_ctx* c)
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     drop_graph(c);
     delete c;
+}
+
+qtb_status qtb_filter_taps(int32_t kind, double T, int32_t n_beads, double dt, int32_t two_nf,
+                           double hbar, double kB, double* taps_out)
+{
+    if (!taps_out) return QTB_E_INVALID;
+    if (kind < QTB_NOISE_CLASSICAL || kind > QTB_NOISE_QTB_PIMD) return QTB_E_INVALID;
+    if (!(T > 0.0) || !(dt > 0.0) || !(hbar > 0.0) || !(kB > 0.0)) return QTB_E_INVALID;
+    if (n_beads < 1 || n_beads > 64) return QTB_E_INVALID;
+    if (two_nf < 2 || two_nf > 8192 || (two_nf & (two_nf - 1))) return QTB_E_INVALID;
+    design_taps(kind, T, n_beads, dt, two_nf, hbar, kB, taps_out);
+    for (int32_t k = 0; k < two_nf; ++k)
+        if (!std::isfinite(taps_out[k])) return QTB_E_NONFINITE;
+    return QTB_OK;
 }
 
 const char* qtb_version(void) { return "qtb-mi355x 0.1 (gfx950)"; }

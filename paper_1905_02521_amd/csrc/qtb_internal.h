@@ -15,10 +15,13 @@ constexpr int kMaxSpecies = QTB_MAX_SPECIES;
 constexpr int kPairs = kMaxSpecies * kMaxSpecies;
 constexpr int kDofTile = 256;      // replica dof ranges are padded to this
 constexpr int kWavesPerAtomDefault = 2;  // force kernel: wavefronts per atom (1, 2, 4)
-constexpr int kNobs = 6;           // ke, U, spring, virial, x2, pair virial
+// ke, U, spring, virial, x2, pair virial, centroid kinetic energy
+constexpr int kNobs = 7;
 // sample accumulators: the kNobs slots, then (pair potential) volume and the
 // pressure of each sample
-constexpr int kAcc = 8;
+constexpr int kAcc = 9;
+// atoms per chunk of the centroid kinetic-energy sums
+constexpr int kCentroidChunk = 256;
 
 // Pair potential in the form the force kernels evaluate:
 //   F(r) = -dV/dr = Arho e^{-r irho} - C6 r^-7
@@ -331,9 +334,14 @@ void launch_forces_onsite(hipStream_t st, bool fp64, int kind, const RepDev* rep
                           const BlockEntry* blocks, int n_blocks, int32_t flags,
                           double* partials);
 // tick: a sample (advances the velocity recorders), not a surrogate check;
-// pair: the pair potential (the volume and pressure slots are filled)
+// pair: the pair potential (the volume and pressure slots are filled).
+// cpart (may be null): [n_rep][cchunks] scratch; when given, the kinetic
+// energy of the ring-polymer centroids is summed from the velocities first
+// (chunks of kCentroidChunk atoms, max_atoms the largest replica) and added
+// to slot 6; null: slot 6 of the partials already holds it.
 void launch_obs_reduce(hipStream_t st, const RepDev* reps, int n_rep, const double* partials,
-                       double* acc, int32_t* counts, bool tick, bool pair);
+                       double* acc, int32_t* counts, bool tick, bool pair, double* cpart,
+                       int cchunks);
 void launch_fill(hipStream_t st, void* p, int64_t n_words, int32_t value);
 // vdos.hip
 constexpr int kVdosMinSeg = 16, kVdosMaxSeg = 4096;  // samples per segment, powers of two

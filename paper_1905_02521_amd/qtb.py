@@ -89,7 +89,7 @@ EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
            "qtb_observables", "qtb_get_state", "qtb_set_state", "qtb_evaluate",
            "qtb_get_noise", "qtb_gaussian", "qtb_profile", "qtb_profile_read",
            "qtb_vdos_workspace_bytes", "qtb_vdos_spectrum", "qtb_vdos_attach", "qtb_vdos_read",
-           "qtb_vdos_detach", "qtb_barostat", "qtb_get_box",
+           "qtb_vdos_detach", "qtb_barostat", "qtb_get_box", "qtb_filter_taps",
            "qtb_last_error", "qtb_destroy", "qtb_version",
            "qtb_ml_workspace_bytes", "qtb_ml_create", "qtb_ml_init_params", "qtb_ml_set_params",
            "qtb_ml_get_params", "qtb_ml_attach", "qtb_ml_evaluate", "qtb_ml_fit_norm",
@@ -105,10 +105,11 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise OSError(f"{LIB_PATH} not found: build it with "
+    path = os.environ.get("QTB_LIB", LIB_PATH)  # e.g. a host-sanitizer build of the same sources
+    if not os.path.exists(path):
+        raise OSError(f"{path} not found: build it with "
                       "`python -m paper_1905_02521_amd.build`")
-    L = ctypes.CDLL(LIB_PATH)
+    L = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     L.qtb_workspace_bytes.restype = ctypes.c_size_t
     L.qtb_workspace_bytes.argtypes = [ctypes.POINTER(qtb_potential), ctypes.POINTER(qtb_replica),
@@ -134,6 +135,9 @@ def lib():
     L.qtb_gaussian.restype = ctypes.c_int
     L.qtb_gaussian.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                                ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, vp, vp]
+    L.qtb_filter_taps.restype = ctypes.c_int
+    L.qtb_filter_taps.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                  ctypes.c_int32, ctypes.c_double, ctypes.c_double, _PD]
     L.qtb_vdos_workspace_bytes.restype = ctypes.c_size_t
     L.qtb_vdos_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.qtb_vdos_spectrum.restype = ctypes.c_int
@@ -214,6 +218,16 @@ def current_stream_ptr():
 
 
 # ---------------------------------------------------------------- gaussian
+def qtb_filter_taps(kind, T, n_beads, dt, two_nf, hbar, kB):
+    """Host FIR design without a context: taps h_k, k = -Nf..Nf-1 (numpy)."""
+    out = np.zeros(int(two_nf))
+    st = lib().qtb_filter_taps(int(kind), float(T), int(n_beads), float(dt), int(two_nf),
+                               float(hbar), float(kB), _pd(out))
+    if st != QTB_OK:
+        raise QtbError(st, "qtb_filter_taps rejected its arguments")
+    return out
+
+
 def qtb_gaussian(seed, stream, tag, n0, n_rows, d0, n_dof, out=None):
     """Device tensor [n_rows, n_dof] float64 of the library's white noise."""
     torch = _torch()

@@ -102,7 +102,7 @@ def _force_rel(f, ref):
 
 
 @pytest.mark.parametrize("prec,tol", [(qtb.PREC_FP32, 1e-5), (qtb.PREC_FP64, 1e-12)])
-@pytest.mark.parametrize("n_cells,P", [(4, 1), (3, 4), (2, 3), (5, 2)])
+@pytest.mark.parametrize("n_cells,P", [(4, 1), (3, 4), (2, 3), (5, 2), (3, 16), (2, 32)])
 def test_forces_match_bruteforce(orc, prec, tol, n_cells, P):
     beads, sp, box = crystal(n_cells, P, seed=7, bead_spread=0.03)
     fir = qtb.FIR_FP64 if prec == qtb.PREC_FP64 else qtb.FIR_FP32
@@ -127,7 +127,8 @@ def _traj_compare(orc, ctx, osim, n_steps, scale):
     return np.sqrt(np.mean((r - ro) ** 2)) / scale, np.sqrt(np.mean((v - vo) ** 2))
 
 
-@pytest.mark.parametrize("P,noise,two_nf", [(1, 1, 512), (4, 2, 256), (3, 2, 128), (2, 0, 2)])
+@pytest.mark.parametrize("P,noise,two_nf", [(1, 1, 512), (4, 2, 256), (3, 2, 128), (2, 0, 2),
+                                             (16, 2, 128), (32, 0, 2), (32, 2, 128)])
 def test_crystal_trajectory_fp64(orc, P, noise, two_nf):
     n_cells = 3 if P > 1 else 4
     beads, sp, box = crystal(n_cells, P, seed=3, bead_spread=0.02)
@@ -175,7 +176,7 @@ def test_crystal_trajectory_fp32_close(orc):
 
 
 # ------------------------------------------------------------------ observables
-@pytest.mark.parametrize("P,noise", [(1, 1), (4, 2)])
+@pytest.mark.parametrize("P,noise", [(1, 1), (4, 2), (16, 2), (32, 0)])
 def test_observables_match_oracle(orc, P, noise):
     beads, sp, box = crystal(3, P, seed=4, bead_spread=0.02)
     T, gamma, dt = 50.0, 5e-3, 1.0
@@ -216,6 +217,9 @@ def test_invalid_arguments_rejected():
                      fir=qtb.FIR_FP64, max_two_nf=64)
     with pytest.raises(qtb.QtbError) as e:
         ctx.build_filter(0, 1, 128)
+    assert e.value.status == qtb.QTB_E_INVALID
+    with pytest.raises(qtb.QtbError) as e:  # the FIR length is a power of two
+        ctx.build_filter(0, 1, 48)
     assert e.value.status == qtb.QTB_E_INVALID
     with pytest.raises(qtb.QtbError) as e:
         ctx.build_filter(0, 2, 64)
@@ -282,17 +286,20 @@ def test_graph_replay_matches_eager(prec, fir):
     assert np.array_equal(rg, re) and np.array_equal(vg, ve)
 
 
-@pytest.mark.parametrize("prec,tol", [(qtb.PREC_FP64, 1e-9), (qtb.PREC_FP32, 1e-5)])
-def test_trajectory_with_frequent_rebuilds(orc, prec, tol):
+@pytest.mark.parametrize("prec,tol,P", [(qtb.PREC_FP64, 1e-9, 4), (qtb.PREC_FP32, 1e-5, 4),
+                                        (qtb.PREC_FP64, 1e-9, 16), (qtb.PREC_FP32, 1e-5, 32)])
+def test_trajectory_with_frequent_rebuilds(orc, prec, tol, P):
     """A 0.02 A skin forces neighbour-list rebuilds during the run; the
-    trajectory must still follow the oracle (which never misses a pair)."""
-    beads, sp, box = crystal(3, 4, seed=12, bead_spread=0.03)
+    trajectory must still follow the oracle (which never misses a pair).
+    P = 16 and 32 split every atom's beads over several 8-bead groups, each
+    group's workgroup reading the one list the rebuild writes."""
+    beads, sp, box = crystal(3, P, seed=12, bead_spread=0.03)
     p = W.mgo_potential(skin=0.02)
     fir = qtb.FIR_FP64 if prec == qtb.PREC_FP64 else qtb.FIR_FP32
     ctx = gpu_crystal_ctx(beads, sp, box, T=300.0, gamma=2e-3, dt=1.0, noise=2, prec=prec,
                           fir=fir, seed=21, max_two_nf=128, pot=p)
     ctx.build_filter(0, 2, 128)
-    osim = orc.Sim(oracle_pair_pot(orc), oracle_units(orc, False), beads.shape[2], 4, 3, box, sp,
+    osim = orc.Sim(oracle_pair_pot(orc), oracle_units(orc, False), beads.shape[2], P, 3, box, sp,
                    300.0, 2e-3, 1.0, 21, 0, 2, 128, beads, n_threads=8)
     rel, _ = _traj_compare(orc, ctx, osim, 30, scale=0.0421)
     assert rel <= tol, rel
@@ -362,7 +369,11 @@ def test_one_kernel_steps_equal_separate_kernels(P):
         assert s1 == s2 == 121 and o1["n_samples"] == o2["n_samples"] == 15
         if exact:
             assert np.array_equal(r1, r2) and np.array_equal(v1, v2)
-            assert o1 == o2
+            # the centroid kinetic energy of the virial estimator is summed in
+            # the kernel's own order by the one-kernel step: agreement to rounding
+            assert {k: x for k, x in o1.items() if k != "e_virial"} == \
+                {k: x for k, x in o2.items() if k != "e_virial"}
+            assert abs(o1["e_virial"] - o2["e_virial"]) <= 1e-12 * abs(o2["e_virial"])
         else:
             assert np.max(np.abs(r1 - r2)) < 1e-10 and np.max(np.abs(v1 - v2)) < 1e-10
             assert abs(o1["e_primitive"] - o2["e_primitive"]) < 1e-9 * abs(o2["e_primitive"])

@@ -82,7 +82,8 @@ def test_workspace_grows_with_the_work(L):
     dict(rep=dict(N=0)), dict(rep=dict(P=0)), dict(rep=dict(P=65)), dict(rep=dict(dims=1)),
     dict(rep=dict(T=0.0)), dict(rep=dict(noise=3)), dict(rep=dict(box=(0.0, 16.84, 16.84))),
     dict(rep=dict(species="bad")), dict(opt=dict(K=32)), dict(opt=dict(max_two_nf=511)),
-    dict(opt=dict(max_two_nf=8192)), dict(opt=dict(prec=qtb.PREC_FP64)),
+    dict(opt=dict(max_two_nf=8192)), dict(opt=dict(max_two_nf=768)),
+    dict(opt=dict(max_two_nf=6)), dict(opt=dict(prec=qtb.PREC_FP64)),
     dict(opt=dict(flags=qtb.OPT_NOISE_BLOCKS, max_two_nf=768)),
     dict(opt=dict(flags=qtb.OPT_NOISE_BLOCKS | qtb.OPT_FUSE)),
     dict(opt=dict(ml_r_cut=12.0)), dict(n_rep=0)])
