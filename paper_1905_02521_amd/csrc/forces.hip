@@ -106,13 +106,36 @@ struct PairPos {
     }
 };
 
+// Buffer resource over [base, base + bytes) for raw buffer loads: 32-bit
+// byte offsets instead of 64-bit address arithmetic, and loads past the end
+// return zeros.  base and bytes must be uniform over the wavefront.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    const uint64_t a = (uint64_t)base;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const void* b = (const void*)(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(b), (short)0,
+                                             (int)__builtin_amdgcn_readfirstlane(bytes),
+                                             0x00020000);
+}
+__device__ __forceinline__ f4v bload(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+
 // NS: species count rounded up to 2 or 4 (parameters of the centre atom's
 // row are kept in registers and picked per neighbour with selects).
-// FAST (FP32 only): hardware rsq / exp2 and the fitted erfcx polynomial.
+// FAST (FP32 only): hardware rsq / exp2, the Coulomb force shape
+// erfc(x) + (2x/sqrt(pi)) e^{-x^2} = 1 + (r r^2) psi(s) as a polynomial of
+// degree DEG in s = r^2 (2 / r_cut^2) - 1 (no exponential), and for the
+// energy the fitted erfcx polynomial.
 // Force (FP64 sums) and, if want_e, energy and pair virial sum F(r) r of bead
-// s of atom i over the list entries ch, ch + ST, ...; spi receives the atom's
-// species.
-template <typename T, int NS, bool FAST, int DEG, int MODE>
+// s of atom i over its list: the core entries (reference distance below
+// r_cut) at slots 0 .. core - 1, then the shell entries at slots maxnb - 1,
+// maxnb - 2, ...; lane entries ch, ch + ST, ... of each range.  spi
+// receives the atom's species.
+template <typename T, int NS, bool FAST, int DEG, int MODE, int G>
 __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& tab,
                                          const PairPos<T, MODE>& pp, int i, int s, int ch,
                                          int ST, bool want_e, double& fx, double& fy, double& fz,
@@ -135,32 +158,29 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
         pC[b] = q.C;
         pE0[b] = q.E0;
     }
-    // keep the neighbour-species parameters in VGPRs for the whole loop
-    // (selects on gfx950 take at most one SGPR operand)
+    // keep the parameters of neighbour species 1, 2, ... in VGPRs for the
+    // whole loop (a select on gfx950 takes at most one SGPR operand, which
+    // species 0's uniform values use)
 #pragma unroll
-    for (int b = 0; b < NS; ++b) {
+    for (int b = 1; b < NS; ++b) {
         asm volatile("" : "+v"(pArho[b]), "+v"(pirho[b]), "+v"(pC6[b]), "+v"(pkqq[b]),
                      "+v"(pF0[b]));
     }
-    T ex[DEG + 1];
+    T ex[DEG + 1], ph[DEG + 1];
 #pragma unroll
-    for (int k = 0; k <= DEG; ++k) ex[k] = tab.ex[k];
+    for (int k = 0; k <= DEG; ++k) {
+        ex[k] = tab.ex[k];
+        ph[k] = tab.ph[k];
+    }
     const T rc2 = tab.rc2, a2l = tab.a2l, s_mul = tab.s_mul, alpha = tab.alpha, g = tab.g;
-    gptr<V4> ent = (gptr<V4>)R.nb_entries + (size_t)i * R.maxnb;
-    const int cnt = R.nb_count[i];
+    const T ph_s = tab.ph_s;
+    const int maxnb = R.maxnb;
+    const int cnt = R.nb_count[i], ncore = R.nb_core[i];
     // entries of a list built before the box last changed scale with it
     // (entries built in this pass, MODE kPosRef, have the current geometry)
     const T lsc = (T)R.npt_S;
-    // three-stage pipeline: entry q+2*ST and the neighbour of entry q+ST
-    // are loading while the pair of entry q is evaluated
-    int q = ch;
-    V4 E0 = ent[q < cnt ? q : 0];
-    V4 E1 = ent[q + ST < cnt ? q + ST : 0];
-    V4 U0 = pp.at(vbits(E0), s);
-    while (q < cnt) {
-        const int q2 = q + 2 * ST;
-        const V4 E2 = ent[q2 < cnt ? q2 : 0];
-        const V4 U1 = pp.at(vbits(E1), s);
+
+    auto pair = [&](const V4 E0, const V4 U0) {
         T dx, dy, dz;
         if constexpr (MODE == kPosRef) {
             dx = (E0.x + ui.x) - U0.x;
@@ -188,17 +208,25 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                 kqq = m ? pkqq[b] : kqq;
                 F0 = m ? pF0[b] : F0;
             }
-            T rinv, r, e1, e2, ec;
+            T rinv, r, e1, ec = (T)0, e2 = (T)0, Fc;
             if constexpr (FAST) {
                 rinv = __builtin_amdgcn_rsqf(r2);
                 r = r2 * rinv;
                 e1 = __builtin_amdgcn_exp2f(-r * irho);
-                e2 = __builtin_amdgcn_exp2f(-r2 * a2l);
-                const T sx = fmaf(r, s_mul, -1.0f);
-                T pe = ex[DEG];
+                const T sp = fmaf(r2, ph_s, -1.0f);
+                T ps = ph[DEG];
 #pragma unroll
-                for (int k = DEG - 1; k >= 0; --k) pe = fmaf(pe, sx, ex[k]);
-                ec = e2 * pe;
+                for (int k = DEG - 1; k >= 0; --k) ps = fmaf(ps, sp, ph[k]);
+                const T rinv2 = rinv * rinv;
+                Fc = fmaf(r * r2, ps, 1.0f) * rinv2;  // erfc + Gaussian term, over r^2
+                if (want_e) {
+                    e2 = __builtin_amdgcn_exp2f(-r2 * a2l);
+                    const T sx = fmaf(r, s_mul, -1.0f);
+                    T pe = ex[DEG];
+#pragma unroll
+                    for (int k = DEG - 1; k >= 0; --k) pe = fmaf(pe, sx, ex[k]);
+                    ec = e2 * pe;
+                }
             } else {
                 rinv = t_rsqrt(r2);
                 r = r2 * rinv;
@@ -206,10 +234,11 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                 const T x = alpha * r;
                 e2 = t_exp(-x * x);
                 ec = t_erfc(x);
+                Fc = ec * (rinv * rinv) + g * e2 * rinv;
             }
             const T rinv2 = rinv * rinv;
             const T rinv6 = rinv2 * rinv2 * rinv2;
-            const T F = Arho * e1 - C6 * rinv6 * rinv + kqq * (ec * rinv2 + g * e2 * rinv) + F0;
+            const T F = Arho * e1 - C6 * rinv6 * rinv + kqq * Fc + F0;
             const T fr = F * rinv;
             fx += (double)(fr * dx);
             fy += (double)(fr * dy);
@@ -227,10 +256,69 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                 w += (double)(F * r);
             }
         }
-        E0 = E1;
-        E1 = E2;
-        U0 = U1;
-        q += ST;
+    };
+
+    if constexpr (MODE == kPosDirect && sizeof(T) == 4) {
+        // buffer loads with 32-bit byte offsets: entry slot q of atom i at
+        // 16 q, bead s of neighbour j at 16 (j P + s)
+        const __amdgpu_buffer_rsrc_t re =
+            make_rsrc((const char*)R.nb_entries + (size_t)i * maxnb * 16, (uint32_t)maxnb * 16);
+        const __amdgpu_buffer_rsrc_t ru =
+            make_rsrc((const void*)(uintptr_t)pp.u, (uint32_t)(R.N * R.P) * 16u);
+        const uint32_t Pb = (uint32_t)R.P * 16u, sb = (uint32_t)s * 16u;
+        // one range: n entries, lane entries k = ch, ch + ST, ... at slots
+        // first + dir k; three-stage pipeline (entry k + 2 ST and the
+        // neighbour of entry k + ST load while entry k is evaluated)
+        auto uoff = [&](const f4v E) { return __umul24((uint32_t)vbits(E), Pb) + sb; };
+        auto range = [&](int n, int first, int dir) {
+            if (ch >= n) return;
+            const uint32_t dstep = (uint32_t)(dir * ST * 16);
+            uint32_t eo = (uint32_t)(first + dir * ch) * 16u;
+            f4v E0 = bload(re, eo), E1 = bload(re, eo + dstep), E2;
+            f4v U0 = bload(ru, uoff(E0)), U1;
+            int k = ch;
+            // unrolled six times so that the three entry and two neighbour
+            // registers rotate by renaming instead of copies
+#define QTB_PAIR_STEP(Ea, Eb, Ec, Ua, Ub)      \
+    if (k >= n) break;                         \
+    Ec = bload(re, eo + 2 * dstep);            \
+    Ub = bload(ru, uoff(Eb));                  \
+    pair(Ea, Ua);                              \
+    eo += dstep;                               \
+    k += ST;
+            for (;;) {
+                QTB_PAIR_STEP(E0, E1, E2, U0, U1)
+                QTB_PAIR_STEP(E1, E2, E0, U1, U0)
+                QTB_PAIR_STEP(E2, E0, E1, U0, U1)
+                QTB_PAIR_STEP(E0, E1, E2, U1, U0)
+                QTB_PAIR_STEP(E1, E2, E0, U0, U1)
+                QTB_PAIR_STEP(E2, E0, E1, U1, U0)
+            }
+#undef QTB_PAIR_STEP
+        };
+        range(ncore, 0, 1);
+        range(cnt - ncore, maxnb - 1, -1);
+    } else {
+        gptr<V4> ent = (gptr<V4>)R.nb_entries + (size_t)i * maxnb;
+        auto range = [&](int n, int first, int dir) {
+            if (ch >= n) return;
+            auto slot = [&](int k) { return first + dir * (k < n ? k : 0); };
+            int k = ch;
+            V4 E0 = ent[slot(k)];
+            V4 E1 = ent[slot(k + ST)];
+            V4 U0 = pp.at(vbits(E0), s);
+            while (k < n) {
+                const V4 E2 = ent[slot(k + 2 * ST)];
+                const V4 U1 = pp.at(vbits(E1), s);
+                pair(E0, U0);
+                E0 = E1;
+                E1 = E2;
+                U0 = U1;
+                k += ST;
+            }
+        };
+        range(ncore, 0, 1);
+        range(cnt - ncore, maxnb - 1, -1);
     }
 }
 
@@ -328,7 +416,8 @@ __device__ void rebuild_list(const RepDev& R, int i, bool active, const double* 
     if (over && active && lane == 0) atomicOr(status, kStatusRange);
     V4* __restrict__ ent = (V4*)R.nb_entries + (size_t)i * R.maxnb;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int cnt = 0;
+    const double rc2 = R.r_cut * R.r_cut;
+    int ncore = 0, nshell = 0;
     for (int t0 = 0; t0 < N; t0 += 256) {
         __syncthreads();
         const int jl = t0 + threadIdx.x;
@@ -363,26 +452,17 @@ __device__ void rebuild_list(const RepDev& R, int i, bool active, const double* 
                         const double r2 = ex * ex + ey * ey + ez * ez;
                         const bool self = (j == i) && nx == 0 && ny == 0 && nz == 0;
                         const bool hit = valid && r2 < R2 && !self;
-                        const uint64_t mask = __ballot(hit);
-                        if (hit) {
-                            const int sl = cnt + __popcll(mask & below);
-                            if (sl < R.maxnb) {
-                                V4 v;
-                                v.x = (T)ex;
-                                v.y = (T)ey;
-                                v.z = (T)ez;
-                                v.w = as_bits_t<T>(j);
-                                ent[sl] = v;
-                            }
-                        }
-                        cnt += __popcll(mask);
+                        V4 v;
+                        v.x = (T)ex;
+                        v.y = (T)ey;
+                        v.z = (T)ez;
+                        v.w = as_bits_t<T>(j);
+                        list_push(ent, R.maxnb, hit, r2 < rc2, v, below, ncore, nshell);
                     }
         }
     }
-    if (active && lane == 0) {
-        R.nb_count[i] = min(cnt, R.maxnb);
-        if (cnt > R.maxnb) atomicOr(status, kStatusNbOverflow);
-    }
+    if (active && lane == 0)
+        list_finish(R.nb_count, R.nb_core, i, R.maxnb, ncore, nshell, status);
     __syncthreads();
 }
 
@@ -392,7 +472,7 @@ __device__ void rebuild_list(const RepDev& R, int i, bool active, const double* 
 // spills; FP64 is left to the compiler.
 template <typename T, int G, int NS, bool FAST, int DEG, bool WE>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (WE ? 5 : 8)))) k_force_pair(const RepDev* __restrict__ reps,
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (WE ? 5 : 7)))) k_force_pair(const RepDev* __restrict__ reps,
                                                     const BlockEntry* __restrict__ blocks,
                                                     const PairTable<T> tab, int32_t flags,
                                                     double* __restrict__ partials, int clear,
@@ -465,13 +545,13 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (WE ? 5 : 8)))) k_force_
         if (rebuild) {
             const PairPos<T, kPosRef> pp{nullptr, nullptr, (gptr<double>)cen, N, P,
                                          (gptr<double>)R.pos, (gptr<int32_t>)R.species};
-            pair_sum<T, NS, FAST, DEG, kPosRef>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy, fz,
+            pair_sum<T, NS, FAST, DEG, kPosRef, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy, fz,
                                                 e, vir, spi);
         } else {
             // u is atom-major [N][P]: the G beads of a neighbour share cache lines
             const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[si.p] + 0, nullptr, nullptr, N, P,
                                             nullptr, nullptr};
-            pair_sum<T, NS, FAST, DEG, kPosDirect>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
+            pair_sum<T, NS, FAST, DEG, kPosDirect, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
                                                    fz, e, vir, spi);
         }
     }
@@ -563,12 +643,12 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
         if (rebuild) {
             const PairPos<T, kPosRecon> pp{(gptr<V4>)R.ub[pin] + 0, (gptr<double>)rin,
                                            (gptr<double>)cin, N, P, nullptr, nullptr};
-            pair_sum<T, NS, FAST, DEG, kPosRecon>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
+            pair_sum<T, NS, FAST, DEG, kPosRecon, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
                                                   fz, e, vir, spi);
         } else {
             const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[pin] + 0, nullptr, nullptr, N, P,
                                             nullptr, nullptr};
-            pair_sum<T, NS, FAST, DEG, kPosDirect>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
+            pair_sum<T, NS, FAST, DEG, kPosDirect, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
                                                    fz, e, vir, spi);
         }
     }

@@ -95,7 +95,8 @@ __global__ void __launch_bounds__(256) k_ml_list(const RepDev* __restrict__ reps
         const double* __restrict__ devb = R.devbb[si.p];
         const T4* __restrict__ ent = (const T4*)R.nb_entries + (size_t)i * R.maxnb;
         T4* __restrict__ out = (T4*)R.ml_nb + (size_t)i * R.maxml;
-        const int cnt = R.nb_count[i];
+        // the pair list's core entries, then its shell entries, each in scan order
+        const int cnt = R.nb_count[i], ncore = R.nb_core[i];
         const double base = R.ml_rcs + devb[i];  // r_ml + skin + dev_i
         int n = 0;
         for (int k0 = 0; k0 < cnt; k0 += 64) {
@@ -103,7 +104,7 @@ __global__ void __launch_bounds__(256) k_ml_list(const RepDev* __restrict__ reps
             bool hit = false;
             T4 E;
             if (k < cnt) {
-                E = ent[k];
+                E = ent[k < ncore ? k : R.maxnb - 1 - (k - ncore)];
                 const double Rij = base + devb[ebits<T>(E)];
                 const double r2 = (double)E.x * E.x + (double)E.y * E.y + (double)E.z * E.z;
                 hit = r2 < Rij * Rij;

@@ -127,7 +127,10 @@ __global__ void __launch_bounds__(256) k_tile_box(const RepDev* __restrict__ rep
 // One wavefront per atom i: new reference r_ref_i = current bead centroid,
 // relative positions of its beads, and its list.  Lane l scans atoms
 // j = j0 + l; matches are compacted with a ballot, so entries come out in a
-// fixed order (j chunk, image, lane) whatever the timing.
+// fixed order (j chunk, image, lane) whatever the timing, the core entries
+// (reference distance below r_cut, in range at almost every step) apart from
+// the shell (list_push), so that the force loop's wavefronts meet the
+// out-of-range pairs together.
 template <typename T>
 __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be, const int p,
                                             int32_t* __restrict__ status, double* tx, double* ty,
@@ -179,7 +182,8 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
     if (over && active && lane == 0) atomicOr(status, kStatusRange);
     T4* __restrict__ ent = (T4*)R.nb_entries + (size_t)i * R.maxnb;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int cnt = 0;
+    const double rc2 = R.r_cut * R.r_cut;
+    int ncore = 0, nshell = 0;
     // tiles of 256 candidate atoms staged in LDS, shared by the 4 wavefronts;
     // a tile whose centroid bounds (widened by the spreads) are out of range
     // of all four atoms of the block is skipped, which leaves the entries and
@@ -260,26 +264,17 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
                         const double r2 = ex * ex + ey * ey + ez * ez;
                         const bool self = (j == i) && nx == 0 && ny == 0 && nz == 0;
                         const bool hit = valid && r2 < R2 && !self;
-                        const uint64_t mask = __ballot(hit);
-                        if (hit) {
-                            const int slot = cnt + __popcll(mask & below);
-                            if (slot < R.maxnb) {
-                                T4 v;
-                                v.x = (T)ex;
-                                v.y = (T)ey;
-                                v.z = (T)ez;
-                                v.w = bits_f(j, T());
-                                ent[slot] = v;
-                            }
-                        }
-                        cnt += __popcll(mask);
+                        T4 v;
+                        v.x = (T)ex;
+                        v.y = (T)ey;
+                        v.z = (T)ez;
+                        v.w = bits_f(j, T());
+                        list_push(ent, R.maxnb, hit, r2 < rc2, v, below, ncore, nshell);
                     }
         }
     }
-    if (active && lane == 0) {
-        R.nb_count[i] = min(cnt, R.maxnb);
-        if (cnt > R.maxnb) atomicOr(status, kStatusNbOverflow);
-    }
+    if (active && lane == 0)
+        list_finish(R.nb_count, R.nb_core, i, R.maxnb, ncore, nshell, status);
 }
 
 // Grid-stride over the block table with at most 2048 workgroups, so the

@@ -45,7 +45,7 @@ struct Layout {
     // surrogate (ml_r_cut > 0)
     Region blk_mlc, blk_mlm, ml_acc, ml_counts, ml_loss, ml_stats, ml_foff, ml_wpart;
     struct Per {
-        Region force, r0, eatom, species, homega, nb, nbc, nm, ring;
+        Region force, r0, eatom, species, homega, nb, nbc, nbcore, nm, ring;
         Region u[2], rref[2], cnow[2], dev[2], devb[2];  // by step parity
         Region tbox;
         Region mlnb, mlnc, mlrev, mlG, mlaux, mlg, mly, mlfp, mlin, mlnin, mlv, mlu, mladj, mlebar;
@@ -353,6 +353,7 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
             add(cur, p.tbox, 8 * 8 * ((N + kListTile - 1) / kListTile));
             add(cur, p.nb, 4 * ts * N * (size_t)L.maxnb[r]);
             add(cur, p.nbc, 4 * N);
+            add(cur, p.nbcore, 4 * N);
             if (L.ml) {
                 const size_t M = L.maxml[r];
                 add(cur, p.mlnb, 4 * ts * N * M);
@@ -686,7 +687,7 @@ void fill_pair_table(qtb_ctx* c, PairTable<T>& tab)
     };
     int deg = 10;
     if (tail_after(10) >= 3e-7 * std::fabs(cc[0])) deg = kErfcxMaxDeg;
-    const bool fit_ok = tail_after(deg) < 5e-7 * std::fabs(cc[0]);
+    bool fit_ok = tail_after(deg) < 5e-7 * std::fabs(cc[0]);
     // monomial coefficients of sum_j cc[j] T_j(s), j <= deg
     std::vector<double> mono(deg + 1, 0.0), tm1(deg + 1, 0.0), t0(deg + 1, 0.0), t1(deg + 1, 0.0);
     tm1[0] = 1.0;            // T_0
@@ -704,8 +705,67 @@ void fill_pair_table(qtb_ctx* c, PairTable<T>& tab)
         t0 = t1;
     }
     for (int q = 0; q <= kErfcxMaxDeg; ++q) tab.ex[q] = (T)(q <= deg ? mono[q] : 0.0);
-    tab.ex_deg = fit_ok ? deg : 0;
     tab.s_mul = (T)(2.0 * al / xmax);
+    // Coulomb force shape phi(a r) = erfc(a r) + (2 a r / sqrt(pi)) e^{-a^2 r^2}
+    // = 1 + (r r^2) a^3 psi(a^2 r^2) on r in [0, r_cut]: Chebyshev
+    // interpolation of a^3 psi in s = r^2 (2 / r_cut^2) - 1, psi from its
+    // Taylor series (alternating, all terms of one sign pair summed in FP64)
+    // psi(y) = -(4 / sqrt(pi)) sum_n (-y)^n / (n! (2n + 3)).
+    auto psi = [&](double y) {
+        double t = 1.0, sum = 0.0;
+        for (int n = 0; n < 200; ++n) {
+            const double term = t / (2.0 * n + 3.0);
+            sum += term;
+            if (std::fabs(term) < 1e-18 * std::fabs(sum) && n > 2 * y + 5) break;
+            t *= -y / (n + 1.0);
+        }
+        return -4.0 / std::sqrt(kPi) * sum;
+    };
+    std::vector<double> cp(nn, 0.0);
+    for (int j = 0; j < nn; ++j) {
+        double acc = 0.0;
+        for (int q = 0; q < nn; ++q) {
+            const double th = kPi * (q + 0.5) / nn;
+            const double r2 = 0.5 * (std::cos(th) + 1.0) * rc * rc;
+            acc += al * al * al * psi(al * al * r2) * std::cos(j * th);
+        }
+        cp[j] = 2.0 * acc / nn;
+    }
+    cp[0] *= 0.5;
+    auto ptail = [&](int d) {
+        double t = 0.0;
+        for (int j = d + 1; j < nn; ++j) t += std::fabs(cp[j]);
+        return t;
+    };
+    // relative to phi, whose smallest value on [0, r_cut] is phi(a r_cut):
+    // the tail of r^3 ph must stay below 5e-8 of it (2e-7 for degree 14)
+    const double phimin = std::erfc(xmax) + 2.0 * xmax / std::sqrt(kPi) * std::exp(-xmax * xmax);
+    const double r3 = rc * rc * rc;
+    const bool phi10 = ptail(10) * r3 < 5e-8 * phimin;
+    const bool phi14 = ptail(kErfcxMaxDeg) * r3 < 2e-7 * phimin;
+    if (!phi10 && deg == 10 && phi14) deg = kErfcxMaxDeg;  // both polynomials of one degree
+    const bool phi_ok = deg == 10 ? phi10 : phi14;
+    std::vector<double> pm(deg + 1, 0.0);
+    {
+        std::vector<double> a(deg + 1, 0.0), b(deg + 1, 0.0), c2(deg + 1, 0.0);
+        a[0] = 1.0;
+        pm[0] += cp[0];
+        if (deg >= 1) {
+            b[1] = 1.0;
+            pm[1] += cp[1];
+        }
+        for (int j = 2; j <= deg; ++j) {
+            std::fill(c2.begin(), c2.end(), 0.0);
+            for (int q = 0; q < deg; ++q) c2[q + 1] += 2.0 * b[q];
+            for (int q = 0; q <= deg; ++q) c2[q] -= a[q];
+            for (int q = 0; q <= deg; ++q) pm[q] += cp[j] * c2[q];
+            a = b;
+            b = c2;
+        }
+    }
+    for (int q = 0; q <= kErfcxMaxDeg; ++q) tab.ph[q] = (T)(q <= deg ? pm[q] : 0.0);
+    tab.ph_s = (T)(2.0 / (rc * rc));
+    tab.ex_deg = (fit_ok && phi_ok) ? deg : 0;
 }
 
 void fill_repdev(qtb_ctx* c, int r)
@@ -729,6 +789,7 @@ void fill_repdev(qtb_ctx* c, int r)
     d.homega = c->pair ? nullptr : c->at<double>(p.homega);
     d.nb_entries = c->pair ? c->at<void>(p.nb) : nullptr;
     d.nb_count = c->pair ? c->at<int32_t>(p.nbc) : nullptr;
+    d.nb_core = c->pair ? c->at<int32_t>(p.nbcore) : nullptr;
     d.tbox = c->pair ? c->at<double>(p.tbox) : nullptr;
     d.nm = c->at<double>(p.nm);
     d.ring = c->at<double>(p.ring);
@@ -750,6 +811,7 @@ void fill_repdev(qtb_ctx* c, int r)
     d.half_skin0 = d.half_skin;
     d.npt_S = 1.0;
     d.r_cs = c->rc + c->skin;
+    d.r_cut = c->rc;
     for (int a = 0; a < kMaxSpecies; ++a) {
         const double m = a < (int)c->mass.size() ? c->mass[a] * c->opt.mass_unit : 1.0;
         d.mmu[a] = m;

@@ -41,6 +41,11 @@ struct PairParam {
 // cannot cover to 5e-7, where the FP32 kernel calls erfcf instead.
 constexpr int kErfcxMaxDeg = 14;
 
+// The Coulomb part of F(r) / kqq, erfc(a r) / r^2 + g e^{-a^2 r^2} / r, is
+// phi(a r) / r^2 with phi(x) = erfc(x) + (2 x / sqrt(pi)) e^{-x^2}
+// = 1 - (4 / sqrt(pi)) int_0^x t^2 e^{-t^2} dt = 1 + x^3 psi(x^2), psi entire;
+// the FP32 force kernels take phi = 1 + (r r^2) ph(s), s = r^2 ph_s - 1,
+// ph a polynomial of degree ex_deg fitted on the host (a^3 folded in).
 template <typename T>
 struct PairTable {
     PairParam<T> p[kPairs];
@@ -48,6 +53,8 @@ struct PairTable {
     T a2l;     // alpha^2 log2(e): e^{-a^2 r^2} = 2^{-r^2 a2l}
     T s_mul;   // 2 alpha / x_max
     T ex[kErfcxMaxDeg + 1];
+    T ph[kErfcxMaxDeg + 1];
+    T ph_s;    // 2 / r_cut^2
     int32_t ex_deg;
     int32_t n_species;
 };
@@ -69,8 +76,13 @@ struct RepDev {
     double* eatom;       // [P][N] per-atom energies (evaluate mode)
     const int32_t* species;  // [N]
     const double* homega;    // [N]
-    void* nb_entries;        // T4 [N][maxnb]: reference displacement d_ij, j bits in .w
+    // T4 [N][maxnb]: reference displacement d_ij, j bits in .w; the core
+    // entries (reference distance below r_cut) at slots 0 .. nb_core - 1 in
+    // scan order, the shell entries at slots maxnb - 1, maxnb - 2, ... in
+    // scan order, nb_count entries in all
+    void* nb_entries;
     int32_t* nb_count;       // [N]
+    int32_t* nb_core;        // [N]
     const double* nm;        // [P][P] orthonormal normal-mode matrix C[s][k]
     const double* ring;      // [3][P]: cos(w h), sin(w h)/w, -w sin(w h), h = dt/2
     int32_t* rflag;          // [3] neighbour-list rebuild flags, by step mod 3
@@ -84,6 +96,7 @@ struct RepDev {
     // half_skin: the displacement from the reference that triggers a list
     // rebuild (lowered under the barostat while the box is compressed)
     double c1, kT, omega_P, half_skin, r_cs;  // r_cs = r_cut + skin
+    double r_cut;
     double kick[kMaxSpecies];   // dt / (2 P m mu)
     double sigma[kMaxSpecies];  // sqrt((1 - c1^2) / (m mu))
     double mmu[kMaxSpecies];    // m mu
@@ -199,6 +212,21 @@ enum StatusBits : int32_t {
     kStatusMlList = 8,
     kStatusRange = 16,  // pair range beyond kMaxImages periodic images (diverged state)
 };
+// Counts of atom i's list after the build (one lane calls it); an overflowing
+// list is left empty (every entry read is then a written one) and reported.
+__device__ __forceinline__ void list_finish(int32_t* nb_count, int32_t* nb_core, int i, int maxnb,
+                                            int ncore, int nshell, int32_t* status)
+{
+    if (ncore + nshell > maxnb) {
+        nb_count[i] = 0;
+        nb_core[i] = 0;
+        atomicOr(status, kStatusNbOverflow);
+    } else {
+        nb_count[i] = ncore + nshell;
+        nb_core[i] = ncore;
+    }
+}
+
 // Periodic images searched per direction when a list is built: enough for
 // any box wider than r_cut / 8; a larger range (a diverging trajectory's
 // bead spread) is clamped to it and reported through kStatusRange, so the
@@ -213,6 +241,31 @@ constexpr int kMaxListTiles = 4096;
 // scan skips candidate tiles out of range by their bounding boxes; smaller
 // ones rebuild inside the force kernel (one launch less per step).
 constexpr int kInlineRebuildMaxAtoms = 16384;
+
+// One step of a list build: each lane holds at most one accepted candidate
+// (hit), stored with ballot compaction in lane order; core entries
+// (reference distance below r_cut) go to slots ncore, ncore + 1, ...,
+// shell entries to slots maxnb - 1 - nshell, maxnb - 2 - nshell, ....  A
+// store that would cross into the other range is dropped: the total then
+// exceeds maxnb and list_finish reports the overflow.
+template <typename V>
+__device__ __forceinline__ void list_push(V* __restrict__ ent, int maxnb, bool hit, bool core,
+                                          const V& v, uint64_t below, int& ncore, int& nshell)
+{
+    const uint64_t mc = __ballot(hit && core), ms = __ballot(hit && !core);
+    const int nc = __popcll(mc), ns = __popcll(ms);
+    if (hit) {
+        if (core) {
+            const int slot = ncore + __popcll(mc & below);
+            if (slot < maxnb - (nshell + ns)) ent[slot] = v;
+        } else {
+            const int slot = maxnb - 1 - (nshell + __popcll(ms & below));
+            if (slot >= ncore + nc) ent[slot] = v;
+        }
+    }
+    ncore += nc;
+    nshell += ns;
+}
 
 // Image range ceil(R / L - 1/2) along one direction, clamped to
 // [0, kMaxImages] (also for non-finite R); over is set when clamped.
