@@ -14,7 +14,7 @@ The GPU test runs the same systems with another noise seed and compares means
 and the heat capacity C = dE/dT from the temperature ladder, within two
 combined standard errors of the block means.
 
-    python tests/golden/make_thermo.py      # about ten minutes on 8 threads
+    python tests/golden/make_thermo.py      # about fifteen minutes on 8 threads
 """
 from __future__ import annotations
 
@@ -35,8 +35,8 @@ OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "thermo_mgo_3x3x3
 
 SETTINGS = dict(n_cells=3, sigma=0.0421, pos_seed=5, gamma=1e-2, dt=1.0, two_nf=512,
                 noise_seed=11, every=8, block=1000, n_eq=3000)
-RUNS = [dict(P=1, noise=1, T=T, n_blocks=24) for T in (50.0, 100.0, 200.0, 400.0)] + \
-       [dict(P=4, noise=2, T=T, n_blocks=16) for T in (100.0, 200.0)]
+RUNS = [dict(P=1, noise=1, T=T, n_blocks=48) for T in (50.0, 100.0, 200.0, 400.0)] + \
+       [dict(P=4, noise=2, T=T, n_blocks=48) for T in (100.0, 200.0)]
 FIELDS = ("kinetic", "potential", "e_primitive", "e_virial", "t_kinetic")
 
 
