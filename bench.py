@@ -31,18 +31,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work of one unique pair within r_cut (see the pair kernel):
-# displacement 6, r^2 5, rsqrt 1, r 1, Buckingham exp 2, damping x 1, Gaussian
-# exp 2, erfc 1, r^-2 / r^-6 3, force magnitude 11, F/r 1, force on i 6,
-# reaction on j 3 (Newton's third law) -> 43 flops.
-FLOPS_PER_PAIR = 43
-# The same pair in VALU lane-slots (one per instruction, FMA fused; rsqrt,
-# the two exponentials and erfc at four slots each, quarter rate):
-# displacement 6, r^2 3, rsqrt 4, r 1, Buckingham exp 5, Gaussian exp 5,
-# erfc 4, r^-2 / r^-6 3, force magnitude 6, F/r 1, force on i 3, reaction 3
-# -> 44 slots.  Lane-slot peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no
-# packed FP32: the build disables it).
-SLOTS_PER_PAIR = 44
+# Algorithmic work of one unique pair within r_cut, counted from the closed
+# forms of the Buckingham (shifted-force) and damped-shifted-force Coulomb
+# terms, each of rsqrt, exp, exp counted as one flop: 50 flops, or 47 VALU
+# lane-slots with FMA fused and the transcendentals (rsqrt, the Buckingham
+# and Gaussian exponentials) at four slots each, quarter rate.  Lane-slot
+# peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no packed FP32: the build
+# disables it).
+FLOPS_PER_PAIR = 50
+SLOTS_PER_PAIR = 47
 PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
 # Algorithmic HBM bytes of the FIR per dof-step: one white-noise value read and
 # one coloured-noise value written, FP32 each.
@@ -200,12 +197,31 @@ def unique_pairs(beads, box, r_cut):
     return n
 
 
+def host_cpu():
+    """The host the oracle ran on: logical CPUs, those this process may use,
+    and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
 def cpu_baseline(w, beads, sp, box, pot, budget_s=15.0):
     """The oracle (plain FP64 C, OpenMP over atoms) on the same workload,
     bounded to about budget_s seconds of stepping."""
     from oracle import oracle as orc
     from paper_1905_02521_amd import workloads as W
-    threads = min(os.cpu_count() or 1, 16)
+    threads = min(host_cpu()["usable_cpus"], 16)
     U = orc.make_units(**W.METAL_UNITS)
     opot = orc.make_pot(0, pot.mass, pot.charge, pot.buck_A, pot.buck_rho, pot.buck_C,
                         pot.dsf_alpha, pot.r_cut, pot.skin)
@@ -222,7 +238,7 @@ def cpu_baseline(w, beads, sp, box, pot, budget_s=15.0):
         t += time.perf_counter() - t0
         n += k
     return {"value": N * P * n / t, "unit": "atom-bead-steps/s", "cores": threads,
-            "kind": "oracle", "_ab": N * P * n, "_t": t,
+            "kind": "oracle", "_ab": N * P * n, "_t": t, **host_cpu(),
             "sample": f"{n} steps of the same workload ({N} atoms x {P} beads), "
                       f"{t:.1f} s, FP64, {threads} OpenMP threads"}
 
@@ -551,8 +567,8 @@ def npt_bench(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=640)
+    ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--workload", default="mgo-8x8x8-qtbpimd-P8-50K",
                     help="a named single workload, batched-64 (the T / gamma / P sweep) or "
                          "surrogate-20x20x20-P4 (the learned force surrogate) or qtb-vs-pimd "
@@ -631,7 +647,20 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
-    ctx.step(a.warmup)
+    # The coloured noise is made K steps at a time (white-noise rows and the FIR
+    # contraction open every block).  The timed steps start on a block
+    # boundary, so the timed region makes the noise of every step it runs:
+    # after the warmup, untimed steps up to the next multiple of K.  With
+    # --steps not a multiple of K the last block's noise is made for steps
+    # beyond the timed ones too (a conservative figure).
+    # The timed pattern (a.steps from a block boundary) is also run once
+    # untimed, so that the graphs it replays are captured before the clock
+    # starts, then the context steps on to the next block boundary.
+    align = (-a.warmup) % a.K
+    ctx.step(a.warmup + align)
+    ctx.step(a.steps)
+    ctx.step((-a.steps) % a.K)
+    untimed = a.warmup + align + a.steps + (-a.steps) % a.K
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.step(a.steps)
@@ -684,6 +713,8 @@ def main():
                    "two_nf": sorted(set(x.two_nf for x in works)), "fir": a.fir,
                    "noise_generator": "eq. 9 blocks" if a.noise_blocks else "streaming FIR",
                    "fir_block_K": a.K,
+                   "untimed_steps": untimed,
+                   "noise_blocks_in_timed_region": -(-a.steps // a.K),
                    "forces": "fp32" if prec == qtb.PREC_FP32 else "fp64", "state": "fp64",
                    "r_cut_A": pot.r_cut, "skin_A": pot.skin, "parallelism": "1 GPU"},
         "roofline": {"kernel": "pair forces", "bound": "alu", "achieved": achieved,
@@ -718,7 +749,7 @@ def main():
             n_ab = sum(p_["_ab"] for p_ in parts)
             t_all = sum(p_["_t"] for p_ in parts)
             out["cpu_baseline"] = {"value": n_ab / t_all, "unit": "atom-bead-steps/s",
-                                   "cores": parts[0]["cores"], "kind": "oracle",
+                                   "cores": parts[0]["cores"], "kind": "oracle", **host_cpu(),
                                    "sample": "; ".join(p_["sample"] for p_ in parts)}
         else:
             cb = cpu_baseline(w, beads, sp, box, pot, a.cpu_seconds)

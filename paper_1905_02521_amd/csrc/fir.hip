@@ -17,6 +17,14 @@
 //                  operands, hi*hi + hi*lo + lo*hi, FP32 accumulation
 //  mode 2  BF16:   hi*hi only
 //  mode 3  FP64:   vector FMA, register-blocked over 8 outputs
+//
+// Ring layouts.  FP32 / FP64 modes: [R][n_cols], row m in slot m mod R.
+// BF16 modes: the white noise is stored already split into its BF16 hi and
+// lo parts (hi = bf16(w), lo = bf16(w - hi), w the FP32 value), each part a
+// plane [R/8][n_cols][8]: the 8 rows of a column that one matrix-core lane
+// takes as its B fragment are one aligned 16-byte load.  The window then
+// starts at the 8-aligned row J0 = floor8(n_b - Nf + 1); the delta rows
+// before the first needed one meet zero taps (the padding).
 #include "qtb_internal.h"
 
 namespace qtb {
@@ -50,12 +58,16 @@ __global__ void __launch_bounds__(256) k_fir_fp64(const FirTile* __restrict__ ti
     for (int x = threadIdx.x; x < L; x += blockDim.x) sh64[x] = taps[t.taps_off + x];
     __syncthreads();
     const int64_t col = (int64_t)blockIdx.x * kDofTile + threadIdx.x;
+    const int s0 = (int)ring_slot(nb - Nf + 1, R);  // slot of window row 0
     for (int i0 = 0; i0 < K; i0 += 8) {
         double acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        int sl = s0 + i0;
+        if (sl >= R) sl -= R;
         for (int j = i0; j < i0 + two_nf + 7; ++j) {
-            const double wv = ring[ring_slot(nb - Nf + 1 + j, R) * n_cols + col];
+            const double wv = ring[(int64_t)sl * n_cols + col];
+            if (++sl == R) sl = 0;
             const int xb = i0 - j + two_nf - 1 + kPad;
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc[q] = __builtin_fma(sh64[xb + q], wv, acc[q]);
@@ -91,8 +103,11 @@ __global__ void __launch_bounds__(256) k_fir_f32(const FirTile* __restrict__ til
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[mt][r] = 0.0f;
     const int jend = K + two_nf - 1;
+    int sl = (int)ring_slot(nb - Nf + 1 + lk, R);  // slot of this lane's row j0 + lk
     for (int j0 = 0; j0 < jend; j0 += 2) {
-        const float b = ring[ring_slot(nb - Nf + 1 + j0 + lk, R) * n_cols + col];
+        const float b = ring[(int64_t)sl * n_cols + col];
+        sl += 2;
+        if (sl >= R) sl -= R;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const int i0 = 32 * mt;
@@ -122,7 +137,8 @@ __device__ __forceinline__ float bf16_value(uint32_t h) { return __uint_as_float
 template <int K, bool X3>
 __global__ void __launch_bounds__(256) k_fir_bf16(const FirTile* __restrict__ tiles,
                                                   const float* __restrict__ taps,
-                                                  const float* __restrict__ ring,
+                                                  const uint16_t* __restrict__ ring_hi,
+                                                  const uint16_t* __restrict__ ring_lo,
                                                   float* __restrict__ zeta, int64_t n_cols,
                                                   const int64_t* __restrict__ clock, int R, int LR)
 {
@@ -150,33 +166,36 @@ __global__ void __launch_bounds__(256) k_fir_bf16(const FirTile* __restrict__ ti
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 31, lk = lane >> 5;
     const int64_t col = col0 + 32 * wave + li;
+    // window from the 8-aligned row J0 = m0 - delta, m0 = nb - Nf + 1 the
+    // first row with a non-zero tap; row J0 + j meets tap index
+    // i - j + 2Nf - 1 + delta (zero outside 0 .. 2Nf - 1)
+    const int64_t m0 = nb - Nf + 1;
+    const int delta = (int)(((m0 % 8) + 8) % 8);
+    const int jend = K + two_nf - 1 + delta;
+    const int RC = R >> 3;  // 8-row chunks in the ring
+    int c = (int)(ring_slot(m0 - delta, R) >> 3) + lk;  // chunk of this lane's rows
+    if (c >= RC) c -= RC;
+    typedef const __attribute__((address_space(1))) u32x4* gp4;
+    const gp4 hp = (gp4)ring_hi + col, lp = (gp4)ring_lo + col;
     f32x16 acc[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[mt][r] = 0.0f;
-    const int jend = K + two_nf - 1;
     for (int j0 = 0; j0 < jend; j0 += 16) {
         const int jb = j0 + 8 * lk;
-        uint32_t bh[8], bl[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float w = ring[ring_slot(nb - Nf + 1 + jb + q, R) * n_cols + col];
-            bh[q] = bf16_bits_rn(w);
-            bl[q] = bf16_bits_rn(w - bf16_value(bh[q]));
-        }
-        u32x4 ph, pl;
-        ph[0] = bh[0] | (bh[1] << 16); ph[1] = bh[2] | (bh[3] << 16);
-        ph[2] = bh[4] | (bh[5] << 16); ph[3] = bh[6] | (bh[7] << 16);
-        pl[0] = bl[0] | (bl[1] << 16); pl[1] = bl[2] | (bl[3] << 16);
-        pl[2] = bl[4] | (bl[5] << 16); pl[3] = bl[6] | (bl[7] << 16);
+        const u32x4 ph = hp[(int64_t)c * n_cols];
+        const u32x4 pl = lp[(int64_t)c * n_cols];
+        c += 2;
+        if (c >= RC) c -= RC;
         const bf16x8 Bhi = __builtin_bit_cast(bf16x8, ph);
         const bf16x8 Blo = __builtin_bit_cast(bf16x8, pl);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const int i0 = 32 * mt;
-            if (j0 + 15 < i0 || j0 > i0 + 30 + two_nf) continue;
-            const int X0 = i0 + li - jb + two_nf - 1 + kPad;
+            // rows j0 .. j0 + 15 against outputs i0 .. i0 + 31: any tap in band?
+            if (j0 + 15 < i0 + delta || j0 > i0 + 30 + delta + two_nf) continue;
+            const int X0 = i0 + li - jb + two_nf - 1 + delta + kPad;
             const int s = Lh - 1 - X0;
             const int off = (s & 7) * LR + (s & ~7);
             const bf16x8 Ahi = __builtin_bit_cast(bf16x8, *(const u32x4*)(Rhi + off));
@@ -224,14 +243,14 @@ void launch_fir_K(hipStream_t st, int mode, const FirTile* tiles, int n_tiles, c
         const size_t lds = (size_t)16 * LR * sizeof(uint16_t);
         allow_lds(k_fir_bf16<K, true>, lds);
         allow_lds(k_fir_bf16<K, false>, lds);
+        const uint16_t* hi = (const uint16_t*)ring;
+        const uint16_t* lo = hi + (size_t)R * n_cols;
         if (mode == QTB_FIR_BF16X3)
             launch((k_fir_bf16<K, true>), dim3(n_tiles * 2), dim3(256), lds, st,
-                               tiles, (const float*)taps, (const float*)ring, (float*)zeta,
-                               n_cols, nb, R, LR);
+                               tiles, (const float*)taps, hi, lo, (float*)zeta, n_cols, nb, R, LR);
         else
             launch((k_fir_bf16<K, false>), dim3(n_tiles * 2), dim3(256), lds, st,
-                               tiles, (const float*)taps, (const float*)ring, (float*)zeta,
-                               n_cols, nb, R, LR);
+                               tiles, (const float*)taps, hi, lo, (float*)zeta, n_cols, nb, R, LR);
     }
 }
 

@@ -158,6 +158,67 @@ __global__ void k_gen_white(const RepDev* __restrict__ reps, const FirTile* __re
     ring[slot * n_cols + col] = w;
 }
 
+__device__ __forceinline__ uint32_t bf16_rn_bits(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// The same rows for the BF16 matrix-core FIR: each FP32 value w split into
+// hi = bf16(w) and lo = bf16(w - hi), stored in two planes [R/8][n_cols][8]
+// (R a multiple of 8): one thread per column and aligned group of 8 rows,
+// blockIdx.y the group; rows of the group outside m0 .. m0+rows-1 are left
+// alone.  A full group is one 16-byte store per plane.
+__global__ void k_gen_white_split(const RepDev* __restrict__ reps,
+                                  const FirTile* __restrict__ tiles, uint16_t* __restrict__ hi,
+                                  uint16_t* __restrict__ lo, const int64_t* __restrict__ clock,
+                                  int64_t off, int rows, int R, int64_t n_cols)
+{
+    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= n_cols) return;
+    const int64_t m0 = *clock + off, m1 = m0 + rows;
+    const int64_t g0 = m0 - (((m0 % 8) + 8) % 8);  // first row of the first group
+    const int64_t gm = g0 + 8 * (int64_t)blockIdx.y;
+    const int tile = (int)(col / kDofTile);
+    const int rep = __builtin_amdgcn_readfirstlane(tiles[tile].rep);
+    const RepDev& Rp = reps[rep];
+    const int64_t d = col - Rp.dof_off;
+    const int64_t D = (int64_t)Rp.dims * Rp.N * Rp.P;
+    uint32_t h[8], l[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t m = gm + q;
+        float w = 0.0f;
+        if (m >= m0 && m < m1 && d < D)
+            w = (float)white_gauss(Rp.seed, m + Rp.step_off, (uint32_t)d, Rp.stream, 0);
+        h[q] = bf16_rn_bits(w);
+        l[q] = bf16_rn_bits(w - __uint_as_float(h[q] << 16));
+    }
+    int64_t slot = gm % R;
+    if (slot < 0) slot += R;
+    const size_t base = ((size_t)(slot >> 3) * n_cols + col) * 8;
+    if (gm >= m0 && gm + 8 <= m1) {
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+        u4 ph, pl;
+        ph[0] = h[0] | (h[1] << 16); ph[1] = h[2] | (h[3] << 16);
+        ph[2] = h[4] | (h[5] << 16); ph[3] = h[6] | (h[7] << 16);
+        pl[0] = l[0] | (l[1] << 16); pl[1] = l[2] | (l[3] << 16);
+        pl[2] = l[4] | (l[5] << 16); pl[3] = l[6] | (l[7] << 16);
+        *(u4*)(hi + base) = ph;
+        *(u4*)(lo + base) = pl;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t m = gm + q;
+            if (m >= m0 && m < m1) {
+                hi[base + q] = (uint16_t)h[q];
+                lo[base + q] = (uint16_t)l[q];
+            }
+        }
+    }
+}
+
 }  // namespace
 
 void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
@@ -172,12 +233,21 @@ void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t ta
 }
 
 void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, void* ring,
-                      bool fp64, const int64_t* clock, int64_t off, int rows, int R,
+                      int fir_mode, const int64_t* clock, int64_t off, int rows, int R,
                       int64_t n_cols)
 {
     if (rows <= 0) return;
+    if (fir_mode == QTB_FIR_BF16X3 || fir_mode == QTB_FIR_BF16) {
+        // groups of 8 rows touched by rows clock+off .. clock+off+rows-1
+        // (the clock's alignment mod 8 is unknown here: one group spare)
+        dim3 grid((unsigned)((n_cols + 255) / 256), (unsigned)((rows + 7) / 8 + 1));
+        uint16_t* hi = (uint16_t*)ring;
+        launch(k_gen_white_split, grid, dim3(256), 0, st, reps, tiles, hi, hi + (size_t)R * n_cols,
+               clock, off, rows, R, n_cols);
+        return;
+    }
     dim3 grid((unsigned)((n_cols + 255) / 256), (unsigned)rows);
-    if (fp64)
+    if (fir_mode == QTB_FIR_FP64)
         launch(k_gen_white<double>, grid, dim3(256), 0, st, reps, tiles,
                            (double*)ring, clock, off, R, n_cols);
     else

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -192,7 +193,7 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
     L.max_two_nf = opt->max_two_nf;
     L.eq9 = (opt->flags & QTB_OPT_NOISE_BLOCKS) != 0;
     L.zeta_rows = L.eq9 ? 2 * (int64_t)opt->max_two_nf : L.K;
-    L.R = L.K + opt->max_two_nf;
+    L.R = (L.K + opt->max_two_nf + 15) / 16 * 16;  // ring rows (BF16 planes: groups of 8)
     L.taps_stride = opt->max_two_nf + 2 * fir_pad();
     L.per.assign(n_rep, {});
     L.dof_off.assign(n_rep, 0);
@@ -461,8 +462,8 @@ struct qtb_ctx {
     bool tuned = false;
     // captured noise blocks of K steps, replayed while nothing changes; one
     // per sampling / checking pattern (block start modulo obs_every and
-    // modulo the surrogate's check interval)
-    std::vector<std::pair<std::pair<int64_t, int64_t>, hipGraphExec_t>> graphs;
+    // modulo the surrogate's check interval) and per row range of the block
+    std::vector<std::pair<std::array<int64_t, 4>, hipGraphExec_t>> graphs;
     bool graph_failed = false;
     // surrogate
     qtb_ml* ml = nullptr;
@@ -1041,7 +1042,7 @@ void gen_rows(qtb_ctx* c, int64_t off, int64_t rows)
     for (int64_t r0 = 0; r0 < rows; r0 += 1024) {
         const int rr = (int)std::min<int64_t>(1024, rows - r0);
         launch_gen_white(c->st, c->at<RepDev>(L.reps), c->at<FirTile>(L.tiles),
-                         c->at<void>(L.ring), c->opt.fir == QTB_FIR_FP64,
+                         c->at<void>(L.ring), c->opt.fir,
                          c->at<int64_t>(L.clock), off + r0, rr, L.R, L.n_cols);
     }
 }
@@ -1259,38 +1260,52 @@ void drop_graph(qtb_ctx* c)
 }
 
 constexpr size_t kMaxGraphs = 32;
+// Shortest row range of a noise block worth a graph of its own (shorter runs
+// of steps launch eagerly).
+constexpr int kMinGraphRows = 8;
 
-// A whole block of K steps as one graph launch.  Valid while the kernel
-// arguments stay the same: they only depend on the workspace layout, the
-// potential table, the force provider and the sampling / checking pattern
-// inside the block, which is the key of the cached graphs.
-bool graph_block(qtb_ctx* c)
+// Rows r0 .. r1 - 1 of a noise block as one graph launch: at a block
+// boundary r0 = 0 and the graph opens the new block (clock, white noise,
+// FIR); otherwise it continues the current block from its next row.  r1 - r0
+// is at most left.  Valid while the kernel arguments stay the same: they
+// only depend on the workspace layout, the potential table, the force
+// provider, the sampling / checking pattern and the row range, which are the
+// key of the cached graphs.  Returns the number of steps launched (0: not
+// taken, run eagerly).
+int64_t graph_rows(qtb_ctx* c, int64_t left)
 {
     const Layout& L = c->L;
-    if (c->graph_failed || c->prof || c->st == nullptr) return false;
-    if (c->opt.flags & QTB_OPT_NO_GRAPH) return false;
-    if (c->opt.obs_every > 0 && L.K % c->opt.obs_every != 0) return false;
+    if (c->graph_failed || c->prof || c->st == nullptr) return 0;
+    if (c->opt.flags & QTB_OPT_NO_GRAPH) return 0;
+    if (c->opt.obs_every > 0 && L.K % c->opt.obs_every != 0) return 0;
+    if (!c->ring_valid) return 0;
+    const bool boundary = c->block_start < 0 || c->block_row >= L.K;
+    const int r0 = boundary ? 0 : c->block_row;
+    const int r1 = (int)std::min<int64_t>(L.K, r0 + left);
+    if (r1 - r0 < kMinGraphRows && !(r0 == 0 && r1 == L.K)) return 0;
     const int64_t obs_phase = c->opt.obs_every > 0 ? c->step % c->opt.obs_every : 0;
     const int64_t chk_phase = (c->ml && c->ml_check_every > 0) ? c->step % c->ml_check_every : 0;
     const bool fused = fused_step(c);
     // the sequence also depends on whether a step's close is pending
-    const std::pair<int64_t, int64_t> key{obs_phase, chk_phase * 4 + (fused ? 2 : 0) + (c->open ? 1 : 0)};
+    const std::array<int64_t, 4> key{obs_phase, chk_phase * 4 + (fused ? 2 : 0) + (c->open ? 1 : 0),
+                                     r0, r1};
     hipGraphExec_t exec = nullptr;
     for (auto& g : c->graphs)
         if (g.first == key) exec = g.second;
     if (!exec) {
-        if (c->graphs.size() >= kMaxGraphs) return false;  // too many patterns: run eagerly
+        if (c->graphs.size() >= kMaxGraphs) return 0;  // too many patterns: run eagerly
         hipGraph_t g = nullptr;
         if (hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             c->graph_failed = true;
             (void)hipGetLastError();
-            return false;
+            return 0;
         }
-        record_block_start(c);
+        if (r0 == 0) record_block_start(c);
         const bool open0 = c->open;
-        for (int r = 0; r < L.K; ++r) {
-            if (fused) record_fused(c, r, sample_at(c, c->step + r - 1));
-            else record_step(c, r, sample_at(c, c->step + r), check_at(c, c->step + r));
+        for (int r = r0; r < r1; ++r) {
+            const int64_t n = c->step + (r - r0);
+            if (fused) record_fused(c, r, sample_at(c, n - 1));
+            else record_step(c, r, sample_at(c, n), check_at(c, n));
         }
         c->open = open0;  // capture records, it does not run
         if (hipStreamEndCapture(c->st, &g) != hipSuccess || !g ||
@@ -1298,24 +1313,24 @@ bool graph_block(qtb_ctx* c)
             if (g) (void)hipGraphDestroy(g);
             c->graph_failed = true;
             (void)hipGetLastError();
-            return false;
+            return 0;
         }
         (void)hipGraphDestroy(g);
         c->graphs.push_back({key, exec});
     }
-    if (c->block_start < 0 || c->block_start + L.K != c->step)
+    if (boundary && (c->block_start < 0 || c->block_start + L.K != c->step))
         launch_clock(c->st, c->at<int64_t>(L.clock), c->step - L.K, false);
     if (hipGraphLaunch(exec, c->st) != hipSuccess) {
         drop_graph(c);
         c->graph_failed = true;
         (void)hipGetLastError();
-        return false;
+        return 0;
     }
-    c->block_start = c->step;
-    c->block_row = L.K;
-    c->step += L.K;
+    if (boundary) c->block_start = c->step;
+    c->block_row = r1;
+    c->step += r1 - r0;
     if (fused) c->open = true;
-    return true;
+    return r1 - r0;
 }
 
 // Make the force table of W current (host image, device copy, replica
@@ -1624,9 +1639,8 @@ qtb_status qtb_step(qtb_ctx* c, int64_t n_steps)
     }
     int64_t left = n_steps;
     while (left > 0) {
-        const bool at_boundary = c->ring_valid && (c->block_start < 0 || c->block_row >= c->L.K);
-        if (at_boundary && left >= c->L.K && graph_block(c)) {
-            left -= c->L.K;
+        if (const int64_t done = graph_rows(c, left)) {
+            left -= done;
             vdos_flush(c);
             continue;
         }

@@ -326,8 +326,11 @@ inline void launch(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t st
 
 // ---------------------------------------------------------------- launchers
 // noise.hip
+// White-noise rows clock+off .. clock+off+rows-1 into the ring, in the
+// layout of the FIR mode (FP64, FP32 rows, or BF16 hi/lo planes of 8-row
+// groups; see fir.hip).
 void launch_gen_white(hipStream_t st, const RepDev* reps, const FirTile* tiles, void* ring,
-                      bool fp64, const int64_t* clock, int64_t off, int rows, int R,
+                      int fir_mode, const int64_t* clock, int64_t off, int rows, int R,
                       int64_t n_cols);
 void launch_clock(hipStream_t st, int64_t* clock, int64_t v, bool add);
 // Block noise (eq. 9, n = 2^L2 steps per block, n >= K): makes the noise
