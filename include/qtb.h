@@ -323,6 +323,21 @@ qtb_status qtb_vdos_spectrum(const double *d_v, int64_t n_samples, int32_t n_dof
                              int32_t seg, double *d_spec, void *d_workspace, size_t ws_bytes,
                              void *hip_stream);
 
+/* qtb_vdos_spectrum for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * the same arguments without the workspace.  The scratch is a static device
+ * array of 16 MiB per GPU, held until the process ends; sizes whose
+ * qtb_vdos_workspace_bytes(n_dof, seg, 0) exceeds it return QTB_E_INVALID
+ * (nothing is enqueued).  No hipMalloc, hipFree or allocating call.  Every
+ * call on a GPU uses that GPU's one scratch array: calls that overlap on one
+ * GPU (on different streams, or from several threads) race; calls on one
+ * stream are ordered by it.  hip_stream must belong to the current device.
+ * The first call on a device looks up the array's device address. */
+qtb_status qtb_vdos_spectrum_noalloc(const double *d_v, int64_t n_samples, int32_t n_dof,
+                                     int64_t sample_stride, int64_t dof_stride,
+                                     const double *d_weight, int32_t seg, double *d_spec,
+                                     void *hip_stream);
+
 /* Attach a velocity recorder to a replica with P = 1 (QTB_E_INVALID for
  * P > 1: ring-polymer bead velocities carry no physical time correlations).
  * From now on every observable sample (every obs_every steps; QTB_E_STATE

@@ -604,6 +604,12 @@ qtb_status fail(qtb_ctx* c, qtb_status s, const std::string& m)
     return s;
 }
 
+}  // namespace
+
+void qtb::set_static_error(const std::string& m) { g_static_err = m; }
+
+namespace {
+
 qtb_status hip_check(qtb_ctx* c, hipError_t e, const char* what)
 {
     if (e == hipSuccess) return QTB_OK;

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 #include "qtb.h"
 
@@ -417,6 +418,8 @@ void launch_vdos_segment(hipStream_t st, const VdosPlan& p, const double* v, int
 // sqrt_w of a replica's dofs ([dims][N]: the square roots of the masses)
 void launch_vdos_weights(hipStream_t st, const RepDev* reps, int r, int n_dof, double* sqrt_w);
 void launch_vdos_sqrt(hipStream_t st, const double* w, int n, double* sqrt_w);
+// the error message of calls without a context (qtb_last_error(NULL))
+void set_static_error(const std::string& m);
 // ml.hip
 void launch_ml_lists(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* nl_blocks,
                      int n_nl, int32_t* status, StepRef sync);

@@ -21,6 +21,8 @@
 // in bit-reversed order; twiddles from a table computed once.  Each block
 // keeps the sum of its groups' periodograms in its own row of partials; two
 // fixed-order passes sum the rows: the result does not depend on scheduling.
+#include <mutex>
+
 #include "fft_lds.h"
 #include "qtb_internal.h"
 
@@ -211,3 +213,70 @@ void launch_vdos_sqrt(hipStream_t st, const double* w, int n, double* sw)
 }
 
 }  // namespace qtb
+
+// ------------------------------------------------- allocation-free spectrum
+namespace qtb {
+namespace {
+// The scratch of qtb_vdos_spectrum_noalloc: a file-scope device array, one
+// copy per GPU, alive until the process ends.  In host code its name stands
+// for a host-side shadow, so the device address of each GPU's copy is looked
+// up once (hipGetSymbolAddress, with that GPU current) and used instead.
+constexpr size_t kVdosScratchBytes = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kVdosScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch (null on failure).
+void* scratch_address(hipError_t& err)
+{
+    int dev = 0;
+    err = hipGetDevice(&dev);
+    if (err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (err != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    err = hipSuccess;
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+}  // namespace qtb
+
+extern "C" qtb_status qtb_vdos_spectrum_noalloc(const double* d_v, int64_t n_samples,
+                                                int32_t n_dof, int64_t sample_stride,
+                                                int64_t dof_stride, const double* d_weight,
+                                                int32_t seg, double* d_spec, void* hip_stream)
+{
+    if (!d_v || !d_weight || !d_spec || n_samples < 0 || sample_stride < 1 || dof_stride < 1) {
+        qtb::set_static_error("bad spectrum arguments");
+        return QTB_E_INVALID;
+    }
+    const size_t need = qtb_vdos_workspace_bytes(n_dof, seg, 0);
+    if (need == 0) {
+        qtb::set_static_error("n_dof >= 1 and seg a power of two in [16, 4096]");
+        return QTB_E_INVALID;
+    }
+    if (need > qtb::kVdosScratchBytes) {
+        qtb::set_static_error("qtb_vdos_spectrum_noalloc: the sizes need more scratch than its "
+                              "static 16 MiB (qtb_vdos_workspace_bytes(n_dof, seg, 0)); use "
+                              "qtb_vdos_spectrum with a workspace");
+        return QTB_E_INVALID;
+    }
+    hipError_t err = hipSuccess;
+    void* ws = qtb::scratch_address(err);
+    if (!ws) {
+        qtb::set_static_error(std::string("scratch address: ") + hipGetErrorString(err));
+        return QTB_E_DEVICE;
+    }
+    return qtb_vdos_spectrum(d_v, n_samples, n_dof, sample_stride, dof_stride, d_weight, seg,
+                             d_spec, ws, qtb::kVdosScratchBytes, hip_stream);
+}

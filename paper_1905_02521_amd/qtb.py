@@ -88,7 +88,8 @@ class qtb_obs(ctypes.Structure):
 EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
            "qtb_observables", "qtb_get_state", "qtb_set_state", "qtb_evaluate",
            "qtb_get_noise", "qtb_gaussian", "qtb_profile", "qtb_profile_read",
-           "qtb_vdos_workspace_bytes", "qtb_vdos_spectrum", "qtb_vdos_attach", "qtb_vdos_read",
+           "qtb_vdos_workspace_bytes", "qtb_vdos_spectrum", "qtb_vdos_spectrum_noalloc",
+           "qtb_vdos_attach", "qtb_vdos_read",
            "qtb_vdos_detach", "qtb_barostat", "qtb_get_box", "qtb_filter_taps",
            "qtb_last_error", "qtb_destroy", "qtb_version",
            "qtb_ml_workspace_bytes", "qtb_ml_create", "qtb_ml_init_params", "qtb_ml_set_params",
@@ -144,6 +145,9 @@ def lib():
     L.qtb_vdos_spectrum.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                     ctypes.c_int64, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t,
                                     vp]
+    L.qtb_vdos_spectrum_noalloc.restype = ctypes.c_int
+    L.qtb_vdos_spectrum_noalloc.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                            ctypes.c_int64, vp, ctypes.c_int32, vp, vp]
     L.qtb_vdos_attach.restype = ctypes.c_int
     L.qtb_vdos_attach.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_size_t]
     L.qtb_vdos_read.restype = ctypes.c_int
@@ -258,6 +262,25 @@ def vdos_spectrum(v, weight, seg, dof_major=False):
                                    ctypes.c_void_p(weight.data_ptr()), seg,
                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                    nbytes, current_stream_ptr()))
+    return out
+
+
+def vdos_spectrum_noalloc(v, weight, seg, dof_major=False, out=None):
+    """As vdos_spectrum, through the entry point that allocates nothing (its
+    scratch is the library's static per-GPU array); out: optional device
+    tensor [seg/2 + 1] float64 that receives S."""
+    torch = _torch()
+    if dof_major:
+        n_dof, n_samples = v.shape
+    else:
+        n_samples, n_dof = v.shape
+    ts, js = v.stride() if not dof_major else v.stride()[::-1]
+    if out is None:
+        out = torch.empty(seg // 2 + 1, dtype=torch.float64, device=v.device)
+    _check(lib().qtb_vdos_spectrum_noalloc(ctypes.c_void_p(v.data_ptr()), n_samples, n_dof, ts,
+                                           js, ctypes.c_void_p(weight.data_ptr()), seg,
+                                           ctypes.c_void_p(out.data_ptr()),
+                                           current_stream_ptr()))
     return out
 
 
