@@ -126,6 +126,10 @@ def lib():
         L.orc_nm_matrix.argtypes = [ctypes.c_int, _PD]
         L.orc_sim_set_barostat.restype = ctypes.c_int
         L.orc_sim_set_barostat.argtypes = [ctypes.c_void_p, _D, _D, _D]
+        L.orc_sim_set_piston.restype = ctypes.c_int
+        L.orc_sim_set_piston.argtypes = [ctypes.c_void_p, _D, _D, _D]
+        L.orc_sim_piston_momentum.restype = _D
+        L.orc_sim_piston_momentum.argtypes = [ctypes.c_void_p]
         L.orc_sim_box.argtypes = [ctypes.c_void_p, _PD]
     return _lib
 
@@ -340,7 +344,14 @@ class Sim:
 
     def set_barostat(self, P0, tau_p, beta_T):
         if lib().orc_sim_set_barostat(self.h, float(P0), float(tau_p), float(beta_T)):
-            raise ValueError("oracle refused the barostat (P = 1 and the pair kind only)")
+            raise ValueError("oracle refused the barostat (the pair kind only)")
+
+    def set_piston(self, P0, tau_p, gamma_p):
+        if lib().orc_sim_set_piston(self.h, float(P0), float(tau_p), float(gamma_p)):
+            raise ValueError("oracle refused the piston (the pair kind only, T > 0)")
+
+    def piston_momentum(self):
+        return lib().orc_sim_piston_momentum(self.h)
 
     def box(self):
         b = np.zeros(3)

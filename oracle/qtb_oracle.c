@@ -428,9 +428,15 @@ struct orc_sim {
     int *nb_start, *nb_j, nb_cap;
     double *nb_shift;       /* [3 * entries] */
     int nthreads;
-    /* stochastic cell rescaling (isotropic barostat, P = 1, pair kind) */
+    /* isotropic barostat (pair kind): 1 stochastic cell rescaling, 2 Langevin
+     * piston; npt_pe is the piston momentum */
     int npt, nb_force;
     double npt_P0, npt_tau, npt_beta;
+    double npt_W, npt_gp, npt_pe;
+    /* scalings the last barostat update left for the next step: velocities
+     * at its start (sv1) and after its closing kick (sv2), positions before
+     * its forces (sr) */
+    double npt_sr, npt_sv1, npt_sv2;
 };
 
 static int64_t pmod(int64_t a, int64_t m) { int64_t r = a % m; return r < 0 ? r + m : r; }
@@ -745,52 +751,147 @@ double orc_sim_hamiltonian(orc_sim *s)
 }
 
 /*
- * Isotropic stochastic cell rescaling (after Bernetti and Bussi, J. Chem.
- * Phys. 153, 114107 (2020)): one Euler-Maruyama (Ito) step of eps = ln V
- * after the step of step index n,
+ * Pressure of the closed step for the isotropic barostats: the volume
+ * derivative of the ring polymer's configurational weight under uniform
+ * scaling of every bead coordinate, with the instantaneous momenta for the
+ * kinetic part (for P = 1 the virial pressure):
+ *   p = (2K - 2 U_spring + (1/P) sum_s W_s) / (3V),
+ * K the kinetic energy of all beads, U_spring the ring springs of eq. (3)
+ * (homogeneous of degree 2 in the bead coordinates), W_s = sum over pairs of
+ * F(r) r at bead s.  *kin receives K.
+ */
+static double npt_pressure(const orc_sim *s, double *kin)
+{
+    int N = s->N, P = s->P;
+    double mu = s->u.mass_unit;
+    double wP = sqrt((double)P) * s->u.kB * s->T / s->u.hbar;
+    double ke = 0.0, spring = 0.0, W = 0.0;
+    for (int b = 0; b < P; ++b)
+        for (int d = 0; d < 3; ++d)
+            for (int i = 0; i < N; ++i) {
+                double m = s->pot.mass[s->species[i]] * mu;
+                size_t id = ((size_t)b * 3 + d) * N + i;
+                ke += 0.5 * m * s->v[id] * s->v[id];
+                if (P > 1) {
+                    size_t nx = ((size_t)((b + 1) % P) * 3 + d) * N + i;
+                    double dr = s->r[id] - s->r[nx];
+                    spring += 0.5 * m * wP * wP * dr * dr;
+                }
+            }
+    for (int b = 0; b < P; ++b) W += s->wpair[b];
+    double V = s->box[0] * s->box[1] * s->box[2];
+    *kin = ke;
+    return (2.0 * ke - 2.0 * spring + W / P) / (3.0 * V);
+}
+
+/*
+ * One barostat update after the step of step index n (after its closing
+ * kick), g the unit Gaussian at (step n, dof 0, tag 4).  The box scales by s
+ * at once; in the next step every velocity scales by s_v1 at its start and
+ * by s_v2 after its closing kick, and every bead coordinate by sqrt(s) before
+ * and after its A-O-A (so its forces are those of the scaled positions).
+ *
+ * Stochastic cell rescaling (after Bernetti and Bussi, J. Chem. Phys. 153,
+ * 114107 (2020)), one Euler-Maruyama (Ito) step of eps = ln V:
  *   d eps = -(beta_T / tau_p) (P0 - p) dt + sqrt(2 k_B T beta_T dt / (V tau_p)) g,
- * p the instantaneous virial pressure (2K + W) / (3V) of the closed step,
- * g the unit Gaussian at (step n, dof 0, tag 4); positions and box scale by
- * s = e^{d eps / 3}, velocities by 1 / s, and the neighbour list is rebuilt.
+ *   s = e^{d eps / 3},  s_v1 = 1 / s,  s_v2 = 1.
  * With the diffusion in eps proportional to 1 / V, the Ito drift needs no
- * separate k_B T / V term: the stationary law is V^N e^{-P0 V / k_B T} for
- * an ideal gas (pinned).  (The paper cites a Langevin barostat for its
- * constant-pressure runs without giving one; this is the reading used.)
+ * separate k_B T / V term: the stationary law is V^N e^{-P0 V / k_B T} for an
+ * ideal gas (pinned).
+ *
+ * Langevin piston (the isothermal-isobaric Langevin scheme of Quigley and
+ * Probert, J. Chem. Phys. 120, 11432 (2004), isotropic): the strain
+ * eps = ln(V) / 3 has a momentum p_e of mass W_p, driven by
+ *   G = 3V (p - P0) + (3 / N_f) 2K,   N_f = 3 N P,
+ * (the Martyna-Tobias-Klein form, whose invariant law for an ideal gas is
+ * V^N e^{-P0 V / k_B T}) and thermostatted at T with friction gamma_p:
+ *   p_e <- c_p (p_e + dt G / 2) + sqrt((1 - c_p^2) W_p k_B T) g + dt G / 2,
+ *   c_p = e^{-gamma_p dt},  v_e = p_e / W_p,
+ *   s = e^{dt v_e},  s_v1 = s_v2 = e^{-(1 + 3 / N_f) dt v_e / 2},
+ * a symmetric splitting around the particle step (kicks of p_e between
+ * steps, the strain velocity's drag on the momenta half before and half
+ * after the step, the strain's drift with the positions).  The particle
+ * dynamics within a step is that of eq. (4) / (8) with its own thermostat.
+ * (The paper cites the Langevin barostat of refs 11-12 for its
+ * constant-pressure runs without giving its equations; this is the reading.)
  */
 static void barostat_step(orc_sim *s, int64_t n)
 {
-    int N = s->N;
-    double mu = s->u.mass_unit, kT = s->u.kB * s->T;
-    double ke = 0.0;
-    for (int d = 0; d < 3; ++d)
-        for (int i = 0; i < N; ++i) {
-            double m = s->pot.mass[s->species[i]] * mu;
-            double v = s->v[(size_t)d * N + i];
-            ke += 0.5 * m * v * v;
-        }
+    int N = s->N, P = s->P;
+    double kT = s->u.kB * s->T;
+    double ke;
+    double p = npt_pressure(s, &ke);
     double V = s->box[0] * s->box[1] * s->box[2];
-    double p = (2.0 * ke + s->wpair[0]) / (3.0 * V);
     double g = orc_gauss(s->seed, n, 0, s->stream, 4);
-    double deps = -(s->npt_beta / s->npt_tau) * (s->npt_P0 - p) * s->dt +
-                  sqrt(2.0 * kT * s->npt_beta * s->dt / (V * s->npt_tau)) * g;
-    double sc = exp(deps / 3.0);
-    for (int d = 0; d < 3; ++d) s->box[d] *= sc;
-    for (size_t q = 0; q < (size_t)3 * N; ++q) {
-        s->r[q] *= sc;
-        s->v[q] /= sc;
+    double sc, sv1, sv2;
+    if (s->npt == 1) {
+        double deps = -(s->npt_beta / s->npt_tau) * (s->npt_P0 - p) * s->dt +
+                      sqrt(2.0 * kT * s->npt_beta * s->dt / (V * s->npt_tau)) * g;
+        sc = exp(deps / 3.0);
+        sv1 = 1.0 / sc;
+        sv2 = 1.0;
+    } else {
+        double Nf = 3.0 * N * P;
+        double G = 3.0 * V * (p - s->npt_P0) + (3.0 / Nf) * 2.0 * ke;
+        double cp = exp(-s->npt_gp * s->dt);
+        double pe = s->npt_pe + 0.5 * s->dt * G;
+        pe = cp * pe + sqrt((1.0 - cp * cp) * s->npt_W * kT) * g;
+        pe += 0.5 * s->dt * G;
+        s->npt_pe = pe;
+        double ve = pe / s->npt_W;
+        sc = exp(s->dt * ve);
+        sv1 = sv2 = exp(-(1.0 + 3.0 / Nf) * 0.5 * s->dt * ve);
     }
+    for (int d = 0; d < 3; ++d) s->box[d] *= sc;
+    s->npt_sr = sc;
+    s->npt_sv1 = sv1;
+    s->npt_sv2 = sv2;
+}
+
+/* Velocity scaling of the step (start: sv1; after the closing kick: sv2). */
+static void barostat_scale_v(orc_sim *s, double f)
+{
+    size_t n = (size_t)3 * s->N * s->P;
+    for (size_t q = 0; q < n; ++q) s->v[q] *= f;
+}
+
+/* After the step's update (which scaled the positions, half before and half
+ * after its A-O-A): the list follows the new box at the force pass. */
+static void barostat_scale_r(orc_sim *s)
+{
+    s->npt_sr = 1.0;
     s->nb_force = 1;
 }
 
 int orc_sim_set_barostat(orc_sim *s, double P0, double tau_p, double beta_T)
 {
-    if (s->P != 1 || s->pot.kind != ORC_POT_PAIR || !(tau_p > 0.0) || !(beta_T > 0.0)) return 1;
+    if (s->pot.kind != ORC_POT_PAIR || s->dims != 3 || !(tau_p > 0.0) || !(beta_T > 0.0)) return 1;
     s->npt = 1;
     s->npt_P0 = P0;
     s->npt_tau = tau_p;
     s->npt_beta = beta_T;
+    s->npt_sr = s->npt_sv1 = s->npt_sv2 = 1.0;
     return 0;
 }
+
+/* Piston mass W_p = (N_f + 3) k_B T tau_p^2 (tau_p the piston's time scale),
+ * friction gamma_p; the piston starts at rest. */
+int orc_sim_set_piston(orc_sim *s, double P0, double tau_p, double gamma_p)
+{
+    if (s->pot.kind != ORC_POT_PAIR || s->dims != 3 || !(tau_p > 0.0) || !(gamma_p >= 0.0) ||
+        !(s->T > 0.0))
+        return 1;
+    s->npt = 2;
+    s->npt_P0 = P0;
+    s->npt_tau = tau_p;
+    s->npt_gp = gamma_p;
+    s->npt_W = (3.0 * s->N * s->P + 3.0) * s->u.kB * s->T * tau_p * tau_p;
+    s->npt_pe = 0.0;
+    s->npt_sr = s->npt_sv1 = s->npt_sv2 = 1.0;
+    return 0;
+}
+
+double orc_sim_piston_momentum(const orc_sim *s) { return s->npt_pe; }
 
 void orc_sim_box(const orc_sim *s, double *box)
 {
@@ -814,6 +915,8 @@ int orc_sim_run(orc_sim *s, int64_t n_steps, int obs_every, double *obs_out)
     int nobs = 0;
     for (int64_t it = 0; it < n_steps; ++it) {
         int64_t n = s->step;
+        const double rh = s->npt ? sqrt(s->npt_sr) : 1.0;
+        if (s->npt) barostat_scale_v(s, s->npt_sv1);
 #pragma omp parallel for schedule(static) num_threads(s->nthreads)
         for (int i = 0; i < N; ++i) {
             double qq[64], pp[64];
@@ -836,6 +939,8 @@ int orc_sim_run(orc_sim *s, int64_t n_steps, int obs_every, double *obs_out)
                     qq[k] = a; pp[k] = c;
                 }
                 for (int k = 0; k < P; ++k) {
+                    /* the barostat's strain: half of the position scaling */
+                    if (s->npt) qq[k] *= rh;
                     /* A(dt/2) */
                     double w = s->wk[k];
                     if (k == 0) qq[k] += h * pp[k];
@@ -859,6 +964,7 @@ int orc_sim_run(orc_sim *s, int64_t n_steps, int obs_every, double *obs_out)
                         double p1 = -w * sw * qq[k] + cw * pp[k];
                         qq[k] = q1; pp[k] = p1;
                     }
+                    if (s->npt) qq[k] *= rh;  /* the other half */
                 }
                 /* back to beads */
                 for (int b = 0; b < P; ++b) {
@@ -872,6 +978,7 @@ int orc_sim_run(orc_sim *s, int64_t n_steps, int obs_every, double *obs_out)
                 }
             }
         }
+        if (s->npt) barostat_scale_r(s);
         compute_forces(s);
         for (int b = 0; b < P; ++b)
             for (int d = 0; d < dims; ++d)
@@ -880,6 +987,7 @@ int orc_sim_run(orc_sim *s, int64_t n_steps, int obs_every, double *obs_out)
                     size_t id = ((size_t)b * dims + d) * N + i;
                     s->v[id] += h * s->f[id] / (P * m);
                 }
+        if (s->npt) barostat_scale_v(s, s->npt_sv2);
         s->step = n + 1;
         /* slide the white-noise window: row n+1+Nf replaces row n+1-Nf */
         fill_noise_row(s, n + 1 + Nf);

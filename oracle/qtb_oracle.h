@@ -107,10 +107,15 @@ const double *orc_sim_taps(const orc_sim *s, int *two_nf);
 void orc_sim_free(orc_sim *s);
 /* Observables of the current state (the same ORC_NOBS numbers). */
 void orc_sim_observe(orc_sim *s, double *obs);
-/* Isotropic stochastic cell rescaling after every step (P = 1, pair kind):
+/* Isotropic stochastic cell rescaling after every step (pair kind, any P):
  * target pressure P0, relaxation time tau_p, compressibility beta_T (the
  * caller's units).  Returns nonzero if refused. */
 int orc_sim_set_barostat(orc_sim *s, double P0, double tau_p, double beta_T);
+/* Isotropic Langevin piston after every step (pair kind, any P): target
+ * pressure P0, piston time scale tau_p (mass (3 N P + 3) k_B T tau_p^2),
+ * piston friction gamma_p.  Returns nonzero if refused. */
+int orc_sim_set_piston(orc_sim *s, double P0, double tau_p, double gamma_p);
+double orc_sim_piston_momentum(const orc_sim *s);
 /* Current box lengths. */
 void orc_sim_box(const orc_sim *s, double *box);
 /* Hamiltonian of the ring polymer, sum p^2/2m + sum_s [V_s/P + springs]. */
