@@ -364,38 +364,81 @@ qtb_status qtb_vdos_detach(qtb_ctx *ctx, int32_t replica);
 
 /*
  * Constant pressure.  Sec. 2.1 extends the equations of motion to the
- * isothermal-isobaric ensemble with a Langevin barostat, and Sec. 2.2 (Fig. 6)
- * applies QTB-MD at constant pressure to the lattice parameter of a crystal
- * and its isotope shift.  Here the box of a replica follows isotropic
- * stochastic cell rescaling (Bernetti and Bussi, J. Chem. Phys. 153, 114107
- * (2020)), one Euler-Maruyama step of eps = ln V after every step:
- *   d eps = -(beta_T / tau_p) (P0 - p) dt + sqrt(2 k_B T beta_T dt / (V tau_p)) g,
- * p = (2 K + W) / (3 V) the instantaneous virial pressure of the step just
- * closed (K kinetic energy, W = sum over pairs of F(r) r), g a unit Gaussian
- * of the replica's counter-based stream (step n, dof 0, tag 4); positions
- * and box are scaled by s = e^{d eps / 3}, velocities by 1 / s.  The
- * neighbour lists follow the box by a scale factor and are rebuilt when the
- * compression since their build uses up half of the skin.  The list capacity
- * is planned for the initial density: compressing the box by more than about
- * 20 % in volume can overflow it (QTB_E_NOMEM at the next synchronising call).
- * Units: P0 in energy / length^3, tau_p in time, beta_T (isothermal
- * compressibility) in length^3 / energy.
+ * isothermal-isobaric ensemble with a Langevin barostat (cited, not written
+ * out), and Sec. 2.2 (Fig. 6) applies QTB-MD at constant pressure to the
+ * lattice parameter of a crystal and its isotope shift.  Two isotropic
+ * barostats, for classical replicas and ring polymers alike.  After every
+ * step the pressure of the step just closed,
+ *   p = (2 K - 2 U_spring + W / P) / (3 V),
+ * is taken (the ring polymer's primitive pressure; K the kinetic energy of
+ * all beads, U_spring the springs of eq. 3, W the pair virial sum of F(r) r
+ * summed over the beads; for P = 1 the virial pressure), g is a unit
+ * Gaussian of the replica's counter-based stream (step n, dof 0, tag 4), and
+ * the update sets a scale factor s of the box lengths:
  *
- * qtb_barostat: enable (enable != 0) or disable the barostat of a replica.
- * QTB_E_INVALID unless the potential is the pair potential, the context has
- * no surrogate buffers, the replica has P = 1 and three dimensions, every
- * replica is small enough for the force kernel's own list rebuild, the
- * one-kernel step (QTB_OPT_FUSE) is off, and tau_p, beta_T > 0.  Synchronises.
- * While it runs, every step's force pass also computes the observables.
+ *   qtb_barostat: stochastic cell rescaling (Bernetti and Bussi, J. Chem.
+ *   Phys. 153, 114107 (2020)), one Euler-Maruyama step of eps = ln V,
+ *     d eps = -(beta_T / tau_p) (P0 - p) dt + sqrt(2 k_B T beta_T dt / (V tau_p)) g,
+ *     s = e^{d eps / 3},  s_v1 = 1 / s,  s_v2 = 1;
+ *   beta_T the isothermal compressibility (length^3 / energy).
+ *
+ *   qtb_barostat_piston: Langevin piston (Quigley and Probert, J. Chem.
+ *   Phys. 120, 11432 (2004), in the Martyna-Tobias-Klein form): the strain
+ *   ln(V) / 3 has momentum p_e and mass W_p = (3 N P + 3) k_B T tau_p^2
+ *   (tau_p the piston's time scale), driven by G = 3V (p - P0) + (3/N_f) 2K,
+ *   N_f = 3 N P, with friction gamma_p (1 / time):
+ *     p_e <- c (p_e + dt G / 2) + sqrt((1 - c^2) W_p k_B T) g + dt G / 2,
+ *     c = e^{-gamma_p dt},  s = e^{dt p_e / W_p},
+ *     s_v1 = s_v2 = e^{-(1 + 3 / N_f) dt p_e / (2 W_p)}.
+ *   The piston starts at rest; with gamma = gamma_p = 0 the dynamics keeps
+ *   H + P0 V + p_e^2 / (2 W_p) up to the splitting error.
+ *
+ * The next step applies the scalings symmetrically: velocities times s_v1
+ * before its first half-kick, every bead's normal-mode coordinates times
+ * sqrt(s) before and after its A-O-A and the box times s with them (so its
+ * forces see the scaled box and positions), velocities times s_v2 after its
+ * closing half-kick.  Between steps the box is the one the positions were
+ * taken in, and the factors wait as the barostat's state.  Both
+ * sample V^N e^{-P0 V / k_B T} for an ideal gas.  The neighbour lists follow
+ * the box by a scale factor and are rebuilt when the compression since
+ * their build uses up half of the skin.  The list capacity is planned for
+ * the initial density: compressing the box by more than about 20 % in
+ * volume can overflow it (QTB_E_NOMEM at the next synchronising call).
+ * Units: P0 in energy / length^3, tau_p in time.
+ *
+ * Enable with enable != 0, disable with 0 (either call disables whichever
+ * barostat runs).  QTB_E_INVALID unless the potential is the pair potential,
+ * the context has no surrogate buffers, the replica has three dimensions,
+ * every replica is small enough for the force kernel's own list rebuild, the
+ * one-kernel step (QTB_OPT_FUSE) is off, tau_p > 0, P0 finite, beta_T > 0
+ * (cell rescaling) and gamma_p >= 0 (piston).  Synchronises.  While a
+ * barostat runs every step's force pass also computes the observables.
  * Switching it off rebuilds the neighbour lists and recomputes the forces of
- * every replica at the current positions (as qtb_set_state does).
+ * every replica at the current positions (as qtb_set_state does); the
+ * scalings still pending from the last update are applied by the next step.
+ * Force passes between steps (qtb_evaluate, qtb_set_state) see the box and
+ * positions as they are, without the pending factors.
  *
  * qtb_get_box: synchronise and copy the replica's current box lengths
  * (host double[3]); status errors as qtb_observables.
+ *
+ * qtb_get_barostat_state / qtb_set_barostat_state: the part of a replica's
+ * state that a checkpoint needs besides qtb_get_state and the box, host
+ * double[4] = {p_e, s, s_v1, s_v2} (the piston momentum, 0 under cell
+ * rescaling, and the scalings pending for the next step, 1 when none).
+ * To resume exactly: create a context with the saved box, qtb_set_state,
+ * enable the same barostat (which sets p_e = 0), then
+ * qtb_set_barostat_state.  The setter returns QTB_E_INVALID for non-finite
+ * values or non-positive scalings, and where no barostat can run (see
+ * above).  Both synchronise.
  */
 qtb_status qtb_barostat(qtb_ctx *ctx, int32_t replica, double P0, double tau_p, double beta_T,
                         int32_t enable);
+qtb_status qtb_barostat_piston(qtb_ctx *ctx, int32_t replica, double P0, double tau_p,
+                               double gamma_p, int32_t enable);
 qtb_status qtb_get_box(qtb_ctx *ctx, int32_t replica, double *h_box);
+qtb_status qtb_get_barostat_state(qtb_ctx *ctx, int32_t replica, double *h_state);
+qtb_status qtb_set_barostat_state(qtb_ctx *ctx, int32_t replica, const double *h_state);
 
 /*
  * Diagnostics: while enabled, qtb_step records a HIP event pair around every

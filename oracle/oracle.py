@@ -130,6 +130,8 @@ def lib():
         L.orc_sim_set_piston.argtypes = [ctypes.c_void_p, _D, _D, _D]
         L.orc_sim_piston_momentum.restype = _D
         L.orc_sim_piston_momentum.argtypes = [ctypes.c_void_p]
+        L.orc_sim_barostat_state.restype = None
+        L.orc_sim_barostat_state.argtypes = [ctypes.c_void_p, _PD, _PD]
         L.orc_sim_box.argtypes = [ctypes.c_void_p, _PD]
     return _lib
 
@@ -357,6 +359,16 @@ class Sim:
         b = np.zeros(3)
         lib().orc_sim_box(self.h, _pd(b))
         return b
+
+    def barostat_state(self):
+        """(p_e, s, s_v1, s_v2): piston momentum and the pending scalings."""
+        b = np.zeros(4)
+        lib().orc_sim_barostat_state(self.h, _pd(b), None)
+        return b
+
+    def set_barostat_state(self, state):
+        b = np.ascontiguousarray(state, dtype=np.float64)
+        lib().orc_sim_barostat_state(self.h, None, _pd(b))
 
     def hamiltonian(self):
         return lib().orc_sim_hamiltonian(self.h)

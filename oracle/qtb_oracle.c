@@ -434,8 +434,9 @@ struct orc_sim {
     double npt_P0, npt_tau, npt_beta;
     double npt_W, npt_gp, npt_pe;
     /* scalings the last barostat update left for the next step: velocities
-     * at its start (sv1) and after its closing kick (sv2), positions before
-     * its forces (sr) */
+     * at its start (sv1) and after its closing kick (sv2), positions and box
+     * before its forces (sr); between steps the box is the one the positions
+     * were taken in */
     double npt_sr, npt_sv1, npt_sv2;
 };
 
@@ -786,10 +787,10 @@ static double npt_pressure(const orc_sim *s, double *kin)
 
 /*
  * One barostat update after the step of step index n (after its closing
- * kick), g the unit Gaussian at (step n, dof 0, tag 4).  The box scales by s
- * at once; in the next step every velocity scales by s_v1 at its start and
- * by s_v2 after its closing kick, and every bead coordinate by sqrt(s) before
- * and after its A-O-A (so its forces are those of the scaled positions).
+ * kick), g the unit Gaussian at (step n, dof 0, tag 4).  In the next step
+ * every velocity scales by s_v1 at its start and by s_v2 after its closing
+ * kick, every bead coordinate by sqrt(s) before and after its A-O-A, and the
+ * box by s with them (so its forces are those of the scaled system).
  *
  * Stochastic cell rescaling (after Bernetti and Bussi, J. Chem. Phys. 153,
  * 114107 (2020)), one Euler-Maruyama (Ito) step of eps = ln V:
@@ -842,7 +843,6 @@ static void barostat_step(orc_sim *s, int64_t n)
         sc = exp(s->dt * ve);
         sv1 = sv2 = exp(-(1.0 + 3.0 / Nf) * 0.5 * s->dt * ve);
     }
-    for (int d = 0; d < 3; ++d) s->box[d] *= sc;
     s->npt_sr = sc;
     s->npt_sv1 = sv1;
     s->npt_sv2 = sv2;
@@ -856,9 +856,11 @@ static void barostat_scale_v(orc_sim *s, double f)
 }
 
 /* After the step's update (which scaled the positions, half before and half
- * after its A-O-A): the list follows the new box at the force pass. */
+ * after its A-O-A): the box scales with them, and the list follows the new
+ * box at the force pass. */
 static void barostat_scale_r(orc_sim *s)
 {
+    for (int d = 0; d < 3; ++d) s->box[d] *= s->npt_sr;
     s->npt_sr = 1.0;
     s->nb_force = 1;
 }
@@ -892,6 +894,16 @@ int orc_sim_set_piston(orc_sim *s, double P0, double tau_p, double gamma_p)
 }
 
 double orc_sim_piston_momentum(const orc_sim *s) { return s->npt_pe; }
+
+void orc_sim_barostat_state(orc_sim *s, double *get, const double *set)
+{
+    if (get) {
+        get[0] = s->npt_pe; get[1] = s->npt_sr; get[2] = s->npt_sv1; get[3] = s->npt_sv2;
+    }
+    if (set) {
+        s->npt_pe = set[0]; s->npt_sr = set[1]; s->npt_sv1 = set[2]; s->npt_sv2 = set[3];
+    }
+}
 
 void orc_sim_box(const orc_sim *s, double *box)
 {

@@ -116,6 +116,10 @@ int orc_sim_set_barostat(orc_sim *s, double P0, double tau_p, double beta_T);
  * piston friction gamma_p.  Returns nonzero if refused. */
 int orc_sim_set_piston(orc_sim *s, double P0, double tau_p, double gamma_p);
 double orc_sim_piston_momentum(const orc_sim *s);
+/* {p_e, s, s_v1, s_v2}: piston momentum and the scalings pending for the
+ * next step (1 when none; the box between steps is the one the positions
+ * were taken in).  get and/or set may be NULL. */
+void orc_sim_barostat_state(orc_sim *s, double *get, const double *set);
 /* Current box lengths. */
 void orc_sim_box(const orc_sim *s, double *box);
 /* Hamiltonian of the ring polymer, sum p^2/2m + sum_s [V_s/P + springs]. */

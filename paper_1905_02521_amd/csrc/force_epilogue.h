@@ -53,13 +53,14 @@ __device__ __forceinline__ void force_epilogue_src(const RepDev& R, int i, int s
         return;
     }
     const double kick = R.kick[spi];
+    const double sv2 = R.npt_sv2;  // a barostat's pending scaling after the kick (else 1)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const size_t idx = ((size_t)s * 3 + a) * N + i;
         force[idx] = (T)f[a];
         double v = src.vel(s, a);
         if (flags & kKick) {
-            v = __builtin_fma(kick, f[a], v);  // half-kick B(dt/2)
+            v = __builtin_fma(kick, f[a], v) * sv2;  // half-kick B(dt/2)
             if (STORE_V) R.vel[idx] = v;
         }
         vn[a] = v;

@@ -337,77 +337,127 @@ __global__ void __launch_bounds__(256) k_eq9(const RepDev* __restrict__ reps,
     }
 }
 
-// Isotropic stochastic cell rescaling (after Bernetti and Bussi, J. Chem.
-// Phys. 153, 114107 (2020)), one block per replica: the virial pressure
-// p = (2K + W) / (3V) of the step just closed from the force pass's block
-// sums (fixed order), then one Euler-Maruyama (Ito) step of eps = ln V,
+// Isotropic barostats, one block per replica, after the step of replica step
+// n closed (its force pass sampled): the ring polymer's primitive pressure
+//   p = (2K - 2 U_spring + W / P) / (3V)
+// from the force pass's block sums (the order of the observables'
+// reduction), K and U_spring over all beads, W the pair virial summed over
+// the beads (P = 1: the virial pressure), and g the unit Gaussian at
+// (replica step n, dof 0, tag 4).
+//
+// Stochastic cell rescaling (after Bernetti and Bussi, J. Chem. Phys. 153,
+// 114107 (2020)), one Euler-Maruyama (Ito) step of eps = ln V:
 //   d eps = -(beta_T / tau_p) (P0 - p) dt + sqrt(2 k_B T beta_T dt / (V tau_p)) g,
-// g the unit Gaussian at (replica step n, dof 0, tag 4).  With the
-// diffusion in eps proportional to 1/V this samples V^N e^{-P0 V / k_B T} for
-// an ideal gas.  The box scales by s = e^{d eps / 3}; the neighbour lists
-// follow through npt_S (below) until the compression eats into the skin.
+//   s = e^{d eps / 3},  s_v1 = 1 / s,  s_v2 = 1.
+// With the diffusion in eps proportional to 1/V this samples
+// V^N e^{-P0 V / k_B T} for an ideal gas.
+//
+// Langevin piston (Quigley and Probert, J. Chem. Phys. 120, 11432 (2004),
+// isotropic, in the Martyna-Tobias-Klein form): the strain ln(V) / 3 has a
+// momentum p_e of mass W_p, driven by G = 3V (p - P0) + (3 / N_f) 2K,
+// N_f = 3 N P, with friction gamma_p at temperature T:
+//   p_e <- c_p (p_e + dt G / 2) + sqrt((1 - c_p^2) W_p k_B T) g + dt G / 2,
+//   s = e^{dt p_e / W_p},  s_v1 = s_v2 = e^{-(1 + 3 / N_f) dt p_e / (2 W_p)}.
+//
+// The next step applies s_v1 to the velocities before its first kick,
+// sqrt(s) to the normal-mode positions before and after its A-O-A (update
+// kernel), s to the box and the lists' scale after its update
+// (k_npt_commit) and s_v2 after its closing kick (force epilogue); until
+// then box and positions stay consistent, so that force passes between
+// steps see the system as it is.  The neighbour lists follow the box through
+// npt_S (below) until a compression eats into the skin.  A replica whose
+// barostat is off has its pending scalings reset to 1 here, after the step
+// that applied them.
 __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int n_rep,
                                                   const double* __restrict__ partials,
                                                   const StepRef sync)
 {
-    __shared__ double red[2][256];
+    __shared__ double red[3][256];
     const int r = blockIdx.x;
     if (r >= n_rep) return;
     RepDev& R = reps[r];
-    if (!R.npt) return;
-    double ke = 0.0, w = 0.0;
+    if (!R.npt) {
+        if (threadIdx.x == 0) R.npt_sr = R.npt_sv1 = R.npt_sv2 = 1.0;
+        return;
+    }
+    double ke = 0.0, spr = 0.0, w = 0.0;
     for (int b = threadIdx.x; b < R.obs_nblocks; b += blockDim.x) {
         ke += partials[(size_t)(R.obs_block0 + b) * kNobs + 0];
+        spr += partials[(size_t)(R.obs_block0 + b) * kNobs + 2];
         w += partials[(size_t)(R.obs_block0 + b) * kNobs + 5];
     }
     red[0][threadIdx.x] = ke;
-    red[1][threadIdx.x] = w;
+    red[1][threadIdx.x] = spr;
+    red[2][threadIdx.x] = w;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
             red[0][threadIdx.x] += red[0][threadIdx.x + h];
             red[1][threadIdx.x] += red[1][threadIdx.x + h];
+            red[2][threadIdx.x] += red[2][threadIdx.x + h];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         const int64_t n = (sync.clk ? *sync.clk : 0) + sync.off;
         const double V = R.box[0] * R.box[1] * R.box[2];
-        const double p = (2.0 * red[0][0] + red[1][0]) / (3.0 * V);
+        const double K = red[0][0];
+        const double p = (2.0 * K - 2.0 * red[1][0] + red[2][0] / R.P) / (3.0 * V);
         const double g = white_gauss(R.seed, n + R.step_off, 0u, R.stream, 4);
-        const double deps = -(R.npt_beta / R.npt_tau) * (R.npt_P0 - p) * R.dt +
-                            sqrt(2.0 * R.kT * R.npt_beta * R.dt / (V * R.npt_tau)) * g;
-        const double sc = exp(deps / 3.0);
-        for (int a = 0; a < 3; ++a) R.box[a] *= sc;
-        R.npt_s = sc;
+        double sc, sv1, sv2;
+        if (R.npt == 1) {
+            const double deps = -(R.npt_beta / R.npt_tau) * (R.npt_P0 - p) * R.dt +
+                                sqrt(2.0 * R.kT * R.npt_beta * R.dt / (V * R.npt_tau)) * g;
+            sc = exp(deps / 3.0);
+            sv1 = 1.0 / sc;
+            sv2 = 1.0;
+        } else {
+            const double Nf = 3.0 * R.N * R.P;
+            const double G = 3.0 * V * (p - R.npt_P0) + (3.0 / Nf) * 2.0 * K;
+            const double cp = exp(-R.npt_gp * R.dt);
+            double pe = R.npt_pe + 0.5 * R.dt * G;
+            pe = cp * pe + sqrt((1.0 - cp * cp) * R.npt_W * R.kT) * g;
+            pe += 0.5 * R.dt * G;
+            R.npt_pe = pe;
+            const double ve = pe / R.npt_W;
+            sc = exp(R.dt * ve);
+            sv1 = sv2 = exp(-(1.0 + 3.0 / Nf) * 0.5 * R.dt * ve);
+        }
+        R.npt_sr = sc;
+        R.npt_sv1 = sv1;
+        R.npt_sv2 = sv2;
         // The lists keep the geometry of their build, scaled by npt_S.  A pair
-        // left out at the build lay beyond r_c + skin, and lies beyond
-        // npt_S (r_c + skin) now: while npt_S < 1 the displacement allowed
-        // before a rebuild shrinks by (1 - npt_S)(r_c + skin) / 2.  Past half
-        // of the skin the next step's force pass rebuilds.
+        // left out at the build lay beyond r_c + skin + dev_i + dev_j, and
+        // lies beyond S = npt_S s times that when the next force pass runs:
+        // while S < 1 the displacement allowed before a rebuild shrinks by
+        // (1 - S)(r_c + skin) / 2 here and by (1 - S) dev_i in the update
+        // kernel's test.  Past half of the skin the next step's force pass
+        // rebuilds.
         int64_t f1 = (n + 1) % 3, f2 = (n + 2) % 3;
         if (f1 < 0) f1 += 3;
         if (f2 < 0) f2 += 3;
         const bool rebuilt = R.rflag[f1] != 0;  // this step's force pass rebuilt
-        const double S = (rebuilt ? 1.0 : R.npt_S) * sc;
-        R.npt_S = S;
+        if (rebuilt) R.npt_S = 1.0;
+        const double S = R.npt_S * sc;
         const double hs = R.half_skin0 - fmax(0.0, 1.0 - S) * 0.5 * R.r_cs;
         R.half_skin = hs;
         if (hs < 0.5 * R.half_skin0) R.rflag[f2] = 1;
     }
 }
 
-__global__ void __launch_bounds__(256) k_npt_scale(const RepDev* __restrict__ reps, int n_rep)
+// After the update kernel applied a replica's pending scalings to positions
+// and velocities: the box and the lists' scale follow (the update read them
+// before), and only s_v2 stays pending, for the closing kick.
+__global__ void k_npt_commit(RepDev* __restrict__ reps, int n_rep)
 {
-    const RepDev& R = reps[blockIdx.y];
-    if (!R.npt) return;
-    const int64_t n = (int64_t)R.P * R.dims * R.N;
-    const double sc = R.npt_s, isc = 1.0 / sc;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        R.pos[q] *= sc;
-        R.vel[q] *= isc;
-    }
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rep) return;
+    RepDev& R = reps[r];
+    const double sc = R.npt_sr;
+    for (int a = 0; a < 3; ++a) R.box[a] *= sc;
+    R.npt_S *= sc;
+    R.npt_sr = 1.0;
+    R.npt_sv1 = 1.0;
 }
 
 // After k_eq9: record which noise block each half holds (invalidate: none).
@@ -473,13 +523,14 @@ void launch_eq9(hipStream_t st, bool fp64, const RepDev* reps, const FirTile* ti
 }
 
 void launch_barostat(hipStream_t st, RepDev* reps, int n_rep, const double* partials,
-                     StepRef sync, int64_t max_dof)
+                     StepRef sync)
 {
     launch(k_barostat, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, sync);
-    int64_t bx = (max_dof + 255) / 256;
-    if (bx > 256) bx = 256;
-    launch(k_npt_scale, dim3((unsigned)bx, (unsigned)n_rep), dim3(256), 0, st,
-           (const RepDev*)reps, n_rep);
+}
+
+void launch_npt_commit(hipStream_t st, RepDev* reps, int n_rep)
+{
+    launch(k_npt_commit, dim3((n_rep + 63) / 64), dim3(64), 0, st, reps, n_rep);
 }
 
 void launch_eq9_invalidate(hipStream_t st, int64_t* marker)

@@ -817,6 +817,7 @@ void fill_repdev(qtb_ctx* c, int r)
     d.half_skin = 0.5 * c->skin;
     d.half_skin0 = d.half_skin;
     d.npt_S = 1.0;
+    d.npt_sr = d.npt_sv1 = d.npt_sv2 = 1.0;
     d.r_cs = c->rc + c->skin;
     d.r_cut = c->rc;
     for (int a = 0; a < kMaxSpecies; ++a) {
@@ -876,6 +877,10 @@ qtb_status sync_boxes(qtb_ctx* c)
         }
         c->rd[r].npt_S = dev[r].npt_S;
         c->rd[r].half_skin = dev[r].half_skin;
+        c->rd[r].npt_pe = dev[r].npt_pe;
+        c->rd[r].npt_sr = dev[r].npt_sr;
+        c->rd[r].npt_sv1 = dev[r].npt_sv1;
+        c->rd[r].npt_sv2 = dev[r].npt_sv2;
     }
     return QTB_OK;
 }
@@ -1007,9 +1012,9 @@ qtb_status refresh_forces(qtb_ctx* c)
 {
     if (c->npt_used) {  // every list is rebuilt from the current geometry
         if (qtb_status s = sync_boxes(c)) return s;
-        for (auto& d : c->rd) {
+        for (auto& d : c->rd) {  // (a pending box factor still applies next step)
             d.npt_S = 1.0;
-            d.half_skin = d.half_skin0;
+            d.half_skin = d.half_skin0 - std::max(0.0, 1.0 - d.npt_sr) * 0.5 * d.r_cs;
         }
         if (qtb_status s = upload_tables_raw(c)) return s;
     }
@@ -1083,6 +1088,8 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
                 launch_update(c->st, c->fp64, c->pair, g.first, L.upd_threads, dreps, ub + b0, nb, zrow,
                               c->at<int32_t>(L.status), step_ref(c), zmod, L.n_cols);
         }
+        // a barostat's pending box factor, applied to the positions just now
+        if (c->npt_used) launch_npt_commit(c->st, c->at<RepDev>(L.reps), c->n_rep);
     }
     c->rec_extra = 1;
     // the pair potential's force kernel rebuilds flagged lists itself, except
@@ -1107,14 +1114,14 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
                           c->at<int32_t>(L.counts), true, c->pair && !c->ml,
                           c->at<double>(L.cpart), L.cchunks);
     }
-    if (npt) {  // after the sample: observables see the box the step ran in
+    // after the sample: observables see the box the step ran in; once a
+    // barostat has run, replicas whose barostat is off have their pending
+    // scalings cleared here too
+    if (c->npt_used) {
         Phase ph(c, 5);
         c->rec_extra = 0;  // step n itself
-        int64_t max_dof = 0;
-        for (const auto& R : c->reps)
-            max_dof = std::max<int64_t>(max_dof, (int64_t)R.n_beads * R.n_dims * R.n_atoms);
         launch_barostat(c->st, c->at<RepDev>(L.reps), c->n_rep, c->at<double>(L.partials),
-                        step_ref(c), max_dof);
+                        step_ref(c));
     }
     if (check) {  // the pair potential judges the surrogate on the same positions
         launch_plain_forces(c, kCompare);
@@ -1937,38 +1944,100 @@ qtb_status qtb_vdos_detach(qtb_ctx* c, int32_t replica)
     return QTB_OK;
 }
 
-qtb_status qtb_barostat(qtb_ctx* c, int32_t replica, double P0, double tau_p, double beta_T,
-                        int32_t enable)
+namespace {
+// Enable (kind 1 cell rescaling, 2 Langevin piston; q the compressibility or
+// the piston friction) or disable (kind 0) the barostat of a replica.
+qtb_status set_barostat(qtb_ctx* c, int32_t replica, int kind, double P0, double tau_p, double q)
 {
     if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
     if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
-    if (enable) {
+    if (kind) {
         if (!c->pair || c->ml || c->L.ml)
             return fail(c, QTB_E_INVALID, "barostat: pair potential without surrogate buffers only");
-        if (c->reps[replica].n_beads != 1 || c->reps[replica].n_dims != 3)
-            return fail(c, QTB_E_INVALID, "barostat: P = 1 and three dimensions only");
+        if (c->reps[replica].n_dims != 3)
+            return fail(c, QTB_E_INVALID, "barostat: three dimensions only");
         if (list_kernel(c))
             return fail(c, QTB_E_INVALID, "barostat: replicas above the inline-rebuild size");
         if (c->opt.flags & QTB_OPT_FUSE)
             return fail(c, QTB_E_INVALID, "barostat: not with the one-kernel step");
-        if (!(tau_p > 0.0) || !(beta_T > 0.0) || !std::isfinite(P0))
-            return fail(c, QTB_E_INVALID, "barostat: tau_p and beta_T must be positive");
+        if (!(tau_p > 0.0) || !std::isfinite(tau_p) || !std::isfinite(P0))
+            return fail(c, QTB_E_INVALID, "barostat: tau_p must be positive and finite");
+        if (kind == 1 && !(q > 0.0 && std::isfinite(q)))
+            return fail(c, QTB_E_INVALID, "barostat: beta_T must be positive and finite");
+        if (kind == 2 && !(q >= 0.0 && std::isfinite(q)))
+            return fail(c, QTB_E_INVALID, "piston: gamma_p must be non-negative and finite");
     }
     QTB_HIP(c, hipStreamSynchronize(c->st));
     if (qtb_status s = sync_boxes(c)) return s;
     RepDev& d = c->rd[replica];
-    if (enable) c->npt_used = true;
-    d.npt = enable ? 1 : 0;
-    d.npt_P0 = enable ? P0 : 0.0;
-    d.npt_tau = enable ? tau_p : 0.0;
-    d.npt_beta = enable ? beta_T : 0.0;
-    d.npt_s = 1.0;
+    if (kind) c->npt_used = true;
+    const qtb_replica& R = c->reps[replica];
+    d.npt = kind;
+    d.npt_P0 = kind ? P0 : 0.0;
+    d.npt_tau = kind ? tau_p : 0.0;
+    d.npt_beta = kind == 1 ? q : 0.0;
+    d.npt_gp = kind == 2 ? q : 0.0;
+    // piston mass (3 N P + 3) k_B T tau_p^2; the piston starts at rest
+    d.npt_W = kind == 2 ? (3.0 * R.n_atoms * R.n_beads + 3.0) * d.kT * tau_p * tau_p : 0.0;
+    d.npt_pe = 0.0;
     drop_graph(c);  // the step sequence changes
-    qtb_status s = upload_tables(c);
+    qtb_status s = upload_tables_raw(c);  // synchronised above
     if (s) return s;
     // switched off: nothing follows the lists' scale any more, so they are
     // rebuilt from the current geometry (forces recomputed there)
-    if (!enable && d.npt_S != 1.0 && (s = refresh_forces(c))) return s;
+    if (!kind && d.npt_S != 1.0 && (s = refresh_forces(c))) return s;
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    return read_status(c);
+}
+}  // namespace
+
+qtb_status qtb_barostat(qtb_ctx* c, int32_t replica, double P0, double tau_p, double beta_T,
+                        int32_t enable)
+{
+    return set_barostat(c, replica, enable ? 1 : 0, P0, tau_p, beta_T);
+}
+
+qtb_status qtb_barostat_piston(qtb_ctx* c, int32_t replica, double P0, double tau_p,
+                               double gamma_p, int32_t enable)
+{
+    return set_barostat(c, replica, enable ? 2 : 0, P0, tau_p, gamma_p);
+}
+
+qtb_status qtb_get_barostat_state(qtb_ctx* c, int32_t replica, double* h_state)
+{
+    if (!c || !h_state) return fail(c, QTB_E_INVALID, "null argument");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    if (qtb_status s = sync_boxes(c)) return s;
+    const RepDev& d = c->rd[replica];
+    h_state[0] = d.npt_pe;
+    h_state[1] = d.npt_sr;
+    h_state[2] = d.npt_sv1;
+    h_state[3] = d.npt_sv2;
+    return read_status(c);
+}
+
+qtb_status qtb_set_barostat_state(qtb_ctx* c, int32_t replica, const double* h_state)
+{
+    if (!c || !h_state) return fail(c, QTB_E_INVALID, "null argument");
+    if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    if (!c->pair || c->ml || c->L.ml || list_kernel(c) || (c->opt.flags & QTB_OPT_FUSE))
+        return fail(c, QTB_E_INVALID, "barostat state: only where a barostat can run");
+    for (int q = 0; q < 4; ++q)
+        if (!std::isfinite(h_state[q]) || (q > 0 && !(h_state[q] > 0.0)))
+            return fail(c, QTB_E_INVALID, "barostat state: non-finite or non-positive scaling");
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    if (qtb_status s = sync_boxes(c)) return s;
+    c->npt_used = true;  // the barostat kernel clears the scalings after use
+    RepDev& d = c->rd[replica];
+    d.npt_pe = h_state[0];
+    d.npt_sr = h_state[1];
+    d.npt_sv1 = h_state[2];
+    d.npt_sv2 = h_state[3];
+    // the skin the next step leaves for its list scale npt_S s
+    d.half_skin = d.half_skin0 - std::max(0.0, 1.0 - d.npt_S * d.npt_sr) * 0.5 * d.r_cs;
+    drop_graph(c);
+    if (qtb_status s = upload_tables_raw(c)) return s;  // synchronised above
     QTB_HIP(c, hipStreamSynchronize(c->st));
     return read_status(c);
 }

@@ -130,11 +130,20 @@ struct RepDev {
     double* vt;
     int64_t* vt_n;
     int32_t vt_cap;
-    // isotropic stochastic cell rescaling after every step (P = 1, pair
-    // potential); box[] above is then the current box, updated on the device
+    // isotropic barostat after every step (pair potential, any P): 0 off,
+    // 1 stochastic cell rescaling, 2 Langevin piston; box[] above is then
+    // the current box, updated on the device
     int32_t npt;
-    double npt_P0, npt_tau, npt_beta;  // target pressure, relaxation time, compressibility
-    double npt_s;                      // this step's length scale factor
+    double npt_P0, npt_tau;            // target pressure, relaxation / piston time
+    double npt_beta;                   // compressibility (cell rescaling)
+    double npt_W, npt_gp, npt_pe;      // piston mass, friction, momentum
+    // scalings the last barostat update left for the next step (1 when
+    // none): velocities before its first kick (sv1) and after its closing
+    // kick (sv2), normal-mode positions by sqrt(sr) before and after its
+    // A-O-A, box and npt_S by sr after its update.  Every step applies them
+    // (a multiplication by 1 is exact); between steps box, npt_S and the
+    // positions agree.
+    double npt_sr, npt_sv1, npt_sv2;
     double dt;
     // length scale of the box relative to the last list build (1 without a
     // barostat): list entries and reference centroids keep the geometry of
@@ -343,12 +352,14 @@ void launch_eq9(hipStream_t st, bool fp64, const RepDev* reps, const FirTile* ti
                 const double* amp, int amp_stride, const double* tw, int n, void* zeta,
                 int64_t n_cols, const int64_t* clock, int64_t* marker, int K);
 void launch_eq9_invalidate(hipStream_t st, int64_t* marker);
-// Cell rescaling of the replicas with npt set, after the force pass of step
-// n (sync gives n; partials hold that pass's block sums): new box, scale
-// factor, list rebuild flagged for step n + 1; then positions and velocities
-// scaled (max_dof: the largest P dims N).
+// Barostat update of the replicas with npt set, after the force pass of step
+// n (sync gives n; partials hold that pass's block sums): new box, the
+// scalings step n + 1 applies, list rebuild flagged for it; replicas with
+// npt clear have their pending scalings reset to 1.
 void launch_barostat(hipStream_t st, RepDev* reps, int n_rep, const double* partials,
-                     StepRef sync, int64_t max_dof);
+                     StepRef sync);
+// After the update kernel: box and list scale take the pending factor s.
+void launch_npt_commit(hipStream_t st, RepDev* reps, int n_rep);
 int eq9_columns(int n);
 void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
                      int64_t n_rows, uint32_t d0, uint32_t n_dof, double* out);

@@ -10,6 +10,9 @@
 //    zeta, c1 = exp(-gamma dt), applied to the normal modes with the
 //    coloured noise whose spectrum is theta (eq. 7) or kappa_P (eq. 12), as
 //    Sec. 2.3 prescribes for QTB-PIMD.
+// Under a barostat the velocities take the pending scaling s_v1 before B
+// and the normal-mode positions sqrt(s) before and after A-O-A (both 1
+// otherwise).
 //
 // Bead-parallel: one thread per (atom, component, bead); the P x P
 // transforms exchange values through LDS.
@@ -96,7 +99,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
         double kick = R.kick[0];
 #pragma unroll
         for (int q = 1; q < kMaxSpecies; ++q) kick = (sp == q) ? R.kick[q] : kick;
-        v = half_kick(v, kick, f);
+        v = half_kick(v * R.npt_sv1, kick, f);  // barostat's pending velocity scaling
     }
     xr[t] = r;
     xv[t] = v;
@@ -115,7 +118,11 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
         double sig = R.sigma[0];
 #pragma unroll
         for (int qq = 1; qq < kMaxSpecies; ++qq) sig = (sp == qq) ? R.sigma[qq] : sig;
+        // the barostat's pending length scaling, half before and half after
+        const double rh = sqrt(R.npt_sr);
+        q *= rh;
         mode_aoa(q, pm, cw, sw, ws, R.c1, sig, z);
+        q *= rh;
     }
     __syncthreads();
     xr[t] = q;
@@ -148,11 +155,14 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
             cen[il][a] = c;
         }
         __syncthreads();
+        // the lists' scale for this step's force pass: the box factor that
+        // this update applied joins it after the kernel (k_npt_commit)
+        const double lsc = R.npt_S * R.npt_sr;
         if (active && a == 0) {
             double u3[3], u2 = 0.0, d2 = 0.0;
             for (int a2 = 0; a2 < 3; ++a2) {
                 const double x = xr[(a2 * P + s) * A + il];
-                u3[a2] = __builtin_fma(-R.npt_S, ref3[a2], x);  // npt_S = 1: x - ref
+                u3[a2] = __builtin_fma(-lsc, ref3[a2], x);  // lsc = 1: x - ref
                 const double dc = x - cen[il][a2];
                 u2 = nm_acc(u2, u3[a2], u3[a2]);
                 d2 = nm_acc(d2, dc, dc);
@@ -164,8 +174,9 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
             val.w = bits_as<T>(sp);
             ((T4*)R.ub[pout])[(size_t)i * P + s] = val;
             xv[t] = d2;
-            const double lim = devb + R.half_skin;
-            if (!(u2 <= lim * lim)) atomicOr(&flags, 8);
+            // a compressed box (npt_S < 1) shrinks the bead spreads with it
+            const double lim = __builtin_fma(devb, fmin(1.0, lsc), R.half_skin);
+            if (!(u2 <= lim * lim) || !(lim > 0.0)) atomicOr(&flags, 8);
         }
         __syncthreads();
         if (t < A && be.atom0 + t < N) {

@@ -90,7 +90,8 @@ EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
            "qtb_get_noise", "qtb_gaussian", "qtb_profile", "qtb_profile_read",
            "qtb_vdos_workspace_bytes", "qtb_vdos_spectrum", "qtb_vdos_spectrum_noalloc",
            "qtb_vdos_attach", "qtb_vdos_read",
-           "qtb_vdos_detach", "qtb_barostat", "qtb_get_box", "qtb_filter_taps",
+           "qtb_vdos_detach", "qtb_barostat", "qtb_barostat_piston", "qtb_get_box",
+           "qtb_get_barostat_state", "qtb_set_barostat_state", "qtb_filter_taps",
            "qtb_last_error", "qtb_destroy", "qtb_version",
            "qtb_ml_workspace_bytes", "qtb_ml_create", "qtb_ml_init_params", "qtb_ml_set_params",
            "qtb_ml_get_params", "qtb_ml_attach", "qtb_ml_evaluate", "qtb_ml_fit_norm",
@@ -158,8 +159,15 @@ def lib():
     L.qtb_barostat.restype = ctypes.c_int
     L.qtb_barostat.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_int32]
+    L.qtb_barostat_piston.restype = ctypes.c_int
+    L.qtb_barostat_piston.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int32]
     L.qtb_get_box.restype = ctypes.c_int
     L.qtb_get_box.argtypes = [vp, ctypes.c_int32, _PD]
+    L.qtb_get_barostat_state.restype = ctypes.c_int
+    L.qtb_get_barostat_state.argtypes = [vp, ctypes.c_int32, _PD]
+    L.qtb_set_barostat_state.restype = ctypes.c_int
+    L.qtb_set_barostat_state.argtypes = [vp, ctypes.c_int32, _PD]
     L.qtb_profile.restype = ctypes.c_int
     L.qtb_profile.argtypes = [vp, ctypes.c_int32]
     L.qtb_profile_read.restype = ctypes.c_int
@@ -471,10 +479,29 @@ class Context:
         _check(lib().qtb_barostat(self.ctx, replica, float(P0), float(tau_p), float(beta_T),
                                   1 if enable else 0), self.ctx)
 
+    def piston(self, replica, P0, tau_p, gamma_p, enable=True):
+        """Isotropic Langevin piston of a replica's box (P0 in energy /
+        length^3, tau_p the piston's time scale, gamma_p its friction in
+        1 / time)."""
+        _check(lib().qtb_barostat_piston(self.ctx, replica, float(P0), float(tau_p),
+                                         float(gamma_p), 1 if enable else 0), self.ctx)
+
     def box(self, replica=0):
         b = np.zeros(3)
         _check(lib().qtb_get_box(self.ctx, replica, _pd(b)), self.ctx)
         return b
+
+    def barostat_state(self, replica=0):
+        """(p_e, s, s_v1, s_v2): piston momentum and the pending scalings."""
+        b = np.zeros(4)
+        _check(lib().qtb_get_barostat_state(self.ctx, replica, _pd(b)), self.ctx)
+        return b
+
+    def set_barostat_state(self, replica, state):
+        b = np.ascontiguousarray(state, dtype=np.float64)
+        if b.shape != (4,):
+            raise ValueError("barostat state is (p_e, s, s_v1, s_v2)")
+        _check(lib().qtb_set_barostat_state(self.ctx, replica, _pd(b)), self.ctx)
 
     # -- surrogate --------------------------------------------------------------
     def ml_attach(self, model, check_every=0):

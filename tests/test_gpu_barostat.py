@@ -1,14 +1,20 @@
-"""Constant pressure on the GPU: isotropic stochastic cell rescaling of the
-box after every step (the isothermal-isobaric extension of Sec. 2.1, used for
-the lattice parameters of Sec. 2.2, Fig. 6).
+"""Constant pressure on the GPU: the isotropic barostats after every step
+(the isothermal-isobaric extension of Sec. 2.1, used for the lattice
+parameters of Sec. 2.2, Fig. 6): stochastic cell rescaling and the Langevin
+piston, for classical replicas and ring polymers.
 
-* Parity: an FP64 QTB trajectory of the compressed MgO crystal under a
-  barostat fast enough to expand the box by several tenths of a per cent in
-  128 steps follows the oracle's (same counter-based Gaussians, tag 4 for the
-  barostat) in positions, velocities, box and the sampled pressure to 1e-9,
-  through eager steps and a replayed graph block; switching the barostat off
-  freezes the box again.  Beside it, constant-volume replicas of the same
-  context (QTB-PIMD and classical) still follow their oracle runs.
+* Parity: FP64 trajectories of the compressed MgO crystal, QTB (P = 1) and
+  QTB-PIMD (P = 4), under barostats fast enough to move the box by several
+  tenths of a per cent to a few per cent in 128 steps follow the oracle's
+  (same counter-based Gaussians, tag 4 for the barostat) in positions,
+  velocities, box, piston momentum, pending scalings, the forces of a force
+  pass between steps and the sampled pressure to 1e-9, through eager steps
+  and a replayed graph block; switching the barostat off freezes the box
+  again.  Beside it, constant-volume replicas of the same context
+  (QTB-PIMD and classical) still follow their oracle runs.
+* Checkpoint: a piston run of ring polymers stopped after 64 steps and
+  resumed in a new context from its state, box and barostat state continues
+  as the uninterrupted run does.
 * Statistics: at P0 = 0 the mean lattice parameter of 512-atom crystals
   (production precision; classical Langevin and QTB at 50 and 300 K, QTB at
   50 K for a second isotope) agrees with the zero of the constant-volume equation of state
@@ -34,23 +40,49 @@ def _gpu():
     qtb.lib()
 
 
-@pytest.mark.parametrize("P0", [0.0, 0.2])   # eV/A^3: expansion; compression
-def test_barostat_trajectory_matches_oracle(orc, P0):
-    """Skin 0.3 A: the lists follow the box through their scale factor, and
-    under P0 = 0.2 the compression (a few per cent in length) eats into the
-    skin past half of it, so that the force pass rebuilds them (the oracle
-    rebuilds at every step)."""
-    beads, sp, box = crystal(3, 1, seed=7)
+def _npt_pair(orc, kind, P, P0, seed=13):
+    """GPU context and oracle run of the compressed 216-atom crystal (skin
+    0.3 A) under one barostat: cell rescaling tau_p = 20 fs, beta_T = 0.5
+    A^3/eV, or a piston of time scale 200 fs and friction 0.01 / fs."""
+    beads, sp, box = crystal(3, P, seed=7, bead_spread=0.02 if P > 1 else 0.0)
     pot = W.mgo_potential(skin=0.3)
-    T, gamma, dt, seed, two_nf = 300.0, 5e-3, 1.0, 13, 256
-    tau_p, beta_T = 20.0, 0.5   # fs, A^3/eV
-    ctx = gpu_crystal_ctx(beads, sp, box, T=T, gamma=gamma, dt=dt, noise=1, prec=qtb.PREC_FP64,
-                          fir=qtb.FIR_FP64, seed=seed, max_two_nf=two_nf, obs_every=4, pot=pot)
-    ctx.build_filter(0, 1, two_nf)
-    ctx.barostat(0, P0, tau_p, beta_T)
-    osim = orc.Sim(oracle_pair_pot(orc, pot), oracle_units(orc, False), beads.shape[2], 1, 3, box, sp,
-                   T, gamma, dt, seed, 0, 1, two_nf, beads, n_threads=8)
-    osim.set_barostat(P0, tau_p, beta_T)
+    noise = 2 if P > 1 else 1
+    T, gamma, dt, two_nf = 300.0, 5e-3, 1.0, 256
+    ctx = gpu_crystal_ctx(beads, sp, box, T=T, gamma=gamma, dt=dt, noise=noise,
+                          prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, seed=seed, max_two_nf=two_nf,
+                          obs_every=4, pot=pot)
+    ctx.build_filter(0, noise, two_nf)
+    osim = orc.Sim(oracle_pair_pot(orc, pot), oracle_units(orc, False), beads.shape[2], P, 3, box,
+                   sp, T, gamma, dt, seed, 0, noise, two_nf, beads, n_threads=8)
+    if kind == "rescale":
+        ctx.barostat(0, P0, 20.0, 0.5)
+        osim.set_barostat(P0, 20.0, 0.5)
+    else:
+        ctx.piston(0, P0, 200.0, 0.01)
+        osim.set_piston(P0, 200.0, 0.01)
+    return ctx, osim, box
+
+
+def _compare(ctx, osim, k=0, box_tol=1e-12):
+    r, v, st = ctx.get_state(k)
+    ro, vo, _, sto = osim.state()
+    assert st == sto
+    b, bo = ctx.box(k), osim.box()
+    assert np.max(np.abs(b - bo)) <= box_tol * bo[0], (b, bo)
+    assert np.sqrt(np.mean((r - ro) ** 2)) <= 1e-9 * 0.0421
+    assert np.sqrt(np.mean((v - vo) ** 2)) <= 1e-9 * np.sqrt(np.mean(vo ** 2))
+    return b
+
+
+@pytest.mark.parametrize("kind,P,P0", [("rescale", 1, 0.0), ("rescale", 1, 0.2),
+                                       ("rescale", 4, 0.2), ("piston", 1, 0.0),
+                                       ("piston", 1, 0.1), ("piston", 4, 0.0)])
+def test_barostat_trajectory_matches_oracle(orc, kind, P, P0):
+    """Skin 0.3 A: the lists follow the box through their scale factor, and
+    under compression (P0 = 0.1 and 0.2 eV/A^3, a few per cent in length)
+    the compression eats into the skin past half of it, so that the force
+    pass rebuilds them (the oracle rebuilds at every step)."""
+    ctx, osim, box = _npt_pair(orc, kind, P, P0)
     ip = orc.OBS_NAMES.index("pressure")
     obs_o = []
     # the first noise block runs eagerly (10 + 54 steps), the second is a
@@ -58,27 +90,69 @@ def test_barostat_trajectory_matches_oracle(orc, P0):
     for n in (10, 54, 64):
         ctx.step(n)
         obs_o.append(osim.run(n, 4))
-        r, v, st = ctx.get_state(0)
-        ro, vo, _, sto = osim.state()
-        assert st == sto
-        b, bo = ctx.box(0), osim.box()
-        print(f"step {st}: box {b[0]:.8f} (oracle {bo[0]:.8f}, start {box[0]:.8f})")
-        assert np.max(np.abs(b - bo)) <= 1e-12 * bo[0]
-        assert np.sqrt(np.mean((r - ro) ** 2)) <= 1e-9 * 0.0421
-        assert np.sqrt(np.mean((v - vo) ** 2)) <= 1e-9 * np.sqrt(np.mean(vo ** 2))
+        b = _compare(ctx, osim)
+        print(f"{kind} P={P} P0={P0} step {osim.state()[3]}: box {b[0]:.8f} "
+              f"(start {box[0]:.8f})")
+        # between steps box and positions agree: a force pass there gives
+        # the forces the step computed (and the next step starts from)
+        f, _ = ctx.evaluate(0)
+        fo = osim.state()[2]
+        assert np.max(np.abs(f - fo)) <= 1e-9 * np.max(np.abs(fo))
+        bs, bs_o = ctx.barostat_state(0), osim.barostat_state()
+        assert abs(bs[0] - bs_o[0]) <= 1e-9 * max(abs(bs_o[0]), 1.0), (bs, bs_o)
+        assert np.max(np.abs(bs[1:] - bs_o[1:])) <= 1e-12, (bs, bs_o)
     assert abs(b[0] / box[0] - 1.0) > 2e-3          # the box did move
-    assert (b[0] > box[0]) == (P0 == 0.0)
+    if kind == "rescale":
+        assert (b[0] > box[0]) == (P0 == 0.0)
     g = ctx.observables(0)
     o = np.concatenate(obs_o)
     assert g["n_samples"] == len(o) == 32
     assert abs(g["pressure"] - o[:, ip].mean()) <= 1e-9 * abs(o[:, ip]).max()
     assert g["volume"] > 0.0
-    # off again: the box stays where it is
-    ctx.barostat(0, 0.0, 1.0, 1.0, enable=False)
-    b0 = ctx.box(0)
+    # off again: the next step still applies the pending factor, then the
+    # box stays where it is
+    if kind == "rescale":
+        ctx.barostat(0, 0.0, 1.0, 1.0, enable=False)
+    else:
+        ctx.piston(0, 0.0, 1.0, 0.0, enable=False)
+    b0, s_pending = ctx.box(0), ctx.barostat_state(0)[1]
+    ctx.step(1)
+    b1 = ctx.box(0)
+    assert np.array_equal(b1, b0 * s_pending)
+    assert np.array_equal(ctx.barostat_state(0)[1:], np.ones(3))
     ctx.step(20)
-    assert np.array_equal(ctx.box(0), b0)
+    assert np.array_equal(ctx.box(0), b1)
     ctx.close()
+
+
+def test_piston_checkpoint_resume(orc):
+    """QTB-PIMD (P = 4) under the piston: 64 steps, then the state, box and
+    barostat state go to a new context, which runs 64 more steps; both that
+    run and the uninterrupted one match the oracle's 128 steps."""
+    ctx, osim, box = _npt_pair(orc, "piston", 4, 0.0)
+    ctx.step(64)
+    r, v, st = ctx.get_state(0)
+    bx, bs = ctx.box(0), ctx.barostat_state(0)
+    assert bs[1] != 1.0   # a scaling is pending
+    ctx.step(64)
+    osim.run(128)
+    _compare(ctx, osim)
+    ctx.close()
+    beads, sp, _ = crystal(3, 4, seed=7, bead_spread=0.02)
+    ctx2 = gpu_crystal_ctx(beads, sp, bx, T=300.0, gamma=5e-3, dt=1.0, noise=2,
+                           prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, seed=13, max_two_nf=256,
+                           obs_every=4, pot=W.mgo_potential(skin=0.3))
+    ctx2.build_filter(0, 2, 256)
+    ctx2.set_state(0, r, v, st)
+    ctx2.piston(0, 0.0, 200.0, 0.01)
+    ctx2.set_barostat_state(0, bs)
+    assert np.array_equal(ctx2.barostat_state(0), bs)
+    assert np.array_equal(ctx2.box(0), bx)
+    ctx2.step(64)
+    _compare(ctx2, osim)
+    with pytest.raises(qtb.QtbError):
+        ctx2.set_barostat_state(0, [0.0, 1.0, -1.0, 1.0])
+    ctx2.close()
 
 
 def test_barostat_beside_constant_volume_replicas(orc):
@@ -124,25 +198,27 @@ def test_barostat_beside_constant_volume_replicas(orc):
 
 
 def test_barostat_rejected_where_unsupported():
-    beads, sp, box = crystal(2, 4, seed=1)
-    ctx = gpu_crystal_ctx(beads, sp, box, T=100.0, gamma=1e-3, dt=1.0, noise=2,
-                          prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, max_two_nf=128)
-    with pytest.raises(qtb.QtbError):   # P = 4
-        ctx.barostat(0, 0.0, 100.0, 1.0)
-    ctx.close()
     beads, sp, box = crystal(2, 1, seed=1)
     ctx = gpu_crystal_ctx(beads, sp, box, T=100.0, gamma=1e-3, dt=1.0, noise=1,
                           prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, max_two_nf=128)
-    for args in ((0.0, 0.0, 1.0), (0.0, 100.0, -1.0), (float("nan"), 100.0, 1.0)):
+    for args in ((0.0, 0.0, 1.0), (0.0, 100.0, -1.0), (float("nan"), 100.0, 1.0),
+                 (0.0, float("inf"), 1.0)):
         with pytest.raises(qtb.QtbError):
             ctx.barostat(0, *args)
+    for args in ((0.0, 0.0, 0.01), (0.0, 100.0, -0.01), (float("nan"), 100.0, 0.0)):
+        with pytest.raises(qtb.QtbError):
+            ctx.piston(0, *args)
     with pytest.raises(qtb.QtbError):
         ctx.barostat(1, 0.0, 100.0, 1.0)
+    with pytest.raises(qtb.QtbError):
+        ctx.set_barostat_state(0, [float("nan"), 1.0, 1.0, 1.0])
     ctx.close()
     ctx = gpu_crystal_ctx(beads, sp, box, T=100.0, gamma=1e-3, dt=1.0, noise=1,
                           prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, max_two_nf=128, fuse=True)
     with pytest.raises(qtb.QtbError):   # not with the one-kernel step
         ctx.barostat(0, 0.0, 100.0, 1.0)
+    with pytest.raises(qtb.QtbError):
+        ctx.piston(0, 0.0, 100.0, 0.0)
     ctx.close()
 
 
