@@ -15,6 +15,9 @@ piston, for classical replicas and ring polymers.
 * Checkpoint: a piston run of ring polymers stopped after 64 steps and
   resumed in a new context from its state, box and barostat state continues
   as the uninterrupted run does.
+* Ring polymers: QTB-PIMD (P = 4) at 50 K under either barostat reaches the
+  lattice parameter where the constant-volume ring-polymer pressure
+  vanishes.
 * Statistics: at P0 = 0 the mean lattice parameter of 512-atom crystals
   (production precision; classical Langevin and QTB at 50 and 300 K, QTB at
   50 K for a second isotope) agrees with the zero of the constant-volume equation of state
@@ -220,6 +223,81 @@ def test_barostat_rejected_where_unsupported():
     with pytest.raises(qtb.QtbError):
         ctx.piston(0, 0.0, 100.0, 0.0)
     ctx.close()
+
+
+RP_LAT = (4.240, 4.2475, 4.255)
+
+
+def test_ring_polymer_npt_matches_constant_volume_pressure():
+    """QTB-PIMD (P = 4, kappa_P noise) of the 512-atom crystal at 50 K in
+    production precision.  At P0 = 0, eight replicas under the Langevin
+    piston (time scale 500 fs, friction 0.005 / fs) and eight under cell
+    rescaling (tau_p = 500 fs, beta_T = 1 A^3/eV) give the mean lattice
+    parameter; four constant-volume replicas at each of three lattice
+    parameters give the primitive ring-polymer pressure p(a), whose zero (the
+    quadratic through the three means) is the same quantity.  The two
+    barostats and the equation of state agree within four combined standard
+    errors: the ring-polymer pressure, its estimator and both barostats'
+    invariant laws are consistent in the quantum regime."""
+    P, T, noise = 4, 50.0, 2
+    potd = qtb.pair_potential_dict(W.mgo_potential(skin=1.0))
+    keys, reps = [], []
+
+    def add(kind, a, seed):
+        pos, sp, box = W.rocksalt(4, a)
+        base = W.displaced(pos, 0.01 * a, seed)
+        beads = np.stack([W.displaced(base, 0.005, 1000 + 10 * seed + b) for b in range(P)])
+        reps.append(qtb.Replica(pos=beads, species=sp, T=T, gamma=1e-3, dt=1.0, noise=noise,
+                                box=tuple(box), seed=100 + len(reps), stream=len(reps)))
+        keys.append((kind, a))
+    for k in range(8):
+        add("piston", 4.2475, 40 + k)
+        add("rescale", 4.2475, 50 + k)
+    for a in RP_LAT:
+        for k in range(4):
+            add("nvt", a, 60 + k)
+    ctx = qtb.Context(potd, reps, dict(W.METAL_UNITS), prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3,
+                      obs_every=8, max_two_nf=512)
+    for r, (kind, _) in enumerate(keys):
+        ctx.build_filter(r, noise, 512)
+        if kind == "piston":
+            ctx.piston(r, 0.0, 500.0, 0.005)
+        elif kind == "rescale":
+            ctx.barostat(r, 0.0, 500.0, 1.0)
+    ctx.step(20_000)
+    for r in range(len(keys)):
+        ctx.observables(r)
+    blocks = {k: [] for k in ("piston", "rescale") + RP_LAT}
+    for _ in range(16):
+        ctx.step(5000)
+        acc = {k: [] for k in blocks}
+        for r, (kind, a) in enumerate(keys):
+            o = ctx.observables(r)
+            if kind == "nvt":
+                acc[a].append(o["pressure"])
+            else:
+                acc[kind].append(o["volume"])
+        for k in ("piston", "rescale"):
+            blocks[k].append(np.mean(acc[k]) ** (1.0 / 3.0) / 4.0)
+        for a in RP_LAT:
+            blocks[a].append(np.mean(acc[a]))
+    ctx.close()
+    ms = {k: (np.mean(b), np.std(b, ddof=1) / math.sqrt(len(b))) for k, b in blocks.items()}
+    pm = np.array([ms[a][0] for a in RP_LAT])
+    c = np.polyfit(np.array(RP_LAT) - RP_LAT[1], pm, 2)
+    roots = np.roots(c).real + RP_LAT[1]
+    a_eos = roots[np.argmin(np.abs(roots - RP_LAT[1]))]
+    slope = (pm[2] - pm[0]) / (RP_LAT[2] - RP_LAT[0])
+    se_eos = max(ms[a][1] for a in RP_LAT) / abs(slope)
+    for a in RP_LAT:
+        print(f"p({a:.4f} A) = {ms[a][0]:+.5f} +- {ms[a][1]:.5f} eV/A^3")
+    print(f"zero of p(a): {a_eos:.5f} +- {se_eos:.5f} A")
+    for k in ("piston", "rescale"):
+        m, se = ms[k]
+        print(f"{k}: <a> = {m:.5f} +- {se:.5f} A")
+        assert se < 1e-4
+        assert abs(m - a_eos) < 4 * math.hypot(se, se_eos), (k, m, a_eos)
+    assert pm[0] > 0 > pm[2]   # the zero lies inside the scanned interval
 
 
 # zeros of the constant-volume p(a) (same potential, precision, dt, gamma
