@@ -139,7 +139,7 @@ template <typename T, int NS, bool FAST, int DEG, int MODE, int G>
 __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& tab,
                                          const PairPos<T, MODE>& pp, int i, int s, int ch,
                                          int ST, bool want_e, double& fx, double& fy, double& fz,
-                                         double& e, double& w, int& spi)
+                                         double& e, double& w, int& spi, double lscale)
 {
     using V4 = typename NV<T>::v4;
     const V4 ui = pp.at(i, s);
@@ -176,9 +176,10 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
     const T ph_s = tab.ph_s;
     const int maxnb = R.maxnb;
     const int cnt = R.nb_count[i], ncore = R.nb_core[i];
-    // entries of a list built before the box last changed scale with it
-    // (entries built in this pass, MODE kPosRef, have the current geometry)
-    const T lsc = (T)R.npt_S;
+    // entries of a list built before the box last changed scale with it,
+    // by lscale (entries built in this pass, MODE kPosRef, have the current
+    // geometry)
+    const T lsc = (T)lscale;
 
     auto pair = [&](const V4 E0, const V4 U0) {
         T dx, dy, dz;
@@ -388,7 +389,7 @@ template <typename T>
 __device__ void rebuild_list(const RepDev& R, int i, bool active, const double* cx,
                              const double* cy, const double* cz, const double* dv,
                              int32_t* status, double* tx, double* ty, double* tz, double* td,
-                             double* dmax_s)
+                             double* dmax_s, double box_scale)
 {
     using V4 = typename NV<T>::v4;
     const int N = R.N;
@@ -400,7 +401,7 @@ __device__ void rebuild_list(const RepDev& R, int i, bool active, const double* 
         zi = cz[i];
         devi = dv[i];
     }
-    const double Lx = R.box[0], Ly = R.box[1], Lz = R.box[2];
+    const double Lx = R.box[0] * box_scale, Ly = R.box[1] * box_scale, Lz = R.box[2] * box_scale;
     const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
     double dmax = 0.0;
     for (int j = threadIdx.x; j < N; j += 256) dmax = fmax(dmax, dv[j]);
@@ -521,9 +522,14 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (WE ? 5 : 7)))) k_force_
         }
     }
     const double* __restrict__ cen = R.cnb[si.p];
+    // Within a step (kKick) the positions already carry a barostat's pending
+    // box factor npt_sr, which the box and the lists' scale take at the end
+    // of the step (k_barostat); between steps they agree as they are.
+    const double bsc = (flags & kKick) ? R.npt_sr : 1.0;
+    const double lscale = R.npt_S * bsc;
     if (rebuild) {
         rebuild_list<T>(R, i, active && wsub == 0, cen, cen + N, cen + 2 * (size_t)N,
-                        R.devn[si.p], status, tx, ty, tz, td, dmax_s);
+                        R.devn[si.p], status, tx, ty, tz, td, dmax_s, bsc);
         if (active && wsub == 0) {
             // new references and relative positions of the atom, as the list kernel
             if (lane < 3) R.rrefb[si.p][(size_t)lane * N + i] = cen[(size_t)lane * N + i];
@@ -546,13 +552,13 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (WE ? 5 : 7)))) k_force_
             const PairPos<T, kPosRef> pp{nullptr, nullptr, (gptr<double>)cen, N, P,
                                          (gptr<double>)R.pos, (gptr<int32_t>)R.species};
             pair_sum<T, NS, FAST, DEG, kPosRef, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy, fz,
-                                                e, vir, spi);
+                                                e, vir, spi, 1.0);
         } else {
             // u is atom-major [N][P]: the G beads of a neighbour share cache lines
             const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[si.p] + 0, nullptr, nullptr, N, P,
                                             nullptr, nullptr};
             pair_sum<T, NS, FAST, DEG, kPosDirect, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
-                                                   fz, e, vir, spi);
+                                                   fz, e, vir, spi, lscale);
         }
     }
     reduce_atom<G>(fx, fy, fz, e, vir, want_e, W, wave, wsub, lane, part);
@@ -636,7 +642,7 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
     const double* __restrict__ rin = R.rrefb[pin];
     if (rebuild)
         rebuild_list<T>(R, i, active && wsub == 0, cin, cin + N, cin + 2 * (size_t)N, R.devn[pin],
-                        status, tx, ty, tz, td, dmax_s);
+                        status, tx, ty, tz, td, dmax_s, 1.0);
     double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, vir = 0.0;
     int spi = 0;
     if (active) {
@@ -644,12 +650,13 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
             const PairPos<T, kPosRecon> pp{(gptr<V4>)R.ub[pin] + 0, (gptr<double>)rin,
                                            (gptr<double>)cin, N, P, nullptr, nullptr};
             pair_sum<T, NS, FAST, DEG, kPosRecon, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
-                                                  fz, e, vir, spi);
+                                                  fz, e, vir, spi, 1.0);
         } else {
+            // (no barostat with the one-kernel step)
             const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[pin] + 0, nullptr, nullptr, N, P,
                                             nullptr, nullptr};
             pair_sum<T, NS, FAST, DEG, kPosDirect, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
-                                                   fz, e, vir, spi);
+                                                   fz, e, vir, spi, R.npt_S);
         }
     }
     reduce_atom<G>(fx, fy, fz, e, vir, want_e, W, wave, wsub, lane, part);
@@ -955,9 +962,12 @@ __global__ void __launch_bounds__(256) k_obs_reduce(const RepDev* __restrict__ r
             a[6] += kc;
         }
         if (pair) {
-            // volume of this sample's box (it changes under the barostat) and
-            // the primitive pressure (2K - 2 U_spring + W / P) / (3V)
-            const double V = R.box[0] * R.box[1] * R.box[2];
+            // volume of this sample's box (it changes under the barostat: the
+            // positions already carry the pending factor npt_sr, the box
+            // takes it at the end of the step) and the primitive pressure
+            // (2K - 2 U_spring + W / P) / (3V)
+            const double sr = R.npt_sr;
+            const double V = (R.box[0] * sr) * (R.box[1] * sr) * (R.box[2] * sr);
             a[kNobs] += V;
             a[kNobs + 1] += (2.0 * red[0][0] - 2.0 * red[2][0] + red[5][0] / R.P) / (3.0 * V);
         }

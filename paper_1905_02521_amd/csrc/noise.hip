@@ -361,13 +361,13 @@ __global__ void __launch_bounds__(256) k_eq9(const RepDev* __restrict__ reps,
 //
 // The next step applies s_v1 to the velocities before its first kick,
 // sqrt(s) to the normal-mode positions before and after its A-O-A (update
-// kernel), s to the box and the lists' scale after its update
-// (k_npt_commit) and s_v2 after its closing kick (force epilogue); until
-// then box and positions stay consistent, so that force passes between
-// steps see the system as it is.  The neighbour lists follow the box through
-// npt_S (below) until a compression eats into the skin.  A replica whose
-// barostat is off has its pending scalings reset to 1 here, after the step
-// that applied them.
+// kernel) and s_v2 after its closing kick (force epilogue); its force pass
+// and sample take box and list scale times s, and this kernel, at the end of
+// that step, first commits s to them.  Between steps box and positions so
+// agree, and force passes there see the system as it is.  The neighbour
+// lists follow the box through npt_S (below) until a compression eats into
+// the skin.  A replica whose barostat is off has its pending factors
+// committed and reset to 1 here, after the step that applied them.
 __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int n_rep,
                                                   const double* __restrict__ partials,
                                                   const StepRef sync)
@@ -376,6 +376,20 @@ __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int
     const int r = blockIdx.x;
     if (r >= n_rep) return;
     RepDev& R = reps[r];
+    int64_t f1 = 0, f2 = 0;
+    {
+        const int64_t n = (sync.clk ? *sync.clk : 0) + sync.off;
+        f1 = (n + 1) % 3;
+        f2 = (n + 2) % 3;
+        if (f1 < 0) f1 += 3;
+        if (f2 < 0) f2 += 3;
+    }
+    if (threadIdx.x == 0) {  // the factor this step applied: box and list scale follow
+        const double sr = R.npt_sr;
+        for (int a = 0; a < 3; ++a) R.box[a] *= sr;
+        // this step's force pass rebuilt the lists: entries in its geometry
+        R.npt_S = R.rflag[f1] != 0 ? 1.0 : R.npt_S * sr;
+    }
     if (!R.npt) {
         if (threadIdx.x == 0) R.npt_sr = R.npt_sv1 = R.npt_sv2 = 1.0;
         return;
@@ -400,7 +414,7 @@ __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int
     }
     if (threadIdx.x == 0) {
         const int64_t n = (sync.clk ? *sync.clk : 0) + sync.off;
-        const double V = R.box[0] * R.box[1] * R.box[2];
+        const double V = R.box[0] * R.box[1] * R.box[2];  // committed above
         const double K = red[0][0];
         const double p = (2.0 * K - 2.0 * red[1][0] + red[2][0] / R.P) / (3.0 * V);
         const double g = white_gauss(R.seed, n + R.step_off, 0u, R.stream, 4);
@@ -433,31 +447,11 @@ __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int
         // (1 - S)(r_c + skin) / 2 here and by (1 - S) dev_i in the update
         // kernel's test.  Past half of the skin the next step's force pass
         // rebuilds.
-        int64_t f1 = (n + 1) % 3, f2 = (n + 2) % 3;
-        if (f1 < 0) f1 += 3;
-        if (f2 < 0) f2 += 3;
-        const bool rebuilt = R.rflag[f1] != 0;  // this step's force pass rebuilt
-        if (rebuilt) R.npt_S = 1.0;
         const double S = R.npt_S * sc;
         const double hs = R.half_skin0 - fmax(0.0, 1.0 - S) * 0.5 * R.r_cs;
         R.half_skin = hs;
         if (hs < 0.5 * R.half_skin0) R.rflag[f2] = 1;
     }
-}
-
-// After the update kernel applied a replica's pending scalings to positions
-// and velocities: the box and the lists' scale follow (the update read them
-// before), and only s_v2 stays pending, for the closing kick.
-__global__ void k_npt_commit(RepDev* __restrict__ reps, int n_rep)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_rep) return;
-    RepDev& R = reps[r];
-    const double sc = R.npt_sr;
-    for (int a = 0; a < 3; ++a) R.box[a] *= sc;
-    R.npt_S *= sc;
-    R.npt_sr = 1.0;
-    R.npt_sv1 = 1.0;
 }
 
 // After k_eq9: record which noise block each half holds (invalidate: none).
@@ -526,11 +520,6 @@ void launch_barostat(hipStream_t st, RepDev* reps, int n_rep, const double* part
                      StepRef sync)
 {
     launch(k_barostat, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, sync);
-}
-
-void launch_npt_commit(hipStream_t st, RepDev* reps, int n_rep)
-{
-    launch(k_npt_commit, dim3((n_rep + 63) / 64), dim3(64), 0, st, reps, n_rep);
 }
 
 void launch_eq9_invalidate(hipStream_t st, int64_t* marker)

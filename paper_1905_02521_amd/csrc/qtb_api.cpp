@@ -1088,8 +1088,6 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
                 launch_update(c->st, c->fp64, c->pair, g.first, L.upd_threads, dreps, ub + b0, nb, zrow,
                               c->at<int32_t>(L.status), step_ref(c), zmod, L.n_cols);
         }
-        // a barostat's pending box factor, applied to the positions just now
-        if (c->npt_used) launch_npt_commit(c->st, c->at<RepDev>(L.reps), c->n_rep);
     }
     c->rec_extra = 1;
     // the pair potential's force kernel rebuilds flagged lists itself, except

@@ -140,8 +140,9 @@ struct RepDev {
     // scalings the last barostat update left for the next step (1 when
     // none): velocities before its first kick (sv1) and after its closing
     // kick (sv2), normal-mode positions by sqrt(sr) before and after its
-    // A-O-A, box and npt_S by sr after its update.  Every step applies them
-    // (a multiplication by 1 is exact); between steps box, npt_S and the
+    // A-O-A; its force pass and sample use box and npt_S times sr, which the
+    // barostat kernel commits at its end.  Every step applies them (a
+    // multiplication by 1 is exact); between steps box, npt_S and the
     // positions agree.
     double npt_sr, npt_sv1, npt_sv2;
     double dt;
@@ -352,14 +353,12 @@ void launch_eq9(hipStream_t st, bool fp64, const RepDev* reps, const FirTile* ti
                 const double* amp, int amp_stride, const double* tw, int n, void* zeta,
                 int64_t n_cols, const int64_t* clock, int64_t* marker, int K);
 void launch_eq9_invalidate(hipStream_t st, int64_t* marker);
-// Barostat update of the replicas with npt set, after the force pass of step
-// n (sync gives n; partials hold that pass's block sums): new box, the
-// scalings step n + 1 applies, list rebuild flagged for it; replicas with
-// npt clear have their pending scalings reset to 1.
+// Barostat update after the force pass of step n (sync gives n; partials
+// hold that pass's block sums): box and list scale take the factor step n
+// applied; for replicas with npt set, the scalings step n + 1 applies and a
+// list rebuild flagged for it; for the others, the factors reset to 1.
 void launch_barostat(hipStream_t st, RepDev* reps, int n_rep, const double* partials,
                      StepRef sync);
-// After the update kernel: box and list scale take the pending factor s.
-void launch_npt_commit(hipStream_t st, RepDev* reps, int n_rep);
 int eq9_columns(int n);
 void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
                      int64_t n_rows, uint32_t d0, uint32_t n_dof, double* out);

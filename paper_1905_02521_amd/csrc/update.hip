@@ -155,8 +155,8 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
             cen[il][a] = c;
         }
         __syncthreads();
-        // the lists' scale for this step's force pass: the box factor that
-        // this update applied joins it after the kernel (k_npt_commit)
+        // the lists' scale for this step's force pass, with the box factor
+        // this update applies (committed at the end of the step)
         const double lsc = R.npt_S * R.npt_sr;
         if (active && a == 0) {
             double u3[3], u2 = 0.0, d2 = 0.0;
