@@ -31,7 +31,8 @@ __device__ __forceinline__ double* recorder_row(const RepDev& R, int32_t flags)
 }
 
 // e_atom: this atom's share of the bead potential V(r^(s)).
-// ob (kNobs slots): kinetic, V/P, spring, virial, x^2 in kSample mode;
+// ob (kNobs slots): kinetic, V/P, spring, virial, x^2 in kSample mode
+// (kPressure alone: kinetic and spring);
 // |F - F_stored|^2 and |F|^2 in kCompare mode (nothing is written then).
 // vn receives the velocity after the kick; STORE_V: write it back.  A sample
 // also stores vn into the velocity recorder's row vrec (recorder_row).
@@ -93,6 +94,20 @@ __device__ __forceinline__ void force_epilogue_src(const RepDev& R, int i, int s
 #pragma unroll
             for (int a = 0; a < 3; ++a) vrec[(size_t)a * N + i] = vn[a];
         }
+    } else if (flags & kPressure) {  // kinetic energy and springs only
+        const double m = R.mmu[spi];
+        const int sn = (s + 1 == P) ? 0 : s + 1;
+        double ke = 0.0, spr = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ke = __builtin_fma(vn[a], vn[a], ke);
+            if (P > 1) {
+                const double dn = src.pos(s, a) - src.pos(sn, a);
+                spr = __builtin_fma(dn, dn, spr);
+            }
+        }
+        ob[0] = 0.5 * m * ke;
+        ob[2] = (P > 1) ? 0.5 * m * R.omega_P * R.omega_P * spr : 0.0;
     }
 }
 

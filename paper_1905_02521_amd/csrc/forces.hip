@@ -130,7 +130,8 @@ __device__ __forceinline__ f4v bload(__amdgpu_buffer_rsrc_t r, uint32_t off)
 // erfc(x) + (2x/sqrt(pi)) e^{-x^2} = 1 + (r r^2) psi(s) as a polynomial of
 // degree DEG in s = r^2 (2 / r_cut^2) - 1 (no exponential), and for the
 // energy the fitted erfcx polynomial.
-// Force (FP64 sums) and, if want_e, energy and pair virial sum F(r) r of bead
+// Force (FP64 sums), if want_e the energy, and if want_w the pair virial
+// sum F(r) r of bead
 // s of atom i over its list: the core entries (reference distance below
 // r_cut) at slots 0 .. core - 1, then the shell entries at slots maxnb - 1,
 // maxnb - 2, ...; lane entries ch, ch + ST, ... of each range.  spi
@@ -138,8 +139,9 @@ __device__ __forceinline__ f4v bload(__amdgpu_buffer_rsrc_t r, uint32_t off)
 template <typename T, int NS, bool FAST, int DEG, int MODE, int G>
 __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& tab,
                                          const PairPos<T, MODE>& pp, int i, int s, int ch,
-                                         int ST, bool want_e, double& fx, double& fy, double& fz,
-                                         double& e, double& w, int& spi, double lscale)
+                                         int ST, bool want_e, bool want_w, double& fx,
+                                         double& fy, double& fz, double& e, double& w, int& spi,
+                                         double lscale)
 {
     using V4 = typename NV<T>::v4;
     const V4 ui = pp.at(i, s);
@@ -254,8 +256,8 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                     E0c = m ? pE0[b] : E0c;
                 }
                 e += (double)(A * e1 - C * rinv6 + kqq * ec * rinv - F0 * r + E0c);
-                w += (double)(F * r);
             }
+            if (want_w) w += (double)(F * r);
         }
     };
 
@@ -328,18 +330,16 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
 // lanes < G of the atom's first wavefront.
 template <int G>
 __device__ __forceinline__ void reduce_atom(double& fx, double& fy, double& fz, double& e,
-                                            double& vir, bool want_e, int W, int wave, int wsub,
-                                            int lane, double (*part)[G][5])
+                                            double& vir, bool want_e, bool want_w, int W,
+                                            int wave, int wsub, int lane, double (*part)[G][5])
 {
 #pragma unroll
     for (int off = G; off < 64; off <<= 1) {
         fx += __shfl_xor(fx, off);
         fy += __shfl_xor(fy, off);
         fz += __shfl_xor(fz, off);
-        if (want_e) {
-            e += __shfl_xor(e, off);
-            vir += __shfl_xor(vir, off);
-        }
+        if (want_e) e += __shfl_xor(e, off);
+        if (want_w) vir += __shfl_xor(vir, off);
     }
     if (W > 1) {
         if (lane < G) {
@@ -471,9 +471,9 @@ __device__ void rebuild_list(const RepDev& R, int i, bool active, const double* 
 // FP32 force pass at eight wavefronts per SIMD (64 registers, a few spilled)
 // ran 27.9 us against 28.6 at five; the sampling pass keeps five without
 // spills; FP64 is left to the compiler.
-template <typename T, int G, int NS, bool FAST, int DEG, bool WE>
+template <typename T, int G, int NS, bool FAST, int DEG, int EM>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (WE ? 5 : 7)))) k_force_pair(const RepDev* __restrict__ reps,
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (EM == 2 ? 5 : 7)))) k_force_pair(const RepDev* __restrict__ reps,
                                                     const BlockEntry* __restrict__ blocks,
                                                     const PairTable<T> tab, int32_t flags,
                                                     double* __restrict__ partials, int clear,
@@ -500,9 +500,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (WE ? 5 : 7)))) k_force_
     const bool active = i < N;
     const int s = be.group * G + bl;
     // energies and the pair virial only in the instantiation that samples or
-    // evaluates (WE = flags & (kSample | kEvaluate)): the plain force pass
-    // keeps fewer registers live
-    constexpr bool want_e = WE;
+    // evaluates (EM = 2: flags & (kSample | kEvaluate)), the pair virial alone
+    // for a barostat's step (EM = 1: kPressure): the plain force pass keeps
+    // fewer registers live
+    constexpr bool want_e = EM == 2;
+    constexpr bool want_w = EM >= 1;
     double* const vrec = recorder_row(R, flags);
     const StepIdx si = step_index(sync);
     // clear == 1: the list kernel ran before; this step's and the previous
@@ -551,24 +553,25 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (WE ? 5 : 7)))) k_force_
         if (rebuild) {
             const PairPos<T, kPosRef> pp{nullptr, nullptr, (gptr<double>)cen, N, P,
                                          (gptr<double>)R.pos, (gptr<int32_t>)R.species};
-            pair_sum<T, NS, FAST, DEG, kPosRef, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy, fz,
-                                                e, vir, spi, 1.0);
+            pair_sum<T, NS, FAST, DEG, kPosRef, G>(R, tab, pp, i, s, ch, NCH * W, want_e, want_w,
+                                                fx, fy, fz, e, vir, spi, 1.0);
         } else {
             // u is atom-major [N][P]: the G beads of a neighbour share cache lines
             const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[si.p] + 0, nullptr, nullptr, N, P,
                                             nullptr, nullptr};
-            pair_sum<T, NS, FAST, DEG, kPosDirect, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
-                                                   fz, e, vir, spi, lscale);
+            pair_sum<T, NS, FAST, DEG, kPosDirect, G>(R, tab, pp, i, s, ch, NCH * W, want_e,
+                                                   want_w, fx, fy, fz, e, vir, spi, lscale);
         }
     }
-    reduce_atom<G>(fx, fy, fz, e, vir, want_e, W, wave, wsub, lane, part);
+    reduce_atom<G>(fx, fy, fz, e, vir, want_e, want_w, W, wave, wsub, lane, part);
     double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (active && wsub == 0 && lane < G && s < P) {
         const double f[3] = {fx, fy, fz};
         force_epilogue<T>(R, i, s, spi, f, 0.5 * e, flags, ob, vrec);
-        if (flags & kSample) ob[5] = 0.5 * vir;  // each pair is listed from both sides
+        // each pair is listed from both sides
+        if (flags & (kSample | kPressure)) ob[5] = 0.5 * vir;
     }
-    if (flags & (kSample | kCompare)) block_partials(ob, wave, lane, lb, red, partials);
+    if (flags & (kSample | kCompare | kPressure)) block_partials(ob, wave, lane, lb, red, partials);
 }
 
 // One step of the pair potential for P = G <= 8 beads (all beads of an atom
@@ -649,17 +652,17 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
         if (rebuild) {
             const PairPos<T, kPosRecon> pp{(gptr<V4>)R.ub[pin] + 0, (gptr<double>)rin,
                                            (gptr<double>)cin, N, P, nullptr, nullptr};
-            pair_sum<T, NS, FAST, DEG, kPosRecon, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
-                                                  fz, e, vir, spi, 1.0);
+            pair_sum<T, NS, FAST, DEG, kPosRecon, G>(R, tab, pp, i, s, ch, NCH * W, want_e, want_e,
+                                                  fx, fy, fz, e, vir, spi, 1.0);
         } else {
             // (no barostat with the one-kernel step)
             const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[pin] + 0, nullptr, nullptr, N, P,
                                             nullptr, nullptr};
-            pair_sum<T, NS, FAST, DEG, kPosDirect, G>(R, tab, pp, i, s, ch, NCH * W, want_e, fx, fy,
-                                                   fz, e, vir, spi, R.npt_S);
+            pair_sum<T, NS, FAST, DEG, kPosDirect, G>(R, tab, pp, i, s, ch, NCH * W, want_e,
+                                                   want_e, fx, fy, fz, e, vir, spi, R.npt_S);
         }
     }
-    reduce_atom<G>(fx, fy, fz, e, vir, want_e, W, wave, wsub, lane, part);
+    reduce_atom<G>(fx, fy, fz, e, vir, want_e, want_e, W, wave, wsub, lane, part);
     double ob[kNobs] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int my_flags = 0;
     // the atom's wavefront, lanes 0 .. P-1 = beads: wavefront-uniform branch.
@@ -981,17 +984,17 @@ __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v)
         p[id] = v;
 }
 
-template <typename T, int NS, bool FAST, int DEG, bool WE>
+template <typename T, int NS, bool FAST, int DEG, int EM>
 void launch_pair_GW(hipStream_t st, int G, const RepDev* reps, const BlockEntry* blocks,
                     int n_blocks, const PairTable<T>& tab, int32_t flags, double* partials,
                     int clear, int n_rep, int32_t* status, StepRef sync, int W)
 {
     const dim3 g(n_blocks), b(256);
     switch (G) {
-    case 1: launch((k_force_pair<T, 1, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
-    case 2: launch((k_force_pair<T, 2, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
-    case 4: launch((k_force_pair<T, 4, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
-    case 8: launch((k_force_pair<T, 8, NS, FAST, DEG, WE>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    case 1: launch((k_force_pair<T, 1, NS, FAST, DEG, EM>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    case 2: launch((k_force_pair<T, 2, NS, FAST, DEG, EM>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    case 4: launch((k_force_pair<T, 4, NS, FAST, DEG, EM>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
+    case 8: launch((k_force_pair<T, 8, NS, FAST, DEG, EM>), g, b, 0, st, reps, blocks, tab, flags, partials, clear, n_rep, status, sync, W); break;
     default: break;
     }
 }
@@ -1001,11 +1004,14 @@ void launch_pair_G(hipStream_t st, int G, const RepDev* reps, const BlockEntry* 
                    int clear, int n_rep, int32_t* status, StepRef sync, int W)
 {
     if (flags & (kSample | kEvaluate))
-        launch_pair_GW<T, NS, FAST, DEG, true>(st, G, reps, blocks, n_blocks, tab, flags, partials,
-                                               clear, n_rep, status, sync, W);
+        launch_pair_GW<T, NS, FAST, DEG, 2>(st, G, reps, blocks, n_blocks, tab, flags, partials,
+                                            clear, n_rep, status, sync, W);
+    else if (flags & kPressure)
+        launch_pair_GW<T, NS, FAST, DEG, 1>(st, G, reps, blocks, n_blocks, tab, flags, partials,
+                                            clear, n_rep, status, sync, W);
     else
-        launch_pair_GW<T, NS, FAST, DEG, false>(st, G, reps, blocks, n_blocks, tab, flags, partials,
-                                                clear, n_rep, status, sync, W);
+        launch_pair_GW<T, NS, FAST, DEG, 0>(st, G, reps, blocks, n_blocks, tab, flags, partials,
+                                            clear, n_rep, status, sync, W);
 }
 
 template <typename T, bool FAST, int DEG>

@@ -1098,9 +1098,10 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
         Phase ph(c, 3, true);  // tile bounds and list kernels (+ surrogate lists)
         launch_rebuild(c);
     }
-    // the barostat needs the kinetic energy and the pair virial of every step
+    // the barostat needs the kinetic energy, springs and pair virial of every
+    // step (the sampling pass has them; otherwise the pressure-only pass)
     const bool npt = npt_any(c);
-    const int32_t fflags = kKick | (sample || npt ? kSample : 0);
+    const int32_t fflags = kKick | (sample ? kSample : npt ? kPressure : 0);
     {
         Phase ph(c, 4, L.force_groups.size() > 1 || c->ml);
         if (inline_rebuild) launch_plain_forces(c, fflags, true);

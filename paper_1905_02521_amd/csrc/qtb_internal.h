@@ -314,7 +314,9 @@ __device__ __forceinline__ StepIdx step_index(const StepRef r)
 // Kernel-side flags of the force kernels.
 // kCompare: leave force and state untouched, accumulate |F - F_stored|^2 and
 // |F|^2 into observable slots 0 and 1 (the surrogate's check).
-enum ForceFlags : int32_t { kKick = 1, kSample = 2, kEvaluate = 4, kCompare = 8 };
+// kPressure: only what a barostat needs of a step that does not sample:
+// kinetic energy, springs and pair virial into slots 0, 2 and 5.
+enum ForceFlags : int32_t { kKick = 1, kSample = 2, kEvaluate = 4, kCompare = 8, kPressure = 16 };
 
 // Profiling: when set, the next launch time-stamps these events from its own
 // dispatch packet (no marker packets around the kernel), then clears them.
