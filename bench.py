@@ -491,6 +491,56 @@ def vdos_bench(a):
     print(json.dumps(out))
 
 
+def fir_modes_bench(a):
+    """The default workload (MgO 8x8x8 x P = 8, 50 K, kappa_P, 2Nf = 512,
+    K = 64, FP32 forces) with each FIR arithmetic: wall time per step over
+    whole noise blocks, and the FIR and white-noise GPU time per block from
+    the dispatch stamps of four further blocks.  The FIR's algorithmic bytes
+    are 8 per noise value (one new white-noise value read, one coloured value
+    written: 98 304 columns x 64 steps per block).  The FP64 FIR runs with
+    FP64 forces and state (the library pairs them)."""
+    from paper_1905_02521_amd import qtb, workloads as W
+    w = W.workload("mgo-8x8x8-qtbpimd-P8-50K")
+    beads, sp, box = W.crystal_inputs(w)
+    n_dof = beads.size
+    K = 64
+    steps = max(K, (a.steps // K) * K)
+    res = {}
+    for name, fir in (("fp64", qtb.FIR_FP64), ("fp32", qtb.FIR_FP32),
+                      ("bf16x3", qtb.FIR_BF16X3), ("bf16", qtb.FIR_BF16)):
+        rep = qtb.Replica(pos=beads, species=sp, T=w.T, gamma=w.gamma, dt=w.dt, noise=w.noise,
+                          box=tuple(box), seed=w.seed, stream=w.stream)
+        ctx = qtb.Context(qtb.pair_potential_dict(W.mgo_potential(skin=0.4)), [rep],
+                          W.METAL_UNITS, prec=qtb.PREC_FP64 if name == "fp64" else qtb.PREC_FP32,
+                          fir=fir, fir_block_K=K, max_two_nf=w.two_nf)
+        ctx.build_filter(0, w.noise, w.two_nf)
+        ctx.step(2 * K)
+        ctx.get_state(0)   # synchronises
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        ctx.get_state(0)
+        t = (time.perf_counter() - t0) / steps
+        ctx.profile(True)
+        ctx.step(4 * K)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        ctx.close()
+        fir_us = prof["fir"][0] / 4 * 1e3
+        res[name] = {"ms_per_step": t * 1e3, "atom_bead_steps_per_s": n_dof / 3 / t,
+                     "fir_us_per_block": fir_us,
+                     "white_noise_us_per_block": prof["noise"][0] / 4 * 1e3,
+                     "fir_GB_s": 8.0 * n_dof * K / (fir_us * 1e-6) / 1e9}
+    out = {"metric": "atom-bead-steps/s per FIR arithmetic", "value": res["bf16x3"]["atom_bead_steps_per_s"],
+           "unit": "atom-bead-steps/s", "n_gpus": 1, "steps": steps, "warmup": 2 * K,
+           "ms_per_step": res["bf16x3"]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3 noise, f32 forces",
+           "data": "synthetic (seeded rock-salt crystal, numpy PCG64 displacements)",
+           "config": {"workload": "mgo-8x8x8-qtbpimd-P8-50K", "fir_block_K": K,
+                      "noise_columns": n_dof},
+           "modes": res}
+    print(json.dumps(out))
+
+
 def npt_bench(a):
     """Constant pressure on the 8x8x8 MgO crystal (4096 atoms, FP32 forces,
     BF16x3 noise): wall time per step at constant volume and under a
@@ -592,7 +642,8 @@ def main():
                          "surrogate-20x20x20-P4 (the learned force surrogate) or qtb-vs-pimd "
                          "(QTB, QTB-PIMD and PIMD cost and energies on one crystal) or vdos "
                          "(the velocity spectrum's recorder and transform) or npt (the step "
-                         "at constant pressure)")
+                         "at constant pressure) or fir-modes (the default workload with each "
+                         "FIR arithmetic)")
     ap.add_argument("--fir", default="bf16x3", choices=["fp32", "bf16x3", "bf16", "fp64"])
     ap.add_argument("--K", type=int, default=64)
     ap.add_argument("--noise-blocks", action="store_true",
@@ -633,6 +684,8 @@ def main():
         return vdos_bench(a)
     if a.workload == "npt":
         return npt_bench(a)
+    if a.workload == "fir-modes":
+        return fir_modes_bench(a)
     if a.workload.startswith("surrogate"):
         surrogate_bench(a)
         return
