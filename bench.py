@@ -356,11 +356,23 @@ def surrogate_bench(a):
 
 
 def pimd_compare_bench(a):
-    """QTB (P = 1, theta noise), QTB-PIMD (P = 8, kappa_P noise) and classical
-    PIMD (P = 32, white noise) on the 4x4x4 MgO crystal at 50 K, gamma = 1/ps:
-    the time per step of each and the eq. 5 energies per atom (block means),
-    beside the paper's statement that QTB needs about a twentieth of the PIMD
-    computation time (its hardware and workload are not stated)."""
+    """QTB (P = 1, theta noise), QTB-PIMD (kappa_P noise) and classical PIMD
+    (white noise) on the 4x4x4 MgO crystal at 50 K.
+
+    Cost: one replica of each of QTB, QTB-PIMD P = 8 and PIMD P = 32 at
+    gamma = 1/ps, time per step, beside the paper's statement that QTB needs
+    about a twentieth of the PIMD computation time (its hardware and workload
+    are not stated).
+
+    Convergence in P (Sec. 2.3, Fig. 8: QTB-PIMD converges with far fewer
+    beads): one batched context of three replicas per condition, PIMD at
+    P = 32 and 64, QTB-PIMD at P = 4, 8, 16 (gamma = 1/ps) and at P = 8 with
+    gamma = 2, 0.5, 0.25 /ps and with a 2048-tap filter, QTB at gamma = 1 and
+    0.25 /ps; 20 000 steps of equilibration, then a.blocks blocks of 5000
+    steps.  Per condition the block means (eV/atom) of the potential energy
+    (free of any kinetic estimator), the centroid-virial and primitive
+    energies and the pressure, and PIMD's P -> infinity limit from P = 32
+    and 64 with the 1/P^2 law of the primitive discretisation."""
     import torch
     from paper_1905_02521_amd import qtb, workloads as W
     pot = W.mgo_potential(skin=1.0)
@@ -368,7 +380,6 @@ def pimd_compare_bench(a):
     pos, sp, box = W.rocksalt(4)
     base = W.displaced(pos, 0.0421, 2)
     N = len(sp)
-    n_eq, block, n_blocks = 4000, 1000, a.blocks
     out_runs = {}
     for name, P, noise in (("qtb", 1, 1), ("qtb-pimd", 8, 2), ("pimd", 32, 0)):
         rep = qtb.Replica(pos=W.beads_from(base, P), species=sp, T=50.0, gamma=1e-3, dt=1.0,
@@ -377,35 +388,74 @@ def pimd_compare_bench(a):
                           fir=qtb.FIR_BF16X3, obs_every=8, max_two_nf=512)
         if noise:
             ctx.build_filter(0, noise, 512)
-        ctx.step(n_eq)
+        ctx.step(2000)
         ctx.observables(0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        blocks = {"e_primitive": [], "e_virial": [], "t_kinetic": []}
-        for _ in range(n_blocks):
-            ctx.step(block)
-            o = ctx.observables(0)
-            for k in blocks:
-                blocks[k].append(o[k])
-        dt = (time.perf_counter() - t0) / (n_blocks * block)
+        ctx.step(a.steps * 4)
+        ctx.observables(0)
+        dt = (time.perf_counter() - t0) / (a.steps * 4)
         ctx.close()
-        r = {"beads": P, "ms_per_step": dt * 1e3, "atom_bead_steps_per_s": N * P / dt}
-        for k, v in blocks.items():
-            v = np.asarray(v) / (N if k != "t_kinetic" else 1)
-            r[k] = [float(v.mean()), float(v.std(ddof=1) / math.sqrt(len(v)))]
-        out_runs[name] = r
+        out_runs[name] = {"beads": P, "ms_per_step": dt * 1e3, "atom_bead_steps_per_s": N * P / dt}
+    conds = [("pimd-P32", 32, 0, 1e-3, 512), ("pimd-P64", 64, 0, 1e-3, 512),
+             ("qtbpimd-P4", 4, 2, 1e-3, 512), ("qtbpimd-P8", 8, 2, 1e-3, 512),
+             ("qtbpimd-P16", 16, 2, 1e-3, 512), ("qtbpimd-P8-gamma2", 8, 2, 2e-3, 512),
+             ("qtbpimd-P8-gamma0.5", 8, 2, 5e-4, 512), ("qtbpimd-P8-gamma0.25", 8, 2, 2.5e-4, 1024),
+             ("qtbpimd-P8-2Nf2048", 8, 2, 1e-3, 2048), ("qtb", 1, 1, 1e-3, 512),
+             ("qtb-gamma0.25", 1, 1, 2.5e-4, 1024)]
+    n_r = 3
+    reps, keys = [], []
+    for name, P, noise, g, nf in conds:
+        for k in range(n_r):
+            b0 = W.displaced(pos, 0.02, 10 + k)
+            beads = (b0[None] if P == 1 else
+                     np.stack([W.displaced(b0, 0.005, 100 + 10 * k + b) for b in range(P)]))
+            reps.append(qtb.Replica(pos=beads, species=sp, T=50.0, gamma=g, dt=1.0, noise=noise,
+                                    box=tuple(box), seed=300 + len(reps), stream=len(reps)))
+            keys.append((name, noise, nf))
+    ctx = qtb.Context(qtb.pair_potential_dict(pot), reps, U, prec=qtb.PREC_FP32,
+                      fir=qtb.FIR_BF16X3, obs_every=8, max_two_nf=2048)
+    for r, (_, noise, nf) in enumerate(keys):
+        if noise:
+            ctx.build_filter(r, noise, nf)
+    ctx.step(20_000)
+    for r in range(len(keys)):
+        ctx.observables(r)
+    fields = ("potential", "e_virial", "e_primitive", "pressure")
+    blocks = {c[0]: {f: [] for f in fields} for c in conds}
+    for _ in range(a.blocks):
+        ctx.step(5000)
+        acc = {c[0]: {f: [] for f in fields} for c in conds}
+        for r, (name, _, _) in enumerate(keys):
+            o = ctx.observables(r)
+            for f in fields:
+                acc[name][f].append(o[f] / (1 if f == "pressure" else N))
+        for c in conds:
+            for f in fields:
+                blocks[c[0]][f].append(float(np.mean(acc[c[0]][f])))
+    ctx.close()
+    conv = {}
+    for c in conds:
+        conv[c[0]] = {f: [float(np.mean(v)), float(np.std(v, ddof=1) / math.sqrt(len(v)))]
+                      for f, v in blocks[c[0]].items()}
+    lim = {}
+    for f in fields:   # X(P) = X_inf + c / P^2 through P = 32 and 64
+        (m32, s32), (m64, s64) = conv["pimd-P32"][f], conv["pimd-P64"][f]
+        lim[f] = [m64 + (m64 - m32) / 3.0, math.hypot(4.0 * s64, s32) / 3.0]
+    conv["pimd-P-infinity"] = lim
     out = {
-        "metric": "QTB vs QTB-PIMD vs PIMD: time per step and eq. 5 energies per atom",
-        "unit": "ms/step; eV/atom (mean, standard error of block means); K",
+        "metric": "QTB vs QTB-PIMD vs PIMD: time per step and the energies' convergence in P",
+        "unit": "ms/step; eV/atom and eV/A^3 (mean, standard error of block means)",
         "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
         "data": "synthetic (seeded rock-salt crystal, numpy PCG64 displacements)",
         "config": {"workload": "mgo-4x4x4-50K-qtb-vs-pimd", "atoms": N, "T_K": 50.0,
-                   "gamma_per_ps": 1.0, "two_nf": 512, "equilibration_steps": n_eq,
-                   "blocks": n_blocks, "block_steps": block},
+                   "replicas_per_condition": n_r, "equilibration_steps": 20_000,
+                   "blocks": a.blocks, "block_steps": 5000},
         "runs": out_runs,
         "pimd_over_qtb_time": out_runs["pimd"]["ms_per_step"] / out_runs["qtb"]["ms_per_step"],
         "pimd_over_qtbpimd_time": (out_runs["pimd"]["ms_per_step"] /
                                    out_runs["qtb-pimd"]["ms_per_step"]),
+        "convergence": conv,
         "paper": "QTB about 20x cheaper than PIMD (abstract; hardware and workload not stated)",
     }
     print(json.dumps(out))
@@ -650,7 +700,7 @@ def main():
                     help="make the coloured noise with the paper's block generator (eq. 9, "
                          "blocks of max two_nf steps) instead of the streaming FIR")
     ap.add_argument("--blocks", type=int, default=40,
-                    help="qtb-vs-pimd: measured blocks of 1000 steps per method")
+                    help="qtb-vs-pimd: measured blocks of 5000 steps of the convergence sweep")
     ap.add_argument("--skin", type=float, default=None,
                     help="Verlet skin (A); default 0.4 for one crystal (fastest measured), "
                          "1.3 for the sweep (hot replicas: measured 0.5-1.6, best 1.3-1.45), "
