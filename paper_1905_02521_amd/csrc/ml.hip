@@ -1108,14 +1108,23 @@ __global__ void __launch_bounds__(1024) k_ml_train_mlp(const RepDev* __restrict_
     }
 }
 
-// dL/dtheta as outer-product sums over the centres of one species:
+// dL/dtheta as outer-product sums over the centres of each species:
 //   W1 += z1b x^T + z1db xd^T, W2 += z2b h1^T + z2db h1d^T, b1 += z1b,
 //   b2 += z2b, w3 += t3, b3 += e.
-// Workgroup (g, a) takes the network tiles g, g + kWgBlocks, ... in order,
-// stages 16 centres at a time in LDS and accumulates a 4x6 block of W1 and a
-// 4x4 block of W2 per thread in FP32; its partial sums go to part[g][a], and
+// The two weight sums are dense contractions over the centres, run on the
+// matrix cores: v_mfma_f32_32x32x2_f32 with A = (z_b, z_db) of one centre
+// (its two columns) and B = (x, x_d) (its two rows), so one instruction adds
+// both rank-one terms of a centre to a 32 x 32 tile, FP32 products (exact)
+// and FP32 accumulation.  Workgroup g (8 wavefronts) takes the network tiles
+// g, g + kWgBlocks, ... in order and stages 16 centres at a time in LDS
+// (zeros for padding); wavefronts 0-3 accumulate species 0, 4-7 species 1
+// (a centre of the other species enters as zeros): W1 (64 x 96) is 2 x 3
+// tiles, W2 (64 x 64) 2 x 2, so wavefront w % 4 holds W1 row tile w % 4
+// (w % 4 < 2: three column tiles) or W2 row tile w % 4 - 2 (two).  The bias
+// sums stay on the vector ALU.  Partial sums go to part[g][a];
 // k_ml_wgrad_sum adds the kWgBlocks partials in order in FP64.
 constexpr int kWgStage = 16;
+static_assert(kMlFeat == 96 && kMlHidden == 64, "the weight-gradient tiles assume 96 x 64 x 64");
 
 struct WgLds {
     float x[kWgStage][kMlFeat], xd[kWgStage][kMlFeat];
@@ -1123,100 +1132,111 @@ struct WgLds {
     float h1[kWgStage][kMlHidden], h1d[kWgStage][kMlHidden];
     float z2b[kWgStage][kMlHidden], z2db[kWgStage][kMlHidden], t3[kWgStage][kMlHidden];
     float e[kWgStage];
-    int ok[kWgStage];
+    int sp[kWgStage];   // species of the centre, -1 for padding
 };
 
-__global__ void __launch_bounds__(256) k_ml_wgrad_part(const RepDev* __restrict__ reps,
+__global__ void __launch_bounds__(512) k_ml_wgrad_part(const RepDev* __restrict__ reps,
                                                        const MlDev m,
                                                        const BlockEntry* __restrict__ blocks,
                                                        int n_blocks, float* __restrict__ part)
 {
     __shared__ WgLds L;
-    const int a = blockIdx.y, t = threadIdx.x;
-    const int og = t >> 4, mg = t & 15;     // W1: rows 4 og.., cols 6 mg..; W2: cols 4 mg..
-    float w1[4][6], w2[4][4];
-    for (int i = 0; i < 4; ++i) {
-        for (int j = 0; j < 6; ++j) w1[i][j] = 0.f;
-        for (int j = 0; j < 4; ++j) w2[i][j] = 0.f;
-    }
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int a = wave >> 2, role = wave & 3;          // species, tile role
+    const int li = lane & 31, lk = lane >> 5;
+    const bool w1role = role < 2;
+    const int o0 = 32 * (w1role ? role : role - 2);   // output row tile
+    f32x16 acc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+    // bias sums: threads of wavefront 0 (species 0) and 4 (species 1)
     float vb1 = 0.f, vb2 = 0.f, vw3 = 0.f, vb3 = 0.f;
+    constexpr int kRow = 2 * kMlFeat + 7 * kMlHidden + 1;
     for (int b = blockIdx.x; b < n_blocks; b += gridDim.x) {
         const BlockEntry be = blocks[b];
         const RepDev& R = reps[be.rep];
         const int N = R.N;
         for (int q0 = 0; q0 < be.group; q0 += kWgStage) {
             __syncthreads();  // previous stage consumed
-            for (int idx = t; idx < kWgStage * (2 * kMlFeat + 7 * kMlHidden + 1); idx += blockDim.x) {
-                const int qi = idx / (2 * kMlFeat + 7 * kMlHidden + 1);
-                const int k = idx % (2 * kMlFeat + 7 * kMlHidden + 1);
+            for (int idx = t; idx < kWgStage * kRow; idx += blockDim.x) {
+                const int qi = idx / kRow, k = idx % kRow;
                 const int q = q0 + qi;
                 const bool valid = q < be.group;
                 const size_t c = (size_t)be.atom0 + (valid ? q : 0);
                 const int sp = R.species[c % N];
-                if (k == 0) L.ok[qi] = valid && sp == a;
+                if (k == 0) L.sp[qi] = valid ? sp : -1;
                 const float* row = R.ml_adj + c * kMlAdj;
                 if (k < kMlFeat) {
-                    L.x[qi][k] = (R.ml_G[c * kMlFeat + k] - m.mu[sp * kMlFeat + k]) *
-                                 m.inv_sd[sp * kMlFeat + k];
+                    L.x[qi][k] = valid ? (R.ml_G[c * kMlFeat + k] - m.mu[sp * kMlFeat + k]) *
+                                             m.inv_sd[sp * kMlFeat + k]
+                                       : 0.0f;
                 } else if (k < 2 * kMlFeat) {
-                    L.xd[qi][k - kMlFeat] = row[k - kMlFeat];
+                    L.xd[qi][k - kMlFeat] = valid ? row[k - kMlFeat] : 0.0f;
                 } else if (k < 2 * kMlFeat + 7 * kMlHidden) {
                     const int kk = k - 2 * kMlFeat, blk = kk / kMlHidden, o = kk % kMlHidden;
-                    const float v = row[kMlFeat + kk];
+                    const float v = valid ? row[kMlFeat + kk] : 0.0f;
                     float* dst = blk == 0 ? L.z1b[qi] : blk == 1 ? L.z1db[qi] : blk == 2 ? L.h1[qi]
                                : blk == 3 ? L.h1d[qi] : blk == 4 ? L.z2b[qi] : blk == 5 ? L.z2db[qi]
                                : L.t3[qi];
                     dst[o] = v;
                 } else {
-                    L.e[qi] = row[kMlFeat + 7 * kMlHidden];
+                    L.e[qi] = valid ? row[kMlFeat + 7 * kMlHidden] : 0.0f;
                 }
             }
             __syncthreads();
             for (int qi = 0; qi < kWgStage; ++qi) {
-                if (!L.ok[qi]) continue;  // uniform over the workgroup
-                float zb[4], zdb[4], yb[4], ydb[4];
+                const bool mine = L.sp[qi] == a;   // uniform over the wavefront
+                if (!mine) continue;
+                if (w1role) {
+                    const float av = lk ? L.z1db[qi][o0 + li] : L.z1b[qi][o0 + li];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    zb[i] = L.z1b[qi][4 * og + i];
-                    zdb[i] = L.z1db[qi][4 * og + i];
-                    yb[i] = L.z2b[qi][4 * og + i];
-                    ydb[i] = L.z2db[qi][4 * og + i];
+                    for (int ft = 0; ft < 3; ++ft) {
+                        const float bv = lk ? L.xd[qi][32 * ft + li] : L.x[qi][32 * ft + li];
+                        acc[ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[ft], 0, 0, 0);
+                    }
+                } else {
+                    const float av = lk ? L.z2db[qi][o0 + li] : L.z2b[qi][o0 + li];
+#pragma unroll
+                    for (int ht = 0; ht < 2; ++ht) {
+                        const float bv = lk ? L.h1d[qi][32 * ht + li] : L.h1[qi][32 * ht + li];
+                        acc[ht] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[ht], 0, 0, 0);
+                    }
                 }
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    const float x = L.x[qi][6 * mg + j], xd = L.xd[qi][6 * mg + j];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) w1[i][j] += zb[i] * x + zdb[i] * xd;
+                if (role == 0) {
+                    vb1 += L.z1b[qi][lane];
+                    vb2 += L.z2b[qi][lane];
+                    vw3 += L.t3[qi][lane];
+                    if (lane == 0) vb3 += L.e[qi];
                 }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float h = L.h1[qi][4 * mg + j], hd = L.h1d[qi][4 * mg + j];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) w2[i][j] += yb[i] * h + ydb[i] * hd;
-                }
-                if (t < kMlHidden) {
-                    vb1 += L.z1b[qi][t];
-                    vb2 += L.z2b[qi][t];
-                    vw3 += L.t3[qi][t];
-                }
-                if (t == 0) vb3 += L.e[qi];
             }
         }
     }
     float* out = part + ((size_t)blockIdx.x * kMlSpecies + a) * kMlParamsSp;
+    if (w1role) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+        for (int ft = 0; ft < 3; ++ft)
 #pragma unroll
-        for (int j = 0; j < 6; ++j) out[kMlOffW1 + (4 * og + i) * kMlFeat + 6 * mg + j] = w1[i][j];
+            for (int r = 0; r < 16; ++r) {
+                const int o = o0 + 8 * (r >> 2) + 4 * lk + (r & 3);
+                out[kMlOffW1 + o * kMlFeat + 32 * ft + li] = acc[ft][r];
+            }
+    } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) out[kMlOffW2 + (4 * og + i) * kMlHidden + 4 * mg + j] = w2[i][j];
+        for (int ht = 0; ht < 2; ++ht)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int o = o0 + 8 * (r >> 2) + 4 * lk + (r & 3);
+                out[kMlOffW2 + o * kMlHidden + 32 * ht + li] = acc[ht][r];
+            }
     }
-    if (t < kMlHidden) {
-        out[kMlOffB1 + t] = vb1;
-        out[kMlOffB2 + t] = vb2;
-        out[kMlOffW3 + t] = vw3;
+    if (role == 0) {
+        out[kMlOffB1 + lane] = vb1;
+        out[kMlOffB2 + lane] = vb2;
+        out[kMlOffW3 + lane] = vw3;
+        if (lane == 0) out[kMlOffB3] = vb3;
     }
-    if (t == 0) out[kMlOffB3] = vb3;
 }
 
 __global__ void k_ml_wgrad_sum(const float* __restrict__ part, int n_part, float* __restrict__ grad)
@@ -1398,8 +1418,8 @@ void launch_ml_train_mlp(hipStream_t st, const RepDev* reps, const MlDev& m,
 void launch_ml_wgrad(hipStream_t st, const RepDev* reps, const MlDev& m,
                      const BlockEntry* mblocks, int n_mblocks, float* part, float* grad)
 {
-    launch(k_ml_wgrad_part, dim3(kWgBlocks, kMlSpecies), dim3(256), 0, st, reps, m, mblocks,
-           n_mblocks, part);
+    launch(k_ml_wgrad_part, dim3(kWgBlocks), dim3(512), 0, st, reps, m, mblocks, n_mblocks,
+           part);
     launch(k_ml_wgrad_sum, dim3((kMlParams + 255) / 256), dim3(256), 0, st, part, (int)kWgBlocks,
            grad);
 }

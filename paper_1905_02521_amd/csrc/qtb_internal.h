@@ -174,8 +174,8 @@ constexpr int kMlParams = kMlSpecies * kMlParamsSp;
 // adjoint row of one centre (training): xd[96] z1b[64] z1db[64] h1[64]
 // h1d[64] z2b[64] z2db[64] t3[64] e[1] (pad to 576)
 constexpr int kMlAdj = 576;
-// workgroups per species of the weight-gradient sums (partials kept apart)
-constexpr int kWgBlocks = 64;
+// workgroups of the weight-gradient sums (each keeps partials per species)
+constexpr int kWgBlocks = 256;
 
 // Model as the kernels see it (device pointers into the model workspace).
 struct MlDev {

@@ -1,0 +1,111 @@
+"""Training data and training loop of the learned force surrogate (the
+library's qtb_ml_* calls): frames from the method's own QTB and QTB-PIMD runs
+of the pair potential, labelled by that potential, and mini-batch Adam on the
+GPU.  Argument marshalling and bookkeeping only: the runs, labels,
+descriptors, network, loss, gradient and Adam step are the library's
+kernels."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import qtb, workloads as W
+
+
+def qtb_frames(pot, conditions, n_frames, every=40, warm=2000, n_cells=4, gamma=1e-3,
+               two_nf=512, seed=0):
+    """Frames of the n_cells^3 rock-salt crystal from one batched context that
+    runs one replica per (T, P) in `conditions`: QTB (theta noise, eq. 1) for
+    P = 1, QTB-PIMD (kappa_P noise, eq. 10-12) for P > 1, production
+    precision.  After `warm` steps, every `every` steps each bead of each
+    replica is one frame (n_frames samples per replica).  Labels are the pair
+    potential's forces and energy of that bead configuration.
+
+    Returns (positions [M][3][N], forces [M][3][N], energies [M], species,
+    box, tags [M] of (T, P))."""
+    pos, sp, box = W.rocksalt(n_cells)
+    reps = []
+    for k, (T, P) in enumerate(conditions):
+        base = W.displaced(pos, 0.0421, 1000 + seed * 100 + k)
+        beads = (base[None] if P == 1 else
+                 np.stack([W.displaced(base, 0.005, 2000 + seed * 1000 + 10 * k + b)
+                           for b in range(P)]))
+        reps.append(qtb.Replica(pos=beads, species=sp, T=float(T), gamma=gamma, dt=1.0,
+                                noise=1 if P == 1 else 2, box=tuple(box), seed=500 + seed,
+                                stream=k))
+    ctx = qtb.Context(qtb.pair_potential_dict(pot), reps, dict(W.METAL_UNITS),
+                      prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3, max_two_nf=two_nf)
+    for k, (_, P) in enumerate(conditions):
+        ctx.build_filter(k, 1 if P == 1 else 2, two_nf)
+    ctx.step(warm)
+    frames, forces, energies, tags = [], [], [], []
+    for _ in range(n_frames):
+        ctx.step(every)
+        for k, (T, P) in enumerate(conditions):
+            r, _, _ = ctx.get_state(k)
+            f, e = ctx.evaluate(k)
+            for b in range(P):
+                frames.append(r[b])
+                forces.append(f[b])
+                energies.append(e[b])
+                tags.append((float(T), int(P)))
+    ctx.close()
+    return (np.array(frames), np.array(forces), np.array(energies), sp, np.asarray(box),
+            tags)
+
+
+def _ctx(pot, frames, sp, box, train, ml_r_cut):
+    reps = [qtb.Replica(pos=f[None], species=sp, T=300.0, gamma=1e-3, dt=1.0, noise=0,
+                        box=tuple(box), seed=1, stream=k) for k, f in enumerate(frames)]
+    return qtb.Context(qtb.pair_potential_dict(pot), reps, dict(W.METAL_UNITS),
+                       prec=qtb.PREC_FP32, fir=qtb.FIR_FP32, ml_r_cut=ml_r_cut,
+                       ml_train=train)
+
+
+def train(model, pot, frames, forces, energies, sp, box, steps, batch=256, lr=(3e-3, 1e-3),
+          w_E=1.0, w_F=1.0, ml_r_cut=6.0, seed=0):
+    """Mini-batch Adam: the training frames are shuffled once into batches
+    of at most `batch` frames (one context each); step k uses batch
+    k mod n_batches with learning rate lr[0] for the first two thirds of the
+    steps and lr[1] after.  The input normalisation and energy offsets are
+    fitted on the first batch.  Returns the loss of every step."""
+    import torch
+    order = np.random.default_rng(seed).permutation(len(frames))
+    n_b = max(1, math.ceil(len(frames) / batch))
+    batches = []
+    for q in range(n_b):
+        idx = order[q::n_b]
+        c = _ctx(pot, frames[idx], sp, box, True, ml_r_cut)
+        d_e = torch.tensor(energies[idx], dtype=torch.float64, device="cuda")
+        d_f = torch.tensor(forces[idx].reshape(-1), dtype=torch.float64, device="cuda")
+        batches.append((c, d_e, d_f))
+    batches[0][0].ml_fit_norm(model, batches[0][1])
+    losses = []
+    for k in range(steps):
+        c, d_e, d_f = batches[k % n_b]
+        rate = lr[0] if k < (2 * steps) // 3 else lr[1]
+        losses.append(c.ml_train_step(model, d_e, d_f, w_E, w_F, rate))
+    for c, _, _ in batches:
+        c.close()
+    return np.array(losses)
+
+
+def errors(model, pot, frames, forces, energies, sp, box, ml_r_cut=6.0, chunk=256):
+    """Force and energy errors of the surrogate against the labels: RMS of
+    the force components (eV/A), the same relative to the labels' RMS, and
+    the RMS energy error per atom (eV)."""
+    err = ref = 0.0
+    de = []
+    N = len(sp)
+    for q0 in range(0, len(frames), chunk):
+        sub = frames[q0:q0 + chunk]
+        c = _ctx(pot, sub, sp, box, False, ml_r_cut)
+        for k in range(len(sub)):
+            f, e, _, _ = c.ml_evaluate(model, k)
+            err += float(np.sum((f[0] - forces[q0 + k]) ** 2))
+            ref += float(np.sum(forces[q0 + k] ** 2))
+            de.append((e[0] - energies[q0 + k]) / N)
+        c.close()
+    n = forces.size
+    return math.sqrt(err / n), math.sqrt(err / ref), float(np.sqrt(np.mean(np.square(de))))
