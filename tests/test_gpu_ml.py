@@ -24,7 +24,7 @@ def _qtb():
     return qtb
 
 
-def frames_ctx(frames, sp, box, train=False, T=300.0, noise=0, graphs=True):
+def frames_ctx(frames, sp, box, train=False, T=300.0, noise=0, graphs=True, obs_every=0):
     qtb = _qtb()
     pot = W.mgo_potential()
     reps = [qtb.Replica(pos=f[None] if f.ndim == 2 else f, species=sp, T=T, gamma=1e-3, dt=1.0,
@@ -32,7 +32,7 @@ def frames_ctx(frames, sp, box, train=False, T=300.0, noise=0, graphs=True):
             for k, f in enumerate(frames)]
     return qtb.Context(qtb.pair_potential_dict(pot), reps, dict(W.METAL_UNITS),
                        prec=qtb.PREC_FP32, fir=qtb.FIR_FP32, max_two_nf=512, ml_r_cut=RC,
-                       ml_train=train, graphs=graphs)
+                       ml_train=train, graphs=graphs, obs_every=obs_every)
 
 
 def random_norm(seed):
@@ -170,76 +170,40 @@ def test_graph_replay_and_check_with_the_surrogate():
     assert outs[0][2] == outs[1][2]
 
 
-def _md_frames(temps, n_frames, every=25, warm=300):
-    """Frames of the 4x4x4 crystal from pair-potential Langevin runs on the GPU."""
+def test_training_on_qtb_frames_and_the_method_with_it():
+    """The learned part as it is meant to be used: trained on frames of the
+    method's own QTB (P = 1 at 100, 300, 1000 K) and QTB-PIMD (P = 4 beads at
+    100 K) runs, labelled by the pair potential.  On held-out frames the
+    force error falls from several times the force scale (untrained) to a
+    fraction of it, and the energy error to meV/atom; a QTB run at 600 K on
+    surrogate forces, judged by the pair potential every 32 steps, agrees;
+    and the method with the surrogate against the method with the pair
+    potential (QTB at 300 K, same crystal and noise, 10 000 steps): the mean
+    kinetic and potential energies per atom are close.  (The surrogate is
+    slower per step than the pair potential it approximates; the benchmark
+    reports both.  With a quarter of these frames the network has no
+    repulsive wall where the frames never went, and a long run collapses.)"""
     qtb = _qtb()
+    from paper_1905_02521_amd import surrogate
     pot = W.mgo_potential()
-    out = []
-    for k, T in enumerate(temps):
-        pos, sp, box = W.rocksalt(4)
-        pos = W.displaced(pos, 0.0421, 50 + k)
-        rep = qtb.Replica(pos=pos[None], species=sp, T=T, gamma=5e-3, dt=1.0, noise=0,
-                          box=tuple(box), seed=60 + k)
-        ctx = qtb.Context(qtb.pair_potential_dict(pot), [rep], dict(W.METAL_UNITS),
-                          prec=qtb.PREC_FP32, fir=qtb.FIR_FP32)
-        ctx.step(warm)
-        for _ in range(n_frames):
-            ctx.step(every)
-            out.append(ctx.get_state(0)[0][0])
-        ctx.close()
-    return out, sp, box
-
-
-def test_training_gains_over_the_untrained_network():
-    """What the learned part gains: trained on frames of the method's own runs
-    (300 K and 1000 K), the network's force error on held-out frames falls
-    from several times the force scale to a fraction of it, and the pair
-    potential's periodic check while stepping QTB on surrogate forces agrees.
-    (Against the pair potential itself the surrogate is slower per step; the
-    benchmark reports both.)"""
-    import torch
-    frames, sp, box = _md_frames((300.0, 1000.0), 12)
-    rng = np.random.default_rng(1)
-    perm = rng.permutation(len(frames))
-    train = [frames[k] for k in perm[:18]]
-    test = [frames[k] for k in perm[18:]]
-    tr = frames_ctx(train, sp, box, train=True)
-    te = frames_ctx(test, sp, box)
-
-    def labels(ctx, n):
-        F, E = [], []
-        for k in range(n):
-            f, e = ctx.evaluate(k)
-            F.append(f[0])
-            E.append(e[0])
-        return np.array(F), np.array(E)
-
-    Ftr, Etr = labels(tr, len(train))
-    Fte, Ete = labels(te, len(test))
-    qtb = _qtb()
+    conds = [(100.0, 1), (300.0, 1), (1000.0, 1), (100.0, 4)]
+    frames, forces, energies, sp, box, _ = surrogate.qtb_frames(pot, conds, n_frames=48,
+                                                                every=25, warm=300)
+    assert len(frames) == 48 * 7
+    perm = np.random.default_rng(1).permutation(len(frames))
+    te, tr = perm[:48], perm[48:]
     m = qtb.Model(RC, RMIN)
     m.init_params(2)
-    d_e = torch.tensor(Etr, dtype=torch.float64, device="cuda")
-    d_f = torch.tensor(Ftr.reshape(-1), dtype=torch.float64, device="cuda")
-    tr.ml_fit_norm(m, d_e)
-
-    def test_error():
-        err, ref, de = 0.0, 0.0, []
-        for k in range(len(test)):
-            f, e, _, _ = te.ml_evaluate(m, k)
-            err += np.sum((f[0] - Fte[k]) ** 2)
-            ref += np.sum(Fte[k] ** 2)
-            de.append((e[0] - Ete[k]) / len(sp))
-        return np.sqrt(err / ref), np.sqrt(np.mean(np.square(de)))
-
-    rel0, e0 = test_error()
-    losses = []
-    for it in range(300):
-        losses.append(tr.ml_train_step(m, d_e, d_f, 1.0, 1.0, 3e-3))
-    rel1, e1 = test_error()
+    # untrained error (the normalisation fitted on the training frames)
+    surrogate.train(m, pot, frames[tr], forces[tr], energies[tr], sp, box, steps=0)
+    _, rel0, _ = surrogate.errors(m, pot, frames[te], forces[te], energies[te], sp, box)
+    losses = surrogate.train(m, pot, frames[tr], forces[tr], energies[tr], sp, box, steps=1000)
+    _, rel1, e1 = surrogate.errors(m, pot, frames[te], forces[te], energies[te], sp, box)
+    print(f"held-out relative force error {rel0:.3f} -> {rel1:.3f}; energy error "
+          f"{e1 * 1e3:.3f} meV/atom; loss {losses[0]:.3g} -> {losses[-1]:.3g}")
     assert losses[-1] < 0.05 * losses[0]
-    assert rel1 < 0.35 and rel1 < 0.1 * rel0, (rel0, rel1)
-    assert e1 < 3e-3, e1   # eV per atom on held-out frames
+    assert rel1 < 0.3 and rel1 < 0.1 * rel0, (rel0, rel1)
+    assert e1 < 2e-3, e1   # eV per atom on held-out frames
     # QTB on surrogate forces, judged by the pair potential every 32 steps
     pos, _, _ = W.rocksalt(4)
     step_ctx = frames_ctx([W.displaced(pos, 0.0421, 70)], sp, box, T=600.0, noise=1)
@@ -249,4 +213,28 @@ def test_training_gains_over_the_untrained_network():
     rmse, rel, n = step_ctx.ml_check(0)
     r, v, _ = step_ctx.get_state(0)
     assert n == 8 and np.all(np.isfinite(r)) and np.all(np.isfinite(v))
-    assert rel < 0.35, rel
+    assert rel < 0.3, rel
+    step_ctx.close()
+    # the method with and without the network: QTB at 300 K
+    means = {}
+    for name in ("pair", "surrogate"):
+        c = frames_ctx([W.displaced(pos, 0.0421, 71)], sp, box, T=300.0, noise=1, obs_every=8)
+        c.build_filter(0, 1, 512)
+        if name == "surrogate":
+            c.ml_attach(m)
+        c.step(2000)
+        k, u = [], []
+        for _ in range(8):
+            c.step(1000)
+            o = c.observables(0)
+            k.append(o["kinetic"] / len(sp))
+            u.append(o["potential"] / len(sp))
+        means[name] = (np.mean(k), np.mean(u))
+        c.close()
+    dk = means["surrogate"][0] - means["pair"][0]
+    du = means["surrogate"][1] - means["pair"][1]
+    print(f"QTB 300 K: kinetic {means['pair'][0] * 1e3:.2f} (pair) / "
+          f"{means['surrogate'][0] * 1e3:.2f} (surrogate) meV/atom; potential difference "
+          f"{du * 1e3:+.2f} meV/atom")
+    assert abs(dk) < 0.05 * means["pair"][0]
+    assert abs(du) < 5e-3
