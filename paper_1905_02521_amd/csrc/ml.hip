@@ -1117,7 +1117,7 @@ __global__ void __launch_bounds__(1024) k_ml_train_mlp(const RepDev* __restrict_
 // both rank-one terms of a centre to a 32 x 32 tile, FP32 products (exact)
 // and FP32 accumulation.  Workgroup g (8 wavefronts) takes the network tiles
 // g, g + kWgBlocks, ... in order and stages 16 centres at a time in LDS
-// (zeros for padding); wavefronts 0-3 accumulate species 0, 4-7 species 1
+// (32 threads per centre, 16-byte loads; zeros for padding); wavefronts 0-3 accumulate species 0, 4-7 species 1
 // (a centre of the other species enters as zeros): W1 (64 x 96) is 2 x 3
 // tiles, W2 (64 x 64) 2 x 2, so wavefront w % 4 holds W1 row tile w % 4
 // (w % 4 < 2: three column tiles) or W2 row tile w % 4 - 2 (two).  The bias
@@ -1126,7 +1126,7 @@ __global__ void __launch_bounds__(1024) k_ml_train_mlp(const RepDev* __restrict_
 constexpr int kWgStage = 16;
 static_assert(kMlFeat == 96 && kMlHidden == 64, "the weight-gradient tiles assume 96 x 64 x 64");
 
-struct WgLds {
+struct __attribute__((aligned(16))) WgLds {
     float x[kWgStage][kMlFeat], xd[kWgStage][kMlFeat];
     float z1b[kWgStage][kMlHidden], z1db[kWgStage][kMlHidden];
     float h1[kWgStage][kMlHidden], h1d[kWgStage][kMlHidden];
@@ -1134,6 +1134,12 @@ struct WgLds {
     float e[kWgStage];
     int sp[kWgStage];   // species of the centre, -1 for padding
 };
+static_assert(offsetof(WgLds, t3) - offsetof(WgLds, z1b) ==
+                  6 * sizeof(float) * kWgStage * kMlHidden,
+              "the seven adjoint blocks are consecutive in the stage");
+static_assert(offsetof(WgLds, z1b) % 16 == 0 && offsetof(WgLds, xd) % 16 == 0,
+              "16-byte stage stores");
+static_assert(kWgStage * 32 == 512, "32 threads per staged centre");
 
 __global__ void __launch_bounds__(512) k_ml_wgrad_part(const RepDev* __restrict__ reps,
                                                        const MlDev m,
@@ -1153,37 +1159,45 @@ __global__ void __launch_bounds__(512) k_ml_wgrad_part(const RepDev* __restrict_
         for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
     // bias sums: threads of wavefront 0 (species 0) and 4 (species 1)
     float vb1 = 0.f, vb2 = 0.f, vw3 = 0.f, vb3 = 0.f;
-    constexpr int kRow = 2 * kMlFeat + 7 * kMlHidden + 1;
     for (int b = blockIdx.x; b < n_blocks; b += gridDim.x) {
         const BlockEntry be = blocks[b];
         const RepDev& R = reps[be.rep];
         const int N = R.N;
         for (int q0 = 0; q0 < be.group; q0 += kWgStage) {
             __syncthreads();  // previous stage consumed
-            for (int idx = t; idx < kWgStage * kRow; idx += blockDim.x) {
-                const int qi = idx / kRow, k = idx % kRow;
+            {
+                // 32 threads per centre, 16-byte loads along its rows
+                const int qi = t >> 5, sub = t & 31;
                 const int q = q0 + qi;
                 const bool valid = q < be.group;
                 const size_t c = (size_t)be.atom0 + (valid ? q : 0);
-                const int sp = R.species[c % N];
-                if (k == 0) L.sp[qi] = valid ? sp : -1;
-                const float* row = R.ml_adj + c * kMlAdj;
-                if (k < kMlFeat) {
-                    L.x[qi][k] = valid ? (R.ml_G[c * kMlFeat + k] - m.mu[sp * kMlFeat + k]) *
-                                             m.inv_sd[sp * kMlFeat + k]
-                                       : 0.0f;
-                } else if (k < 2 * kMlFeat) {
-                    L.xd[qi][k - kMlFeat] = valid ? row[k - kMlFeat] : 0.0f;
-                } else if (k < 2 * kMlFeat + 7 * kMlHidden) {
-                    const int kk = k - 2 * kMlFeat, blk = kk / kMlHidden, o = kk % kMlHidden;
-                    const float v = valid ? row[kMlFeat + kk] : 0.0f;
-                    float* dst = blk == 0 ? L.z1b[qi] : blk == 1 ? L.z1db[qi] : blk == 2 ? L.h1[qi]
-                               : blk == 3 ? L.h1d[qi] : blk == 4 ? L.z2b[qi] : blk == 5 ? L.z2db[qi]
-                               : L.t3[qi];
-                    dst[o] = v;
-                } else {
-                    L.e[qi] = valid ? row[kMlFeat + 7 * kMlHidden] : 0.0f;
+                const int sp = valid ? R.species[c % N] : -1;
+                if (sub == 0) L.sp[qi] = sp;
+                const float4* G4 = (const float4*)(R.ml_G + c * kMlFeat);
+                const float4* row4 = (const float4*)(R.ml_adj + c * kMlAdj);
+                const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (sub < kMlFeat / 4) {
+                    float4 g = valid ? G4[sub] : z4;
+                    if (valid) {
+                        const float* mu = m.mu + sp * kMlFeat + 4 * sub;
+                        const float* is = m.inv_sd + sp * kMlFeat + 4 * sub;
+                        g.x = (g.x - mu[0]) * is[0];
+                        g.y = (g.y - mu[1]) * is[1];
+                        g.z = (g.z - mu[2]) * is[2];
+                        g.w = (g.w - mu[3]) * is[3];
+                    }
+                    *(float4*)&L.x[qi][4 * sub] = g;
+                    *(float4*)&L.xd[qi][4 * sub] = valid ? row4[sub] : z4;
                 }
+                // z1b z1db h1 h1d z2b z2db t3: consecutive [kWgStage][64] arrays,
+                // the adjoint row's blocks in the same order
+                float* blk0 = &L.z1b[0][0];
+                for (int k4 = sub; k4 < 7 * kMlHidden / 4; k4 += 32) {
+                    const int blk = k4 / (kMlHidden / 4), o4 = k4 % (kMlHidden / 4);
+                    *(float4*)(blk0 + ((size_t)blk * kWgStage + qi) * kMlHidden + 4 * o4) =
+                        valid ? row4[kMlFeat / 4 + k4] : z4;
+                }
+                if (sub == 0) L.e[qi] = valid ? R.ml_adj[c * kMlAdj + kMlFeat + 7 * kMlHidden] : 0.0f;
             }
             __syncthreads();
             for (int qi = 0; qi < kWgStage; ++qi) {
