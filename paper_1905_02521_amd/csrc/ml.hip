@@ -1253,14 +1253,30 @@ __global__ void __launch_bounds__(512) k_ml_wgrad_part(const RepDev* __restrict_
     }
 }
 
-__global__ void k_ml_wgrad_sum(const float* __restrict__ part, int n_part, float* __restrict__ grad)
+// Sum of the n_part partial gradients in a fixed order, in FP64: block of 8
+// wavefronts per 64 parameters, wavefront w adds partials
+// [w n_part / 8, (w + 1) n_part / 8) in order, then the eight wavefront sums
+// are added in order.
+__global__ void __launch_bounds__(512) k_ml_wgrad_sum(const float* __restrict__ part, int n_part,
+                                                      float* __restrict__ grad)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= kMlParams) return;
-    const int a = p / kMlParamsSp, off = p % kMlParamsSp;
+    __shared__ double ws[8][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
     double acc = 0.0;
-    for (int g = 0; g < n_part; ++g) acc += (double)part[((size_t)g * kMlSpecies + a) * kMlParamsSp + off];
-    grad[p] = (float)acc;
+    if (p < kMlParams) {
+        const int a = p / kMlParamsSp, off = p % kMlParamsSp;
+        const int g0 = (w * n_part) / 8, g1 = ((w + 1) * n_part) / 8;
+        for (int g = g0; g < g1; ++g)
+            acc += (double)part[((size_t)g * kMlSpecies + a) * kMlParamsSp + off];
+    }
+    ws[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && p < kMlParams) {
+        double s = 0.0;
+        for (int q = 0; q < 8; ++q) s += ws[q][lane];
+        grad[p] = (float)s;
+    }
 }
 
 __global__ void k_ml_adam(float* __restrict__ master, uint16_t* __restrict__ wq,
@@ -1434,7 +1450,7 @@ void launch_ml_wgrad(hipStream_t st, const RepDev* reps, const MlDev& m,
 {
     launch(k_ml_wgrad_part, dim3(kWgBlocks), dim3(512), 0, st, reps, m, mblocks, n_mblocks,
            part);
-    launch(k_ml_wgrad_sum, dim3((kMlParams + 255) / 256), dim3(256), 0, st, part, (int)kWgBlocks,
+    launch(k_ml_wgrad_sum, dim3((kMlParams + 63) / 64), dim3(512), 0, st, part, (int)kWgBlocks,
            grad);
 }
 
