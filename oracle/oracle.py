@@ -17,6 +17,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qtb_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "qtb_oracle_abi.c")]
+_HDRS = [os.path.join(_HERE, "qtb_oracle.h"), os.path.join(_HERE, "qtb_oracle_abi.h")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # -ffp-contract=off: the Gaussian transform is specified operation by operation.
@@ -33,9 +35,10 @@ SAN_FLAGS = ["-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recove
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (always, when force=True)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(f) for f in _SRCS + _HDRS)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -44,7 +47,7 @@ def build_sanitized(out_dir: str) -> str:
     """Compile the oracle with the sanitizers into out_dir; returns the path."""
     os.makedirs(out_dir, exist_ok=True)
     out = os.path.join(out_dir, "liboracle_san.so")
-    subprocess.check_call(["gcc", *CFLAGS, *SAN_FLAGS, "-o", out, _SRC, "-lm"])
+    subprocess.check_call(["gcc", *CFLAGS, *SAN_FLAGS, "-o", out, *_SRCS, "-lm"])
     return out
 
 
@@ -382,3 +385,179 @@ class Sim:
         if getattr(self, "h", None):
             lib().orc_sim_free(self.h)
             self.h = None
+
+
+# ------------------------------------------------------------------------
+# The oracle behind the library's call shape (qtb_oracle_abi.h): one
+# harness can drive either back end.  Descriptions are duck-typed: any
+# object with the replica attributes (pos, vel, species, T, gamma, dt, noise,
+# box, seed, stream, harm_omega) and a potential dict with the library
+# binding's keys (kind, mass, charge, buck_A, buck_rho, buck_C, dsf_alpha,
+# r_cut, skin).
+class AbiPotential(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_species", ctypes.c_int32),
+                ("mass", _PD), ("charge", _PD), ("buck_A", _PD), ("buck_rho", _PD),
+                ("buck_C", _PD), ("dsf_alpha", ctypes.c_double), ("r_cut", ctypes.c_double),
+                ("skin", ctypes.c_double), ("onsite_V0", _PD), ("onsite_d", _PD)]
+
+
+class AbiReplica(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("n_beads", ctypes.c_int32),
+                ("n_dims", ctypes.c_int32), ("noise", ctypes.c_int32),
+                ("box", ctypes.c_double * 3), ("T", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("dt", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("stream", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("species", ctypes.POINTER(ctypes.c_int32)),
+                ("harm_omega", _PD), ("pos", _PD), ("vel", _PD)]
+
+
+class AbiOptions(ctypes.Structure):
+    _fields_ = [("hbar", ctypes.c_double), ("kB", ctypes.c_double),
+                ("coulomb_k", ctypes.c_double), ("mass_unit", ctypes.c_double),
+                ("prec", ctypes.c_int32), ("fir", ctypes.c_int32),
+                ("fir_block_K", ctypes.c_int32), ("obs_every", ctypes.c_int32),
+                ("max_two_nf", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("ml_r_cut", ctypes.c_double)]
+
+
+class AbiObs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("kinetic", ctypes.c_double),
+                ("potential", ctypes.c_double), ("spring", ctypes.c_double),
+                ("e_primitive", ctypes.c_double), ("e_virial", ctypes.c_double),
+                ("t_kinetic", ctypes.c_double), ("x2_mean", ctypes.c_double),
+                ("virial_pair", ctypes.c_double), ("pressure", ctypes.c_double),
+                ("volume", ctypes.c_double), ("n_samples", ctypes.c_int32)]
+
+
+class AbiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"oracle status {status}: {msg}")
+        self.status = status
+
+
+def _abi_lib():
+    L = lib()
+    if not getattr(L, "_abi_ready", False):
+        vp = ctypes.c_void_p
+        L.orc_qtb_workspace_bytes.restype = ctypes.c_size_t
+        L.orc_qtb_workspace_bytes.argtypes = [vp, vp, ctypes.c_int32, vp]
+        L.orc_qtb_init.restype = ctypes.c_int
+        L.orc_qtb_init.argtypes = [ctypes.POINTER(vp), vp, vp, ctypes.c_int32, vp, vp,
+                                   ctypes.c_size_t, vp]
+        L.orc_qtb_build_filter.restype = ctypes.c_int
+        L.orc_qtb_build_filter.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           _PD]
+        L.orc_qtb_step.restype = ctypes.c_int
+        L.orc_qtb_step.argtypes = [vp, ctypes.c_int64]
+        L.orc_qtb_observables.restype = ctypes.c_int
+        L.orc_qtb_observables.argtypes = [vp, ctypes.c_int32, vp]
+        L.orc_qtb_get_state.restype = ctypes.c_int
+        L.orc_qtb_get_state.argtypes = [vp, ctypes.c_int32, _PD, _PD,
+                                        ctypes.POINTER(ctypes.c_int64)]
+        L.orc_qtb_set_state.restype = ctypes.c_int
+        L.orc_qtb_set_state.argtypes = [vp, ctypes.c_int32, _PD, _PD, ctypes.c_int64]
+        L.orc_qtb_last_error.restype = ctypes.c_char_p
+        L.orc_qtb_last_error.argtypes = [vp]
+        L.orc_qtb_destroy.restype = None
+        L.orc_qtb_destroy.argtypes = [vp]
+        L._abi_ready = True
+    return L
+
+
+class AbiContext:
+    """The oracle driven through its ABI-shaped calls, with the methods of
+    the library binding's Context that the parity harness uses
+    (build_filter, step, observables, get_state, set_state, close)."""
+
+    def __init__(self, potd, reps, units, obs_every=0, max_two_nf=512):
+        L = _abi_lib()
+        self._keep = []
+
+        def arr(x, dt=np.float64):
+            a = np.ascontiguousarray(x, dtype=dt)
+            self._keep.append(a)
+            return a
+        mass = arr(potd["mass"])
+        ns = len(mass)
+        pot = AbiPotential()
+        pot.kind, pot.n_species = int(potd.get("kind", 0)), ns
+        pot.mass = _pd(mass)
+        for key in ("charge", "buck_A", "buck_rho", "buck_C"):
+            if potd.get(key) is not None:
+                setattr(pot, key, _pd(arr(potd[key])))
+        pot.dsf_alpha = float(potd.get("dsf_alpha", 0.0))
+        pot.r_cut = float(potd.get("r_cut", 1.0))
+        pot.skin = float(potd.get("skin", 0.0))
+        n = len(reps)
+        self.reps = (AbiReplica * n)()
+        self.shapes, self.state = [], []
+        for k, rp in enumerate(reps):
+            pos = arr(np.array(rp.pos, dtype=np.float64))
+            vel = arr(np.zeros_like(pos) if rp.vel is None else np.array(rp.vel, np.float64))
+            P, dims, N = pos.shape
+            R = self.reps[k]
+            R.n_atoms, R.n_beads, R.n_dims, R.noise = N, P, dims, int(rp.noise)
+            if rp.box is not None:
+                for a in range(3):
+                    R.box[a] = float(rp.box[a])
+            R.T, R.gamma, R.dt = float(rp.T), float(rp.gamma), float(rp.dt)
+            R.seed, R.stream = int(rp.seed), int(rp.stream)
+            sp = arr(rp.species, np.int32)
+            R.species = sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            if getattr(rp, "harm_omega", None) is not None:
+                R.harm_omega = _pd(arr(rp.harm_omega))
+            R.pos, R.vel = _pd(pos), _pd(vel)
+            self.shapes.append((P, dims, N))
+            self.state.append((pos, vel))
+        opt = AbiOptions()
+        opt.hbar, opt.kB = units["hbar"], units["kB"]
+        opt.coulomb_k, opt.mass_unit = units.get("coulomb_k", 0.0), units["mass_unit"]
+        opt.prec, opt.fir, opt.fir_block_K = 1, 3, 64
+        opt.obs_every, opt.max_two_nf = int(obs_every), int(max_two_nf)
+        self.ctx = ctypes.c_void_p()
+        st = L.orc_qtb_init(ctypes.byref(self.ctx), ctypes.byref(pot), self.reps, n,
+                            ctypes.byref(opt), None, 0, None)
+        if st:
+            raise AbiError(st, "orc_qtb_init rejected the description")
+
+    def _check(self, st):
+        if st:
+            raise AbiError(st, _abi_lib().orc_qtb_last_error(self.ctx).decode())
+
+    def build_filter(self, replica, kind, two_nf):
+        taps = np.zeros(max(int(two_nf), 2))
+        self._check(_abi_lib().orc_qtb_build_filter(self.ctx, replica, kind, two_nf, _pd(taps)))
+        return taps
+
+    def step(self, n):
+        self._check(_abi_lib().orc_qtb_step(self.ctx, int(n)))
+
+    def observables(self, replica=0):
+        o = AbiObs()
+        self._check(_abi_lib().orc_qtb_observables(self.ctx, replica, ctypes.byref(o)))
+        return {f: getattr(o, f) for f, _ in AbiObs._fields_}
+
+    def get_state(self, replica=0):
+        r, v = np.zeros(self.shapes[replica]), np.zeros(self.shapes[replica])
+        st = ctypes.c_int64()
+        self._check(_abi_lib().orc_qtb_get_state(self.ctx, replica, _pd(r), _pd(v),
+                                                 ctypes.byref(st)))
+        return r, v, st.value
+
+    def set_state(self, replica, pos, vel, step):
+        p = None if pos is None else np.ascontiguousarray(pos, dtype=np.float64)
+        v = None if vel is None else np.ascontiguousarray(vel, dtype=np.float64)
+        self._check(_abi_lib().orc_qtb_set_state(self.ctx, replica,
+                                                 None if p is None else _pd(p),
+                                                 None if v is None else _pd(v), int(step)))
+
+    def close(self):
+        if self.ctx:
+            _abi_lib().orc_qtb_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -175,6 +175,52 @@ def test_crystal_trajectory_fp32_close(orc):
     assert rel <= 1e-5, rel
 
 
+# ------------------------------------------------------------- one harness, two back ends
+def _harness(make_ctx, reps, noise_of):
+    """Drive a context through the call shape both back ends export: build
+    the filters, 10 + 54 eager steps and a 64-step block, a checkpoint
+    restore, 30 more steps; returns the states and the observables."""
+    ctx = make_ctx()
+    for k in range(len(reps)):
+        ctx.build_filter(k, noise_of[k], 128)
+    out = []
+    for n in (10, 54, 64):
+        ctx.step(n)
+    r, v, st = ctx.get_state(0)
+    ctx.set_state(0, r, v, st)
+    ctx.step(30)
+    for k in range(len(reps)):
+        out.append((ctx.get_state(k), ctx.observables(k)))
+    ctx.close()
+    return out
+
+
+def test_one_harness_drives_both_back_ends(orc):
+    """The same harness code on the library (FP64) and on the oracle behind
+    the library's call shape: states to 1e-9, sampled means to 1e-9."""
+    specs = [(2, 4, 2, 100.0, 5), (3, 1, 1, 300.0, 6)]
+    reps, noise_of = [], []
+    for k, (n, P, noise, T, seed) in enumerate(specs):
+        beads, sp, box = crystal(n, P, seed=seed, bead_spread=0.02 if P > 1 else 0.0)
+        reps.append(qtb.Replica(pos=beads, species=sp, T=T, gamma=5e-3, dt=1.0, noise=noise,
+                                box=tuple(box), seed=seed, stream=k))
+        noise_of.append(noise)
+    potd = qtb.pair_potential_dict(W.mgo_potential())
+    gpu = _harness(lambda: qtb.Context(potd, reps, dict(W.METAL_UNITS), prec=qtb.PREC_FP64,
+                                       fir=qtb.FIR_FP64, max_two_nf=128, obs_every=8),
+                   reps, noise_of)
+    ora = _harness(lambda: orc.AbiContext(potd, reps, dict(W.METAL_UNITS), obs_every=8,
+                                          max_two_nf=128), reps, noise_of)
+    for ((r, v, st), og), ((ro, vo, so), oo) in zip(gpu, ora):
+        assert st == so == 158
+        assert np.sqrt(np.mean((r - ro) ** 2)) <= 1e-9 * 0.0421
+        assert np.sqrt(np.mean((v - vo) ** 2)) <= 1e-9 * np.sqrt(np.mean(vo ** 2))
+        assert og["n_samples"] == oo["n_samples"] == 19
+        for f in ("kinetic", "potential", "e_primitive", "e_virial", "x2_mean", "pressure",
+                  "volume"):
+            assert abs(og[f] - oo[f]) <= 1e-9 * max(abs(oo[f]), 1e-12), f
+
+
 # ------------------------------------------------------------------ observables
 @pytest.mark.parametrize("P,noise", [(1, 1), (4, 2), (16, 2), (32, 0)])
 def test_observables_match_oracle(orc, P, noise):

@@ -22,7 +22,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE_TESTS = ["tests/test_oracle_forces.py", "tests/test_oracle_noise.py",
                 "tests/test_oracle_observe.py", "tests/test_oracle_pressure.py",
-                "tests/test_oracle_barostat.py"]
+                "tests/test_oracle_barostat.py", "tests/test_oracle_abi.py"]
 HOST_TESTS = ["tests/test_host_layout.py", "tests/test_abi.py", "tests/test_host_filter.py"]
 SAN_ENV = {"ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1",
            "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1"}
