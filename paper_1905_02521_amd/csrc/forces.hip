@@ -160,9 +160,21 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
         pC[b] = q.C;
         pE0[b] = q.E0;
     }
-    // keep the parameters of neighbour species 1, 2, ... in VGPRs for the
-    // whole loop (a select on gfx950 takes at most one SGPR operand, which
-    // species 0's uniform values use)
+    // Two species in the FP32 path: a neighbour's parameters are the blend
+    // p0 + s_j (p1 - p0) with s_j in {0, 1}, one FMA each (p0 uniform, the
+    // difference in a VGPR); s_j = 0 gives p0 exactly, s_j = 1 gives p1 to
+    // the rounding of p1 - p0 (one unit in the last place).  Otherwise keep
+    // the parameters of neighbour species 1, 2, ... in VGPRs for the whole
+    // loop (an instruction on gfx950 reads at most one SGPR, VCC included, so
+    // a select of a uniform species-0 value needs its own move).
+    constexpr bool BLEND = FAST && NS == 2;
+    if constexpr (BLEND) {
+        pArho[1] -= pArho[0];
+        pirho[1] -= pirho[0];
+        pC6[1] -= pC6[0];
+        pkqq[1] -= pkqq[0];
+        pF0[1] -= pF0[0];
+    }
 #pragma unroll
     for (int b = 1; b < NS; ++b) {
         asm volatile("" : "+v"(pArho[b]), "+v"(pirho[b]), "+v"(pC6[b]), "+v"(pkqq[b]),
@@ -176,6 +188,9 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
     }
     const T rc2 = tab.rc2, a2l = tab.a2l, s_mul = tab.s_mul, alpha = tab.alpha, g = tab.g;
     const T ph_s = tab.ph_s;
+    // the Horner start in a VGPR, so its first FMA reads one SGPR only
+    T ph_top = ph[DEG];
+    asm volatile("" : "+v"(ph_top));
     const int maxnb = R.maxnb;
     const int cnt = R.nb_count[i], ncore = R.nb_core[i];
     // entries of a list built before the box last changed scale with it,
@@ -202,14 +217,23 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
         if (r2 < rc2) {
             const int spj = vbits(U0);
             T Arho = pArho[0], irho = pirho[0], C6 = pC6[0], kqq = pkqq[0], F0 = pF0[0];
+            if constexpr (BLEND) {
+                const T sj = (T)spj;
+                Arho = fmaf(sj, pArho[1], Arho);
+                irho = fmaf(sj, pirho[1], irho);
+                C6 = fmaf(sj, pC6[1], C6);
+                kqq = fmaf(sj, pkqq[1], kqq);
+                F0 = fmaf(sj, pF0[1], F0);
+            } else {
 #pragma unroll
-            for (int b = 1; b < NS; ++b) {
-                const bool m = spj == b;
-                Arho = m ? pArho[b] : Arho;
-                irho = m ? pirho[b] : irho;
-                C6 = m ? pC6[b] : C6;
-                kqq = m ? pkqq[b] : kqq;
-                F0 = m ? pF0[b] : F0;
+                for (int b = 1; b < NS; ++b) {
+                    const bool m = spj == b;
+                    Arho = m ? pArho[b] : Arho;
+                    irho = m ? pirho[b] : irho;
+                    C6 = m ? pC6[b] : C6;
+                    kqq = m ? pkqq[b] : kqq;
+                    F0 = m ? pF0[b] : F0;
+                }
             }
             T rinv, r, e1, ec = (T)0, e2 = (T)0, Fc;
             if constexpr (FAST) {
@@ -217,7 +241,7 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                 r = r2 * rinv;
                 e1 = __builtin_amdgcn_exp2f(-r * irho);
                 const T sp = fmaf(r2, ph_s, -1.0f);
-                T ps = ph[DEG];
+                T ps = ph_top;
 #pragma unroll
                 for (int k = DEG - 1; k >= 0; --k) ps = fmaf(ps, sp, ph[k]);
                 const T rinv2 = rinv * rinv;
