@@ -267,9 +267,18 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
             const T rinv6 = rinv2 * rinv2 * rinv2;
             const T F = Arho * e1 - C6 * rinv6 * rinv + kqq * Fc + F0;
             const T fr = F * rinv;
-            fx += (double)(fr * dx);
-            fy += (double)(fr * dy);
-            fz += (double)(fr * dz);
+            if constexpr (sizeof(T) == 4) {
+                // FP64 sums of the exact products (fr dx in FP64): one
+                // conversion of fr shared by the three components
+                const double frd = (double)fr;
+                fx = __builtin_fma(frd, (double)dx, fx);
+                fy = __builtin_fma(frd, (double)dy, fy);
+                fz = __builtin_fma(frd, (double)dz, fz);
+            } else {
+                fx += fr * dx;
+                fy += fr * dy;
+                fz += fr * dz;
+            }
             if (want_e) {
                 T A = pA[0], C = pC[0], E0c = pE0[0];
 #pragma unroll
