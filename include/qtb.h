@@ -441,6 +441,23 @@ qtb_status qtb_get_barostat_state(qtb_ctx *ctx, int32_t replica, double *h_state
 qtb_status qtb_set_barostat_state(qtb_ctx *ctx, int32_t replica, const double *h_state);
 
 /*
+ * Decomposition of the pair-force kernel (pair potential): waves_per_atom
+ * wavefronts share one atom's neighbour list (1, 2 or 4), and each wavefront
+ * holds G beads of it, G the widest power of two up to 8 that divides P, or
+ * half of that (half_groups != 0; no effect where G = 1).  Every choice
+ * computes the same forces; the order of the sums, and so the last bits,
+ * depend on it.  The first qtb_step of a context times all choices on the
+ * actual replicas and keeps the fastest (unless QTB_OPT_NO_AUTOTUNE);
+ * qtb_set_decomposition pins one instead (for bit-reproducible runs across
+ * contexts) and skips that autotuning.  QTB_E_INVALID for other values, a
+ * potential other than the pair potential, with the surrogate attached
+ * anything but (1, 0), and half groups with the one-kernel step.  Both
+ * synchronise.
+ */
+qtb_status qtb_set_decomposition(qtb_ctx *ctx, int32_t waves_per_atom, int32_t half_groups);
+qtb_status qtb_get_decomposition(qtb_ctx *ctx, int32_t *waves_per_atom, int32_t *half_groups);
+
+/*
  * Diagnostics: while enabled, qtb_step records a HIP event pair around every
  * kernel phase on the context's stream (steps then run without graph
  * replay).  qtb_profile_read synchronises and returns, per phase, the total

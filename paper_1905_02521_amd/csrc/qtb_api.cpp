@@ -66,9 +66,13 @@ struct Layout {
     std::vector<BlockEntry> upd, nl, force;   // force: table of the chosen W
     std::vector<BlockEntry> tb;               // candidate tiles of the list kernel
     int upd_threads = 128;
-    std::vector<BlockEntry> force_w[3];        // W = 1, 2, 4
-    std::vector<std::pair<int, std::pair<int, int>>> force_groups_w[3];
-    std::vector<int> obs_b0_w[3], obs_nb_w[3];
+    // force tables for every decomposition the autotuner tries: index
+    // 2 wi + gi, W = 2^wi wavefronts per atom, gi = 0 the widest bead group
+    // G that divides P (up to 8), gi = 1 half of it (G / 2 beads per
+    // wavefront and twice the groups; the same as gi = 0 where G = 1)
+    std::vector<BlockEntry> force_w[6];
+    std::vector<std::pair<int, std::pair<int, int>>> force_groups_w[6];
+    std::vector<int> obs_b0_w[6], obs_nb_w[6];
     size_t max_force_blocks = 1;
     std::vector<std::pair<int, std::pair<int, int>>> upd_groups;    // P -> [b0, b1)
     std::vector<std::pair<int, std::pair<int, int>>> force_groups;  // G -> [b0, b1)
@@ -251,38 +255,39 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
         for (int a = 0; a < reps[r].n_atoms; a += 4) L.nl.push_back({r, a, 0, 0});
         for (int a = 0; a < reps[r].n_atoms; a += kListTile) L.tb.push_back({r, a, 0, 0});
     }
-    // force tables for every waves-per-atom choice (the autotuner picks one)
-    for (int wi = 0; wi < 3; ++wi) {
+    // force tables for every decomposition (the autotuner picks one)
+    for (int t = 0; t < 6; ++t) {
+        const int wi = t / 2, gi = t % 2;
         const int W = 1 << wi, apb = 4 / W;
-        auto& F = L.force_w[wi];
-        auto& FG = L.force_groups_w[wi];
+        auto& F = L.force_w[t];
+        auto& FG = L.force_groups_w[t];
         F.clear();
         FG.clear();
-        L.obs_b0_w[wi].assign(n_rep, 0);
-        L.obs_nb_w[wi].assign(n_rep, 0);
+        L.obs_b0_w[t].assign(n_rep, 0);
+        L.obs_nb_w[t].assign(n_rep, 0);
         if (pair) {
             for (auto& kv : byG) {
-                const int G = kv.first;
+                const int G = (gi && kv.first > 1) ? kv.first / 2 : kv.first;
                 const int b0 = (int)F.size();
                 for (int r : kv.second) {
-                    L.obs_b0_w[wi][r] = (int)F.size();
+                    L.obs_b0_w[t][r] = (int)F.size();
                     for (int g = 0; g < reps[r].n_beads / G; ++g)
                         for (int a = 0; a < reps[r].n_atoms; a += apb) F.push_back({r, a, g, 0});
-                    L.obs_nb_w[wi][r] = (int)F.size() - L.obs_b0_w[wi][r];
+                    L.obs_nb_w[t][r] = (int)F.size() - L.obs_b0_w[t][r];
                 }
                 FG.push_back({G, {b0, (int)F.size()}});
             }
         } else {
             for (int r = 0; r < n_rep; ++r) {
-                L.obs_b0_w[wi][r] = (int)F.size();
+                L.obs_b0_w[t][r] = (int)F.size();
                 for (int a = 0; a < reps[r].n_atoms; a += 256) F.push_back({r, a, 0, 0});
-                L.obs_nb_w[wi][r] = (int)F.size() - L.obs_b0_w[wi][r];
+                L.obs_nb_w[t][r] = (int)F.size() - L.obs_b0_w[t][r];
             }
             FG.push_back({0, {0, (int)F.size()}});
         }
         L.max_force_blocks = std::max(L.max_force_blocks, F.size());
     }
-    const int wdef = kWavesPerAtomDefault == 1 ? 0 : (kWavesPerAtomDefault == 2 ? 1 : 2);
+    const int wdef = 2 * (kWavesPerAtomDefault == 1 ? 0 : (kWavesPerAtomDefault == 2 ? 1 : 2));
     L.force = L.force_w[wdef];
     L.force_groups = L.force_groups_w[wdef];
     L.obs_b0 = L.obs_b0_w[wdef];
@@ -459,6 +464,7 @@ struct qtb_ctx {
     bool ring_valid = false;
     std::string err;
     int W = kWavesPerAtomDefault;  // force kernel wavefronts per atom
+    bool half_groups = false;      // force kernel: half the widest bead group per wavefront
     bool tuned = false;
     // captured noise blocks of K steps, replayed while nothing changes; one
     // per sampling / checking pattern (block start modulo obs_every and
@@ -1347,15 +1353,16 @@ int64_t graph_rows(qtb_ctx* c, int64_t left)
 
 // Make the force table of W current (host image, device copy, replica
 // observable ranges); drops the captured graph, whose launches embed it.
-qtb_status select_force_table(qtb_ctx* c, int W)
+qtb_status select_force_table(qtb_ctx* c, int W, int half)
 {
     Layout& L = c->L;
-    const int wi = W == 1 ? 0 : (W == 2 ? 1 : 2);
-    L.force = L.force_w[wi];
-    L.force_groups = L.force_groups_w[wi];
-    L.obs_b0 = L.obs_b0_w[wi];
-    L.obs_nb = L.obs_nb_w[wi];
+    const int t = 2 * (W == 1 ? 0 : (W == 2 ? 1 : 2)) + (half ? 1 : 0);
+    L.force = L.force_w[t];
+    L.force_groups = L.force_groups_w[t];
+    L.obs_b0 = L.obs_b0_w[t];
+    L.obs_nb = L.obs_nb_w[t];
     c->W = W;
+    c->half_groups = half != 0;
     for (int r = 0; r < c->n_rep; ++r) {
         c->rd[r].obs_block0 = L.obs_b0[r];
         c->rd[r].obs_nblocks = L.obs_nb[r];
@@ -1369,38 +1376,48 @@ qtb_status select_force_table(qtb_ctx* c, int W)
 }
 
 // Autotuner: time the pair-force kernel of the actual workload for every
-// waves-per-atom choice (forces only, no kick: the state is unchanged) and
-// keep the fastest, best of three launches each (all replica groups).
+// decomposition, waves per atom W in {1, 2, 4} times beads per wavefront G
+// (the widest group that divides P, or half of it), forces only with no kick
+// (the state is unchanged), and keep the fastest: one warm-up launch, then
+// the best of five (all replica groups).  The one-kernel step keeps whole ring polymers per
+// wavefront.
 qtb_status autotune(qtb_ctx* c)
 {
     c->tuned = true;
     if (!c->pair || c->ml || (c->opt.flags & QTB_OPT_NO_AUTOTUNE)) return QTB_OK;
+    bool can_half = !(c->opt.flags & QTB_OPT_FUSE);
+    bool any_half = false;
+    for (const auto& R : c->reps) any_half = any_half || bead_group(R.n_beads) > 1;
+    can_half = can_half && any_half;
     hipEvent_t a = nullptr, b = nullptr;
     QTB_HIP(c, hipEventCreate(&a));
     QTB_HIP(c, hipEventCreate(&b));
     float best = 1e30f;
-    int bestW = c->W;
-    for (int W : {1, 2, 4}) {
-        qtb_status s = select_force_table(c, W);
-        if (s) return s;
-        float tmin = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-            QTB_HIP(c, hipEventRecord(a, c->st));
-            launch_plain_forces(c, 0);
-            QTB_HIP(c, hipEventRecord(b, c->st));
-            QTB_HIP(c, hipEventSynchronize(b));
-            float t = 0.0f;
-            QTB_HIP(c, hipEventElapsedTime(&t, a, b));
-            tmin = std::min(tmin, t);
+    int bestW = c->W, bestH = c->half_groups ? 1 : 0;
+    for (int half = 0; half <= (can_half ? 1 : 0); ++half)
+        for (int W : {1, 2, 4}) {
+            qtb_status s = select_force_table(c, W, half);
+            if (s) return s;
+            float tmin = 1e30f;
+            launch_plain_forces(c, 0);  // warm-up (caches, first-touch)
+            for (int rep = 0; rep < 5; ++rep) {
+                QTB_HIP(c, hipEventRecord(a, c->st));
+                launch_plain_forces(c, 0);
+                QTB_HIP(c, hipEventRecord(b, c->st));
+                QTB_HIP(c, hipEventSynchronize(b));
+                float t = 0.0f;
+                QTB_HIP(c, hipEventElapsedTime(&t, a, b));
+                tmin = std::min(tmin, t);
+            }
+            if (tmin < best) {
+                best = tmin;
+                bestW = W;
+                bestH = half;
+            }
         }
-        if (tmin < best) {
-            best = tmin;
-            bestW = W;
-        }
-    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    qtb_status s = select_force_table(c, bestW);
+    qtb_status s = select_force_table(c, bestW, bestH);
     if (s) return s;
     QTB_HIP(c, hipStreamSynchronize(c->st));
     return QTB_OK;
@@ -2051,6 +2068,31 @@ qtb_status qtb_get_box(qtb_ctx* c, int32_t replica, double* h_box)
     return read_status(c);
 }
 
+qtb_status qtb_set_decomposition(qtb_ctx* c, int32_t waves_per_atom, int32_t half_groups)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (!c->pair) return fail(c, QTB_E_INVALID, "decomposition: pair potential only");
+    if (waves_per_atom != 1 && waves_per_atom != 2 && waves_per_atom != 4)
+        return fail(c, QTB_E_INVALID, "waves_per_atom must be 1, 2 or 4");
+    if (c->ml && (waves_per_atom != 1 || half_groups))
+        return fail(c, QTB_E_INVALID, "with the surrogate attached: 1 wavefront, whole groups");
+    if (half_groups && (c->opt.flags & QTB_OPT_FUSE))
+        return fail(c, QTB_E_INVALID, "the one-kernel step keeps whole groups");
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    if (qtb_status s = select_force_table(c, waves_per_atom, half_groups ? 1 : 0)) return s;
+    c->tuned = true;  // pinned: no autotuning at the next step
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    return read_status(c);
+}
+
+qtb_status qtb_get_decomposition(qtb_ctx* c, int32_t* waves_per_atom, int32_t* half_groups)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (waves_per_atom) *waves_per_atom = c->W;
+    if (half_groups) *half_groups = c->half_groups ? 1 : 0;
+    return QTB_OK;
+}
+
 qtb_status qtb_profile(qtb_ctx* c, int32_t enable)
 {
     if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
@@ -2231,7 +2273,7 @@ qtb_status qtb_ml_attach(qtb_ctx* c, qtb_ml* m, int32_t check_every)
     qtb_status s = QTB_OK;
     if (m) {
         // one wavefront per atom in the gather: the W = 1 table
-        if ((s = select_force_table(c, 1))) return s;
+        if ((s = select_force_table(c, 1, 0))) return s;
         c->tuned = true;
         launch_fill(c->st, c->at<double>(c->L.ml_acc), 2 * kAcc * c->n_rep, 0);
         launch_fill(c->st, c->at<int32_t>(c->L.ml_counts), c->n_rep, 0);

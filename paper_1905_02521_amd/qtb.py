@@ -92,6 +92,7 @@ EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
            "qtb_vdos_attach", "qtb_vdos_read",
            "qtb_vdos_detach", "qtb_barostat", "qtb_barostat_piston", "qtb_get_box",
            "qtb_get_barostat_state", "qtb_set_barostat_state", "qtb_filter_taps",
+           "qtb_set_decomposition", "qtb_get_decomposition",
            "qtb_last_error", "qtb_destroy", "qtb_version",
            "qtb_ml_workspace_bytes", "qtb_ml_create", "qtb_ml_init_params", "qtb_ml_set_params",
            "qtb_ml_get_params", "qtb_ml_attach", "qtb_ml_evaluate", "qtb_ml_fit_norm",
@@ -168,6 +169,11 @@ def lib():
     L.qtb_get_barostat_state.argtypes = [vp, ctypes.c_int32, _PD]
     L.qtb_set_barostat_state.restype = ctypes.c_int
     L.qtb_set_barostat_state.argtypes = [vp, ctypes.c_int32, _PD]
+    L.qtb_set_decomposition.restype = ctypes.c_int
+    L.qtb_set_decomposition.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.qtb_get_decomposition.restype = ctypes.c_int
+    L.qtb_get_decomposition.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]
     L.qtb_profile.restype = ctypes.c_int
     L.qtb_profile.argtypes = [vp, ctypes.c_int32]
     L.qtb_profile_read.restype = ctypes.c_int
@@ -485,6 +491,16 @@ class Context:
         1 / time)."""
         _check(lib().qtb_barostat_piston(self.ctx, replica, float(P0), float(tau_p),
                                          float(gamma_p), 1 if enable else 0), self.ctx)
+
+    def set_decomposition(self, waves_per_atom, half_groups=False):
+        """Pin the pair-force kernel's decomposition (no autotuning)."""
+        _check(lib().qtb_set_decomposition(self.ctx, int(waves_per_atom),
+                                           1 if half_groups else 0), self.ctx)
+
+    def decomposition(self):
+        w, h = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qtb_get_decomposition(self.ctx, ctypes.byref(w), ctypes.byref(h)), self.ctx)
+        return w.value, bool(h.value)
 
     def box(self, replica=0):
         b = np.zeros(3)

@@ -117,6 +117,53 @@ def test_forces_match_bruteforce(orc, prec, tol, n_cells, P):
         assert abs(e[b] - eo) <= (1e-6 if prec == qtb.PREC_FP32 else 1e-11) * abs(eo)
 
 
+@pytest.mark.parametrize("prec,tol", [(qtb.PREC_FP32, 1e-5), (qtb.PREC_FP64, 1e-12)])
+@pytest.mark.parametrize("P", [4, 8, 6])
+def test_every_decomposition_matches_bruteforce(orc, prec, tol, P):
+    """The autotuner's choices (1, 2 or 4 wavefronts per atom; the widest
+    bead group per wavefront or half of it): each gives the brute-force
+    forces, and pinning one skips the autotuning."""
+    beads, sp, box = crystal(3, P, seed=8, bead_spread=0.03)
+    fir = qtb.FIR_FP64 if prec == qtb.PREC_FP64 else qtb.FIR_FP32
+    ctx = gpu_crystal_ctx(beads, sp, box, T=100.0, gamma=1e-3, dt=1.0, noise=0, prec=prec,
+                          fir=fir)
+    U = oracle_units(orc, False)
+    pot = oracle_pair_pot(orc)
+    ref = [orc.pair_bruteforce(pot, U, box, sp, beads[b])[1] for b in range(P)]
+    for W in (1, 2, 4):
+        for half in (False, True):
+            ctx.set_decomposition(W, half)
+            assert ctx.decomposition() == (W, half)
+            f, _ = ctx.evaluate(0)
+            for b in range(P):
+                assert _force_rel(f[b], ref[b]) <= tol, (W, half, b)
+    ctx.set_decomposition(2, True)
+    ctx.step(3)   # pinned: the first step does not retune
+    assert ctx.decomposition() == (2, True)
+    for bad in ((3, False), (0, True)):
+        with pytest.raises(qtb.QtbError):
+            ctx.set_decomposition(*bad)
+    ctx.close()
+
+
+def test_half_groups_trajectory_fp64(orc):
+    """QTB-PIMD (P = 8) with four beads per wavefront, 40 steps in FP64
+    against the oracle (the bead groups of one atom sit in separate
+    workgroups)."""
+    P = 8
+    beads, sp, box = crystal(3, P, seed=4, bead_spread=0.02)
+    T, gamma, dt, seed = 100.0, 5e-3, 1.0, 12
+    ctx = gpu_crystal_ctx(beads, sp, box, T=T, gamma=gamma, dt=dt, noise=2,
+                          prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, seed=seed, max_two_nf=128)
+    ctx.build_filter(0, 2, 128)
+    ctx.set_decomposition(1, True)
+    osim = orc.Sim(oracle_pair_pot(orc), oracle_units(orc, False), beads.shape[2], P, 3, box,
+                   sp, T, gamma, dt, seed, 0, 2, 128, beads, n_threads=8)
+    rel, dv = _traj_compare(orc, ctx, osim, 40, 0.0421)
+    assert rel <= 1e-9, rel
+    ctx.close()
+
+
 # ------------------------------------------------------------------ trajectories
 def _traj_compare(orc, ctx, osim, n_steps, scale):
     ctx.step(n_steps)
