@@ -34,8 +34,10 @@ def qtb_frames(pot, conditions, n_frames, every=40, warm=2000, n_cells=4, gamma=
         reps.append(qtb.Replica(pos=beads, species=sp, T=float(T), gamma=gamma, dt=1.0,
                                 noise=1 if P == 1 else 2, box=tuple(box), seed=500 + seed,
                                 stream=k))
+    # one fixed force decomposition: the same frames on every run
     ctx = qtb.Context(qtb.pair_potential_dict(pot), reps, dict(W.METAL_UNITS),
-                      prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3, max_two_nf=two_nf)
+                      prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3, max_two_nf=two_nf,
+                      autotune=False)
     for k, (_, P) in enumerate(conditions):
         ctx.build_filter(k, 1 if P == 1 else 2, two_nf)
     ctx.step(warm)
