@@ -183,7 +183,7 @@ def test_training_on_qtb_frames_and_the_method_with_it():
     slower per step than the pair potential it approximates; the benchmark
     reports both.  With an eighth of these frames the network has no
     repulsive wall where the frames never went and a long run collapses; with
-    half of them it did in one run out of three.)"""
+    half of them it did in one of two runs.)"""
     qtb = _qtb()
     from paper_1905_02521_amd import surrogate
     pot = W.mgo_potential()
