@@ -258,7 +258,7 @@ def surrogate_bench(a):
     t_gen = time.perf_counter()
     conds = [(50.0, 1), (100.0, 1), (200.0, 1), (400.0, 1), (700.0, 1), (1000.0, 1),
              (50.0, 4), (100.0, 4), (300.0, 4)]
-    frames, forces, energies, sp, box, tags = surrogate.qtb_frames(pot, conds, n_frames=96,
+    frames, forces, energies, sp, box, tags = surrogate.qtb_frames(pot, conds, n_frames=a.ml_samples,
                                                                    every=40, warm=2000)
     t_gen = time.perf_counter() - t_gen
     perm = np.random.default_rng(0).permutation(len(frames))
@@ -266,7 +266,7 @@ def surrogate_bench(a):
     te, tr = perm[:n_test], perm[n_test:]
     model = qtb.Model(6.0, 0.5)
     model.init_params(1)
-    n_train = 1500
+    n_train = a.ml_steps
     torch.cuda.synchronize()
     t_train = time.perf_counter()
     losses = surrogate.train(model, pot, frames[tr], forces[tr], energies[tr], sp, box,
@@ -319,7 +319,7 @@ def surrogate_bench(a):
         "value": ab / ml_s, "unit": "atom-bead-steps/s", "n_gpus": 1, "steps": steps,
         "ms_per_step": ml_s * 1e3, "higher_is_better": True, "dtype": "f32 (bf16 weights)",
         "data": "synthetic (seeded rock-salt crystal; training frames from the method's own "
-                "pair-potential runs)",
+                "QTB and QTB-PIMD runs of the pair potential, labelled by it)",
         "config": {"workload": "surrogate-20x20x20-P4", "atoms": n ** 3 * 8, "beads": P,
                    "atom_beads_per_step": ab, "T_K": 300.0, "noise": "QTB-PIMD kappa_P",
                    "r_ml_A": 6.0, "network": "96-64-64-1 silu per species"},
@@ -689,6 +689,11 @@ def main():
                          "blocks of max two_nf steps) instead of the streaming FIR")
     ap.add_argument("--blocks", type=int, default=40,
                     help="qtb-vs-pimd: measured blocks of 5000 steps of the convergence sweep")
+    ap.add_argument("--ml-samples", type=int, default=512,
+                    help="surrogate workload: samples per training replica (9 replicas; the "
+                         "QTB-PIMD ones give 4 frames per sample)")
+    ap.add_argument("--ml-steps", type=int, default=3000,
+                    help="surrogate workload: mini-batch Adam steps")
     ap.add_argument("--skin", type=float, default=None,
                     help="Verlet skin (A); default 0.4 for one crystal (fastest measured), "
                          "1.3 for the sweep (hot replicas: measured 0.5-1.6, best 1.3-1.45), "
