@@ -209,3 +209,82 @@ def stationary_moments_cov(M, b, R):
         if R[t] != 0.0:
             S += R[t] * (X0 @ Mt.T + Mt @ X0)
     return S
+
+
+# ------------------------------------------------ many harmonic modes at once
+def ring_mode_moments(omegas, P, kT, hbar, gamma, dt, taps):
+    """Exact stationary energies of the BAOAB / normal-mode scheme for many
+    independent unit-mass harmonic modes (the mass-weighted normal modes of a
+    crystal) at once: the same linear map and FIR-noise covariance sum as
+    ``stationary_moments``, vectorised over modes and ring-polymer normal
+    modes.  A mode with omega = 0 (a uniform translation) carries only its
+    velocity, v_{n+1} = c1 v_n + sigma zeta_n, whose stationary variance is
+    sigma^2 (R0 + 2 sum_tau c1^tau R_tau) / (1 - c1^2); its other ring modes
+    are bounded by the springs.
+
+    Returns arrays over the physical modes: kinetic, bead-averaged potential
+    (omega^2 / 2P sum_k <q_k^2>), spring, E_prim (eq. 5) and the centroid
+    virial energy (as in ``ho_virial_discrete``)."""
+    taps = np.asarray(taps, dtype=np.float64)
+    L = len(taps)
+    R = np.array([np.dot(taps[: L - t], taps[t:]) for t in range(L)])
+    om = np.asarray(omegas, dtype=np.float64)
+    n = len(om)
+    c1 = math.exp(-gamma * dt)
+    sigma = math.sqrt(1.0 - c1 * c1)
+    wP = math.sqrt(P) * kT / hbar
+    wf = 2.0 * wP * np.sin(np.pi * np.arange(P) / P)
+    acc2 = np.repeat(om * om / P, P)                       # [n*P], mode-major
+    wfr = np.tile(wf, n)
+    free = (acc2 == 0.0) & (wfr == 0.0)
+    h = dt / 2.0
+    m = n * P
+    B = np.zeros((m, 2, 2)); B[:, 0, 0] = 1.0; B[:, 1, 1] = 1.0; B[:, 1, 0] = -h * acc2
+    A = np.zeros((m, 2, 2))
+    rot = wfr > 0.0
+    c, s = np.cos(wfr * h), np.sin(wfr * h)
+    A[:, 0, 0] = np.where(rot, c, 1.0)
+    A[:, 0, 1] = np.where(rot, s / np.where(rot, wfr, 1.0), h)
+    A[:, 1, 0] = np.where(rot, -wfr * s, 0.0)
+    A[:, 1, 1] = np.where(rot, c, 1.0)
+    Om = np.zeros((m, 2, 2)); Om[:, 0, 0] = 1.0; Om[:, 1, 1] = c1
+    BA = B @ A
+    M = BA @ Om @ A @ B
+    b = BA @ np.array([0.0, sigma])
+    # a free mode gets a stand-in stable map; its moments are set below
+    M[free] = np.diag([0.5, 0.5])
+    # discrete Lyapunov X = M X M^T + b b^T as a 4x4 linear system per mode
+    K4 = np.einsum("nij,nkl->nikjl", M, M).reshape(m, 4, 4)
+    rhs = np.einsum("ni,nj->nij", b, b).reshape(m, 4)
+    X0 = np.linalg.solve(np.eye(4)[None] - K4, rhs[..., None])[..., 0].reshape(m, 2, 2)
+    S = R[0] * X0
+    Mt = np.broadcast_to(np.eye(2), (m, 2, 2)).copy()
+    for t in range(1, L):
+        Mt = Mt @ M
+        if R[t] != 0.0:
+            XM = X0 @ np.swapaxes(Mt, 1, 2)
+            S += R[t] * (XM + np.swapaxes(XM, 1, 2))
+    q2 = S[:, 0, 0].copy()
+    v2 = S[:, 1, 1].copy()
+    if free.any():
+        v2[free] = sigma * sigma * (R[0] + 2.0 * np.sum(R[1:] * c1 ** np.arange(1, L))) \
+            / (1.0 - c1 * c1)
+        q2[free] = 0.0
+    q2 = q2.reshape(n, P)
+    v2 = v2.reshape(n, P)
+    ke = 0.5 * v2.sum(1)
+    pot = 0.5 * (om * om / P) * q2.sum(1)
+    spring = 0.5 * (q2 * wf[None] ** 2).sum(1)
+    e_vir = 0.5 * v2[:, 0] + 0.5 * (om * om / P) * q2[:, 0] + (om * om / P) * q2[:, 1:].sum(1)
+    return {"kinetic": ke, "potential": pot, "spring": spring,
+            "e_primitive": ke - spring + pot, "e_virial": e_vir}
+
+
+def quantum_heat_capacity(omegas, kT, hbar):
+    """Heat capacity of quantum harmonic modes in units of k_B:
+    sum_m (x/2)^2 / sinh^2(x/2), x = hbar omega_m / kT (a zero mode counts
+    1/2, its kinetic part)."""
+    om = np.asarray(omegas, dtype=np.float64)
+    x = hbar * om[om > 0] / kT
+    # (x/2)^2 / sinh^2(x/2) = x^2 e^-x / (1 - e^-x)^2, without overflow
+    return float(np.sum(x * x * np.exp(-x) / np.expm1(-x) ** 2) + 0.5 * np.sum(om == 0))

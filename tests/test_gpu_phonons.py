@@ -1,0 +1,159 @@
+"""The crystal against its harmonic-phonon closed form (no statistics on the
+reference side).
+
+For a harmonic crystal the integrator's answer is exact and computable: the
+mass-weighted normal modes decouple into unit-mass oscillators, each driven by
+an orthonormal combination of the atoms' independent filtered noises (which
+has the same filter), so the stationary energies are the sums over the modes
+of the exact second moments of the discrete BAOAB / normal-mode map under the
+FIR noise (``closed_forms.ring_mode_moments``).  The modes are those of the
+4x4x4 supercell itself (the force constants are central differences of the
+oracle's forces at the perfect lattice).  What is left between the GPU and
+that sum is the crystal's anharmonicity plus the statistical error: this test
+reports it, with the exact quantum heat capacity of the same modes beside.
+
+Conditions: QTB (P = 1) at 30 K (2Nf = 2048) and 60 K, QTB-PIMD at P = 4
+(gamma = 1/ps, 100 K) and P = 8 at gamma = 20/ps, 73.68 K, where the friction
+is comparable to the ring polymer's internal frequencies and the eq. 5
+primitive energy falls with temperature (a heat capacity of -0.5 k_B per
+degree of freedom, reproduced by the closed form), and QTB at 400 K.  Each
+condition runs beside a twin at 1.05 T with the same start and white-noise
+stream, so their energy difference (the heat capacity) keeps little noise.
+GPU production precision (FP32 forces, BF16x3 FIR).
+
+Bars: bead-averaged potential, primitive and centroid-virial energies
+relative to the static lattice within 3 standard errors plus 2 % of the
+harmonic value (the anharmonic residual, measured at most 0.7 %); the heat
+capacity of each estimator within 3 standard errors plus 0.03 k_B per degree
+of freedom."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1905_02521_amd import qtb, workloads as W
+from tests import phonons as ph
+from tests.gpu_common import crystal
+
+pytestmark = pytest.mark.gpu
+
+N_CELLS = 4
+COND = (  # T (K), beads, gamma (1/fs)
+    (30.0, 1, 1e-3),
+    (60.0, 1, 5e-3),
+    (100.0, 4, 1e-3),
+    (73.68, 8, 2e-2),
+    (400.0, 1, 2e-2),
+)
+FIELDS = (("potential", 2.0), ("e_primitive", 1.0), ("e_virial", 1.0))
+REL_ANH = 0.02
+C_ABS = 0.03
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qtb.lib()
+
+
+def _two_nf(T):
+    return 2048 if T < 50.0 else 512
+
+
+@pytest.fixture(scope="module")
+def harmonic(orc):
+    Phi, e0, sp, _ = ph.force_constants(orc, N_CELLS)
+    om = ph.normal_mode_frequencies(Phi, sp, W.mgo_potential().mass, W.METAL_UNITS["mass_unit"])
+    out = []
+    for T, P, g in COND:
+        out.append([ph.harmonic_energies(orc, om, TT, P, g, 1.0, _two_nf(T))
+                    for TT in (T, 1.05 * T)])
+    return e0, om, out
+
+
+@pytest.fixture(scope="module")
+def measured():
+    reps = []
+    for k, (T, P, g) in enumerate(COND):
+        beads, sp, box = crystal(N_CELLS, P, seed=7 + k)
+        for TT in (T, 1.05 * T):
+            reps.append(qtb.Replica(pos=beads, species=sp, T=TT, gamma=g, dt=1.0,
+                                    noise=1 if P == 1 else 2, box=tuple(box), seed=11,
+                                    stream=k))
+    ctx = qtb.Context(qtb.pair_potential_dict(W.mgo_potential()), reps, dict(W.METAL_UNITS),
+                      prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3, obs_every=8, max_two_nf=2048)
+    for k, (T, P, g) in enumerate(COND):
+        for twin in (0, 1):
+            ctx.build_filter(2 * k + twin, 1 if P == 1 else 2, _two_nf(T))
+    tau = 1.0 / min(g for _, _, g in COND)
+    ctx.step(int(10 * tau))
+    for r in range(len(reps)):
+        ctx.observables(r)
+    blocks = [{f: [] for f, _ in FIELDS} for _ in reps]
+    for _ in range(16):
+        ctx.step(int(4 * tau))
+        for r in range(len(reps)):
+            o = ctx.observables(r)
+            for f, _ in FIELDS:
+                blocks[r][f].append(o[f])
+    ctx.close()
+    return len(sp), [{f: np.array(v) for f, v in b.items()} for b in blocks]
+
+
+def _mean_se(x):
+    return float(np.mean(x)), float(np.std(x, ddof=1) / math.sqrt(len(x)))
+
+
+def test_energies_match_the_harmonic_closed_form(harmonic, measured):
+    e0, om, harm = harmonic
+    N, blocks = measured
+    bad = []
+    for k, (T, P, g) in enumerate(COND):
+        for f, _ in FIELDS:
+            m, se = _mean_se((blocks[2 * k][f] - e0) / N)
+            h = harm[k][0][f] / N
+            res = m - h
+            print(f"T={T} P={P} gamma={g * 1e3}/ps {f}: gpu {m * 1e3:.3f} +- {se * 1e3:.3f} "
+                  f"meV/atom, harmonic {h * 1e3:.3f}, residual {res / h * 100:+.2f} %")
+            if not abs(res) <= 3 * se + REL_ANH * abs(h):
+                bad.append((T, P, g, f, m, se, h))
+    assert not bad, bad
+
+
+def test_heat_capacity_matches_the_harmonic_closed_form(harmonic, measured):
+    e0, om, harm = harmonic
+    N, blocks = measured
+    kB = W.METAL_UNITS["kB"]
+    bad = []
+    for k, (T, P, g) in enumerate(COND):
+        scale = 1.0 / (0.05 * T * kB * 3 * N)
+        cq = ph.quantum_cv(om, 1.025 * T) / (3 * N)
+        for f, mult in FIELDS:
+            d = mult * scale * (blocks[2 * k + 1][f] - blocks[2 * k][f])
+            c, se = _mean_se(d)
+            ch = mult * scale * (harm[k][1][f] - harm[k][0][f])
+            print(f"T={T} P={P} gamma={g * 1e3}/ps C from {f}: gpu {c:+.4f} +- {se:.4f}, "
+                  f"harmonic scheme {ch:+.4f}, quantum harmonic {cq:.4f} (k_B per dof)")
+            if not abs(c - ch) <= 3 * se + C_ABS:
+                bad.append((T, P, g, f, c, se, ch))
+    assert not bad, bad
+
+
+def test_the_primitive_heat_capacity_turns_negative_where_the_closed_form_says(harmonic,
+                                                                               measured):
+    """P = 8 at gamma = 20/ps, 73.68 K: the closed form gives a negative
+    primitive-energy heat capacity and a positive configurational one; the
+    GPU shows both signs, each beyond 5 standard errors."""
+    e0, om, harm = harmonic
+    N, blocks = measured
+    k = 3
+    T = COND[k][0]
+    scale = 1.0 / (0.05 * T * W.METAL_UNITS["kB"] * 3 * N)
+    hp = scale * (harm[k][1]["e_primitive"] - harm[k][0]["e_primitive"])
+    hv = 2 * scale * (harm[k][1]["potential"] - harm[k][0]["potential"])
+    assert hp < -0.2 and hv > 0.1
+    cp, sp_ = _mean_se(scale * (blocks[2 * k + 1]["e_primitive"] - blocks[2 * k]["e_primitive"]))
+    cv, sv = _mean_se(2 * scale * (blocks[2 * k + 1]["potential"] - blocks[2 * k]["potential"]))
+    assert cp < -5 * sp_ and cv > 5 * sv
