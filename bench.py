@@ -529,6 +529,69 @@ def vdos_bench(a):
     print(json.dumps(out))
 
 
+def sweep_heat_capacity(works, inputs, pot, a):
+    """Heat capacity per replica of the batched sweep: every replica beside a
+    twin at T (1 + 0.05) with the same cells, beads, friction, filter length,
+    start and white-noise stream (correlated sampling: the twins differ only
+    in the filter's temperature, so most of the noise cancels in their
+    energy difference), production precision.  Equilibration of 10/gamma of
+    the weakest friction, then a.hc_blocks blocks of 2/gamma each, sampled
+    every 8 steps.  C = (E(T') - E(T)) / (T' - T) per atom in units of 3 k_B,
+    with the standard error of the blocks' paired differences, from three
+    energies: the eq. 5 primitive energy and the centroid-virial energy
+    (both with measured momenta, so both carry the friction tail of the
+    Langevin dynamics; the primitive one with the internal ring-polymer
+    modes' share, which shrinks as T, and with it omega_P, grows), and twice
+    the bead-averaged potential energy (no momenta; equal to the total
+    energy for harmonic modes)."""
+    from paper_1905_02521_amd import qtb, workloads as W
+    reps = []
+    for k, w in enumerate(works):
+        beads, sp, box = inputs[k]
+        for T in (w.T, 1.05 * w.T):
+            reps.append(qtb.Replica(pos=beads, species=sp, T=T, gamma=w.gamma, dt=w.dt,
+                                    noise=w.noise, box=tuple(box), seed=w.seed + 1000,
+                                    stream=w.stream))
+    ctx = qtb.Context(qtb.pair_potential_dict(pot), reps, W.METAL_UNITS, prec=qtb.PREC_FP32,
+                      fir=qtb.FIR_BF16X3, obs_every=8,
+                      max_two_nf=max(max(w.two_nf, 2) for w in works))
+    for k, w in enumerate(works):
+        if w.noise:
+            for twin in (0, 1):
+                ctx.build_filter(2 * k + twin, w.noise, w.two_nf)
+    tau = 1.0 / min(w.gamma * w.dt for w in works)
+    warm, block = int(10 * tau), int(2 * tau)
+    ctx.step(warm)
+    for r in range(len(reps)):
+        ctx.observables(r)
+    fields = (("C_prim", "e_primitive", 1.0), ("C_vir", "e_virial", 1.0),
+              ("C_2V", "potential", 2.0))
+    blocks = [{f: [] for _, f, _ in fields} for _ in reps]
+    for q in range(a.hc_blocks):
+        ctx.step(block)
+        for r in range(len(reps)):
+            o = ctx.observables(r)
+            for _, f, _ in fields:
+                blocks[r][f].append(o[f])
+        print(f"heat capacity: block {q + 1}/{a.hc_blocks} of {block} steps", file=sys.stderr,
+              flush=True)
+    ctx.close()
+    kB = W.METAL_UNITS["kB"]
+    out = []
+    for k, w in enumerate(works):
+        n_at = inputs[k][0].shape[2]
+        scale = 1.0 / (0.05 * w.T * 3 * kB * n_at)
+        e = {"T_K": round(w.T, 2), "beads": w.P, "gamma_per_ps": round(w.gamma * 1e3, 3),
+             "atoms": int(n_at)}
+        for name, f, mult in fields:
+            d = mult * scale * (np.array(blocks[2 * k + 1][f]) - np.array(blocks[2 * k][f]))
+            e[name] = [float(d.mean()), float(d.std(ddof=1) / math.sqrt(len(d)))]
+        out.append(e)
+    return {"twin_dT": "0.05 T", "equilibration_steps": warm, "block_steps": block,
+            "blocks": a.hc_blocks, "units": "3 k_B per atom, [mean, standard error]",
+            "replicas": out}
+
+
 def fir_modes_bench(a):
     """The default workload (MgO 8x8x8 x P = 8, 50 K, kappa_P, 2Nf = 512,
     K = 64, FP32 forces) with each FIR arithmetic: wall time per step over
@@ -689,6 +752,9 @@ def main():
                          "blocks of max two_nf steps) instead of the streaming FIR")
     ap.add_argument("--blocks", type=int, default=40,
                     help="qtb-vs-pimd: measured blocks of 5000 steps of the convergence sweep")
+    ap.add_argument("--hc-blocks", type=int, default=8,
+                    help="batched workloads: blocks of 2/gamma for the heat capacity of every "
+                         "replica (0: skip)")
     ap.add_argument("--ml-samples", type=int, default=512,
                     help="surrogate workload: samples per training replica (9 replicas; the "
                          "QTB-PIMD ones give 4 frames per sample)")
@@ -848,6 +914,10 @@ def main():
             "bytes_per_launch": fir_bytes, "ms_per_launch": fir_ms / max(fir_n, 1)},
         "phases": phases,
     }
+    if batched and a.hc_blocks > 0:
+        ctx.close()
+        ctx = None
+        out["heat_capacity"] = sweep_heat_capacity(works, inputs, pot, a)
     if not a.no_cpu:
         if batched:
             # smallest replica of each friction group, sharing the time budget
@@ -869,7 +939,8 @@ def main():
             cb = cpu_baseline(w, beads, sp, box, pot, a.cpu_seconds)
             cb.pop("_ab"); cb.pop("_t")
             out["cpu_baseline"] = cb
-    ctx.close()
+    if ctx is not None:
+        ctx.close()
     print(json.dumps(out))
 
 
