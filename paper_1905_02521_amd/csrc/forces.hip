@@ -141,7 +141,7 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                                          const PairPos<T, MODE>& pp, int i, int s, int ch,
                                          int ST, bool want_e, bool want_w, double& fx,
                                          double& fy, double& fz, double& e, double& w, int& spi,
-                                         double lscale)
+                                         double lscale, const f4v* ltab)
 {
     using V4 = typename NV<T>::v4;
     const V4 ui = pp.at(i, s);
@@ -160,25 +160,21 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
         pC[b] = q.C;
         pE0[b] = q.E0;
     }
-    // Two species in the FP32 path: a neighbour's parameters are the blend
-    // p0 + s_j (p1 - p0) with s_j in {0, 1}, one FMA each (p0 uniform, the
-    // difference in a VGPR); s_j = 0 gives p0 exactly, s_j = 1 gives p1 to
-    // the rounding of p1 - p0 (one unit in the last place).  Otherwise keep
-    // the parameters of neighbour species 1, 2, ... in VGPRs for the whole
-    // loop (an instruction on gfx950 reads at most one SGPR, VCC included, so
-    // a select of a uniform species-0 value needs its own move).
-    constexpr bool BLEND = FAST && NS == 2;
-    if constexpr (BLEND) {
-        pArho[1] -= pArho[0];
-        pirho[1] -= pirho[0];
-        pC6[1] -= pC6[0];
-        pkqq[1] -= pkqq[0];
-        pF0[1] -= pF0[0];
-    }
+    // FP32 path with several species: a neighbour's parameters come from the
+    // block's LDS copy of the centre species' row (two 16-byte reads per
+    // pair, indexed by the neighbour's species: no per-species registers and
+    // no selects).  Otherwise keep the parameters of neighbour species 1,
+    // 2, ... in VGPRs for the whole loop (an instruction on gfx950 reads at
+    // most one SGPR, VCC included, so a select of a uniform species-0 value
+    // needs its own move).
+    constexpr bool LTAB = FAST && NS >= 2;
+    const f4v* const lrow = LTAB ? ltab + 2 * row : nullptr;
+    if constexpr (!LTAB) {
 #pragma unroll
-    for (int b = 1; b < NS; ++b) {
-        asm volatile("" : "+v"(pArho[b]), "+v"(pirho[b]), "+v"(pC6[b]), "+v"(pkqq[b]),
-                     "+v"(pF0[b]));
+        for (int b = 1; b < NS; ++b) {
+            asm volatile("" : "+v"(pArho[b]), "+v"(pirho[b]), "+v"(pC6[b]), "+v"(pkqq[b]),
+                         "+v"(pF0[b]));
+        }
     }
     T ex[DEG + 1], ph[DEG + 1];
 #pragma unroll
@@ -217,13 +213,19 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
         if (r2 < rc2) {
             const int spj = vbits(U0);
             T Arho = pArho[0], irho = pirho[0], C6 = pC6[0], kqq = pkqq[0], F0 = pF0[0];
-            if constexpr (BLEND) {
-                const T sj = (T)spj;
-                Arho = fmaf(sj, pArho[1], Arho);
-                irho = fmaf(sj, pirho[1], irho);
-                C6 = fmaf(sj, pC6[1], C6);
-                kqq = fmaf(sj, pkqq[1], kqq);
-                F0 = fmaf(sj, pF0[1], F0);
+            f4v q1 = {0.0f, 0.0f, 0.0f, 0.0f};
+            if constexpr (LTAB) {
+                const f4v q0 = lrow[2 * spj];
+                Arho = q0.x;
+                irho = q0.y;
+                C6 = q0.z;
+                kqq = q0.w;
+                if (want_e) {
+                    q1 = lrow[2 * spj + 1];
+                    F0 = q1.x;
+                } else {
+                    F0 = ((const float*)(lrow + 2 * spj + 1))[0];
+                }
             } else {
 #pragma unroll
                 for (int b = 1; b < NS; ++b) {
@@ -235,7 +237,7 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                     F0 = m ? pF0[b] : F0;
                 }
             }
-            T rinv, r, e1, ec = (T)0, e2 = (T)0, Fc;
+            T rinv, r, e1, ec = (T)0, e2 = (T)0, fr;
             if constexpr (FAST) {
                 rinv = __builtin_amdgcn_rsqf(r2);
                 r = r2 * rinv;
@@ -244,8 +246,14 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                 T ps = ph_top;
 #pragma unroll
                 for (int k = DEG - 1; k >= 0; --k) ps = fmaf(ps, sp, ph[k]);
+                // F / r = (Arho e1 + F0 + kqq / r^2) / r + kqq psi - C6 / r^8:
+                // the Coulomb shape over r^3 is 1 / r^3 + psi(s)
                 const T rinv2 = rinv * rinv;
-                Fc = fmaf(r * r2, ps, 1.0f) * rinv2;  // erfc + Gaussian term, over r^2
+                const T rinv4 = rinv2 * rinv2;
+                T a = fmaf(Arho, e1, F0);
+                a = fmaf(kqq, rinv2, a);
+                const T c = fmaf(-C6, rinv4 * rinv4, kqq * ps);
+                fr = fmaf(a, rinv, c);
                 if (want_e) {
                     e2 = __builtin_amdgcn_exp2f(-r2 * a2l);
                     const T sx = fmaf(r, s_mul, -1.0f);
@@ -261,12 +269,11 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                 const T x = alpha * r;
                 e2 = t_exp(-x * x);
                 ec = t_erfc(x);
-                Fc = ec * (rinv * rinv) + g * e2 * rinv;
+                const T Fc = ec * (rinv * rinv) + g * e2 * rinv;
+                const T rinv2 = rinv * rinv;
+                const T rinv6 = rinv2 * rinv2 * rinv2;
+                fr = (Arho * e1 - C6 * rinv6 * rinv + kqq * Fc + F0) * rinv;
             }
-            const T rinv2 = rinv * rinv;
-            const T rinv6 = rinv2 * rinv2 * rinv2;
-            const T F = Arho * e1 - C6 * rinv6 * rinv + kqq * Fc + F0;
-            const T fr = F * rinv;
             if constexpr (sizeof(T) == 4) {
                 // FP64 sums of the exact products (fr dx in FP64): one
                 // conversion of fr shared by the three components
@@ -280,17 +287,25 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                 fz += fr * dz;
             }
             if (want_e) {
+                const T rinv2 = rinv * rinv;
+                const T rinv6 = rinv2 * rinv2 * rinv2;
                 T A = pA[0], C = pC[0], E0c = pE0[0];
+                if constexpr (LTAB) {
+                    A = q1.y;
+                    C = q1.z;
+                    E0c = q1.w;
+                } else {
 #pragma unroll
-                for (int b = 1; b < NS; ++b) {
-                    const bool m = spj == b;
-                    A = m ? pA[b] : A;
-                    C = m ? pC[b] : C;
-                    E0c = m ? pE0[b] : E0c;
+                    for (int b = 1; b < NS; ++b) {
+                        const bool m = spj == b;
+                        A = m ? pA[b] : A;
+                        C = m ? pC[b] : C;
+                        E0c = m ? pE0[b] : E0c;
+                    }
                 }
                 e += (double)(A * e1 - C * rinv6 + kqq * ec * rinv - F0 * r + E0c);
             }
-            if (want_w) w += (double)(F * r);
+            if (want_w) w += (double)(fr * r2);
         }
     };
 
@@ -355,6 +370,21 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
         };
         range(ncore, 0, 1);
         range(cnt - ncore, maxnb - 1, -1);
+    }
+}
+
+// The block's LDS copy of the pair parameters for the FP32 path with
+// several species (see pair_sum): per species pair (Arho, irho2, C6, kqq)
+// and (F0, A, C, E0).  The caller synchronises the block afterwards.
+template <typename T, int NS, bool FAST>
+__device__ __forceinline__ void fill_ltab(const PairTable<T>& tab, f4v* ltab)
+{
+    if constexpr (FAST && NS >= 2) {
+        for (int t = threadIdx.x; t < kPairs; t += blockDim.x) {
+            const PairParam<T>& q = tab.p[t];
+            ltab[2 * t] = f4v{(float)q.Arho, (float)q.irho2, (float)q.C6, (float)q.kqq};
+            ltab[2 * t + 1] = f4v{(float)q.F0, (float)q.A, (float)q.C, (float)q.E0};
+        }
     }
 }
 
@@ -532,6 +562,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (EM == 2 ? 5 : 7)))) k_f
     const int N = R.N, P = R.P;
     const bool active = i < N;
     const int s = be.group * G + bl;
+    __shared__ f4v ltab[2 * kPairs];
+    if constexpr (FAST && NS >= 2) {
+        fill_ltab<T, NS, FAST>(tab, ltab);
+        __syncthreads();
+    }
     // energies and the pair virial only in the instantiation that samples or
     // evaluates (EM = 2: flags & (kSample | kEvaluate)), the pair virial alone
     // for a barostat's step (EM = 1: kPressure): the plain force pass keeps
@@ -587,13 +622,13 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (EM == 2 ? 5 : 7)))) k_f
             const PairPos<T, kPosRef> pp{nullptr, nullptr, (gptr<double>)cen, N, P,
                                          (gptr<double>)R.pos, (gptr<int32_t>)R.species};
             pair_sum<T, NS, FAST, DEG, kPosRef, G>(R, tab, pp, i, s, ch, NCH * W, want_e, want_w,
-                                                fx, fy, fz, e, vir, spi, 1.0);
+                                                fx, fy, fz, e, vir, spi, 1.0, ltab);
         } else {
             // u is atom-major [N][P]: the G beads of a neighbour share cache lines
             const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[si.p] + 0, nullptr, nullptr, N, P,
                                             nullptr, nullptr};
             pair_sum<T, NS, FAST, DEG, kPosDirect, G>(R, tab, pp, i, s, ch, NCH * W, want_e,
-                                                   want_w, fx, fy, fz, e, vir, spi, lscale);
+                                                   want_w, fx, fy, fz, e, vir, spi, lscale, ltab);
         }
     }
     reduce_atom<G>(fx, fy, fz, e, vir, want_e, want_w, W, wave, wsub, lane, part);
@@ -657,6 +692,8 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
     const int s = bl;  // G = P: the wavefront holds every bead
     constexpr bool want_e = WE;  // = flags & kSample (the launcher's choice)
     double* const vrec = recorder_row(R, flags);
+    __shared__ f4v ltab[2 * kPairs];
+    fill_ltab<T, NS, FAST>(tab, ltab);
     {
         const int apb = 4 / W;
         for (int t = threadIdx.x; t < G * G; t += blockDim.x) Cs[t] = R.nm[t];
@@ -686,13 +723,13 @@ __global__ void __launch_bounds__(256) k_step_pair(const RepDev* __restrict__ re
             const PairPos<T, kPosRecon> pp{(gptr<V4>)R.ub[pin] + 0, (gptr<double>)rin,
                                            (gptr<double>)cin, N, P, nullptr, nullptr};
             pair_sum<T, NS, FAST, DEG, kPosRecon, G>(R, tab, pp, i, s, ch, NCH * W, want_e, want_e,
-                                                  fx, fy, fz, e, vir, spi, 1.0);
+                                                  fx, fy, fz, e, vir, spi, 1.0, ltab);
         } else {
             // (no barostat with the one-kernel step)
             const PairPos<T, kPosDirect> pp{(gptr<V4>)R.ub[pin] + 0, nullptr, nullptr, N, P,
                                             nullptr, nullptr};
             pair_sum<T, NS, FAST, DEG, kPosDirect, G>(R, tab, pp, i, s, ch, NCH * W, want_e,
-                                                   want_e, fx, fy, fz, e, vir, spi, R.npt_S);
+                                                   want_e, fx, fy, fz, e, vir, spi, R.npt_S, ltab);
         }
     }
     reduce_atom<G>(fx, fy, fz, e, vir, want_e, want_e, W, wave, wsub, lane, part);
