@@ -752,6 +752,9 @@ def main():
                          "blocks of max two_nf steps) instead of the streaming FIR")
     ap.add_argument("--blocks", type=int, default=40,
                     help="qtb-vs-pimd: measured blocks of 5000 steps of the convergence sweep")
+    ap.add_argument("--decomposition", default=None,
+                    help="pin the pair-force decomposition instead of autotuning it: "
+                         "waves per atom (1, 2 or 4), optionally ',half' for half bead groups")
     ap.add_argument("--hc-blocks", type=int, default=8,
                     help="batched workloads: blocks of 2/gamma for the heat capacity of every "
                          "replica (0: skip)")
@@ -816,6 +819,9 @@ def main():
     for k, w in enumerate(works):
         if w.noise:
             ctx.build_filter(k, w.noise, w.two_nf)
+    if a.decomposition:
+        wpa, _, half = a.decomposition.partition(",")
+        ctx.set_decomposition(int(wpa), half.strip() == "half")
     w = works[0]
     beads, sp, box = inputs[0]
     ab_per_step = sum(b.shape[0] * b.shape[2] for b, _, _ in inputs)
@@ -848,6 +854,7 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / a.steps
     value = ab_per_step * a.steps / (t1 - t0)
+    wpa, half = ctx.decomposition()
 
     # per-kernel durations from HIP events on the library's stream
     ctx.profile(True)
@@ -896,7 +903,10 @@ def main():
                    "untimed_steps": untimed,
                    "noise_blocks_in_timed_region": -(-a.steps // a.K),
                    "forces": "fp32" if prec == qtb.PREC_FP32 else "fp64", "state": "fp64",
-                   "r_cut_A": pot.r_cut, "skin_A": pot.skin, "parallelism": "1 GPU"},
+                   "r_cut_A": pot.r_cut, "skin_A": pot.skin, "parallelism": "1 GPU",
+                   "force_decomposition": {"waves_per_atom": wpa, "half_bead_groups": half,
+                                           "chosen_by": "pinned" if a.decomposition
+                                           else "autotuner"}},
         "roofline": {"kernel": "pair forces", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
