@@ -447,15 +447,32 @@ qtb_status qtb_set_barostat_state(qtb_ctx *ctx, int32_t replica, const double *h
  * half of that (half_groups != 0; no effect where G = 1).  Every choice
  * computes the same forces; the order of the sums, and so the last bits,
  * depend on it.  The first qtb_step of a context times all choices on the
- * actual replicas and keeps the fastest (unless QTB_OPT_NO_AUTOTUNE);
- * qtb_set_decomposition pins one instead (for bit-reproducible runs across
- * contexts) and skips that autotuning.  QTB_E_INVALID for other values, a
- * potential other than the pair potential, with the surrogate attached
- * anything but (1, 0), and half groups with the one-kernel step.  Both
- * synchronise.
+ * actual replicas and keeps the fastest (unless QTB_OPT_NO_AUTOTUNE),
+ * separately for each force launch: a context whose replicas have different
+ * bead-group widths G runs one launch per width, and each keeps its own
+ * choice.  qtb_set_decomposition pins one choice for every launch instead
+ * (for bit-reproducible runs across contexts) and skips that autotuning;
+ * qtb_get_decomposition reports the choice of the launch with the most
+ * workgroups.  QTB_E_INVALID for other values, a potential other than the
+ * pair potential, with the surrogate attached anything but (1, 0), and half
+ * groups with the one-kernel step.  Both synchronise.
  */
 qtb_status qtb_set_decomposition(qtb_ctx *ctx, int32_t waves_per_atom, int32_t half_groups);
 qtb_status qtb_get_decomposition(qtb_ctx *ctx, int32_t *waves_per_atom, int32_t *half_groups);
+/*
+ * The same for one force launch: group_width is the launch's whole bead-group
+ * width G (1, 2, 4 or 8; the widest power of two up to 8 dividing the
+ * replicas' P).  qtb_set_group_decomposition pins that launch's choice, keeps
+ * the others' and skips the autotuning (with qtb_get_group_decomposition of
+ * every width, an autotuned mix can be pinned again in another context).
+ * QTB_E_INVALID where no launch has that width, for the values above, with
+ * the surrogate attached or with the one-kernel step.  The setter
+ * synchronises.
+ */
+qtb_status qtb_set_group_decomposition(qtb_ctx *ctx, int32_t group_width,
+                                       int32_t waves_per_atom, int32_t half_groups);
+qtb_status qtb_get_group_decomposition(qtb_ctx *ctx, int32_t group_width,
+                                       int32_t *waves_per_atom, int32_t *half_groups);
 
 /*
  * Diagnostics: while enabled, qtb_step records a HIP event pair around every

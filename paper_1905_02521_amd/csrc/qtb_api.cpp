@@ -76,6 +76,8 @@ struct Layout {
     size_t max_force_blocks = 1;
     std::vector<std::pair<int, std::pair<int, int>>> upd_groups;    // P -> [b0, b1)
     std::vector<std::pair<int, std::pair<int, int>>> force_groups;  // G -> [b0, b1)
+    std::vector<int> force_group_W;   // waves per atom of each force group's launch
+    std::vector<int> force_group_t;   // the decomposition table each group came from
     std::vector<int> obs_b0, obs_nb;
     std::vector<FirTile> tilev;
 };
@@ -287,9 +289,23 @@ void plan(const qtb_potential* pot, const qtb_replica* reps, int n_rep, const qt
         }
         L.max_force_blocks = std::max(L.max_force_blocks, F.size());
     }
+    {   // a table that mixes decompositions per group takes each group's largest
+        size_t mix = 0;
+        for (size_t k = 0; k < L.force_groups_w[0].size(); ++k) {
+            int most = 0;
+            for (int t = 0; t < 6; ++t) {
+                const auto& g = L.force_groups_w[t][k].second;
+                most = std::max(most, g.second - g.first);
+            }
+            mix += (size_t)most;
+        }
+        L.max_force_blocks = std::max(L.max_force_blocks, mix);
+    }
     const int wdef = 2 * (kWavesPerAtomDefault == 1 ? 0 : (kWavesPerAtomDefault == 2 ? 1 : 2));
     L.force = L.force_w[wdef];
     L.force_groups = L.force_groups_w[wdef];
+    L.force_group_W.assign(L.force_groups.size(), kWavesPerAtomDefault);
+    L.force_group_t.assign(L.force_groups.size(), wdef);
     L.obs_b0 = L.obs_b0_w[wdef];
     L.obs_nb = L.obs_nb_w[wdef];
     L.tilev.assign(cols / kDofTile, FirTile{0, 2, 0, 0});
@@ -953,20 +969,23 @@ bool list_kernel(const qtb_ctx* c)
 
 // inline_rebuild: the force kernel rebuilds flagged lists itself (no list
 // kernel launched before it).
-void launch_plain_forces(qtb_ctx* c, int32_t flags, bool inline_rebuild = false)
+// Force group k of the current table (only = k), or all of them (only < 0).
+void launch_plain_forces(qtb_ctx* c, int32_t flags, bool inline_rebuild = false, int only = -1)
 {
     const Layout& L = c->L;
     const RepDev* dreps = c->at<RepDev>(L.reps);
     const BlockEntry* fb = c->at<BlockEntry>(L.blk_force);
     double* part = c->at<double>(L.partials);
     const int clear = (flags & kCompare) ? 0 : (inline_rebuild ? 2 : 1);
-    for (auto& g : L.force_groups) {
+    for (size_t k = 0; k < L.force_groups.size(); ++k) {
+        if (only >= 0 && (size_t)only != k) continue;
+        const auto& g = L.force_groups[k];
         const int b0 = g.second.first, nb = g.second.second - g.second.first;
         if (nb <= 0) continue;
         if (c->pair) {
             const void* tab = c->fp64 ? (const void*)&c->tabd : (const void*)&c->tabf;
-            launch_forces_pair(c->st, c->fp64, g.first, c->W, dreps, fb + b0, nb, tab, flags,
-                               part + (size_t)b0 * kNobs, clear, c->n_rep,
+            launch_forces_pair(c->st, c->fp64, g.first, L.force_group_W[k], dreps, fb + b0, nb,
+                               tab, flags, part + (size_t)b0 * kNobs, clear, c->n_rep,
                                c->at<int32_t>(L.status), step_ref(c));
         } else {
             launch_forces_onsite(c->st, c->fp64, c->kind, dreps, fb + b0, nb, flags,
@@ -1359,6 +1378,8 @@ qtb_status select_force_table(qtb_ctx* c, int W, int half)
     const int t = 2 * (W == 1 ? 0 : (W == 2 ? 1 : 2)) + (half ? 1 : 0);
     L.force = L.force_w[t];
     L.force_groups = L.force_groups_w[t];
+    L.force_group_W.assign(L.force_groups.size(), W);
+    L.force_group_t.assign(L.force_groups.size(), t);
     L.obs_b0 = L.obs_b0_w[t];
     L.obs_nb = L.obs_nb_w[t];
     c->W = W;
@@ -1375,11 +1396,65 @@ qtb_status select_force_table(qtb_ctx* c, int W, int half)
     return QTB_OK;
 }
 
+// A table whose force group k comes from decomposition table tsel[k] (index
+// 2 wi + gi as above): each bead-group width keeps its own waves per atom
+// and bead-group split.  c->W and c->half_groups report the choice of the
+// launch with the most workgroups.
+qtb_status select_force_mix(qtb_ctx* c, const std::vector<int>& tsel)
+{
+    Layout& L = c->L;
+    std::vector<BlockEntry> F;
+    std::vector<std::pair<int, std::pair<int, int>>> FG;
+    std::vector<int> gw, gt;
+    std::vector<int> ob0(c->n_rep, 0), onb(c->n_rep, 0);
+    for (size_t k = 0; k < tsel.size(); ++k) {
+        const int t = tsel[k];
+        const auto& src = L.force_groups_w[t][k];
+        const int s0 = src.second.first, s1 = src.second.second, b0 = (int)F.size();
+        F.insert(F.end(), L.force_w[t].begin() + s0, L.force_w[t].begin() + s1);
+        FG.push_back({src.first, {b0, (int)F.size()}});
+        gw.push_back(1 << (t / 2));
+        gt.push_back(t);
+        for (int r = 0; r < c->n_rep; ++r) {
+            const int o = L.obs_b0_w[t][r];
+            if (L.obs_nb_w[t][r] > 0 && o >= s0 && o < s1) {
+                ob0[r] = b0 + (o - s0);
+                onb[r] = L.obs_nb_w[t][r];
+            }
+        }
+    }
+    if (F.size() > L.max_force_blocks) return fail(c, QTB_E_STATE, "force table size");
+    L.force = F;
+    L.force_groups = FG;
+    L.force_group_W = gw;
+    L.force_group_t = gt;
+    L.obs_b0 = ob0;
+    L.obs_nb = onb;
+    size_t kmax = 0;  // the launch with the most workgroups
+    for (size_t k = 1; k < FG.size(); ++k)
+        if (FG[k].second.second - FG[k].second.first >
+            FG[kmax].second.second - FG[kmax].second.first)
+            kmax = k;
+    c->W = gw.empty() ? 1 : gw[kmax];
+    c->half_groups = !gt.empty() && (gt[kmax] % 2) == 1;
+    for (int r = 0; r < c->n_rep; ++r) {
+        c->rd[r].obs_block0 = L.obs_b0[r];
+        c->rd[r].obs_nblocks = L.obs_nb[r];
+    }
+    QTB_HIP(c, hipMemcpyAsync(c->at<void>(L.blk_force), L.force.data(),
+                              sizeof(BlockEntry) * L.force.size(), hipMemcpyHostToDevice, c->st));
+    qtb_status s = upload_tables(c);
+    if (s) return s;
+    drop_graph(c);
+    return QTB_OK;
+}
+
 // Autotuner: time the pair-force kernel of the actual workload for every
 // decomposition, waves per atom W in {1, 2, 4} times beads per wavefront G
 // (the widest group that divides P, or half of it), forces only with no kick
 // (the state is unchanged), and keep the fastest: one warm-up launch, then
-// the best of five (all replica groups).  The one-kernel step keeps whole ring polymers per
+// the best of five, separately for each launch (one per bead-group width, all
+// replicas of that width).  The one-kernel step keeps whole ring polymers per
 // wavefront.
 qtb_status autotune(qtb_ctx* c)
 {
@@ -1392,32 +1467,37 @@ qtb_status autotune(qtb_ctx* c)
     hipEvent_t a = nullptr, b = nullptr;
     QTB_HIP(c, hipEventCreate(&a));
     QTB_HIP(c, hipEventCreate(&b));
-    float best = 1e30f;
-    int bestW = c->W, bestH = c->half_groups ? 1 : 0;
+    // each force group (one launch per bead-group width) is timed on its own
+    // and keeps its own fastest decomposition
+    const size_t ng = c->L.force_groups.size();
+    std::vector<float> best(ng, 1e30f);
+    std::vector<int> bestT(ng, c->L.force_group_t.empty() ? 0 : c->L.force_group_t[0]);
     for (int half = 0; half <= (can_half ? 1 : 0); ++half)
         for (int W : {1, 2, 4}) {
             qtb_status s = select_force_table(c, W, half);
             if (s) return s;
-            float tmin = 1e30f;
-            launch_plain_forces(c, 0);  // warm-up (caches, first-touch)
-            for (int rep = 0; rep < 5; ++rep) {
-                QTB_HIP(c, hipEventRecord(a, c->st));
-                launch_plain_forces(c, 0);
-                QTB_HIP(c, hipEventRecord(b, c->st));
-                QTB_HIP(c, hipEventSynchronize(b));
-                float t = 0.0f;
-                QTB_HIP(c, hipEventElapsedTime(&t, a, b));
-                tmin = std::min(tmin, t);
-            }
-            if (tmin < best) {
-                best = tmin;
-                bestW = W;
-                bestH = half;
+            for (size_t k = 0; k < ng; ++k) {
+                float tmin = 1e30f;
+                launch_plain_forces(c, 0, false, (int)k);  // warm-up (caches, first-touch)
+                for (int rep = 0; rep < 5; ++rep) {
+                    QTB_HIP(c, hipEventRecord(a, c->st));
+                    launch_plain_forces(c, 0, false, (int)k);
+                    QTB_HIP(c, hipEventRecord(b, c->st));
+                    QTB_HIP(c, hipEventSynchronize(b));
+                    float t = 0.0f;
+                    QTB_HIP(c, hipEventElapsedTime(&t, a, b));
+                    tmin = std::min(tmin, t);
+                }
+                if (tmin < best[k]) {
+                    best[k] = tmin;
+                    bestT[k] = c->L.force_group_t[k];
+                }
             }
         }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    qtb_status s = select_force_table(c, bestW, bestH);
+    qtb_status s = ng == 1 ? select_force_table(c, 1 << (bestT[0] / 2), bestT[0] % 2)
+                           : select_force_mix(c, bestT);
     if (s) return s;
     QTB_HIP(c, hipStreamSynchronize(c->st));
     return QTB_OK;
@@ -2090,6 +2170,51 @@ qtb_status qtb_get_decomposition(qtb_ctx* c, int32_t* waves_per_atom, int32_t* h
     if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
     if (waves_per_atom) *waves_per_atom = c->W;
     if (half_groups) *half_groups = c->half_groups ? 1 : 0;
+    return QTB_OK;
+}
+
+namespace {
+// Index of the force launch of bead-group width G (its whole-group width),
+// or -1.
+int force_group_of(const qtb_ctx* c, int32_t G)
+{
+    const auto& FG = c->L.force_groups_w[0];
+    for (size_t k = 0; k < FG.size(); ++k)
+        if (FG[k].first == G) return (int)k;
+    return -1;
+}
+}  // namespace
+
+qtb_status qtb_set_group_decomposition(qtb_ctx* c, int32_t group_width, int32_t waves_per_atom,
+                                       int32_t half_groups)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (!c->pair || c->ml) return fail(c, QTB_E_INVALID, "group decomposition: pair potential, no surrogate");
+    if (c->opt.flags & QTB_OPT_FUSE)
+        return fail(c, QTB_E_INVALID, "the one-kernel step takes one decomposition");
+    if (waves_per_atom != 1 && waves_per_atom != 2 && waves_per_atom != 4)
+        return fail(c, QTB_E_INVALID, "waves_per_atom must be 1, 2 or 4");
+    const int k = force_group_of(c, group_width);
+    if (k < 0) return fail(c, QTB_E_INVALID, "no force launch of that bead-group width");
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    std::vector<int> tsel = c->L.force_group_t;
+    tsel[k] = 2 * (waves_per_atom == 1 ? 0 : (waves_per_atom == 2 ? 1 : 2)) + (half_groups ? 1 : 0);
+    if (qtb_status s = select_force_mix(c, tsel)) return s;
+    c->tuned = true;  // pinned: no autotuning at the next step
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    return read_status(c);
+}
+
+qtb_status qtb_get_group_decomposition(qtb_ctx* c, int32_t group_width, int32_t* waves_per_atom,
+                                       int32_t* half_groups)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (!c->pair) return fail(c, QTB_E_INVALID, "group decomposition: pair potential only");
+    const int k = force_group_of(c, group_width);
+    if (k < 0) return fail(c, QTB_E_INVALID, "no force launch of that bead-group width");
+    const int t = c->L.force_group_t[k];
+    if (waves_per_atom) *waves_per_atom = 1 << (t / 2);
+    if (half_groups) *half_groups = t % 2;
     return QTB_OK;
 }
 

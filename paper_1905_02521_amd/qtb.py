@@ -93,6 +93,7 @@ EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
            "qtb_vdos_detach", "qtb_barostat", "qtb_barostat_piston", "qtb_get_box",
            "qtb_get_barostat_state", "qtb_set_barostat_state", "qtb_filter_taps",
            "qtb_set_decomposition", "qtb_get_decomposition",
+           "qtb_set_group_decomposition", "qtb_get_group_decomposition",
            "qtb_last_error", "qtb_destroy", "qtb_version",
            "qtb_ml_workspace_bytes", "qtb_ml_create", "qtb_ml_init_params", "qtb_ml_set_params",
            "qtb_ml_get_params", "qtb_ml_attach", "qtb_ml_evaluate", "qtb_ml_fit_norm",
@@ -171,6 +172,11 @@ def lib():
     L.qtb_set_barostat_state.argtypes = [vp, ctypes.c_int32, _PD]
     L.qtb_set_decomposition.restype = ctypes.c_int
     L.qtb_set_decomposition.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.qtb_set_group_decomposition.restype = ctypes.c_int
+    L.qtb_set_group_decomposition.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.qtb_get_group_decomposition.restype = ctypes.c_int
+    L.qtb_get_group_decomposition.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32)]
     L.qtb_get_decomposition.restype = ctypes.c_int
     L.qtb_get_decomposition.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -500,6 +506,17 @@ class Context:
     def decomposition(self):
         w, h = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().qtb_get_decomposition(self.ctx, ctypes.byref(w), ctypes.byref(h)), self.ctx)
+        return w.value, bool(h.value)
+
+    def set_group_decomposition(self, group_width, waves_per_atom, half_groups=False):
+        """Pin the decomposition of the force launch of one bead-group width."""
+        _check(lib().qtb_set_group_decomposition(self.ctx, int(group_width), int(waves_per_atom),
+                                                 1 if half_groups else 0), self.ctx)
+
+    def group_decomposition(self, group_width):
+        w, h = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qtb_get_group_decomposition(self.ctx, int(group_width), ctypes.byref(w),
+                                                 ctypes.byref(h)), self.ctx)
         return w.value, bool(h.value)
 
     def box(self, replica=0):

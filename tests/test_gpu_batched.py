@@ -101,3 +101,34 @@ def test_batched_observables_per_replica():
         assert np.isfinite(o["e_primitive"])
         # kinetic temperature of the beads is of the order of T after 64 fs
         assert 0.0 < o["t_kinetic"] < 20 * r.T
+
+
+def test_mixed_decompositions_per_bead_group():
+    """One launch per bead-group width, each with its own decomposition
+    (what the autotuner may choose): the FP64 trajectories and the
+    observables of every replica equal those of one uniform decomposition
+    to the rounding of the sums' order, and the pinned mix reads back."""
+    specs = [(2, 1, 300.0, 1e-3, 1, 128, 0), (3, 4, 50.0, 5e-3, 2, 256, 1),
+             (2, 8, 80.0, 2e-2, 2, 128, 2), (2, 2, 20.0, 5e-4, 2, 256, 4)]
+    reps = make_reps(specs)
+    mix = ctx_for(reps, qtb.PREC_FP64, qtb.FIR_FP64, obs_every=4)
+    for G, W_, half in ((1, 4, False), (2, 2, True), (4, 1, True), (8, 2, False)):
+        mix.set_group_decomposition(G, W_, half)
+    assert [mix.group_decomposition(G) for G in (1, 2, 4, 8)] == \
+        [(4, False), (2, True), (1, True), (2, False)]
+    uni = ctx_for(reps, qtb.PREC_FP64, qtb.FIR_FP64, obs_every=4)
+    uni.set_decomposition(1, False)
+    mix.step(40)
+    uni.step(40)
+    for k in range(len(reps)):
+        rm, vm, _ = mix.get_state(k)
+        ru, vu, _ = uni.get_state(k)
+        assert np.max(np.abs(rm - ru)) < 1e-10, k
+        om, ou = mix.observables(k), uni.observables(k)
+        assert om["n_samples"] == ou["n_samples"] == 10
+        for f in ("kinetic", "potential", "e_primitive", "e_virial"):
+            assert abs(om[f] - ou[f]) <= 1e-9 * max(1.0, abs(ou[f])), (k, f)
+    with pytest.raises(qtb.QtbError):
+        mix.set_group_decomposition(3, 1, False)
+    mix.close()
+    uni.close()
