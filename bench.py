@@ -752,6 +752,11 @@ def main():
                          "blocks of max two_nf steps) instead of the streaming FIR")
     ap.add_argument("--blocks", type=int, default=40,
                     help="qtb-vs-pimd: measured blocks of 5000 steps of the convergence sweep")
+    ap.add_argument("--skin-full-T", type=float, default=600.0,
+                    help="batched workloads: replicas at or above this temperature keep the full "
+                         "skin, colder ones a thinner one, skin sqrt(T / this) (0: one skin)")
+    ap.add_argument("--skin-min", type=float, default=0.8,
+                    help="batched workloads: the thinnest per-replica skin (A)")
     ap.add_argument("--decomposition", default=None,
                     help="pin the pair-force decomposition instead of autotuning it: "
                          "waves per atom (1, 2 or 4), optionally ',half' for half bead groups")
@@ -822,6 +827,14 @@ def main():
     if a.decomposition:
         wpa, _, half = a.decomposition.partition(",")
         ctx.set_decomposition(int(wpa), half.strip() == "half")
+    skins = None
+    if batched and a.skin_full_T > 0:
+        # per-replica list skin: the potential's at and above skin_full_T,
+        # thinner for colder replicas (their atoms move less between rebuilds)
+        skins = [max(min(a.skin, a.skin_min), min(a.skin, a.skin * math.sqrt(x.T / a.skin_full_T)))
+                 for x in works]
+        for k, sk in enumerate(skins):
+            ctx.set_replica_skin(k, sk)
     w = works[0]
     beads, sp, box = inputs[0]
     ab_per_step = sum(b.shape[0] * b.shape[2] for b, _, _ in inputs)
@@ -904,6 +917,10 @@ def main():
                    "noise_blocks_in_timed_region": -(-a.steps // a.K),
                    "forces": "fp32" if prec == qtb.PREC_FP32 else "fp64", "state": "fp64",
                    "r_cut_A": pot.r_cut, "skin_A": pot.skin, "parallelism": "1 GPU",
+                   "replica_skins_A": None if skins is None else
+                   {"rule": f"min(skin, skin sqrt(T / {a.skin_full_T:g} K)), at least "
+                            f"{min(a.skin, a.skin_min):g} A",
+                    "min": round(min(skins), 3), "max": round(max(skins), 3)},
                    "force_decomposition": {"waves_per_atom": wpa, "half_bead_groups": half,
                                            "chosen_by": "pinned" if a.decomposition
                                            else "autotuner"}},

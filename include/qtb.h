@@ -441,6 +441,20 @@ qtb_status qtb_get_barostat_state(qtb_ctx *ctx, int32_t replica, double *h_state
 qtb_status qtb_set_barostat_state(qtb_ctx *ctx, int32_t replica, const double *h_state);
 
 /*
+ * Neighbour-list skin of one replica (replica = -1: every replica), pair
+ * potential: 0 <= skin <= the potential's skin (which sizes the lists).  A
+ * replica's list holds the pairs within r_cut + skin + the two atoms' bead
+ * spreads and is rebuilt when an atom has moved more than skin / 2 from the
+ * list's reference: a thin skin lists fewer pairs, a thick one rebuilds less
+ * often (a cold replica moves little, a hot one much).  The forces are the
+ * same (the order of the sums, and so the last bits, may differ).  The lists
+ * are rebuilt and the forces recomputed at once; the state and step are
+ * unchanged.  QTB_E_INVALID for a skin outside that range, other
+ * potentials, or contexts with surrogate buffers.  Synchronises.
+ */
+qtb_status qtb_set_replica_skin(qtb_ctx *ctx, int32_t replica, double skin);
+
+/*
  * Decomposition of the pair-force kernel (pair potential): waves_per_atom
  * wavefronts share one atom's neighbour list (1, 2 or 4), and each wavefront
  * holds G beads of it, G the widest power of two up to 8 that divides P, or

@@ -2148,6 +2148,30 @@ qtb_status qtb_get_box(qtb_ctx* c, int32_t replica, double* h_box)
     return read_status(c);
 }
 
+qtb_status qtb_set_replica_skin(qtb_ctx* c, int32_t replica, double skin)
+{
+    if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");
+    if (!c->pair) return fail(c, QTB_E_INVALID, "replica skin: pair potential only");
+    if (c->ml || c->L.ml)
+        return fail(c, QTB_E_INVALID, "replica skin: the surrogate's lists keep the potential's skin");
+    if (replica < -1 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
+    if (!(skin >= 0.0) || skin > c->skin)
+        return fail(c, QTB_E_INVALID, "replica skin must lie in [0, the potential's skin]");
+    QTB_HIP(c, hipStreamSynchronize(c->st));
+    if (qtb_status s = sync_boxes(c)) return s;
+    for (int r = 0; r < c->n_rep; ++r) {
+        if (replica >= 0 && r != replica) continue;
+        RepDev& d = c->rd[r];
+        d.r_cs = c->rc + skin;
+        d.half_skin0 = 0.5 * skin;
+        d.half_skin = d.half_skin0 - std::max(0.0, 1.0 - d.npt_S * d.npt_sr) * 0.5 * d.r_cs;
+    }
+    drop_graph(c);
+    if (qtb_status s = upload_tables_raw(c)) return s;
+    if (qtb_status s = refresh_forces(c)) return s;  // lists rebuilt with the new radius
+    return read_status(c);
+}
+
 qtb_status qtb_set_decomposition(qtb_ctx* c, int32_t waves_per_atom, int32_t half_groups)
 {
     if (!c) return fail(nullptr, QTB_E_INVALID, "ctx is NULL");

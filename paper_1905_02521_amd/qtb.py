@@ -94,6 +94,7 @@ EXPORTS = ("qtb_workspace_bytes", "qtb_init", "qtb_build_filter", "qtb_step",
            "qtb_get_barostat_state", "qtb_set_barostat_state", "qtb_filter_taps",
            "qtb_set_decomposition", "qtb_get_decomposition",
            "qtb_set_group_decomposition", "qtb_get_group_decomposition",
+           "qtb_set_replica_skin",
            "qtb_last_error", "qtb_destroy", "qtb_version",
            "qtb_ml_workspace_bytes", "qtb_ml_create", "qtb_ml_init_params", "qtb_ml_set_params",
            "qtb_ml_get_params", "qtb_ml_attach", "qtb_ml_evaluate", "qtb_ml_fit_norm",
@@ -172,6 +173,8 @@ def lib():
     L.qtb_set_barostat_state.argtypes = [vp, ctypes.c_int32, _PD]
     L.qtb_set_decomposition.restype = ctypes.c_int
     L.qtb_set_decomposition.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.qtb_set_replica_skin.restype = ctypes.c_int
+    L.qtb_set_replica_skin.argtypes = [vp, ctypes.c_int32, ctypes.c_double]
     L.qtb_set_group_decomposition.restype = ctypes.c_int
     L.qtb_set_group_decomposition.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.qtb_get_group_decomposition.restype = ctypes.c_int
@@ -507,6 +510,10 @@ class Context:
         w, h = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().qtb_get_decomposition(self.ctx, ctypes.byref(w), ctypes.byref(h)), self.ctx)
         return w.value, bool(h.value)
+
+    def set_replica_skin(self, replica, skin):
+        """Neighbour-list skin of one replica (-1: all), at most the potential's."""
+        _check(lib().qtb_set_replica_skin(self.ctx, int(replica), float(skin)), self.ctx)
 
     def set_group_decomposition(self, group_width, waves_per_atom, half_groups=False):
         """Pin the decomposition of the force launch of one bead-group width."""

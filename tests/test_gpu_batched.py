@@ -132,3 +132,36 @@ def test_mixed_decompositions_per_bead_group():
         mix.set_group_decomposition(3, 1, False)
     mix.close()
     uni.close()
+
+
+def test_replica_skins_change_only_the_lists():
+    """Per-replica list skins (thin ones rebuild often): the same FP64
+    trajectories as the potential's skin everywhere, to the rounding of the
+    sums' order; skins outside [0, the potential's skin] are rejected."""
+    reps = make_reps(replica_specs()[:4])
+    a = ctx_for(reps, qtb.PREC_FP64, qtb.FIR_FP64, obs_every=4)
+    b = ctx_for(reps, qtb.PREC_FP64, qtb.FIR_FP64, obs_every=4)
+    for c in (a, b):
+        c.set_decomposition(1, False)
+    a.step(16)
+    b.step(16)
+    for r, sk in enumerate((0.05, 0.2, 0.5, 0.35)):   # potential skin 0.5
+        a.set_replica_skin(r, sk)
+    a.step(60)
+    b.step(60)
+    for k in range(4):
+        ra, va, sa = a.get_state(k)
+        rb, vb, sb = b.get_state(k)
+        assert sa == sb == 76
+        assert np.max(np.abs(ra - rb)) < 1e-10 and np.max(np.abs(va - vb)) < 1e-10, k
+        oa, ob = a.observables(k), b.observables(k)
+        for f in ("potential", "e_primitive", "e_virial"):
+            assert abs(oa[f] - ob[f]) <= 1e-9 * max(1.0, abs(ob[f])), (k, f)
+    a.set_replica_skin(-1, 0.5)
+    for bad in (0.51, -0.1, float("nan")):
+        with pytest.raises(qtb.QtbError):
+            a.set_replica_skin(0, bad)
+    with pytest.raises(qtb.QtbError):
+        a.set_replica_skin(4, 0.2)
+    a.close()
+    b.close()
