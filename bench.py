@@ -535,9 +535,10 @@ def sweep_heat_capacity(works, inputs, pot, a):
     start and white-noise stream (correlated sampling: the twins differ only
     in the filter's temperature, so most of the noise cancels in their
     energy difference), production precision.  Equilibration of 10/gamma of
-    the weakest friction, then a.hc_blocks blocks of 2/gamma each, sampled
-    every 8 steps.  C = (E(T') - E(T)) / (T' - T) per atom in units of 3 k_B,
-    with the standard error of the blocks' paired differences, from three
+    the weakest friction, then a.hc_blocks x 2/gamma steps sampled every 8
+    and read out in windows of about 1/(8 gamma) (whole noise blocks).  C = (E(T') - E(T)) / (T' - T)
+    per atom in units of 3 k_B, with the standard error of the windows'
+    paired differences by blocking (Flyvbjerg-Petersen), from three
     energies: the eq. 5 primitive energy and the centroid-virial energy
     (both with measured momenta, so both carry the friction tail of the
     Langevin dynamics; the primitive one with the internal ring-polymer
@@ -545,6 +546,7 @@ def sweep_heat_capacity(works, inputs, pot, a):
     the bead-averaged potential energy (no momenta; equal to the total
     energy for harmonic modes)."""
     from paper_1905_02521_amd import qtb, workloads as W
+    from paper_1905_02521_amd.stats import mean_and_error
     reps = []
     for k, w in enumerate(works):
         beads, sp, box = inputs[k]
@@ -561,6 +563,7 @@ def sweep_heat_capacity(works, inputs, pot, a):
                 ctx.build_filter(2 * k + twin, w.noise, w.two_nf)
     tau = 1.0 / min(w.gamma * w.dt for w in works)
     warm, block = int(10 * tau), int(2 * tau)
+    window = 64 * max(1, round(block / 16 / 64))   # whole noise blocks
     ctx.step(warm)
     for r in range(len(reps)):
         ctx.observables(r)
@@ -568,12 +571,13 @@ def sweep_heat_capacity(works, inputs, pot, a):
               ("C_2V", "potential", 2.0))
     blocks = [{f: [] for _, f, _ in fields} for _ in reps]
     for q in range(a.hc_blocks):
-        ctx.step(block)
-        for r in range(len(reps)):
-            o = ctx.observables(r)
-            for _, f, _ in fields:
-                blocks[r][f].append(o[f])
-        print(f"heat capacity: block {q + 1}/{a.hc_blocks} of {block} steps", file=sys.stderr,
+        for _ in range(block // window):
+            ctx.step(window)
+            for r in range(len(reps)):
+                o = ctx.observables(r)
+                for _, f, _ in fields:
+                    blocks[r][f].append(o[f])
+        print(f"heat capacity: {q + 1}/{a.hc_blocks} x {block} steps", file=sys.stderr,
               flush=True)
     ctx.close()
     kB = W.METAL_UNITS["kB"]
@@ -585,10 +589,13 @@ def sweep_heat_capacity(works, inputs, pot, a):
              "atoms": int(n_at)}
         for name, f, mult in fields:
             d = mult * scale * (np.array(blocks[2 * k + 1][f]) - np.array(blocks[2 * k][f]))
-            e[name] = [float(d.mean()), float(d.std(ddof=1) / math.sqrt(len(d)))]
+            m, se = mean_and_error(d)
+            e[name] = [m, se]
         out.append(e)
-    return {"twin_dT": "0.05 T", "equilibration_steps": warm, "block_steps": block,
-            "blocks": a.hc_blocks, "units": "3 k_B per atom, [mean, standard error]",
+    return {"twin_dT": "0.05 T", "equilibration_steps": warm,
+            "sampled_steps": a.hc_blocks * (block // window) * window, "window_steps": window,
+            "error": "blocking (Flyvbjerg-Petersen) over the windows' paired differences",
+            "units": "3 k_B per atom, [mean, standard error]",
             "replicas": out}
 
 

@@ -19,19 +19,20 @@ primitive energy falls with temperature (a heat capacity of -0.5 k_B per
 degree of freedom, reproduced by the closed form), and QTB at 400 K.  Each
 condition runs beside a twin at 1.05 T with the same start and white-noise
 stream, so their energy difference (the heat capacity) keeps little noise.
-GPU production precision (FP32 forces, BF16x3 FIR).
+GPU production precision (FP32 forces, BF16x3 FIR); 10/gamma of the weakest
+friction discarded, standard errors by blocking (Flyvbjerg-Petersen) over
+128 windows of 1/(2 gamma).
 
 Bars: bead-averaged potential, primitive and centroid-virial energies
 relative to the static lattice within 3 standard errors plus 2 % of the
 harmonic value (the anharmonic residual, measured at most 0.7 %); the heat
 capacity of each estimator within 3 standard errors plus 0.03 k_B per degree
 of freedom."""
-import math
-
 import numpy as np
 import pytest
 
 from paper_1905_02521_amd import qtb, workloads as W
+from paper_1905_02521_amd.stats import mean_and_error
 from tests import phonons as ph
 from tests.gpu_common import crystal
 
@@ -92,8 +93,9 @@ def measured():
     for r in range(len(reps)):
         ctx.observables(r)
     blocks = [{f: [] for f, _ in FIELDS} for _ in reps]
-    for _ in range(16):
-        ctx.step(int(4 * tau))
+    window = 64 * max(1, round(tau / 2 / 64))   # about 1 / (2 gamma), whole noise blocks
+    for _ in range(128):
+        ctx.step(window)
         for r in range(len(reps)):
             o = ctx.observables(r)
             for f, _ in FIELDS:
@@ -103,7 +105,7 @@ def measured():
 
 
 def _mean_se(x):
-    return float(np.mean(x)), float(np.std(x, ddof=1) / math.sqrt(len(x)))
+    return mean_and_error(x)
 
 
 def test_energies_match_the_harmonic_closed_form(harmonic, measured):
