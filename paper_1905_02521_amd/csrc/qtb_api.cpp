@@ -456,6 +456,11 @@ struct VdosRec {
 struct qtb_ctx {
     qtb_options opt{};
     hipStream_t st = nullptr;
+    // launches of different bead-group widths (disjoint replicas) run on
+    // streams of their own, forked from and joined back into st
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_ev;   // [0] the fork, [k] the join of side stream k - 1
+    bool side_failed = false;
     bool fp64 = false, pair = false;
     int n_rep = 0;
     std::vector<qtb_replica> reps;
@@ -969,6 +974,54 @@ bool list_kernel(const qtb_ctx* c)
 
 // inline_rebuild: the force kernel rebuilds flagged lists itself (no list
 // kernel launched before it).
+// Streams for n independent launches: launch k on the returned stream k
+// (stream 0 is st).  With more than one launch (and no phase profiling, whose
+// event pairs bracket st only) the others get side streams that wait for an
+// event recorded on st; join_branches makes st wait for them.  Any failure
+// to create a stream or event leaves every launch on st.
+std::vector<hipStream_t> fork_branches(qtb_ctx* c, size_t n)
+{
+    std::vector<hipStream_t> out(n, c->st);
+    if (n <= 1 || c->prof || c->side_failed) return out;
+    while (c->side.size() < n - 1) {
+        hipStream_t x = nullptr;
+        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) {
+            c->side_failed = true;
+            (void)hipGetLastError();
+            return out;
+        }
+        c->side.push_back(x);
+    }
+    while (c->side_ev.size() < n) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            c->side_failed = true;
+            (void)hipGetLastError();
+            return out;
+        }
+        c->side_ev.push_back(e);
+    }
+    if (hipEventRecord(c->side_ev[0], c->st) != hipSuccess) {
+        c->side_failed = true;
+        (void)hipGetLastError();
+        return out;
+    }
+    for (size_t k = 1; k < n; ++k) {
+        (void)hipStreamWaitEvent(c->side[k - 1], c->side_ev[0], 0);
+        out[k] = c->side[k - 1];
+    }
+    return out;
+}
+
+void join_branches(qtb_ctx* c, const std::vector<hipStream_t>& br)
+{
+    for (size_t k = 1; k < br.size(); ++k) {
+        if (br[k] == c->st) continue;
+        (void)hipEventRecord(c->side_ev[k], br[k]);
+        (void)hipStreamWaitEvent(c->st, c->side_ev[k], 0);
+    }
+}
+
 // Force group k of the current table (only = k), or all of them (only < 0).
 void launch_plain_forces(qtb_ctx* c, int32_t flags, bool inline_rebuild = false, int only = -1)
 {
@@ -977,21 +1030,24 @@ void launch_plain_forces(qtb_ctx* c, int32_t flags, bool inline_rebuild = false,
     const BlockEntry* fb = c->at<BlockEntry>(L.blk_force);
     double* part = c->at<double>(L.partials);
     const int clear = (flags & kCompare) ? 0 : (inline_rebuild ? 2 : 1);
+    const auto br = fork_branches(c, only >= 0 ? 1 : L.force_groups.size());
     for (size_t k = 0; k < L.force_groups.size(); ++k) {
         if (only >= 0 && (size_t)only != k) continue;
+        const hipStream_t st = only >= 0 ? c->st : br[k];
         const auto& g = L.force_groups[k];
         const int b0 = g.second.first, nb = g.second.second - g.second.first;
         if (nb <= 0) continue;
         if (c->pair) {
             const void* tab = c->fp64 ? (const void*)&c->tabd : (const void*)&c->tabf;
-            launch_forces_pair(c->st, c->fp64, g.first, L.force_group_W[k], dreps, fb + b0, nb,
+            launch_forces_pair(st, c->fp64, g.first, L.force_group_W[k], dreps, fb + b0, nb,
                                tab, flags, part + (size_t)b0 * kNobs, clear, c->n_rep,
                                c->at<int32_t>(L.status), step_ref(c));
         } else {
-            launch_forces_onsite(c->st, c->fp64, c->kind, dreps, fb + b0, nb, flags,
+            launch_forces_onsite(st, c->fp64, c->kind, dreps, fb + b0, nb, flags,
                                  part + (size_t)b0 * kNobs);
         }
     }
+    join_branches(c, br);
 }
 
 // Surrogate forces of every replica with model m: descriptors, network,
@@ -1107,12 +1163,15 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
     const BlockEntry* ub = c->at<BlockEntry>(L.blk_upd);
     {
         Phase ph(c, 2);
-        for (auto& g : L.upd_groups) {
+        const auto br = fork_branches(c, L.upd_groups.size());
+        for (size_t k = 0; k < L.upd_groups.size(); ++k) {
+            const auto& g = L.upd_groups[k];
             const int b0 = g.second.first, nb = g.second.second - g.second.first;
             if (nb > 0)
-                launch_update(c->st, c->fp64, c->pair, g.first, L.upd_threads, dreps, ub + b0, nb, zrow,
-                              c->at<int32_t>(L.status), step_ref(c), zmod, L.n_cols);
+                launch_update(br[k], c->fp64, c->pair, g.first, L.upd_threads, dreps, ub + b0, nb,
+                              zrow, c->at<int32_t>(L.status), step_ref(c), zmod, L.n_cols);
         }
+        join_branches(c, br);
     }
     c->rec_extra = 1;
     // the pair potential's force kernel rebuilds flagged lists itself, except
@@ -2609,6 +2668,11 @@ void qtb_destroy(qtb_ctx* c)
     (void)hipStreamSynchronize(c->st);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     drop_graph(c);
+    for (hipStream_t x : c->side) {
+        (void)hipStreamSynchronize(x);
+        (void)hipStreamDestroy(x);
+    }
+    for (hipEvent_t e : c->side_ev) (void)hipEventDestroy(e);
     delete c;
 }
 
