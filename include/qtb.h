@@ -178,6 +178,11 @@ typedef struct {
  * [fir_block_K, 4096]; qtb_build_filter's two_nf must equal n; the noise
  * precision follows prec; not with QTB_OPT_FUSE. */
 #define QTB_OPT_NOISE_BLOCKS 16
+/* Build every replica's neighbour lists in the separate list kernel (by
+ * default only replicas above 16 384 atoms and contexts with surrogate
+ * buffers do; smaller replicas rebuild inside the force kernel).  The lists,
+ * forces and trajectories are the same. */
+#define QTB_OPT_LIST_KERNEL 32
 
 /* Means over the samples taken since the previous qtb_observables call of
  * this replica (eq. 5 primitive estimator with instantaneous momenta). */
@@ -409,8 +414,7 @@ qtb_status qtb_vdos_detach(qtb_ctx *ctx, int32_t replica);
  * Enable with enable != 0, disable with 0 (either call disables whichever
  * barostat runs).  QTB_E_INVALID unless the potential is the pair potential,
  * the context has no surrogate buffers, the replica has three dimensions,
- * every replica is small enough for the force kernel's own list rebuild, the
- * one-kernel step (QTB_OPT_FUSE) is off, tau_p > 0, P0 finite, beta_T > 0
+ * the one-kernel step (QTB_OPT_FUSE) is off, tau_p > 0, P0 finite, beta_T > 0
  * (cell rescaling) and gamma_p >= 0 (piston).  Synchronises.  While a
  * barostat runs every step's force pass also computes the observables.
  * Switching it off rebuilds the neighbour lists and recomputes the forces of

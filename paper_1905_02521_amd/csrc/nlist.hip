@@ -132,10 +132,10 @@ __global__ void __launch_bounds__(256) k_tile_box(const RepDev* __restrict__ rep
 // the shell (list_push), so that the force loop's wavefronts meet the
 // out-of-range pairs together.
 template <typename T>
-__device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be, const int p,
+__device__ __forceinline__ void nlist_entry(RepDev& R, const BlockEntry be, const int p,
                                             int32_t* __restrict__ status, double* tx, double* ty,
                                             double* tz, double* td, double* dmax_s,
-                                            uint8_t* skip)
+                                            uint8_t* skip, double box_scale)
 {
     using T4 = typename Vec4<T>::type;
     const int N = R.N, P = R.P;
@@ -165,7 +165,8 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
             u[b] = v;
         }
     }
-    const double Lx = R.box[0], Ly = R.box[1], Lz = R.box[2];
+    // inside a step the positions carry a barostat's pending box factor
+    const double Lx = R.box[0] * box_scale, Ly = R.box[1] * box_scale, Lz = R.box[2] * box_scale;
     const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
     // image range from the largest pair radius any atom of the block can have
     double dmax = 0.0;
@@ -279,11 +280,17 @@ __device__ __forceinline__ void nlist_entry(const RepDev& R, const BlockEntry be
 
 // Grid-stride over the block table with at most 2048 workgroups, so the
 // launch of a step that needs no rebuild costs one flag load per group.
+// in_step: the build runs inside a step, after its update: the box takes
+// the pending factor npt_sr of the positions, the list scale of this step's
+// force pass becomes 1 (npt_S = 1 / npt_sr), and each rebuilt replica is
+// marked for the barostat (list_built), which then resets the scale to 1.
+// Between steps box and positions agree, and a rebuilt replica's list scale
+// is 1 at once (its rebuild threshold with it).
 template <typename T>
-__global__ void __launch_bounds__(256) k_nlist(const RepDev* __restrict__ reps,
+__global__ void __launch_bounds__(256) k_nlist(RepDev* __restrict__ reps,
                                                const BlockEntry* __restrict__ blocks,
                                                int n_entries, int32_t* __restrict__ status,
-                                               const StepRef sync)
+                                               const StepRef sync, int in_step)
 {
     __shared__ double tx[256], ty[256], tz[256], td[256];
     __shared__ uint8_t skip[kMaxListTiles];
@@ -292,9 +299,22 @@ __global__ void __launch_bounds__(256) k_nlist(const RepDev* __restrict__ reps,
     if (status[kAnyRebuild + si.f] == 0) return;  // nothing to do: one load, then exit
     for (int e = blockIdx.x; e < n_entries; e += gridDim.x) {
         const BlockEntry be = blocks[e];
-        const RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
+        RepDev& R = reps[__builtin_amdgcn_readfirstlane(be.rep)];
         if (R.rflag[si.f] == 0) continue;  // uniform over the block
-        nlist_entry<T>(R, be, si.p, status, tx, ty, tz, td, dmax_s, skip);
+        nlist_entry<T>(R, be, si.p, status, tx, ty, tz, td, dmax_s, skip,
+                       in_step ? R.npt_sr : 1.0);
+        if (threadIdx.x == 0) {
+            if (in_step) {
+                // the entries are in this step's geometry: the force pass's
+                // list scale npt_S npt_sr is 1; the barostat then sets it to
+                // exactly 1 for the next step
+                R.npt_S = 1.0 / R.npt_sr;
+                R.list_built = 1;
+            } else {  // between steps box and positions agree: the lists' scale is 1
+                R.npt_S = 1.0;
+                R.half_skin = R.half_skin0 - fmax(0.0, 1.0 - R.npt_sr) * 0.5 * R.r_cs;
+            }
+        }
         __syncthreads();
     }
 }
@@ -320,7 +340,7 @@ void launch_mark_rebuild(hipStream_t st, const RepDev* reps, int n_rep, int32_t*
 
 void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
                   int n_blocks, const BlockEntry* tiles, int n_tiles, int32_t* status,
-                  bool centroids, StepRef sync)
+                  bool centroids, StepRef sync, bool in_step)
 {
     if (centroids)
         launch(k_centroids, dim3(n_blocks), dim3(64), 0, st, reps, blocks, sync);
@@ -329,10 +349,14 @@ void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntr
     // a list build is rare but long for large replicas: enough groups to
     // fill the chip; a step without a rebuild costs one flag load per group
     const int grid = n_blocks < 2048 ? n_blocks : 2048;
+    RepDev* const wreps = const_cast<RepDev*>(reps);  // the builds mark their replicas
+    const int ins = in_step ? 1 : 0;
     if (fp64)
-        launch(k_nlist<double>, dim3(grid), dim3(256), 0, st, reps, blocks, n_blocks, status, sync);
+        launch(k_nlist<double>, dim3(grid), dim3(256), 0, st, wreps, blocks, n_blocks, status,
+               sync, ins);
     else
-        launch(k_nlist<float>, dim3(grid), dim3(256), 0, st, reps, blocks, n_blocks, status, sync);
+        launch(k_nlist<float>, dim3(grid), dim3(256), 0, st, wreps, blocks, n_blocks, status,
+               sync, ins);
 }
 
 }  // namespace qtb

@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(256) k_eq9(const RepDev* __restrict__ reps,
 // committed and reset to 1 here, after the step that applied them.
 __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int n_rep,
                                                   const double* __restrict__ partials,
-                                                  const StepRef sync)
+                                                  const StepRef sync, int32_t* __restrict__ status)
 {
     __shared__ double red[3][256];
     const int r = blockIdx.x;
@@ -387,8 +387,11 @@ __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int
     if (threadIdx.x == 0) {  // the factor this step applied: box and list scale follow
         const double sr = R.npt_sr;
         for (int a = 0; a < 3; ++a) R.box[a] *= sr;
-        // this step's force pass rebuilt the lists: entries in its geometry
-        R.npt_S = R.rflag[f1] != 0 ? 1.0 : R.npt_S * sr;
+        // this step rebuilt the lists (in the force pass, whose flag stays
+        // set, or in the list kernel, which marks its builds): entries in
+        // its geometry
+        R.npt_S = (R.rflag[f1] != 0 || R.list_built != 0) ? 1.0 : R.npt_S * sr;
+        R.list_built = 0;
     }
     if (!R.npt) {
         if (threadIdx.x == 0) R.npt_sr = R.npt_sv1 = R.npt_sv2 = 1.0;
@@ -450,7 +453,10 @@ __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int
         const double S = R.npt_S * sc;
         const double hs = R.half_skin0 - fmax(0.0, 1.0 - S) * 0.5 * R.r_cs;
         R.half_skin = hs;
-        if (hs < 0.5 * R.half_skin0) R.rflag[f2] = 1;
+        if (hs < 0.5 * R.half_skin0) {  // (the list kernel reads the context-wide flag)
+            R.rflag[f2] = 1;
+            atomicOr(status + kAnyRebuild + f2, 1);
+        }
     }
 }
 
@@ -517,9 +523,9 @@ void launch_eq9(hipStream_t st, bool fp64, const RepDev* reps, const FirTile* ti
 }
 
 void launch_barostat(hipStream_t st, RepDev* reps, int n_rep, const double* partials,
-                     StepRef sync)
+                     StepRef sync, int32_t* status)
 {
-    launch(k_barostat, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, sync);
+    launch(k_barostat, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, sync, status);
 }
 
 void launch_eq9_invalidate(hipStream_t st, int64_t* marker)

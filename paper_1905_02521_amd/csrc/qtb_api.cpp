@@ -966,7 +966,7 @@ qtb_status upload_taps(qtb_ctx* c, int r)
 // Whether steps rebuild lists in the list kernel (else inside the force kernel).
 bool list_kernel(const qtb_ctx* c)
 {
-    if (c->ml || c->L.ml) return true;
+    if (c->ml || c->L.ml || (c->opt.flags & QTB_OPT_LIST_KERNEL)) return true;
     for (const auto& R : c->reps)
         if (R.n_atoms > kInlineRebuildMaxAtoms) return true;
     return false;
@@ -1077,13 +1077,15 @@ void launch_forces(qtb_ctx* c, int32_t flags)
     else launch_plain_forces(c, flags);
 }
 
-void launch_rebuild(qtb_ctx* c, bool centroids = false)
+// in_step: inside a step, after its update (positions carry a barostat's
+// pending box factor; the builds are marked for the barostat).
+void launch_rebuild(qtb_ctx* c, bool centroids = false, bool in_step = false)
 {
     if (!c->pair) return;
     const Layout& L = c->L;
     launch_nlist(c->st, c->fp64, c->at<RepDev>(L.reps), c->at<BlockEntry>(L.blk_nl),
                  (int)L.nl.size(), c->at<BlockEntry>(L.blk_tb), (int)L.tb.size(),
-                 c->at<int32_t>(L.status), centroids, step_ref(c));
+                 c->at<int32_t>(L.status), centroids, step_ref(c), in_step);
     if (L.ml)  // the surrogate's shorter lists follow every rebuild
         launch_ml_lists(c->st, c->fp64, c->at<RepDev>(L.reps), c->at<BlockEntry>(L.blk_nl),
                         (int)L.nl.size(), c->at<int32_t>(L.status), step_ref(c));
@@ -1180,7 +1182,7 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
     const bool inline_rebuild = c->pair && !list_kernel(c);
     if (c->pair && !inline_rebuild) {
         Phase ph(c, 3, true);  // tile bounds and list kernels (+ surrogate lists)
-        launch_rebuild(c);
+        launch_rebuild(c, false, true);
     }
     // the barostat needs the kinetic energy, springs and pair virial of every
     // step (the sampling pass has them; otherwise the pressure-only pass)
@@ -1204,7 +1206,7 @@ void record_step(qtb_ctx* c, int row, bool sample, bool check)
         Phase ph(c, 5);
         c->rec_extra = 0;  // step n itself
         launch_barostat(c->st, c->at<RepDev>(L.reps), c->n_rep, c->at<double>(L.partials),
-                        step_ref(c));
+                        step_ref(c), c->at<int32_t>(L.status));
     }
     if (check) {  // the pair potential judges the surrogate on the same positions
         launch_plain_forces(c, kCompare);
@@ -2111,8 +2113,6 @@ qtb_status set_barostat(qtb_ctx* c, int32_t replica, int kind, double P0, double
             return fail(c, QTB_E_INVALID, "barostat: pair potential without surrogate buffers only");
         if (c->reps[replica].n_dims != 3)
             return fail(c, QTB_E_INVALID, "barostat: three dimensions only");
-        if (list_kernel(c))
-            return fail(c, QTB_E_INVALID, "barostat: replicas above the inline-rebuild size");
         if (c->opt.flags & QTB_OPT_FUSE)
             return fail(c, QTB_E_INVALID, "barostat: not with the one-kernel step");
         if (!(tau_p > 0.0) || !std::isfinite(tau_p) || !std::isfinite(P0))
@@ -2176,7 +2176,7 @@ qtb_status qtb_set_barostat_state(qtb_ctx* c, int32_t replica, const double* h_s
 {
     if (!c || !h_state) return fail(c, QTB_E_INVALID, "null argument");
     if (replica < 0 || replica >= c->n_rep) return fail(c, QTB_E_INVALID, "replica out of range");
-    if (!c->pair || c->ml || c->L.ml || list_kernel(c) || (c->opt.flags & QTB_OPT_FUSE))
+    if (!c->pair || c->ml || c->L.ml || (c->opt.flags & QTB_OPT_FUSE))
         return fail(c, QTB_E_INVALID, "barostat state: only where a barostat can run");
     for (int q = 0; q < 4; ++q)
         if (!std::isfinite(h_state[q]) || (q > 0 && !(h_state[q] > 0.0)))

@@ -152,6 +152,7 @@ struct RepDev {
     // u = r - npt_S * reference
     double npt_S;
     double half_skin0;                 // half the skin
+    int32_t list_built;                // the list kernel rebuilt inside this step (barostat)
 };
 
 // ------------------------------------------------ descriptor-MLP surrogate
@@ -360,7 +361,7 @@ void launch_eq9_invalidate(hipStream_t st, int64_t* marker);
 // applied; for replicas with npt set, the scalings step n + 1 applies and a
 // list rebuild flagged for it; for the others, the factors reset to 1.
 void launch_barostat(hipStream_t st, RepDev* reps, int n_rep, const double* partials,
-                     StepRef sync);
+                     StepRef sync, int32_t* status);
 int eq9_columns(int n);
 void launch_gaussian(hipStream_t st, uint64_t seed, uint32_t stream, uint32_t tag, int64_t n0,
                      int64_t n_rows, uint32_t d0, uint32_t n_dof, double* out);
@@ -383,7 +384,7 @@ int update_block_atoms(int dims, int P, int threads);
 // nlist.hip
 void launch_nlist(hipStream_t st, bool fp64, const RepDev* reps, const BlockEntry* blocks,
                   int n_blocks, const BlockEntry* tiles, int n_tiles, int32_t* status,
-                  bool centroids, StepRef sync);
+                  bool centroids, StepRef sync, bool in_step = false);
 void launch_mark_rebuild(hipStream_t st, const RepDev* reps, int n_rep, int32_t* status,
                          StepRef sync);
 // forces.hip

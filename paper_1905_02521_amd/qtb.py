@@ -27,6 +27,7 @@ OPT_NO_AUTOTUNE = 2
 OPT_ML_TRAIN = 4
 OPT_FUSE = 8
 OPT_NOISE_BLOCKS = 16
+OPT_LIST_KERNEL = 32
 MAX_SPECIES = 4
 ML_FEATURES = 96
 ML_PARAMS_PER_SPECIES = 10433
@@ -330,7 +331,7 @@ class Context:
     def __init__(self, potential: dict, replicas: list[Replica], units: dict, *,
                  prec=PREC_FP32, fir=FIR_BF16X3, fir_block_K=64, obs_every=0, max_two_nf=512,
                  graphs=True, autotune=True, stream=None, ml_r_cut=0.0, ml_train=False,
-                 fuse=False, noise_blocks=False):
+                 fuse=False, noise_blocks=False, list_kernel=False):
         torch = _torch()
         L = lib()
         self._keep = []
@@ -388,7 +389,7 @@ class Context:
         opt.obs_every, opt.max_two_nf = obs_every, max_two_nf
         opt.flags = (0 if graphs else OPT_NO_GRAPH) | (0 if autotune else OPT_NO_AUTOTUNE) | \
             (OPT_ML_TRAIN if ml_train else 0) | (OPT_FUSE if fuse else 0) | \
-            (OPT_NOISE_BLOCKS if noise_blocks else 0)
+            (OPT_NOISE_BLOCKS if noise_blocks else 0) | (OPT_LIST_KERNEL if list_kernel else 0)
         opt.ml_r_cut = ml_r_cut
         self.opt = opt
         nbytes = L.qtb_workspace_bytes(ctypes.byref(pot), self.reps, self.n_rep, ctypes.byref(opt))

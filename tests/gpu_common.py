@@ -31,13 +31,13 @@ def crystal(n_cells, P, seed, sigma=0.0421, bead_spread=0.0):
 
 def gpu_crystal_ctx(beads, sp, box, *, T, gamma, dt, noise, prec, fir, seed=1, stream=0,
                     K=64, max_two_nf=512, obs_every=0, vel=None, pot=None, graphs=True,
-                    fuse=False, autotune=True):
+                    fuse=False, autotune=True, list_kernel=False):
     p = pot or W.mgo_potential()
     rep = qtb.Replica(pos=beads, species=sp, T=T, gamma=gamma, dt=dt, noise=noise, vel=vel,
                       box=tuple(box), seed=seed, stream=stream)
     return qtb.Context(qtb.pair_potential_dict(p), [rep], units_dict(False), prec=prec, fir=fir,
                        fir_block_K=K, obs_every=obs_every, max_two_nf=max_two_nf, graphs=graphs,
-                       fuse=fuse, autotune=autotune)
+                       fuse=fuse, autotune=autotune, list_kernel=list_kernel)
 
 
 def gpu_ho_ctx(omegas, P, *, T, gamma, dt, noise, prec, fir, seed=0, stream=0, K=64,

@@ -43,7 +43,7 @@ def _gpu():
     qtb.lib()
 
 
-def _npt_pair(orc, kind, P, P0, seed=13):
+def _npt_pair(orc, kind, P, P0, seed=13, list_kernel=False):
     """GPU context and oracle run of the compressed 216-atom crystal (skin
     0.3 A) under one barostat: cell rescaling tau_p = 20 fs, beta_T = 0.5
     A^3/eV, or a piston of time scale 200 fs and friction 0.01 / fs."""
@@ -53,7 +53,7 @@ def _npt_pair(orc, kind, P, P0, seed=13):
     T, gamma, dt, two_nf = 300.0, 5e-3, 1.0, 256
     ctx = gpu_crystal_ctx(beads, sp, box, T=T, gamma=gamma, dt=dt, noise=noise,
                           prec=qtb.PREC_FP64, fir=qtb.FIR_FP64, seed=seed, max_two_nf=two_nf,
-                          obs_every=4, pot=pot)
+                          obs_every=4, pot=pot, list_kernel=list_kernel)
     ctx.build_filter(0, noise, two_nf)
     osim = orc.Sim(oracle_pair_pot(orc, pot), oracle_units(orc, False), beads.shape[2], P, 3, box,
                    sp, T, gamma, dt, seed, 0, noise, two_nf, beads, n_threads=8)
@@ -77,15 +77,17 @@ def _compare(ctx, osim, k=0, box_tol=1e-12):
     return b
 
 
-@pytest.mark.parametrize("kind,P,P0", [("rescale", 1, 0.0), ("rescale", 1, 0.2),
-                                       ("rescale", 4, 0.2), ("piston", 1, 0.0),
-                                       ("piston", 1, 0.1), ("piston", 4, 0.0)])
-def test_barostat_trajectory_matches_oracle(orc, kind, P, P0):
+@pytest.mark.parametrize("kind,P,P0,lk", [("rescale", 1, 0.0, False), ("rescale", 1, 0.2, False),
+                                          ("rescale", 4, 0.2, False), ("piston", 1, 0.0, False),
+                                          ("piston", 1, 0.1, False), ("piston", 4, 0.0, False),
+                                          ("rescale", 1, 0.2, True), ("rescale", 4, 0.2, True),
+                                          ("piston", 1, 0.1, True)])
+def test_barostat_trajectory_matches_oracle(orc, kind, P, P0, lk):
     """Skin 0.3 A: the lists follow the box through their scale factor, and
     under compression (P0 = 0.1 and 0.2 eV/A^3, a few per cent in length)
     the compression eats into the skin past half of it, so that the force
     pass rebuilds them (the oracle rebuilds at every step)."""
-    ctx, osim, box = _npt_pair(orc, kind, P, P0)
+    ctx, osim, box = _npt_pair(orc, kind, P, P0, list_kernel=lk)
     ip = orc.OBS_NAMES.index("pressure")
     obs_o = []
     # the first noise block runs eagerly (10 + 54 steps), the second is a
