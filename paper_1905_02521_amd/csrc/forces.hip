@@ -193,6 +193,9 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
     // by lscale (entries built in this pass, MODE kPosRef, have the current
     // geometry)
     const T lsc = (T)lscale;
+    // FP32 path: the lane's pair virial in FP32 (one FMA per pair), added to
+    // the FP64 sum once at the end (the pressure needs no more)
+    float wf = 0.0f;
 
     auto pair = [&](const V4 E0, const V4 U0) {
         T dx, dy, dz;
@@ -305,7 +308,10 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
                 }
                 e += (double)(A * e1 - C * rinv6 + kqq * ec * rinv - F0 * r + E0c);
             }
-            if (want_w) w += (double)(fr * r2);
+            if (want_w) {
+                if constexpr (FAST) wf = fmaf(fr, r2, wf);
+                else w += (double)(fr * r2);
+            }
         }
     };
 
@@ -371,6 +377,7 @@ __device__ __forceinline__ void pair_sum(const RepDev& R, const PairTable<T>& ta
         range(ncore, 0, 1);
         range(cnt - ncore, maxnb - 1, -1);
     }
+    if (FAST && want_w) w += (double)wf;
 }
 
 // The block's LDS copy of the pair parameters for the FP32 path with
