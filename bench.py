@@ -791,7 +791,7 @@ def main():
         print(rocprof_summary(a.rocprof_summary))
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU: --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
 

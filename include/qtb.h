@@ -53,7 +53,7 @@ typedef enum {
     QTB_E_DEVICE = 3,      /* HIP runtime error */
     QTB_E_STATE = 4,       /* call out of order (e.g. step before its filter) */
     QTB_E_NONFINITE = 5,   /* NaN / Inf found in the state */
-    QTB_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+    QTB_E_UNSUPPORTED = 6  /* valid request the library does not implement */
 } qtb_status;
 
 /* Noise kinds: the power spectral density of the random force, eq. (7)/(12). */
@@ -560,7 +560,7 @@ qtb_status qtb_ml_get_params(qtb_ml *m, float *h_params, float *h_used, double *
 /* Step the context with the surrogate's forces (m = NULL: back to the pair
  * potential).  Every check_every steps (0 = never) the pair potential is
  * evaluated on the same positions and |F_ml - F_pair|^2 accumulated (the
- * pair potential judges the surrogate); read with qtb_ml_check.  Needs a
+ * pair potential checks the surrogate); read with qtb_ml_check.  Needs a
  * pair-potential context created with ml_r_cut >= the model's r_cut and
  * FP32 precision. */
 qtb_status qtb_ml_attach(qtb_ctx *ctx, qtb_ml *m, int32_t check_every);
