@@ -1007,7 +1007,11 @@ std::vector<hipStream_t> fork_branches(qtb_ctx* c, size_t n)
         return out;
     }
     for (size_t k = 1; k < n; ++k) {
-        (void)hipStreamWaitEvent(c->side[k - 1], c->side_ev[0], 0);
+        if (hipStreamWaitEvent(c->side[k - 1], c->side_ev[0], 0) != hipSuccess) {
+            c->side_failed = true;  // this launch and later ones stay on st
+            (void)hipGetLastError();
+            break;
+        }
         out[k] = c->side[k - 1];
     }
     return out;
@@ -1017,8 +1021,13 @@ void join_branches(qtb_ctx* c, const std::vector<hipStream_t>& br)
 {
     for (size_t k = 1; k < br.size(); ++k) {
         if (br[k] == c->st) continue;
-        (void)hipEventRecord(c->side_ev[k], br[k]);
-        (void)hipStreamWaitEvent(c->st, c->side_ev[k], 0);
+        if (hipEventRecord(c->side_ev[k], br[k]) != hipSuccess ||
+            hipStreamWaitEvent(c->st, c->side_ev[k], 0) != hipSuccess) {
+            // without the join st must not run ahead: wait for the branch
+            c->side_failed = true;
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(br[k]);
+        }
     }
 }
 
