@@ -130,6 +130,23 @@ def test_barostat_trajectory_matches_oracle(orc, kind, P, P0, lk):
     ctx.close()
 
 
+@pytest.mark.parametrize("lk", [False, True])
+def test_barostat_with_a_thin_replica_skin(orc, lk):
+    """Compression under cell rescaling (P0 = 0.2 eV/A^3) with the replica's
+    list skin narrowed to 0.12 A (the potential's is 0.3 A): the rebuild
+    threshold follows the thinner skin and the box scale, and the FP64
+    trajectory still follows the oracle (which rebuilds at every step), on
+    both rebuild paths."""
+    ctx, osim, box = _npt_pair(orc, "rescale", 1, 0.2, list_kernel=lk)
+    ctx.set_replica_skin(0, 0.12)
+    for n in (10, 54, 64):
+        ctx.step(n)
+        osim.run(n, 4)
+        _compare(ctx, osim)
+    assert abs(ctx.box(0)[0] / box[0] - 1.0) > 2e-3
+    ctx.close()
+
+
 def test_piston_checkpoint_resume(orc):
     """QTB-PIMD (P = 4) under the piston: 64 steps, then the state, box and
     barostat state go to a new context, which runs 64 more steps; both that
