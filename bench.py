@@ -261,6 +261,7 @@ def surrogate_bench(a):
     frames, forces, energies, sp, box, tags = surrogate.qtb_frames(pot, conds, n_frames=a.ml_samples,
                                                                    every=40, warm=2000)
     t_gen = time.perf_counter() - t_gen
+    print(f"surrogate: {len(frames)} frames in {t_gen:.1f} s", file=sys.stderr, flush=True)
     perm = np.random.default_rng(0).permutation(len(frames))
     n_test = len(frames) // 5
     te, tr = perm[:n_test], perm[n_test:]
@@ -273,6 +274,7 @@ def surrogate_bench(a):
                              steps=n_train, batch=256)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t_train
+    print(f"surrogate: {n_train} training steps in {t_train:.1f} s", file=sys.stderr, flush=True)
     test_rmse, test_rel, test_e = surrogate.errors(model, pot, frames[te], forces[te],
                                                    energies[te], sp, box)
     by_cond = {}
@@ -770,9 +772,10 @@ def main():
     ap.add_argument("--hc-blocks", type=int, default=8,
                     help="batched workloads: blocks of 2/gamma for the heat capacity of every "
                          "replica (0: skip)")
-    ap.add_argument("--ml-samples", type=int, default=512,
+    ap.add_argument("--ml-samples", type=int, default=11112,
                     help="surrogate workload: samples per training replica (9 replicas; the "
-                         "QTB-PIMD ones give 4 frames per sample)")
+                         "QTB-PIMD ones give 4 frames per sample: 18 frames per sample, "
+                         "200 016 frames at the default)")
     ap.add_argument("--ml-steps", type=int, default=3000,
                     help="surrogate workload: mini-batch Adam steps")
     ap.add_argument("--skin", type=float, default=None,

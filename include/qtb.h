@@ -258,9 +258,12 @@ qtb_status qtb_step(qtb_ctx *ctx, int64_t n_steps);
 qtb_status qtb_observables(qtb_ctx *ctx, int32_t replica, qtb_obs *out);
 
 /* Copy a replica's state to / from host arrays [P][n_dims][N]; set_state
- * also sets the replica's step counter, rebuilds its neighbour list,
- * recomputes its forces and opens a new noise block at that step.  Either
- * pointer may be NULL (that half unchanged).  Positions, velocities and the
+ * also sets the replica's step counter, rebuilds the neighbour lists and
+ * recomputes the forces of every replica, and opens a new noise block at
+ * that step.  Either pointer may be NULL (that half unchanged): a caller
+ * that wrote new states into its device arrays in place (on the context's
+ * stream, between calls) makes the context take them all with one set_state
+ * with both pointers NULL.  Positions, velocities and the
  * step are the whole state of a replica: a context created from a
  * checkpoint taken with get_state (same seed, stream, filter and options)
  * continues bit for bit like the context that set the same checkpoint back

@@ -438,6 +438,27 @@ class Context:
         _check(lib().qtb_set_state(self.ctx, replica, None if p is None else _pd(p),
                                    None if v is None else _pd(v), int(step)), self.ctx)
 
+    def set_positions(self, d_pos):
+        """New positions for every replica from a device tensor holding the
+        replicas' [P][n_dims][N] arrays one after another (FP64): copied into
+        the context's state arrays on its stream, then taken by the library
+        (qtb_set_state with null arrays: every list rebuilt, every force
+        recomputed; velocities and step unchanged)."""
+        torch = _torch()
+        src = d_pos.reshape(-1)
+        if src.numel() != sum(dp.numel() for dp in self.d_pos):
+            raise ValueError("set_positions: size does not match the replicas")
+        self.torch_stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.torch_stream):
+            off = 0
+            for dp in self.d_pos:
+                n = dp.numel()
+                dp.view(-1).copy_(src[off:off + n])
+                off += n
+        st = ctypes.c_int64()
+        _check(lib().qtb_get_state(self.ctx, 0, None, None, ctypes.byref(st)), self.ctx)
+        _check(lib().qtb_set_state(self.ctx, 0, None, None, st.value), self.ctx)
+
     def evaluate(self, replica=0):
         shape = self.shapes[replica]
         f = np.zeros(shape)
