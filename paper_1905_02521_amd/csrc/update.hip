@@ -36,6 +36,25 @@ __device__ __forceinline__ float bits_as<float>(int32_t b) { return __int_as_flo
 template <>
 __device__ __forceinline__ double bits_as<double>(int32_t b) { return __longlong_as_double((long long)b); }
 
+// Loads through the global address space: the state pointers are generic,
+// and generic loads make every wait drain all outstanding memory operations.
+template <typename X>
+__device__ __forceinline__ X gld(const X* p, size_t k)
+{
+    return ((const __attribute__((address_space(1))) X*)p)[k];
+}
+
+// A wavefront-uniform double (a replica's constant): kept in scalar
+// registers, so a select between such values does not become a load
+// indexed by a per-lane value.
+__device__ __forceinline__ double uni(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // One thread per (atom, Cartesian component, bead).  Consecutive lanes are
 // consecutive atoms, so every state load and store of a wavefront is a
 // contiguous run of the [P][dims][N] arrays; the P x P normal-mode
@@ -70,37 +89,55 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
     const int s = rest % P, a = rest / P;        // bead (then mode), component
     const int i = be.atom0 + il;
     const bool active = (a < dims) && (i < N);
-    for (int x = t; x < P * P; x += blockDim.x) Cs[x] = R.nm[x];
-    if (t == 0) flags = 0;
     const size_t idx = ((size_t)s * dims + a) * N + i;
-    // every global load of the thread is issued here, ahead of the barriers
-    double r = 0.0, v = 0.0, z = 0.0, ref3[3] = {0.0, 0.0, 0.0}, devb = 0.0;
+    // Every global load of the thread is issued here, before the first LDS or
+    // global store: the state pointers are generic, so the compiler keeps
+    // loads behind any store that might alias them, and each store between
+    // loads would add a round of memory latency.
+    const int PP = P * P;
+    const double nm0 = t < PP ? gld(R.nm, t) : 0.0;
+    const double c1 = R.c1, sv1 = R.npt_sv1, sr = R.npt_sr;
+    const double lsc = R.npt_S * R.npt_sr;  // the lists' scale for this step's force pass
+    const double half_skin = R.half_skin;
+    double r = 0.0, v = 0.0, f = 0.0, z = 0.0, ref3[3] = {0.0, 0.0, 0.0}, devb = 0.0;
+    double kick = 0.0, sig = 0.0, cw = 0.0, sw = 0.0, ws = 0.0;
     int sp = 0;
     if (active) {
-        sp = R.species[i];
-        r = R.pos[idx];
-        v = R.vel[idx];
-        const double f = (double)((const T*)R.force)[idx];
+        sp = gld(R.species, i);
+        r = gld(R.pos, idx);
+        v = gld(R.vel, idx);
+        f = (double)gld((const T*)R.force, idx);
         const T* zr = zeta_row;
         if (zmod > 0) {  // block noise: the row of this step in the [zmod] ring
             int64_t m = ((sync.clk ? *sync.clk : 0) + sync.off) % zmod;
             if (m < 0) m += zmod;
             zr += m * n_cols;
         }
-        z = (double)zr[R.dof_off + ((int64_t)dims * i + a) * P + s];
+        z = (double)gld(zr, (size_t)(R.dof_off + ((int64_t)dims * i + a) * P + s));
         if (PAIR && a == 0) {
-            for (int a2 = 0; a2 < 3; ++a2) ref3[a2] = R.rrefb[pin][(size_t)a2 * N + i];
-            devb = R.devbb[pin][i];
-            if (s == 0) {  // the references carry over to the next step
-                for (int a2 = 0; a2 < 3; ++a2) R.rrefb[pout][(size_t)a2 * N + i] = ref3[a2];
-                R.devbb[pout][i] = devb;
-            }
+            for (int a2 = 0; a2 < 3; ++a2) ref3[a2] = gld(R.rrefb[pin], (size_t)a2 * N + i);
+            devb = gld(R.devbb[pin], i);
         }
-        double kick = R.kick[0];
+        // this thread holds mode k = s after the transform
+        cw = gld(R.ring, s);
+        sw = gld(R.ring, P + s);
+        ws = gld(R.ring, 2 * P + s);
+        kick = uni(R.kick[0]);
+        sig = uni(R.sigma[0]);
 #pragma unroll
-        for (int q = 1; q < kMaxSpecies; ++q) kick = (sp == q) ? R.kick[q] : kick;
-        v = half_kick(v * R.npt_sv1, kick, f);  // barostat's pending velocity scaling
+        for (int q = 1; q < kMaxSpecies; ++q) {
+            kick = (sp == q) ? uni(R.kick[q]) : kick;
+            sig = (sp == q) ? uni(R.sigma[q]) : sig;
+        }
     }
+    if (PAIR && active && a == 0 && s == 0) {  // the references carry over to the next step
+        for (int a2 = 0; a2 < 3; ++a2) R.rrefb[pout][(size_t)a2 * N + i] = ref3[a2];
+        R.devbb[pout][i] = devb;
+    }
+    if (t < PP) Cs[t] = nm0;
+    for (int x = t + (int)blockDim.x; x < PP; x += blockDim.x) Cs[x] = gld(R.nm, x);
+    if (t == 0) flags = 0;
+    if (active) v = half_kick(v * sv1, kick, f);  // barostat's pending velocity scaling
     xr[t] = r;
     xv[t] = v;
     __syncthreads();
@@ -113,15 +150,11 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
             q = nm_acc(q, c, xr[base + b * A]);
             pm = nm_acc(pm, c, xv[base + b * A]);
         }
-        const int k = s;  // this thread now holds mode k (its noise value z)
-        const double cw = R.ring[k], sw = R.ring[P + k], ws = R.ring[2 * P + k];
-        double sig = R.sigma[0];
-#pragma unroll
-        for (int qq = 1; qq < kMaxSpecies; ++qq) sig = (sp == qq) ? R.sigma[qq] : sig;
-        // the barostat's pending length scaling, half before and half after
-        const double rh = sqrt(R.npt_sr);
+        // this thread now holds mode k = s (its noise value z); the
+        // barostat's pending length scaling, half before and half after
+        const double rh = sqrt(sr);
         q *= rh;
-        mode_aoa(q, pm, cw, sw, ws, R.c1, sig, z);
+        mode_aoa(q, pm, cw, sw, ws, c1, sig, z);
         q *= rh;
     }
     __syncthreads();
@@ -155,9 +188,8 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
             cen[il][a] = c;
         }
         __syncthreads();
-        // the lists' scale for this step's force pass, with the box factor
-        // this update applies (committed at the end of the step)
-        const double lsc = R.npt_S * R.npt_sr;
+        // lsc: the lists' scale for this step's force pass, with the box
+        // factor this update applies (committed at the end of the step)
         if (active && a == 0) {
             double u3[3], u2 = 0.0, d2 = 0.0;
             for (int a2 = 0; a2 < 3; ++a2) {
@@ -175,7 +207,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_update(const RepDev* __restrict
             ((T4*)R.ub[pout])[(size_t)i * P + s] = val;
             xv[t] = d2;
             // a compressed box (npt_S < 1) shrinks the bead spreads with it
-            const double lim = __builtin_fma(devb, fmin(1.0, lsc), R.half_skin);
+            const double lim = __builtin_fma(devb, fmin(1.0, lsc), half_skin);
             if (!(u2 <= lim * lim) || !(lim > 0.0)) atomicOr(&flags, 8);
         }
         __syncthreads();
