@@ -239,3 +239,46 @@ def test_training_on_qtb_frames_and_the_method_with_it():
           f"{du * 1e3:+.2f} meV/atom")
     assert abs(dk) < 0.05 * means["pair"][0]
     assert abs(du) < 5e-3
+
+
+def test_streamed_training_and_reloaded_errors_equal_one_context_per_batch():
+    """Frame sets too large for a context per batch are streamed: each batch
+    is copied into one context's state arrays, which then rebuilds its lists
+    and forces.  Twelve Adam steps over four batches of 2x2x2-cell frames
+    give the same losses and parameters, bit for bit, streamed (max_contexts =
+    1) as with a context per batch, and the errors measured through one
+    reloaded context of six frames equal those through one context of all
+    twenty."""
+    qtb = _qtb()
+    from paper_1905_02521_amd import surrogate
+    pot = W.mgo_potential()
+    frames = []
+    for k in range(20):
+        p, sp, box = crystal_frame(2, 100 + k, sigma=0.08)
+        frames.append(p)
+    frames = np.array(frames)
+    lc = frames_ctx(list(frames), sp, box)
+    lab = [lc.evaluate(k) for k in range(len(frames))]
+    lc.close()
+    forces = np.array([f[0] for f, _ in lab])
+    energies = np.array([e[0] for _, e in lab])
+    runs = []
+    for max_contexts in (64, 1):
+        m = qtb.Model(RC, RMIN)
+        m.init_params(2)
+        losses = surrogate.train(m, pot, frames, forces, energies, sp, box, steps=12, batch=6,
+                                 max_contexts=max_contexts)
+        runs.append((losses, m.get_params()[1], m))
+    print("losses per batch context", runs[0][0])
+    print("max |difference| of losses", np.max(np.abs(runs[1][0] - runs[0][0])),
+          "of parameters", np.max(np.abs(runs[1][1] - runs[0][1])))
+    # the same positions give the same lists and the same sums: equal bits
+    assert np.array_equal(runs[1][0], runs[0][0])
+    assert np.array_equal(runs[1][1], runs[0][1])
+    m = runs[0][2]
+    chunked = surrogate.errors(m, pot, frames, forces, energies, sp, box, chunk=6)
+    whole = surrogate.errors(m, pot, frames, forces, energies, sp, box, chunk=20)
+    print("errors through a reloaded context", chunked, "through one context", whole)
+    assert chunked == whole
+    for _, _, mm in runs:
+        mm.close()
