@@ -368,77 +368,118 @@ __global__ void __launch_bounds__(256) k_eq9(const RepDev* __restrict__ reps,
 // lists follow the box through npt_S (below) until a compression eats into
 // the skin.  A replica whose barostat is off has its pending factors
 // committed and reset to 1 here, after the step that applied them.
-__global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int n_rep,
-                                                  const double* __restrict__ partials,
-                                                  const StepRef sync, int32_t* __restrict__ status)
+// Block of 320 threads: the first four wavefronts sum the block partials,
+// the fifth draws the Gaussian meanwhile (both feed thread 0's update).
+constexpr int kBaroThreads = 320;
+
+__global__ void __launch_bounds__(kBaroThreads) k_barostat(RepDev* __restrict__ reps, int n_rep,
+                                                           const double* __restrict__ partials,
+                                                           const StepRef sync,
+                                                           int32_t* __restrict__ status)
 {
     __shared__ double red[3][256];
+    __shared__ double gsh;
     const int r = blockIdx.x;
     if (r >= n_rep) return;
     RepDev& R = reps[r];
-    int64_t f1 = 0, f2 = 0;
-    {
-        const int64_t n = (sync.clk ? *sync.clk : 0) + sync.off;
-        f1 = (n + 1) % 3;
-        f2 = (n + 2) % 3;
-        if (f1 < 0) f1 += 3;
-        if (f2 < 0) f2 += 3;
-    }
-    if (threadIdx.x == 0) {  // the factor this step applied: box and list scale follow
-        const double sr = R.npt_sr;
-        for (int a = 0; a < 3; ++a) R.box[a] *= sr;
-        // this step rebuilt the lists (in the force pass, whose flag stays
-        // set, or in the list kernel, which marks its builds): entries in
-        // its geometry
-        R.npt_S = (R.rflag[f1] != 0 || R.list_built != 0) ? 1.0 : R.npt_S * sr;
+    const int t = threadIdx.x;
+    // Every value of the replica is read before the first store to it: the
+    // stores would otherwise hold back the loads that follow them.
+    const int64_t n = (sync.clk ? *sync.clk : 0) + sync.off;
+    int64_t f1 = (n + 1) % 3, f2 = (n + 2) % 3;
+    if (f1 < 0) f1 += 3;
+    if (f2 < 0) f2 += 3;
+    const int npt = R.npt;
+    const int nblk = R.obs_nblocks;
+    const int64_t blk0 = R.obs_block0;
+    const double sr = R.npt_sr;
+    // the factor this step applied: box and list scale follow.  This step
+    // rebuilt the lists (in the force pass, whose flag stays set, or in the
+    // list kernel, which marks its builds): entries in its geometry
+    const double box0 = R.box[0] * sr, box1 = R.box[1] * sr, box2 = R.box[2] * sr;
+    const double S0 = (R.rflag[f1] != 0 || R.list_built != 0) ? 1.0 : R.npt_S * sr;
+    const int P = R.P, N = R.N;
+    const double dt = R.dt, kT = R.kT, P0 = R.npt_P0;
+    const double beta = R.npt_beta, tau = R.npt_tau, gp = R.npt_gp, Wp = R.npt_W;
+    const double pe0 = R.npt_pe, hs0 = R.half_skin0, rcs = R.r_cs;
+    const uint64_t seed = R.seed;
+    const int64_t step_off = R.step_off;
+    const uint32_t stream = R.stream;
+    if (t == 0) {
+        R.box[0] = box0;
+        R.box[1] = box1;
+        R.box[2] = box2;
+        R.npt_S = S0;
         R.list_built = 0;
     }
-    if (!R.npt) {
-        if (threadIdx.x == 0) R.npt_sr = R.npt_sv1 = R.npt_sv2 = 1.0;
+    if (!npt) {
+        if (t == 0) R.npt_sr = R.npt_sv1 = R.npt_sv2 = 1.0;
         return;
     }
-    double ke = 0.0, spr = 0.0, w = 0.0;
-    for (int b = threadIdx.x; b < R.obs_nblocks; b += blockDim.x) {
-        ke += partials[(size_t)(R.obs_block0 + b) * kNobs + 0];
-        spr += partials[(size_t)(R.obs_block0 + b) * kNobs + 2];
-        w += partials[(size_t)(R.obs_block0 + b) * kNobs + 5];
+    if (t >= 256) {
+        if (t == 256) gsh = white_gauss(seed, n + step_off, 0u, stream, 4);
+    } else {
+        // partials t, t + 256, ... added in that order; loads four at a time
+        double ke = 0.0, spr = 0.0, w = 0.0;
+        int b = t;
+        for (; b + 768 < nblk; b += 1024) {
+            double k4[4], s4[4], w4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double* q = partials + (size_t)(blk0 + b + 256 * u) * kNobs;
+                k4[u] = q[0];
+                s4[u] = q[2];
+                w4[u] = q[5];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ke += k4[u];
+                spr += s4[u];
+                w += w4[u];
+            }
+        }
+        for (; b < nblk; b += 256) {
+            const double* q = partials + (size_t)(blk0 + b) * kNobs;
+            ke += q[0];
+            spr += q[2];
+            w += q[5];
+        }
+        red[0][t] = ke;
+        red[1][t] = spr;
+        red[2][t] = w;
     }
-    red[0][threadIdx.x] = ke;
-    red[1][threadIdx.x] = spr;
-    red[2][threadIdx.x] = w;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + h];
-            red[1][threadIdx.x] += red[1][threadIdx.x + h];
-            red[2][threadIdx.x] += red[2][threadIdx.x + h];
+        if (t < h) {
+            red[0][t] += red[0][t + h];
+            red[1][t] += red[1][t + h];
+            red[2][t] += red[2][t + h];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const int64_t n = (sync.clk ? *sync.clk : 0) + sync.off;
-        const double V = R.box[0] * R.box[1] * R.box[2];  // committed above
+    if (t == 0) {
+        const double V = box0 * box1 * box2;  // committed above
         const double K = red[0][0];
-        const double p = (2.0 * K - 2.0 * red[1][0] + red[2][0] / R.P) / (3.0 * V);
-        const double g = white_gauss(R.seed, n + R.step_off, 0u, R.stream, 4);
+        const double p = (2.0 * K - 2.0 * red[1][0] + red[2][0] / P) / (3.0 * V);
+        const double g = gsh;
         double sc, sv1, sv2;
-        if (R.npt == 1) {
-            const double deps = -(R.npt_beta / R.npt_tau) * (R.npt_P0 - p) * R.dt +
-                                sqrt(2.0 * R.kT * R.npt_beta * R.dt / (V * R.npt_tau)) * g;
+        if (npt == 1) {
+            const double deps = -(beta / tau) * (P0 - p) * dt +
+                                sqrt(2.0 * kT * beta * dt / (V * tau)) * g;
             sc = exp(deps / 3.0);
             sv1 = 1.0 / sc;
             sv2 = 1.0;
         } else {
-            const double Nf = 3.0 * R.N * R.P;
-            const double G = 3.0 * V * (p - R.npt_P0) + (3.0 / Nf) * 2.0 * K;
-            const double cp = exp(-R.npt_gp * R.dt);
-            double pe = R.npt_pe + 0.5 * R.dt * G;
-            pe = cp * pe + sqrt((1.0 - cp * cp) * R.npt_W * R.kT) * g;
-            pe += 0.5 * R.dt * G;
+            const double Nf = 3.0 * N * P;
+            const double G = 3.0 * V * (p - P0) + (3.0 / Nf) * 2.0 * K;
+            const double cp = exp(-gp * dt);
+            double pe = pe0 + 0.5 * dt * G;
+            pe = cp * pe + sqrt((1.0 - cp * cp) * Wp * kT) * g;
+            pe += 0.5 * dt * G;
             R.npt_pe = pe;
-            const double ve = pe / R.npt_W;
-            sc = exp(R.dt * ve);
-            sv1 = sv2 = exp(-(1.0 + 3.0 / Nf) * 0.5 * R.dt * ve);
+            const double ve = pe / Wp;
+            sc = exp(dt * ve);
+            sv1 = sv2 = exp(-(1.0 + 3.0 / Nf) * 0.5 * dt * ve);
         }
         R.npt_sr = sc;
         R.npt_sv1 = sv1;
@@ -450,10 +491,10 @@ __global__ void __launch_bounds__(256) k_barostat(RepDev* __restrict__ reps, int
         // (1 - S)(r_c + skin) / 2 here and by (1 - S) dev_i in the update
         // kernel's test.  Past half of the skin the next step's force pass
         // rebuilds.
-        const double S = R.npt_S * sc;
-        const double hs = R.half_skin0 - fmax(0.0, 1.0 - S) * 0.5 * R.r_cs;
+        const double S = S0 * sc;
+        const double hs = hs0 - fmax(0.0, 1.0 - S) * 0.5 * rcs;
         R.half_skin = hs;
-        if (hs < 0.5 * R.half_skin0) {  // (the list kernel reads the context-wide flag)
+        if (hs < 0.5 * hs0) {  // (the list kernel reads the context-wide flag)
             R.rflag[f2] = 1;
             atomicOr(status + kAnyRebuild + f2, 1);
         }
@@ -525,7 +566,8 @@ void launch_eq9(hipStream_t st, bool fp64, const RepDev* reps, const FirTile* ti
 void launch_barostat(hipStream_t st, RepDev* reps, int n_rep, const double* partials,
                      StepRef sync, int32_t* status)
 {
-    launch(k_barostat, dim3(n_rep), dim3(256), 0, st, reps, n_rep, partials, sync, status);
+    launch(k_barostat, dim3(n_rep), dim3(kBaroThreads), 0, st, reps, n_rep, partials, sync,
+           status);
 }
 
 void launch_eq9_invalidate(hipStream_t st, int64_t* marker)
