@@ -246,18 +246,20 @@ def cpu_baseline(w, beads, sp, box, pot, budget_s=15.0):
 def surrogate_bench(a):
     """The learned surrogate on the 20x20x20-cell crystal x P = 4 (QTB-PIMD,
     300 K): trained on the GPU on frames of the method's own QTB (P = 1 at
-    50 to 1000 K) and QTB-PIMD (P = 4 at 50 to 300 K) runs of the 4x4x4
-    crystal, labelled by the pair potential, by mini-batch Adam; held-out
-    force and energy errors; then timed against the pair potential on the
-    production workload, with the pair potential's check of the force error
-    every 64 steps."""
+    16 temperatures from 50 to 1000 K) and QTB-PIMD (P = 4 at 50 to 300 K)
+    runs of the 4x4x4 crystal, labelled by the pair potential, by mini-batch
+    Adam; held-out force and energy errors; then timed against the pair
+    potential on the production workload, with the pair potential's check of
+    the force error every 64 steps."""
     import torch
     from paper_1905_02521_amd import qtb, surrogate, workloads as W
     pot = W.mgo_potential(skin=a.skin)
     U = dict(W.METAL_UNITS)
     t_gen = time.perf_counter()
-    conds = [(50.0, 1), (100.0, 1), (200.0, 1), (400.0, 1), (700.0, 1), (1000.0, 1),
-             (50.0, 4), (100.0, 4), (300.0, 4)]
+    # QTB at 16 temperatures 50 * 20^(j / 15) K (50 to 1000 K), and QTB-PIMD
+    # with P = 4 at 50, 100 and 300 K: the production run's bead configurations
+    conds = ([(round(50.0 * 20.0 ** (j / 15.0), 1), 1) for j in range(16)] +
+             [(50.0, 4), (100.0, 4), (300.0, 4)])
     frames, forces, energies, sp, box, tags = surrogate.qtb_frames(pot, conds, n_frames=a.ml_samples,
                                                                    every=40, warm=2000)
     t_gen = time.perf_counter() - t_gen
@@ -333,7 +335,7 @@ def surrogate_bench(a):
                      "run_check_force_rmse_eV_A": rmse, "run_check_rel_rmse": rel,
                      "run_checks": n_chk},
         "training": {"frames": int(len(tr)), "atoms_per_frame": n_at,
-                     "frame_sources": "QTB P=1 at 50-1000 K, QTB-PIMD P=4 beads at 50-300 K",
+                     "frame_sources": "QTB P=1 at 16 T from 50 to 1000 K, QTB-PIMD P=4 beads at 50-300 K",
                      "frame_generation_s": t_gen, "adam_steps": n_train, "batch_frames": 256,
                      "first_loss": float(losses[0]), "last_loss": float(losses[-1]),
                      "ms_per_step": t_train / n_train * 1e3},
@@ -772,10 +774,10 @@ def main():
     ap.add_argument("--hc-blocks", type=int, default=8,
                     help="batched workloads: blocks of 2/gamma for the heat capacity of every "
                          "replica (0: skip)")
-    ap.add_argument("--ml-samples", type=int, default=11112,
-                    help="surrogate workload: samples per training replica (9 replicas; the "
-                         "QTB-PIMD ones give 4 frames per sample: 18 frames per sample, "
-                         "200 016 frames at the default)")
+    ap.add_argument("--ml-samples", type=int, default=7143,
+                    help="surrogate workload: samples per training replica (19 replicas; the "
+                         "three QTB-PIMD ones give 4 frames per sample: 28 frames per sample, "
+                         "200 004 frames at the default)")
     ap.add_argument("--ml-steps", type=int, default=3000,
                     help="surrogate workload: mini-batch Adam steps")
     ap.add_argument("--skin", type=float, default=None,
