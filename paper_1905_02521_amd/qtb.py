@@ -450,11 +450,9 @@ class Context:
             raise ValueError("set_positions: size does not match the replicas")
         self.torch_stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(self.torch_stream):
-            off = 0
-            for dp in self.d_pos:
-                n = dp.numel()
-                dp.view(-1).copy_(src[off:off + n])
-                off += n
+            # one fused multi-tensor copy rather than a copy per replica
+            torch._foreach_copy_([dp.view(-1) for dp in self.d_pos],
+                                 list(src.split([dp.numel() for dp in self.d_pos])))
         st = ctypes.c_int64()
         _check(lib().qtb_get_state(self.ctx, 0, None, None, ctypes.byref(st)), self.ctx)
         _check(lib().qtb_set_state(self.ctx, 0, None, None, st.value), self.ctx)

@@ -74,7 +74,7 @@ def train(model, pot, frames, forces, energies, sp, box, steps, batch=256, lr=(3
     two thirds of the steps and lr[1] after.  Up to max_contexts batches each
     keep a context of their own; beyond that one context takes the batches in
     turn (the frames and labels stay on the GPU and each batch is loaded into
-    the context's state arrays, its lists and forces following: about 9 ms
+    the context's state arrays, its lists and forces following: about 8 ms
     per load of 256 frames of 512 atoms).  The input normalisation and energy
     offsets are fitted on the first batch.  Returns the loss of every step."""
     import torch
