@@ -263,11 +263,13 @@ qtb_status qtb_observables(qtb_ctx *ctx, int32_t replica, qtb_obs *out);
  * that step.  Either pointer may be NULL (that half unchanged): a caller
  * that wrote new states into its device arrays in place (on the context's
  * stream, between calls) makes the context take them all with one set_state
- * with both pointers NULL.  Positions, velocities and the
- * step are the whole state of a replica: a context created from a
- * checkpoint taken with get_state (same seed, stream, filter and options)
- * continues bit for bit like the context that set the same checkpoint back
- * with set_state. */
+ * with both pointers NULL.  Positions passed to set_state also become the
+ * reference of the observables' x2_mean (as the positions given at
+ * creation do); positions written in place leave that reference as it was.
+ * Positions, velocities and the step are the whole state of a replica: a
+ * context created from a checkpoint taken with get_state (same seed,
+ * stream, filter and options) continues bit for bit like the context that
+ * set the same checkpoint back with set_state. */
 qtb_status qtb_get_state(qtb_ctx *ctx, int32_t replica, double *h_pos, double *h_vel,
                          int64_t *step);
 qtb_status qtb_set_state(qtb_ctx *ctx, int32_t replica, const double *h_pos,
