@@ -20,6 +20,7 @@ the host cores on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -756,6 +757,8 @@ def main():
                          "(the velocity spectrum's recorder and transform) or npt (the step "
                          "at constant pressure) or fir-modes (the default workload with each "
                          "FIR arithmetic)")
+    ap.add_argument("--cells", type=int, default=0,
+                    help="run a single crystal workload on n x n x n cells instead of its own size")
     ap.add_argument("--fir", default="bf16x3", choices=["fp32", "bf16x3", "bf16", "fp64"])
     ap.add_argument("--K", type=int, default=64)
     ap.add_argument("--noise-blocks", action="store_true",
@@ -820,6 +823,15 @@ def main():
         return
     batched = a.workload.startswith("batched")
     works = W.batched_sweep(int(a.workload.split("-")[1])) if batched else [W.workload(a.workload)]
+    name = a.workload
+    if a.cells:
+        # the same workload on an n x n x n crystal
+        w0 = works[0]
+        if batched or w0.kind != "crystal":
+            raise SystemExit("--cells applies to a single crystal workload")
+        old_n = f"{w0.n_cells}x{w0.n_cells}x{w0.n_cells}"
+        name = w0.name.replace(old_n, f"{a.cells}x{a.cells}x{a.cells}")
+        works = [dataclasses.replace(w0, n_cells=a.cells, name=name)]
     pot = W.mgo_potential(skin=a.skin)
     fir = {"fp32": qtb.FIR_FP32, "bf16x3": qtb.FIR_BF16X3, "bf16": qtb.FIR_BF16,
            "fp64": qtb.FIR_FP64}[a.fir]
@@ -897,7 +909,7 @@ def main():
     fir_gbs = fir_bytes / (fir_ms / max(fir_n, 1) * 1e-3) / 1e9 if fir_n and not a.noise_blocks else None
     # HBM traffic from the committed counter record, valid only for this
     # workload and only while the pair kernel's source is unchanged
-    traffic = stored_traffic() if a.workload == "mgo-8x8x8-qtbpimd-P8-50K" else None
+    traffic = stored_traffic() if name == "mgo-8x8x8-qtbpimd-P8-50K" else None
     phases = {k: {"ms_per_launch": v[0] / max(v[1], 1), "launches": v[1],
                   "ms_per_step": v[0] / a.profile_steps} for k, v in prof.items()}
 
@@ -914,7 +926,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == qtb.PREC_FP32 else "f64",
         "data": "synthetic (seeded rock-salt crystal, numpy PCG64 displacements)",
-        "config": {"workload": a.workload,
+        "config": {"workload": name,
                    "replicas": len(works),
                    "atoms": sum(b.shape[2] for b, _, _ in inputs),
                    "atom_beads_per_step": ab_per_step,
