@@ -266,10 +266,12 @@ qtb_status qtb_observables(qtb_ctx *ctx, int32_t replica, qtb_obs *out);
  * with both pointers NULL.  Positions passed to set_state also become the
  * reference of the observables' x2_mean (as the positions given at
  * creation do); positions written in place leave that reference as it was.
- * Positions, velocities and the step are the whole state of a replica: a
- * context created from a checkpoint taken with get_state (same seed,
- * stream, filter and options) continues bit for bit like the context that
- * set the same checkpoint back with set_state. */
+ * A context that sets back a checkpoint of its own trajectory taken with
+ * get_state continues bit for bit like a context created from that
+ * checkpoint (same seed, stream, filter and options).  After a context has
+ * run a different history, a restored state agrees with a fresh context to
+ * FP32 rounding (measured 3e-7 A after 64 steps of a 3x3x3 crystal), not bit
+ * for bit. */
 qtb_status qtb_get_state(qtb_ctx *ctx, int32_t replica, double *h_pos, double *h_vel,
                          int64_t *step);
 qtb_status qtb_set_state(qtb_ctx *ctx, int32_t replica, const double *h_pos,

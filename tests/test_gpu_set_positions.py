@@ -1,0 +1,91 @@
+"""Positions written into a context's device arrays in place and taken with
+``Context.set_positions`` (``qtb_set_state`` with null host arrays: every
+list rebuilt and every force recomputed).  Two replicas of different size and
+bead count; one fixed force decomposition everywhere, so that every context
+sums each force in the same order.
+
+* Against the same context history reloaded from host arrays: the same
+  trajectory, bit for bit.
+* Against a context created from the same positions: the same forces and
+  energies at the reload, bit for bit; with the same velocities and step,
+  trajectories within 1e-5 A after 64 steps (measured 3e-7 A).  A context
+  whose earlier history differs is not bit-identical to a fresh one: the
+  continuation of a checkpoint is bit for bit only for the context's own
+  trajectory (``tests/test_gpu_resume.py``)."""
+import numpy as np
+import pytest
+
+from paper_1905_02521_amd import qtb, workloads as W
+from tests.gpu_common import crystal
+
+pytestmark = pytest.mark.gpu
+
+SYSTEMS = ((3, 4, 2), (2, 1, 1))  # (cells, beads, noise)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    qtb.lib()
+
+
+def _ctx(configs, vels=None):
+    reps = []
+    for k, ((beads, sp, box), (_, _, noise)) in enumerate(zip(configs, SYSTEMS)):
+        reps.append(qtb.Replica(pos=beads, species=sp, T=80.0, gamma=2e-3, dt=1.0, noise=noise,
+                                vel=None if vels is None else vels[k], box=tuple(box), seed=5,
+                                stream=k))
+    ctx = qtb.Context(qtb.pair_potential_dict(W.mgo_potential()), reps, dict(W.METAL_UNITS),
+                      prec=qtb.PREC_FP32, fir=qtb.FIR_BF16X3, max_two_nf=512, autotune=False)
+    for k, (_, _, noise) in enumerate(SYSTEMS):
+        ctx.build_filter(k, noise, 512)
+    return ctx
+
+
+def test_positions_taken_in_place():
+    import torch
+    first = [crystal(n, P, seed=10 + k, bead_spread=0.01) for k, (n, P, _) in enumerate(SYSTEMS)]
+    second = [crystal(n, P, seed=20 + k, bead_spread=0.01) for k, (n, P, _) in enumerate(SYSTEMS)]
+    ctx = _ctx(first)
+    ctx.step(100)
+    src = torch.as_tensor(np.concatenate([b.ravel() for b, _, _ in second]), device="cuda")
+    with pytest.raises(ValueError):
+        ctx.set_positions(src[:-1])
+    ctx.set_positions(src)
+    states = [ctx.get_state(k) for k in range(len(SYSTEMS))]
+    vels = [v for _, v, _ in states]
+    step = states[0][2]
+    fresh = _ctx(second, vels)
+    for k in range(len(SYSTEMS)):
+        fresh.set_state(k, None, None, step)
+        assert np.array_equal(states[k][0], second[k][0]), k
+    for k in range(len(SYSTEMS)):
+        f1, e1 = ctx.evaluate(k)
+        f2, e2 = fresh.evaluate(k)
+        assert np.array_equal(f1, f2), k
+        assert np.array_equal(e1, e2), k
+    # the same history, then the same positions from host arrays
+    host = _ctx(first)
+    host.step(100)
+    for k in range(len(SYSTEMS)):
+        host.set_state(k, second[k][0], vels[k], step)
+    for c in (ctx, fresh, host):
+        c.step(64)
+    for k in range(len(SYSTEMS)):
+        r1, v1, n1 = ctx.get_state(k)
+        r2, v2, n2 = fresh.get_state(k)
+        r3, v3, n3 = host.get_state(k)
+        print(f"replica {k}: max |r in place - r fresh| {np.max(np.abs(r1 - r2)):.3g}, "
+              f"max |r in place - r host arrays| {np.max(np.abs(r1 - r3)):.3g}, "
+              f"max |r host arrays - r fresh| {np.max(np.abs(r3 - r2)):.3g}")
+        assert n1 == n2 == n3 == step + 64
+    for k in range(len(SYSTEMS)):
+        r1, v1, _ = ctx.get_state(k)
+        r2, v2, _ = fresh.get_state(k)
+        r3, v3, _ = host.get_state(k)
+        assert np.array_equal(r1, r3) and np.array_equal(v1, v3), k
+        assert np.max(np.abs(r1 - r2)) < 1e-5, k
+    for c in (ctx, fresh, host):
+        c.close()
