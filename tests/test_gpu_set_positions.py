@@ -8,10 +8,11 @@ sums each force in the same order.
   trajectory, bit for bit.
 * Against a context created from the same positions: the same forces and
   energies at the reload, bit for bit; with the same velocities and step,
-  trajectories within 1e-5 A after 64 steps (measured 3e-7 A).  A context
-  whose earlier history differs is not bit-identical to a fresh one: the
-  continuation of a checkpoint is bit for bit only for the context's own
-  trajectory (``tests/test_gpu_resume.py``)."""
+  trajectories within 1e-5 A after 64 steps (measured 3e-7 A).  The BF16x3
+  noise contraction used here groups the noise window's rows by their place
+  in each context's noise ring, which differs between a context at step 100
+  of its own count and a fresh one whose replicas start at step 100; with
+  white noise, the FP32 or the FP64 contraction the two agree bit for bit."""
 import numpy as np
 import pytest
 
