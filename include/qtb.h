@@ -269,12 +269,12 @@ qtb_status qtb_observables(qtb_ctx *ctx, int32_t replica, qtb_obs *out);
  * A restored state continues bit for bit like a context created from it
  * (same seed, stream, filter and options) with white noise and with the
  * FP32 and FP64 noise contractions, whatever the context ran before.  With
- * QTB_FIR_BF16X3 the contraction groups the noise window's rows by their
- * place in the context's noise ring, which the context's own step count
- * sets: the two runs agree bit for bit when their step counts put the
- * window at the same place (as for a checkpoint of a context's own
- * trajectory set back), and otherwise to FP32 rounding of the noise
- * (measured 3e-7 A after 64 steps of a 3x3x3 crystal). */
+ * QTB_FIR_BF16X3 the contraction sums the noise window in chunks aligned
+ * to 8-row groups of the context's own step count: the two runs agree bit
+ * for bit when their context step counts are equal modulo 8 (a restored
+ * replica step minus the context's step count a multiple of 8), and
+ * otherwise to FP32 rounding of the noise (measured 3e-7 A after 64 steps
+ * of a 3x3x3 crystal). */
 qtb_status qtb_get_state(qtb_ctx *ctx, int32_t replica, double *h_pos, double *h_vel,
                          int64_t *step);
 qtb_status qtb_set_state(qtb_ctx *ctx, int32_t replica, const double *h_pos,

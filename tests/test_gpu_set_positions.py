@@ -9,10 +9,10 @@ sums each force in the same order.
 * Against a context created from the same positions: the same forces and
   energies at the reload, bit for bit; with the same velocities and step,
   trajectories within 1e-5 A after 64 steps (measured 3e-7 A).  The BF16x3
-  noise contraction used here groups the noise window's rows by their place
-  in each context's noise ring, which differs between a context at step 100
-  of its own count and a fresh one whose replicas start at step 100; with
-  white noise, the FP32 or the FP64 contraction the two agree bit for bit."""
+  noise contraction used here sums the window in chunks aligned to 8-row
+  groups of each context's own step count, 100 in the reloaded context and 0
+  in the fresh one (whose replicas start at step 100); with white noise, the
+  FP32 or the FP64 contraction the two agree bit for bit."""
 import numpy as np
 import pytest
 
