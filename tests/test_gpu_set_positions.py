@@ -90,3 +90,30 @@ def test_positions_taken_in_place():
         assert np.max(np.abs(r1 - r2)) < 1e-5, k
     for c in (ctx, fresh, host):
         c.close()
+
+
+def test_bf16x3_restore_is_bit_exact_when_step_counts_agree_modulo_8():
+    """The restore condition of the BF16x3 contraction: a state restored at
+    step 104 of a context's own count (104 = 0 mod 8) continues bit for bit
+    like a fresh context (count 0) whose replicas start at step 104."""
+    first = [crystal(n, P, seed=30 + k, bead_spread=0.01) for k, (n, P, _) in enumerate(SYSTEMS)]
+    second = [crystal(n, P, seed=40 + k, bead_spread=0.01) for k, (n, P, _) in enumerate(SYSTEMS)]
+    host = _ctx(first)
+    host.step(104)
+    vels = [host.get_state(k)[1] for k in range(len(SYSTEMS))]
+    step = host.get_state(0)[2]
+    assert step == 104
+    for k in range(len(SYSTEMS)):
+        host.set_state(k, second[k][0], vels[k], step)
+    fresh = _ctx(second, vels)
+    for k in range(len(SYSTEMS)):
+        fresh.set_state(k, None, None, step)
+    host.step(64)
+    fresh.step(64)
+    for k in range(len(SYSTEMS)):
+        r1, v1, n1 = host.get_state(k)
+        r2, v2, n2 = fresh.get_state(k)
+        assert n1 == n2 == step + 64
+        assert np.array_equal(r1, r2) and np.array_equal(v1, v2), k
+    host.close()
+    fresh.close()
